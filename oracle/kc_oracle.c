@@ -1,0 +1,490 @@
+/*
+ * kc_oracle.c -- plain, slow CPU oracle for the SIMT race and deadlock checker.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library calls this code;
+ * only the tests, the smoke check and the benchmark's CPU-baseline leg load it.
+ * It shares no source with the HIP path: it has its own instruction decoder,
+ * its own interpreter and its own conflict check.
+ *
+ * What it computes (Hathhorn et al., "Formal Semantics of Heterogeneous
+ * CUDA-C", SSV 2012):
+ *
+ *   - A job is an initial global memory followed by launches executed in order,
+ *     as items of one stream are executed serially (Section 2, last paragraph;
+ *     Section 3 "Streams and events").  A launch whose grid does not complete
+ *     (a block deadlocked) ends the job: a grid counts as complete only when
+ *     all of its threads have finished (Section 3 "Threads and memory").
+ *   - Within a launch the blocks run one after another in ascending linear
+ *     block id; this is one of the interleavings the semantics admits
+ *     (Section 3 "Threads and memory": scheduling is constrained only by grid
+ *     completion).  Inside a block the threads run in lockstep: every running
+ *     thread executes one instruction per step, loads of a step read memory as
+ *     it was at the start of the step, and the step's stores are then applied
+ *     in ascending thread id.  This is a legal sequentially consistent
+ *     interleaving (all loads, then the stores in tid order).
+ *   - Barriers: a thread at __syncthreads() waits until every thread of its
+ *     block waits at a barrier; the rewrite rules of Section 3 "Barrier
+ *     synchronization" pass a token through all NThrds threads of the block
+ *     and never compare which barrier each thread reached.  When every thread
+ *     waits, the episode completes: the block enters the next barrier epoch and
+ *     all threads resume after their own barrier.  If the barrier sites differ
+ *     a DIVERGENCE finding is recorded.  If some threads wait and the others
+ *     have exited, no rule can fire again: that is the deadlock of Section 3.1
+ *     (a thread fails to reach a barrier another thread reached); a DEADLOCK
+ *     finding is recorded and the block halts.
+ *   - Every in-bounds load and store appends an access record
+ *     {space, word address, block, barrier epoch, tid, read/write}, the
+ *     information the race tuples of Section 3.1 keep per location.
+ *   - Races (Section 3.1): two accesses to one location by different threads,
+ *     at least one a write, with no synchronization point between them.  For
+ *     shared memory the synchronization point is a completed barrier episode of
+ *     the block (the tuples are cleared at __syncthreads()).  The same rule is
+ *     applied to global memory within a block; global accesses of different
+ *     blocks are ordered only by the end of the kernel (Section 2: blocks
+ *     synchronize only through the implicit barrier at kernel end), so they
+ *     conflict in any epochs.
+ *
+ * Numeric conventions where C leaves behaviour undefined: int32 arithmetic
+ * wraps; DIV/REM truncate; division by zero yields 0 and an ARITH finding;
+ * INT_MIN / -1 = INT_MIN and INT_MIN % -1 = 0; shift counts use the low five
+ * bits; out-of-bounds accesses yield an OOB finding, loads return 0, stores are
+ * dropped and no access record is made; every thread may execute at most
+ * `fuel` instructions (FUEL finding, the thread exits); falling off the end of
+ * the program is an exit.  Shared memory starts zeroed.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ---- instruction set (decoded here independently of the GPU path) ---- */
+enum {
+    OP_ADD = 0x01, OP_SUB, OP_MUL, OP_DIV, OP_REM, OP_AND, OP_OR, OP_XOR,
+    OP_SHL, OP_SHRA, OP_SHRL, OP_MIN, OP_MAX, OP_SLT, OP_SLE, OP_SEQ, OP_SNE, OP_SLTU,
+    OP_MOV = 0x40, OP_MOVI = 0x41, OP_SREG = 0x42,
+    OP_LDS = 0x50, OP_STS = 0x51, OP_LDG = 0x52, OP_STG = 0x53,
+    OP_JMP = 0x60, OP_BZ = 0x61, OP_BNZ = 0x62, OP_BAR = 0x63, OP_EXIT = 0x64
+};
+
+enum { ST_RUN = 0, ST_WAIT = 1, ST_EXIT = 2 };
+enum { SP_SHARED = 0, SP_GLOBAL = 1 };
+enum { K_READ = 0, K_WRITE = 1 };
+enum { F_DEADLOCK = 1, F_DIVERGENCE = 2, F_OOB = 3, F_FUEL = 4, F_ARITH = 5 };
+
+typedef struct {
+    uint32_t grid[3], block[3];
+    uint32_t shmem_bytes;
+    int32_t params[8];
+} ora_launch;
+
+typedef struct { uint32_t launch, space, addr, block, epoch, tid, kind; } ora_record;
+typedef struct { uint32_t launch, space, scope, block, epoch, addr, w_tid, o_tid; } ora_race;
+typedef struct { uint32_t launch, kind, block, epoch, a, b, c, d; } ora_fault;
+
+typedef struct {
+    ora_record *recs;   uint64_t n_recs, cap_recs;     /* current launch's records */
+    ora_record *kept;   uint64_t n_kept, cap_kept;     /* all records, if asked for */
+    ora_race *races;    uint64_t n_races, cap_races;
+    ora_fault *faults;  uint64_t n_faults, cap_faults;
+    uint64_t n_records;
+    uint32_t launches_completed;
+    int keep_records;
+    int oom;
+} ora_result;
+
+#define GROW(ptr, n, cap, T)                                                  \
+    do {                                                                      \
+        if ((n) == (cap)) {                                                   \
+            uint64_t nc = (cap) ? 2 * (cap) : 1024;                           \
+            T *np_ = (T *)realloc((ptr), nc * sizeof(T));                     \
+            if (!np_) { res->oom = 1; return; }                               \
+            (ptr) = np_; (cap) = nc;                                          \
+        }                                                                     \
+    } while (0)
+
+static void add_record(ora_result *res, uint32_t launch, uint32_t space, uint32_t addr,
+                       uint32_t block, uint32_t epoch, uint32_t tid, uint32_t kind) {
+    ora_record r = {launch, space, addr, block, epoch, tid, kind};
+    GROW(res->recs, res->n_recs, res->cap_recs, ora_record);
+    res->recs[res->n_recs++] = r;
+    res->n_records++;
+    if (res->keep_records) {
+        GROW(res->kept, res->n_kept, res->cap_kept, ora_record);
+        res->kept[res->n_kept++] = r;
+    }
+}
+
+static void add_fault(ora_result *res, uint32_t launch, uint32_t kind, uint32_t block,
+                      uint32_t epoch, uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
+    ora_fault f = {launch, kind, block, epoch, a, b, c, d};
+    GROW(res->faults, res->n_faults, res->cap_faults, ora_fault);
+    res->faults[res->n_faults++] = f;
+}
+
+static void add_race(ora_result *res, ora_race r) {
+    GROW(res->races, res->n_races, res->cap_races, ora_race);
+    res->races[res->n_races++] = r;
+}
+
+/* ---- program validation (independent of the library's validator) ---- */
+static int valid_op(uint32_t op) {
+    uint32_t base = op & ~0x20u;
+    if (base >= OP_ADD && base <= OP_SLTU) return 1;
+    return op == OP_MOV || op == OP_MOVI || op == OP_SREG || op == OP_LDS || op == OP_STS ||
+           op == OP_LDG || op == OP_STG || op == OP_JMP || op == OP_BZ || op == OP_BNZ ||
+           op == OP_BAR || op == OP_EXIT;
+}
+
+int ora_validate(const uint64_t *prog, uint32_t n) {
+    if (n == 0 || n > 65536) return 2;
+    for (uint32_t pc = 0; pc < n; pc++) {
+        uint64_t w = prog[pc];
+        uint32_t op = w & 0xFF, d = (w >> 8) & 0xFF, a = (w >> 16) & 0xFF, b = (w >> 24) & 0xFF;
+        int32_t imm = (int32_t)(uint32_t)(w >> 32);
+        if (!valid_op(op) || d >= 16 || a >= 16 || b >= 16) return 2;
+        if ((op == OP_JMP || op == OP_BZ || op == OP_BNZ) && (imm < 0 || (uint32_t)imm > n)) return 2;
+        if (op == OP_SREG && (imm < 0 || imm >= 24)) return 2;
+    }
+    return 0;
+}
+
+/* ---- int32 ALU (wrapping two's complement; see header comment) ---- */
+static int32_t alu(uint32_t base, int32_t x, int32_t y, int *arith) {
+    uint32_t ux = (uint32_t)x, uy = (uint32_t)y;
+    switch (base) {
+    case OP_ADD: return (int32_t)(ux + uy);
+    case OP_SUB: return (int32_t)(ux - uy);
+    case OP_MUL: return (int32_t)(ux * uy);
+    case OP_DIV:
+        if (y == 0) { *arith = 1; return 0; }
+        if (x == INT32_MIN && y == -1) return INT32_MIN;
+        return x / y;
+    case OP_REM:
+        if (y == 0) { *arith = 1; return 0; }
+        if (x == INT32_MIN && y == -1) return 0;
+        return x % y;
+    case OP_AND: return x & y;
+    case OP_OR: return x | y;
+    case OP_XOR: return x ^ y;
+    case OP_SHL: return (int32_t)(ux << (uy & 31));
+    case OP_SHRA: {
+        /* arithmetic shift written without relying on implementation-defined >> */
+        uint32_t s = uy & 31;
+        uint32_t r = ux >> s;
+        if (x < 0 && s) r |= ~(0xFFFFFFFFu >> s);
+        return (int32_t)r;
+    }
+    case OP_SHRL: return (int32_t)(ux >> (uy & 31));
+    case OP_MIN: return x < y ? x : y;
+    case OP_MAX: return x > y ? x : y;
+    case OP_SLT: return x < y;
+    case OP_SLE: return x <= y;
+    case OP_SEQ: return x == y;
+    case OP_SNE: return x != y;
+    case OP_SLTU: return ux < uy;
+    }
+    return 0;
+}
+
+typedef struct {
+    uint32_t pc;
+    int32_t r[16];
+    int status;
+    uint32_t fuel;
+    uint32_t bar_pc;
+} ora_thread;
+
+typedef struct { uint32_t tid; uint32_t space; int32_t addr; int32_t val; } ora_store;
+
+/* Special registers (Section 3 feature list: gridDim, blockDim, blockIdx, threadIdx, warpSize). */
+static int32_t sreg(const ora_launch *L, uint32_t k, uint32_t tid, uint32_t bid) {
+    uint32_t bx = L->block[0], by = L->block[1], gx = L->grid[0], gy = L->grid[1];
+    switch (k) {
+    case 0: return (int32_t)(tid % bx);
+    case 1: return (int32_t)((tid / bx) % by);
+    case 2: return (int32_t)(tid / (bx * by));
+    case 3: return (int32_t)(bid % gx);
+    case 4: return (int32_t)((bid / gx) % gy);
+    case 5: return (int32_t)(bid / (gx * gy));
+    case 6: return (int32_t)L->block[0];
+    case 7: return (int32_t)L->block[1];
+    case 8: return (int32_t)L->block[2];
+    case 9: return (int32_t)L->grid[0];
+    case 10: return (int32_t)L->grid[1];
+    case 11: return (int32_t)L->grid[2];
+    case 12: return (int32_t)tid;
+    case 13: return (int32_t)bid;
+    case 14: return (int32_t)(bx * by * L->block[2]);
+    case 15: return 32;
+    default: return L->params[k - 16];
+    }
+}
+
+/* Run one block to completion or halt under lockstep steps.  Returns 1 if it deadlocked. */
+static int run_block(ora_result *res, uint32_t li, const uint64_t *prog, uint32_t n,
+                     const ora_launch *L, uint32_t bid, int32_t *mem, uint64_t n_words,
+                     uint32_t fuel, ora_thread *th, int32_t *sh, ora_store *q) {
+    uint32_t nt = L->block[0] * L->block[1] * L->block[2];
+    uint32_t sh_words = L->shmem_bytes / 4;
+    uint32_t epoch = 0;
+    memset(sh, 0, (size_t)sh_words * sizeof(int32_t));
+    for (uint32_t t = 0; t < nt; t++) {
+        memset(&th[t], 0, sizeof(ora_thread));
+        th[t].status = ST_RUN;
+        th[t].fuel = fuel;
+    }
+    for (;;) {
+        int any_run = 0;
+        for (uint32_t t = 0; t < nt; t++)
+            if (th[t].status == ST_RUN) { any_run = 1; break; }
+        if (any_run) {
+            /* one lockstep step: phase A executes, stores are queued */
+            uint32_t nq = 0;
+            for (uint32_t t = 0; t < nt; t++) {
+                ora_thread *T = &th[t];
+                if (T->status != ST_RUN) continue;
+                if (T->pc == n) { T->status = ST_EXIT; continue; }
+                if (T->fuel == 0) {
+                    T->status = ST_EXIT;
+                    add_fault(res, li, F_FUEL, bid, epoch, 0, t, 0, 0);
+                    continue;
+                }
+                T->fuel--;
+                uint64_t w = prog[T->pc];
+                uint32_t op = w & 0xFF, d = (w >> 8) & 0xFF, a = (w >> 16) & 0xFF, b = (w >> 24) & 0xFF;
+                int32_t imm = (int32_t)(uint32_t)(w >> 32);
+                uint32_t next = T->pc + 1;
+                uint32_t base = op & ~0x20u;
+                if (base >= OP_ADD && base <= OP_SLTU) {
+                    int arith = 0;
+                    int32_t y = (op & 0x20) ? imm : T->r[b];
+                    int32_t v = alu(base, T->r[a], y, &arith);
+                    if (arith) add_fault(res, li, F_ARITH, bid, epoch, 0, t, T->pc, 0);
+                    T->r[d] = v;
+                } else {
+                    switch (op) {
+                    case OP_MOV: T->r[d] = T->r[a]; break;
+                    case OP_MOVI: T->r[d] = imm; break;
+                    case OP_SREG: T->r[d] = sreg(L, (uint32_t)imm, t, bid); break;
+                    case OP_LDS: case OP_LDG: {
+                        uint32_t space = (op == OP_LDS) ? SP_SHARED : SP_GLOBAL;
+                        int32_t addr = (int32_t)((uint32_t)T->r[a] + (uint32_t)imm);
+                        uint64_t lim = space == SP_SHARED ? sh_words : n_words;
+                        if (addr < 0 || (uint64_t)addr >= lim) {
+                            add_fault(res, li, F_OOB, bid, epoch, space * 2 + K_READ, t, (uint32_t)addr, 0);
+                            T->r[d] = 0;
+                        } else {
+                            T->r[d] = space == SP_SHARED ? sh[addr] : mem[addr];
+                            add_record(res, li, space, (uint32_t)addr, bid, epoch, t, K_READ);
+                        }
+                        break;
+                    }
+                    case OP_STS: case OP_STG: {
+                        uint32_t space = (op == OP_STS) ? SP_SHARED : SP_GLOBAL;
+                        int32_t addr = (int32_t)((uint32_t)T->r[a] + (uint32_t)imm);
+                        uint64_t lim = space == SP_SHARED ? sh_words : n_words;
+                        if (addr < 0 || (uint64_t)addr >= lim) {
+                            add_fault(res, li, F_OOB, bid, epoch, space * 2 + K_WRITE, t, (uint32_t)addr, 0);
+                        } else {
+                            q[nq].tid = t; q[nq].space = space; q[nq].addr = addr; q[nq].val = T->r[b];
+                            nq++;
+                            add_record(res, li, space, (uint32_t)addr, bid, epoch, t, K_WRITE);
+                        }
+                        break;
+                    }
+                    case OP_JMP: next = (uint32_t)imm; break;
+                    case OP_BZ: if (T->r[a] == 0) next = (uint32_t)imm; break;
+                    case OP_BNZ: if (T->r[a] != 0) next = (uint32_t)imm; break;
+                    case OP_BAR: T->status = ST_WAIT; T->bar_pc = T->pc; break;
+                    case OP_EXIT: T->status = ST_EXIT; break;
+                    }
+                }
+                T->pc = next;
+            }
+            /* phase B: stores in ascending tid order (queued in that order) */
+            for (uint32_t i = 0; i < nq; i++) {
+                if (q[i].space == SP_SHARED) sh[q[i].addr] = q[i].val;
+                else mem[q[i].addr] = q[i].val;
+            }
+            if (res->oom) return 0;
+        } else {
+            uint32_t nwait = 0, nexit = 0;
+            for (uint32_t t = 0; t < nt; t++) {
+                if (th[t].status == ST_WAIT) nwait++;
+                else nexit++;
+            }
+            if (nwait == 0) return 0;                 /* all threads finished */
+            if (nexit == 0) {
+                /* every thread waits: the episode completes */
+                uint32_t lo = UINT32_MAX, lo_tid = 0, hi = UINT32_MAX, hi_tid = 0;
+                for (uint32_t t = 0; t < nt; t++)
+                    if (th[t].bar_pc < lo) { lo = th[t].bar_pc; lo_tid = t; }
+                for (uint32_t t = 0; t < nt; t++)
+                    if (th[t].bar_pc > lo && th[t].bar_pc < hi) { hi = th[t].bar_pc; hi_tid = t; }
+                if (hi != UINT32_MAX)
+                    add_fault(res, li, F_DIVERGENCE, bid, epoch, lo, lo_tid, hi, hi_tid);
+                epoch++;
+                for (uint32_t t = 0; t < nt; t++) {
+                    th[t].status = ST_RUN;
+                    th[t].pc = th[t].bar_pc + 1;
+                }
+            } else {
+                uint32_t min_wait = UINT32_MAX, min_exit = UINT32_MAX;
+                for (uint32_t t = 0; t < nt; t++) {
+                    if (th[t].status == ST_WAIT && t < min_wait) min_wait = t;
+                    if (th[t].status == ST_EXIT && t < min_exit) min_exit = t;
+                }
+                add_fault(res, li, F_DEADLOCK, bid, epoch, nwait, min_wait, min_exit, 0);
+                return 1;
+            }
+        }
+    }
+}
+
+/* ---- conflict check over one launch's records (Section 3.1) ---- */
+static uint32_t g_nt;   /* threads per block of the launch being checked (qsort context) */
+
+static int cmp_intra(const void *pa, const void *pb) {
+    const ora_record *x = pa, *y = pb;
+    if (x->space != y->space) return x->space < y->space ? -1 : 1;
+    if (x->block != y->block) return x->block < y->block ? -1 : 1;
+    if (x->epoch != y->epoch) return x->epoch < y->epoch ? -1 : 1;
+    if (x->addr != y->addr) return x->addr < y->addr ? -1 : 1;
+    if (x->tid != y->tid) return x->tid < y->tid ? -1 : 1;
+    return (int)x->kind - (int)y->kind;
+}
+
+static int cmp_cross(const void *pa, const void *pb) {
+    const ora_record *x = pa, *y = pb;
+    if (x->space != y->space) return x->space < y->space ? -1 : 1;
+    if (x->addr != y->addr) return x->addr < y->addr ? -1 : 1;
+    uint64_t gx = (uint64_t)x->block * g_nt + x->tid, gy = (uint64_t)y->block * g_nt + y->tid;
+    if (gx != gy) return gx < gy ? -1 : 1;
+    return (int)x->kind - (int)y->kind;
+}
+
+static void check_launch(ora_result *res, uint32_t li, uint32_t nt) {
+    ora_record *r = res->recs;
+    uint64_t n = res->n_recs;
+    /* intra-block: records of one (space, block, epoch, addr) are unordered by barriers */
+    qsort(r, n, sizeof(ora_record), cmp_intra);
+    for (uint64_t i = 0; i < n;) {
+        uint64_t j = i;
+        while (j < n && r[j].space == r[i].space && r[j].block == r[i].block &&
+               r[j].epoch == r[i].epoch && r[j].addr == r[i].addr) j++;
+        /* tids ascend inside the group: the first writer is the minimum writer */
+        int has_w = 0; uint32_t w = 0;
+        for (uint64_t k = i; k < j; k++)
+            if (r[k].kind == K_WRITE) { has_w = 1; w = r[k].tid; break; }
+        if (has_w) {
+            for (uint64_t k = i; k < j; k++) {
+                if (r[k].tid != w) {
+                    ora_race rc = {li, r[i].space, 0, r[i].block, r[i].epoch, r[i].addr, w, r[k].tid};
+                    add_race(res, rc);
+                    break;
+                }
+            }
+        }
+        i = j;
+    }
+    /* cross-block (global memory): records of different blocks are never ordered */
+    g_nt = nt;
+    qsort(r, n, sizeof(ora_record), cmp_cross);
+    for (uint64_t i = 0; i < n;) {
+        uint64_t j = i;
+        while (j < n && r[j].space == r[i].space && r[j].addr == r[i].addr) j++;
+        if (r[i].space == SP_GLOBAL) {
+            int has_w = 0; uint64_t wk = 0;
+            for (uint64_t k = i; k < j; k++)
+                if (r[k].kind == K_WRITE) { has_w = 1; wk = k; break; }
+            if (has_w) {
+                uint32_t wb = r[wk].block;
+                for (uint64_t k = i; k < j; k++) {
+                    if (r[k].block != wb) {
+                        ora_race rc = {li, SP_GLOBAL, 1, wb, 0xFFFFFFFFu, r[i].addr,
+                                       wb * nt + r[wk].tid, r[k].block * nt + r[k].tid};
+                        add_race(res, rc);
+                        break;
+                    }
+                }
+            }
+        }
+        i = j;
+    }
+    res->n_recs = 0;
+}
+
+static int cmp_race(const void *pa, const void *pb) {
+    const ora_race *x = pa, *y = pb;
+    const uint32_t kx[6] = {x->launch, x->space, x->scope, x->block, x->epoch, x->addr};
+    const uint32_t ky[6] = {y->launch, y->space, y->scope, y->block, y->epoch, y->addr};
+    for (int i = 0; i < 6; i++)
+        if (kx[i] != ky[i]) return kx[i] < ky[i] ? -1 : 1;
+    return 0;
+}
+
+static int cmp_fault(const void *pa, const void *pb) {
+    const ora_fault *x = pa, *y = pb;
+    const uint32_t kx[8] = {x->launch, x->block, x->epoch, x->kind, x->a, x->b, x->c, x->d};
+    const uint32_t ky[8] = {y->launch, y->block, y->epoch, y->kind, y->a, y->b, y->c, y->d};
+    for (int i = 0; i < 8; i++)
+        if (kx[i] != ky[i]) return kx[i] < ky[i] ? -1 : 1;
+    return 0;
+}
+
+/* Run a job.  progs[i]/prog_lens[i] is launch i's program; mem is updated in place. */
+int ora_run_job(uint32_t n_launches, const uint64_t *const *progs, const uint32_t *prog_lens,
+                const ora_launch *launches, int32_t *mem, uint64_t n_words, uint32_t fuel,
+                int keep_records, ora_result **out) {
+    *out = NULL;
+    for (uint32_t i = 0; i < n_launches; i++) {
+        if (ora_validate(progs[i], prog_lens[i])) return 2;
+        const ora_launch *L = &launches[i];
+        uint64_t nt = (uint64_t)L->block[0] * L->block[1] * L->block[2];
+        uint64_t nb = (uint64_t)L->grid[0] * L->grid[1] * L->grid[2];
+        if (nt == 0 || nt > 1024 || nb == 0 || nb * nt > 0xFFFFFFFFull || (L->shmem_bytes & 3)) return 1;
+    }
+    ora_result *res = calloc(1, sizeof(ora_result));
+    if (!res) return 3;
+    res->keep_records = keep_records;
+    for (uint32_t li = 0; li < n_launches; li++) {
+        const ora_launch *L = &launches[li];
+        uint32_t nt = L->block[0] * L->block[1] * L->block[2];
+        uint32_t nb = L->grid[0] * L->grid[1] * L->grid[2];
+        ora_thread *th = calloc(nt, sizeof(ora_thread));
+        int32_t *sh = calloc(L->shmem_bytes / 4 + 1, sizeof(int32_t));
+        ora_store *q = calloc(nt, sizeof(ora_store));
+        if (!th || !sh || !q) { free(th); free(sh); free(q); res->oom = 1; break; }
+        int deadlocked = 0;
+        for (uint32_t b = 0; b < nb; b++)
+            deadlocked |= run_block(res, li, progs[li], prog_lens[li], L, b, mem, n_words, fuel, th, sh, q);
+        free(th); free(sh); free(q);
+        if (res->oom) break;
+        check_launch(res, li, nt);
+        if (res->oom) break;
+        if (deadlocked) break;
+        res->launches_completed = li + 1;
+    }
+    if (res->oom) {
+        free(res->recs); free(res->kept); free(res->races); free(res->faults); free(res);
+        return 3;
+    }
+    qsort(res->races, res->n_races, sizeof(ora_race), cmp_race);
+    qsort(res->faults, res->n_faults, sizeof(ora_fault), cmp_fault);
+    uint64_t m = 0;     /* findings form a set: drop repeated identical tuples */
+    for (uint64_t i = 0; i < res->n_faults; i++)
+        if (m == 0 || cmp_fault(&res->faults[m - 1], &res->faults[i]) != 0) res->faults[m++] = res->faults[i];
+    res->n_faults = m;
+    *out = res;
+    return 0;
+}
+
+uint64_t ora_records(const ora_result *r) { return r->n_records; }
+uint32_t ora_launches_completed(const ora_result *r) { return r->launches_completed; }
+const ora_race *ora_races(const ora_result *r, uint64_t *n) { *n = r->n_races; return r->races; }
+const ora_fault *ora_faults(const ora_result *r, uint64_t *n) { *n = r->n_faults; return r->faults; }
+const ora_record *ora_kept_records(const ora_result *r, uint64_t *n) { *n = r->n_kept; return r->kept; }
+
+void ora_free(ora_result *r) {
+    if (!r) return;
+    free(r->recs); free(r->kept); free(r->races); free(r->faults); free(r);
+}

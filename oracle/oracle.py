@@ -1,0 +1,132 @@
+"""ctypes binding of the CPU oracle (kc_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, by the smoke check and by the
+benchmark's CPU-baseline leg, never by the product library.  It accepts any
+job-like object (``job.launches[i].program/grid/block/shmem_bytes/params`` and
+``job.memory``) and imports nothing from the product package.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass
+from typing import List, Optional, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libkc_oracle.so")
+SRC_PATH = os.path.join(_HERE, "kc_oracle.c")
+
+DEFAULT_FUEL = 1 << 20
+
+F_DEADLOCK, F_DIVERGENCE, F_OOB, F_FUEL, F_ARITH = 1, 2, 3, 4, 5
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc -O2 into a shared library next to its source."""
+    if force or not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(SRC_PATH):
+        tmp = LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-shared", "-fPIC",
+                               "-o", tmp, SRC_PATH])
+        os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+class _Launch(C.Structure):
+    _fields_ = [("grid", C.c_uint32 * 3), ("block", C.c_uint32 * 3), ("shmem_bytes", C.c_uint32),
+                ("params", C.c_int32 * 8)]
+
+
+RACE_DTYPE = np.dtype([(f, "<u4") for f in ("launch", "space", "scope", "block", "epoch", "addr", "w_tid", "o_tid")])
+FAULT_DTYPE = np.dtype([(f, "<u4") for f in ("launch", "kind", "block", "epoch", "a", "b", "c", "d")])
+RECORD_DTYPE = np.dtype([(f, "<u4") for f in ("launch", "space", "addr", "block", "epoch", "tid", "kind")])
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        lib = C.CDLL(LIB_PATH)
+        lib.ora_run_job.argtypes = [C.c_uint32, C.POINTER(C.c_void_p), C.POINTER(C.c_uint32),
+                                    C.POINTER(_Launch), C.c_void_p, C.c_uint64, C.c_uint32, C.c_int,
+                                    C.POINTER(C.c_void_p)]
+        lib.ora_run_job.restype = C.c_int
+        lib.ora_records.argtypes = [C.c_void_p]
+        lib.ora_records.restype = C.c_uint64
+        lib.ora_launches_completed.argtypes = [C.c_void_p]
+        lib.ora_launches_completed.restype = C.c_uint32
+        for name in ("ora_races", "ora_faults", "ora_kept_records"):
+            f = getattr(lib, name)
+            f.argtypes = [C.c_void_p, C.POINTER(C.c_uint64)]
+            f.restype = C.c_void_p
+        lib.ora_free.argtypes = [C.c_void_p]
+        lib.ora_validate.argtypes = [C.c_void_p, C.c_uint32]
+        lib.ora_validate.restype = C.c_int
+        _lib = lib
+    return _lib
+
+
+@dataclass
+class OracleResult:
+    records: int                  # canonical access-record count
+    launches_completed: int
+    races: np.ndarray             # RACE_DTYPE, canonical order
+    faults: np.ndarray            # FAULT_DTYPE, canonical order, no duplicates
+    memory: np.ndarray            # final global memory (int32)
+    record_log: Optional[np.ndarray] = None   # RECORD_DTYPE if keep_records
+
+    def race_tuples(self) -> List[Tuple[int, ...]]:
+        return [tuple(int(x) for x in r) for r in self.races]
+
+    def fault_tuples(self) -> List[Tuple[int, ...]]:
+        return [tuple(int(x) for x in f) for f in self.faults]
+
+
+def _copy(ptr, n, dtype):
+    if n == 0 or not ptr:
+        return np.zeros(0, dtype=dtype)
+    buf = (C.c_char * (n * dtype.itemsize)).from_address(ptr)
+    return np.frombuffer(bytes(buf), dtype=dtype).copy()
+
+
+def validate(words) -> bool:
+    w = np.ascontiguousarray(np.asarray(words, dtype=np.uint64))
+    return _load().ora_validate(w.ctypes.data, len(w)) == 0
+
+
+def run_job(job, fuel: int = DEFAULT_FUEL, keep_records: bool = False,
+            memory: Optional[np.ndarray] = None) -> OracleResult:
+    """Run every launch of ``job`` on a copy of its memory (or on ``memory``)."""
+    lib = _load()
+    progs = [np.ascontiguousarray(np.asarray(L.program, dtype=np.uint64)) for L in job.launches]
+    n = len(progs)
+    ptrs = (C.c_void_p * n)(*[p.ctypes.data for p in progs])
+    lens = (C.c_uint32 * n)(*[len(p) for p in progs])
+    ls = (_Launch * n)()
+    for i, L in enumerate(job.launches):
+        ls[i].grid[:] = list(L.grid)
+        ls[i].block[:] = list(L.block)
+        ls[i].shmem_bytes = L.shmem_bytes
+        params = list(L.params) + [0] * (8 - len(L.params))
+        ls[i].params[:] = [int(np.int32(p)) for p in params]
+    mem = np.array(job.memory if memory is None else memory, dtype=np.int32, copy=True)
+    out = C.c_void_p()
+    rc = lib.ora_run_job(n, ptrs, lens, ls, mem.ctypes.data, len(mem), fuel, int(keep_records), C.byref(out))
+    if rc != 0:
+        raise ValueError(f"oracle rejected the job (code {rc})")
+    try:
+        cnt = C.c_uint64()
+        races = _copy(lib.ora_races(out, C.byref(cnt)), cnt.value, RACE_DTYPE)
+        faults = _copy(lib.ora_faults(out, C.byref(cnt)), cnt.value, FAULT_DTYPE)
+        log = None
+        if keep_records:
+            log = _copy(lib.ora_kept_records(out, C.byref(cnt)), cnt.value, RECORD_DTYPE)
+        return OracleResult(int(lib.ora_records(out)), int(lib.ora_launches_completed(out)),
+                            races, faults, mem, log)
+    finally:
+        lib.ora_free(out)
