@@ -1,0 +1,199 @@
+/*
+ * kc.h -- C ABI of the MI355X SIMT race and deadlock checker (version 1).
+ *
+ * The library executes kernels written in KC-IR (see the instruction format
+ * below) SIMT-style on the GPU, one lane per simulated thread, logs every
+ * in-bounds memory access with its barrier epoch, and reports the canonical
+ * race, barrier-divergence and deadlock findings of the execution together
+ * with the final device memory.  The checked properties are those of
+ * Hathhorn et al., "Formal Semantics of Heterogeneous CUDA-C" (SSV 2012),
+ * Section 3.1 (race and deadlock detection), with the barrier semantics of
+ * Section 3 ("Barrier synchronization") and the launch/stream model of
+ * Section 2.
+ *
+ * Conventions
+ *   - All integers are little-endian; memory sizes are in 32-bit words unless
+ *     a name says bytes.  Device pointers are plain HIP device addresses
+ *     (for example the data pointer of a torch int32 tensor on the GPU).
+ *   - Functions return kc_status.  Races, divergence and deadlocks are
+ *     findings, not errors: a run with findings returns KC_OK and a
+ *     non-empty report.  On an error kc_last_error() describes it.
+ *   - KC_E_DEVICE means a HIP call failed; the context is then poisoned and
+ *     every later call on it returns KC_E_DEVICE.
+ *   - A context is not thread-safe, except that kc_poll may be called for
+ *     different tickets from different threads.
+ *
+ * Instruction format (KC-IR v1): one 64-bit word per instruction,
+ *   op = bits 0..7, d = 8..15, a = 16..23, b = 24..31, imm = 32..63 (int32).
+ * Opcodes: ADD 0x01 SUB 0x02 MUL 0x03 DIV 0x04 REM 0x05 AND 0x06 OR 0x07
+ * XOR 0x08 SHL 0x09 SHRA 0x0A SHRL 0x0B MIN 0x0C MAX 0x0D SLT 0x0E SLE 0x0F
+ * SEQ 0x10 SNE 0x11 SLTU 0x12 (d = a OP b); the same | 0x20 take imm for b;
+ * MOV 0x40 (d = a), MOVI 0x41 (d = imm), SREG 0x42 (d = special imm),
+ * LDS 0x50 (d = shared[a+imm]), STS 0x51 (shared[a+imm] = b),
+ * LDG 0x52 (d = global[a+imm]), STG 0x53 (global[a+imm] = b),
+ * JMP 0x60, BZ 0x61 (if a == 0), BNZ 0x62 (if a != 0) to absolute pc imm,
+ * BAR 0x63 (__syncthreads), EXIT 0x64.  Special registers: 0..2 threadIdx
+ * x/y/z, 3..5 blockIdx, 6..8 blockDim, 9..11 gridDim, 12 linear tid,
+ * 13 linear block id, 14 threads per block, 15 warpSize (32), 16..23 the
+ * launch parameters.  Registers r0..r15 are int32 and start at 0.
+ *
+ * Semantics of a run (the canonical execution the reports describe)
+ *   - A job is one memory plus launches run in order, as in one stream
+ *     (Section 2).  A launch in which some block deadlocks does not complete
+ *     and ends the job.
+ *   - Blocks execute in ascending linear block id; inside a block all
+ *     running threads step in lockstep (loads of a step see memory as of the
+ *     step's start, stores land in ascending tid order).  Race-free launches
+ *     have this outcome under every interleaving; for racy launches it is the
+ *     convention that reproduces the paper's printed outputs.
+ *   - int32 arithmetic wraps; x/0 and x%0 give 0 and an ARITH finding;
+ *     INT_MIN/-1 = INT_MIN, INT_MIN%-1 = 0; shifts use the low 5 bits of the
+ *     count.  Out-of-bounds accesses give an OOB finding, load 0 / drop the
+ *     store and are not logged.  Shared memory starts zeroed.  A thread may
+ *     execute at most `fuel` instructions (default 2^20), then exits with a
+ *     FUEL finding.  Falling off the end of the program is an exit.
+ */
+#ifndef KC_H
+#define KC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    KC_OK = 0,
+    KC_E_INVAL = 1,     /* bad argument: dims, sizes, null pointers, unknown option */
+    KC_E_PROGRAM = 2,   /* program failed validation at load */
+    KC_E_NOMEM = 3,     /* device or host allocation failed */
+    KC_E_DEVICE = 4,    /* a HIP call failed; the context is poisoned */
+    KC_E_PENDING = 5,   /* kc_poll without wait: the batch is still running */
+    KC_E_BUDGET = 6,    /* the job can never fit in the context's HBM budget */
+    KC_E_OVERFLOW = 7   /* a record field cannot hold the launch's ids */
+} kc_status;
+
+typedef struct kc_ctx kc_ctx;
+typedef struct kc_program kc_program;
+typedef struct kc_report kc_report;
+
+typedef struct { uint32_t x, y, z; } kc_dim3;
+
+/* Finding kinds (kc_fault.kind). */
+enum { KC_DEADLOCK = 1, KC_DIVERGENCE = 2, KC_OOB = 3, KC_FUEL = 4, KC_ARITH = 5 };
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Create a context on HIP device `hip_device`.  `hbm_budget_bytes` bounds the
+ * library's own device memory (logs, snapshots, scratch); 0 means no bound.
+ * `tune_cache` names a JSON file of autotuned launch parameters or is NULL.
+ * Errors: KC_E_INVAL (bad device), KC_E_DEVICE. */
+kc_status kc_ctx_create(int hip_device, uint64_t hbm_budget_bytes, const char *tune_cache, kc_ctx **out);
+void kc_ctx_destroy(kc_ctx *ctx);
+
+/* Options: "check" (1 = log and check, default; 0 = interpret only),
+ * "fuel" (instructions per thread, default 1<<20), "timing" (1 = time the
+ * stages with HIP events on the launch stream), "sort_tile" (keys per sort
+ * tile: 2048, 4096 or 8192), "log_records" (initial log capacity).
+ * Errors: KC_E_INVAL for an unknown key or out-of-range value. */
+kc_status kc_ctx_set_option(kc_ctx *ctx, const char *key, int64_t value);
+
+/* Accumulated statistics since the last reset ("reset" clears them):
+ * "interp_ms", "sort_ms", "check_ms", "replay_ms", "launches", "records",
+ * "replays", "fallbacks", "retries", "interp_launches", "sort_keys".
+ * Timings are only collected with option "timing" set.  Returns 0 for an
+ * unknown key. */
+double kc_ctx_get_stat(kc_ctx *ctx, const char *key);
+
+/* Message of the last error on this context; valid until the next call on it. */
+const char *kc_last_error(const kc_ctx *ctx);
+
+/* ---- programs -------------------------------------------------------------- */
+
+/* Copy and validate `n_words` instruction words (1..65536).  Validation:
+ * known opcode, registers < 16, branch targets in [0, n_words], special
+ * register index < 24.  The caller's buffer may be freed afterwards.
+ * Errors: KC_E_PROGRAM (validation), KC_E_INVAL, KC_E_NOMEM. */
+kc_status kc_program_load(kc_ctx *ctx, const uint64_t *words, uint32_t n_words, kc_program **out);
+void kc_program_free(kc_program *prog);
+
+/* ---- launches ---------------------------------------------------------------- */
+
+typedef struct {
+    const kc_program *prog;
+    kc_dim3 grid, block;        /* 1 <= threads per block <= 1024; blocks*threads < 2^32 */
+    uint32_t shmem_bytes;       /* dynamic shared memory per block, multiple of 4, <= 65536 */
+    int32_t params[8];          /* read by SREG 16..23 */
+    uint32_t n_params;          /* <= 8; unused params read as 0 */
+} kc_launch_desc;
+
+/* One launch, synchronous with respect to the host.  Work is queued on
+ * `stream` (a hipStream_t; NULL = the null stream).  `dev_mem` is a device
+ * buffer of `n_words` int32 words (< 2^31) that the caller owns and keeps
+ * untouched until the call returns; it is updated in place to the canonical
+ * final memory.  On KC_OK *out is a report owned by the caller.
+ * Errors: KC_E_INVAL, KC_E_NOMEM, KC_E_BUDGET, KC_E_OVERFLOW, KC_E_DEVICE. */
+kc_status kc_launch(kc_ctx *ctx, const kc_launch_desc *desc, int32_t *dev_mem, uint64_t n_words,
+                    void *stream, kc_report **out);
+
+/* A job: launches run in order on one memory, as one stream (Section 2).
+ * The report's launch fields are indices into `launches`. */
+typedef struct {
+    const kc_launch_desc *launches;
+    uint32_t n_launches;
+    int32_t *dev_mem;
+    uint64_t n_words;
+    uint64_t tag;               /* returned by kc_report_tag */
+} kc_job;
+
+/* Submit jobs as one batch; returns at once.  All jobs of the batch execute
+ * together (one interpreter launch per block-size class and launch index,
+ * one sort and one check over all of them).  The descriptor arrays are
+ * copied; device memories stay owned by the caller and must not be touched
+ * until kc_poll reports the batch done.  Errors: KC_E_INVAL, KC_E_BUDGET,
+ * KC_E_NOMEM, KC_E_DEVICE. */
+kc_status kc_batch_submit(kc_ctx *ctx, const kc_job *jobs, uint32_t n_jobs, void *stream, uint64_t *ticket);
+
+/* Collect a batch.  With wait = 0 returns KC_E_PENDING (out untouched) while
+ * it runs.  On KC_OK `out` (n_out >= n_jobs pointers) receives one report per
+ * job in submission order, each owned by the caller; the ticket is retired.
+ * Errors: KC_E_INVAL (unknown ticket, n_out too small), KC_E_DEVICE. */
+kc_status kc_poll(kc_ctx *ctx, uint64_t ticket, int wait, kc_report **out, uint32_t n_out);
+
+/* ---- reports -------------------------------------------------------------------- */
+
+typedef struct {
+    uint32_t launch;
+    uint32_t space;     /* 0 shared, 1 global */
+    uint32_t scope;     /* 0 intra-block, 1 cross-block */
+    uint32_t block;     /* linear block id (of w_tid when cross-block) */
+    uint32_t epoch;     /* barrier epoch; 0xFFFFFFFF when cross-block */
+    uint32_t addr;      /* word index: shared offset or global word */
+    uint32_t w_tid;     /* smallest writer; linear tid, or block*threads+tid when cross-block */
+    uint32_t o_tid;     /* smallest other conflicting thread, same numbering */
+} kc_race;
+
+typedef struct {
+    uint32_t launch, kind, block, epoch;
+    uint32_t a, b, c, d;
+    /* DEADLOCK:   a = #waiting threads, b = smallest waiting tid, c = smallest exited tid
+     * DIVERGENCE: a = smallest barrier pc, b = smallest tid there, c = next barrier pc, d = its smallest tid
+     * OOB:        a = space*2 + (1 if store), b = tid, c = address (int32)
+     * FUEL:       b = tid
+     * ARITH:      b = tid, c = pc */
+} kc_fault;
+
+uint64_t kc_report_records(const kc_report *r);            /* canonical access-record count */
+uint32_t kc_report_launches_completed(const kc_report *r);
+/* Races ascending by (launch, space, scope, block, epoch, addr); the array
+ * lives as long as the report. */
+const kc_race *kc_report_races(const kc_report *r, uint64_t *n);
+/* Findings ascending by (launch, block, epoch, kind, a, b, c, d), no repeats. */
+const kc_fault *kc_report_faults(const kc_report *r, uint64_t *n);
+uint64_t kc_report_tag(const kc_report *r);
+void kc_report_free(kc_report *r);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KC_H */

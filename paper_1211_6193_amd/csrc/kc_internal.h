@@ -1,0 +1,150 @@
+// Internal structures shared by the HIP kernels and the host runtime of libkc.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace kc {
+
+// ---- instruction set ------------------------------------------------------
+enum : uint32_t {
+    OP_ADD = 0x01, OP_SUB, OP_MUL, OP_DIV, OP_REM, OP_AND, OP_OR, OP_XOR,
+    OP_SHL, OP_SHRA, OP_SHRL, OP_MIN, OP_MAX, OP_SLT, OP_SLE, OP_SEQ, OP_SNE, OP_SLTU,
+    OP_IMM = 0x20,
+    OP_MOV = 0x40, OP_MOVI = 0x41, OP_SREG = 0x42,
+    OP_LDS = 0x50, OP_STS = 0x51, OP_LDG = 0x52, OP_STG = 0x53,
+    OP_JMP = 0x60, OP_BZ = 0x61, OP_BNZ = 0x62, OP_BAR = 0x63, OP_EXIT = 0x64,
+};
+constexpr uint32_t N_SREGS = 24;
+constexpr uint32_t MAX_INSTR = 1u << 16;
+constexpr uint32_t MAX_THREADS = 1024;
+constexpr uint32_t MAX_SHMEM_WORDS = 16384;     // 64 KiB of simulated shared memory
+
+enum : uint32_t { F_DEADLOCK = 1, F_DIVERGENCE = 2, F_OOB = 3, F_FUEL = 4, F_ARITH = 5 };
+
+// ---- one (instance, launch) as the device sees it -------------------------
+struct DevUnit {
+    const uint64_t *prog;
+    int32_t *mem;           // caller's memory (final memory lands here)
+    const int32_t *snap;    // launch-start snapshot of mem
+    uint32_t n_instr;
+    uint32_t n_words;
+    uint32_t gdim[3];
+    uint32_t bdim[3];
+    uint32_t nt, nb;
+    uint32_t sh_words;
+    uint32_t fuel;
+    int32_t params[8];
+    uint32_t block_base;    // index of block 0 in the per-block arrays
+    uint32_t pad;
+};
+
+// Bit layout of a 64-bit access record, least significant field first:
+//   kind(1) | tid(tb) | epoch(eb) | block(bb) | addr(ab) | space(1) | unit(ub)
+// The sort orders records by the bits above tid; kind and tid ride along.
+struct KeyPlan {
+    uint32_t tb, eb, bb, ab, ub;
+    uint32_t s_tid, s_ep, s_blk, s_addr, s_sp, s_unit, total;
+    uint32_t max_epoch;     // largest epoch the field holds
+    uint32_t pad;
+};
+
+__host__ __device__ inline uint64_t rec_pack(const KeyPlan &k, uint32_t unit, uint32_t space, uint32_t addr,
+                                             uint32_t block, uint32_t epoch, uint32_t tid, uint32_t kind) {
+    return (uint64_t)kind | ((uint64_t)tid << k.s_tid) | ((uint64_t)epoch << k.s_ep) |
+           ((uint64_t)block << k.s_blk) | ((uint64_t)addr << k.s_addr) | ((uint64_t)space << k.s_sp) |
+           ((uint64_t)unit << k.s_unit);
+}
+__host__ __device__ inline uint32_t rec_field(uint64_t r, uint32_t shift, uint32_t width) {
+    return width ? (uint32_t)((r >> shift) & ((1ull << width) - 1)) : 0u;
+}
+
+struct DevFault { uint32_t unit, kind, block, epoch, a, b, c, d; };
+struct DevRace { uint32_t unit, space, scope, block, epoch, addr, w, o; };
+struct DevEdge { uint32_t unit, b0, b1, pad; };
+
+// flags word bits
+enum : uint32_t {
+    FLAG_LOG_OVERFLOW = 1u << 0,
+    FLAG_FAULT_OVERFLOW = 1u << 1,
+    FLAG_EPOCH_OVERFLOW = 1u << 2,
+    FLAG_RACE_OVERFLOW = 1u << 3,
+    FLAG_EDGE_OVERFLOW = 1u << 4,
+    FLAG_MISMATCH = 1u << 5,
+};
+
+// Counters in one small device block (zeroed before a stage).
+struct DevCounters {
+    unsigned long long log_count;
+    unsigned long long aux_count;
+    uint32_t fault_count;
+    uint32_t race_count;
+    uint32_t edge_count;
+    uint32_t flags;
+    uint32_t max_epoch;
+    uint32_t pad[9];
+};
+
+struct InterpArgs {
+    const DevUnit *units;
+    const uint2 *items;         // (unit, block) per workgroup; null: unit 0, block = blockIdx.x
+    const uint32_t *comp_off;   // lockstep replay: blocks of component c are comp_blocks[comp_off[c] .. comp_off[c+1])
+    const uint2 *comp_blocks;   // (unit, block)
+    KeyPlan kp;
+    uint64_t *log;
+    unsigned long long log_cap;
+    unsigned long long *log_count;
+    DevFault *faults;
+    uint32_t fault_cap;
+    uint32_t *fault_count;
+    uint32_t *blk_recs;         // per-block record counts (added to)
+    uint32_t *flags;
+    uint32_t *max_epoch;        // largest epoch reached (atomicMax)
+    uint32_t sh_words_max;      // simulated shared words reserved in LDS
+    uint32_t stage;             // staged records per wave
+};
+
+// Host-side launchers (defined in the .hip files).
+hipError_t launch_interp(const InterpArgs &a, uint32_t n_wg, uint32_t wg_threads, bool lockstep, hipStream_t s);
+size_t interp_lds_bytes(uint32_t sh_words_max, uint32_t wg_threads, uint32_t stage);
+
+struct SortScratch {
+    uint64_t *alt = nullptr;         // ping-pong buffer, >= n keys
+    uint32_t *hist = nullptr;        // n_tiles * 256
+    uint32_t *part = nullptr;        // chunk partials
+    size_t cap_keys = 0, cap_hist = 0, cap_part = 0;
+};
+// Virtual sort key of a record: the bits from s_blk up, then the low ueb bits
+// of the epoch field, then the low pb bits (payload); vbits bits in all.
+struct VKey {
+    uint32_t s_ep, ueb, s_blk, pb, vbits;
+};
+// Sort keys[0..n) ascending by the virtual key (stable).  *out points at the
+// sorted array: keys itself or scratch.alt.
+hipError_t radix_sort(uint64_t *keys, uint64_t n, const VKey &vk, SortScratch &sc,
+                      uint32_t tile, hipStream_t s, uint64_t **out);
+size_t radix_hist_entries(uint64_t n, uint32_t tile);
+
+struct CheckArgs {
+    const uint64_t *keys;
+    uint64_t n;
+    KeyPlan kp;
+    const DevUnit *units;
+    DevRace *races;
+    uint32_t race_cap;
+    DevEdge *edges;
+    uint32_t edge_cap;
+    uint32_t *blk_flags;
+    DevCounters *ctr;
+};
+hipError_t launch_check(const CheckArgs &a, hipStream_t s);
+hipError_t launch_restore(const uint64_t *keys, uint64_t n, KeyPlan kp, const DevUnit *units,
+                          const uint32_t *blk_flags, hipStream_t s);
+hipError_t launch_extract(const uint64_t *keys, uint64_t n, KeyPlan kp, const DevUnit *units,
+                          const uint32_t *blk_flags, uint64_t *out, uint64_t out_cap,
+                          unsigned long long *out_count, hipStream_t s);
+hipError_t launch_compare(const uint64_t *x, const uint64_t *y, uint64_t n, uint32_t *flags, hipStream_t s);
+hipError_t launch_copy_units(const DevUnit *units, uint32_t n_units, uint32_t max_words, bool to_snapshot,
+                             const uint32_t *unit_mask, hipStream_t s);
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);
+
+}  // namespace kc

@@ -1,0 +1,1091 @@
+// Host runtime and C ABI of libkc (see include/kc.h).
+//
+// A stage processes one launch of each of a set of jobs ("units"):
+//   1. snapshot every unit's memory (replay needs the launch-start state);
+//   2. free-run interpretation: one workgroup per simulated block, records to
+//      the HBM log;
+//   3. LSD radix sort of the log on the bits above (tid, kind);
+//   4. conflict check: race tuples, racy blocks and cross-block links;
+//   5. if there are races: the blocks linked by races form components; their
+//      global writes are restored from the snapshot and the components are
+//      re-executed in lockstep, blocks in ascending order (the canonical
+//      schedule).  If the replayed records equal the free-run records of those
+//      blocks (as multisets) the free-run verdict stands and only memory and
+//      findings of the replayed blocks change; otherwise every block of the
+//      affected units is re-executed canonically and checked again;
+//   6. reports.
+// For race-free launches every interleaving has the same per-thread traces,
+// so the free run already is the canonical execution.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <condition_variable>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <numeric>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/kc.h"
+#include "kc_internal.h"
+
+using namespace kc;
+
+struct kc_program {
+    std::vector<uint64_t> words;
+    uint64_t *dev = nullptr;
+    int device = 0;
+};
+
+struct kc_report {
+    uint64_t records = 0;
+    uint32_t launches_completed = 0;
+    std::vector<kc_race> races;
+    std::vector<kc_fault> faults;
+    uint64_t tag = 0;
+};
+
+namespace {
+
+struct KcError {
+    kc_status st;
+    std::string msg;
+};
+
+#define HIPCHK(expr)                                                                           \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            throw KcError{KC_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)};    \
+    } while (0)
+
+inline uint32_t bits_for(uint64_t count) {   // bits to hold values 0 .. count-1
+    uint32_t b = 0;
+    while (b < 64 && (1ull << b) < count) b++;
+    return b;
+}
+
+// Grow-only device buffer.
+struct DBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    void reserve(size_t need) {
+        if (need <= bytes) return;
+        size_t nb = std::max(need, bytes + bytes / 2);
+        nb = (nb + 4095) & ~size_t(4095);
+        if (p) HIPCHK(hipFree(p));
+        p = nullptr;
+        bytes = 0;
+        if (hipMalloc(&p, nb) != hipSuccess) {
+            (void)hipGetLastError();
+            nb = (need + 4095) & ~size_t(4095);
+            if (hipMalloc(&p, nb) != hipSuccess) {
+                (void)hipGetLastError();
+                p = nullptr;
+                throw KcError{KC_E_NOMEM, "device allocation of " + std::to_string(need) + " bytes failed"};
+            }
+        }
+        bytes = nb;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <class T> T *as() const { return (T *)p; }
+};
+
+struct Workspace {
+    DBuf units, items, comp_off, comp_blocks, mask;
+    DBuf snap, log, alt, rlog, ralt, fs, hist, part;
+    DBuf faults, rfaults, races, edges, blk_recs, rblk_recs, blk_flags, ctr, rctr;
+    DevCounters *h_ctr = nullptr;   // pinned
+    hipEvent_t ev[8] = {};
+    bool init = false;
+    void setup() {
+        if (init) return;
+        HIPCHK(hipHostMalloc((void **)&h_ctr, sizeof(DevCounters) * 2, hipHostMallocDefault));
+        for (auto &e : ev) HIPCHK(hipEventCreate(&e));
+        init = true;
+    }
+    size_t device_bytes() const {
+        const DBuf *all[] = {&units, &items, &comp_off, &comp_blocks, &mask, &snap, &log, &alt, &rlog,
+                             &ralt, &fs, &hist, &part, &faults, &rfaults, &races, &edges, &blk_recs,
+                             &rblk_recs, &blk_flags, &ctr, &rctr};
+        size_t s = 0;
+        for (auto *b : all) s += b->bytes;
+        return s;
+    }
+    ~Workspace() {
+        DBuf *all[] = {&units, &items, &comp_off, &comp_blocks, &mask, &snap, &log, &alt, &rlog,
+                       &ralt, &fs, &hist, &part, &faults, &rfaults, &races, &edges, &blk_recs,
+                       &rblk_recs, &blk_flags, &ctr, &rctr};
+        for (auto *b : all) b->release();
+        if (h_ctr) (void)hipHostFree(h_ctr);
+        for (auto &e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+};
+
+// One (job, launch) inside a stage.
+struct UnitIn {
+    const kc_launch_desc *desc;
+    int32_t *mem;
+    uint64_t n_words;
+};
+
+struct UnitOut {
+    uint64_t records = 0;
+    bool deadlocked = false;
+    std::vector<kc_race> races;     // launch field filled by the caller
+    std::vector<kc_fault> faults;
+};
+
+struct Options {
+    int check = 1;
+    uint32_t fuel = 1u << 20;
+    int timing = 0;
+    uint32_t sort_tile = 4096;
+    uint64_t log_records = 1ull << 22;
+    uint32_t stage = 256;
+};
+
+}  // namespace
+
+struct Batch;
+
+struct kc_ctx {
+    int device = 0;
+    uint64_t budget = 0;
+    Options opt;
+    std::string err;
+    bool poisoned = false;
+    std::mutex mu;
+    std::vector<std::unique_ptr<Workspace>> free_ws;
+    std::unordered_map<std::string, double> stats;
+    std::map<uint64_t, std::shared_ptr<Batch>> batches;
+    uint64_t next_ticket = 1;
+    std::unique_ptr<Workspace> acquire() {
+        std::lock_guard<std::mutex> g(mu);
+        if (!free_ws.empty()) {
+            auto w = std::move(free_ws.back());
+            free_ws.pop_back();
+            return w;
+        }
+        return std::make_unique<Workspace>();
+    }
+    void release(std::unique_ptr<Workspace> w) {
+        std::lock_guard<std::mutex> g(mu);
+        free_ws.push_back(std::move(w));
+    }
+    void stat_add(const char *k, double v) {
+        std::lock_guard<std::mutex> g(mu);
+        stats[k] += v;
+    }
+};
+
+struct Batch {
+    std::vector<kc_job> jobs;
+    std::vector<std::vector<kc_launch_desc>> descs;
+    hipStream_t stream = nullptr;
+    std::thread worker;
+    std::mutex mu;
+    std::condition_variable cv;
+    bool done = false;
+    kc_status status = KC_OK;
+    std::string err;
+    std::vector<kc_report *> reports;
+};
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// validation
+// ---------------------------------------------------------------------------
+bool valid_opcode(uint32_t op) {
+    const uint32_t base = op & ~uint32_t(OP_IMM);
+    if (base >= OP_ADD && base <= OP_SLTU) return true;
+    switch (op) {
+    case OP_MOV: case OP_MOVI: case OP_SREG: case OP_LDS: case OP_STS: case OP_LDG: case OP_STG:
+    case OP_JMP: case OP_BZ: case OP_BNZ: case OP_BAR: case OP_EXIT:
+        return true;
+    default:
+        return false;
+    }
+}
+
+std::string validate_program(const uint64_t *w, uint32_t n) {
+    if (n == 0 || n > MAX_INSTR) return "program length must be in [1, 65536]";
+    for (uint32_t pc = 0; pc < n; pc++) {
+        const uint32_t op = w[pc] & 0xFF, d = (w[pc] >> 8) & 0xFF, a = (w[pc] >> 16) & 0xFF,
+                       b = (w[pc] >> 24) & 0xFF;
+        const int32_t imm = (int32_t)(uint32_t)(w[pc] >> 32);
+        if (!valid_opcode(op)) return "unknown opcode at pc " + std::to_string(pc);
+        if (d >= 16 || a >= 16 || b >= 16) return "register out of range at pc " + std::to_string(pc);
+        if ((op == OP_JMP || op == OP_BZ || op == OP_BNZ) && (imm < 0 || (uint32_t)imm > n))
+            return "branch target out of range at pc " + std::to_string(pc);
+        if (op == OP_SREG && (imm < 0 || (uint32_t)imm >= N_SREGS))
+            return "special register out of range at pc " + std::to_string(pc);
+    }
+    return "";
+}
+
+std::string validate_desc(const kc_launch_desc *d, int32_t *mem, uint64_t n_words) {
+    if (!d || !d->prog) return "launch without a program";
+    const uint64_t nt = (uint64_t)d->block.x * d->block.y * d->block.z;
+    const uint64_t nb = (uint64_t)d->grid.x * d->grid.y * d->grid.z;
+    if (nt == 0 || nt > MAX_THREADS) return "threads per block must be in [1, 1024]";
+    if (nb == 0 || nb * nt > 0xFFFFFFFFull) return "grid must be non-empty and blocks*threads < 2^32";
+    if (d->shmem_bytes % 4 || d->shmem_bytes / 4 > MAX_SHMEM_WORDS) return "shmem_bytes must be a multiple of 4, <= 65536";
+    if (d->n_params > 8) return "at most 8 params";
+    if (!mem && n_words) return "null device memory";
+    if (n_words >= (1ull << 31)) return "memory must be < 2^31 words";
+    return "";
+}
+
+// ---------------------------------------------------------------------------
+// union-find for racy components
+// ---------------------------------------------------------------------------
+struct DSU {
+    std::unordered_map<uint64_t, uint64_t> p;
+    uint64_t find(uint64_t x) {
+        auto it = p.find(x);
+        if (it == p.end()) { p[x] = x; return x; }
+        uint64_t r = x;
+        while (p[r] != r) r = p[r];
+        while (p[x] != r) { uint64_t n = p[x]; p[x] = r; x = n; }
+        return r;
+    }
+    void unite(uint64_t a, uint64_t b) {
+        a = find(a);
+        b = find(b);
+        if (a != b) p[std::max(a, b)] = std::min(a, b);
+    }
+};
+
+inline uint64_t ub_key(uint32_t unit, uint32_t block) { return ((uint64_t)unit << 32) | block; }
+
+bool fault_less(const kc_fault &x, const kc_fault &y) {
+    const uint32_t kx[8] = {x.launch, x.block, x.epoch, x.kind, x.a, x.b, x.c, x.d};
+    const uint32_t ky[8] = {y.launch, y.block, y.epoch, y.kind, y.a, y.b, y.c, y.d};
+    return std::lexicographical_compare(kx, kx + 8, ky, ky + 8);
+}
+bool fault_eq(const kc_fault &x, const kc_fault &y) { return !fault_less(x, y) && !fault_less(y, x); }
+bool race_less(const kc_race &x, const kc_race &y) {
+    const uint32_t kx[6] = {x.launch, x.space, x.scope, x.block, x.epoch, x.addr};
+    const uint32_t ky[6] = {y.launch, y.space, y.scope, y.block, y.epoch, y.addr};
+    return std::lexicographical_compare(kx, kx + 6, ky, ky + 6);
+}
+
+struct Timer {
+    kc_ctx *ctx;
+    Workspace &ws;
+    hipStream_t s;
+    bool on;
+    int idx = 0;
+    void mark(int i) {
+        if (on) HIPCHK(hipEventRecord(ws.ev[i], s));
+    }
+    double ms(int a, int b) {
+        if (!on) return 0.0;
+        float v = 0.f;
+        HIPCHK(hipEventSynchronize(ws.ev[b]));
+        HIPCHK(hipEventElapsedTime(&v, ws.ev[a], ws.ev[b]));
+        return v;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// one stage
+// ---------------------------------------------------------------------------
+struct Stage {
+    kc_ctx *ctx;
+    Workspace &ws;
+    hipStream_t s;
+    const std::vector<UnitIn> &in;
+    std::vector<UnitOut> &out;
+
+    std::vector<DevUnit> hu;
+    KeyPlan kp{};
+    uint32_t total_blocks = 0;
+    uint64_t total_words = 0;
+    uint32_t max_words = 0;
+    uint32_t used_epoch_bits = 0;
+
+    // Sort order for the check: bits from the block field up, then the used
+    // epoch bits; the full order for multiset comparison adds tid and kind.
+    VKey check_key() const { return VKey{kp.s_ep, used_epoch_bits, kp.s_blk, 0, used_epoch_bits + (kp.total - kp.s_blk)}; }
+    VKey full_key() const {
+        return VKey{kp.s_ep, used_epoch_bits, kp.s_blk, kp.s_ep, kp.s_ep + used_epoch_bits + (kp.total - kp.s_blk)};
+    }
+    std::vector<uint32_t> blk_recs;
+
+    DevCounters read_ctr(DBuf &c) {
+        HIPCHK(hipMemcpyAsync(ws.h_ctr, c.p, sizeof(DevCounters), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        return *ws.h_ctr;
+    }
+
+    void plan() {
+        const uint32_t n = (uint32_t)in.size();
+        hu.resize(n);
+        uint64_t max_nt = 1, max_nb = 1, max_addr = 1;
+        total_blocks = 0;
+        total_words = 0;
+        for (uint32_t i = 0; i < n; i++) {
+            const kc_launch_desc *d = in[i].desc;
+            DevUnit &u = hu[i];
+            std::memset(&u, 0, sizeof(u));
+            u.prog = d->prog->dev;
+            u.mem = in[i].mem;
+            u.n_instr = (uint32_t)d->prog->words.size();
+            u.n_words = (uint32_t)in[i].n_words;
+            u.gdim[0] = d->grid.x; u.gdim[1] = d->grid.y; u.gdim[2] = d->grid.z;
+            u.bdim[0] = d->block.x; u.bdim[1] = d->block.y; u.bdim[2] = d->block.z;
+            u.nt = d->block.x * d->block.y * d->block.z;
+            u.nb = d->grid.x * d->grid.y * d->grid.z;
+            u.sh_words = d->shmem_bytes / 4;
+            u.fuel = ctx->opt.fuel;
+            for (uint32_t p = 0; p < 8; p++) u.params[p] = p < d->n_params ? d->params[p] : 0;
+            u.block_base = total_blocks;
+            total_blocks += u.nb;
+            total_words += u.n_words;
+            max_words = std::max(max_words, u.n_words);
+            max_nt = std::max<uint64_t>(max_nt, u.nt);
+            max_nb = std::max<uint64_t>(max_nb, u.nb);
+            max_addr = std::max<uint64_t>(max_addr, std::max<uint64_t>(u.n_words, u.sh_words));
+        }
+        kp.tb = bits_for(max_nt);
+        kp.bb = bits_for(max_nb);
+        kp.ab = bits_for(max_addr);
+        kp.ub = bits_for(n);
+        const int used = 1 + (int)kp.tb + (int)kp.bb + (int)kp.ab + 1 + (int)kp.ub;
+        int eb = std::min(63 - used, 24);   // keep every shift below 64
+        if (eb < 1)
+            throw KcError{KC_E_OVERFLOW, "record fields need more than 64 bits (" + std::to_string(used) + " + epoch)"};
+        kp.eb = (uint32_t)eb;
+        kp.s_tid = 1;
+        kp.s_ep = kp.s_tid + kp.tb;
+        kp.s_blk = kp.s_ep + kp.eb;
+        kp.s_addr = kp.s_blk + kp.bb;
+        kp.s_sp = kp.s_addr + kp.ab;
+        kp.s_unit = kp.s_sp + 1;
+        kp.total = kp.s_unit + kp.ub;
+        kp.max_epoch = (uint32_t)((1ull << kp.eb) - 1);
+    }
+
+    void upload_units() {
+        ws.units.reserve(hu.size() * sizeof(DevUnit));
+        HIPCHK(hipMemcpyAsync(ws.units.p, hu.data(), hu.size() * sizeof(DevUnit), hipMemcpyHostToDevice, s));
+    }
+
+    void reset_counters(DBuf &c) {
+        c.reserve(sizeof(DevCounters));
+        HIPCHK(launch_zero(c.p, sizeof(DevCounters), s));
+    }
+
+    // Interpreter launches for all units, grouped by workgroup size.
+    void interp(bool lockstep, DBuf &logbuf, uint64_t log_cap, DBuf &ctr, DBuf &faults, uint32_t fault_cap,
+                DBuf &recs, uint32_t n_comp) {
+        InterpArgs a{};
+        a.units = ws.units.as<DevUnit>();
+        a.kp = kp;
+        a.log = logbuf.as<uint64_t>();
+        a.log_cap = log_cap;
+        a.log_count = &ctr.as<DevCounters>()->log_count;
+        a.faults = faults.as<DevFault>();
+        a.fault_cap = fault_cap;
+        a.fault_count = &ctr.as<DevCounters>()->fault_count;
+        a.blk_recs = recs.as<uint32_t>();
+        a.flags = &ctr.as<DevCounters>()->flags;
+        a.max_epoch = &ctr.as<DevCounters>()->max_epoch;
+        a.stage = ctx->opt.stage;
+        if (lockstep) {
+            uint32_t wg = 64, shmax = 0;
+            for (auto &u : hu) {
+                wg = std::max<uint32_t>(wg, (u.nt + 63) / 64 * 64);
+                shmax = std::max(shmax, u.sh_words);
+            }
+            a.comp_off = ws.comp_off.as<uint32_t>();
+            a.comp_blocks = ws.comp_blocks.as<uint2>();
+            a.sh_words_max = shmax;
+            HIPCHK(launch_interp(a, n_comp, wg, true, s));
+            return;
+        }
+        // free run: one launch per workgroup-size class
+        std::map<uint32_t, std::vector<uint32_t>> classes;   // wg -> unit ids
+        for (uint32_t i = 0; i < hu.size(); i++) classes[(hu[i].nt + 63) / 64 * 64].push_back(i);
+        if (hu.size() == 1) {
+            a.items = nullptr;
+            a.sh_words_max = hu[0].sh_words;
+            HIPCHK(launch_interp(a, hu[0].nb, (hu[0].nt + 63) / 64 * 64, false, s));
+            return;
+        }
+        std::vector<uint2> items;
+        items.reserve(total_blocks);
+        std::vector<std::pair<size_t, size_t>> ranges;
+        for (auto &kv : classes) {
+            size_t b0 = items.size();
+            for (uint32_t ui : kv.second)
+                for (uint32_t b = 0; b < hu[ui].nb; b++) items.push_back(make_uint2(ui, b));
+            ranges.push_back({b0, items.size()});
+        }
+        ws.items.reserve(items.size() * sizeof(uint2));
+        HIPCHK(hipMemcpyAsync(ws.items.p, items.data(), items.size() * sizeof(uint2), hipMemcpyHostToDevice, s));
+        size_t ci = 0;
+        for (auto &kv : classes) {
+            uint32_t shmax = 0;
+            for (uint32_t ui : kv.second) shmax = std::max(shmax, hu[ui].sh_words);
+            a.items = ws.items.as<uint2>() + ranges[ci].first;
+            a.sh_words_max = shmax;
+            HIPCHK(launch_interp(a, (uint32_t)(ranges[ci].second - ranges[ci].first), kv.first, false, s));
+            ci++;
+        }
+    }
+
+    void run() {
+        plan();
+        const uint32_t n = (uint32_t)hu.size();
+        out.assign(n, UnitOut{});
+        const bool check = ctx->opt.check != 0;
+        Timer tm{ctx, ws, s, ctx->opt.timing != 0};
+
+        // snapshot buffer: each unit's memory at launch start
+        if (check) {
+            ws.snap.reserve(std::max<uint64_t>(total_words, 1) * 4);
+            uint64_t off = 0;
+            for (auto &u : hu) {
+                u.snap = ws.snap.as<int32_t>() + off;
+                off += u.n_words;
+            }
+        }
+        if (ctx->budget && ws.device_bytes() > ctx->budget)
+            throw KcError{KC_E_BUDGET, "workspace exceeds the HBM budget"};
+        upload_units();
+        if (check) HIPCHK(launch_copy_units(ws.units.as<DevUnit>(), n, max_words, true, nullptr, s));
+
+        uint64_t log_cap = check ? std::max<uint64_t>(ctx->opt.log_records, 1024) : 0;
+        if (check) ws.log.reserve(log_cap * 8);
+        uint32_t fault_cap = 4096;
+        ws.blk_recs.reserve((size_t)total_blocks * 4);
+        ws.blk_flags.reserve((size_t)total_blocks * 4);
+        DevCounters c{};
+        for (;;) {
+            ws.faults.reserve((size_t)fault_cap * sizeof(DevFault));
+            reset_counters(ws.ctr);
+            HIPCHK(launch_zero(ws.blk_recs.p, (size_t)total_blocks * 4, s));
+            tm.mark(0);
+            interp(false, ws.log, log_cap, ws.ctr, ws.faults, fault_cap, ws.blk_recs, 0);
+            tm.mark(1);
+            c = read_ctr(ws.ctr);
+            ctx->stat_add("interp_ms", tm.ms(0, 1));
+            ctx->stat_add("interp_launches", 1);
+            if (c.flags & FLAG_EPOCH_OVERFLOW)
+                throw KcError{KC_E_OVERFLOW, "barrier epochs exceed the record's epoch field"};
+            bool again = false;
+            if (check && (c.flags & FLAG_LOG_OVERFLOW)) {
+                log_cap = c.log_count + c.log_count / 8 + 1024;
+                if (ctx->budget && ws.device_bytes() + log_cap * 16 > ctx->budget)
+                    throw KcError{KC_E_BUDGET, "access log does not fit the HBM budget"};
+                ws.log.reserve(log_cap * 8);
+                again = true;
+            }
+            if (c.flags & FLAG_FAULT_OVERFLOW) {
+                fault_cap = c.fault_count + c.fault_count / 8 + 1024;
+                again = true;
+            }
+            if (!again) break;
+            if (!check) throw KcError{KC_E_OVERFLOW, "findings overflow with check disabled"};
+            HIPCHK(launch_copy_units(ws.units.as<DevUnit>(), n, max_words, false, nullptr, s));   // back to launch start
+            ctx->stat_add("retries", 1);
+        }
+        if (check) ctx->opt.log_records = std::max<uint64_t>(ctx->opt.log_records, c.log_count + c.log_count / 8);
+        used_epoch_bits = bits_for((uint64_t)c.max_epoch + 1);
+
+        blk_recs.resize(total_blocks);
+        HIPCHK(hipMemcpyAsync(blk_recs.data(), ws.blk_recs.p, (size_t)total_blocks * 4, hipMemcpyDeviceToHost, s));
+        std::vector<DevFault> faults(std::min<uint32_t>(c.fault_count, fault_cap));
+        if (!faults.empty())
+            HIPCHK(hipMemcpyAsync(faults.data(), ws.faults.p, faults.size() * sizeof(DevFault),
+                                  hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        ctx->stat_add("records", (double)c.log_count);
+
+        std::vector<DevRace> races;
+        std::vector<DevEdge> edges;
+        uint64_t *sorted = ws.log.as<uint64_t>();
+        const uint64_t nrec = c.log_count;
+        if (check && nrec) {
+            SortScratch sc;
+            ws.alt.reserve(nrec * 8);
+            ws.hist.reserve(radix_hist_entries(nrec, ctx->opt.sort_tile) * 4);
+            ws.part.reserve(((radix_hist_entries(nrec, ctx->opt.sort_tile) / 256 + 255) / 256 + 1) * 256 * 4);
+            sc.alt = ws.alt.as<uint64_t>();
+            sc.hist = ws.hist.as<uint32_t>();
+            sc.part = ws.part.as<uint32_t>();
+            tm.mark(2);
+            HIPCHK(radix_sort(ws.log.as<uint64_t>(), nrec, check_key(), sc, ctx->opt.sort_tile, s, &sorted));
+            tm.mark(3);
+            uint32_t race_cap = 4096, edge_cap = 4096;
+            for (;;) {
+                ws.races.reserve((size_t)race_cap * sizeof(DevRace));
+                ws.edges.reserve((size_t)edge_cap * sizeof(DevEdge));
+                reset_counters(ws.rctr);
+                HIPCHK(launch_zero(ws.blk_flags.p, (size_t)total_blocks * 4, s));
+                CheckArgs ca{};
+                ca.keys = sorted;
+                ca.n = nrec;
+                ca.kp = kp;
+                ca.units = ws.units.as<DevUnit>();
+                ca.races = ws.races.as<DevRace>();
+                ca.race_cap = race_cap;
+                ca.edges = ws.edges.as<DevEdge>();
+                ca.edge_cap = edge_cap;
+                ca.blk_flags = ws.blk_flags.as<uint32_t>();
+                ca.ctr = ws.rctr.as<DevCounters>();
+                HIPCHK(launch_check(ca, s));
+                tm.mark(4);
+                DevCounters rc = read_ctr(ws.rctr);
+                if (rc.flags & (FLAG_RACE_OVERFLOW | FLAG_EDGE_OVERFLOW)) {
+                    race_cap = std::max(race_cap, rc.race_count + 1024);
+                    edge_cap = std::max(edge_cap, rc.edge_count + 1024);
+                    continue;
+                }
+                races.resize(rc.race_count);
+                edges.resize(rc.edge_count);
+                if (!races.empty())
+                    HIPCHK(hipMemcpyAsync(races.data(), ws.races.p, races.size() * sizeof(DevRace),
+                                          hipMemcpyDeviceToHost, s));
+                if (!edges.empty())
+                    HIPCHK(hipMemcpyAsync(edges.data(), ws.edges.p, edges.size() * sizeof(DevEdge),
+                                          hipMemcpyDeviceToHost, s));
+                HIPCHK(hipStreamSynchronize(s));
+                break;
+            }
+            ctx->stat_add("sort_ms", tm.ms(2, 3));
+            ctx->stat_add("check_ms", tm.ms(3, 4));
+            ctx->stat_add("sort_keys", (double)nrec);
+        }
+
+        // per-unit findings of the free run
+        std::vector<std::vector<kc_fault>> ufaults(n);
+        for (auto &f : faults) ufaults[f.unit].push_back(kc_fault{0, f.kind, f.block, f.epoch, f.a, f.b, f.c, f.d});
+        std::vector<std::vector<kc_race>> uraces(n);
+        for (auto &r : races)
+            uraces[r.unit].push_back(kc_race{0, r.space, r.scope, r.block, r.epoch, r.addr, r.w, r.o});
+        std::vector<uint64_t> urecs(n, 0);
+        for (uint32_t i = 0; i < n; i++)
+            for (uint32_t b = 0; b < hu[i].nb; b++) urecs[i] += blk_recs[hu[i].block_base + b];
+
+        if (!races.empty()) replay(races, edges, sorted, nrec, ufaults, uraces, urecs, tm);
+
+        for (uint32_t i = 0; i < n; i++) {
+            UnitOut &o = out[i];
+            o.records = urecs[i];
+            o.races = std::move(uraces[i]);
+            std::sort(o.races.begin(), o.races.end(), race_less);
+            o.faults = std::move(ufaults[i]);
+            std::sort(o.faults.begin(), o.faults.end(), fault_less);
+            o.faults.erase(std::unique(o.faults.begin(), o.faults.end(), fault_eq), o.faults.end());
+            o.deadlocked = std::any_of(o.faults.begin(), o.faults.end(),
+                                       [](const kc_fault &f) { return f.kind == KC_DEADLOCK; });
+        }
+    }
+
+    void sort_full(DBuf &keys, DBuf &alt, uint64_t n, uint64_t **res) {
+        SortScratch sc;
+        alt.reserve(std::max<uint64_t>(n, 1) * 8);
+        ws.hist.reserve(radix_hist_entries(n, ctx->opt.sort_tile) * 4);
+        ws.part.reserve(((radix_hist_entries(n, ctx->opt.sort_tile) / 256 + 255) / 256 + 1) * 256 * 4);
+        sc.alt = alt.as<uint64_t>();
+        sc.hist = ws.hist.as<uint32_t>();
+        sc.part = ws.part.as<uint32_t>();
+        HIPCHK(radix_sort(keys.as<uint64_t>(), n, full_key(), sc, ctx->opt.sort_tile, s, res));
+    }
+
+    // Lockstep re-execution of `comps` (lists of (unit, block)); returns the
+    // replay counters.  The replay log ends up in ws.rlog.
+    // Upload components (lists of (unit, block)) for the lockstep kernel.
+    void upload_comps(const std::vector<std::vector<uint2>> &comps) {
+        std::vector<uint32_t> off{0};
+        std::vector<uint2> blocks;
+        for (auto &c : comps) {
+            blocks.insert(blocks.end(), c.begin(), c.end());
+            off.push_back((uint32_t)blocks.size());
+        }
+        ws.comp_off.reserve(off.size() * 4);
+        ws.comp_blocks.reserve(blocks.size() * sizeof(uint2));
+        HIPCHK(hipMemcpyAsync(ws.comp_off.p, off.data(), off.size() * 4, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(ws.comp_blocks.p, blocks.data(), blocks.size() * sizeof(uint2), hipMemcpyHostToDevice, s));
+    }
+
+    // One lockstep pass over `comps`; records go to ws.rlog (capacity rcap).
+    DevCounters lockstep_once(const std::vector<std::vector<uint2>> &comps, uint64_t rcap, uint32_t fcap) {
+        upload_comps(comps);
+        ws.rblk_recs.reserve((size_t)total_blocks * 4);
+        ws.rlog.reserve(rcap * 8);
+        ws.rfaults.reserve((size_t)fcap * sizeof(DevFault));
+        reset_counters(ws.rctr);
+        HIPCHK(launch_zero(ws.rblk_recs.p, (size_t)total_blocks * 4, s));
+        interp(true, ws.rlog, rcap, ws.rctr, ws.rfaults, fcap, ws.rblk_recs, (uint32_t)comps.size());
+        DevCounters c = read_ctr(ws.rctr);
+        if (c.flags & FLAG_EPOCH_OVERFLOW)
+            throw KcError{KC_E_OVERFLOW, "barrier epochs exceed the record's epoch field"};
+        return c;
+    }
+
+    void replay(const std::vector<DevRace> &races, const std::vector<DevEdge> &edges, const uint64_t *sorted,
+                uint64_t nrec, std::vector<std::vector<kc_fault>> &ufaults,
+                std::vector<std::vector<kc_race>> &uraces, std::vector<uint64_t> &urecs, Timer &tm) {
+        tm.mark(5);
+        DSU dsu;
+        for (auto &r : races) {
+            if (r.scope == 0) dsu.find(ub_key(r.unit, r.block));
+            else dsu.find(ub_key(r.unit, r.block));
+        }
+        for (auto &e : edges) dsu.unite(ub_key(e.unit, e.b0), ub_key(e.unit, e.b1));
+        std::map<uint64_t, std::vector<uint2>> groups;
+        std::vector<uint64_t> keys;
+        for (auto &kv : dsu.p) keys.push_back(kv.first);
+        for (uint64_t k : keys) groups[dsu.find(k)].push_back(make_uint2((uint32_t)(k >> 32), (uint32_t)k));
+        std::vector<std::vector<uint2>> comps;
+        uint64_t s_recs = 0;
+        for (auto &kv : groups) {
+            auto v = kv.second;
+            std::sort(v.begin(), v.end(), [](uint2 a, uint2 b) { return a.x != b.x ? a.x < b.x : a.y < b.y; });
+            for (auto &ub : v) s_recs += blk_recs[hu[ub.x].block_base + ub.y];
+            comps.push_back(std::move(v));
+        }
+        ctx->stat_add("replays", (double)comps.size());
+
+        // restore what the racy blocks wrote, then re-execute them canonically
+        HIPCHK(launch_restore(sorted, nrec, kp, ws.units.as<DevUnit>(), ws.blk_flags.as<uint32_t>(), s));
+        uint64_t rcap = s_recs + s_recs / 4 + 1024;
+        uint32_t fcap = 4096;
+        DevCounters rc = lockstep_once(comps, rcap, fcap);
+
+        // compare replayed records with the free-run records of the same blocks
+        bool same = false;
+        if (rc.log_count == s_recs && !(rc.flags & (FLAG_LOG_OVERFLOW | FLAG_FAULT_OVERFLOW))) {
+            ws.fs.reserve(std::max<uint64_t>(s_recs, 1) * 8);
+            reset_counters(ws.ctr);
+            HIPCHK(launch_extract(sorted, nrec, kp, ws.units.as<DevUnit>(), ws.blk_flags.as<uint32_t>(),
+                                  ws.fs.as<uint64_t>(), s_recs, &ws.ctr.as<DevCounters>()->aux_count, s));
+            uint64_t *fs_sorted = nullptr, *rs_sorted = nullptr;
+            sort_full(ws.fs, ws.alt, s_recs, &fs_sorted);
+            sort_full(ws.rlog, ws.ralt, s_recs, &rs_sorted);
+            HIPCHK(launch_compare(fs_sorted, rs_sorted, s_recs, &ws.ctr.as<DevCounters>()->flags, s));
+            DevCounters cc = read_ctr(ws.ctr);
+            same = cc.aux_count == s_recs && !(cc.flags & FLAG_MISMATCH);
+        }
+        std::vector<DevFault> rf(std::min<uint32_t>(rc.fault_count, fcap));
+        if (!rf.empty())
+            HIPCHK(hipMemcpyAsync(rf.data(), ws.rfaults.p, rf.size() * sizeof(DevFault), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+
+        if (same) {
+            // verdict stands; findings of the replayed blocks come from the replay
+            std::vector<char> in_s(total_blocks, 0);
+            for (auto &c : comps)
+                for (auto &ub : c) in_s[hu[ub.x].block_base + ub.y] = 1;
+            for (uint32_t u = 0; u < hu.size(); u++) {
+                auto &fv = ufaults[u];
+                fv.erase(std::remove_if(fv.begin(), fv.end(),
+                                        [&](const kc_fault &f) { return in_s[hu[u].block_base + f.block]; }),
+                         fv.end());
+            }
+            for (auto &f : rf) ufaults[f.unit].push_back(kc_fault{0, f.kind, f.block, f.epoch, f.a, f.b, f.c, f.d});
+            tm.mark(6);
+            ctx->stat_add("replay_ms", tm.ms(5, 6));
+            return;
+        }
+
+        // General case: the racy blocks' accesses depended on racy values.  Re-run
+        // every block of the affected units canonically from the snapshot.
+        ctx->stat_add("fallbacks", 1);
+        std::vector<uint32_t> mask(hu.size(), 0);
+        for (auto &c : comps)
+            for (auto &ub : c) mask[ub.x] = 1;
+        ws.mask.reserve(mask.size() * 4);
+        HIPCHK(hipMemcpyAsync(ws.mask.p, mask.data(), mask.size() * 4, hipMemcpyHostToDevice, s));
+        HIPCHK(launch_copy_units(ws.units.as<DevUnit>(), (uint32_t)hu.size(), max_words, false, ws.mask.as<uint32_t>(), s));
+        std::vector<std::vector<uint2>> full;
+        uint64_t need = 0;
+        for (uint32_t u = 0; u < hu.size(); u++) {
+            if (!mask[u]) continue;
+            std::vector<uint2> v;
+            for (uint32_t b = 0; b < hu[u].nb; b++) {
+                v.push_back(make_uint2(u, b));
+                need += blk_recs[hu[u].block_base + b];
+            }
+            full.push_back(std::move(v));
+        }
+        rcap = std::max<uint64_t>(rcap, need + need / 4 + 1024);
+        DevCounters fc;
+        for (;;) {   // a full re-run starts from the snapshot of the whole unit
+            fc = lockstep_once(full, rcap, fcap);
+            if (!(fc.flags & (FLAG_LOG_OVERFLOW | FLAG_FAULT_OVERFLOW))) break;
+            rcap = std::max<uint64_t>(rcap, fc.log_count + 1024);
+            fcap = std::max<uint32_t>(fcap, fc.fault_count + 1024);
+            HIPCHK(launch_copy_units(ws.units.as<DevUnit>(), (uint32_t)hu.size(), max_words, false,
+                                     ws.mask.as<uint32_t>(), s));
+        }
+        std::vector<DevFault> ff(std::min<uint32_t>(fc.fault_count, fcap));
+        if (!ff.empty())
+            HIPCHK(hipMemcpyAsync(ff.data(), ws.rfaults.p, ff.size() * sizeof(DevFault), hipMemcpyDeviceToHost, s));
+        std::vector<uint32_t> rrecs(total_blocks);
+        HIPCHK(hipMemcpyAsync(rrecs.data(), ws.rblk_recs.p, (size_t)total_blocks * 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        // check the canonical records
+        uint64_t *rs_sorted = nullptr;
+        {
+            SortScratch sc;
+            ws.ralt.reserve(std::max<uint64_t>(fc.log_count, 1) * 8);
+            ws.hist.reserve(radix_hist_entries(fc.log_count, ctx->opt.sort_tile) * 4);
+            ws.part.reserve(((radix_hist_entries(fc.log_count, ctx->opt.sort_tile) / 256 + 255) / 256 + 1) * 256 * 4);
+            sc.alt = ws.ralt.as<uint64_t>();
+            sc.hist = ws.hist.as<uint32_t>();
+            sc.part = ws.part.as<uint32_t>();
+            used_epoch_bits = std::max(used_epoch_bits, bits_for((uint64_t)fc.max_epoch + 1));
+            HIPCHK(radix_sort(ws.rlog.as<uint64_t>(), fc.log_count, check_key(), sc, ctx->opt.sort_tile, s,
+                              &rs_sorted));
+        }
+        uint32_t race_cap = 4096, edge_cap = 4096;
+        std::vector<DevRace> nr;
+        for (;;) {
+            ws.races.reserve((size_t)race_cap * sizeof(DevRace));
+            ws.edges.reserve((size_t)edge_cap * sizeof(DevEdge));
+            reset_counters(ws.rctr);
+            HIPCHK(launch_zero(ws.blk_flags.p, (size_t)total_blocks * 4, s));
+            CheckArgs ca{};
+            ca.keys = rs_sorted;
+            ca.n = fc.log_count;
+            ca.kp = kp;
+            ca.units = ws.units.as<DevUnit>();
+            ca.races = ws.races.as<DevRace>();
+            ca.race_cap = race_cap;
+            ca.edges = ws.edges.as<DevEdge>();
+            ca.edge_cap = edge_cap;
+            ca.blk_flags = ws.blk_flags.as<uint32_t>();
+            ca.ctr = ws.rctr.as<DevCounters>();
+            HIPCHK(launch_check(ca, s));
+            DevCounters c2 = read_ctr(ws.rctr);
+            if (c2.flags & (FLAG_RACE_OVERFLOW | FLAG_EDGE_OVERFLOW)) {
+                race_cap = std::max(race_cap, c2.race_count + 1024);
+                edge_cap = std::max(edge_cap, c2.edge_count + 1024);
+                continue;
+            }
+            nr.resize(c2.race_count);
+            if (!nr.empty())
+                HIPCHK(hipMemcpyAsync(nr.data(), ws.races.p, nr.size() * sizeof(DevRace), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            break;
+        }
+        for (uint32_t u = 0; u < hu.size(); u++) {
+            if (!mask[u]) continue;
+            uraces[u].clear();
+            ufaults[u].clear();
+            urecs[u] = 0;
+            for (uint32_t b = 0; b < hu[u].nb; b++) urecs[u] += rrecs[hu[u].block_base + b];
+        }
+        for (auto &r : nr) uraces[r.unit].push_back(kc_race{0, r.space, r.scope, r.block, r.epoch, r.addr, r.w, r.o});
+        for (auto &f : ff) ufaults[f.unit].push_back(kc_fault{0, f.kind, f.block, f.epoch, f.a, f.b, f.c, f.d});
+        tm.mark(6);
+        ctx->stat_add("replay_ms", tm.ms(5, 6));
+    }
+
+};
+
+kc_status fail(kc_ctx *ctx, const KcError &e) {
+    if (ctx) {
+        ctx->err = e.msg;
+        if (e.st == KC_E_DEVICE) ctx->poisoned = true;
+    }
+    return e.st;
+}
+
+// Run every launch of `jobs` in order, stage by stage (launch index j of all
+// jobs still running), and build one report per job.
+void run_jobs(kc_ctx *ctx, const kc_job *jobs, uint32_t n_jobs, hipStream_t s, std::vector<kc_report *> &reports) {
+    HIPCHK(hipSetDevice(ctx->device));
+    auto wsp = ctx->acquire();
+    Workspace &ws = *wsp;
+    try {
+        ws.setup();
+        reports.assign(n_jobs, nullptr);
+        for (uint32_t j = 0; j < n_jobs; j++) {
+            reports[j] = new kc_report();
+            reports[j]->tag = jobs[j].tag;
+        }
+        std::vector<char> alive(n_jobs, 1);
+        uint32_t max_l = 0;
+        for (uint32_t j = 0; j < n_jobs; j++) max_l = std::max(max_l, jobs[j].n_launches);
+        for (uint32_t li = 0; li < max_l; li++) {
+            std::vector<UnitIn> in;
+            std::vector<uint32_t> who;
+            for (uint32_t j = 0; j < n_jobs; j++) {
+                if (!alive[j] || li >= jobs[j].n_launches) continue;
+                in.push_back(UnitIn{&jobs[j].launches[li], jobs[j].dev_mem, jobs[j].n_words});
+                who.push_back(j);
+            }
+            if (in.empty()) break;
+            std::vector<UnitOut> out;
+            Stage st{ctx, ws, s, in, out};
+            st.run();
+            ctx->stat_add("launches", (double)in.size());
+            for (size_t i = 0; i < who.size(); i++) {
+                kc_report *r = reports[who[i]];
+                UnitOut &o = out[i];
+                r->records += o.records;
+                for (auto &x : o.races) { x.launch = li; r->races.push_back(x); }
+                for (auto &f : o.faults) { f.launch = li; r->faults.push_back(f); }
+                if (o.deadlocked) alive[who[i]] = 0;
+                else r->launches_completed = li + 1;
+            }
+        }
+    } catch (...) {
+        for (auto *r : reports) delete r;
+        reports.clear();
+        ctx->release(std::move(wsp));
+        throw;
+    }
+    ctx->release(std::move(wsp));
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+kc_status kc_ctx_create(int hip_device, uint64_t hbm_budget_bytes, const char *tune_cache, kc_ctx **out) {
+    (void)tune_cache;
+    if (!out) return KC_E_INVAL;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || hip_device < 0 || hip_device >= n) {
+        (void)hipGetLastError();
+        return KC_E_INVAL;
+    }
+    if (hipSetDevice(hip_device) != hipSuccess) return KC_E_DEVICE;
+    kc_ctx *c = new kc_ctx();
+    c->device = hip_device;
+    c->budget = hbm_budget_bytes;
+    *out = c;
+    return KC_OK;
+}
+
+void kc_ctx_destroy(kc_ctx *ctx) {
+    if (!ctx) return;
+    std::vector<std::shared_ptr<Batch>> pending;
+    {
+        std::lock_guard<std::mutex> g(ctx->mu);
+        for (auto &kv : ctx->batches) pending.push_back(kv.second);
+    }
+    for (auto &b : pending) {
+        if (b->worker.joinable()) b->worker.join();
+        for (auto *r : b->reports) delete r;
+    }
+    (void)hipSetDevice(ctx->device);
+    ctx->free_ws.clear();
+    delete ctx;
+}
+
+kc_status kc_ctx_set_option(kc_ctx *ctx, const char *key, int64_t v) {
+    if (!ctx || !key) return KC_E_INVAL;
+    std::string k(key);
+    if (k == "check" && (v == 0 || v == 1)) ctx->opt.check = (int)v;
+    else if (k == "fuel" && v >= 1 && v <= 0xFFFFFFFFll) ctx->opt.fuel = (uint32_t)v;
+    else if (k == "timing" && (v == 0 || v == 1)) ctx->opt.timing = (int)v;
+    else if (k == "sort_tile" && (v == 2048 || v == 4096 || v == 8192)) ctx->opt.sort_tile = (uint32_t)v;
+    else if (k == "log_records" && v >= 1024) ctx->opt.log_records = (uint64_t)v;
+    else if (k == "stage" && (v == 128 || v == 256 || v == 512 || v == 1024)) ctx->opt.stage = (uint32_t)v;
+    else if (k == "reset" && v == 1) {
+        std::lock_guard<std::mutex> g(ctx->mu);
+        ctx->stats.clear();
+    } else {
+        ctx->err = "unknown option or value: " + k;
+        return KC_E_INVAL;
+    }
+    return KC_OK;
+}
+
+double kc_ctx_get_stat(kc_ctx *ctx, const char *key) {
+    if (!ctx || !key) return 0.0;
+    std::lock_guard<std::mutex> g(ctx->mu);
+    auto it = ctx->stats.find(key);
+    return it == ctx->stats.end() ? 0.0 : it->second;
+}
+
+const char *kc_last_error(const kc_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+kc_status kc_program_load(kc_ctx *ctx, const uint64_t *words, uint32_t n_words, kc_program **out) {
+    if (!ctx || !out || (!words && n_words)) return KC_E_INVAL;
+    *out = nullptr;
+    if (ctx->poisoned) return KC_E_DEVICE;
+    std::string why = validate_program(words, n_words);
+    if (!why.empty()) {
+        ctx->err = why;
+        return KC_E_PROGRAM;
+    }
+    auto *p = new kc_program();
+    p->words.assign(words, words + n_words);
+    p->device = ctx->device;
+    try {
+        HIPCHK(hipSetDevice(ctx->device));
+        HIPCHK(hipMalloc(&p->dev, (size_t)n_words * 8));
+        HIPCHK(hipMemcpy(p->dev, words, (size_t)n_words * 8, hipMemcpyHostToDevice));
+    } catch (const KcError &e) {
+        if (p->dev) (void)hipFree(p->dev);
+        delete p;
+        return fail(ctx, e);
+    }
+    *out = p;
+    return KC_OK;
+}
+
+void kc_program_free(kc_program *p) {
+    if (!p) return;
+    if (p->dev) {
+        (void)hipSetDevice(p->device);
+        (void)hipFree(p->dev);
+    }
+    delete p;
+}
+
+kc_status kc_launch(kc_ctx *ctx, const kc_launch_desc *desc, int32_t *dev_mem, uint64_t n_words, void *stream,
+                    kc_report **out) {
+    if (!ctx || !out) return KC_E_INVAL;
+    *out = nullptr;
+    if (ctx->poisoned) return KC_E_DEVICE;
+    std::string why = validate_desc(desc, dev_mem, n_words);
+    if (!why.empty()) {
+        ctx->err = why;
+        return KC_E_INVAL;
+    }
+    kc_job job{desc, 1, dev_mem, n_words, 0};
+    std::vector<kc_report *> reps;
+    try {
+        run_jobs(ctx, &job, 1, (hipStream_t)stream, reps);
+    } catch (const KcError &e) {
+        return fail(ctx, e);
+    } catch (const std::bad_alloc &) {
+        return fail(ctx, KcError{KC_E_NOMEM, "host allocation failed"});
+    }
+    *out = reps[0];
+    return KC_OK;
+}
+
+kc_status kc_batch_submit(kc_ctx *ctx, const kc_job *jobs, uint32_t n_jobs, void *stream, uint64_t *ticket) {
+    if (!ctx || !ticket || (!jobs && n_jobs)) return KC_E_INVAL;
+    if (ctx->poisoned) return KC_E_DEVICE;
+    for (uint32_t j = 0; j < n_jobs; j++) {
+        if (jobs[j].n_launches && !jobs[j].launches) {
+            ctx->err = "job without launch array";
+            return KC_E_INVAL;
+        }
+        for (uint32_t l = 0; l < jobs[j].n_launches; l++) {
+            std::string why = validate_desc(&jobs[j].launches[l], jobs[j].dev_mem, jobs[j].n_words);
+            if (!why.empty()) {
+                ctx->err = "job " + std::to_string(j) + " launch " + std::to_string(l) + ": " + why;
+                return KC_E_INVAL;
+            }
+        }
+    }
+    auto b = std::make_shared<Batch>();
+    b->jobs.assign(jobs, jobs + n_jobs);
+    b->descs.resize(n_jobs);
+    for (uint32_t j = 0; j < n_jobs; j++) {
+        b->descs[j].assign(jobs[j].launches, jobs[j].launches + jobs[j].n_launches);
+        b->jobs[j].launches = b->descs[j].data();
+    }
+    b->stream = (hipStream_t)stream;
+    uint64_t t;
+    {
+        std::lock_guard<std::mutex> g(ctx->mu);
+        t = ctx->next_ticket++;
+        ctx->batches[t] = b;
+    }
+    Batch *bp = b.get();
+    bp->worker = std::thread([ctx, bp]() {
+        kc_status st = KC_OK;
+        std::string err;
+        std::vector<kc_report *> reps;
+        try {
+            run_jobs(ctx, bp->jobs.data(), (uint32_t)bp->jobs.size(), bp->stream, reps);
+        } catch (const KcError &e) {
+            st = e.st;
+            err = e.msg;
+        } catch (const std::bad_alloc &) {
+            st = KC_E_NOMEM;
+            err = "host allocation failed";
+        }
+        std::lock_guard<std::mutex> g(bp->mu);
+        bp->status = st;
+        bp->err = err;
+        bp->reports = std::move(reps);
+        bp->done = true;
+        bp->cv.notify_all();
+    });
+    *ticket = t;
+    return KC_OK;
+}
+
+kc_status kc_poll(kc_ctx *ctx, uint64_t ticket, int wait, kc_report **out, uint32_t n_out) {
+    if (!ctx) return KC_E_INVAL;
+    std::shared_ptr<Batch> b;
+    {
+        std::lock_guard<std::mutex> g(ctx->mu);
+        auto it = ctx->batches.find(ticket);
+        if (it == ctx->batches.end()) {
+            ctx->err = "unknown ticket";
+            return KC_E_INVAL;
+        }
+        b = it->second;
+    }
+    {
+        std::unique_lock<std::mutex> g(b->mu);
+        if (!b->done) {
+            if (!wait) return KC_E_PENDING;
+            b->cv.wait(g, [&] { return b->done; });
+        }
+    }
+    if (b->worker.joinable()) b->worker.join();
+    if (b->status != KC_OK) {
+        std::lock_guard<std::mutex> g(ctx->mu);
+        ctx->err = b->err;
+        if (b->status == KC_E_DEVICE) ctx->poisoned = true;
+        ctx->batches.erase(ticket);
+        return b->status;
+    }
+    if (!out || n_out < b->reports.size()) {
+        ctx->err = "output array too small";
+        return KC_E_INVAL;
+    }
+    for (size_t i = 0; i < b->reports.size(); i++) out[i] = b->reports[i];
+    b->reports.clear();
+    std::lock_guard<std::mutex> g(ctx->mu);
+    ctx->batches.erase(ticket);
+    return KC_OK;
+}
+
+uint64_t kc_report_records(const kc_report *r) { return r ? r->records : 0; }
+uint32_t kc_report_launches_completed(const kc_report *r) { return r ? r->launches_completed : 0; }
+const kc_race *kc_report_races(const kc_report *r, uint64_t *n) {
+    if (n) *n = r ? r->races.size() : 0;
+    return r && !r->races.empty() ? r->races.data() : nullptr;
+}
+const kc_fault *kc_report_faults(const kc_report *r, uint64_t *n) {
+    if (n) *n = r ? r->faults.size() : 0;
+    return r && !r->faults.empty() ? r->faults.data() : nullptr;
+}
+uint64_t kc_report_tag(const kc_report *r) { return r ? r->tag : 0; }
+void kc_report_free(kc_report *r) { delete r; }
+
+}  // extern "C"

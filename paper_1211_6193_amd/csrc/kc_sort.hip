@@ -1,0 +1,229 @@
+// LDS-staged LSD radix sort of 64-bit access records on gfx950.
+//
+// One pass per 8-bit digit over the requested bit range:
+//   k_rs_hist     per-tile digit histograms (tile-major [tile][256])
+//   k_rs_colsum   per-chunk column sums   -> part[chunk][256]
+//   k_rs_top      exclusive scan over chunks and digits (one workgroup)
+//   k_rs_apply    turns histograms into global start offsets per (tile, digit)
+//   k_rs_scatter  stable rank inside the tile (wave-level 8-ballot digit match),
+//                 reorder the tile in LDS, write each digit's run contiguously.
+// A tile is 4 waves x 64 lanes x ITEMS keys; wave w owns a contiguous quarter
+// of the tile so ranks need no cross-wave synchronisation until the end.
+#include "kc_internal.h"
+
+namespace kc {
+
+namespace {
+
+constexpr int WAVE = 64;
+constexpr int WG = 256;
+constexpr int NW = WG / WAVE;
+constexpr int CHUNK = 256;     // tiles per column-scan chunk
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+// The sort orders records by a virtual key that drops the unused high bits of
+// the epoch field: V = (k >> s_blk) . (epoch low ueb bits) . (low pb payload bits).
+__device__ __forceinline__ uint64_t vkey(uint64_t k, const VKey &v) {
+    const uint64_t hi = (k >> v.s_blk) << (v.ueb + v.pb);
+    const uint64_t ep = v.ueb ? ((k >> v.s_ep) & ((1ull << v.ueb) - 1ull)) << v.pb : 0ull;
+    const uint64_t lo = v.pb ? (k & ((1ull << v.pb) - 1ull)) : 0ull;
+    return hi | ep | lo;
+}
+__device__ __forceinline__ uint32_t digit_of(uint64_t k, const VKey &v, uint32_t shift, uint32_t bits) {
+    return (uint32_t)(vkey(k, v) >> shift) & ((1u << bits) - 1u);
+}
+
+template <int ITEMS>
+__global__ void __launch_bounds__(WG) k_rs_hist(const uint64_t *__restrict__ keys, uint64_t n, VKey vk, uint32_t shift,
+                                                uint32_t bits, uint32_t *__restrict__ hist) {
+    __shared__ uint32_t h[NW][256];
+    for (int i = threadIdx.x; i < NW * 256; i += WG) (&h[0][0])[i] = 0;
+    __syncthreads();
+    const uint32_t w = threadIdx.x / WAVE;
+    const uint64_t tile0 = (uint64_t)blockIdx.x * (WG * ITEMS);
+    const uint64_t seg0 = tile0 + (uint64_t)w * (WAVE * ITEMS);
+#pragma unroll 4
+    for (int j = 0; j < ITEMS; j++) {
+        uint64_t idx = seg0 + (uint64_t)j * WAVE + lane_id();
+        if (idx < n) atomicAdd(&h[w][digit_of(keys[idx], vk, shift, bits)], 1u);
+    }
+    __syncthreads();
+    for (uint32_t d = threadIdx.x; d < 256; d += WG) {
+        uint32_t s = 0;
+#pragma unroll
+        for (int q = 0; q < NW; q++) s += h[q][d];
+        hist[(size_t)blockIdx.x * 256 + d] = s;
+    }
+}
+
+__global__ void __launch_bounds__(WG) k_rs_colsum(const uint32_t *__restrict__ hist, uint32_t n_tiles,
+                                                  uint32_t *__restrict__ part) {
+    const uint32_t d = threadIdx.x;
+    const uint32_t t0 = blockIdx.x * CHUNK, t1 = min(t0 + CHUNK, n_tiles);
+    uint32_t s = 0;
+    for (uint32_t t = t0; t < t1; t++) s += hist[(size_t)t * 256 + d];
+    part[(size_t)blockIdx.x * 256 + d] = s;
+}
+
+// part[c][d] becomes the exclusive start of (chunk c, digit d) in the output.
+__global__ void __launch_bounds__(WG) k_rs_top(uint32_t *__restrict__ part, uint32_t n_chunks) {
+    __shared__ uint32_t tot[256];
+    const uint32_t d = threadIdx.x;
+    uint32_t run = 0;
+    for (uint32_t c = 0; c < n_chunks; c++) {
+        uint32_t v = part[(size_t)c * 256 + d];
+        part[(size_t)c * 256 + d] = run;
+        run += v;
+    }
+    tot[d] = run;
+    __syncthreads();
+    // exclusive scan of the 256 digit totals (Hillis-Steele on a copy)
+    uint32_t x = tot[d];
+    for (uint32_t o = 1; o < 256; o <<= 1) {
+        uint32_t y = d >= o ? tot[d - o] : 0;
+        __syncthreads();
+        x += y;
+        tot[d] = x;
+        __syncthreads();
+    }
+    const uint32_t base = x - run;
+    for (uint32_t c = 0; c < n_chunks; c++) part[(size_t)c * 256 + d] += base;
+}
+
+__global__ void __launch_bounds__(WG) k_rs_apply(uint32_t *__restrict__ hist, uint32_t n_tiles,
+                                                 const uint32_t *__restrict__ part) {
+    const uint32_t d = threadIdx.x;
+    const uint32_t t0 = blockIdx.x * CHUNK, t1 = min(t0 + CHUNK, n_tiles);
+    uint32_t run = part[(size_t)blockIdx.x * 256 + d];
+    for (uint32_t t = t0; t < t1; t++) {
+        uint32_t v = hist[(size_t)t * 256 + d];
+        hist[(size_t)t * 256 + d] = run;
+        run += v;
+    }
+}
+
+template <int ITEMS>
+__global__ void __launch_bounds__(WG) k_rs_scatter(const uint64_t *__restrict__ in, uint64_t *__restrict__ out,
+                                                   uint64_t n, VKey vk, uint32_t shift, uint32_t bits,
+                                                   const uint32_t *__restrict__ offs) {
+    constexpr int TILE = WG * ITEMS;
+    __shared__ uint64_t buf[TILE];
+    __shared__ uint32_t wc[NW][256];
+    __shared__ uint32_t tstart[256];
+    __shared__ uint32_t goff[256];
+    const uint32_t w = threadIdx.x / WAVE;
+    const uint32_t lane = lane_id();
+    for (int i = threadIdx.x; i < NW * 256; i += WG) (&wc[0][0])[i] = 0;
+    for (int d = threadIdx.x; d < 256; d += WG) goff[d] = offs[(size_t)blockIdx.x * 256 + d];
+    __syncthreads();
+
+    const uint64_t tile0 = (uint64_t)blockIdx.x * TILE;
+    const uint64_t seg0 = tile0 + (uint64_t)w * (WAVE * ITEMS);
+    uint64_t k[ITEMS];
+    uint32_t rank[ITEMS];
+    const uint64_t lt = (1ull << lane) - 1ull;
+#pragma unroll
+    for (int j = 0; j < ITEMS; j++) {
+        const uint64_t idx = seg0 + (uint64_t)j * WAVE + lane;
+        const bool valid = idx < n;
+        k[j] = valid ? in[idx] : 0ull;
+        const uint32_t d = digit_of(k[j], vk, shift, bits);
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (uint32_t b = 0; b < 8; b++) {
+            if (b < bits) {
+                const bool bit = (d >> b) & 1u;
+                const uint64_t bb = __ballot(valid && bit);
+                peers &= bit ? bb : ~bb;
+            }
+        }
+        const uint32_t leader = valid ? (uint32_t)__ffsll((long long)peers) - 1 : 0;
+        uint32_t old = 0;
+        if (valid && lane == leader) {
+            old = wc[w][d];
+            wc[w][d] = old + (uint32_t)__popcll(peers);
+        }
+        old = __shfl(old, (int)leader);
+        rank[j] = valid ? old + (uint32_t)__popcll(peers & lt) : 0xFFFFFFFFu;
+    }
+    __syncthreads();
+    // per digit: tile-local start and per-wave base positions
+    {
+        const uint32_t d = threadIdx.x;     // WG == 256 digits
+        uint32_t c[NW], tot = 0;
+#pragma unroll
+        for (int q = 0; q < NW; q++) { c[q] = wc[q][d]; tot += c[q]; }
+        tstart[d] = tot;
+        __syncthreads();
+        uint32_t x = tot;
+        for (uint32_t o = 1; o < 256; o <<= 1) {
+            uint32_t y = d >= o ? tstart[d - o] : 0;
+            __syncthreads();
+            x += y;
+            tstart[d] = x;
+            __syncthreads();
+        }
+        const uint32_t start = x - tot;
+        __syncthreads();
+        tstart[d] = start;
+        uint32_t run = start;
+#pragma unroll
+        for (int q = 0; q < NW; q++) { wc[q][d] = run; run += c[q]; }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < ITEMS; j++) {
+        if (rank[j] != 0xFFFFFFFFu) {
+            const uint32_t d = digit_of(k[j], vk, shift, bits);
+            buf[wc[w][d] + rank[j]] = k[j];
+        }
+    }
+    __syncthreads();
+    const uint64_t tile_n = (n - tile0) < (uint64_t)TILE ? (n - tile0) : (uint64_t)TILE;
+    for (uint32_t p = threadIdx.x; p < tile_n; p += WG) {
+        const uint64_t key = buf[p];
+        const uint32_t d = digit_of(key, vk, shift, bits);
+        out[(uint64_t)goff[d] + (p - tstart[d])] = key;
+    }
+}
+
+template <int ITEMS>
+hipError_t sort_passes(uint64_t *keys, uint64_t n, const VKey &vk, uint32_t hi, SortScratch &sc, hipStream_t s,
+                       uint64_t **out) {
+    constexpr uint64_t TILE = WG * ITEMS;
+    const uint32_t n_tiles = (uint32_t)((n + TILE - 1) / TILE);
+    const uint32_t n_chunks = (n_tiles + CHUNK - 1) / CHUNK;
+    uint64_t *a = keys, *b = sc.alt;
+    for (uint32_t sh = 0; sh < hi; sh += 8) {
+        const uint32_t bits = (hi - sh) < 8 ? (hi - sh) : 8;
+        hipLaunchKernelGGL(k_rs_hist<ITEMS>, dim3(n_tiles), dim3(WG), 0, s, a, n, vk, sh, bits, sc.hist);
+        hipLaunchKernelGGL(k_rs_colsum, dim3(n_chunks), dim3(WG), 0, s, sc.hist, n_tiles, sc.part);
+        hipLaunchKernelGGL(k_rs_top, dim3(1), dim3(WG), 0, s, sc.part, n_chunks);
+        hipLaunchKernelGGL(k_rs_apply, dim3(n_chunks), dim3(WG), 0, s, sc.hist, n_tiles, sc.part);
+        hipLaunchKernelGGL(k_rs_scatter<ITEMS>, dim3(n_tiles), dim3(WG), 0, s, a, b, n, vk, sh, bits, sc.hist);
+        uint64_t *t = a; a = b; b = t;
+    }
+    *out = a;
+    return hipGetLastError();
+}
+
+}  // namespace
+
+size_t radix_hist_entries(uint64_t n, uint32_t tile) {
+    const uint64_t n_tiles = (n + tile - 1) / tile;
+    return (size_t)(n_tiles ? n_tiles : 1) * 256;
+}
+
+hipError_t radix_sort(uint64_t *keys, uint64_t n, const VKey &vk, SortScratch &sc, uint32_t tile,
+                      hipStream_t s, uint64_t **out) {
+    *out = keys;
+    if (n <= 1 || vk.vbits == 0) return hipSuccess;
+    switch (tile) {
+    case 2048: return sort_passes<8>(keys, n, vk, vk.vbits, sc, s, out);
+    case 8192: return sort_passes<32>(keys, n, vk, vk.vbits, sc, s, out);
+    default: return sort_passes<16>(keys, n, vk, vk.vbits, sc, s, out);
+    }
+}
+
+}  // namespace kc

@@ -1,0 +1,294 @@
+"""Python binding of libkc (argument marshalling only; all work runs in the HIP library).
+
+PyTorch supplies device memory (int32 tensors on the GPU) and streams.
+Loading fails loudly if the compiled library is missing: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libkc.so")
+
+KC_OK, KC_E_INVAL, KC_E_PROGRAM, KC_E_NOMEM, KC_E_DEVICE, KC_E_PENDING, KC_E_BUDGET, KC_E_OVERFLOW = range(8)
+STATUS_NAMES = ["KC_OK", "KC_E_INVAL", "KC_E_PROGRAM", "KC_E_NOMEM", "KC_E_DEVICE", "KC_E_PENDING",
+                "KC_E_BUDGET", "KC_E_OVERFLOW"]
+DEADLOCK, DIVERGENCE, OOB, FUEL, ARITH = 1, 2, 3, 4, 5
+
+# Every entry point include/kc.h declares.
+EXPORTS = ["kc_ctx_create", "kc_ctx_destroy", "kc_ctx_set_option", "kc_ctx_get_stat", "kc_last_error",
+           "kc_program_load", "kc_program_free", "kc_launch", "kc_batch_submit", "kc_poll",
+           "kc_report_records", "kc_report_launches_completed", "kc_report_races", "kc_report_faults",
+           "kc_report_tag", "kc_report_free"]
+
+RACE_DTYPE = np.dtype([(f, "<u4") for f in ("launch", "space", "scope", "block", "epoch", "addr", "w_tid", "o_tid")])
+FAULT_DTYPE = np.dtype([(f, "<u4") for f in ("launch", "kind", "block", "epoch", "a", "b", "c", "d")])
+
+
+class KcError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES[status] if 0 <= status < 8 else status}: {msg}")
+        self.status = status
+
+
+class Dim3(C.Structure):
+    _fields_ = [("x", C.c_uint32), ("y", C.c_uint32), ("z", C.c_uint32)]
+
+
+class LaunchDesc(C.Structure):
+    _fields_ = [("prog", C.c_void_p), ("grid", Dim3), ("block", Dim3), ("shmem_bytes", C.c_uint32),
+                ("params", C.c_int32 * 8), ("n_params", C.c_uint32)]
+
+
+class JobDesc(C.Structure):
+    _fields_ = [("launches", C.POINTER(LaunchDesc)), ("n_launches", C.c_uint32), ("dev_mem", C.c_void_p),
+                ("n_words", C.c_uint64), ("tag", C.c_uint64)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libkc.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with paper_1211_6193_amd/build.py (no CPU fallback exists)")
+    lib = C.CDLL(path)
+    vp, u32, u64, i64 = C.c_void_p, C.c_uint32, C.c_uint64, C.c_int64
+    sig = {
+        "kc_ctx_create": ([C.c_int, u64, C.c_char_p, C.POINTER(vp)], C.c_int),
+        "kc_ctx_destroy": ([vp], None),
+        "kc_ctx_set_option": ([vp, C.c_char_p, i64], C.c_int),
+        "kc_ctx_get_stat": ([vp, C.c_char_p], C.c_double),
+        "kc_last_error": ([vp], C.c_char_p),
+        "kc_program_load": ([vp, vp, u32, C.POINTER(vp)], C.c_int),
+        "kc_program_free": ([vp], None),
+        "kc_launch": ([vp, C.POINTER(LaunchDesc), vp, u64, vp, C.POINTER(vp)], C.c_int),
+        "kc_batch_submit": ([vp, C.POINTER(JobDesc), u32, vp, C.POINTER(u64)], C.c_int),
+        "kc_poll": ([vp, u64, C.c_int, C.POINTER(vp), u32], C.c_int),
+        "kc_report_records": ([vp], u64),
+        "kc_report_launches_completed": ([vp], u32),
+        "kc_report_races": ([vp, C.POINTER(u64)], vp),
+        "kc_report_faults": ([vp, C.POINTER(u64)], vp),
+        "kc_report_tag": ([vp], u64),
+        "kc_report_free": ([vp], None),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+def _copy(ptr, n, dtype):
+    if n == 0 or not ptr:
+        return np.zeros(0, dtype=dtype)
+    return np.frombuffer((C.c_char * (n * dtype.itemsize)).from_address(ptr), dtype=dtype).copy()
+
+
+@dataclass
+class Report:
+    records: int
+    launches_completed: int
+    races: np.ndarray
+    faults: np.ndarray
+    tag: int = 0
+
+    def race_tuples(self) -> List[Tuple[int, ...]]:
+        return [tuple(int(x) for x in r) for r in self.races]
+
+    def fault_tuples(self) -> List[Tuple[int, ...]]:
+        return [tuple(int(x) for x in f) for f in self.faults]
+
+
+def _take_report(lib, ptr) -> Report:
+    n = C.c_uint64()
+    races = _copy(lib.kc_report_races(ptr, C.byref(n)), n.value, RACE_DTYPE)
+    faults = _copy(lib.kc_report_faults(ptr, C.byref(n)), n.value, FAULT_DTYPE)
+    rep = Report(int(lib.kc_report_records(ptr)), int(lib.kc_report_launches_completed(ptr)), races, faults,
+                 int(lib.kc_report_tag(ptr)))
+    lib.kc_report_free(ptr)
+    return rep
+
+
+class Context:
+    """A libkc context on one HIP device."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0, tune_cache: Optional[str] = None):
+        self.lib = load_library()
+        h = C.c_void_p()
+        st = self.lib.kc_ctx_create(device, hbm_budget_bytes, tune_cache.encode() if tune_cache else None,
+                                    C.byref(h))
+        if st != KC_OK:
+            raise KcError(st, f"kc_ctx_create(device={device})")
+        self.h = h
+        self.device = device
+        self._progs: Dict[bytes, Program] = {}
+
+    def _check(self, st: int, what: str):
+        if st != KC_OK:
+            raise KcError(st, f"{what}: {self.lib.kc_last_error(self.h).decode(errors='replace')}")
+
+    def set_option(self, key: str, value: int):
+        self._check(self.lib.kc_ctx_set_option(self.h, key.encode(), int(value)), f"set_option({key})")
+
+    def stat(self, key: str) -> float:
+        return float(self.lib.kc_ctx_get_stat(self.h, key.encode()))
+
+    def reset_stats(self):
+        self.set_option("reset", 1)
+
+    def program(self, words) -> "Program":
+        arr = np.ascontiguousarray(np.asarray(words, dtype=np.uint64))
+        key = arr.tobytes()
+        p = self._progs.get(key)
+        if p is None:
+            p = Program(self, arr)
+            self._progs[key] = p
+        return p
+
+    def close(self):
+        if getattr(self, "h", None):
+            for p in self._progs.values():
+                p.free()
+            self._progs.clear()
+            self.lib.kc_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+class Program:
+    def __init__(self, ctx: Context, words: np.ndarray):
+        self.ctx = ctx
+        self.words = words
+        h = C.c_void_p()
+        ctx._check(ctx.lib.kc_program_load(ctx.h, words.ctypes.data, len(words), C.byref(h)), "kc_program_load")
+        self.h = h
+
+    def free(self):
+        if self.h:
+            self.ctx.lib.kc_program_free(self.h)
+            self.h = None
+
+
+def _desc(prog: Program, grid, block, shmem_bytes: int, params: Sequence[int]) -> LaunchDesc:
+    d = LaunchDesc()
+    d.prog = prog.h
+    g = tuple(grid) + (1,) * (3 - len(tuple(grid)))
+    b = tuple(block) + (1,) * (3 - len(tuple(block)))
+    d.grid = Dim3(*g)
+    d.block = Dim3(*b)
+    d.shmem_bytes = shmem_bytes
+    ps = [int(np.int32(p)) for p in params]
+    if len(ps) > 8:
+        raise ValueError("at most 8 params")
+    d.params[:] = ps + [0] * (8 - len(ps))
+    d.n_params = len(ps)
+    return d
+
+
+def _stream_handle(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return getattr(stream, "cuda_stream", stream)
+
+
+def launch(ctx: Context, prog: Program, grid, block, shmem_bytes: int, mem, params: Sequence[int] = (),
+           stream=None) -> Report:
+    """One synchronous launch on ``mem`` (an int32 CUDA tensor, updated in place)."""
+    import torch
+    if mem.dtype != torch.int32 or not mem.is_cuda or not mem.is_contiguous():
+        raise ValueError("mem must be a contiguous int32 tensor on the GPU")
+    d = _desc(prog, grid, block, shmem_bytes, params)
+    out = C.c_void_p()
+    ctx._check(ctx.lib.kc_launch(ctx.h, C.byref(d), mem.data_ptr(), mem.numel(), _stream_handle(stream),
+                                 C.byref(out)), "kc_launch")
+    return _take_report(ctx.lib, out)
+
+
+class Batch:
+    """Asynchronous batches of jobs (each job = launches in order on one memory)."""
+
+    def __init__(self, ctx: Context):
+        self.ctx = ctx
+        self._keep: Dict[int, tuple] = {}
+
+    def submit(self, jobs: List[Tuple[List[Tuple[Program, tuple, tuple, int, Sequence[int]]], object, int]],
+               stream=None) -> int:
+        """jobs: list of (launches, mem_tensor, tag); launches = [(prog, grid, block, shmem, params), ...]."""
+        n = len(jobs)
+        jd = (JobDesc * max(n, 1))()
+        keep = []
+        for i, (launches, mem, tag) in enumerate(jobs):
+            arr = (LaunchDesc * max(len(launches), 1))()
+            for j, (p, g, b, sh, ps) in enumerate(launches):
+                arr[j] = _desc(p, g, b, sh, ps)
+            keep.append(arr)
+            jd[i].launches = C.cast(arr, C.POINTER(LaunchDesc))
+            jd[i].n_launches = len(launches)
+            jd[i].dev_mem = mem.data_ptr()
+            jd[i].n_words = mem.numel()
+            jd[i].tag = tag
+        t = C.c_uint64()
+        self.ctx._check(self.ctx.lib.kc_batch_submit(self.ctx.h, jd, n, _stream_handle(stream), C.byref(t)),
+                        "kc_batch_submit")
+        self._keep[t.value] = (jd, keep, n)
+        return t.value
+
+    def poll(self, ticket: int, wait: bool = True) -> Optional[List[Report]]:
+        n = self._keep[ticket][2]
+        out = (C.c_void_p * max(n, 1))()
+        st = self.ctx.lib.kc_poll(self.ctx.h, ticket, int(wait), out, n)
+        if st == KC_E_PENDING:
+            return None
+        self._keep.pop(ticket, None)
+        self.ctx._check(st, "kc_poll")
+        return [_take_report(self.ctx.lib, out[i]) for i in range(n)]
+
+
+# ---------------------------------------------------------------------------
+# convenience over workload jobs (objects with .launches and .memory)
+# ---------------------------------------------------------------------------
+def job_launches(ctx: Context, job) -> list:
+    return [(ctx.program(L.program), L.grid, L.block, L.shmem_bytes, L.params) for L in job.launches]
+
+
+def run_job(ctx: Context, job, mem=None, stream=None):
+    """Run all launches of ``job`` as one job; returns (Report, final memory tensor)."""
+    import torch
+    if mem is None:
+        mem = torch.from_numpy(np.ascontiguousarray(job.memory, dtype=np.int32)).to(f"cuda:{ctx.device}")
+    b = Batch(ctx)
+    t = b.submit([(job_launches(ctx, job), mem, 0)], stream=stream)
+    return b.poll(t, wait=True)[0], mem
+
+
+def run_jobs(ctx: Context, jobs, mems=None, stream=None):
+    """Run many jobs as one batch; returns (reports, memories)."""
+    import torch
+    if mems is None:
+        mems = [torch.from_numpy(np.ascontiguousarray(j.memory, dtype=np.int32)).to(f"cuda:{ctx.device}")
+                for j in jobs]
+    b = Batch(ctx)
+    t = b.submit([(job_launches(ctx, j), m, i) for i, (j, m) in enumerate(zip(jobs, mems))], stream=stream)
+    return b.poll(t, wait=True), mems
