@@ -20,9 +20,6 @@ namespace {
 constexpr int WG = 256;
 constexpr uint32_t NONE = 0xFFFFFFFFu;
 
-__device__ __forceinline__ uint32_t lane_prefix(uint64_t m) {
-    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-}
 
 __device__ void push_race(const CheckArgs &A, const DevRace &r) {
     uint32_t idx = atomicAdd(&A.ctr->race_count, 1u);
@@ -41,47 +38,67 @@ __device__ void push_edge(const CheckArgs &A, uint32_t unit, uint32_t b0, uint32
     }
 }
 
-__global__ void __launch_bounds__(WG) k_check(CheckArgs A) {
-    const uint64_t i = (uint64_t)blockIdx.x * WG + threadIdx.x;
-    if (i >= A.n) return;
-    const KeyPlan &k = A.kp;
-    const uint64_t *keys = A.keys;
-    const uint64_t ki = keys[i];
-    const uint32_t ps = k.s_ep;                  // bits below: tid and kind
-    const uint64_t inner = ki >> ps;
-    const uint32_t unit = rec_field(ki, k.s_unit, k.ub);
-    const uint32_t space = rec_field(ki, k.s_sp, 1);
-    const uint32_t addr = rec_field(ki, k.s_addr, k.ab);
-    const uint32_t block0 = rec_field(ki, k.s_blk, k.bb);
+constexpr int CHECK_ITEMS = 8;
+constexpr int CHECK_TILE = WG * CHECK_ITEMS;
 
-    if (i == 0 || (keys[i - 1] >> ps) != inner) {
-        // intra-block segment: smallest writer and two smallest distinct tids
-        uint32_t minw = NONE, t1 = NONE, t2 = NONE;
-        for (uint64_t j = i; j < A.n; j++) {
-            const uint64_t kj = keys[j];
-            if ((kj >> ps) != inner) break;
-            const uint32_t tid = rec_field(kj, k.s_tid, k.tb);
-            if (kj & 1ull) minw = min(minw, tid);
-            if (tid < t1) { t2 = t1; t1 = tid; }
-            else if (tid != t1 && tid < t2) t2 = tid;
+// One workgroup per tile of sorted records, staged in LDS; thread t owns the
+// records at t, t + WG, t + 2 WG, ... (conflict-free LDS reads) and reduces
+// every segment that starts at one of them (reading past the tile from global
+// memory when a segment continues into the next tile).
+__global__ void __launch_bounds__(WG) k_check(CheckArgs A) {
+    __shared__ uint64_t tk[CHECK_TILE];
+    const uint64_t tile0 = (uint64_t)blockIdx.x * CHECK_TILE;
+    const uint64_t tile_n = min((uint64_t)CHECK_TILE, A.n - tile0);
+    for (uint32_t p = threadIdx.x; p < tile_n; p += WG) tk[p] = A.keys[tile0 + p];
+    __syncthreads();
+    const KeyPlan &k = A.kp;
+    const uint32_t ps = k.s_ep;                  // bits below: tid and kind
+    auto key_at = [&](uint64_t j) -> uint64_t {
+        return (j >= tile0 && j < tile0 + tile_n) ? tk[j - tile0] : A.keys[j];
+    };
+    for (uint32_t q = 0; q < CHECK_ITEMS; q++) {
+        const uint64_t p = (uint64_t)q * WG + threadIdx.x;
+        if (p >= tile_n) break;
+        const uint64_t i = tile0 + p;
+        // (segments are scanned serially by their head thread)
+        const uint64_t ki = tk[p];
+        const uint64_t prev = i ? key_at(i - 1) : ~0ull;
+        const uint64_t inner = ki >> ps;
+        const bool head_in = i == 0 || (prev >> ps) != inner;
+        const uint32_t space = rec_field(ki, k.s_sp, 1);
+        const bool head_out = space == 1u && (i == 0 || (prev >> k.s_addr) != (ki >> k.s_addr));
+        if (!head_in && !head_out) continue;
+        const uint32_t unit = rec_field(ki, k.s_unit, k.ub);
+        const uint32_t addr = rec_field(ki, k.s_addr, k.ab);
+        const uint32_t block0 = rec_field(ki, k.s_blk, k.bb);
+        if (head_in) {
+            // intra-block segment: smallest writer and two smallest distinct tids
+            uint32_t minw = NONE, t1 = NONE, t2 = NONE;
+            for (uint64_t j = i; j < A.n; j++) {
+                const uint64_t kj = key_at(j);
+                if ((kj >> ps) != inner) break;
+                const uint32_t tid = rec_field(kj, k.s_tid, k.tb);
+                if (kj & 1ull) minw = min(minw, tid);
+                if (tid < t1) { t2 = t1; t1 = tid; }
+                else if (tid != t1 && tid < t2) t2 = tid;
+            }
+            if (minw != NONE && t2 != NONE) {
+                DevRace r;
+                r.unit = unit; r.space = space; r.scope = 0; r.block = block0;
+                r.epoch = rec_field(ki, k.s_ep, k.eb); r.addr = addr;
+                r.w = minw; r.o = (t1 == minw) ? t2 : t1;
+                push_race(A, r);
+                A.blk_flags[A.units[unit].block_base + block0] = 1u;
+            }
         }
-        if (minw != NONE && t2 != NONE) {
-            DevRace r;
-            r.unit = unit; r.space = space; r.scope = 0; r.block = block0;
-            r.epoch = rec_field(ki, k.s_ep, k.eb); r.addr = addr;
-            r.w = minw; r.o = (t1 == minw) ? t2 : t1;
-            push_race(A, r);
-            A.blk_flags[A.units[unit].block_base + block0] = 1u;
-        }
-    }
-    if (space == 1u) {
-        const uint64_t outer = ki >> k.s_addr;
-        if (i == 0 || (keys[i - 1] >> k.s_addr) != outer) {
+        if (head_out) {
+            // cross-block segment: smallest writer gtid, two smallest gtids of distinct blocks
+            const uint64_t outer = ki >> k.s_addr;
             const uint32_t nt = A.units[unit].nt;
             uint32_t wg = NONE, wb = NONE, g1 = NONE, b1 = NONE, g2 = NONE;
             uint64_t end = i;
             for (uint64_t j = i; j < A.n; j++) {
-                const uint64_t kj = keys[j];
+                const uint64_t kj = key_at(j);
                 if ((kj >> k.s_addr) != outer) break;
                 end = j + 1;
                 const uint32_t b = rec_field(kj, k.s_blk, k.bb);
@@ -100,13 +117,13 @@ __global__ void __launch_bounds__(WG) k_check(CheckArgs A) {
                 r.w = wg; r.o = (wb == b1) ? g2 : g1;
                 push_race(A, r);
                 // every block touching the location joins the racy component
-                uint32_t prev = NONE;
+                uint32_t prevb = NONE;
                 for (uint64_t j = i; j < end; j++) {
-                    const uint32_t b = rec_field(keys[j], k.s_blk, k.bb);
-                    if (b != prev) {
+                    const uint32_t b = rec_field(key_at(j), k.s_blk, k.bb);
+                    if (b != prevb) {
                         A.blk_flags[A.units[unit].block_base + b] = 1u;
                         if (b != block0) push_edge(A, unit, block0, b);
-                        prev = b;
+                        prevb = b;
                     }
                 }
             }
@@ -128,35 +145,39 @@ __global__ void __launch_bounds__(WG) k_restore(const uint64_t *__restrict__ key
     u.mem[a] = u.snap[a];
 }
 
-// Records of flagged blocks, appended in any order.
-__global__ void __launch_bounds__(WG) k_extract(const uint64_t *__restrict__ keys, uint64_t n, KeyPlan k,
-                                                const DevUnit *__restrict__ units,
-                                                const uint32_t *__restrict__ blk_flags, uint64_t *__restrict__ out,
-                                                uint64_t out_cap, unsigned long long *__restrict__ cnt) {
+// Exactness condition of a replay: no global location may be touched both by
+// a replayed block (its canonical records `rs`, sorted) and by a block that was
+// not replayed (free-run records in `log`, sorted, with blk_flags == 0) unless
+// both only read it.  The first replayed record of each location looks up the
+// location's records in the free-run log by binary search.
+__global__ void __launch_bounds__(WG) k_coverage(const uint64_t *__restrict__ rs, uint64_t n_rs,
+                                                 const uint64_t *__restrict__ log, uint64_t n_log, KeyPlan k,
+                                                 const DevUnit *__restrict__ units,
+                                                 const uint32_t *__restrict__ blk_flags, uint32_t *__restrict__ flags) {
     const uint64_t i = (uint64_t)blockIdx.x * WG + threadIdx.x;
-    bool take = false;
-    uint64_t r = 0;
-    if (i < n) {
-        r = keys[i];
-        const DevUnit &u = units[rec_field(r, k.s_unit, k.ub)];
-        take = blk_flags[u.block_base + rec_field(r, k.s_blk, k.bb)] != 0;
+    if (i >= n_rs) return;
+    const uint64_t r = rs[i];
+    if (rec_field(r, k.s_sp, 1) != 1u) return;
+    const uint64_t target = r >> k.s_addr;
+    if (i > 0 && (rs[i - 1] >> k.s_addr) == target) return;
+    bool r_w = false;
+    for (uint64_t j = i; j < n_rs && (rs[j] >> k.s_addr) == target; j++) r_w |= (rs[j] & 1ull) != 0;
+    uint64_t lo = 0, hi = n_log;
+    while (lo < hi) {
+        const uint64_t mid = (lo + hi) / 2;
+        if ((log[mid] >> k.s_addr) < target) lo = mid + 1;
+        else hi = mid;
     }
-    const uint64_t m = __ballot(take);
-    if (m == 0) return;
-    const uint32_t leader = (uint32_t)__ffsll((long long)m) - 1;
-    unsigned long long base = 0;
-    if (__lane_id() == leader) base = atomicAdd(cnt, (unsigned long long)__popcll(m));
-    const uint32_t lo = __shfl((uint32_t)base, (int)leader), hi = __shfl((uint32_t)(base >> 32), (int)leader);
-    base = ((unsigned long long)hi << 32) | lo;
-    const uint64_t idx = base + lane_prefix(m);
-    if (take && idx < out_cap) out[idx] = r;
-}
-
-__global__ void __launch_bounds__(WG) k_compare(const uint64_t *__restrict__ x, const uint64_t *__restrict__ y,
-                                                uint64_t n, uint32_t *__restrict__ flags) {
-    const uint64_t i = (uint64_t)blockIdx.x * WG + threadIdx.x;
-    const bool diff = i < n && x[i] != y[i];
-    if (__ballot(diff) && __lane_id() == 0) atomicOr(flags, FLAG_MISMATCH);
+    const DevUnit &u = units[rec_field(r, k.s_unit, k.ub)];
+    for (uint64_t j = lo; j < n_log; j++) {
+        const uint64_t x = log[j];
+        if ((x >> k.s_addr) != target) break;
+        if (blk_flags[u.block_base + rec_field(x, k.s_blk, k.bb)]) continue;    // replayed block
+        if (r_w || (x & 1ull)) {
+            atomicOr(flags, FLAG_MISMATCH);
+            return;
+        }
+    }
 }
 
 // mem <-> snapshot of each unit (blockIdx.y = unit), optionally masked.
@@ -183,7 +204,7 @@ inline uint32_t blocks_for(uint64_t n) { return (uint32_t)((n + WG - 1) / WG); }
 
 hipError_t launch_check(const CheckArgs &a, hipStream_t s) {
     if (a.n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_check, dim3(blocks_for(a.n)), dim3(WG), 0, s, a);
+    hipLaunchKernelGGL(k_check, dim3((uint32_t)((a.n + CHECK_TILE - 1) / CHECK_TILE)), dim3(WG), 0, s, a);
     return hipGetLastError();
 }
 
@@ -194,18 +215,11 @@ hipError_t launch_restore(const uint64_t *keys, uint64_t n, KeyPlan kp, const De
     return hipGetLastError();
 }
 
-hipError_t launch_extract(const uint64_t *keys, uint64_t n, KeyPlan kp, const DevUnit *units,
-                          const uint32_t *blk_flags, uint64_t *out, uint64_t out_cap,
-                          unsigned long long *out_count, hipStream_t s) {
-    if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_extract, dim3(blocks_for(n)), dim3(WG), 0, s, keys, n, kp, units, blk_flags, out,
-                       out_cap, out_count);
-    return hipGetLastError();
-}
-
-hipError_t launch_compare(const uint64_t *x, const uint64_t *y, uint64_t n, uint32_t *flags, hipStream_t s) {
-    if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_compare, dim3(blocks_for(n)), dim3(WG), 0, s, x, y, n, flags);
+hipError_t launch_coverage(const uint64_t *rs, uint64_t n_rs, const uint64_t *log, uint64_t n_log, KeyPlan kp,
+                           const DevUnit *units, const uint32_t *blk_flags, uint32_t *flags, hipStream_t s) {
+    if (n_rs == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_coverage, dim3(blocks_for(n_rs)), dim3(WG), 0, s, rs, n_rs, log, n_log, kp, units, blk_flags,
+                       flags);
     return hipGetLastError();
 }
 

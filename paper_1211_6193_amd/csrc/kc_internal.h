@@ -105,7 +105,7 @@ struct InterpArgs {
 
 // Host-side launchers (defined in the .hip files).
 hipError_t launch_interp(const InterpArgs &a, uint32_t n_wg, uint32_t wg_threads, bool lockstep, hipStream_t s);
-size_t interp_lds_bytes(uint32_t sh_words_max, uint32_t wg_threads, uint32_t stage);
+size_t interp_lds_bytes(uint32_t sh_words_max, uint32_t wg_threads, uint32_t stage, bool lockstep);
 
 struct SortScratch {
     uint64_t *alt = nullptr;         // ping-pong buffer, >= n keys
@@ -139,10 +139,8 @@ struct CheckArgs {
 hipError_t launch_check(const CheckArgs &a, hipStream_t s);
 hipError_t launch_restore(const uint64_t *keys, uint64_t n, KeyPlan kp, const DevUnit *units,
                           const uint32_t *blk_flags, hipStream_t s);
-hipError_t launch_extract(const uint64_t *keys, uint64_t n, KeyPlan kp, const DevUnit *units,
-                          const uint32_t *blk_flags, uint64_t *out, uint64_t out_cap,
-                          unsigned long long *out_count, hipStream_t s);
-hipError_t launch_compare(const uint64_t *x, const uint64_t *y, uint64_t n, uint32_t *flags, hipStream_t s);
+hipError_t launch_coverage(const uint64_t *rs, uint64_t n_rs, const uint64_t *log, uint64_t n_log, KeyPlan kp,
+                           const DevUnit *units, const uint32_t *blk_flags, uint32_t *flags, hipStream_t s);
 hipError_t launch_copy_units(const DevUnit *units, uint32_t n_units, uint32_t max_words, bool to_snapshot,
                              const uint32_t *unit_mask, hipStream_t s);
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);

@@ -49,6 +49,12 @@ __device__ __forceinline__ int wave_max(int v) {
     return v;
 }
 
+__device__ __forceinline__ uint32_t wave_min_u(uint32_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, o));
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+
 __device__ __forceinline__ unsigned long long bcast_u64(unsigned long long v, uint32_t src) {
     uint32_t lo = __shfl((uint32_t)v, (int)src), hi = __shfl((uint32_t)(v >> 32), (int)src);
     return ((unsigned long long)hi << 32) | lo;
@@ -104,7 +110,8 @@ struct BlockCtx {
     uint32_t tid;           // linear tid of this lane
     uint32_t nt, nwaves, wave;
     uint32_t n_instr, n_words, sh_words;
-    int32_t sreg_lane[6];   // tid x,y,z  bid x,y,z
+    uint64_t kbase;         // record bits fixed for this lane: unit, block, tid
+    uint64_t kep;           // kbase plus the current epoch
 };
 
 // Wave-aggregated append of findings.
@@ -179,7 +186,7 @@ struct Lane {
 enum : int { EP_RELEASED = 0, EP_DONE = 1 };
 
 // All waves are quiescent (no running lane).  Count arrivals and decide.
-__device__ __forceinline__ int barrier_episode(const InterpArgs &A, const BlockCtx &B, const Shared &S, Lane &t,
+__device__ __forceinline__ int barrier_episode(const InterpArgs &A, BlockCtx &B, const Shared &S, Lane &t,
                                uint32_t &epoch) {
     __syncthreads();
     bool is_thread = t.st != ST_DEAD;
@@ -244,18 +251,20 @@ __device__ __forceinline__ int barrier_episode(const InterpArgs &A, const BlockC
         t.st = ST_RUN;
         t.pc = t.bar_pc + 1;
     }
+    B.kep = B.kbase | ((uint64_t)epoch << A.kp.s_ep);
     return EP_RELEASED;
 }
 
 __device__ __forceinline__ int32_t special(const BlockCtx &B, uint32_t k) {
     const DevUnit *u = B.u;
+    const uint32_t bx = u->bdim[0], by = u->bdim[1], gx = u->gdim[0], gy = u->gdim[1];
     switch (k) {
-    case 0: return B.sreg_lane[0];
-    case 1: return B.sreg_lane[1];
-    case 2: return B.sreg_lane[2];
-    case 3: return B.sreg_lane[3];
-    case 4: return B.sreg_lane[4];
-    case 5: return B.sreg_lane[5];
+    case 0: return (int32_t)(B.tid % bx);
+    case 1: return (int32_t)((B.tid / bx) % by);
+    case 2: return (int32_t)(B.tid / (bx * by));
+    case 3: return (int32_t)(B.block % gx);
+    case 4: return (int32_t)((B.block / gx) % gy);
+    case 5: return (int32_t)(B.block / (gx * gy));
     case 6: return (int32_t)u->bdim[0];
     case 7: return (int32_t)u->bdim[1];
     case 8: return (int32_t)u->bdim[2];
@@ -282,10 +291,12 @@ struct Pending {
 // value; a single indexed write after the dispatch keeps the register file in
 // place (one write site avoids copies of the whole 16-register vector).
 struct RegWrite {
+    bool writes;    // wave-uniform: the opcode writes register d
     bool on;
     int32_t v;
 };
 __device__ __forceinline__ void wr(RegWrite &W, bool active, int32_t v) {
+    W.writes = true;
     W.on = active;
     W.v = v;
 }
@@ -299,7 +310,7 @@ __device__ __forceinline__ void exec_one(const InterpArgs &A, const BlockCtx &B,
     ctl = 0;
     target = cur + 1;
     cond = false;
-    RegWrite W{false, 0};
+    RegWrite W{false, false, 0};
     const uint64_t w = B.prog[(uint32_t)uni(cur)];
     const uint32_t op = uniu((uint32_t)w & 0xFFu);
     const uint32_t d = uniu((uint32_t)(w >> 8) & 0xFFu);
@@ -310,7 +321,9 @@ __device__ __forceinline__ void exec_one(const InterpArgs &A, const BlockCtx &B,
     if (base >= OP_ADD && base <= OP_SLTU) {
         bool arith = false;
         const int32_t x = t.r[ra];
-        const int32_t y = (op & OP_IMM) ? imm : t.r[rb];
+        int32_t y;
+        if (op & OP_IMM) y = imm;
+        else y = t.r[rb];
         const int32_t v = alu(base, x, y, arith);
         if (base == OP_DIV || base == OP_REM)
             emit_fault(active && arith, A, B, F_ARITH, epoch, 0, B.tid, (uint32_t)cur, 0);
@@ -333,7 +346,7 @@ __device__ __forceinline__ void exec_one(const InterpArgs &A, const BlockCtx &B,
         int32_t v = 0;
         if (inb) v = S.sh[addr];
         wr(W, active, v);
-        log_rec(A, S.stage, L, inb, rec_pack(k, B.unit, 0u, (uint32_t)addr, B.block, epoch, B.tid, 0u));
+        log_rec(A, S.stage, L, inb, B.kep | ((uint64_t)0u << k.s_sp) | 0ull | ((uint64_t)(uint32_t)addr << k.s_addr));
         emit_fault(active && !inb, A, B, F_OOB, epoch, 0u, B.tid, (uint32_t)addr, 0);
         break;
     }
@@ -343,7 +356,7 @@ __device__ __forceinline__ void exec_one(const InterpArgs &A, const BlockCtx &B,
         int32_t v = 0;
         if (inb) v = B.mem[addr];
         wr(W, active, v);
-        log_rec(A, S.stage, L, inb, rec_pack(k, B.unit, 1u, (uint32_t)addr, B.block, epoch, B.tid, 0u));
+        log_rec(A, S.stage, L, inb, B.kep | ((uint64_t)1u << k.s_sp) | 0ull | ((uint64_t)(uint32_t)addr << k.s_addr));
         emit_fault(active && !inb, A, B, F_OOB, epoch, 2u, B.tid, (uint32_t)addr, 0);
         break;
     }
@@ -356,7 +369,7 @@ __device__ __forceinline__ void exec_one(const InterpArgs &A, const BlockCtx &B,
         } else if (inb) {
             S.sh[addr] = v;
         }
-        log_rec(A, S.stage, L, inb, rec_pack(k, B.unit, 0u, (uint32_t)addr, B.block, epoch, B.tid, 1u));
+        log_rec(A, S.stage, L, inb, B.kep | ((uint64_t)0u << k.s_sp) | 1ull | ((uint64_t)(uint32_t)addr << k.s_addr));
         emit_fault(active && !inb, A, B, F_OOB, epoch, 1u, B.tid, (uint32_t)addr, 0);
         break;
     }
@@ -369,7 +382,7 @@ __device__ __forceinline__ void exec_one(const InterpArgs &A, const BlockCtx &B,
         } else if (inb) {
             B.mem[addr] = v;
         }
-        log_rec(A, S.stage, L, inb, rec_pack(k, B.unit, 1u, (uint32_t)addr, B.block, epoch, B.tid, 1u));
+        log_rec(A, S.stage, L, inb, B.kep | ((uint64_t)1u << k.s_sp) | 1ull | ((uint64_t)(uint32_t)addr << k.s_addr));
         emit_fault(active && !inb, A, B, F_OOB, epoch, 3u, B.tid, (uint32_t)addr, 0);
         break;
     }
@@ -397,8 +410,10 @@ __device__ __forceinline__ void exec_one(const InterpArgs &A, const BlockCtx &B,
         break;   // validated programs contain no other opcode
     }
     }
-    const int32_t old = t.r[d];
-    t.r[d] = W.on ? W.v : old;
+    if (W.writes) {
+        const int32_t old = t.r[d];
+        t.r[d] = W.on ? W.v : old;
+    }
 }
 
 __device__ __forceinline__ void setup_block(const InterpArgs &A, BlockCtx &B, const Shared &S, Lane &t, uint32_t unit,
@@ -414,13 +429,8 @@ __device__ __forceinline__ void setup_block(const InterpArgs &A, BlockCtx &B, co
     B.n_words = u->n_words;
     B.sh_words = u->sh_words;
     B.tid = threadIdx.x;
-    const uint32_t bx = u->bdim[0], by = u->bdim[1], gx = u->gdim[0], gy = u->gdim[1];
-    B.sreg_lane[0] = (int32_t)(B.tid % bx);
-    B.sreg_lane[1] = (int32_t)((B.tid / bx) % by);
-    B.sreg_lane[2] = (int32_t)(B.tid / (bx * by));
-    B.sreg_lane[3] = (int32_t)(block % gx);
-    B.sreg_lane[4] = (int32_t)((block / gx) % gy);
-    B.sreg_lane[5] = (int32_t)(block / (gx * gy));
+    B.kbase = rec_pack(A.kp, unit, 0u, 0u, block, 0u, B.tid, 0u);
+    B.kep = B.kbase;
     for (uint32_t i = threadIdx.x; i < B.sh_words; i += blockDim.x) S.sh[i] = 0;
     t.pc = 0;
     t.st = (B.tid < B.nt) ? ST_RUN : ST_DEAD;
@@ -444,6 +454,7 @@ __device__ __forceinline__ void run_block_free(const InterpArgs &A, BlockCtx &B,
     Pending P{false, false, 0, 0};
     bool conv = true;    // every running lane of the wave is at upc
     int upc = 0;
+    uint32_t guard = B.u->fuel;     // lower bound of every live lane's fuel
     for (;;) {
         for (;;) {
             uint64_t runm = __ballot(t.st == ST_RUN);
@@ -462,13 +473,17 @@ __device__ __forceinline__ void run_block_free(const InterpArgs &A, BlockCtx &B,
                 if (active) t.st = ST_EXIT;
                 continue;
             }
-            const bool nofuel = active && t.fuel == 0;
-            if (__ballot(nofuel)) {
+            // Every lane that has not exited holds at least `guard` fuel, so the
+            // per-lane check is needed only when the guard runs out.
+            if (guard == 0) {
+                const bool nofuel = active && t.fuel == 0;
                 emit_fault(nofuel, A, B, F_FUEL, epoch, 0, B.tid, 0, 0);
                 if (nofuel) { t.st = ST_EXIT; active = false; }
+                guard = wave_min_u((t.st == ST_RUN || t.st == ST_WAIT) ? t.fuel : 0xFFFFFFFFu);
                 if (__ballot(active) == 0) continue;
             }
             if (active) t.fuel--;
+            if (guard) guard--;
             int ctl, target;
             bool cond;
             exec_one<false>(A, B, S, t, L, P, epoch, cur, active, ctl, target, cond);
@@ -501,21 +516,41 @@ __device__ __forceinline__ void run_block_free(const InterpArgs &A, BlockCtx &B,
 }
 
 // ---- lockstep (canonical) block execution ---------------------------------------
-__device__ __forceinline__ void run_block_lockstep(const InterpArgs &A, BlockCtx &B, const Shared &S, Lane &t, LogState &L) {
+// Conflict tables of a lockstep step: the highest tid storing to a location in
+// a step wins (stores land in ascending tid order).  Shared memory uses one
+// owner word per simulated shared word; global memory an open-addressing hash
+// table with room for twice the threads of a block.
+// log2 of the global-store hash table size: at least twice the block's threads.
+__host__ __device__ inline uint32_t lockstep_hash_bits(uint32_t wg_threads) {
+    uint32_t b = 1;
+    while ((1u << b) < 2 * wg_threads) b++;
+    return b;
+}
+
+struct StoreTables {
+    uint32_t *own_sh;   // sh_words_max entries, 0 = free
+    uint32_t *gkey;     // hash keys (global word address), EMPTY = free
+    uint32_t *gown;     // owner tid + 1
+    uint32_t hbits;     // log2 of the table size
+};
+constexpr uint32_t EMPTY_KEY = 0xFFFFFFFFu;
+
+__device__ __forceinline__ uint32_t ghash(uint32_t a, uint32_t hbits) { return (a * 2654435761u) >> (32 - hbits); }
+
+__device__ __forceinline__ void run_block_lockstep(const InterpArgs &A, BlockCtx &B, const Shared &S,
+                                                   const StoreTables &T, Lane &t, LogState &L) {
     uint32_t epoch = 0;
+    uint32_t step = 0;
+    bool any_run = true;
     for (;;) {
-        uint64_t runm = __ballot(t.st == ST_RUN);
-        if (lane_id() == 0) S.slots[8 * B.wave + 7] = runm ? 1u : 0u;
-        __syncthreads();
-        uint32_t any = 0;
-        for (uint32_t w = 0; w < B.nwaves; w++) any |= S.slots[8 * w + 7];
-        if (!any) {
+        if (!any_run) {
             if (barrier_episode(A, B, S, t, epoch) == EP_DONE) break;
-            continue;
+            any_run = true;     // a completed episode releases every thread
         }
-        // phase A: every running lane executes exactly one instruction
+        // phase A: every running lane executes exactly one instruction; loads
+        // read memory as of the start of the step, stores are held back
         Pending P{false, false, 0, 0};
-        uint64_t todo = runm;
+        uint64_t todo = __ballot(t.st == ST_RUN);
         while (todo) {
             const bool mine = (todo >> lane_id()) & 1ull;
             int cur = uni(wave_min(mine ? t.pc : INT_MAX));
@@ -540,30 +575,52 @@ __device__ __forceinline__ void run_block_lockstep(const InterpArgs &A, BlockCtx
                 else t.pc = target;
             }
         }
+        // publish (any lane still running, any pending store) for this step;
+        // two slot words alternate by step parity so no extra barrier is needed
+        const uint32_t par = step & 1u;
+        const uint64_t runm = __ballot(t.st == ST_RUN);
+        const uint64_t stm = __ballot(P.on);
+        if (lane_id() == 0) S.slots[8 * B.wave + 6 + par] = (runm ? 1u : 0u) | (stm ? 2u : 0u);
         __syncthreads();
-        // phase B: stores in ascending tid order -- waves in order, and inside a
-        // wave only the highest lane of each (space, addr) stores.
-        for (uint32_t w = 0; w < B.nwaves; w++) {
-            if (w == B.wave) {
-                bool keep = P.on;
-                const int key = P.addr;
-                const bool ksh = P.shared;
-                for (int j = 1; j < WAVE; j++) {
-                    int src = (int)lane_id() + j;
-                    int oa = __shfl(key, src & (WAVE - 1));
-                    int osh = __shfl((int)ksh, src & (WAVE - 1));
-                    int oon = __shfl((int)P.on, src & (WAVE - 1));
-                    if (src < WAVE && oon && oa == key && (bool)osh == ksh) keep = false;
+        uint32_t flags = 0;
+        for (uint32_t w = 0; w < B.nwaves; w++) flags |= S.slots[8 * w + 6 + par];
+        any_run = (flags & 1u) != 0;
+        step++;
+        if (!(flags & 2u)) continue;
+        // phase B: the highest tid per location wins
+        uint32_t slot = 0;
+        if (P.on) {
+            if (P.shared) {
+                atomicMax(&T.own_sh[P.addr], B.tid + 1);
+            } else {
+                const uint32_t mask = (1u << T.hbits) - 1u;
+                slot = ghash((uint32_t)P.addr, T.hbits);
+                for (uint32_t probe = 0; probe <= mask; probe++) {
+                    const uint32_t old = atomicCAS(&T.gkey[slot], EMPTY_KEY, (uint32_t)P.addr);
+                    if (old == EMPTY_KEY || old == (uint32_t)P.addr) break;
+                    slot = (slot + 1) & mask;
                 }
-                if (keep && P.shared) S.sh[P.addr] = P.val;
-                if (keep && !P.shared) B.mem[P.addr] = P.val;
+                atomicMax(&T.gown[slot], B.tid + 1);
             }
-            __syncthreads();
+        }
+        __syncthreads();
+        bool win = false;
+        if (P.on) win = (P.shared ? T.own_sh[P.addr] : T.gown[slot]) == B.tid + 1;
+        if (win && P.shared) S.sh[P.addr] = P.val;
+        if (win && !P.shared) B.mem[P.addr] = P.val;
+        __syncthreads();
+        if (win) {      // one winner per location clears its entry for the next step
+            if (P.shared) {
+                T.own_sh[P.addr] = 0;
+            } else {
+                T.gown[slot] = 0;
+                T.gkey[slot] = EMPTY_KEY;
+            }
         }
     }
 }
 
-__global__ void __launch_bounds__(1024) k_interp_free(InterpArgs A) {
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6, 6))) k_interp_free(InterpArgs A) {
     extern __shared__ __align__(16) uint8_t smem[];
     Shared S;
     const uint32_t nwaves = (blockDim.x + WAVE - 1) / WAVE;
@@ -591,7 +648,7 @@ __global__ void __launch_bounds__(1024) k_interp_free(InterpArgs A) {
     finish_block(A, B, S, L);
 }
 
-__global__ void __launch_bounds__(1024) k_interp_lockstep(InterpArgs A) {
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6, 6))) k_interp_lockstep(InterpArgs A) {
     extern __shared__ __align__(16) uint8_t smem[];
     Shared S;
     const uint32_t nwaves = (blockDim.x + WAVE - 1) / WAVE;
@@ -603,6 +660,18 @@ __global__ void __launch_bounds__(1024) k_interp_lockstep(InterpArgs A) {
     S.slots = (uint32_t *)(smem + off);
     S.slots2 = S.slots + 16 * 8;
 
+    off += (16 * 8 + 16 * 4) * 4;
+    StoreTables T;
+    T.own_sh = (uint32_t *)(smem + off);
+    off += (size_t)A.sh_words_max * 4;
+    T.hbits = lockstep_hash_bits(blockDim.x);
+    T.gkey = (uint32_t *)(smem + off);
+    T.gown = T.gkey + (1u << T.hbits);
+    for (uint32_t i = threadIdx.x; i < A.sh_words_max; i += blockDim.x) T.own_sh[i] = 0;
+    for (uint32_t i = threadIdx.x; i < (1u << T.hbits); i += blockDim.x) {
+        T.gkey[i] = EMPTY_KEY;
+        T.gown[i] = 0;
+    }
     const uint32_t c0 = uniu(A.comp_off[blockIdx.x]), c1 = uniu(A.comp_off[blockIdx.x + 1]);
     BlockCtx B;
     B.nwaves = nwaves;
@@ -612,24 +681,31 @@ __global__ void __launch_bounds__(1024) k_interp_lockstep(InterpArgs A) {
     for (uint32_t c = c0; c < c1; c++) {
         uint2 it = A.comp_blocks[c];
         setup_block(A, B, S, t, uniu(it.x), uniu(it.y));
-        run_block_lockstep(A, B, S, t, L);
+        run_block_lockstep(A, B, S, T, t, L);
         finish_block(A, B, S, L);
     }
 }
 
 }  // namespace
 
-size_t interp_lds_bytes(uint32_t sh_words_max, uint32_t wg_threads, uint32_t stage) {
+size_t interp_lds_bytes(uint32_t sh_words_max, uint32_t wg_threads, uint32_t stage, bool lockstep) {
     const uint32_t nwaves = (wg_threads + WAVE - 1) / WAVE;
     size_t off = ((size_t)sh_words_max * 4 + 15) & ~(size_t)15;
     off += (size_t)nwaves * stage * 8;
     off += (16 * 8 + 16 * 4) * 4;
+    if (lockstep) off += (size_t)sh_words_max * 4 + ((size_t)8 << lockstep_hash_bits(wg_threads));
     return off;
 }
 
 hipError_t launch_interp(const InterpArgs &a, uint32_t n_wg, uint32_t wg_threads, bool lockstep, hipStream_t s) {
     if (n_wg == 0) return hipSuccess;
-    const size_t lds = interp_lds_bytes(a.sh_words_max, wg_threads, a.stage);
+    InterpArgs args = a;
+    size_t lds = interp_lds_bytes(args.sh_words_max, wg_threads, args.stage, lockstep);
+    while (lds > 160 * 1024 && args.stage > 64) {   // shrink the record staging area to fit
+        args.stage /= 2;
+        lds = interp_lds_bytes(args.sh_words_max, wg_threads, args.stage, lockstep);
+    }
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
     static bool attr_set = false;
     if (!attr_set) {
         hipError_t e1 = hipFuncSetAttribute((const void *)k_interp_free, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -641,9 +717,9 @@ hipError_t launch_interp(const InterpArgs &a, uint32_t n_wg, uint32_t wg_threads
         attr_set = true;
     }
     if (lockstep)
-        hipLaunchKernelGGL(k_interp_lockstep, dim3(n_wg), dim3(wg_threads), lds, s, a);
+        hipLaunchKernelGGL(k_interp_lockstep, dim3(n_wg), dim3(wg_threads), lds, s, args);
     else
-        hipLaunchKernelGGL(k_interp_free, dim3(n_wg), dim3(wg_threads), lds, s, a);
+        hipLaunchKernelGGL(k_interp_free, dim3(n_wg), dim3(wg_threads), lds, s, args);
     return hipGetLastError();
 }
 

@@ -103,7 +103,7 @@ struct DBuf {
 struct Workspace {
     DBuf units, items, comp_off, comp_blocks, mask;
     DBuf snap, log, alt, rlog, ralt, fs, hist, part;
-    DBuf faults, rfaults, races, edges, blk_recs, rblk_recs, blk_flags, ctr, rctr;
+    DBuf faults, rfaults, races, edges, blk_recs, rblk_recs, blk_flags, rflags, ctr, rctr;
     DevCounters *h_ctr = nullptr;   // pinned
     hipEvent_t ev[8] = {};
     bool init = false;
@@ -116,7 +116,7 @@ struct Workspace {
     size_t device_bytes() const {
         const DBuf *all[] = {&units, &items, &comp_off, &comp_blocks, &mask, &snap, &log, &alt, &rlog,
                              &ralt, &fs, &hist, &part, &faults, &rfaults, &races, &edges, &blk_recs,
-                             &rblk_recs, &blk_flags, &ctr, &rctr};
+                             &rblk_recs, &blk_flags, &rflags, &ctr, &rctr};
         size_t s = 0;
         for (auto *b : all) s += b->bytes;
         return s;
@@ -124,7 +124,7 @@ struct Workspace {
     ~Workspace() {
         DBuf *all[] = {&units, &items, &comp_off, &comp_blocks, &mask, &snap, &log, &alt, &rlog,
                        &ralt, &fs, &hist, &part, &faults, &rfaults, &races, &edges, &blk_recs,
-                       &rblk_recs, &blk_flags, &ctr, &rctr};
+                       &rblk_recs, &blk_flags, &rflags, &ctr, &rctr};
         for (auto *b : all) b->release();
         if (h_ctr) (void)hipHostFree(h_ctr);
         for (auto &e : ev)
@@ -521,52 +521,11 @@ struct Stage {
         uint64_t *sorted = ws.log.as<uint64_t>();
         const uint64_t nrec = c.log_count;
         if (check && nrec) {
-            SortScratch sc;
-            ws.alt.reserve(nrec * 8);
-            ws.hist.reserve(radix_hist_entries(nrec, ctx->opt.sort_tile) * 4);
-            ws.part.reserve(((radix_hist_entries(nrec, ctx->opt.sort_tile) / 256 + 255) / 256 + 1) * 256 * 4);
-            sc.alt = ws.alt.as<uint64_t>();
-            sc.hist = ws.hist.as<uint32_t>();
-            sc.part = ws.part.as<uint32_t>();
             tm.mark(2);
-            HIPCHK(radix_sort(ws.log.as<uint64_t>(), nrec, check_key(), sc, ctx->opt.sort_tile, s, &sorted));
+            sorted = sort_check(ws.log, ws.alt, nrec);
             tm.mark(3);
-            uint32_t race_cap = 4096, edge_cap = 4096;
-            for (;;) {
-                ws.races.reserve((size_t)race_cap * sizeof(DevRace));
-                ws.edges.reserve((size_t)edge_cap * sizeof(DevEdge));
-                reset_counters(ws.rctr);
-                HIPCHK(launch_zero(ws.blk_flags.p, (size_t)total_blocks * 4, s));
-                CheckArgs ca{};
-                ca.keys = sorted;
-                ca.n = nrec;
-                ca.kp = kp;
-                ca.units = ws.units.as<DevUnit>();
-                ca.races = ws.races.as<DevRace>();
-                ca.race_cap = race_cap;
-                ca.edges = ws.edges.as<DevEdge>();
-                ca.edge_cap = edge_cap;
-                ca.blk_flags = ws.blk_flags.as<uint32_t>();
-                ca.ctr = ws.rctr.as<DevCounters>();
-                HIPCHK(launch_check(ca, s));
-                tm.mark(4);
-                DevCounters rc = read_ctr(ws.rctr);
-                if (rc.flags & (FLAG_RACE_OVERFLOW | FLAG_EDGE_OVERFLOW)) {
-                    race_cap = std::max(race_cap, rc.race_count + 1024);
-                    edge_cap = std::max(edge_cap, rc.edge_count + 1024);
-                    continue;
-                }
-                races.resize(rc.race_count);
-                edges.resize(rc.edge_count);
-                if (!races.empty())
-                    HIPCHK(hipMemcpyAsync(races.data(), ws.races.p, races.size() * sizeof(DevRace),
-                                          hipMemcpyDeviceToHost, s));
-                if (!edges.empty())
-                    HIPCHK(hipMemcpyAsync(edges.data(), ws.edges.p, edges.size() * sizeof(DevEdge),
-                                          hipMemcpyDeviceToHost, s));
-                HIPCHK(hipStreamSynchronize(s));
-                break;
-            }
+            run_check(sorted, nrec, ws.blk_flags, races, edges);
+            tm.mark(4);
             ctx->stat_add("sort_ms", tm.ms(2, 3));
             ctx->stat_add("check_ms", tm.ms(3, 4));
             ctx->stat_add("sort_keys", (double)nrec);
@@ -597,19 +556,64 @@ struct Stage {
         }
     }
 
-    void sort_full(DBuf &keys, DBuf &alt, uint64_t n, uint64_t **res) {
+    // Sort n records held in `keys` into check order; returns the sorted array
+    // (keys itself or alt).
+    uint64_t *sort_check(DBuf &keys, DBuf &alt, uint64_t n) {
+        uint64_t *res = keys.as<uint64_t>();
+        if (n <= 1) return res;
         SortScratch sc;
-        alt.reserve(std::max<uint64_t>(n, 1) * 8);
+        alt.reserve(n * 8);
         ws.hist.reserve(radix_hist_entries(n, ctx->opt.sort_tile) * 4);
-        ws.part.reserve(((radix_hist_entries(n, ctx->opt.sort_tile) / 256 + 255) / 256 + 1) * 256 * 4);
+        ws.part.reserve((radix_hist_entries(n, ctx->opt.sort_tile) / 256 / 32 + 2) * 256 * 4);
         sc.alt = alt.as<uint64_t>();
         sc.hist = ws.hist.as<uint32_t>();
         sc.part = ws.part.as<uint32_t>();
-        HIPCHK(radix_sort(keys.as<uint64_t>(), n, full_key(), sc, ctx->opt.sort_tile, s, res));
+        HIPCHK(radix_sort(keys.as<uint64_t>(), n, check_key(), sc, ctx->opt.sort_tile, s, &res));
+        return res;
     }
 
-    // Lockstep re-execution of `comps` (lists of (unit, block)); returns the
-    // replay counters.  The replay log ends up in ws.rlog.
+    // Conflict check over sorted records: races and cross-block links to the
+    // host, racy blocks flagged in `flags`.
+    void run_check(const uint64_t *sorted, uint64_t n, DBuf &flags, std::vector<DevRace> &races,
+                   std::vector<DevEdge> &edges) {
+        uint32_t race_cap = 4096, edge_cap = 4096;
+        flags.reserve((size_t)std::max<uint32_t>(total_blocks, 1) * 4);
+        for (;;) {
+            ws.races.reserve((size_t)race_cap * sizeof(DevRace));
+            ws.edges.reserve((size_t)edge_cap * sizeof(DevEdge));
+            reset_counters(ws.rctr);
+            HIPCHK(launch_zero(flags.p, (size_t)total_blocks * 4, s));
+            CheckArgs ca{};
+            ca.keys = sorted;
+            ca.n = n;
+            ca.kp = kp;
+            ca.units = ws.units.as<DevUnit>();
+            ca.races = ws.races.as<DevRace>();
+            ca.race_cap = race_cap;
+            ca.edges = ws.edges.as<DevEdge>();
+            ca.edge_cap = edge_cap;
+            ca.blk_flags = flags.as<uint32_t>();
+            ca.ctr = ws.rctr.as<DevCounters>();
+            HIPCHK(launch_check(ca, s));
+            DevCounters rc = read_ctr(ws.rctr);
+            if (rc.flags & (FLAG_RACE_OVERFLOW | FLAG_EDGE_OVERFLOW)) {
+                race_cap = std::max(race_cap, rc.race_count + 1024);
+                edge_cap = std::max(edge_cap, rc.edge_count + 1024);
+                continue;
+            }
+            races.resize(rc.race_count);
+            edges.resize(rc.edge_count);
+            if (!races.empty())
+                HIPCHK(hipMemcpyAsync(races.data(), ws.races.p, races.size() * sizeof(DevRace),
+                                      hipMemcpyDeviceToHost, s));
+            if (!edges.empty())
+                HIPCHK(hipMemcpyAsync(edges.data(), ws.edges.p, edges.size() * sizeof(DevEdge),
+                                      hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            return;
+        }
+    }
+
     // Upload components (lists of (unit, block)) for the lockstep kernel.
     void upload_comps(const std::vector<std::vector<uint2>> &comps) {
         std::vector<uint32_t> off{0};
@@ -639,81 +643,94 @@ struct Stage {
         return c;
     }
 
+    // Racy blocks: re-execute them canonically and take their records, findings
+    // and memory from the re-execution.  This is exact when (1) no replayed
+    // global access conflicts with an access of a block that was not replayed
+    // and (2) the components replayed side by side do not conflict with each
+    // other; then the canonical execution is the free run of the other blocks
+    // plus the replay, and its races are those of the replayed records.
+    // Otherwise every block of the affected units is re-executed canonically.
     void replay(const std::vector<DevRace> &races, const std::vector<DevEdge> &edges, const uint64_t *sorted,
                 uint64_t nrec, std::vector<std::vector<kc_fault>> &ufaults,
                 std::vector<std::vector<kc_race>> &uraces, std::vector<uint64_t> &urecs, Timer &tm) {
         tm.mark(5);
         DSU dsu;
-        for (auto &r : races) {
-            if (r.scope == 0) dsu.find(ub_key(r.unit, r.block));
-            else dsu.find(ub_key(r.unit, r.block));
-        }
+        for (auto &r : races) dsu.find(ub_key(r.unit, r.block));
         for (auto &e : edges) dsu.unite(ub_key(e.unit, e.b0), ub_key(e.unit, e.b1));
         std::map<uint64_t, std::vector<uint2>> groups;
         std::vector<uint64_t> keys;
         for (auto &kv : dsu.p) keys.push_back(kv.first);
         for (uint64_t k : keys) groups[dsu.find(k)].push_back(make_uint2((uint32_t)(k >> 32), (uint32_t)k));
         std::vector<std::vector<uint2>> comps;
+        std::unordered_map<uint64_t, uint32_t> comp_of;
         uint64_t s_recs = 0;
         for (auto &kv : groups) {
             auto v = kv.second;
             std::sort(v.begin(), v.end(), [](uint2 a, uint2 b) { return a.x != b.x ? a.x < b.x : a.y < b.y; });
-            for (auto &ub : v) s_recs += blk_recs[hu[ub.x].block_base + ub.y];
+            for (auto &ub : v) {
+                s_recs += blk_recs[hu[ub.x].block_base + ub.y];
+                comp_of[ub_key(ub.x, ub.y)] = (uint32_t)comps.size();
+            }
             comps.push_back(std::move(v));
         }
         ctx->stat_add("replays", (double)comps.size());
 
-        // restore what the racy blocks wrote, then re-execute them canonically
+        // put back what the racy blocks wrote, then re-execute them canonically
         HIPCHK(launch_restore(sorted, nrec, kp, ws.units.as<DevUnit>(), ws.blk_flags.as<uint32_t>(), s));
         uint64_t rcap = s_recs + s_recs / 4 + 1024;
         uint32_t fcap = 4096;
         DevCounters rc = lockstep_once(comps, rcap, fcap);
-
-        // compare replayed records with the free-run records of the same blocks
-        bool same = false;
-        if (rc.log_count == s_recs && !(rc.flags & (FLAG_LOG_OVERFLOW | FLAG_FAULT_OVERFLOW))) {
-            ws.fs.reserve(std::max<uint64_t>(s_recs, 1) * 8);
+        bool ok = !(rc.flags & (FLAG_LOG_OVERFLOW | FLAG_FAULT_OVERFLOW));
+        std::vector<DevRace> rr;
+        std::vector<DevEdge> re;
+        if (ok) {
+            used_epoch_bits = std::max(used_epoch_bits, bits_for((uint64_t)rc.max_epoch + 1));
+            uint64_t *rs = sort_check(ws.rlog, ws.ralt, rc.log_count);
+            run_check(rs, rc.log_count, ws.rflags, rr, re);
             reset_counters(ws.ctr);
-            HIPCHK(launch_extract(sorted, nrec, kp, ws.units.as<DevUnit>(), ws.blk_flags.as<uint32_t>(),
-                                  ws.fs.as<uint64_t>(), s_recs, &ws.ctr.as<DevCounters>()->aux_count, s));
-            uint64_t *fs_sorted = nullptr, *rs_sorted = nullptr;
-            sort_full(ws.fs, ws.alt, s_recs, &fs_sorted);
-            sort_full(ws.rlog, ws.ralt, s_recs, &rs_sorted);
-            HIPCHK(launch_compare(fs_sorted, rs_sorted, s_recs, &ws.ctr.as<DevCounters>()->flags, s));
-            DevCounters cc = read_ctr(ws.ctr);
-            same = cc.aux_count == s_recs && !(cc.flags & FLAG_MISMATCH);
+            HIPCHK(launch_coverage(rs, rc.log_count, sorted, nrec, kp, ws.units.as<DevUnit>(),
+                                   ws.blk_flags.as<uint32_t>(), &ws.ctr.as<DevCounters>()->flags, s));
+            ok = !(read_ctr(ws.ctr).flags & FLAG_MISMATCH);
+            for (auto &e : re)
+                if (comp_of[ub_key(e.unit, e.b0)] != comp_of[ub_key(e.unit, e.b1)]) ok = false;
         }
-        std::vector<DevFault> rf(std::min<uint32_t>(rc.fault_count, fcap));
-        if (!rf.empty())
-            HIPCHK(hipMemcpyAsync(rf.data(), ws.rfaults.p, rf.size() * sizeof(DevFault), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-
-        if (same) {
-            // verdict stands; findings of the replayed blocks come from the replay
+        if (ok) {
+            std::vector<DevFault> rf(std::min<uint32_t>(rc.fault_count, fcap));
+            if (!rf.empty())
+                HIPCHK(hipMemcpyAsync(rf.data(), ws.rfaults.p, rf.size() * sizeof(DevFault), hipMemcpyDeviceToHost, s));
+            std::vector<uint32_t> rrecs(total_blocks);
+            HIPCHK(hipMemcpyAsync(rrecs.data(), ws.rblk_recs.p, (size_t)total_blocks * 4, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
             std::vector<char> in_s(total_blocks, 0);
             for (auto &c : comps)
-                for (auto &ub : c) in_s[hu[ub.x].block_base + ub.y] = 1;
+                for (auto &ub : c) {
+                    const uint32_t gb = hu[ub.x].block_base + ub.y;
+                    in_s[gb] = 1;
+                    urecs[ub.x] += (uint64_t)rrecs[gb];
+                    urecs[ub.x] -= (uint64_t)blk_recs[gb];
+                }
             for (uint32_t u = 0; u < hu.size(); u++) {
                 auto &fv = ufaults[u];
                 fv.erase(std::remove_if(fv.begin(), fv.end(),
                                         [&](const kc_fault &f) { return in_s[hu[u].block_base + f.block]; }),
                          fv.end());
+                uraces[u].clear();      // every free-run race involved replayed blocks only
             }
             for (auto &f : rf) ufaults[f.unit].push_back(kc_fault{0, f.kind, f.block, f.epoch, f.a, f.b, f.c, f.d});
+            for (auto &r : rr) uraces[r.unit].push_back(kc_race{0, r.space, r.scope, r.block, r.epoch, r.addr, r.w, r.o});
             tm.mark(6);
             ctx->stat_add("replay_ms", tm.ms(5, 6));
             return;
         }
 
-        // General case: the racy blocks' accesses depended on racy values.  Re-run
-        // every block of the affected units canonically from the snapshot.
+        // General case: re-run every block of the affected units canonically
+        // from the launch-start snapshot and check those records.
         ctx->stat_add("fallbacks", 1);
         std::vector<uint32_t> mask(hu.size(), 0);
         for (auto &c : comps)
             for (auto &ub : c) mask[ub.x] = 1;
         ws.mask.reserve(mask.size() * 4);
         HIPCHK(hipMemcpyAsync(ws.mask.p, mask.data(), mask.size() * 4, hipMemcpyHostToDevice, s));
-        HIPCHK(launch_copy_units(ws.units.as<DevUnit>(), (uint32_t)hu.size(), max_words, false, ws.mask.as<uint32_t>(), s));
         std::vector<std::vector<uint2>> full;
         uint64_t need = 0;
         for (uint32_t u = 0; u < hu.size(); u++) {
@@ -727,13 +744,13 @@ struct Stage {
         }
         rcap = std::max<uint64_t>(rcap, need + need / 4 + 1024);
         DevCounters fc;
-        for (;;) {   // a full re-run starts from the snapshot of the whole unit
+        for (;;) {
+            HIPCHK(launch_copy_units(ws.units.as<DevUnit>(), (uint32_t)hu.size(), max_words, false,
+                                     ws.mask.as<uint32_t>(), s));
             fc = lockstep_once(full, rcap, fcap);
             if (!(fc.flags & (FLAG_LOG_OVERFLOW | FLAG_FAULT_OVERFLOW))) break;
             rcap = std::max<uint64_t>(rcap, fc.log_count + 1024);
             fcap = std::max<uint32_t>(fcap, fc.fault_count + 1024);
-            HIPCHK(launch_copy_units(ws.units.as<DevUnit>(), (uint32_t)hu.size(), max_words, false,
-                                     ws.mask.as<uint32_t>(), s));
         }
         std::vector<DevFault> ff(std::min<uint32_t>(fc.fault_count, fcap));
         if (!ff.empty())
@@ -741,51 +758,11 @@ struct Stage {
         std::vector<uint32_t> rrecs(total_blocks);
         HIPCHK(hipMemcpyAsync(rrecs.data(), ws.rblk_recs.p, (size_t)total_blocks * 4, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
-        // check the canonical records
-        uint64_t *rs_sorted = nullptr;
-        {
-            SortScratch sc;
-            ws.ralt.reserve(std::max<uint64_t>(fc.log_count, 1) * 8);
-            ws.hist.reserve(radix_hist_entries(fc.log_count, ctx->opt.sort_tile) * 4);
-            ws.part.reserve(((radix_hist_entries(fc.log_count, ctx->opt.sort_tile) / 256 + 255) / 256 + 1) * 256 * 4);
-            sc.alt = ws.ralt.as<uint64_t>();
-            sc.hist = ws.hist.as<uint32_t>();
-            sc.part = ws.part.as<uint32_t>();
-            used_epoch_bits = std::max(used_epoch_bits, bits_for((uint64_t)fc.max_epoch + 1));
-            HIPCHK(radix_sort(ws.rlog.as<uint64_t>(), fc.log_count, check_key(), sc, ctx->opt.sort_tile, s,
-                              &rs_sorted));
-        }
-        uint32_t race_cap = 4096, edge_cap = 4096;
+        used_epoch_bits = std::max(used_epoch_bits, bits_for((uint64_t)fc.max_epoch + 1));
+        uint64_t *rs = sort_check(ws.rlog, ws.ralt, fc.log_count);
         std::vector<DevRace> nr;
-        for (;;) {
-            ws.races.reserve((size_t)race_cap * sizeof(DevRace));
-            ws.edges.reserve((size_t)edge_cap * sizeof(DevEdge));
-            reset_counters(ws.rctr);
-            HIPCHK(launch_zero(ws.blk_flags.p, (size_t)total_blocks * 4, s));
-            CheckArgs ca{};
-            ca.keys = rs_sorted;
-            ca.n = fc.log_count;
-            ca.kp = kp;
-            ca.units = ws.units.as<DevUnit>();
-            ca.races = ws.races.as<DevRace>();
-            ca.race_cap = race_cap;
-            ca.edges = ws.edges.as<DevEdge>();
-            ca.edge_cap = edge_cap;
-            ca.blk_flags = ws.blk_flags.as<uint32_t>();
-            ca.ctr = ws.rctr.as<DevCounters>();
-            HIPCHK(launch_check(ca, s));
-            DevCounters c2 = read_ctr(ws.rctr);
-            if (c2.flags & (FLAG_RACE_OVERFLOW | FLAG_EDGE_OVERFLOW)) {
-                race_cap = std::max(race_cap, c2.race_count + 1024);
-                edge_cap = std::max(edge_cap, c2.edge_count + 1024);
-                continue;
-            }
-            nr.resize(c2.race_count);
-            if (!nr.empty())
-                HIPCHK(hipMemcpyAsync(nr.data(), ws.races.p, nr.size() * sizeof(DevRace), hipMemcpyDeviceToHost, s));
-            HIPCHK(hipStreamSynchronize(s));
-            break;
-        }
+        std::vector<DevEdge> ne;
+        run_check(rs, fc.log_count, ws.rflags, nr, ne);
         for (uint32_t u = 0; u < hu.size(); u++) {
             if (!mask[u]) continue;
             uraces[u].clear();
@@ -798,7 +775,6 @@ struct Stage {
         tm.mark(6);
         ctx->stat_add("replay_ms", tm.ms(5, 6));
     }
-
 };
 
 kc_status fail(kc_ctx *ctx, const KcError &e) {

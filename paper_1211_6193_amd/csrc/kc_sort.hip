@@ -18,7 +18,7 @@ namespace {
 constexpr int WAVE = 64;
 constexpr int WG = 256;
 constexpr int NW = WG / WAVE;
-constexpr int CHUNK = 256;     // tiles per column-scan chunk
+constexpr int CHUNK = 32;      // tiles per column-scan chunk
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
@@ -66,38 +66,57 @@ __global__ void __launch_bounds__(WG) k_rs_colsum(const uint32_t *__restrict__ h
     part[(size_t)blockIdx.x * 256 + d] = s;
 }
 
-// part[c][d] becomes the exclusive start of (chunk c, digit d) in the output.
-__global__ void __launch_bounds__(WG) k_rs_top(uint32_t *__restrict__ part, uint32_t n_chunks) {
-    __shared__ uint32_t tot[256];
-    const uint32_t d = threadIdx.x;
-    uint32_t run = 0;
-    for (uint32_t c = 0; c < n_chunks; c++) {
-        uint32_t v = part[(size_t)c * 256 + d];
+// Block-wide exclusive scan of one value per thread (256 threads).
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *tmp, uint32_t &total) {
+    const uint32_t t = threadIdx.x;
+    tmp[t] = v;
+    __syncthreads();
+    uint32_t x = v;
+    for (uint32_t o = 1; o < WG; o <<= 1) {
+        const uint32_t y = t >= o ? tmp[t - o] : 0;
+        __syncthreads();
+        x += y;
+        tmp[t] = x;
+        __syncthreads();
+    }
+    total = tmp[WG - 1];
+    __syncthreads();
+    return x - v;
+}
+
+// Column scan of one digit (blockIdx.x) over the chunk partials:
+// part[c][d] becomes the exclusive start of chunk c within digit d, and
+// tot[d] the digit's total.
+__global__ void __launch_bounds__(WG) k_rs_top(uint32_t *__restrict__ part, uint32_t n_chunks,
+                                               uint32_t *__restrict__ tot) {
+    __shared__ uint32_t tmp[WG];
+    const uint32_t d = blockIdx.x;
+    const uint32_t per = (n_chunks + WG - 1) / WG;
+    const uint32_t c0 = threadIdx.x * per, c1 = min(c0 + per, n_chunks);
+    uint32_t sum = 0;
+    for (uint32_t c = c0; c < c1; c++) sum += part[(size_t)c * 256 + d];
+    uint32_t total;
+    uint32_t run = block_exclusive_scan(sum, tmp, total);
+    for (uint32_t c = c0; c < c1; c++) {
+        const uint32_t v = part[(size_t)c * 256 + d];
         part[(size_t)c * 256 + d] = run;
         run += v;
     }
-    tot[d] = run;
-    __syncthreads();
-    // exclusive scan of the 256 digit totals (Hillis-Steele on a copy)
-    uint32_t x = tot[d];
-    for (uint32_t o = 1; o < 256; o <<= 1) {
-        uint32_t y = d >= o ? tot[d - o] : 0;
-        __syncthreads();
-        x += y;
-        tot[d] = x;
-        __syncthreads();
-    }
-    const uint32_t base = x - run;
-    for (uint32_t c = 0; c < n_chunks; c++) part[(size_t)c * 256 + d] += base;
+    if (threadIdx.x == 0) tot[d] = total;
 }
 
+// Per-tile global start offsets: digit base + chunk start + tiles before.
 __global__ void __launch_bounds__(WG) k_rs_apply(uint32_t *__restrict__ hist, uint32_t n_tiles,
-                                                 const uint32_t *__restrict__ part) {
+                                                 const uint32_t *__restrict__ part,
+                                                 const uint32_t *__restrict__ tot) {
+    __shared__ uint32_t tmp[WG];
     const uint32_t d = threadIdx.x;
+    uint32_t all;
+    const uint32_t base = block_exclusive_scan(tot[d], tmp, all);
     const uint32_t t0 = blockIdx.x * CHUNK, t1 = min(t0 + CHUNK, n_tiles);
-    uint32_t run = part[(size_t)blockIdx.x * 256 + d];
+    uint32_t run = base + part[(size_t)blockIdx.x * 256 + d];
     for (uint32_t t = t0; t < t1; t++) {
-        uint32_t v = hist[(size_t)t * 256 + d];
+        const uint32_t v = hist[(size_t)t * 256 + d];
         hist[(size_t)t * 256 + d] = run;
         run += v;
     }
@@ -199,8 +218,9 @@ hipError_t sort_passes(uint64_t *keys, uint64_t n, const VKey &vk, uint32_t hi, 
         const uint32_t bits = (hi - sh) < 8 ? (hi - sh) : 8;
         hipLaunchKernelGGL(k_rs_hist<ITEMS>, dim3(n_tiles), dim3(WG), 0, s, a, n, vk, sh, bits, sc.hist);
         hipLaunchKernelGGL(k_rs_colsum, dim3(n_chunks), dim3(WG), 0, s, sc.hist, n_tiles, sc.part);
-        hipLaunchKernelGGL(k_rs_top, dim3(1), dim3(WG), 0, s, sc.part, n_chunks);
-        hipLaunchKernelGGL(k_rs_apply, dim3(n_chunks), dim3(WG), 0, s, sc.hist, n_tiles, sc.part);
+        hipLaunchKernelGGL(k_rs_top, dim3(256), dim3(WG), 0, s, sc.part, n_chunks, sc.part + (size_t)n_chunks * 256);
+        hipLaunchKernelGGL(k_rs_apply, dim3(n_chunks), dim3(WG), 0, s, sc.hist, n_tiles, sc.part,
+                           sc.part + (size_t)n_chunks * 256);
         hipLaunchKernelGGL(k_rs_scatter<ITEMS>, dim3(n_tiles), dim3(WG), 0, s, a, b, n, vk, sh, bits, sc.hist);
         uint64_t *t = a; a = b; b = t;
     }

@@ -155,3 +155,29 @@ def test_edge_cases(ctx):
             assert_same(rep, mem, O.run_job(job, fuel=fuel), name)
     finally:
         ctx.set_option("fuel", O.DEFAULT_FUEL)
+
+
+def _redirect_program(reader_block_reads_0: bool):
+    """Block 0: thread 0 writes shared[0] = 5 while thread 1 reads shared[0]
+    without a barrier and stores its tid to global[that value].  Under the
+    canonical lockstep schedule thread 1 reads 0; a free-running wave may read 5.
+    Block 1 (optional) reads global[0]."""
+    a = ir.Asm()
+    a.SREG(0, "TID").SREG(3, "BID").BNZ(3, "B1")
+    a.BNZ(0, "L1").MOVI(1, 5).STS(15, 0, 1).JMP("END")
+    a.label("L1").SEQI(4, 0, 1).BZ(4, "END").LDS(2, 15, 0).STG(2, 0, 0).JMP("END")
+    a.label("B1")
+    if reader_block_reads_0:
+        a.BNZ(0, "END").LDG(5, 15, 0).STG(15, 9, 5)
+    a.label("END").EXIT()
+    return a.assemble()
+
+
+def test_replay_paths(ctx):
+    for reads0 in (False, True):
+        job = _single(_redirect_program(reads0), (2, 1, 1), (2, 1, 1), 16, [7] * 10)
+        say(f"replay path, second block reads global[0]: {reads0}")
+        ctx.reset_stats()
+        rep, mem = kc.run_job(ctx, job)
+        assert_same(rep, mem, O.run_job(job), f"redirect {reads0}")
+        assert ctx.stat("replays") >= 1
