@@ -34,6 +34,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target CPU time of the oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the workload-3 batched vs plain comparison")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the checker's "
@@ -72,7 +73,9 @@ def main():
     value = records * args.steps / elapsed
 
     stats = {k: ctx.stat(k) for k in ("interp_ms", "sort_ms", "check_ms", "replay_ms", "replays",
-                                      "fallbacks", "retries", "sort_keys", "records", "interp_launches")}
+                                      "fallbacks", "retries", "sort_keys", "records", "interp_launches",
+                                      "replay_lockstep_ms", "replay_sort_ms", "replay_check_ms",
+                                      "replay_coverage_ms", "log_entries")}
     # bit-exact check of the final step against the oracle
     from oracle import oracle as O
     t_o = time.perf_counter()
@@ -110,6 +113,9 @@ def main():
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                 "avg_ms": round(per[dom], 4), "bytes_per_launch": int(bytes_launch),
                 "stage_ms": {k: round(v, 4) for k, v in per.items()},
+                "replay_detail_ms": {k: round(stats[k] / args.steps, 4) for k in
+                                     ("replay_lockstep_ms", "replay_sort_ms", "replay_check_ms", "replay_coverage_ms")},
+                "log_entries_per_step": stats["log_entries"] / args.steps,
                 "path_algorithmic_frac": round(value * 16 / (HBM_PEAK_GBS * 1e9), 4)}
 
     cpu = None
@@ -121,6 +127,8 @@ def main():
         cs = time.perf_counter() - t_c
         cpu = {"value": round(orc.records * reps / cs, 1), "unit": "records/s", "cores": 1, "kind": "oracle",
                "sample": f"the same workload run {reps}x by the single-threaded C oracle ({cs:.1f} s)"}
+
+    batched = None if args.no_batched else batched_vs_plain(ctx, W, kc, O, torch, np)
 
     lat_ms = sorted(x * 1e3 for x in lat)
     out = {
@@ -136,11 +144,61 @@ def main():
                    "replays_per_step": stats["replays"] / args.steps, "fallbacks": stats["fallbacks"]},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "batched_vs_plain": batched,
     }
     print(json.dumps(out), flush=True)
     ctx.close()
     if not exact:
         sys.exit(1)
+
+
+def batched_vs_plain(ctx, W, kc, O, torch, np, reps=3, plain_sample=200, verify=40):
+    """Workload 3 (10,000 mixed instances, seed 12116196): the whole set as one
+    batch (kc_batch_submit + kc_poll) against one plain kc_launch per instance
+    on a sample of instances; both on the same resident memories (the
+    instances read their inputs and write disjoint outputs, so reruns are
+    identical).  A sample of instances is compared with the oracle."""
+    jobs = W.config3_jobs(n=10000)
+    mems = [torch.from_numpy(np.ascontiguousarray(j.memory)).cuda() for j in jobs]
+    batch = kc.Batch(ctx)
+    prep = batch.prepare([(kc.job_launches(ctx, j), m, i) for i, (j, m) in enumerate(zip(jobs, mems))])
+    stream = torch.cuda.current_stream()
+    res = batch.poll(batch.submit(prep, stream=stream), wait=True)          # warm-up
+    times = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = batch.poll(batch.submit(prep, stream=stream), wait=True)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    records = sum(r.records for r in res)
+    best = min(times)
+    idx = list(range(0, len(jobs), max(1, len(jobs) // plain_sample)))[:plain_sample]
+    launches = [(ctx.program(jobs[i].launches[0].program), jobs[i].launches[0]) for i in idx]
+    lat, prec = [], 0
+    torch.cuda.synchronize()
+    for (p, L), i in zip(launches, idx):
+        t0 = time.perf_counter()
+        r = kc.launch(ctx, p, L.grid, L.block, L.shmem_bytes, mems[i], L.params, stream=stream)
+        lat.append(time.perf_counter() - t0)
+        prec += r.records
+    plain_rate = prec / sum(lat)
+    exact = True
+    for i in idx[:verify]:
+        orc = O.run_job(jobs[i])
+        r = res[i]
+        exact &= (r.records == orc.records and r.race_tuples() == orc.race_tuples()
+                  and r.fault_tuples() == orc.fault_tuples() and bool(np.array_equal(mems[i].cpu().numpy(), orc.memory)))
+    lat_ms = sorted(x * 1e3 for x in lat)
+    return {"workload": "workload 3: 10000 instances (tree/stencil/transpose, 1-64 blocks x 32-1024 threads, "
+                        "20% seeded faults)",
+            "records": records, "batched_records_per_s": round(records / best, 1),
+            "batched_ms": round(best * 1e3, 3),
+            "plain_records_per_s": round(plain_rate, 1),
+            "plain_p50_ms": round(lat_ms[len(lat_ms) // 2], 4),
+            "plain_p99_ms": round(lat_ms[min(len(lat_ms) - 1, int(0.99 * len(lat_ms)))], 4),
+            "speedup": round((records / best) / plain_rate, 2),
+            "bit_exact_sample": exact, "verified_instances": min(verify, len(idx))}
 
 
 def _sort_passes(job):

@@ -64,7 +64,9 @@ __global__ void __launch_bounds__(WG) k_check(CheckArgs A) {
         const uint64_t ki = tk[p];
         const uint64_t prev = i ? key_at(i - 1) : ~0ull;
         const uint64_t inner = ki >> ps;
-        const bool head_in = i == 0 || (prev >> ps) != inner;
+        // representative records of locally checked epochs take part only in
+        // the cross-block check
+        const bool head_in = (i == 0 || (prev >> ps) != inner) && rec_field(ki, k.s_ep, k.eb) != k.ep_rep;
         const uint32_t space = rec_field(ki, k.s_sp, 1);
         const bool head_out = space == 1u && (i == 0 || (prev >> k.s_addr) != (ki >> k.s_addr));
         if (!head_in && !head_out) continue;

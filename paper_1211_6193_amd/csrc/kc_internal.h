@@ -44,8 +44,8 @@ struct DevUnit {
 struct KeyPlan {
     uint32_t tb, eb, bb, ab, ub;
     uint32_t s_tid, s_ep, s_blk, s_addr, s_sp, s_unit, total;
-    uint32_t max_epoch;     // largest epoch the field holds
-    uint32_t pad;
+    uint32_t max_epoch;     // largest epoch a block may reach
+    uint32_t ep_rep;        // reserved epoch value of representative records
 };
 
 __host__ __device__ inline uint64_t rec_pack(const KeyPlan &k, uint32_t unit, uint32_t space, uint32_t addr,
@@ -100,12 +100,17 @@ struct InterpArgs {
     uint32_t *flags;
     uint32_t *max_epoch;        // largest epoch reached (atomicMax)
     uint32_t sh_words_max;      // simulated shared words reserved in LDS
-    uint32_t stage;             // staged records per wave
+    uint32_t stage;             // staged records per wave (multiple of 64)
+    uint32_t local;             // check each epoch's records in LDS (free run)
+    DevRace *lraces;            // races found by the epoch-local check
+    uint32_t lrace_cap;
+    uint32_t *lrace_count;
+    uint32_t *blk_flags;        // racy blocks
 };
 
 // Host-side launchers (defined in the .hip files).
 hipError_t launch_interp(const InterpArgs &a, uint32_t n_wg, uint32_t wg_threads, bool lockstep, hipStream_t s);
-size_t interp_lds_bytes(uint32_t sh_words_max, uint32_t wg_threads, uint32_t stage, bool lockstep);
+size_t interp_lds_bytes(uint32_t sh_words_max, uint32_t wg_threads, uint32_t stage, bool lockstep, bool local);
 
 struct SortScratch {
     uint64_t *alt = nullptr;         // ping-pong buffer, >= n keys

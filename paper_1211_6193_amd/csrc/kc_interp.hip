@@ -27,6 +27,7 @@ namespace kc {
 namespace {
 
 constexpr int WAVE = 64;
+constexpr uint32_t NONE_U32 = 0xFFFFFFFFu;
 enum : int { ST_RUN = 0, ST_WAIT = 1, ST_EXIT = 2, ST_DEAD = 3 };
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
@@ -38,21 +39,35 @@ __device__ __forceinline__ uint32_t lane_prefix(uint64_t m) {
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 __device__ __forceinline__ uint32_t uniu(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
 
-__device__ __forceinline__ int wave_min(int v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+// Wave-wide min/max: DPP inside each row of 16 lanes, then the four row
+// results through readlane (no LDS traffic).  All 64 lanes must be active.
+__device__ __forceinline__ int row_min(int v) {
+    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false));   // quad_perm 1,0,3,2
+    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xF, 0xF, false));   // quad_perm 2,3,0,1
+    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x141, 0xF, 0xF, false));  // row_half_mirror
+    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x140, 0xF, 0xF, false));  // row_mirror
     return v;
+}
+__device__ __forceinline__ int row_max(int v) {
+    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false));
+    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xF, 0xF, false));
+    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x141, 0xF, 0xF, false));
+    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x140, 0xF, 0xF, false));
+    return v;
+}
+__device__ __forceinline__ int wave_min(int v) {
+    v = row_min(v);
+    return min(min(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
+               min(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
 }
 __device__ __forceinline__ int wave_max(int v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
-    return v;
+    v = row_max(v);
+    return max(max(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
+               max(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
 }
-
 __device__ __forceinline__ uint32_t wave_min_u(uint32_t v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, o));
-    return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+    // order-preserving map of uint32 onto int32
+    return (uint32_t)wave_min((int)(v ^ 0x80000000u)) ^ 0x80000000u;
 }
 
 __device__ __forceinline__ unsigned long long bcast_u64(unsigned long long v, uint32_t src) {
@@ -95,6 +110,11 @@ __device__ __forceinline__ int32_t alu(uint32_t base, int32_t x, int32_t y, bool
 struct Shared {
     int32_t *sh;        // simulated shared memory
     uint64_t *stage;    // this wave's record staging area
+    uint64_t *stage_all;// all waves' staging areas (contiguous, nwaves * stage records)
+    uint64_t *alt;      // second buffer of the same size (epoch-local sort)
+    uint32_t *wc;       // nwaves x 256 digit counters (epoch-local sort)
+    uint32_t *tmp;      // 256 words
+    unsigned long long *shadow;   // per simulated shared word: access tuple of the current epoch
     uint32_t *slots;    // 16 waves x 8 words: episode reductions
     uint32_t *slots2;   // 16 x 4: divergence second round
 };
@@ -154,6 +174,7 @@ __device__ __forceinline__ void flush_stage(const InterpArgs &A, uint64_t *stage
 struct LogState {
     uint32_t cur;       // staged records (wave-uniform)
     uint32_t total;     // records of this wave for the block
+    bool spilled;       // this wave flushed records of the current epoch to HBM
 };
 
 __device__ __forceinline__ void log_rec(const InterpArgs &A, uint64_t *stage, LogState &L, bool rec,
@@ -164,6 +185,7 @@ __device__ __forceinline__ void log_rec(const InterpArgs &A, uint64_t *stage, Lo
     if (L.cur + cnt > A.stage) {
         flush_stage(A, stage, L.cur);
         L.cur = 0;
+        L.spilled = true;
     }
     if (rec) stage[L.cur + lane_prefix(m)] = key;
     L.cur += cnt;
@@ -182,13 +204,219 @@ struct Lane {
     regfile_t r;
 };
 
+// ---- epoch-local conflict check -------------------------------------------
+// At a barrier episode every record of the closing epoch is still in the
+// waves' LDS staging areas unless one of them overflowed.  The block then sorts
+// them in LDS by (space, address) -- block and epoch are fixed -- and reduces
+// each location: an intra-block race is emitted at once, and for a global
+// location only two representative records (the smallest tid, the smallest
+// writer) go to the HBM log for the cross-block check, tagged with the reserved
+// epoch value so the global pass does not check them again within the block.
+// If a wave overflowed, all records of the epoch go to the log unreduced.
+
+// Shadow tuple of a shared word for the current epoch (Section 3.1 keeps a
+// tuple per shared location, cleared at __syncthreads()): the smallest writer
+// tid and the two smallest distinct tids that accessed it, 16 bits each.
+constexpr unsigned long long SHADOW_EMPTY = 0xFFFFFFFFFFFFull;
+constexpr uint32_t SH_NONE = 0xFFFFu;
+
+__device__ __forceinline__ unsigned long long shadow_add(unsigned long long s, uint32_t tid, bool write) {
+    uint32_t t1 = (uint32_t)(s & 0xFFFF), t2 = (uint32_t)((s >> 16) & 0xFFFF), w = (uint32_t)((s >> 32) & 0xFFFF);
+    if (tid < t1) { t2 = t1; t1 = tid; }
+    else if (tid != t1 && tid < t2) t2 = tid;
+    if (write && tid < w) w = tid;
+    return (unsigned long long)t1 | ((unsigned long long)t2 << 16) | ((unsigned long long)w << 32);
+}
+
+__device__ __forceinline__ void shadow_update(unsigned long long *sh, uint32_t addr, uint32_t tid, bool write) {
+    unsigned long long old = sh[addr];
+    for (;;) {
+        const unsigned long long nw = shadow_add(old, tid, write);
+        if (nw == old) return;
+        const unsigned long long prev = atomicCAS(&sh[addr], old, nw);
+        if (prev == old) return;
+        old = prev;
+    }
+}
+
+__device__ __forceinline__ uint32_t local_key(uint64_t r, const KeyPlan &k) {
+    return (rec_field(r, k.s_sp, 1) << k.ab) | rec_field(r, k.s_addr, k.ab);
+}
+
+// One stable counting-sort pass over src[0..n) into dst by 8-bit digit.
+__device__ __forceinline__ void local_sort_pass(const Shared &S, const BlockCtx &B, const KeyPlan &k,
+                                                const uint64_t *src, uint64_t *dst, uint32_t n, uint32_t shift) {
+    const uint32_t lane = lane_id();
+    const uint32_t per = (n + B.nwaves - 1) / B.nwaves;
+    const uint32_t c0 = min(n, B.wave * per), c1 = min(n, c0 + per);
+    uint32_t *wc = S.wc + 256 * B.wave;
+    for (uint32_t d = lane; d < 256; d += WAVE) wc[d] = 0;
+    const uint64_t lt = (1ull << lane) - 1ull;
+    for (uint32_t base = c0; base < c1; base += WAVE) {
+        const bool valid = base + lane < c1;
+        const uint32_t d = valid ? (local_key(src[base + lane], k) >> shift) & 0xFFu : 0u;
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (uint32_t b = 0; b < 8; b++) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t bb = __ballot(valid && bit);
+            peers &= bit ? bb : ~bb;
+        }
+        if (valid && lane == (uint32_t)__ffsll((long long)peers) - 1) wc[d] += (uint32_t)__popcll(peers);
+    }
+    __syncthreads();
+    if (B.wave == 0) {      // exclusive offsets per (digit, wave): digit-major, wave-minor
+        uint32_t sum = 0;
+        for (uint32_t w = 0; w < B.nwaves; w++) {
+            const uint32_t *row = S.wc + 256 * w + lane * 4;
+            sum += row[0] + row[1] + row[2] + row[3];
+        }
+        uint32_t incl = sum;
+#pragma unroll
+        for (int o = 1; o < WAVE; o <<= 1) {
+            const uint32_t y = __shfl_up(incl, o);
+            if ((int)lane >= o) incl += y;
+        }
+        uint32_t run = incl - sum;
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            for (uint32_t w = 0; w < B.nwaves; w++) {
+                const uint32_t x = S.wc[256 * w + lane * 4 + q];
+                S.wc[256 * w + lane * 4 + q] = run;
+                run += x;
+            }
+        }
+    }
+    __syncthreads();
+    for (uint32_t base = c0; base < c1; base += WAVE) {
+        const bool valid = base + lane < c1;
+        const uint64_t key = valid ? src[base + lane] : 0ull;
+        const uint32_t d = valid ? (local_key(key, k) >> shift) & 0xFFu : 0u;
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (uint32_t b = 0; b < 8; b++) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t bb = __ballot(valid && bit);
+            peers &= bit ? bb : ~bb;
+        }
+        const uint32_t leader = valid ? (uint32_t)__ffsll((long long)peers) - 1 : 0u;
+        uint32_t old = 0;
+        if (valid && lane == leader) {
+            old = wc[d];
+            wc[d] = old + (uint32_t)__popcll(peers);
+        }
+        old = __shfl(old, (int)leader);
+        if (valid) dst[old + (uint32_t)__popcll(peers & lt)] = key;
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ void push_local_race(const InterpArgs &A, const BlockCtx &B, uint32_t space, uint32_t epoch,
+                                                uint32_t addr, uint32_t w, uint32_t o) {
+    const uint32_t idx = atomicAdd(A.lrace_count, 1u);
+    if (idx < A.lrace_cap) {
+        DevRace r;
+        r.unit = B.unit; r.space = space; r.scope = 0; r.block = B.block; r.epoch = epoch; r.addr = addr;
+        r.w = w; r.o = o;
+        A.lraces[idx] = r;
+    } else {
+        atomicOr(A.flags, FLAG_RACE_OVERFLOW);
+    }
+    A.blk_flags[B.u->block_base + B.block] = 1u;
+}
+
+// Wave-aggregated append of one record per lane with `has` set.
+__device__ __forceinline__ void append_log(const InterpArgs &A, bool has, uint64_t rec) {
+    const uint64_t m = __ballot(has);
+    if (m == 0) return;
+    const uint32_t leader = (uint32_t)__ffsll((long long)m) - 1;
+    unsigned long long base = 0;
+    if (lane_id() == leader) base = atomicAdd(A.log_count, (unsigned long long)__popcll(m));
+    base = bcast_u64(base, leader);
+    if (has) {
+        const unsigned long long p = base + lane_prefix(m);
+        if (p < A.log_cap) A.log[p] = rec;
+        else atomicOr(A.flags, FLAG_LOG_OVERFLOW);
+    }
+}
+
+__device__ __forceinline__ void epoch_local_check(const InterpArgs &A, const BlockCtx &B, const Shared &S,
+                                                  LogState &L, uint32_t epoch) {
+    const KeyPlan &k = A.kp;
+    if (lane_id() == 0) {
+        S.slots[8 * B.wave + 6] = L.cur;
+        S.slots[8 * B.wave + 7] = L.spilled ? 1u : 0u;
+    }
+    __syncthreads();
+    uint32_t n = 0, off = 0, spilled = 0;
+    for (uint32_t w = 0; w < B.nwaves; w++) {
+        const uint32_t c = S.slots[8 * w + 6];
+        if (w < B.wave) off += c;
+        n += c;
+        spilled |= S.slots[8 * w + 7];
+    }
+    // shared memory: reduce and clear the shadow tuples of this epoch
+    for (uint32_t a = threadIdx.x; a < B.sh_words; a += blockDim.x) {
+        const unsigned long long sv = S.shadow[a];
+        if (sv == SHADOW_EMPTY) continue;
+        const uint32_t t1 = (uint32_t)(sv & 0xFFFF), t2 = (uint32_t)((sv >> 16) & 0xFFFF),
+                       w = (uint32_t)((sv >> 32) & 0xFFFF);
+        if (w != SH_NONE && t2 != SH_NONE) push_local_race(A, B, 0u, epoch, a, w, t1 == w ? t2 : t1);
+        S.shadow[a] = SHADOW_EMPTY;
+    }
+    // global memory: the staged records of the epoch
+    if (spilled) {              // the epoch's records go to the global check unreduced
+        flush_stage(A, S.stage, L.cur);
+    } else if (n) {
+        for (uint32_t i = lane_id(); i < L.cur; i += WAVE) S.alt[off + i] = S.stage[i];
+        __syncthreads();
+        uint64_t *src = S.alt, *dst = S.stage_all;
+        for (uint32_t shift = 0; shift < 1 + k.ab; shift += 8) {
+            local_sort_pass(S, B, k, src, dst, n, shift);
+            uint64_t *t = src; src = dst; dst = t;
+        }
+        const uint64_t ep_mask = ((1ull << k.eb) - 1ull) << k.s_ep;
+        const uint64_t rep_ep = (uint64_t)k.ep_rep << k.s_ep;
+        for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+            const uint64_t r = src[i];
+            const uint32_t lk = local_key(r, k);
+            const bool head = i == 0 || local_key(src[i - 1], k) != lk;
+            uint32_t minw = NONE_U32, t1 = NONE_U32, t2 = NONE_U32, i1 = i, iw = i;
+            bool w1 = false;
+            if (head) {
+                for (uint32_t j = i; j < n; j++) {
+                    const uint64_t x = src[j];
+                    if (local_key(x, k) != lk) break;
+                    const uint32_t tid = rec_field(x, k.s_tid, k.tb);
+                    const bool wr = (x & 1ull) != 0;
+                    if (wr && tid < minw) { minw = tid; iw = j; }
+                    if (tid < t1) { t2 = t1; t1 = tid; i1 = j; w1 = wr; }
+                    else if (tid != t1 && tid < t2) t2 = tid;
+                    else if (tid == t1 && wr) { w1 = true; i1 = j; }
+                }
+                if (minw != NONE_U32 && t2 != NONE_U32)
+                    push_local_race(A, B, rec_field(r, k.s_sp, 1), epoch, rec_field(r, k.s_addr, k.ab), minw,
+                                    t1 == minw ? t2 : t1);
+            }
+            const bool glob = head && rec_field(r, k.s_sp, 1) == 1u;
+            append_log(A, glob, (src[i1] & ~ep_mask) | rep_ep);
+            append_log(A, glob && minw != NONE_U32 && !(w1 && t1 == minw), (src[iw] & ~ep_mask) | rep_ep);
+        }
+    }
+    __syncthreads();            // the staging areas are free again
+    L.cur = 0;
+    L.spilled = false;
+}
+
 // Result of the episode logic, uniform over the workgroup.
 enum : int { EP_RELEASED = 0, EP_DONE = 1 };
 
 // All waves are quiescent (no running lane).  Count arrivals and decide.
+template <bool LOCAL>
 __device__ __forceinline__ int barrier_episode(const InterpArgs &A, BlockCtx &B, const Shared &S, Lane &t,
-                               uint32_t &epoch) {
+                               LogState &L, uint32_t &epoch) {
     __syncthreads();
+    if (LOCAL) epoch_local_check(A, B, S, L, epoch);
     bool is_thread = t.st != ST_DEAD;
     uint64_t wm = __ballot(t.st == ST_WAIT);
     uint64_t em = __ballot(t.st == ST_EXIT);
@@ -287,30 +515,14 @@ struct Pending {
     int32_t val;
 };
 
-// Every instruction writes at most one register.  The cases only produce the
-// value; a single indexed write after the dispatch keeps the register file in
-// place (one write site avoids copies of the whole 16-register vector).
-struct RegWrite {
-    bool writes;    // wave-uniform: the opcode writes register d
-    bool on;
-    int32_t v;
-};
-__device__ __forceinline__ void wr(RegWrite &W, bool active, int32_t v) {
-    W.writes = true;
-    W.on = active;
-    W.v = v;
-}
 
 // Execute the instruction at pc `cur` (wave-uniform) for the lanes in `active`.
-// ctl: 0 falls through, 1 JMP, 2 conditional branch (cond per lane), 3 BAR/EXIT.
-template <bool LOCKSTEP>
+// ctl (wave-uniform, from the opcode alone): 0 falls through, 1 JMP,
+// 2 conditional branch (cond per lane), 3 BAR/EXIT; target is the branch target.
+template <bool LOCKSTEP, bool LOCAL>
 __device__ __forceinline__ void exec_one(const InterpArgs &A, const BlockCtx &B, const Shared &S, Lane &t,
                                          LogState &L, Pending &P, uint32_t epoch, int cur, bool active,
                                          int &ctl, int &target, bool &cond) {
-    ctl = 0;
-    target = cur + 1;
-    cond = false;
-    RegWrite W{false, false, 0};
     const uint64_t w = B.prog[(uint32_t)uni(cur)];
     const uint32_t op = uniu((uint32_t)w & 0xFFu);
     const uint32_t d = uniu((uint32_t)(w >> 8) & 0xFFu);
@@ -318,101 +530,78 @@ __device__ __forceinline__ void exec_one(const InterpArgs &A, const BlockCtx &B,
     const uint32_t rb = uniu((uint32_t)(w >> 24) & 0xFFu);
     const int32_t imm = uni((int32_t)(uint32_t)(w >> 32));
     const uint32_t base = op & ~uint32_t(OP_IMM);
-    if (base >= OP_ADD && base <= OP_SLTU) {
+    const uint32_t cls = op >> 4;
+    ctl = 0;
+    target = cur + 1;
+    cond = false;
+    if (cls == 6) {                                   // control
+        if (op == OP_JMP) {
+            ctl = 1;
+            target = imm;
+        } else if (op == OP_BZ || op == OP_BNZ) {
+            ctl = 2;
+            target = imm;
+            const int32_t x = t.r[ra];
+            cond = (op == OP_BZ) ? (x == 0) : (x != 0);
+        } else {
+            ctl = 3;
+            if (op == OP_BAR) {
+                if (active) { t.st = ST_WAIT; t.bar_pc = cur; }
+            } else if (active) {
+                t.st = ST_EXIT;
+            }
+        }
+        return;
+    }
+    int32_t v = 0;
+    bool writes = true;
+    if (base >= OP_ADD && base <= OP_SLTU) {         // int32 ALU
         bool arith = false;
         const int32_t x = t.r[ra];
         int32_t y;
         if (op & OP_IMM) y = imm;
         else y = t.r[rb];
-        const int32_t v = alu(base, x, y, arith);
+        v = alu(base, x, y, arith);
         if (base == OP_DIV || base == OP_REM)
             emit_fault(active && arith, A, B, F_ARITH, epoch, 0, B.tid, (uint32_t)cur, 0);
-        wr(W, active, v);
-    } else {
-    const KeyPlan &k = A.kp;
-    switch (op) {
-    case OP_MOV:
-        wr(W, active, t.r[ra]);
-        break;
-    case OP_MOVI:
-        wr(W, active, imm);
-        break;
-    case OP_SREG:
-        wr(W, active, special(B, (uint32_t)imm));
-        break;
-    case OP_LDS: {
+    } else if (cls == 5) {                            // memory
+        const KeyPlan &k = A.kp;
         const int32_t addr = (int32_t)((uint32_t)t.r[ra] + (uint32_t)imm);
-        const bool inb = active && (uint32_t)addr < B.sh_words;
-        int32_t v = 0;
-        if (inb) v = S.sh[addr];
-        wr(W, active, v);
-        log_rec(A, S.stage, L, inb, B.kep | ((uint64_t)0u << k.s_sp) | 0ull | ((uint64_t)(uint32_t)addr << k.s_addr));
-        emit_fault(active && !inb, A, B, F_OOB, epoch, 0u, B.tid, (uint32_t)addr, 0);
-        break;
-    }
-    case OP_LDG: {
-        const int32_t addr = (int32_t)((uint32_t)t.r[ra] + (uint32_t)imm);
-        const bool inb = active && (uint32_t)addr < B.n_words;
-        int32_t v = 0;
-        if (inb) v = B.mem[addr];
-        wr(W, active, v);
-        log_rec(A, S.stage, L, inb, B.kep | ((uint64_t)1u << k.s_sp) | 0ull | ((uint64_t)(uint32_t)addr << k.s_addr));
-        emit_fault(active && !inb, A, B, F_OOB, epoch, 2u, B.tid, (uint32_t)addr, 0);
-        break;
-    }
-    case OP_STS: {
-        const int32_t addr = (int32_t)((uint32_t)t.r[ra] + (uint32_t)imm);
-        const bool inb = active && (uint32_t)addr < B.sh_words;
-        const int32_t v = t.r[rb];
-        if (LOCKSTEP) {
-            if (inb) { P.on = true; P.shared = true; P.addr = addr; P.val = v; }
-        } else if (inb) {
-            S.sh[addr] = v;
+        const bool is_sh = (op & 2u) == 0;            // LDS 0x50, STS 0x51, LDG 0x52, STG 0x53
+        const bool is_st = (op & 1u) != 0;
+        const bool inb = active && (uint32_t)addr < (is_sh ? B.sh_words : B.n_words);
+        if (!is_st) {
+            if (inb) v = is_sh ? S.sh[addr] : B.mem[addr];
+        } else {
+            writes = false;
+            const int32_t val = t.r[rb];
+            if (LOCKSTEP) {
+                if (inb) { P.on = true; P.shared = is_sh; P.addr = addr; P.val = val; }
+            } else if (inb) {
+                if (is_sh) S.sh[addr] = val;
+                else B.mem[addr] = val;
+            }
         }
-        log_rec(A, S.stage, L, inb, B.kep | ((uint64_t)0u << k.s_sp) | 1ull | ((uint64_t)(uint32_t)addr << k.s_addr));
-        emit_fault(active && !inb, A, B, F_OOB, epoch, 1u, B.tid, (uint32_t)addr, 0);
-        break;
-    }
-    case OP_STG: {
-        const int32_t addr = (int32_t)((uint32_t)t.r[ra] + (uint32_t)imm);
-        const bool inb = active && (uint32_t)addr < B.n_words;
-        const int32_t v = t.r[rb];
-        if (LOCKSTEP) {
-            if (inb) { P.on = true; P.shared = false; P.addr = addr; P.val = v; }
-        } else if (inb) {
-            B.mem[addr] = v;
+        const uint32_t space = is_sh ? 0u : 1u;
+        if (LOCAL && is_sh) {       // shared accesses update the shadow tuple instead of the log
+            if (inb) shadow_update(S.shadow, (uint32_t)addr, B.tid, is_st);
+            L.total += (uint32_t)__popcll(__ballot(inb));
+        } else {
+            log_rec(A, S.stage, L, inb,
+                    B.kep | ((uint64_t)space << k.s_sp) | (uint64_t)(is_st ? 1u : 0u) |
+                        ((uint64_t)(uint32_t)addr << k.s_addr));
         }
-        log_rec(A, S.stage, L, inb, B.kep | ((uint64_t)1u << k.s_sp) | 1ull | ((uint64_t)(uint32_t)addr << k.s_addr));
-        emit_fault(active && !inb, A, B, F_OOB, epoch, 3u, B.tid, (uint32_t)addr, 0);
-        break;
+        emit_fault(active && !inb, A, B, F_OOB, epoch, space * 2u + (is_st ? 1u : 0u), B.tid, (uint32_t)addr, 0);
+    } else if (op == OP_MOV) {
+        v = t.r[ra];
+    } else if (op == OP_MOVI) {
+        v = imm;
+    } else {                                          // OP_SREG
+        v = special(B, (uint32_t)imm);
     }
-    case OP_JMP:
-        ctl = 1;
-        target = imm;
-        break;
-    case OP_BZ:
-    case OP_BNZ: {
-        const int32_t x = t.r[ra];
-        cond = (op == OP_BZ) ? (x == 0) : (x != 0);
-        ctl = 2;
-        target = imm;
-        break;
-    }
-    case OP_BAR:
-        ctl = 3;
-        if (active) { t.st = ST_WAIT; t.bar_pc = cur; }
-        break;
-    case OP_EXIT:
-        ctl = 3;
-        if (active) t.st = ST_EXIT;
-        break;
-    default:
-        break;   // validated programs contain no other opcode
-    }
-    }
-    if (W.writes) {
+    if (writes) {
         const int32_t old = t.r[d];
-        t.r[d] = W.on ? W.v : old;
+        t.r[d] = active ? v : old;
     }
 }
 
@@ -432,6 +621,8 @@ __device__ __forceinline__ void setup_block(const InterpArgs &A, BlockCtx &B, co
     B.kbase = rec_pack(A.kp, unit, 0u, 0u, block, 0u, B.tid, 0u);
     B.kep = B.kbase;
     for (uint32_t i = threadIdx.x; i < B.sh_words; i += blockDim.x) S.sh[i] = 0;
+    if (A.local)
+        for (uint32_t i = threadIdx.x; i < B.sh_words; i += blockDim.x) S.shadow[i] = SHADOW_EMPTY;
     t.pc = 0;
     t.st = (B.tid < B.nt) ? ST_RUN : ST_DEAD;
     t.fuel = u->fuel;
@@ -449,6 +640,7 @@ __device__ __forceinline__ void finish_block(const InterpArgs &A, const BlockCtx
 }
 
 // ---- free-run block execution ------------------------------------------------
+template <bool LOCAL>
 __device__ __forceinline__ void run_block_free(const InterpArgs &A, BlockCtx &B, const Shared &S, Lane &t, LogState &L) {
     uint32_t epoch = 0;
     Pending P{false, false, 0, 0};
@@ -486,7 +678,7 @@ __device__ __forceinline__ void run_block_free(const InterpArgs &A, BlockCtx &B,
             if (guard) guard--;
             int ctl, target;
             bool cond;
-            exec_one<false>(A, B, S, t, L, P, epoch, cur, active, ctl, target, cond);
+            exec_one<false, LOCAL>(A, B, S, t, L, P, epoch, cur, active, ctl, target, cond);
             if (ctl == 3) continue;                        // BAR/EXIT: lanes left the running set
             if (ctl == 2) {
                 uint64_t actm = __ballot(active);
@@ -507,7 +699,7 @@ __device__ __forceinline__ void run_block_free(const InterpArgs &A, BlockCtx &B,
             }
         }
         // wave quiescent
-        if (barrier_episode(A, B, S, t, epoch) == EP_DONE) break;
+        if (barrier_episode<LOCAL>(A, B, S, t, L, epoch) == EP_DONE) break;
         int lo = wave_min(t.st == ST_RUN ? t.pc : INT_MAX);
         int hi = wave_max(t.st == ST_RUN ? t.pc : -1);
         conv = (lo == hi) || hi < 0;
@@ -544,7 +736,7 @@ __device__ __forceinline__ void run_block_lockstep(const InterpArgs &A, BlockCtx
     bool any_run = true;
     for (;;) {
         if (!any_run) {
-            if (barrier_episode(A, B, S, t, epoch) == EP_DONE) break;
+            if (barrier_episode<false>(A, B, S, t, L, epoch) == EP_DONE) break;
             any_run = true;     // a completed episode releases every thread
         }
         // phase A: every running lane executes exactly one instruction; loads
@@ -569,7 +761,7 @@ __device__ __forceinline__ void run_block_lockstep(const InterpArgs &A, BlockCtx
             if (active) t.fuel--;
             int ctl, target;
             bool cond;
-            exec_one<true>(A, B, S, t, L, P, epoch, cur, active, ctl, target, cond);
+            exec_one<true, false>(A, B, S, t, L, P, epoch, cur, active, ctl, target, cond);
             if (active && ctl != 3) {
                 if (ctl == 2) t.pc = cond ? target : cur + 1;
                 else t.pc = target;
@@ -620,17 +812,39 @@ __device__ __forceinline__ void run_block_lockstep(const InterpArgs &A, BlockCtx
     }
 }
 
-__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6, 6))) k_interp_free(InterpArgs A) {
+// LDS layout: simulated shared memory | staging (nwaves x stage records) |
+// [local check: second buffer of the same size | nwaves x 256 counters |
+// 256 words] | episode slots | [lockstep: store-owner tables].
+__device__ __forceinline__ size_t carve_lds(uint8_t *smem, const InterpArgs &A, Shared &S, uint32_t nwaves,
+                                           uint32_t wave) {
+    S.sh = (int32_t *)smem;
+    size_t off = ((size_t)A.sh_words_max * 4 + 15) & ~(size_t)15;
+    S.stage_all = (uint64_t *)(smem + off);
+    S.stage = S.stage_all + (size_t)wave * A.stage;
+    off += (size_t)nwaves * A.stage * 8;
+    if (A.local) {
+        S.alt = (uint64_t *)(smem + off);
+        off += (size_t)nwaves * A.stage * 8;
+        S.wc = (uint32_t *)(smem + off);
+        off += (size_t)nwaves * 256 * 4;
+        S.tmp = (uint32_t *)(smem + off);
+        off += 256 * 4;
+        S.shadow = (unsigned long long *)(smem + off);
+        off += (size_t)A.sh_words_max * 8;
+    }
+    S.slots = (uint32_t *)(smem + off);
+    S.slots2 = S.slots + 16 * 8;
+    off += (16 * 8 + 16 * 4) * 4;
+    return off;
+}
+
+template <bool LOCAL>
+__device__ __forceinline__ void interp_free_body(const InterpArgs &A) {
     extern __shared__ __align__(16) uint8_t smem[];
     Shared S;
     const uint32_t nwaves = (blockDim.x + WAVE - 1) / WAVE;
     const uint32_t wave = threadIdx.x / WAVE;
-    S.sh = (int32_t *)smem;
-    size_t off = ((size_t)A.sh_words_max * 4 + 15) & ~(size_t)15;
-    S.stage = (uint64_t *)(smem + off) + (size_t)wave * A.stage;
-    off += (size_t)nwaves * A.stage * 8;
-    S.slots = (uint32_t *)(smem + off);
-    S.slots2 = S.slots + 16 * 8;
+    carve_lds(smem, A, S, nwaves, wave);
 
     uint32_t unit = 0, block = blockIdx.x;
     if (A.items) {
@@ -642,25 +856,29 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6, 6)
     B.nwaves = nwaves;
     B.wave = wave;
     Lane t;
-    LogState L{0, 0};
+    LogState L{0, 0, false};
     setup_block(A, B, S, t, unit, block);
-    run_block_free(A, B, S, t, L);
+    run_block_free<LOCAL>(A, B, S, t, L);
     finish_block(A, B, S, L);
 }
 
-__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6, 6))) k_interp_lockstep(InterpArgs A) {
+
+// Free-run kernels: with the epoch-local check (shadow tuples and local sort)
+// and without it; occupancy targets keep them free of register spills.
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(5, 5))) k_interp_free_local(InterpArgs A) {
+    interp_free_body<true>(A);
+}
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6, 6))) k_interp_free(InterpArgs A) {
+    interp_free_body<false>(A);
+}
+
+__global__ void __launch_bounds__(1024) k_interp_lockstep(InterpArgs A) {
     extern __shared__ __align__(16) uint8_t smem[];
     Shared S;
     const uint32_t nwaves = (blockDim.x + WAVE - 1) / WAVE;
     const uint32_t wave = threadIdx.x / WAVE;
-    S.sh = (int32_t *)smem;
-    size_t off = ((size_t)A.sh_words_max * 4 + 15) & ~(size_t)15;
-    S.stage = (uint64_t *)(smem + off) + (size_t)wave * A.stage;
-    off += (size_t)nwaves * A.stage * 8;
-    S.slots = (uint32_t *)(smem + off);
-    S.slots2 = S.slots + 16 * 8;
+    size_t off = carve_lds(smem, A, S, nwaves, wave);
 
-    off += (16 * 8 + 16 * 4) * 4;
     StoreTables T;
     T.own_sh = (uint32_t *)(smem + off);
     off += (size_t)A.sh_words_max * 4;
@@ -677,7 +895,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6, 6)
     B.nwaves = nwaves;
     B.wave = wave;
     Lane t;
-    LogState L{0, 0};
+    LogState L{0, 0, false};
     for (uint32_t c = c0; c < c1; c++) {
         uint2 it = A.comp_blocks[c];
         setup_block(A, B, S, t, uniu(it.x), uniu(it.y));
@@ -688,10 +906,11 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6, 6)
 
 }  // namespace
 
-size_t interp_lds_bytes(uint32_t sh_words_max, uint32_t wg_threads, uint32_t stage, bool lockstep) {
+size_t interp_lds_bytes(uint32_t sh_words_max, uint32_t wg_threads, uint32_t stage, bool lockstep, bool local) {
     const uint32_t nwaves = (wg_threads + WAVE - 1) / WAVE;
     size_t off = ((size_t)sh_words_max * 4 + 15) & ~(size_t)15;
     off += (size_t)nwaves * stage * 8;
+    if (local) off += (size_t)nwaves * stage * 8 + (size_t)nwaves * 256 * 4 + 256 * 4 + (size_t)sh_words_max * 8;
     off += (16 * 8 + 16 * 4) * 4;
     if (lockstep) off += (size_t)sh_words_max * 4 + ((size_t)8 << lockstep_hash_bits(wg_threads));
     return off;
@@ -700,16 +919,24 @@ size_t interp_lds_bytes(uint32_t sh_words_max, uint32_t wg_threads, uint32_t sta
 hipError_t launch_interp(const InterpArgs &a, uint32_t n_wg, uint32_t wg_threads, bool lockstep, hipStream_t s) {
     if (n_wg == 0) return hipSuccess;
     InterpArgs args = a;
-    size_t lds = interp_lds_bytes(args.sh_words_max, wg_threads, args.stage, lockstep);
+    if (lockstep) args.local = 0;
+    size_t lds = interp_lds_bytes(args.sh_words_max, wg_threads, args.stage, lockstep, args.local != 0);
     while (lds > 160 * 1024 && args.stage > 64) {   // shrink the record staging area to fit
-        args.stage /= 2;
-        lds = interp_lds_bytes(args.sh_words_max, wg_threads, args.stage, lockstep);
+        args.stage = (args.stage / 2 + 63) / 64 * 64;
+        lds = interp_lds_bytes(args.sh_words_max, wg_threads, args.stage, lockstep, args.local != 0);
+    }
+    if (lds > 160 * 1024 && args.local) {             // no room for the epoch-local check: log everything
+        args.local = 0;
+        lds = interp_lds_bytes(args.sh_words_max, wg_threads, args.stage, lockstep, false);
     }
     if (lds > 160 * 1024) return hipErrorInvalidValue;
     static bool attr_set = false;
     if (!attr_set) {
-        hipError_t e1 = hipFuncSetAttribute((const void *)k_interp_free, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                            160 * 1024);
+        hipError_t e1 = hipFuncSetAttribute((const void *)k_interp_free,
+                                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        hipError_t e0 = hipFuncSetAttribute((const void *)k_interp_free_local,
+                                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e0 != hipSuccess) return e0;
         hipError_t e2 = hipFuncSetAttribute((const void *)k_interp_lockstep,
                                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e1 != hipSuccess) return e1;
@@ -718,6 +945,8 @@ hipError_t launch_interp(const InterpArgs &a, uint32_t n_wg, uint32_t wg_threads
     }
     if (lockstep)
         hipLaunchKernelGGL(k_interp_lockstep, dim3(n_wg), dim3(wg_threads), lds, s, args);
+    else if (args.local)
+        hipLaunchKernelGGL(k_interp_free_local, dim3(n_wg), dim3(wg_threads), lds, s, args);
     else
         hipLaunchKernelGGL(k_interp_free, dim3(n_wg), dim3(wg_threads), lds, s, args);
     return hipGetLastError();

@@ -103,9 +103,9 @@ struct DBuf {
 struct Workspace {
     DBuf units, items, comp_off, comp_blocks, mask;
     DBuf snap, log, alt, rlog, ralt, fs, hist, part;
-    DBuf faults, rfaults, races, edges, blk_recs, rblk_recs, blk_flags, rflags, ctr, rctr;
+    DBuf faults, rfaults, races, lraces, edges, blk_recs, rblk_recs, blk_flags, rflags, ctr, rctr;
     DevCounters *h_ctr = nullptr;   // pinned
-    hipEvent_t ev[8] = {};
+    hipEvent_t ev[12] = {};
     bool init = false;
     void setup() {
         if (init) return;
@@ -116,7 +116,7 @@ struct Workspace {
     size_t device_bytes() const {
         const DBuf *all[] = {&units, &items, &comp_off, &comp_blocks, &mask, &snap, &log, &alt, &rlog,
                              &ralt, &fs, &hist, &part, &faults, &rfaults, &races, &edges, &blk_recs,
-                             &rblk_recs, &blk_flags, &rflags, &ctr, &rctr};
+                             &rblk_recs, &blk_flags, &rflags, &ctr, &rctr, &lraces};
         size_t s = 0;
         for (auto *b : all) s += b->bytes;
         return s;
@@ -124,7 +124,7 @@ struct Workspace {
     ~Workspace() {
         DBuf *all[] = {&units, &items, &comp_off, &comp_blocks, &mask, &snap, &log, &alt, &rlog,
                        &ralt, &fs, &hist, &part, &faults, &rfaults, &races, &edges, &blk_recs,
-                       &rblk_recs, &blk_flags, &rflags, &ctr, &rctr};
+                       &rblk_recs, &blk_flags, &rflags, &ctr, &rctr, &lraces};
         for (auto *b : all) b->release();
         if (h_ctr) (void)hipHostFree(h_ctr);
         for (auto &e : ev)
@@ -152,7 +152,9 @@ struct Options {
     int timing = 0;
     uint32_t sort_tile = 4096;
     uint64_t log_records = 1ull << 22;
-    uint32_t stage = 256;
+    uint32_t stage = 256;           // staged records per wave in the lockstep replay
+    uint32_t stage_bytes = 16384;   // LDS for staging + local sort per workgroup (free run)
+    int local = 1;                  // epoch-local check in LDS
 };
 
 }  // namespace
@@ -182,6 +184,14 @@ struct kc_ctx {
     void release(std::unique_ptr<Workspace> w) {
         std::lock_guard<std::mutex> g(mu);
         free_ws.push_back(std::move(w));
+    }
+    uint64_t log_hint() {
+        std::lock_guard<std::mutex> g(mu);
+        return opt.log_records;
+    }
+    void note_log_records(uint64_t n) {
+        std::lock_guard<std::mutex> g(mu);
+        opt.log_records = std::max(opt.log_records, n);
     }
     void stat_add(const char *k, double v) {
         std::lock_guard<std::mutex> g(mu);
@@ -316,6 +326,7 @@ struct Stage {
     uint64_t total_words = 0;
     uint32_t max_words = 0;
     uint32_t used_epoch_bits = 0;
+    uint32_t lrace_cap = 4096;
 
     // Sort order for the check: bits from the block field up, then the used
     // epoch bits; the full order for multiset comparison adds tid and kind.
@@ -376,7 +387,16 @@ struct Stage {
         kp.s_sp = kp.s_addr + kp.ab;
         kp.s_unit = kp.s_sp + 1;
         kp.total = kp.s_unit + kp.ub;
-        kp.max_epoch = (uint32_t)((1ull << kp.eb) - 1);
+        kp.ep_rep = (uint32_t)((1ull << kp.eb) - 1);
+        kp.max_epoch = kp.ep_rep - 1;
+    }
+
+    // Records staged per wave: the LDS budget split over the workgroup's waves
+    // (staging + the epoch-local sort's second buffer), a multiple of 64.
+    uint32_t stage_for(uint32_t wg_threads) const {
+        const uint32_t nw = (wg_threads + 63) / 64;
+        uint32_t st = (uint32_t)(ctx->opt.stage_bytes / (nw * 16u)) / 64u * 64u;
+        return std::max<uint32_t>(64u, std::min<uint32_t>(st, 2048u));
     }
 
     void upload_units() {
@@ -405,7 +425,13 @@ struct Stage {
         a.flags = &ctr.as<DevCounters>()->flags;
         a.max_epoch = &ctr.as<DevCounters>()->max_epoch;
         a.stage = ctx->opt.stage;
+        a.local = (!lockstep && ctx->opt.check && ctx->opt.local) ? 1u : 0u;
+        a.lraces = ws.lraces.as<DevRace>();
+        a.lrace_cap = lrace_cap;
+        a.lrace_count = &ctr.as<DevCounters>()->race_count;
+        a.blk_flags = ws.blk_flags.as<uint32_t>();
         if (lockstep) {
+            a.stage = ctx->opt.stage;
             uint32_t wg = 64, shmax = 0;
             for (auto &u : hu) {
                 wg = std::max<uint32_t>(wg, (u.nt + 63) / 64 * 64);
@@ -423,6 +449,7 @@ struct Stage {
         if (hu.size() == 1) {
             a.items = nullptr;
             a.sh_words_max = hu[0].sh_words;
+            a.stage = stage_for((hu[0].nt + 63) / 64 * 64);
             HIPCHK(launch_interp(a, hu[0].nb, (hu[0].nt + 63) / 64 * 64, false, s));
             return;
         }
@@ -443,6 +470,7 @@ struct Stage {
             for (uint32_t ui : kv.second) shmax = std::max(shmax, hu[ui].sh_words);
             a.items = ws.items.as<uint2>() + ranges[ci].first;
             a.sh_words_max = shmax;
+            a.stage = stage_for(kv.first);
             HIPCHK(launch_interp(a, (uint32_t)(ranges[ci].second - ranges[ci].first), kv.first, false, s));
             ci++;
         }
@@ -469,7 +497,7 @@ struct Stage {
         upload_units();
         if (check) HIPCHK(launch_copy_units(ws.units.as<DevUnit>(), n, max_words, true, nullptr, s));
 
-        uint64_t log_cap = check ? std::max<uint64_t>(ctx->opt.log_records, 1024) : 0;
+        uint64_t log_cap = check ? std::max<uint64_t>(ctx->log_hint(), 1024) : 0;
         if (check) ws.log.reserve(log_cap * 8);
         uint32_t fault_cap = 4096;
         ws.blk_recs.reserve((size_t)total_blocks * 4);
@@ -477,8 +505,10 @@ struct Stage {
         DevCounters c{};
         for (;;) {
             ws.faults.reserve((size_t)fault_cap * sizeof(DevFault));
+            ws.lraces.reserve((size_t)lrace_cap * sizeof(DevRace));
             reset_counters(ws.ctr);
             HIPCHK(launch_zero(ws.blk_recs.p, (size_t)total_blocks * 4, s));
+            HIPCHK(launch_zero(ws.blk_flags.p, (size_t)total_blocks * 4, s));
             tm.mark(0);
             interp(false, ws.log, log_cap, ws.ctr, ws.faults, fault_cap, ws.blk_recs, 0);
             tm.mark(1);
@@ -499,13 +529,17 @@ struct Stage {
                 fault_cap = c.fault_count + c.fault_count / 8 + 1024;
                 again = true;
             }
+            if (c.flags & FLAG_RACE_OVERFLOW) {
+                lrace_cap = c.race_count + c.race_count / 8 + 1024;
+                again = true;
+            }
             if (!again) break;
             if (!check) throw KcError{KC_E_OVERFLOW, "findings overflow with check disabled"};
             HIPCHK(launch_copy_units(ws.units.as<DevUnit>(), n, max_words, false, nullptr, s));   // back to launch start
             ctx->stat_add("retries", 1);
         }
-        if (check) ctx->opt.log_records = std::max<uint64_t>(ctx->opt.log_records, c.log_count + c.log_count / 8);
-        used_epoch_bits = bits_for((uint64_t)c.max_epoch + 1);
+        if (check) ctx->note_log_records(c.log_count + c.log_count / 8);
+        used_epoch_bits = bits_for((uint64_t)c.max_epoch + 2);   // one more value: representative records
 
         blk_recs.resize(total_blocks);
         HIPCHK(hipMemcpyAsync(blk_recs.data(), ws.blk_recs.p, (size_t)total_blocks * 4, hipMemcpyDeviceToHost, s));
@@ -513,8 +547,17 @@ struct Stage {
         if (!faults.empty())
             HIPCHK(hipMemcpyAsync(faults.data(), ws.faults.p, faults.size() * sizeof(DevFault),
                                   hipMemcpyDeviceToHost, s));
+        std::vector<DevRace> lraces(std::min<uint32_t>(c.race_count, lrace_cap));
+        if (!lraces.empty())
+            HIPCHK(hipMemcpyAsync(lraces.data(), ws.lraces.p, lraces.size() * sizeof(DevRace),
+                                  hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
-        ctx->stat_add("records", (double)c.log_count);
+        {
+            uint64_t total = 0;
+            for (uint32_t v : blk_recs) total += v;
+            ctx->stat_add("records", (double)total);
+            ctx->stat_add("log_entries", (double)c.log_count);
+        }
 
         std::vector<DevRace> races;
         std::vector<DevEdge> edges;
@@ -524,7 +567,7 @@ struct Stage {
             tm.mark(2);
             sorted = sort_check(ws.log, ws.alt, nrec);
             tm.mark(3);
-            run_check(sorted, nrec, ws.blk_flags, races, edges);
+            run_check(sorted, nrec, ws.blk_flags, races, edges, false);
             tm.mark(4);
             ctx->stat_add("sort_ms", tm.ms(2, 3));
             ctx->stat_add("check_ms", tm.ms(3, 4));
@@ -534,6 +577,7 @@ struct Stage {
         // per-unit findings of the free run
         std::vector<std::vector<kc_fault>> ufaults(n);
         for (auto &f : faults) ufaults[f.unit].push_back(kc_fault{0, f.kind, f.block, f.epoch, f.a, f.b, f.c, f.d});
+        races.insert(races.end(), lraces.begin(), lraces.end());
         std::vector<std::vector<kc_race>> uraces(n);
         for (auto &r : races)
             uraces[r.unit].push_back(kc_race{0, r.space, r.scope, r.block, r.epoch, r.addr, r.w, r.o});
@@ -575,14 +619,14 @@ struct Stage {
     // Conflict check over sorted records: races and cross-block links to the
     // host, racy blocks flagged in `flags`.
     void run_check(const uint64_t *sorted, uint64_t n, DBuf &flags, std::vector<DevRace> &races,
-                   std::vector<DevEdge> &edges) {
+                   std::vector<DevEdge> &edges, bool zero_flags = true) {
         uint32_t race_cap = 4096, edge_cap = 4096;
         flags.reserve((size_t)std::max<uint32_t>(total_blocks, 1) * 4);
         for (;;) {
             ws.races.reserve((size_t)race_cap * sizeof(DevRace));
             ws.edges.reserve((size_t)edge_cap * sizeof(DevEdge));
             reset_counters(ws.rctr);
-            HIPCHK(launch_zero(flags.p, (size_t)total_blocks * 4, s));
+            if (zero_flags) HIPCHK(launch_zero(flags.p, (size_t)total_blocks * 4, s));
             CheckArgs ca{};
             ca.keys = sorted;
             ca.n = n;
@@ -680,17 +724,25 @@ struct Stage {
         uint64_t rcap = s_recs + s_recs / 4 + 1024;
         uint32_t fcap = 4096;
         DevCounters rc = lockstep_once(comps, rcap, fcap);
+        tm.mark(7);
+        ctx->stat_add("replay_lockstep_ms", tm.ms(5, 7));
         bool ok = !(rc.flags & (FLAG_LOG_OVERFLOW | FLAG_FAULT_OVERFLOW));
         std::vector<DevRace> rr;
         std::vector<DevEdge> re;
         if (ok) {
-            used_epoch_bits = std::max(used_epoch_bits, bits_for((uint64_t)rc.max_epoch + 1));
+            used_epoch_bits = std::max(used_epoch_bits, bits_for((uint64_t)rc.max_epoch + 2));
             uint64_t *rs = sort_check(ws.rlog, ws.ralt, rc.log_count);
+            tm.mark(8);
             run_check(rs, rc.log_count, ws.rflags, rr, re);
+            tm.mark(9);
+            ctx->stat_add("replay_sort_ms", tm.ms(7, 8));
+            ctx->stat_add("replay_check_ms", tm.ms(8, 9));
             reset_counters(ws.ctr);
             HIPCHK(launch_coverage(rs, rc.log_count, sorted, nrec, kp, ws.units.as<DevUnit>(),
                                    ws.blk_flags.as<uint32_t>(), &ws.ctr.as<DevCounters>()->flags, s));
             ok = !(read_ctr(ws.ctr).flags & FLAG_MISMATCH);
+            tm.mark(10);
+            ctx->stat_add("replay_coverage_ms", tm.ms(9, 10));
             for (auto &e : re)
                 if (comp_of[ub_key(e.unit, e.b0)] != comp_of[ub_key(e.unit, e.b1)]) ok = false;
         }
@@ -758,7 +810,7 @@ struct Stage {
         std::vector<uint32_t> rrecs(total_blocks);
         HIPCHK(hipMemcpyAsync(rrecs.data(), ws.rblk_recs.p, (size_t)total_blocks * 4, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
-        used_epoch_bits = std::max(used_epoch_bits, bits_for((uint64_t)fc.max_epoch + 1));
+        used_epoch_bits = std::max(used_epoch_bits, bits_for((uint64_t)fc.max_epoch + 2));
         uint64_t *rs = sort_check(ws.rlog, ws.ralt, fc.log_count);
         std::vector<DevRace> nr;
         std::vector<DevEdge> ne;
@@ -882,6 +934,8 @@ kc_status kc_ctx_set_option(kc_ctx *ctx, const char *key, int64_t v) {
     else if (k == "sort_tile" && (v == 2048 || v == 4096 || v == 8192)) ctx->opt.sort_tile = (uint32_t)v;
     else if (k == "log_records" && v >= 1024) ctx->opt.log_records = (uint64_t)v;
     else if (k == "stage" && (v == 128 || v == 256 || v == 512 || v == 1024)) ctx->opt.stage = (uint32_t)v;
+    else if (k == "stage_bytes" && v >= 8192 && v <= 98304) ctx->opt.stage_bytes = (uint32_t)v;
+    else if (k == "local" && (v == 0 || v == 1)) ctx->opt.local = (int)v;
     else if (k == "reset" && v == 1) {
         std::lock_guard<std::mutex> g(ctx->mu);
         ctx->stats.clear();

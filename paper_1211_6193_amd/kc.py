@@ -226,6 +226,14 @@ def launch(ctx: Context, prog: Program, grid, block, shmem_bytes: int, mem, para
     return _take_report(ctx.lib, out)
 
 
+@dataclass
+class Prepared:
+    jd: object
+    keep: list
+    n: int
+    mems: list
+
+
 class Batch:
     """Asynchronous batches of jobs (each job = launches in order on one memory)."""
 
@@ -233,9 +241,8 @@ class Batch:
         self.ctx = ctx
         self._keep: Dict[int, tuple] = {}
 
-    def submit(self, jobs: List[Tuple[List[Tuple[Program, tuple, tuple, int, Sequence[int]]], object, int]],
-               stream=None) -> int:
-        """jobs: list of (launches, mem_tensor, tag); launches = [(prog, grid, block, shmem, params), ...]."""
+    def prepare(self, jobs) -> "Prepared":
+        """Marshal jobs into C descriptors once (reusable by several submits)."""
         n = len(jobs)
         jd = (JobDesc * max(n, 1))()
         keep = []
@@ -249,10 +256,16 @@ class Batch:
             jd[i].dev_mem = mem.data_ptr()
             jd[i].n_words = mem.numel()
             jd[i].tag = tag
+        return Prepared(jd, keep, n, [m for _, m, _ in jobs])
+
+    def submit(self, jobs, stream=None) -> int:
+        """jobs: a Prepared batch or a list of (launches, mem_tensor, tag) with
+        launches = [(prog, grid, block, shmem, params), ...]."""
+        prep = jobs if isinstance(jobs, Prepared) else self.prepare(jobs)
         t = C.c_uint64()
-        self.ctx._check(self.ctx.lib.kc_batch_submit(self.ctx.h, jd, n, _stream_handle(stream), C.byref(t)),
-                        "kc_batch_submit")
-        self._keep[t.value] = (jd, keep, n)
+        self.ctx._check(self.ctx.lib.kc_batch_submit(self.ctx.h, prep.jd, prep.n, _stream_handle(stream),
+                                                     C.byref(t)), "kc_batch_submit")
+        self._keep[t.value] = (prep.jd, prep.keep, prep.n, prep.mems)
         return t.value
 
     def poll(self, ticket: int, wait: bool = True) -> Optional[List[Report]]:

@@ -1,0 +1,90 @@
+"""Workload 4 (ping-pong stencil with in-place bugs, 16 launches as one job).
+
+Reduced size (2^18 elements, same block shape and launch count): report and
+final memory equal the oracle's.  Full size (2^26 elements): properties that
+hold at any size -- the record count per launch has a closed form, the race set
+is exactly the two boundary words of every buggy block's range in the array it
+reads, every launch completes and blocks far from a bug compute the stencil."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from gpu_util import assert_same, say
+from oracle import oracle as O
+from paper_1211_6193_amd import kc, workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = kc.Context(0)
+    yield c
+    c.close()
+
+
+def expected_races(job):
+    n, T, steps = job.meta["n"], job.meta["threads"], job.meta["steps"]
+    nb = n // T
+    bugs = set(int(b) for b in job.meta["bug_blocks"])
+    want = []
+    for s in range(steps):
+        for b in sorted(bugs):
+            g0 = b * T
+            if b > 0:        # right-halo loader of block b-1 reads the first word
+                want.append((s, 1, 1, b, 0xFFFFFFFF, g0 + (n if s % 2 else 0), g0, (b - 1) * T + T - 1))
+            if b < nb - 1:   # left-halo loader of block b+1 reads the last word
+                want.append((s, 1, 1, b, 0xFFFFFFFF, g0 + T - 1 + (n if s % 2 else 0), g0 + T - 1, (b + 1) * T))
+    return sorted(want, key=lambda t: t[:6])
+
+
+def records_per_launch(n, T):
+    nb = n // T
+    return 7 * n + 4 * nb - 2
+
+
+def test_workload4_reduced_vs_oracle(ctx):
+    job = W.stencil_pingpong_job(n=1 << 18, threads=256, steps=16, bug_frac=0.004, seed=12116197)
+    assert len(job.meta["bug_blocks"]) >= 3
+    say("workload 4 at 2^18 x 16 launches")
+    rep, mem = kc.run_job(ctx, job)
+    orc = O.run_job(job)
+    assert_same(rep, mem, orc, "workload4-reduced")
+    non_adjacent = all(b2 - b1 > 2 for b1, b2 in zip(job.meta["bug_blocks"][:-1], job.meta["bug_blocks"][1:]))
+    if non_adjacent:
+        assert rep.race_tuples() == expected_races(job)
+
+
+def test_workload4_full_size_properties(ctx):
+    job = W.stencil_pingpong_job()
+    n, T = job.meta["n"], job.meta["threads"]
+    bugs = job.meta["bug_blocks"]
+    assert len(bugs) == 26
+    say("workload 4 full size: 2^26 x 16 launches")
+    rep, mem = kc.run_job(ctx, job)
+    assert rep.launches_completed == 16
+    assert rep.records == 16 * records_per_launch(n, T)
+    assert len(rep.faults) == 0
+    if all(b2 - b1 > 2 for b1, b2 in zip(bugs[:-1], bugs[1:])):
+        assert rep.race_tuples() == expected_races(job)
+    # far from every bug the result is 16 clean stencil steps; checked on windows
+    # padded by more than the 16 elements the stencil can propagate
+    got = mem.cpu().numpy()[:n]          # 16 launches end in the first array
+    x = job.memory[:n].astype(np.int64)
+    rng = np.random.default_rng(0)
+    checked = 0
+    for c in rng.integers(0, n, 40):
+        lo, hi = max(0, int(c) - 64), min(n, int(c) + 64)
+        if any(abs(int(b) * T - int(c)) < 40 * T for b in bugs):
+            continue
+        a2, b2 = max(0, lo - 20), min(n, hi + 20)
+        v = x[a2:b2].copy()
+        for _ in range(16):
+            vp = np.concatenate([[0], v, [0]])
+            v = (vp[:-2] + 2 * vp[1:-1] + vp[2:]) >> 2
+        assert np.array_equal(got[lo:hi], v[lo - a2:hi - a2].astype(np.int32)), (lo, hi)
+        checked += 1
+    assert checked >= 10
