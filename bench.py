@@ -7,12 +7,14 @@ replay of racy blocks, report): shared-memory tree reduction over 2^20 int32
 inputs uniform in [0, 2^16), 4096 blocks x 256 threads, with the barrier after
 a seeded level dropped in 1% of the blocks and a tid-dependent barrier in
 0.1% (seed 12116193 + 2).  The memory is resident on the GPU before timing;
-the last step's report and memory are compared bit for bit with the CPU
-oracle.
+in the CPU-baseline leg the last step's report and memory are compared bit for
+bit with the CPU oracle.
 
 Prints one JSON line: records/s over the timed steps, per-step latency
 percentiles, the dominant kernel's roofline (HIP-event timing inside the
 library on the launch stream) and the oracle's CPU rate on the same workload.
+The oracle is used only in the CPU-baseline leg (its timing and the bit-exact
+comparison of the GPU's results with it).
 """
 import argparse
 import json
@@ -35,6 +37,11 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target CPU time of the oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the workload-3 batched vs plain comparison")
+    ap.add_argument("--no-serve", action="store_true", help="skip the served-form measurement")
+    ap.add_argument("--serve-seconds", type=float, default=3.0, help="arrival window per served rate")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of 1 GiB three times (the known-size kernel that scales "
+                         "HBM counter readings) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the checker's "
@@ -43,6 +50,14 @@ def main():
 
     import numpy as np
     import torch
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": src.numel() * 4, "bytes_written": dst.numel() * 4}))
+        return
     from paper_1211_6193_amd import kc, workloads as W
 
     job = W.tree256_job()
@@ -75,60 +90,19 @@ def main():
     stats = {k: ctx.stat(k) for k in ("interp_ms", "sort_ms", "check_ms", "replay_ms", "replays",
                                       "fallbacks", "retries", "sort_keys", "records", "interp_launches",
                                       "replay_lockstep_ms", "replay_sort_ms", "replay_check_ms",
-                                      "replay_coverage_ms", "log_entries")}
-    # bit-exact check of the final step against the oracle
-    from oracle import oracle as O
-    t_o = time.perf_counter()
-    orc = O.run_job(job, keep_records=True)
-    oracle_s = time.perf_counter() - t_o
-    got = mem.cpu().numpy()
-    exact = (rep.records == orc.records and rep.race_tuples() == orc.race_tuples()
-             and rep.fault_tuples() == orc.fault_tuples() and rep.launches_completed == orc.launches_completed
-             and bool(np.array_equal(got, orc.memory)))
-    if not exact:
-        print("bench: GPU result differs from the oracle", file=sys.stderr)
-
-    # dominant stage and its roofline: the interpreter writes 8 B per record and
-    # moves 4 B of simulated global data per global-space record; the sort moves
-    # 16 B per key per pass (read + write); the check reads 8 B per record.
-    n_global = int(np.count_nonzero(orc.record_log["space"] == 1))
+                                      "replay_coverage_ms", "log_entries", "instructions")}
     per = {k: stats[k] / args.steps for k in ("interp_ms", "sort_ms", "check_ms", "replay_ms")}
-    dom = max(per, key=per.get)
-    if dom == "interp_ms":
-        bytes_launch = 8 * records + 4 * n_global
-        kernel = "k_interp_free"
-    elif dom == "sort_ms":
-        npass = _sort_passes(job)
-        bytes_launch = 16 * records * npass
-        kernel = "k_rs_* (all passes)"
-    elif dom == "check_ms":
-        bytes_launch = 8 * records
-        kernel = "k_check"
-    else:
-        bytes_launch = 16 * records
-        kernel = "replay"
-    dur_s = per[dom] / 1e3
-    achieved = bytes_launch / dur_s / 1e9 if dur_s > 0 else 0.0
-    roofline = {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "avg_ms": round(per[dom], 4), "bytes_per_launch": int(bytes_launch),
-                "stage_ms": {k: round(v, 4) for k, v in per.items()},
-                "replay_detail_ms": {k: round(stats[k] / args.steps, 4) for k in
-                                     ("replay_lockstep_ms", "replay_sort_ms", "replay_check_ms", "replay_coverage_ms")},
-                "log_entries_per_step": stats["log_entries"] / args.steps,
-                "path_algorithmic_frac": round(value * 16 / (HBM_PEAK_GBS * 1e9), 4)}
+    roofline = interp_roofline(stats, args.steps, records, value, per)
 
-    cpu = None
+    batched, sample = (None, []) if args.no_batched else batched_vs_plain(ctx, W, kc, torch, np)
+    serving = None if args.no_serve else served(ctx, W, torch, np, args.serve_seconds)
+
+    cpu, exact = None, None
     if not args.no_cpu_baseline:
-        reps = max(1, int(args.cpu_seconds / max(oracle_s, 1e-3)))
-        t_c = time.perf_counter()
-        for _ in range(reps):
-            O.run_job(job)
-        cs = time.perf_counter() - t_c
-        cpu = {"value": round(orc.records * reps / cs, 1), "unit": "records/s", "cores": 1, "kind": "oracle",
-               "sample": f"the same workload run {reps}x by the single-threaded C oracle ({cs:.1f} s)"}
-
-    batched = None if args.no_batched else batched_vs_plain(ctx, W, kc, O, torch, np)
+        cpu, exact, sample_exact = cpu_baseline_leg(job, rep, mem, args.cpu_seconds, np, sample)
+        if batched is not None:
+            batched["bit_exact_sample"] = sample_exact
+            batched["verified_instances"] = len(sample)
 
     lat_ms = sorted(x * 1e3 for x in lat)
     out = {
@@ -138,26 +112,104 @@ def main():
         "config": {"workload": "tree256-plain: 4096 blocks x 256 threads over 2^20 int32 in [0,2^16), "
                                "1% dropped-barrier and 0.1% tid-barrier blocks, seed 12116195",
                    "form": "plain (one kc_launch per step)", "records_per_step": records,
-                   "races": len(rep.races), "findings": len(rep.faults), "bit_exact": exact,
+                   "races": len(rep.races), "findings": len(rep.faults),
+                   "bit_exact_vs_oracle": exact,
                    "p50_ms": round(lat_ms[len(lat_ms) // 2], 4),
                    "p99_ms": round(lat_ms[min(len(lat_ms) - 1, int(0.99 * len(lat_ms)))], 4),
                    "replays_per_step": stats["replays"] / args.steps, "fallbacks": stats["fallbacks"]},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "batched_vs_plain": batched,
+        "served": serving,
     }
     print(json.dumps(out), flush=True)
     ctx.close()
-    if not exact:
+    if exact is False or (batched and batched.get("bit_exact_sample") is False):
         sys.exit(1)
 
 
-def batched_vs_plain(ctx, W, kc, O, torch, np, reps=3, plain_sample=200, verify=40):
+# Peak of the interpreter's resource: int32 vector lane-operations.  256 CUs x
+# 4 SIMDs x 16 lanes, one wave64 int32 VALU instruction per SIMD every 4 cycles
+# = 64 lane-ops per CU per clock, at 2.4 GHz.  (The 157.3 TFLOP/s fp32 figure
+# counts an FMA as two flops and packed dual issue; int32 has neither.)
+INT32_LANE_OPS_PEAK_G = 256 * 64 * 2.4       # G lane-ops/s = 39,321.6
+
+
+def interp_roofline(stats, steps, records, value, per):
+    """Roofline of the dominant kernel, the free-run interpreter.  Its
+    algorithmic work is one int32 lane-operation per simulated
+    thread-instruction (the library counts the free run's thread-instructions
+    from the fuel each thread spent); its duration is the library's HIP-event
+    time of the interpreter launch on the launch stream."""
+    instr = stats["instructions"] / steps
+    dur_s = per["interp_ms"] / 1e3 / max(1.0, stats["interp_launches"] / steps)
+    achieved = instr / dur_s / 1e9 if dur_s > 0 else 0.0
+    traffic = measured_traffic()
+    return {"bound": "alu", "kernel": "k_interp_free_local", "achieved": round(achieved, 1),
+            "peak": INT32_LANE_OPS_PEAK_G, "unit": "G thread-instructions/s (int32 lane-ops/s)",
+            "frac": round(achieved / INT32_LANE_OPS_PEAK_G, 5), "traffic": traffic,
+            "avg_ms": round(per["interp_ms"], 4), "thread_instructions_per_launch": int(instr),
+            "stage_ms": {k: round(v, 4) for k, v in per.items()},
+            "replay_detail_ms": {k: round(stats[k] / steps, 4) for k in
+                                 ("replay_lockstep_ms", "replay_sort_ms", "replay_check_ms", "replay_coverage_ms")},
+            "log_entries_per_step": stats["log_entries"] / steps,
+            "path_hbm_algorithmic_gbs": round(value * 16 / 1e9, 1),
+            "path_hbm_algorithmic_frac": round(value * 16 / (HBM_PEAK_GBS * 1e9), 4)}
+
+
+def measured_traffic():
+    """HBM bytes per interpreter launch from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE passes scaled by a copy kernel's reading), or
+    None when the interpreter's sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "interp_tree256_traffic.json")
+    try:
+        with open(path) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    from paper_1211_6193_amd.profsum import kernel_source_digest
+    if t.get("source_digest") != kernel_source_digest():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def _same(rep, got, orc, np):
+    return (rep.records == orc.records and rep.race_tuples() == orc.race_tuples()
+            and rep.fault_tuples() == orc.fault_tuples() and rep.launches_completed == orc.launches_completed
+            and bool(np.array_equal(got, orc.memory)))
+
+
+def cpu_baseline_leg(job, rep, mem, cpu_seconds, np, sample=()):
+    """The oracle on the host cores: its rate on the same workload, and the
+    bit-exact comparison of the GPU's last step (and of a sample of batched
+    instances, (job, report, final memory)) with the oracle's runs."""
+    from oracle import oracle as O
+    t_o = time.perf_counter()
+    orc = O.run_job(job)
+    oracle_s = time.perf_counter() - t_o
+    exact = _same(rep, mem.cpu().numpy(), orc, np)
+    if not exact:
+        print("bench: GPU result differs from the oracle", file=sys.stderr)
+    sample_exact = all(_same(r, m, O.run_job(j), np) for j, r, m in sample)
+    if not sample_exact:
+        print("bench: a batched instance differs from the oracle", file=sys.stderr)
+    reps = max(1, int(cpu_seconds / max(oracle_s, 1e-3)))
+    t_c = time.perf_counter()
+    for _ in range(reps):
+        O.run_job(job)
+    cs = time.perf_counter() - t_c
+    cpu = {"value": round(orc.records * reps / cs, 1), "unit": "records/s", "cores": 1, "kind": "oracle",
+           "sample": f"the whole workload run {reps}x by the single-threaded C oracle ({cs:.1f} s)"}
+    return cpu, exact, sample_exact
+
+
+def batched_vs_plain(ctx, W, kc, torch, np, reps=3, plain_sample=200, verify=40):
     """Workload 3 (10,000 mixed instances, seed 12116196): the whole set as one
     batch (kc_batch_submit + kc_poll) against one plain kc_launch per instance
     on a sample of instances; both on the same resident memories (the
     instances read their inputs and write disjoint outputs, so reruns are
-    identical).  A sample of instances is compared with the oracle."""
+    identical).  Returns the figures and a sample of (job, report, final
+    memory) for the comparison with the oracle in the CPU-baseline leg."""
     jobs = W.config3_jobs(n=10000)
     mems = [torch.from_numpy(np.ascontiguousarray(j.memory)).cuda() for j in jobs]
     batch = kc.Batch(ctx)
@@ -183,12 +235,7 @@ def batched_vs_plain(ctx, W, kc, O, torch, np, reps=3, plain_sample=200, verify=
         lat.append(time.perf_counter() - t0)
         prec += r.records
     plain_rate = prec / sum(lat)
-    exact = True
-    for i in idx[:verify]:
-        orc = O.run_job(jobs[i])
-        r = res[i]
-        exact &= (r.records == orc.records and r.race_tuples() == orc.race_tuples()
-                  and r.fault_tuples() == orc.fault_tuples() and bool(np.array_equal(mems[i].cpu().numpy(), orc.memory)))
+    sample = [(jobs[i], res[i], mems[i].cpu().numpy()) for i in idx[:verify]]
     lat_ms = sorted(x * 1e3 for x in lat)
     return {"workload": "workload 3: 10000 instances (tree/stencil/transpose, 1-64 blocks x 32-1024 threads, "
                         "20% seeded faults)",
@@ -198,17 +245,29 @@ def batched_vs_plain(ctx, W, kc, O, torch, np, reps=3, plain_sample=200, verify=
             "plain_p50_ms": round(lat_ms[len(lat_ms) // 2], 4),
             "plain_p99_ms": round(lat_ms[min(len(lat_ms) - 1, int(0.99 * len(lat_ms)))], 4),
             "speedup": round((records / best) / plain_rate, 2),
-            "bit_exact_sample": exact, "verified_instances": min(verify, len(idx))}
+            "bit_exact_sample": None, "verified_instances": 0}, sample
 
 
-def _sort_passes(job):
-    # virtual sort key: epoch bits used + block + address + space bits
-    import math
-    L = job.launches[0]
-    nb = L.n_blocks
-    words = len(job.memory)
-    bits = 4 + math.ceil(math.log2(nb)) + math.ceil(math.log2(max(words, L.shmem_bytes // 4))) + 1
-    return math.ceil(bits / 8)
+def served(ctx, W, torch, np, seconds, rates=(1000.0, 5000.0, 20000.0)):
+    """Workload 5: Poisson arrivals at each rate for ``seconds``; 95% workload-3
+    instances, 5% 4096x256 trees, drawn from a seeded pool whose initial
+    memories are resident on the device (each request gets its own copy);
+    continuous batching with 4 streams under a 64 GiB budget."""
+    from paper_1211_6193_amd import server
+    small, big = W.request_pool()
+    pristine = {id(j): torch.from_numpy(np.ascontiguousarray(j.memory)).cuda() for j in small + big}
+    torch.cuda.synchronize()
+    out = {"workload": f"workload 5: {seconds:g} s of Poisson arrivals per rate; pool of {len(small)} workload-3 "
+                       f"instances and {len(big)} 4096x256 trees (p=0.05); 4 slots, 64 GiB budget"}
+    srv = server.Server(ctx, budget_bytes=64 << 30, slots=4)
+    srv.run(W.pooled_requests(1000.0, 0.3, small, big), pristine=pristine)          # warm-up
+    for rate in rates:
+        res = srv.run(W.pooled_requests(rate, seconds, small, big), pristine=pristine)
+        out[f"{int(rate)}/s"] = {"requests": res["requests"], "records_per_s": round(res["records_per_s"], 1),
+                                 "p50_ms": round(res["p50_ms"], 3), "p99_ms": round(res["p99_ms"], 3),
+                                 "wall_s": round(res["wall_s"], 3), "batches": res["batches"],
+                                 "mean_batch": round(res["mean_batch"], 1)}
+    return out
 
 
 if __name__ == "__main__":

@@ -86,23 +86,34 @@ enum { KC_DEADLOCK = 1, KC_DIVERGENCE = 2, KC_OOB = 3, KC_FUEL = 4, KC_ARITH = 5
 
 /* Create a context on HIP device `hip_device`.  `hbm_budget_bytes` bounds the
  * library's own device memory (logs, snapshots, scratch); 0 means no bound.
- * `tune_cache` names a JSON file of autotuned launch parameters or is NULL.
- * Errors: KC_E_INVAL (bad device), KC_E_DEVICE. */
+ * `tune_cache` names a JSON file of autotuned launch parameters or is NULL:
+ * a flat object of option names and integer values (see kc_ctx_set_option),
+ * as written by the package's autotuner; each entry is applied as that
+ * option.  Errors: KC_E_INVAL (bad device, unreadable cache, non-integer
+ * value, unknown option or out-of-range value in the cache), KC_E_DEVICE. */
 kc_status kc_ctx_create(int hip_device, uint64_t hbm_budget_bytes, const char *tune_cache, kc_ctx **out);
 void kc_ctx_destroy(kc_ctx *ctx);
 
 /* Options: "check" (1 = log and check, default; 0 = interpret only),
  * "fuel" (instructions per thread, default 1<<20), "timing" (1 = time the
  * stages with HIP events on the launch stream), "sort_tile" (keys per sort
- * tile: 2048, 4096 or 8192), "log_records" (initial log capacity).
+ * tile: 2048, 4096 or 8192), "log_records" (initial log capacity, >= 1024),
+ * "stage" (interpreter staging granule per wave: 128, 256, 512 or 1024
+ * records), "stage_bytes" (LDS bytes of per-block record staging, 8192 to
+ * 98304), "local" (1 = check shared accesses and sort staged global records
+ * per barrier epoch inside the interpreter, default; 0 = log every access),
+ * "reset" (1 = clear the statistics).
  * Errors: KC_E_INVAL for an unknown key or out-of-range value. */
 kc_status kc_ctx_set_option(kc_ctx *ctx, const char *key, int64_t value);
 
 /* Accumulated statistics since the last reset ("reset" clears them):
  * "interp_ms", "sort_ms", "check_ms", "replay_ms", "launches", "records",
- * "replays", "fallbacks", "retries", "interp_launches", "sort_keys".
- * Timings are only collected with option "timing" set.  Returns 0 for an
- * unknown key. */
+ * "replays", "fallbacks", "retries", "interp_launches", "sort_keys",
+ * "instructions" (thread-instructions executed by the parallel free run; a
+ * canonical replay of racy blocks is not counted).
+ * Timings are only collected with option "timing" set.  "option.<name>"
+ * reads back the current value of option <name>.  Returns 0 for an unknown
+ * key. */
 double kc_ctx_get_stat(kc_ctx *ctx, const char *key);
 
 /* Message of the last error on this context; valid until the next call on it. */

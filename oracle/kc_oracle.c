@@ -86,6 +86,7 @@ typedef struct {
     ora_race *races;    uint64_t n_races, cap_races;
     ora_fault *faults;  uint64_t n_faults, cap_faults;
     uint64_t n_records;
+    uint64_t n_instructions;    /* thread-instructions executed (fuel spent) */
     uint32_t launches_completed;
     int keep_records;
     int oom;
@@ -249,6 +250,7 @@ static int run_block(ora_result *res, uint32_t li, const uint64_t *prog, uint32_
                     continue;
                 }
                 T->fuel--;
+                res->n_instructions++;
                 uint64_t w = prog[T->pc];
                 uint32_t op = w & 0xFF, d = (w >> 8) & 0xFF, a = (w >> 16) & 0xFF, b = (w >> 24) & 0xFF;
                 int32_t imm = (int32_t)(uint32_t)(w >> 32);
@@ -479,6 +481,7 @@ int ora_run_job(uint32_t n_launches, const uint64_t *const *progs, const uint32_
 }
 
 uint64_t ora_records(const ora_result *r) { return r->n_records; }
+uint64_t ora_instructions(const ora_result *r) { return r->n_instructions; }
 uint32_t ora_launches_completed(const ora_result *r) { return r->launches_completed; }
 const ora_race *ora_races(const ora_result *r, uint64_t *n) { *n = r->n_races; return r->races; }
 const ora_fault *ora_faults(const ora_result *r, uint64_t *n) { *n = r->n_faults; return r->faults; }

@@ -58,6 +58,8 @@ def _load():
         lib.ora_run_job.restype = C.c_int
         lib.ora_records.argtypes = [C.c_void_p]
         lib.ora_records.restype = C.c_uint64
+        lib.ora_instructions.argtypes = [C.c_void_p]
+        lib.ora_instructions.restype = C.c_uint64
         lib.ora_launches_completed.argtypes = [C.c_void_p]
         lib.ora_launches_completed.restype = C.c_uint32
         for name in ("ora_races", "ora_faults", "ora_kept_records"):
@@ -79,6 +81,7 @@ class OracleResult:
     faults: np.ndarray            # FAULT_DTYPE, canonical order, no duplicates
     memory: np.ndarray            # final global memory (int32)
     record_log: Optional[np.ndarray] = None   # RECORD_DTYPE if keep_records
+    instructions: int = 0         # thread-instructions executed (fuel spent)
 
     def race_tuples(self) -> List[Tuple[int, ...]]:
         return [tuple(int(x) for x in r) for r in self.races]
@@ -127,6 +130,6 @@ def run_job(job, fuel: int = DEFAULT_FUEL, keep_records: bool = False,
         if keep_records:
             log = _copy(lib.ora_kept_records(out, C.byref(cnt)), cnt.value, RECORD_DTYPE)
         return OracleResult(int(lib.ora_records(out)), int(lib.ora_launches_completed(out)),
-                            races, faults, mem, log)
+                            races, faults, mem, log, int(lib.ora_instructions(out)))
     finally:
         lib.ora_free(out)

@@ -81,7 +81,9 @@ struct DevCounters {
     uint32_t edge_count;
     uint32_t flags;
     uint32_t max_epoch;
-    uint32_t pad[9];
+    uint32_t pad0;
+    unsigned long long instructions;   // thread-instructions of the free run
+    uint32_t pad[6];
 };
 
 struct InterpArgs {
@@ -106,6 +108,7 @@ struct InterpArgs {
     uint32_t lrace_cap;
     uint32_t *lrace_count;
     uint32_t *blk_flags;        // racy blocks
+    unsigned long long *instructions;   // free run: thread-instructions executed (added to), or null
 };
 
 // Host-side launchers (defined in the .hip files).

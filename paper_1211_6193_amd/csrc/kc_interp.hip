@@ -325,35 +325,20 @@ __device__ __forceinline__ void push_local_race(const InterpArgs &A, const Block
     A.blk_flags[B.u->block_base + B.block] = 1u;
 }
 
-// Wave-aggregated append of one record per lane with `has` set.
-__device__ __forceinline__ void append_log(const InterpArgs &A, bool has, uint64_t rec) {
-    const uint64_t m = __ballot(has);
-    if (m == 0) return;
-    const uint32_t leader = (uint32_t)__ffsll((long long)m) - 1;
-    unsigned long long base = 0;
-    if (lane_id() == leader) base = atomicAdd(A.log_count, (unsigned long long)__popcll(m));
-    base = bcast_u64(base, leader);
-    if (has) {
-        const unsigned long long p = base + lane_prefix(m);
-        if (p < A.log_cap) A.log[p] = rec;
-        else atomicOr(A.flags, FLAG_LOG_OVERFLOW);
-    }
-}
-
 __device__ __forceinline__ void epoch_local_check(const InterpArgs &A, const BlockCtx &B, const Shared &S,
                                                   LogState &L, uint32_t epoch) {
     const KeyPlan &k = A.kp;
-    if (lane_id() == 0) {
-        S.slots[8 * B.wave + 6] = L.cur;
-        S.slots[8 * B.wave + 7] = L.spilled ? 1u : 0u;
+    if (lane_id() == 0) {       // per-wave staged count and spill flag (tmp[w], tmp[16 + w])
+        S.tmp[B.wave] = L.cur;
+        S.tmp[16 + B.wave] = L.spilled ? 1u : 0u;
     }
     __syncthreads();
     uint32_t n = 0, off = 0, spilled = 0;
     for (uint32_t w = 0; w < B.nwaves; w++) {
-        const uint32_t c = S.slots[8 * w + 6];
+        const uint32_t c = S.tmp[w];
         if (w < B.wave) off += c;
         n += c;
-        spilled |= S.slots[8 * w + 7];
+        spilled |= S.tmp[16 + w];
     }
     // shared memory: reduce and clear the shadow tuples of this epoch
     for (uint32_t a = threadIdx.x; a < B.sh_words; a += blockDim.x) {
@@ -377,6 +362,12 @@ __device__ __forceinline__ void epoch_local_check(const InterpArgs &A, const Blo
         }
         const uint64_t ep_mask = ((1ull << k.eb) - 1ull) << k.s_ep;
         const uint64_t rep_ep = (uint64_t)k.ep_rep << k.s_ep;
+        // Representatives are compacted into dst (a segment yields no more
+        // representatives than records, so n entries suffice) and reserved in
+        // the log with one atomic per block: a single global counter serves
+        // every block of the launch.
+        if (threadIdx.x == 0) S.tmp[32] = 0;
+        __syncthreads();
         for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
             const uint64_t r = src[i];
             const uint32_t lk = local_key(r, k);
@@ -399,8 +390,26 @@ __device__ __forceinline__ void epoch_local_check(const InterpArgs &A, const Blo
                                     t1 == minw ? t2 : t1);
             }
             const bool glob = head && rec_field(r, k.s_sp, 1) == 1u;
-            append_log(A, glob, (src[i1] & ~ep_mask) | rep_ep);
-            append_log(A, glob && minw != NONE_U32 && !(w1 && t1 == minw), (src[iw] & ~ep_mask) | rep_ep);
+            const bool two = glob && minw != NONE_U32 && !(w1 && t1 == minw);
+            if (glob) {
+                const uint32_t at = atomicAdd(&S.tmp[32], two ? 2u : 1u);
+                dst[at] = (src[i1] & ~ep_mask) | rep_ep;
+                if (two) dst[at + 1] = (src[iw] & ~ep_mask) | rep_ep;
+            }
+        }
+        __syncthreads();
+        const uint32_t nrep = S.tmp[32];
+        if (nrep) {
+            if (threadIdx.x == 0) {
+                const unsigned long long base = atomicAdd(A.log_count, (unsigned long long)nrep);
+                S.tmp[33] = (uint32_t)base;
+                S.tmp[34] = (uint32_t)(base >> 32);
+                if (base + nrep > A.log_cap) atomicOr(A.flags, FLAG_LOG_OVERFLOW);
+            }
+            __syncthreads();
+            const unsigned long long base = (unsigned long long)S.tmp[33] | ((unsigned long long)S.tmp[34] << 32);
+            for (uint32_t j = threadIdx.x; j < nrep; j += blockDim.x)
+                if (base + j < A.log_cap) A.log[base + j] = dst[j];
         }
     }
     __syncthreads();            // the staging areas are free again
@@ -471,10 +480,7 @@ __device__ __forceinline__ int barrier_episode(const InterpArgs &A, BlockCtx &B,
         emit_fault(threadIdx.x == 0, A, B, F_DIVERGENCE, epoch, (uint32_t)BMIN, tlo, (uint32_t)C, tc);
     }
     epoch++;
-    if (threadIdx.x == 0) {
-        if (epoch > A.kp.max_epoch) atomicOr(A.flags, FLAG_EPOCH_OVERFLOW);
-        atomicMax(A.max_epoch, epoch);
-    }
+    if (threadIdx.x == 0 && epoch > A.kp.max_epoch) atomicOr(A.flags, FLAG_EPOCH_OVERFLOW);
     if (t.st == ST_WAIT) {
         t.st = ST_RUN;
         t.pc = t.bar_pc + 1;
@@ -631,17 +637,47 @@ __device__ __forceinline__ void setup_block(const InterpArgs &A, BlockCtx &B, co
     __syncthreads();
 }
 
-__device__ __forceinline__ void finish_block(const InterpArgs &A, const BlockCtx &B, const Shared &S, LogState &L) {
+// End of a block: flush the staged records, publish the block's record count,
+// its last epoch (the largest it reached) and, in the free run, the
+// thread-instructions it executed (every executed instruction spent one unit of
+// fuel).  One global atomic per block and counter: the counters are shared by
+// every block of the launch.
+__device__ __forceinline__ void finish_block(const InterpArgs &A, const BlockCtx &B, const Shared &S, LogState &L,
+                                             const Lane &t, uint32_t epoch) {
     flush_stage(A, S.stage, L.cur);
     L.cur = 0;
-    if (lane_id() == 0 && L.total) atomicAdd(&A.blk_recs[B.u->block_base + B.block], L.total);
+    unsigned long long spent = 0;
+    if (A.instructions) {
+        spent = (t.st != ST_DEAD) ? (unsigned long long)(B.u->fuel - t.fuel) : 0ull;
+        for (int o = 32; o > 0; o >>= 1) spent += __shfl_xor(spent, o);
+    }
+    __syncthreads();            // the episode slots are free
+    if (lane_id() == 0) {
+        S.slots[8 * B.wave] = L.total;
+        S.slots[8 * B.wave + 1] = (uint32_t)spent;
+        S.slots[8 * B.wave + 2] = (uint32_t)(spent >> 32);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t recs = 0;
+        unsigned long long instr = 0;
+        for (uint32_t w = 0; w < B.nwaves; w++) {
+            recs += S.slots[8 * w];
+            instr += (unsigned long long)S.slots[8 * w + 1] | ((unsigned long long)S.slots[8 * w + 2] << 32);
+        }
+        if (recs) atomicAdd(&A.blk_recs[B.u->block_base + B.block], recs);
+        if (instr) atomicAdd(A.instructions, instr);
+        if (epoch > __hip_atomic_load(A.max_epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            atomicMax(A.max_epoch, epoch);
+    }
     L.total = 0;
     __syncthreads();
 }
 
 // ---- free-run block execution ------------------------------------------------
 template <bool LOCAL>
-__device__ __forceinline__ void run_block_free(const InterpArgs &A, BlockCtx &B, const Shared &S, Lane &t, LogState &L) {
+__device__ __forceinline__ uint32_t run_block_free(const InterpArgs &A, BlockCtx &B, const Shared &S, Lane &t,
+                                                   LogState &L) {
     uint32_t epoch = 0;
     Pending P{false, false, 0, 0};
     bool conv = true;    // every running lane of the wave is at upc
@@ -705,6 +741,7 @@ __device__ __forceinline__ void run_block_free(const InterpArgs &A, BlockCtx &B,
         conv = (lo == hi) || hi < 0;
         upc = uni(lo);
     }
+    return epoch;
 }
 
 // ---- lockstep (canonical) block execution ---------------------------------------
@@ -729,14 +766,15 @@ constexpr uint32_t EMPTY_KEY = 0xFFFFFFFFu;
 
 __device__ __forceinline__ uint32_t ghash(uint32_t a, uint32_t hbits) { return (a * 2654435761u) >> (32 - hbits); }
 
-__device__ __forceinline__ void run_block_lockstep(const InterpArgs &A, BlockCtx &B, const Shared &S,
+template <bool LOCAL>
+__device__ __forceinline__ uint32_t run_block_lockstep(const InterpArgs &A, BlockCtx &B, const Shared &S,
                                                    const StoreTables &T, Lane &t, LogState &L) {
     uint32_t epoch = 0;
     uint32_t step = 0;
     bool any_run = true;
     for (;;) {
         if (!any_run) {
-            if (barrier_episode<false>(A, B, S, t, L, epoch) == EP_DONE) break;
+            if (barrier_episode<LOCAL>(A, B, S, t, L, epoch) == EP_DONE) break;
             any_run = true;     // a completed episode releases every thread
         }
         // phase A: every running lane executes exactly one instruction; loads
@@ -761,7 +799,7 @@ __device__ __forceinline__ void run_block_lockstep(const InterpArgs &A, BlockCtx
             if (active) t.fuel--;
             int ctl, target;
             bool cond;
-            exec_one<true, false>(A, B, S, t, L, P, epoch, cur, active, ctl, target, cond);
+            exec_one<true, LOCAL>(A, B, S, t, L, P, epoch, cur, active, ctl, target, cond);
             if (active && ctl != 3) {
                 if (ctl == 2) t.pc = cond ? target : cur + 1;
                 else t.pc = target;
@@ -810,6 +848,7 @@ __device__ __forceinline__ void run_block_lockstep(const InterpArgs &A, BlockCtx
             }
         }
     }
+    return epoch;
 }
 
 // LDS layout: simulated shared memory | staging (nwaves x stage records) |
@@ -858,8 +897,8 @@ __device__ __forceinline__ void interp_free_body(const InterpArgs &A) {
     Lane t;
     LogState L{0, 0, false};
     setup_block(A, B, S, t, unit, block);
-    run_block_free<LOCAL>(A, B, S, t, L);
-    finish_block(A, B, S, L);
+    const uint32_t epoch = run_block_free<LOCAL>(A, B, S, t, L);
+    finish_block(A, B, S, L, t, epoch);
 }
 
 
@@ -872,7 +911,8 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6, 6)
     interp_free_body<false>(A);
 }
 
-__global__ void __launch_bounds__(1024) k_interp_lockstep(InterpArgs A) {
+template <bool LOCAL>
+__device__ __forceinline__ void interp_lockstep_body(const InterpArgs &A) {
     extern __shared__ __align__(16) uint8_t smem[];
     Shared S;
     const uint32_t nwaves = (blockDim.x + WAVE - 1) / WAVE;
@@ -899,10 +939,13 @@ __global__ void __launch_bounds__(1024) k_interp_lockstep(InterpArgs A) {
     for (uint32_t c = c0; c < c1; c++) {
         uint2 it = A.comp_blocks[c];
         setup_block(A, B, S, t, uniu(it.x), uniu(it.y));
-        run_block_lockstep(A, B, S, T, t, L);
-        finish_block(A, B, S, L);
+        const uint32_t epoch = run_block_lockstep<LOCAL>(A, B, S, T, t, L);
+        finish_block(A, B, S, L, t, epoch);
     }
 }
+
+__global__ void __launch_bounds__(1024) k_interp_lockstep(InterpArgs A) { interp_lockstep_body<false>(A); }
+__global__ void __launch_bounds__(1024) k_interp_lockstep_local(InterpArgs A) { interp_lockstep_body<true>(A); }
 
 }  // namespace
 
@@ -919,7 +962,6 @@ size_t interp_lds_bytes(uint32_t sh_words_max, uint32_t wg_threads, uint32_t sta
 hipError_t launch_interp(const InterpArgs &a, uint32_t n_wg, uint32_t wg_threads, bool lockstep, hipStream_t s) {
     if (n_wg == 0) return hipSuccess;
     InterpArgs args = a;
-    if (lockstep) args.local = 0;
     size_t lds = interp_lds_bytes(args.sh_words_max, wg_threads, args.stage, lockstep, args.local != 0);
     while (lds > 160 * 1024 && args.stage > 64) {   // shrink the record staging area to fit
         args.stage = (args.stage / 2 + 63) / 64 * 64;
@@ -939,11 +981,16 @@ hipError_t launch_interp(const InterpArgs &a, uint32_t n_wg, uint32_t wg_threads
         if (e0 != hipSuccess) return e0;
         hipError_t e2 = hipFuncSetAttribute((const void *)k_interp_lockstep,
                                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        hipError_t e3 = hipFuncSetAttribute((const void *)k_interp_lockstep_local,
+                                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e3 != hipSuccess) return e3;
         if (e1 != hipSuccess) return e1;
         if (e2 != hipSuccess) return e2;
         attr_set = true;
     }
-    if (lockstep)
+    if (lockstep && args.local)
+        hipLaunchKernelGGL(k_interp_lockstep_local, dim3(n_wg), dim3(wg_threads), lds, s, args);
+    else if (lockstep)
         hipLaunchKernelGGL(k_interp_lockstep, dim3(n_wg), dim3(wg_threads), lds, s, args);
     else if (args.local)
         hipLaunchKernelGGL(k_interp_free_local, dim3(n_wg), dim3(wg_threads), lds, s, args);

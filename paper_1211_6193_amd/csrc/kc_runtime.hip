@@ -21,6 +21,8 @@
 #include <algorithm>
 #include <atomic>
 #include <condition_variable>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -103,7 +105,7 @@ struct DBuf {
 struct Workspace {
     DBuf units, items, comp_off, comp_blocks, mask;
     DBuf snap, log, alt, rlog, ralt, fs, hist, part;
-    DBuf faults, rfaults, races, lraces, edges, blk_recs, rblk_recs, blk_flags, rflags, ctr, rctr;
+    DBuf faults, rfaults, races, lraces, rlraces, edges, blk_recs, rblk_recs, blk_flags, rflags, ctr, rctr;
     DevCounters *h_ctr = nullptr;   // pinned
     hipEvent_t ev[12] = {};
     bool init = false;
@@ -116,7 +118,7 @@ struct Workspace {
     size_t device_bytes() const {
         const DBuf *all[] = {&units, &items, &comp_off, &comp_blocks, &mask, &snap, &log, &alt, &rlog,
                              &ralt, &fs, &hist, &part, &faults, &rfaults, &races, &edges, &blk_recs,
-                             &rblk_recs, &blk_flags, &rflags, &ctr, &rctr, &lraces};
+                             &rblk_recs, &blk_flags, &rflags, &ctr, &rctr, &lraces, &rlraces};
         size_t s = 0;
         for (auto *b : all) s += b->bytes;
         return s;
@@ -124,7 +126,7 @@ struct Workspace {
     ~Workspace() {
         DBuf *all[] = {&units, &items, &comp_off, &comp_blocks, &mask, &snap, &log, &alt, &rlog,
                        &ralt, &fs, &hist, &part, &faults, &rfaults, &races, &edges, &blk_recs,
-                       &rblk_recs, &blk_flags, &rflags, &ctr, &rctr, &lraces};
+                       &rblk_recs, &blk_flags, &rflags, &ctr, &rctr, &lraces, &rlraces};
         for (auto *b : all) b->release();
         if (h_ctr) (void)hipHostFree(h_ctr);
         for (auto &e : ev)
@@ -411,7 +413,7 @@ struct Stage {
 
     // Interpreter launches for all units, grouped by workgroup size.
     void interp(bool lockstep, DBuf &logbuf, uint64_t log_cap, DBuf &ctr, DBuf &faults, uint32_t fault_cap,
-                DBuf &recs, uint32_t n_comp) {
+                DBuf &recs, uint32_t n_comp, DBuf &lrace_buf, uint32_t lrace_cap_, DBuf &flags) {
         InterpArgs a{};
         a.units = ws.units.as<DevUnit>();
         a.kp = kp;
@@ -425,11 +427,12 @@ struct Stage {
         a.flags = &ctr.as<DevCounters>()->flags;
         a.max_epoch = &ctr.as<DevCounters>()->max_epoch;
         a.stage = ctx->opt.stage;
-        a.local = (!lockstep && ctx->opt.check && ctx->opt.local) ? 1u : 0u;
-        a.lraces = ws.lraces.as<DevRace>();
-        a.lrace_cap = lrace_cap;
+        a.local = (ctx->opt.check && ctx->opt.local) ? 1u : 0u;
+        a.lraces = lrace_buf.as<DevRace>();
+        a.lrace_cap = lrace_cap_;
         a.lrace_count = &ctr.as<DevCounters>()->race_count;
-        a.blk_flags = ws.blk_flags.as<uint32_t>();
+        a.blk_flags = flags.as<uint32_t>();
+        a.instructions = lockstep ? nullptr : &ctr.as<DevCounters>()->instructions;
         if (lockstep) {
             a.stage = ctx->opt.stage;
             uint32_t wg = 64, shmax = 0;
@@ -510,7 +513,8 @@ struct Stage {
             HIPCHK(launch_zero(ws.blk_recs.p, (size_t)total_blocks * 4, s));
             HIPCHK(launch_zero(ws.blk_flags.p, (size_t)total_blocks * 4, s));
             tm.mark(0);
-            interp(false, ws.log, log_cap, ws.ctr, ws.faults, fault_cap, ws.blk_recs, 0);
+            interp(false, ws.log, log_cap, ws.ctr, ws.faults, fault_cap, ws.blk_recs, 0, ws.lraces, lrace_cap,
+                   ws.blk_flags);
             tm.mark(1);
             c = read_ctr(ws.ctr);
             ctx->stat_add("interp_ms", tm.ms(0, 1));
@@ -538,6 +542,7 @@ struct Stage {
             HIPCHK(launch_copy_units(ws.units.as<DevUnit>(), n, max_words, false, nullptr, s));   // back to launch start
             ctx->stat_add("retries", 1);
         }
+        ctx->stat_add("instructions", (double)c.instructions);
         if (check) ctx->note_log_records(c.log_count + c.log_count / 8);
         used_epoch_bits = bits_for((uint64_t)c.max_epoch + 2);   // one more value: representative records
 
@@ -673,14 +678,18 @@ struct Stage {
     }
 
     // One lockstep pass over `comps`; records go to ws.rlog (capacity rcap).
-    DevCounters lockstep_once(const std::vector<std::vector<uint2>> &comps, uint64_t rcap, uint32_t fcap) {
+    DevCounters lockstep_once(const std::vector<std::vector<uint2>> &comps, uint64_t rcap, uint32_t fcap,
+                              uint32_t rlcap) {
         upload_comps(comps);
         ws.rblk_recs.reserve((size_t)total_blocks * 4);
+        ws.rflags.reserve((size_t)std::max<uint32_t>(total_blocks, 1) * 4);
         ws.rlog.reserve(rcap * 8);
         ws.rfaults.reserve((size_t)fcap * sizeof(DevFault));
+        ws.rlraces.reserve((size_t)rlcap * sizeof(DevRace));
         reset_counters(ws.rctr);
         HIPCHK(launch_zero(ws.rblk_recs.p, (size_t)total_blocks * 4, s));
-        interp(true, ws.rlog, rcap, ws.rctr, ws.rfaults, fcap, ws.rblk_recs, (uint32_t)comps.size());
+        interp(true, ws.rlog, rcap, ws.rctr, ws.rfaults, fcap, ws.rblk_recs, (uint32_t)comps.size(), ws.rlraces,
+               rlcap, ws.rflags);
         DevCounters c = read_ctr(ws.rctr);
         if (c.flags & FLAG_EPOCH_OVERFLOW)
             throw KcError{KC_E_OVERFLOW, "barrier epochs exceed the record's epoch field"};
@@ -722,11 +731,11 @@ struct Stage {
         // put back what the racy blocks wrote, then re-execute them canonically
         HIPCHK(launch_restore(sorted, nrec, kp, ws.units.as<DevUnit>(), ws.blk_flags.as<uint32_t>(), s));
         uint64_t rcap = s_recs + s_recs / 4 + 1024;
-        uint32_t fcap = 4096;
-        DevCounters rc = lockstep_once(comps, rcap, fcap);
+        uint32_t fcap = 4096, rlcap = 4096 + (uint32_t)races.size() * 2;
+        DevCounters rc = lockstep_once(comps, rcap, fcap, rlcap);
         tm.mark(7);
         ctx->stat_add("replay_lockstep_ms", tm.ms(5, 7));
-        bool ok = !(rc.flags & (FLAG_LOG_OVERFLOW | FLAG_FAULT_OVERFLOW));
+        bool ok = !(rc.flags & (FLAG_LOG_OVERFLOW | FLAG_FAULT_OVERFLOW | FLAG_RACE_OVERFLOW));
         std::vector<DevRace> rr;
         std::vector<DevEdge> re;
         if (ok) {
@@ -752,7 +761,11 @@ struct Stage {
                 HIPCHK(hipMemcpyAsync(rf.data(), ws.rfaults.p, rf.size() * sizeof(DevFault), hipMemcpyDeviceToHost, s));
             std::vector<uint32_t> rrecs(total_blocks);
             HIPCHK(hipMemcpyAsync(rrecs.data(), ws.rblk_recs.p, (size_t)total_blocks * 4, hipMemcpyDeviceToHost, s));
+            std::vector<DevRace> rl(std::min<uint32_t>(rc.race_count, rlcap));
+            if (!rl.empty())
+                HIPCHK(hipMemcpyAsync(rl.data(), ws.rlraces.p, rl.size() * sizeof(DevRace), hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
+            rr.insert(rr.end(), rl.begin(), rl.end());
             std::vector<char> in_s(total_blocks, 0);
             for (auto &c : comps)
                 for (auto &ub : c) {
@@ -799,22 +812,27 @@ struct Stage {
         for (;;) {
             HIPCHK(launch_copy_units(ws.units.as<DevUnit>(), (uint32_t)hu.size(), max_words, false,
                                      ws.mask.as<uint32_t>(), s));
-            fc = lockstep_once(full, rcap, fcap);
-            if (!(fc.flags & (FLAG_LOG_OVERFLOW | FLAG_FAULT_OVERFLOW))) break;
+            fc = lockstep_once(full, rcap, fcap, rlcap);
+            if (!(fc.flags & (FLAG_LOG_OVERFLOW | FLAG_FAULT_OVERFLOW | FLAG_RACE_OVERFLOW))) break;
             rcap = std::max<uint64_t>(rcap, fc.log_count + 1024);
             fcap = std::max<uint32_t>(fcap, fc.fault_count + 1024);
+            rlcap = std::max<uint32_t>(rlcap, fc.race_count + 1024);
         }
         std::vector<DevFault> ff(std::min<uint32_t>(fc.fault_count, fcap));
         if (!ff.empty())
             HIPCHK(hipMemcpyAsync(ff.data(), ws.rfaults.p, ff.size() * sizeof(DevFault), hipMemcpyDeviceToHost, s));
         std::vector<uint32_t> rrecs(total_blocks);
         HIPCHK(hipMemcpyAsync(rrecs.data(), ws.rblk_recs.p, (size_t)total_blocks * 4, hipMemcpyDeviceToHost, s));
+        std::vector<DevRace> fl(std::min<uint32_t>(fc.race_count, rlcap));
+        if (!fl.empty())
+            HIPCHK(hipMemcpyAsync(fl.data(), ws.rlraces.p, fl.size() * sizeof(DevRace), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         used_epoch_bits = std::max(used_epoch_bits, bits_for((uint64_t)fc.max_epoch + 2));
         uint64_t *rs = sort_check(ws.rlog, ws.ralt, fc.log_count);
         std::vector<DevRace> nr;
         std::vector<DevEdge> ne;
         run_check(rs, fc.log_count, ws.rflags, nr, ne);
+        nr.insert(nr.end(), fl.begin(), fl.end());
         for (uint32_t u = 0; u < hu.size(); u++) {
             if (!mask[u]) continue;
             uraces[u].clear();
@@ -892,8 +910,42 @@ void run_jobs(kc_ctx *ctx, const kc_job *jobs, uint32_t n_jobs, hipStream_t s, s
 // ---------------------------------------------------------------------------
 extern "C" {
 
+// Tuned launch parameters: a flat JSON object of integer options written by
+// the autotuner, e.g. {"sort_tile": 4096, "stage_bytes": 16384, "local": 1}.
+static kc_status apply_tune_cache(kc_ctx *c, const char *path) {
+    FILE *f = std::fopen(path, "rb");
+    if (!f) {
+        c->err = std::string("cannot open tune cache ") + path;
+        return KC_E_INVAL;
+    }
+    std::string text;
+    char buf[4096];
+    size_t got;
+    while ((got = std::fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, got);
+    std::fclose(f);
+    size_t i = 0;
+    while ((i = text.find('"', i)) != std::string::npos) {
+        const size_t j = text.find('"', i + 1);
+        if (j == std::string::npos) break;
+        const std::string key = text.substr(i + 1, j - i - 1);
+        size_t k = text.find(':', j);
+        if (k == std::string::npos) break;
+        k++;
+        while (k < text.size() && (text[k] == ' ' || text[k] == '\t' || text[k] == '\n')) k++;
+        char *end = nullptr;
+        const long long v = std::strtoll(text.c_str() + k, &end, 10);
+        if (end == text.c_str() + k) {
+            c->err = "tune cache: value of " + key + " is not an integer";
+            return KC_E_INVAL;
+        }
+        kc_status st = kc_ctx_set_option(c, key.c_str(), (int64_t)v);
+        if (st != KC_OK) return st;
+        i = (size_t)(end - text.c_str());
+    }
+    return KC_OK;
+}
+
 kc_status kc_ctx_create(int hip_device, uint64_t hbm_budget_bytes, const char *tune_cache, kc_ctx **out) {
-    (void)tune_cache;
     if (!out) return KC_E_INVAL;
     *out = nullptr;
     int n = 0;
@@ -905,6 +957,13 @@ kc_status kc_ctx_create(int hip_device, uint64_t hbm_budget_bytes, const char *t
     kc_ctx *c = new kc_ctx();
     c->device = hip_device;
     c->budget = hbm_budget_bytes;
+    if (tune_cache && *tune_cache) {
+        kc_status st = apply_tune_cache(c, tune_cache);
+        if (st != KC_OK) {
+            delete c;
+            return st;
+        }
+    }
     *out = c;
     return KC_OK;
 }
@@ -949,6 +1008,20 @@ kc_status kc_ctx_set_option(kc_ctx *ctx, const char *key, int64_t v) {
 double kc_ctx_get_stat(kc_ctx *ctx, const char *key) {
     if (!ctx || !key) return 0.0;
     std::lock_guard<std::mutex> g(ctx->mu);
+    const std::string k(key);
+    if (k.rfind("option.", 0) == 0) {
+        const std::string o = k.substr(7);
+        const Options &op = ctx->opt;
+        if (o == "check") return op.check;
+        if (o == "fuel") return op.fuel;
+        if (o == "timing") return op.timing;
+        if (o == "sort_tile") return op.sort_tile;
+        if (o == "log_records") return (double)op.log_records;
+        if (o == "stage") return op.stage;
+        if (o == "stage_bytes") return op.stage_bytes;
+        if (o == "local") return op.local;
+        return 0.0;
+    }
     auto it = ctx->stats.find(key);
     return it == ctx->stats.end() ? 0.0 : it->second;
 }

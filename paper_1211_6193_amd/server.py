@@ -134,7 +134,11 @@ class Server:
         self.batch = kc.Batch(ctx)
 
     def run(self, stream: Sequence[Tuple[float, object]], keep_reports: bool = False,
-            keep_memory: bool = False) -> Dict:
+            keep_memory: bool = False, pristine: Optional[Dict[int, object]] = None) -> Dict:
+        """Serve ``stream`` = [(arrival_s, job)].  ``pristine`` optionally maps
+        id(job) to a device tensor holding that job's initial memory; such a
+        request's memory is a device-to-device copy of it on the batch's
+        stream instead of an upload from the host."""
         import torch
         reqs = [Request(i, t, j, estimate_bytes(j)) for i, (t, j) in enumerate(stream)]
         pending = collections.deque(reqs)
@@ -173,9 +177,16 @@ class Server:
                 si = self.free_streams.pop()
                 st = self.streams[si]
                 with torch.cuda.stream(st):
-                    mems = [torch.from_numpy(np.ascontiguousarray(r.job.memory)).to("cuda", non_blocking=False)
-                            for r in batch]
-                st.synchronize()
+                    mems = []
+                    for r in batch:
+                        src = pristine.get(id(r.job)) if pristine else None
+                        if src is not None:
+                            mems.append(src.clone())
+                        else:
+                            mems.append(torch.from_numpy(np.ascontiguousarray(r.job.memory)).to(
+                                "cuda", non_blocking=False))
+                if not pristine:
+                    st.synchronize()
                 now = time.perf_counter() - t0
                 for r in batch:
                     r.admitted = now
@@ -192,7 +203,8 @@ class Server:
         out = {"requests": len(reqs), "records": records, "wall_s": wall,
                "records_per_s": records / wall if wall > 0 else 0.0,
                "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
-               "batches": busy_batches}
+               "batches": busy_batches,
+               "mean_batch": len(reqs) / busy_batches if busy_batches else 0.0}
         if keep_reports:
             out["reports"] = {r.rid: r.report for r in reqs}
         if keep_memory:

@@ -1,0 +1,110 @@
+"""Autotuner for the checker's launch parameters.
+
+The tunable options change how the work is laid out on the GPU, never what is
+computed: the sort tile (keys per radix-sort tile), the interpreter's LDS
+record staging (bytes per block and granule per wave) and whether shared
+accesses are checked per barrier epoch inside the interpreter.  The tuner
+runs a sample workload as one batch under each candidate setting (coordinate
+descent from the current setting, one option at a time), rejects any setting
+whose reports or final memories differ from those of the starting setting,
+and writes the fastest to a JSON cache, a flat object of option names and
+integers that ``kc_ctx_create`` applies when given the file.
+
+Timing is wall clock around submit + poll of the whole batch, with the
+memories restored from pristine device copies before each run (outside the
+timed region); the score of a setting is the median over ``reps`` runs.
+"""
+from __future__ import annotations
+
+import json
+import time
+from typing import Dict, List, Optional, Sequence
+
+import numpy as np
+
+from . import kc
+
+SPACE: Dict[str, Sequence[int]] = {
+    "sort_tile": (2048, 4096, 8192),
+    "stage_bytes": (8192, 16384, 32768, 65536),
+    "stage": (128, 256, 512),
+    "local": (0, 1),
+}
+
+
+def current(ctx: kc.Context) -> Dict[str, int]:
+    return {k: int(ctx.stat("option." + k)) for k in SPACE}
+
+
+def _signature(reports, mems) -> List[tuple]:
+    return [(r.records, tuple(r.race_tuples()), tuple(r.fault_tuples()), r.launches_completed,
+             m.cpu().numpy().tobytes()) for r, m in zip(reports, mems)]
+
+
+class _Runner:
+    def __init__(self, ctx: kc.Context, jobs):
+        import torch
+        self.torch = torch
+        self.ctx = ctx
+        dev = f"cuda:{ctx.device}"
+        self.pristine = [torch.from_numpy(np.ascontiguousarray(j.memory, dtype=np.int32)).to(dev) for j in jobs]
+        self.mems = [p.clone() for p in self.pristine]
+        self.batch = kc.Batch(ctx)
+        self.prep = self.batch.prepare([(kc.job_launches(ctx, j), m, i)
+                                        for i, (j, m) in enumerate(zip(jobs, self.mems))])
+
+    def run(self):
+        for m, p in zip(self.mems, self.pristine):
+            m.copy_(p)
+        self.torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = self.batch.poll(self.batch.submit(self.prep), wait=True)
+        self.torch.cuda.synchronize()
+        return time.perf_counter() - t0, reps
+
+
+def tune(ctx: kc.Context, jobs, path: Optional[str] = None, reps: int = 5, sweeps: int = 2,
+         space: Optional[Dict[str, Sequence[int]]] = None) -> Dict:
+    """Tune ``ctx``'s options on ``jobs``; leaves the best setting applied to
+    ``ctx`` and, if ``path`` is given, writes it there.  Returns the setting,
+    its median time, and every (setting, median seconds, identical) tried."""
+    space = space or SPACE
+    runner = _Runner(ctx, jobs)
+    best = current(ctx)
+
+    def measure(setting):
+        for k, v in setting.items():
+            ctx.set_option(k, v)
+        _, reports = runner.run()                      # warm-up (workspace growth, program upload)
+        times = []
+        for _ in range(reps):
+            dt, reports = runner.run()
+            times.append(dt)
+        return float(np.median(times)), _signature(reports, runner.mems)
+
+    base_t, ref = measure(best)
+    best_t = base_t
+    tried = [(dict(best), base_t, True)]
+    seen = {tuple(sorted(best.items()))}
+    for _ in range(sweeps):
+        improved = False
+        for key, values in space.items():
+            for v in values:
+                cand = dict(best, **{key: v})
+                tag = tuple(sorted(cand.items()))
+                if tag in seen:
+                    continue
+                seen.add(tag)
+                t, sig = measure(cand)
+                same = sig == ref
+                tried.append((cand, t, same))
+                if same and t < best_t:
+                    best, best_t, improved = cand, t, True
+        if not improved:
+            break
+    for k, v in best.items():
+        ctx.set_option(k, v)
+    if path:
+        with open(path, "w") as f:
+            json.dump(best, f, indent=1, sort_keys=True)
+    return {"setting": best, "seconds": best_t, "start_seconds": base_t, "tried": tried}

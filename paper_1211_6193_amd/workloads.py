@@ -472,3 +472,32 @@ def request_stream(rate: float, duration_s: float, seed: int = BASE_SEED + 5,
             job = mixed_instance(sub)
         yield t, job
         i += 1
+
+
+def request_pool(n_small: int = 2048, n_big: int = 8, big_blocks: int = 4096, seed: int = BASE_SEED + 5):
+    """Pre-generated instances for a served run: ``n_small`` workload-3
+    instances and ``n_big`` workload-2-shaped trees (``big_blocks`` x 256), each
+    from its own seed.  Requests draw from the pool (see pooled_requests), so a
+    high arrival rate needs no input generation while the clock runs."""
+    small = [mixed_instance(np.random.default_rng(np.random.SeedSequence([seed, 0, i]))) for i in range(n_small)]
+    big = [tree256_job(n_blocks=big_blocks,
+                       seed=int(np.random.default_rng(np.random.SeedSequence([seed, 1, i])).integers(0, 2**63 - 1)))
+           for i in range(n_big)]
+    return small, big
+
+
+def pooled_requests(rate: float, duration_s: float, small, big, big_p: float = 0.05,
+                    seed: int = BASE_SEED + 5):
+    """Poisson arrivals at ``rate``/s over ``duration_s``: a list of
+    (arrival_time_s, Job) where each request is a pool instance, a big tree
+    with probability ``big_p``, chosen uniformly by a seeded stream."""
+    rng = np.random.default_rng(np.random.SeedSequence([seed, 2, int(rate)]))
+    out, t = [], 0.0
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t >= duration_s:
+            return out
+        if big and rng.random() < big_p:
+            out.append((t, big[int(rng.integers(0, len(big)))]))
+        else:
+            out.append((t, small[int(rng.integers(0, len(small)))]))

@@ -181,3 +181,18 @@ def test_replay_paths(ctx):
         rep, mem = kc.run_job(ctx, job)
         assert_same(rep, mem, O.run_job(job), f"redirect {reads0}")
         assert ctx.stat("replays") >= 1
+
+
+def test_instruction_count_of_race_free_runs(ctx):
+    # A race-free free run executes the canonical per-thread traces, so the
+    # library's count of executed thread-instructions equals the oracle's.
+    rng = np.random.default_rng(7)
+    jobs = [W.family_job(f, 4, 96, rng) for f in ("TREE", "STENCIL", "TRANSPOSE")]
+    jobs.append(W.tree256_job(n_blocks=96, drop_frac=0.0, div_frac=0.0))
+    for job in jobs:
+        orc = O.run_job(job)
+        assert len(orc.races) == 0
+        ctx.reset_stats()
+        rep, mem = kc.run_job(ctx, job)
+        assert_same(rep, mem, orc, job.meta["family"])
+        assert int(ctx.stat("instructions")) == orc.instructions, job.meta["family"]

@@ -104,3 +104,21 @@ def test_special_registers_3d():
             ty, tx = divmod(rem, block[0])
             want = [tx, ty, tz, bx, by, bz, *block, *grid, tid, bid, nt, 32, *params]
             assert m[bid * nt + tid].tolist() == want
+
+
+def test_instruction_count_closed_form():
+    # thread t runs a 3-instruction loop t times: 2 set-up instructions, 3 per
+    # iteration and the final taken BZ, so 3 + 3t; the EXIT after the loop adds
+    # one more.  Sum over T threads and B blocks.  With fuel f < 4 + 3t a
+    # thread spends exactly f.
+    a = ir.Asm()
+    a.SREG(0, "TID").MOVI(1, 0).label("top").BZ(0, "end").ADDI(0, 0, -1).JMP("top").label("end").EXIT()
+    prog = np.array(a.assemble(), dtype=np.uint64)
+    B, T = 3, 37
+    job = Job([LaunchSpec(prog, (B, 1, 1), (T, 1, 1), 0, ())], np.zeros(1, np.int32))
+    r = O.run_job(job)
+    assert r.instructions == B * sum(4 + 3 * t for t in range(T))
+    fuel = 50
+    r = O.run_job(job, fuel=fuel)
+    assert r.instructions == B * sum(min(fuel, 4 + 3 * t) for t in range(T))
+    assert len(r.faults) == sum(1 for t in range(T) if 4 + 3 * t > fuel) * B
