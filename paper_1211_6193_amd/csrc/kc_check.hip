@@ -40,6 +40,16 @@ __device__ void push_edge(const CheckArgs &A, uint32_t unit, uint32_t b0, uint32
 
 constexpr int CHECK_ITEMS = 8;
 constexpr int CHECK_TILE = WG * CHECK_ITEMS;
+// A segment is reduced by its head thread up to this many records; a longer
+// one (a location touched by many threads or blocks) goes to k_check_long,
+// which reduces it with a whole workgroup.
+constexpr uint32_t SEG_LIMIT = 64;
+constexpr uint64_t LONG_CROSS = 1ull << 63;
+
+__device__ void push_long(const CheckArgs &A, uint64_t entry) {
+    const uint32_t idx = atomicAdd(&A.ctr->long_count, 1u);
+    A.longseg[idx] = entry;     // capacity: every long segment has more than SEG_LIMIT records
+}
 
 // One workgroup per tile of sorted records, staged in LDS; thread t owns the
 // records at t, t + WG, t + 2 WG, ... (conflict-free LDS reads) and reduces
@@ -76,15 +86,22 @@ __global__ void __launch_bounds__(WG) k_check(CheckArgs A) {
         if (head_in) {
             // intra-block segment: smallest writer and two smallest distinct tids
             uint32_t minw = NONE, t1 = NONE, t2 = NONE;
+            bool is_long = false;
             for (uint64_t j = i; j < A.n; j++) {
                 const uint64_t kj = key_at(j);
                 if ((kj >> ps) != inner) break;
+                if (j - i == SEG_LIMIT) {
+                    is_long = true;
+                    break;
+                }
                 const uint32_t tid = rec_field(kj, k.s_tid, k.tb);
                 if (kj & 1ull) minw = min(minw, tid);
                 if (tid < t1) { t2 = t1; t1 = tid; }
                 else if (tid != t1 && tid < t2) t2 = tid;
             }
-            if (minw != NONE && t2 != NONE) {
+            if (is_long) {
+                push_long(A, i);
+            } else if (minw != NONE && t2 != NONE) {
                 DevRace r;
                 r.unit = unit; r.space = space; r.scope = 0; r.block = block0;
                 r.epoch = rec_field(ki, k.s_ep, k.eb); r.addr = addr;
@@ -99,9 +116,14 @@ __global__ void __launch_bounds__(WG) k_check(CheckArgs A) {
             const uint32_t nt = A.units[unit].nt;
             uint32_t wg = NONE, wb = NONE, g1 = NONE, b1 = NONE, g2 = NONE;
             uint64_t end = i;
+            bool is_long = false;
             for (uint64_t j = i; j < A.n; j++) {
                 const uint64_t kj = key_at(j);
                 if ((kj >> k.s_addr) != outer) break;
+                if (j - i == SEG_LIMIT) {
+                    is_long = true;
+                    break;
+                }
                 end = j + 1;
                 const uint32_t b = rec_field(kj, k.s_blk, k.bb);
                 const uint32_t g = b * nt + rec_field(kj, k.s_tid, k.tb);
@@ -113,7 +135,9 @@ __global__ void __launch_bounds__(WG) k_check(CheckArgs A) {
                     g2 = g;
                 }
             }
-            if (wg != NONE && g2 != NONE) {
+            if (is_long) {
+                push_long(A, i | LONG_CROSS);
+            } else if (wg != NONE && g2 != NONE) {
                 DevRace r;
                 r.unit = unit; r.space = 1; r.scope = 1; r.block = wb; r.epoch = NONE; r.addr = addr;
                 r.w = wg; r.o = (wb == b1) ? g2 : g1;
@@ -130,6 +154,124 @@ __global__ void __launch_bounds__(WG) k_check(CheckArgs A) {
                 }
             }
         }
+    }
+}
+
+// Reduction states of a segment (merged associatively, in any order).
+// Intra-block: smallest writer tid and the two smallest distinct tids.
+struct IntraState { uint32_t minw, t1, t2; };
+// Cross-block: smallest writer gtid (and its block), smallest gtid g1 (block b1)
+// and the smallest gtid g2 of a block other than b1.
+struct CrossState { uint32_t wg, wb, g1, b1, g2; };
+
+__device__ __forceinline__ void insert2(uint32_t &a1, uint32_t &a2, uint32_t x) {
+    if (x < a1) { a2 = a1; a1 = x; }
+    else if (x != a1 && x < a2) a2 = x;
+}
+__device__ __forceinline__ IntraState merge(IntraState a, const IntraState &b) {
+    a.minw = min(a.minw, b.minw);
+    insert2(a.t1, a.t2, b.t1);
+    insert2(a.t1, a.t2, b.t2);
+    return a;
+}
+__device__ __forceinline__ CrossState merge(CrossState a, CrossState b) {
+    if (b.wg < a.wg) { a.wg = b.wg; a.wb = b.wb; }
+    if (b.g1 < a.g1) {      // b holds the overall minimum
+        const uint32_t wg = a.wg, wb = a.wb;
+        CrossState t = a; a = b; b = t;
+        a.wg = wg; a.wb = wb;
+    }
+    a.g2 = min(a.g2, b.b1 != a.b1 ? b.g1 : b.g2);
+    return a;
+}
+
+// One workgroup per long segment (grid-stride over the list k_check wrote):
+// the threads reduce interleaved records, then a tree reduction in LDS; a
+// racy cross-block segment is walked again to flag its blocks and link them.
+__global__ void __launch_bounds__(WG) k_check_long(CheckArgs A) {
+    __shared__ CrossState cs[WG];
+    __shared__ IntraState is[WG];
+    __shared__ uint32_t racy;
+    const KeyPlan &k = A.kp;
+    const uint32_t cnt = __hip_atomic_load(&A.ctr->long_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (uint32_t e = blockIdx.x; e < cnt; e += gridDim.x) {
+        const uint64_t ent = A.longseg[e];
+        const bool cross = (ent & LONG_CROSS) != 0;
+        const uint64_t i = ent & ~LONG_CROSS;
+        const uint64_t ki = A.keys[i];
+        const uint32_t shift = cross ? k.s_addr : k.s_ep;
+        const uint64_t tag = ki >> shift;
+        const uint32_t unit = rec_field(ki, k.s_unit, k.ub);
+        const uint32_t nt = A.units[unit].nt;
+        IntraState a{NONE, NONE, NONE};
+        CrossState c{NONE, NONE, NONE, NONE, NONE};
+        for (uint64_t base = i;; base += WG) {
+            const uint64_t j = base + threadIdx.x;
+            const uint64_t kj = j < A.n ? A.keys[j] : 0ull;
+            const bool in = j < A.n && (kj >> shift) == tag;
+            if (in) {
+                const uint32_t tid = rec_field(kj, k.s_tid, k.tb);
+                if (cross) {
+                    const uint32_t b = rec_field(kj, k.s_blk, k.bb);
+                    const uint32_t g = b * nt + tid;
+                    c = merge(c, CrossState{(kj & 1ull) ? g : NONE, (kj & 1ull) ? b : NONE, g, b, NONE});
+                } else {
+                    a = merge(a, IntraState{(kj & 1ull) ? tid : NONE, tid, NONE});
+                }
+            }
+            if (__syncthreads_or(!in)) break;       // sorted: the segment ended in this chunk
+        }
+        cs[threadIdx.x] = c;
+        is[threadIdx.x] = a;
+        __syncthreads();
+        for (uint32_t h = WG / 2; h > 0; h >>= 1) {
+            if (threadIdx.x < h) {
+                cs[threadIdx.x] = merge(cs[threadIdx.x], cs[threadIdx.x + h]);
+                is[threadIdx.x] = merge(is[threadIdx.x], is[threadIdx.x + h]);
+            }
+            __syncthreads();
+        }
+        const uint32_t block0 = rec_field(ki, k.s_blk, k.bb);
+        if (threadIdx.x == 0) {
+            racy = 0;
+            DevRace r;
+            r.unit = unit; r.space = rec_field(ki, k.s_sp, 1); r.addr = rec_field(ki, k.s_addr, k.ab);
+            if (cross) {
+                const CrossState f = cs[0];
+                if (f.wg != NONE && f.g2 != NONE) {
+                    r.scope = 1; r.block = f.wb; r.epoch = NONE;
+                    r.w = f.wg; r.o = (f.wb == f.b1) ? f.g2 : f.g1;
+                    push_race(A, r);
+                    racy = 1;
+                }
+            } else {
+                const IntraState f = is[0];
+                if (f.minw != NONE && f.t2 != NONE) {
+                    r.scope = 0; r.block = block0; r.epoch = rec_field(ki, k.s_ep, k.eb);
+                    r.w = f.minw; r.o = (f.t1 == f.minw) ? f.t2 : f.t1;
+                    push_race(A, r);
+                    A.blk_flags[A.units[unit].block_base + block0] = 1u;
+                }
+            }
+        }
+        __syncthreads();
+        if (racy) {             // every block touching the location joins the racy component
+            for (uint64_t base = i;; base += WG) {
+                const uint64_t j = base + threadIdx.x;
+                const uint64_t kj = j < A.n ? A.keys[j] : 0ull;
+                const bool in = j < A.n && (kj >> shift) == tag;
+                if (in) {
+                    const uint32_t b = rec_field(kj, k.s_blk, k.bb);
+                    const bool first = j == i || rec_field(A.keys[j - 1], k.s_blk, k.bb) != b;
+                    if (first) {
+                        A.blk_flags[A.units[unit].block_base + b] = 1u;
+                        if (b != block0) push_edge(A, unit, block0, b);
+                    }
+                }
+                if (__syncthreads_or(!in)) break;
+            }
+        }
+        __syncthreads();        // LDS states are reused by the next segment
     }
 }
 
@@ -151,11 +293,27 @@ __global__ void __launch_bounds__(WG) k_restore(const uint64_t *__restrict__ key
 // a replayed block (its canonical records `rs`, sorted) and by a block that was
 // not replayed (free-run records in `log`, sorted, with blk_flags == 0) unless
 // both only read it.  The first replayed record of each location looks up the
-// location's records in the free-run log by binary search.
+// location's records in the free-run log by binary search and scans them; a
+// location with more than COV_LIMIT records on either side is listed for
+// k_coverage_long instead.
+constexpr uint32_t COV_LIMIT = 32;
+
+__device__ __forceinline__ uint64_t lower_bound_loc(const uint64_t *__restrict__ log, uint64_t n_log, uint64_t target,
+                                                    uint32_t shift) {
+    uint64_t lo = 0, hi = n_log;
+    while (lo < hi) {
+        const uint64_t mid = (lo + hi) / 2;
+        if ((log[mid] >> shift) < target) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
 __global__ void __launch_bounds__(WG) k_coverage(const uint64_t *__restrict__ rs, uint64_t n_rs,
                                                  const uint64_t *__restrict__ log, uint64_t n_log, KeyPlan k,
                                                  const DevUnit *__restrict__ units,
-                                                 const uint32_t *__restrict__ blk_flags, uint32_t *__restrict__ flags) {
+                                                 const uint32_t *__restrict__ blk_flags, DevCounters *ctr,
+                                                 uint64_t *__restrict__ list) {
     const uint64_t i = (uint64_t)blockIdx.x * WG + threadIdx.x;
     if (i >= n_rs) return;
     const uint64_t r = rs[i];
@@ -163,21 +321,61 @@ __global__ void __launch_bounds__(WG) k_coverage(const uint64_t *__restrict__ rs
     const uint64_t target = r >> k.s_addr;
     if (i > 0 && (rs[i - 1] >> k.s_addr) == target) return;
     bool r_w = false;
-    for (uint64_t j = i; j < n_rs && (rs[j] >> k.s_addr) == target; j++) r_w |= (rs[j] & 1ull) != 0;
-    uint64_t lo = 0, hi = n_log;
-    while (lo < hi) {
-        const uint64_t mid = (lo + hi) / 2;
-        if ((log[mid] >> k.s_addr) < target) lo = mid + 1;
-        else hi = mid;
+    for (uint64_t j = i; j < n_rs && (rs[j] >> k.s_addr) == target; j++) {
+        if (j - i == COV_LIMIT) {
+            list[atomicAdd(&ctr->long_count, 1u)] = i;
+            return;
+        }
+        r_w |= (rs[j] & 1ull) != 0;
     }
+    const uint64_t lo = lower_bound_loc(log, n_log, target, k.s_addr);
     const DevUnit &u = units[rec_field(r, k.s_unit, k.ub)];
     for (uint64_t j = lo; j < n_log; j++) {
         const uint64_t x = log[j];
         if ((x >> k.s_addr) != target) break;
+        if (j - lo == COV_LIMIT) {
+            list[atomicAdd(&ctr->long_count, 1u)] = i;
+            return;
+        }
         if (blk_flags[u.block_base + rec_field(x, k.s_blk, k.bb)]) continue;    // replayed block
         if (r_w || (x & 1ull)) {
-            atomicOr(flags, FLAG_MISMATCH);
+            atomicOr(&ctr->flags, FLAG_MISMATCH);
             return;
+        }
+    }
+}
+
+// The listed locations, one workgroup each (grid-stride over the list).
+__global__ void __launch_bounds__(WG) k_coverage_long(const uint64_t *__restrict__ rs, uint64_t n_rs,
+                                                      const uint64_t *__restrict__ log, uint64_t n_log, KeyPlan k,
+                                                      const DevUnit *__restrict__ units,
+                                                      const uint32_t *__restrict__ blk_flags, DevCounters *ctr,
+                                                      const uint64_t *__restrict__ list) {
+    __shared__ uint64_t lo_sh;
+    const uint32_t cnt = __hip_atomic_load(&ctr->long_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (uint32_t e = blockIdx.x; e < cnt; e += gridDim.x) {
+        const uint64_t i = list[e];
+        const uint64_t r = rs[i];
+        const uint64_t target = r >> k.s_addr;
+        const DevUnit &u = units[rec_field(r, k.s_unit, k.ub)];
+        int r_w = 0;
+        for (uint64_t base = i;; base += WG) {
+            const uint64_t j = base + threadIdx.x;
+            const bool in = j < n_rs && (rs[j] >> k.s_addr) == target;
+            const int w = __syncthreads_or(in && (rs[j] & 1ull));
+            r_w |= w;
+            if (__syncthreads_or(!in)) break;
+        }
+        if (threadIdx.x == 0) lo_sh = lower_bound_loc(log, n_log, target, k.s_addr);
+        __syncthreads();
+        const uint64_t lo = lo_sh;
+        for (uint64_t base = lo;; base += WG) {
+            const uint64_t j = base + threadIdx.x;
+            const uint64_t x = j < n_log ? log[j] : 0ull;
+            const bool in = j < n_log && (x >> k.s_addr) == target;
+            if (in && !blk_flags[u.block_base + rec_field(x, k.s_blk, k.bb)] && (r_w || (x & 1ull)))
+                atomicOr(&ctr->flags, FLAG_MISMATCH);
+            if (__syncthreads_or(!in)) break;
         }
     }
 }
@@ -204,9 +402,17 @@ inline uint32_t blocks_for(uint64_t n) { return (uint32_t)((n + WG - 1) / WG); }
 
 }  // namespace
 
+size_t check_long_cap(uint64_t n) { return (size_t)(2 * (n / SEG_LIMIT) + 2); }
+
 hipError_t launch_check(const CheckArgs &a, hipStream_t s) {
     if (a.n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_check, dim3((uint32_t)((a.n + CHECK_TILE - 1) / CHECK_TILE)), dim3(WG), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // long segments: the list length is on the device; enough workgroups for
+    // any list this check can produce, each striding over the list
+    const uint32_t g = (uint32_t)std::min<uint64_t>(1024, check_long_cap(a.n));
+    hipLaunchKernelGGL(k_check_long, dim3(g), dim3(WG), 0, s, a);
     return hipGetLastError();
 }
 
@@ -218,10 +424,16 @@ hipError_t launch_restore(const uint64_t *keys, uint64_t n, KeyPlan kp, const De
 }
 
 hipError_t launch_coverage(const uint64_t *rs, uint64_t n_rs, const uint64_t *log, uint64_t n_log, KeyPlan kp,
-                           const DevUnit *units, const uint32_t *blk_flags, uint32_t *flags, hipStream_t s) {
+                           const DevUnit *units, const uint32_t *blk_flags, DevCounters *ctr, uint64_t *list,
+                           hipStream_t s) {
     if (n_rs == 0) return hipSuccess;
     hipLaunchKernelGGL(k_coverage, dim3(blocks_for(n_rs)), dim3(WG), 0, s, rs, n_rs, log, n_log, kp, units, blk_flags,
-                       flags);
+                       ctr, list);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const uint32_t g = (uint32_t)std::min<uint64_t>(256, n_rs);
+    hipLaunchKernelGGL(k_coverage_long, dim3(g), dim3(WG), 0, s, rs, n_rs, log, n_log, kp, units, blk_flags, ctr,
+                       list);
     return hipGetLastError();
 }
 

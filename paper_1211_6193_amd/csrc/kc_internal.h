@@ -83,7 +83,8 @@ struct DevCounters {
     uint32_t max_epoch;
     uint32_t pad0;
     unsigned long long instructions;   // thread-instructions of the free run
-    uint32_t pad[6];
+    uint32_t long_count;               // segments left to the long-segment pass of the check
+    uint32_t pad[5];
 };
 
 struct InterpArgs {
@@ -117,8 +118,8 @@ size_t interp_lds_bytes(uint32_t sh_words_max, uint32_t wg_threads, uint32_t sta
 
 struct SortScratch {
     uint64_t *alt = nullptr;         // ping-pong buffer, >= n keys
-    uint32_t *hist = nullptr;        // n_tiles * 256
-    uint32_t *part = nullptr;        // chunk partials
+    uint32_t *hist = nullptr;        // 256 * n_tiles, digit-major
+    uint32_t *part = nullptr;        // 256 digit totals
     size_t cap_keys = 0, cap_hist = 0, cap_part = 0;
 };
 // Virtual sort key of a record: the bits from s_blk up, then the low ueb bits
@@ -143,12 +144,17 @@ struct CheckArgs {
     uint32_t edge_cap;
     uint32_t *blk_flags;
     DevCounters *ctr;
+    uint64_t *longseg;          // scratch: segments longer than the serial limit, check_long_cap(n) entries
 };
+size_t check_long_cap(uint64_t n);
 hipError_t launch_check(const CheckArgs &a, hipStream_t s);
 hipError_t launch_restore(const uint64_t *keys, uint64_t n, KeyPlan kp, const DevUnit *units,
                           const uint32_t *blk_flags, hipStream_t s);
+// Exactness of a replay; sets FLAG_MISMATCH in ctr->flags.  ctr->long_count
+// must be zero; `list` holds n_rs entries.
 hipError_t launch_coverage(const uint64_t *rs, uint64_t n_rs, const uint64_t *log, uint64_t n_log, KeyPlan kp,
-                           const DevUnit *units, const uint32_t *blk_flags, uint32_t *flags, hipStream_t s);
+                           const DevUnit *units, const uint32_t *blk_flags, DevCounters *ctr, uint64_t *list,
+                           hipStream_t s);
 hipError_t launch_copy_units(const DevUnit *units, uint32_t n_units, uint32_t max_words, bool to_snapshot,
                              const uint32_t *unit_mask, hipStream_t s);
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);

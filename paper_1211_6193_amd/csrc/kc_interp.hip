@@ -325,6 +325,43 @@ __device__ __forceinline__ void push_local_race(const InterpArgs &A, const Block
     A.blk_flags[B.u->block_base + B.block] = 1u;
 }
 
+// Reduction state of the accesses to one location in one epoch: smallest
+// writer tid and the two smallest distinct tids (merged in any order).
+struct SegState { uint32_t minw, t1, t2; };
+constexpr uint32_t LOCAL_SEG_LIMIT = 16;
+
+__device__ __forceinline__ void seg_insert(SegState &s, uint32_t x) {
+    if (x < s.t1) { s.t2 = s.t1; s.t1 = x; }
+    else if (x != s.t1 && x < s.t2) s.t2 = x;
+}
+__device__ __forceinline__ void seg_add(SegState &s, uint32_t tid, bool write) {
+    if (write) s.minw = min(s.minw, tid);
+    seg_insert(s, tid);
+}
+__device__ __forceinline__ void seg_merge(SegState &s, const SegState &o) {
+    s.minw = min(s.minw, o.minw);
+    seg_insert(s, o.t1);
+    seg_insert(s, o.t2);
+}
+
+// A reduced segment whose first record is `r`: its race, and for global
+// memory its representatives (the smallest tid, a write if that thread wrote,
+// and the smallest writer when it is another thread) with the reserved epoch.
+__device__ __forceinline__ void local_segment_done(const InterpArgs &A, const BlockCtx &B, const Shared &S,
+                                                   uint64_t r, uint32_t epoch, const SegState &st, uint64_t *dst) {
+    const KeyPlan &k = A.kp;
+    const uint32_t space = rec_field(r, k.s_sp, 1);
+    if (st.minw != NONE_U32 && st.t2 != NONE_U32)
+        push_local_race(A, B, space, epoch, rec_field(r, k.s_addr, k.ab), st.minw, st.t1 == st.minw ? st.t2 : st.t1);
+    if (space != 1u) return;
+    const uint64_t keep = ~(((((1ull << k.tb) - 1ull) << k.s_tid)) | (((1ull << k.eb) - 1ull) << k.s_ep) | 1ull);
+    const uint64_t base = (r & keep) | ((uint64_t)k.ep_rep << k.s_ep);
+    const bool two = st.minw != NONE_U32 && st.minw != st.t1;
+    const uint32_t at = atomicAdd(&S.tmp[32], two ? 2u : 1u);
+    dst[at] = base | ((uint64_t)st.t1 << k.s_tid) | (st.minw == st.t1 ? 1ull : 0ull);
+    if (two) dst[at + 1] = base | ((uint64_t)st.minw << k.s_tid) | 1ull;
+}
+
 __device__ __forceinline__ void epoch_local_check(const InterpArgs &A, const BlockCtx &B, const Shared &S,
                                                   LogState &L, uint32_t epoch) {
     const KeyPlan &k = A.kp;
@@ -360,42 +397,57 @@ __device__ __forceinline__ void epoch_local_check(const InterpArgs &A, const Blo
             local_sort_pass(S, B, k, src, dst, n, shift);
             uint64_t *t = src; src = dst; dst = t;
         }
-        const uint64_t ep_mask = ((1ull << k.eb) - 1ull) << k.s_ep;
-        const uint64_t rep_ep = (uint64_t)k.ep_rep << k.s_ep;
+        // Segments (one location) of the sorted epoch: the head thread reduces
+        // up to LOCAL_SEG_LIMIT records; longer segments (a location touched
+        // by many threads) are listed and reduced by whole waves.
         // Representatives are compacted into dst (a segment yields no more
         // representatives than records, so n entries suffice) and reserved in
         // the log with one atomic per block: a single global counter serves
         // every block of the launch.
-        if (threadIdx.x == 0) S.tmp[32] = 0;
+        if (threadIdx.x == 0) {
+            S.tmp[32] = 0;      // representatives in dst
+            S.tmp[35] = 0;      // long segments listed in wc
+        }
         __syncthreads();
         for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
             const uint64_t r = src[i];
             const uint32_t lk = local_key(r, k);
-            const bool head = i == 0 || local_key(src[i - 1], k) != lk;
-            uint32_t minw = NONE_U32, t1 = NONE_U32, t2 = NONE_U32, i1 = i, iw = i;
-            bool w1 = false;
-            if (head) {
-                for (uint32_t j = i; j < n; j++) {
-                    const uint64_t x = src[j];
-                    if (local_key(x, k) != lk) break;
-                    const uint32_t tid = rec_field(x, k.s_tid, k.tb);
-                    const bool wr = (x & 1ull) != 0;
-                    if (wr && tid < minw) { minw = tid; iw = j; }
-                    if (tid < t1) { t2 = t1; t1 = tid; i1 = j; w1 = wr; }
-                    else if (tid != t1 && tid < t2) t2 = tid;
-                    else if (tid == t1 && wr) { w1 = true; i1 = j; }
+            if (i != 0 && local_key(src[i - 1], k) == lk) continue;
+            SegState st{NONE_U32, NONE_U32, NONE_U32};
+            bool is_long = false;
+            for (uint32_t j = i; j < n; j++) {
+                const uint64_t x = src[j];
+                if (local_key(x, k) != lk) break;
+                if (j - i == LOCAL_SEG_LIMIT) {
+                    is_long = true;
+                    break;
                 }
-                if (minw != NONE_U32 && t2 != NONE_U32)
-                    push_local_race(A, B, rec_field(r, k.s_sp, 1), epoch, rec_field(r, k.s_addr, k.ab), minw,
-                                    t1 == minw ? t2 : t1);
+                seg_add(st, rec_field(x, k.s_tid, k.tb), (x & 1ull) != 0);
             }
-            const bool glob = head && rec_field(r, k.s_sp, 1) == 1u;
-            const bool two = glob && minw != NONE_U32 && !(w1 && t1 == minw);
-            if (glob) {
-                const uint32_t at = atomicAdd(&S.tmp[32], two ? 2u : 1u);
-                dst[at] = (src[i1] & ~ep_mask) | rep_ep;
-                if (two) dst[at + 1] = (src[iw] & ~ep_mask) | rep_ep;
+            if (is_long) S.wc[atomicAdd(&S.tmp[35], 1u)] = i;
+            else local_segment_done(A, B, S, r, epoch, st, dst);
+        }
+        __syncthreads();
+        const uint32_t nlong = S.tmp[35];
+        for (uint32_t e = B.wave; e < nlong; e += B.nwaves) {
+            const uint32_t i = S.wc[e];
+            const uint64_t r = src[i];
+            const uint32_t lk = local_key(r, k);
+            SegState st{NONE_U32, NONE_U32, NONE_U32};
+            for (uint32_t base = i;; base += WAVE) {
+                const uint32_t j = base + lane_id();
+                const uint64_t x = j < n ? src[j] : 0ull;
+                const bool in = j < n && local_key(x, k) == lk;
+                if (in) seg_add(st, rec_field(x, k.s_tid, k.tb), (x & 1ull) != 0);
+                if (__ballot(!in)) break;           // sorted: the segment ended in this chunk
             }
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                const SegState y{(uint32_t)__shfl_xor((int)st.minw, o), (uint32_t)__shfl_xor((int)st.t1, o),
+                                 (uint32_t)__shfl_xor((int)st.t2, o)};
+                seg_merge(st, y);
+            }
+            if (lane_id() == 0) local_segment_done(A, B, S, r, epoch, st, dst);
         }
         __syncthreads();
         const uint32_t nrep = S.tmp[32];

@@ -106,6 +106,7 @@ struct Workspace {
     DBuf units, items, comp_off, comp_blocks, mask;
     DBuf snap, log, alt, rlog, ralt, fs, hist, part;
     DBuf faults, rfaults, races, lraces, rlraces, edges, blk_recs, rblk_recs, blk_flags, rflags, ctr, rctr;
+    DBuf longseg;
     DevCounters *h_ctr = nullptr;   // pinned
     hipEvent_t ev[12] = {};
     bool init = false;
@@ -118,7 +119,7 @@ struct Workspace {
     size_t device_bytes() const {
         const DBuf *all[] = {&units, &items, &comp_off, &comp_blocks, &mask, &snap, &log, &alt, &rlog,
                              &ralt, &fs, &hist, &part, &faults, &rfaults, &races, &edges, &blk_recs,
-                             &rblk_recs, &blk_flags, &rflags, &ctr, &rctr, &lraces, &rlraces};
+                             &rblk_recs, &blk_flags, &rflags, &ctr, &rctr, &lraces, &rlraces, &longseg};
         size_t s = 0;
         for (auto *b : all) s += b->bytes;
         return s;
@@ -126,7 +127,7 @@ struct Workspace {
     ~Workspace() {
         DBuf *all[] = {&units, &items, &comp_off, &comp_blocks, &mask, &snap, &log, &alt, &rlog,
                        &ralt, &fs, &hist, &part, &faults, &rfaults, &races, &edges, &blk_recs,
-                       &rblk_recs, &blk_flags, &rflags, &ctr, &rctr, &lraces, &rlraces};
+                       &rblk_recs, &blk_flags, &rflags, &ctr, &rctr, &lraces, &rlraces, &longseg};
         for (auto *b : all) b->release();
         if (h_ctr) (void)hipHostFree(h_ctr);
         for (auto &e : ev)
@@ -613,7 +614,7 @@ struct Stage {
         SortScratch sc;
         alt.reserve(n * 8);
         ws.hist.reserve(radix_hist_entries(n, ctx->opt.sort_tile) * 4);
-        ws.part.reserve((radix_hist_entries(n, ctx->opt.sort_tile) / 256 / 32 + 2) * 256 * 4);
+        ws.part.reserve(256 * 4);
         sc.alt = alt.as<uint64_t>();
         sc.hist = ws.hist.as<uint32_t>();
         sc.part = ws.part.as<uint32_t>();
@@ -627,6 +628,7 @@ struct Stage {
                    std::vector<DevEdge> &edges, bool zero_flags = true) {
         uint32_t race_cap = 4096, edge_cap = 4096;
         flags.reserve((size_t)std::max<uint32_t>(total_blocks, 1) * 4);
+        ws.longseg.reserve(check_long_cap(n) * 8);
         for (;;) {
             ws.races.reserve((size_t)race_cap * sizeof(DevRace));
             ws.edges.reserve((size_t)edge_cap * sizeof(DevEdge));
@@ -643,6 +645,7 @@ struct Stage {
             ca.edge_cap = edge_cap;
             ca.blk_flags = flags.as<uint32_t>();
             ca.ctr = ws.rctr.as<DevCounters>();
+            ca.longseg = ws.longseg.as<uint64_t>();
             HIPCHK(launch_check(ca, s));
             DevCounters rc = read_ctr(ws.rctr);
             if (rc.flags & (FLAG_RACE_OVERFLOW | FLAG_EDGE_OVERFLOW)) {
@@ -747,8 +750,10 @@ struct Stage {
             ctx->stat_add("replay_sort_ms", tm.ms(7, 8));
             ctx->stat_add("replay_check_ms", tm.ms(8, 9));
             reset_counters(ws.ctr);
+            ws.longseg.reserve((size_t)rc.log_count * 8);
             HIPCHK(launch_coverage(rs, rc.log_count, sorted, nrec, kp, ws.units.as<DevUnit>(),
-                                   ws.blk_flags.as<uint32_t>(), &ws.ctr.as<DevCounters>()->flags, s));
+                                   ws.blk_flags.as<uint32_t>(), ws.ctr.as<DevCounters>(),
+                                   ws.longseg.as<uint64_t>(), s));
             ok = !(read_ctr(ws.ctr).flags & FLAG_MISMATCH);
             tm.mark(10);
             ctx->stat_add("replay_coverage_ms", tm.ms(9, 10));

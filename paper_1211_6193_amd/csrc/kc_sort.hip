@@ -1,14 +1,17 @@
 // LDS-staged LSD radix sort of 64-bit access records on gfx950.
 //
-// One pass per 8-bit digit over the requested bit range:
-//   k_rs_hist     per-tile digit histograms (tile-major [tile][256])
-//   k_rs_colsum   per-chunk column sums   -> part[chunk][256]
-//   k_rs_top      exclusive scan over chunks and digits (one workgroup)
-//   k_rs_apply    turns histograms into global start offsets per (tile, digit)
-//   k_rs_scatter  stable rank inside the tile (wave-level 8-ballot digit match),
-//                 reorder the tile in LDS, write each digit's run contiguously.
+// Large inputs: one pass per 8-bit digit over the requested bit range, three
+// kernels per pass:
+//   k_rs_hist     per-tile digit histograms, digit-major ([digit][tile])
+//   k_rs_scan     one workgroup per digit: exclusive scan of the digit's
+//                 column over the tiles, and the digit's total
+//   k_rs_scatter  digit bases (scan of the 256 totals), stable rank inside the
+//                 tile (wave-level 8-ballot digit match), reorder the tile in
+//                 LDS, write each digit's run contiguously.
 // A tile is 4 waves x 64 lanes x ITEMS keys; wave w owns a contiguous quarter
 // of the tile so ranks need no cross-wave synchronisation until the end.
+// Small inputs (a replay's records): k_rs_small sorts in one workgroup of 16
+// waves, all passes in one launch, ping-ponging between the two buffers.
 #include "kc_internal.h"
 
 namespace kc {
@@ -18,7 +21,6 @@ namespace {
 constexpr int WAVE = 64;
 constexpr int WG = 256;
 constexpr int NW = WG / WAVE;
-constexpr int CHUNK = 32;      // tiles per column-scan chunk
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
@@ -53,17 +55,8 @@ __global__ void __launch_bounds__(WG) k_rs_hist(const uint64_t *__restrict__ key
         uint32_t s = 0;
 #pragma unroll
         for (int q = 0; q < NW; q++) s += h[q][d];
-        hist[(size_t)blockIdx.x * 256 + d] = s;
+        hist[(size_t)d * gridDim.x + blockIdx.x] = s;
     }
-}
-
-__global__ void __launch_bounds__(WG) k_rs_colsum(const uint32_t *__restrict__ hist, uint32_t n_tiles,
-                                                  uint32_t *__restrict__ part) {
-    const uint32_t d = threadIdx.x;
-    const uint32_t t0 = blockIdx.x * CHUNK, t1 = min(t0 + CHUNK, n_tiles);
-    uint32_t s = 0;
-    for (uint32_t t = t0; t < t1; t++) s += hist[(size_t)t * 256 + d];
-    part[(size_t)blockIdx.x * 256 + d] = s;
 }
 
 // Block-wide exclusive scan of one value per thread (256 threads).
@@ -84,48 +77,31 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *t
     return x - v;
 }
 
-// Column scan of one digit (blockIdx.x) over the chunk partials:
-// part[c][d] becomes the exclusive start of chunk c within digit d, and
-// tot[d] the digit's total.
-__global__ void __launch_bounds__(WG) k_rs_top(uint32_t *__restrict__ part, uint32_t n_chunks,
-                                               uint32_t *__restrict__ tot) {
+// Column scan of one digit (blockIdx.x): hist[d][t] becomes the exclusive
+// start of tile t within digit d, tot[d] the digit's total.
+__global__ void __launch_bounds__(WG) k_rs_scan(uint32_t *__restrict__ hist, uint32_t n_tiles,
+                                                uint32_t *__restrict__ tot) {
     __shared__ uint32_t tmp[WG];
-    const uint32_t d = blockIdx.x;
-    const uint32_t per = (n_chunks + WG - 1) / WG;
-    const uint32_t c0 = threadIdx.x * per, c1 = min(c0 + per, n_chunks);
+    uint32_t *col = hist + (size_t)blockIdx.x * n_tiles;
+    const uint32_t per = (n_tiles + WG - 1) / WG;
+    const uint32_t c0 = min(n_tiles, threadIdx.x * per), c1 = min(c0 + per, n_tiles);
     uint32_t sum = 0;
-    for (uint32_t c = c0; c < c1; c++) sum += part[(size_t)c * 256 + d];
+    for (uint32_t c = c0; c < c1; c++) sum += col[c];
     uint32_t total;
     uint32_t run = block_exclusive_scan(sum, tmp, total);
     for (uint32_t c = c0; c < c1; c++) {
-        const uint32_t v = part[(size_t)c * 256 + d];
-        part[(size_t)c * 256 + d] = run;
+        const uint32_t v = col[c];
+        col[c] = run;
         run += v;
     }
-    if (threadIdx.x == 0) tot[d] = total;
-}
-
-// Per-tile global start offsets: digit base + chunk start + tiles before.
-__global__ void __launch_bounds__(WG) k_rs_apply(uint32_t *__restrict__ hist, uint32_t n_tiles,
-                                                 const uint32_t *__restrict__ part,
-                                                 const uint32_t *__restrict__ tot) {
-    __shared__ uint32_t tmp[WG];
-    const uint32_t d = threadIdx.x;
-    uint32_t all;
-    const uint32_t base = block_exclusive_scan(tot[d], tmp, all);
-    const uint32_t t0 = blockIdx.x * CHUNK, t1 = min(t0 + CHUNK, n_tiles);
-    uint32_t run = base + part[(size_t)blockIdx.x * 256 + d];
-    for (uint32_t t = t0; t < t1; t++) {
-        const uint32_t v = hist[(size_t)t * 256 + d];
-        hist[(size_t)t * 256 + d] = run;
-        run += v;
-    }
+    if (threadIdx.x == 0) tot[blockIdx.x] = total;
 }
 
 template <int ITEMS>
 __global__ void __launch_bounds__(WG) k_rs_scatter(const uint64_t *__restrict__ in, uint64_t *__restrict__ out,
                                                    uint64_t n, VKey vk, uint32_t shift, uint32_t bits,
-                                                   const uint32_t *__restrict__ offs) {
+                                                   const uint32_t *__restrict__ offs,
+                                                   const uint32_t *__restrict__ tot) {
     constexpr int TILE = WG * ITEMS;
     __shared__ uint64_t buf[TILE];
     __shared__ uint32_t wc[NW][256];
@@ -134,7 +110,12 @@ __global__ void __launch_bounds__(WG) k_rs_scatter(const uint64_t *__restrict__ 
     const uint32_t w = threadIdx.x / WAVE;
     const uint32_t lane = lane_id();
     for (int i = threadIdx.x; i < NW * 256; i += WG) (&wc[0][0])[i] = 0;
-    for (int d = threadIdx.x; d < 256; d += WG) goff[d] = offs[(size_t)blockIdx.x * 256 + d];
+    {   // global start of each digit's run of this tile: digit base + tiles before
+        const uint32_t d = threadIdx.x;
+        uint32_t all;
+        const uint32_t base = block_exclusive_scan(tot[d], tstart, all);
+        goff[d] = base + offs[(size_t)d * gridDim.x + blockIdx.x];
+    }
     __syncthreads();
 
     const uint64_t tile0 = (uint64_t)blockIdx.x * TILE;
@@ -212,20 +193,104 @@ hipError_t sort_passes(uint64_t *keys, uint64_t n, const VKey &vk, uint32_t hi, 
                        uint64_t **out) {
     constexpr uint64_t TILE = WG * ITEMS;
     const uint32_t n_tiles = (uint32_t)((n + TILE - 1) / TILE);
-    const uint32_t n_chunks = (n_tiles + CHUNK - 1) / CHUNK;
     uint64_t *a = keys, *b = sc.alt;
     for (uint32_t sh = 0; sh < hi; sh += 8) {
         const uint32_t bits = (hi - sh) < 8 ? (hi - sh) : 8;
         hipLaunchKernelGGL(k_rs_hist<ITEMS>, dim3(n_tiles), dim3(WG), 0, s, a, n, vk, sh, bits, sc.hist);
-        hipLaunchKernelGGL(k_rs_colsum, dim3(n_chunks), dim3(WG), 0, s, sc.hist, n_tiles, sc.part);
-        hipLaunchKernelGGL(k_rs_top, dim3(256), dim3(WG), 0, s, sc.part, n_chunks, sc.part + (size_t)n_chunks * 256);
-        hipLaunchKernelGGL(k_rs_apply, dim3(n_chunks), dim3(WG), 0, s, sc.hist, n_tiles, sc.part,
-                           sc.part + (size_t)n_chunks * 256);
-        hipLaunchKernelGGL(k_rs_scatter<ITEMS>, dim3(n_tiles), dim3(WG), 0, s, a, b, n, vk, sh, bits, sc.hist);
+        hipLaunchKernelGGL(k_rs_scan, dim3(256), dim3(WG), 0, s, sc.hist, n_tiles, sc.part);
+        hipLaunchKernelGGL(k_rs_scatter<ITEMS>, dim3(n_tiles), dim3(WG), 0, s, a, b, n, vk, sh, bits, sc.hist,
+                           sc.part);
         uint64_t *t = a; a = b; b = t;
     }
     *out = a;
     return hipGetLastError();
+}
+
+// ---- one-workgroup sort of small inputs --------------------------------------
+constexpr int SWG = 1024;
+constexpr int SNW = SWG / WAVE;
+constexpr uint64_t SMALL_N = 32768;
+
+// One stable counting pass of src[0..n) into dst by one digit: wave w owns a
+// contiguous chunk, counts it per digit (8-ballot match), the counters are
+// scanned digit-major / wave-minor, and each wave writes its keys in order.
+__device__ __forceinline__ void small_pass(const uint64_t *__restrict__ src, uint64_t *__restrict__ dst, uint32_t n,
+                                           const VKey &vk, uint32_t shift, uint32_t bits, uint32_t (*wc)[256]) {
+    const uint32_t w = threadIdx.x / WAVE, lane = lane_id();
+    const uint32_t per = (n + SNW - 1) / SNW;
+    const uint32_t c0 = min(n, w * per), c1 = min(n, c0 + per);
+    for (uint32_t d = lane; d < 256; d += WAVE) wc[w][d] = 0;
+    const uint64_t lt = (1ull << lane) - 1ull;
+    for (uint32_t base = c0; base < c1; base += WAVE) {
+        const bool valid = base + lane < c1;
+        const uint32_t d = valid ? digit_of(src[base + lane], vk, shift, bits) : 0u;
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (uint32_t b = 0; b < 8; b++) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t bb = __ballot(valid && bit);
+            peers &= bit ? bb : ~bb;
+        }
+        if (valid && lane == (uint32_t)__ffsll((long long)peers) - 1) wc[w][d] += (uint32_t)__popcll(peers);
+    }
+    __syncthreads();
+    if (w == 0) {       // exclusive offsets: digit-major, wave-minor (lane owns digits 4 lane .. 4 lane + 3)
+        uint32_t sum = 0;
+#pragma unroll 1
+        for (uint32_t q = 0; q < SNW; q++) sum += wc[q][4 * lane] + wc[q][4 * lane + 1] + wc[q][4 * lane + 2] +
+                                                  wc[q][4 * lane + 3];
+        uint32_t incl = sum;
+#pragma unroll
+        for (int o = 1; o < WAVE; o <<= 1) {
+            const uint32_t y = __shfl_up(incl, o);
+            if ((int)lane >= o) incl += y;
+        }
+        uint32_t run = incl - sum;
+#pragma unroll 1
+        for (uint32_t r = 0; r < 4; r++)
+#pragma unroll 1
+            for (uint32_t q = 0; q < SNW; q++) {
+                const uint32_t x = wc[q][4 * lane + r];
+                wc[q][4 * lane + r] = run;
+                run += x;
+            }
+    }
+    __syncthreads();
+    for (uint32_t base = c0; base < c1; base += WAVE) {
+        const bool valid = base + lane < c1;
+        const uint64_t key = valid ? src[base + lane] : 0ull;
+        const uint32_t d = valid ? digit_of(key, vk, shift, bits) : 0u;
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (uint32_t b = 0; b < 8; b++) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t bb = __ballot(valid && bit);
+            peers &= bit ? bb : ~bb;
+        }
+        const uint32_t leader = valid ? (uint32_t)__ffsll((long long)peers) - 1 : 0u;
+        uint32_t old = 0;
+        if (valid && lane == leader) {
+            old = wc[w][d];
+            wc[w][d] = old + (uint32_t)__popcll(peers);
+        }
+        old = __shfl(old, (int)leader);
+        if (valid) dst[old + (uint32_t)__popcll(peers & lt)] = key;
+    }
+    __syncthreads();
+}
+
+// All passes over keys[0..n) ping-ponging with alt; the result is in keys when
+// the number of passes is even, else in alt.
+__global__ void __launch_bounds__(SWG) k_rs_small(uint64_t *__restrict__ keys, uint64_t *__restrict__ alt, uint32_t n,
+                                                  VKey vk, uint32_t hi) {
+    __shared__ uint32_t wc[SNW][256];
+    uint64_t *a = keys, *b = alt;
+    for (uint32_t sh = 0; sh < hi; sh += 8) {
+        small_pass(a, b, n, vk, sh, (hi - sh) < 8 ? (hi - sh) : 8, wc);
+        __threadfence();        // the next pass reads what other waves wrote
+        __syncthreads();
+        uint64_t *t = a; a = b; b = t;
+    }
 }
 
 }  // namespace
@@ -239,6 +304,11 @@ hipError_t radix_sort(uint64_t *keys, uint64_t n, const VKey &vk, SortScratch &s
                       hipStream_t s, uint64_t **out) {
     *out = keys;
     if (n <= 1 || vk.vbits == 0) return hipSuccess;
+    if (n <= SMALL_N) {
+        hipLaunchKernelGGL(k_rs_small, dim3(1), dim3(SWG), 0, s, keys, sc.alt, (uint32_t)n, vk, vk.vbits);
+        *out = ((vk.vbits + 7) / 8) % 2 ? sc.alt : keys;
+        return hipGetLastError();
+    }
     switch (tile) {
     case 2048: return sort_passes<8>(keys, n, vk, vk.vbits, sc, s, out);
     case 8192: return sort_passes<32>(keys, n, vk, vk.vbits, sc, s, out);

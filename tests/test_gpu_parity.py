@@ -196,3 +196,58 @@ def test_instruction_count_of_race_free_runs(ctx):
         rep, mem = kc.run_job(ctx, job)
         assert_same(rep, mem, orc, job.meta["family"])
         assert int(ctx.stat("instructions")) == orc.instructions, job.meta["family"]
+
+
+def _hot_word_program():
+    """Every thread of every block reads global[0] and global[1], stores its
+    tid to shared[0] (a write-write race among all threads of a block) and, in
+    block 5, thread 3 writes global[0] (a cross-block race with every reader);
+    thread 9 of every block writes global[1] (intra- and cross-block races);
+    after a barrier every thread reads shared[0].  The conflict segments of
+    global[0], global[1] and shared[0] are far longer than a head thread
+    reduces alone."""
+    a = ir.Asm()
+    a.SREG(0, "TID").SREG(1, "BID").MOVI(3, 0)
+    a.LDG(2, 3, 0).LDG(4, 3, 1).STS(3, 0, 0)
+    a.SEQI(5, 1, 5).SEQI(6, 0, 3).AND(5, 5, 6).BZ(5, "N").STG(3, 0, 0)
+    a.label("N").SEQI(6, 0, 9).BZ(6, "M").STG(3, 1, 0)
+    a.label("M").BAR().LDS(7, 3, 0).ADD(7, 7, 2).ADD(7, 7, 4).STG(1, 16, 7).EXIT()
+    return a.assemble()
+
+
+@pytest.mark.parametrize("local", [1, 0])
+def test_long_conflict_segments(ctx, local):
+    job = _single(_hot_word_program(), (40, 1, 1), (256, 1, 1), 4, [3, 4] + [0] * 14 + [0] * 40)
+    say(f"long segments, local check {local}")
+    ctx.set_option("local", local)
+    try:
+        rep, mem = kc.run_job(ctx, job)
+        orc = O.run_job(job)
+        assert len(orc.races) > 0
+        assert_same(rep, mem, orc, f"long segments local={local}")
+    finally:
+        ctx.set_option("local", 1)
+
+
+def test_replay_with_long_shared_reads(ctx):
+    """Every block reads global[1]; block 7 races on shared memory and is
+    replayed.  The exactness check then meets a location with many free-run
+    records (all reads), which a whole workgroup scans; the replay stays exact."""
+    a = ir.Asm()
+    a.SREG(0, "TID").SREG(1, "BID").MOVI(3, 0).LDG(2, 3, 1)
+    a.SEQI(5, 1, 7).BZ(5, "N").STS(3, 0, 0)
+    a.label("N").BAR().BNZ(0, "E").LDS(6, 3, 0).ADD(6, 6, 2).STG(1, 16, 6)
+    a.label("E").EXIT()
+    for local in (1, 0):
+        job = _single(a.assemble(), (64, 1, 1), (128, 1, 1), 4, [0, 11] + [0] * 14 + [0] * 64)
+        say(f"replay with long read segment, local check {local}")
+        ctx.set_option("local", local)
+        try:
+            ctx.reset_stats()
+            rep, mem = kc.run_job(ctx, job)
+            orc = O.run_job(job)
+            assert len(orc.races) == 1
+            assert_same(rep, mem, orc, f"long read segment local={local}")
+            assert ctx.stat("replays") >= 1 and ctx.stat("fallbacks") == 0
+        finally:
+            ctx.set_option("local", 1)
