@@ -38,6 +38,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the workload-3 batched vs plain comparison")
     ap.add_argument("--no-serve", action="store_true", help="skip the served-form measurement")
+    ap.add_argument("--jit", type=int, default=0, choices=(0, 1),
+                    help="1: program-specialised free-run kernels; 0: the interpreter (default, faster on this "
+                         "barrier- and shared-memory-heavy workload)")
     ap.add_argument("--serve-seconds", type=float, default=3.0, help="arrival window per served rate")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB three times (the known-size kernel that scales "
@@ -64,6 +67,7 @@ def main():
     L = job.launches[0]
     ctx = kc.Context(0)
     ctx.set_option("timing", 1)
+    ctx.set_option("jit", args.jit)     # program-specialised free-run kernels (compiled at first use)
     prog = ctx.program(L.program)
     mem = torch.from_numpy(job.memory.copy()).cuda()
     stream = torch.cuda.current_stream()
@@ -90,7 +94,7 @@ def main():
     stats = {k: ctx.stat(k) for k in ("interp_ms", "sort_ms", "check_ms", "replay_ms", "replays",
                                       "fallbacks", "retries", "sort_keys", "records", "interp_launches",
                                       "replay_lockstep_ms", "replay_sort_ms", "replay_check_ms",
-                                      "replay_coverage_ms", "log_entries", "instructions")}
+                                      "replay_coverage_ms", "log_entries", "instructions", "jit_launches")}
     per = {k: stats[k] / args.steps for k in ("interp_ms", "sort_ms", "check_ms", "replay_ms")}
     roofline = interp_roofline(stats, args.steps, records, value, per)
 
@@ -144,8 +148,9 @@ def interp_roofline(stats, steps, records, value, per):
     instr = stats["instructions"] / steps
     dur_s = per["interp_ms"] / 1e3 / max(1.0, stats["interp_launches"] / steps)
     achieved = instr / dur_s / 1e9 if dur_s > 0 else 0.0
-    traffic = measured_traffic()
-    return {"bound": "alu", "kernel": "k_interp_free_local", "achieved": round(achieved, 1),
+    kernel = "kc_jit_free_local_256" if stats.get("jit_launches", 0) > 0 else "k_interp_free_local"
+    traffic = measured_traffic(kernel)
+    return {"bound": "alu", "kernel": kernel, "achieved": round(achieved, 1),
             "peak": INT32_LANE_OPS_PEAK_G, "unit": "G thread-instructions/s (int32 lane-ops/s)",
             "frac": round(achieved / INT32_LANE_OPS_PEAK_G, 5), "traffic": traffic,
             "avg_ms": round(per["interp_ms"], 4), "thread_instructions_per_launch": int(instr),
@@ -157,10 +162,10 @@ def interp_roofline(stats, steps, records, value, per):
             "path_hbm_algorithmic_frac": round(value * 16 / (HBM_PEAK_GBS * 1e9), 4)}
 
 
-def measured_traffic():
-    """HBM bytes per interpreter launch from the committed counter summary
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary
     (FETCH_SIZE and WRITE_SIZE passes scaled by a copy kernel's reading), or
-    None when the interpreter's sources changed since it was taken."""
+    None when it covers another kernel or the sources changed since."""
     path = os.path.join(ROOT, "profiles", "interp_tree256_traffic.json")
     try:
         with open(path) as f:
@@ -168,7 +173,7 @@ def measured_traffic():
     except (OSError, ValueError):
         return None
     from paper_1211_6193_amd.profsum import kernel_source_digest
-    if t.get("source_digest") != kernel_source_digest():
+    if t.get("kernel") != kernel or t.get("source_digest") != kernel_source_digest():
         return None
     return t.get("bytes_per_launch")
 

@@ -97,12 +97,16 @@ void kc_ctx_destroy(kc_ctx *ctx);
 /* Options: "check" (1 = log and check, default; 0 = interpret only),
  * "fuel" (instructions per thread, default 1<<20), "timing" (1 = time the
  * stages with HIP events on the launch stream), "sort_tile" (keys per sort
- * tile: 2048, 4096 or 8192), "log_records" (initial log capacity, >= 1024),
+ * tile: 1024, 2048 (default), 4096 or 8192), "log_records" (initial log capacity, >= 1024),
  * "stage" (interpreter staging granule per wave: 128, 256, 512 or 1024
  * records), "stage_bytes" (LDS bytes of per-block record staging, 8192 to
  * 98304), "local" (1 = check shared accesses and sort staged global records
  * per barrier epoch inside the interpreter, default; 0 = log every access),
- * "reset" (1 = clear the statistics).
+ * "jit" (1 = run free runs on program-specialised kernels: each program is
+ * translated to HIP and compiled with hiprtc for gfx950 at its first launch,
+ * once per process, which takes seconds; results are identical to the
+ * interpreter's; 0 = interpreter only, default), "reset" (1 = clear the
+ * statistics).
  * Errors: KC_E_INVAL for an unknown key or out-of-range value. */
 kc_status kc_ctx_set_option(kc_ctx *ctx, const char *key, int64_t value);
 
@@ -110,7 +114,8 @@ kc_status kc_ctx_set_option(kc_ctx *ctx, const char *key, int64_t value);
  * "interp_ms", "sort_ms", "check_ms", "replay_ms", "launches", "records",
  * "replays", "fallbacks", "retries", "interp_launches", "sort_keys",
  * "instructions" (thread-instructions executed by the parallel free run; a
- * canonical replay of racy blocks is not counted).
+ * canonical replay of racy blocks is not counted), "jit_launches",
+ * "jit_compiled", "jit_compile_ms", "jit_failures".
  * Timings are only collected with option "timing" set.  "option.<name>"
  * reads back the current value of option <name>.  Returns 0 for an unknown
  * key. */

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libkc.so")
-SOURCES = ["kc_interp.hip", "kc_sort.hip", "kc_check.hip", "kc_runtime.hip"]
+SOURCES = ["kc_interp.hip", "kc_sort.hip", "kc_check.hip", "kc_jit.hip", "kc_runtime.hip"]
 ARCH = os.environ.get("KC_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [
@@ -19,14 +19,34 @@ FLAGS = [
 ]
 
 
+EMBED = [("kc_jit_internal_h", "kc_internal.h"), ("kc_jit_device_h", "kc_device.h")]
+
+
+def write_embedded(bdir: str) -> None:
+    """The device headers as string constants, for run-time compilation of the
+    program-specialised kernels (kc_jit.hip includes the generated file)."""
+    out = []
+    for name, header in EMBED:
+        text = open(os.path.join(CSRC, header)).read()
+        if ")KCJIT\"" in text:
+            raise RuntimeError(f"{header} contains the raw-string delimiter")
+        out.append(f'static const char *const {name} = R"KCJIT({text})KCJIT";\n')
+    path = os.path.join(bdir, "kc_jit_src.inc")
+    new = "".join(out)
+    if not os.path.exists(path) or open(path).read() != new:
+        with open(path, "w") as f:
+            f.write(new)
+
+
 def build(verbose: bool = False, jobs: int = 4) -> str:
     """Compile every source to an object, then link the shared library."""
     bdir = os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)
+    write_embedded(bdir)
     objs, procs = [], []
     for src in SOURCES:
         obj = os.path.join(bdir, src.replace(".hip", ".o"))
-        cmd = ["hipcc", *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = ["hipcc", *FLAGS, "-I", bdir, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
@@ -35,7 +55,7 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
             _reap(procs)
     _reap(procs)
     tmp = LIB + ".tmp"
-    subprocess.check_call(["hipcc", "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp])
+    subprocess.check_call(["hipcc", "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-lhiprtc", "-o", tmp])
     os.replace(tmp, LIB)
     return LIB
 

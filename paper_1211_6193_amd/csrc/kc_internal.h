@@ -1,6 +1,11 @@
 // Internal structures shared by the HIP kernels and the host runtime of libkc.
+// The part above the host-only section is also compiled at run time (hiprtc)
+// into the program-specialised kernels, where the HIP runtime header is
+// implicit.
 #pragma once
+#ifndef __HIPCC_RTC__
 #include <hip/hip_runtime.h>
+#endif
 #include <stdint.h>
 
 namespace kc {
@@ -112,7 +117,9 @@ struct InterpArgs {
     unsigned long long *instructions;   // free run: thread-instructions executed (added to), or null
 };
 
-// Host-side launchers (defined in the .hip files).
+#ifndef __HIPCC_RTC__
+// ---- host side ----------------------------------------------------------------
+// Launchers (defined in the .hip files).
 hipError_t launch_interp(const InterpArgs &a, uint32_t n_wg, uint32_t wg_threads, bool lockstep, hipStream_t s);
 size_t interp_lds_bytes(uint32_t sh_words_max, uint32_t wg_threads, uint32_t stage, bool lockstep, bool local);
 
@@ -158,5 +165,6 @@ hipError_t launch_coverage(const uint64_t *rs, uint64_t n_rs, const uint64_t *lo
 hipError_t launch_copy_units(const DevUnit *units, uint32_t n_units, uint32_t max_words, bool to_snapshot,
                              const uint32_t *unit_mask, hipStream_t s);
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);
+#endif  // __HIPCC_RTC__
 
 }  // namespace kc

@@ -1,0 +1,399 @@
+// Program-specialised free-run kernels.
+//
+// A KC-IR program is translated into HIP source in which every basic block is
+// straight-line code: the simulated registers are variables (real VGPRs, no
+// indexed register file), operands and special-register numbers are
+// constants, and a converged wave moves between blocks with direct jumps.
+// Only a divergent wave goes back to the smallest-pc dispatch.  Everything
+// else -- block set-up, access logging, the epoch-local check, barrier
+// episodes, deadlock and divergence findings, block publication -- is the
+// interpreter's own device code (kc_device.h), compiled into the same kernel,
+// so a specialised kernel produces exactly the records, findings and memory
+// of the interpreter's free run.
+//
+// Fuel: each basic block of length n runs without per-instruction checks when
+// every live lane of the wave holds at least n units (a wave-uniform lower
+// bound is kept); otherwise its instructions check and spend fuel one by one.
+//
+// The source is compiled with hiprtc for gfx950 by the first launch that needs
+// it (the programs of one stage in parallel, on threads joined before the
+// launch: no compilation outlives the call, so none can be cut short by the
+// process exiting); the code is cached per process by program text and the
+// module loaded once per device.
+#include <hip/hip_runtime.h>
+#include <hip/hiprtc.h>
+
+#include <chrono>
+#include <condition_variable>
+#include <cstdio>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "kc_internal.h"
+#include "kc_jit.h"
+
+namespace kc {
+
+namespace {
+#include "kc_jit_src.inc"   // kc_jit_internal_h, kc_jit_device_h: text of the two device headers
+
+struct Instr {
+    uint32_t op, d, a, b;
+    int32_t imm;
+};
+
+Instr decode(uint64_t w) {
+    return Instr{(uint32_t)(w & 0xFF), (uint32_t)((w >> 8) & 0xFF), (uint32_t)((w >> 16) & 0xFF),
+                 (uint32_t)((w >> 24) & 0xFF), (int32_t)(uint32_t)(w >> 32)};
+}
+
+std::string reg(uint32_t r) { return "r" + std::to_string(r); }
+std::string lit(int32_t v) {
+    if (v == INT32_MIN) return "(-2147483647 - 1)";
+    return "(" + std::to_string(v) + ")";
+}
+std::string label(uint32_t pc, uint32_t n) { return pc >= n ? std::string("BB_END") : "BB_" + std::to_string(pc); }
+
+// Spend fuel one instruction at a time (slow path of a block).
+const char *kSlowFuel =
+    "        if (slow) {\n"
+    "            const bool nofuel = act && t.fuel == 0u;\n"
+    "            if (__ballot(nofuel)) {\n"
+    "                emit_fault(nofuel, A, B, F_FUEL, epoch, 0, B.tid, 0, 0);\n"
+    "                if (nofuel) { t.st = ST_EXIT; act = false; }\n"
+    "                if (__ballot(act) == 0) continue;\n"
+    "            }\n"
+    "            if (act) t.fuel--;\n"
+    "        }\n";
+
+void gen_alu(std::ostringstream &o, const Instr &I, uint32_t pc) {
+    const uint32_t base = I.op & ~uint32_t(OP_IMM);
+    const std::string x = reg(I.a);
+    const std::string y = (I.op & OP_IMM) ? lit(I.imm) : reg(I.b);
+    const std::string d = reg(I.d);
+    o << "        {\n            const int32_t x = " << x << ", y = " << y << ";\n";
+    o << "            const uint32_t ux = (uint32_t)x, uy = (uint32_t)y;\n            (void)ux; (void)uy;\n";
+    std::string v;
+    switch (base) {
+    case OP_ADD: v = "(int32_t)(ux + uy)"; break;
+    case OP_SUB: v = "(int32_t)(ux - uy)"; break;
+    case OP_MUL: v = "(int32_t)(ux * uy)"; break;
+    case OP_DIV:
+    case OP_REM:
+        o << "            emit_fault(act && y == 0, A, B, F_ARITH, epoch, 0, B.tid, " << pc << "u, 0);\n";
+        o << "            const int32_t ys = (y == 0 || y == -1) ? 1 : y;\n";
+        v = base == OP_DIV ? "(y == 0 ? 0 : (y == -1 ? (int32_t)(0u - ux) : x / ys))"
+                           : "((y == 0 || y == -1) ? 0 : x % ys)";
+        break;
+    case OP_AND: v = "(x & y)"; break;
+    case OP_OR: v = "(x | y)"; break;
+    case OP_XOR: v = "(x ^ y)"; break;
+    case OP_SHL: v = "(int32_t)(ux << (uy & 31u))"; break;
+    case OP_SHRA: v = "(x >> (int)(uy & 31u))"; break;
+    case OP_SHRL: v = "(int32_t)(ux >> (uy & 31u))"; break;
+    case OP_MIN: v = "min(x, y)"; break;
+    case OP_MAX: v = "max(x, y)"; break;
+    case OP_SLT: v = "(x < y ? 1 : 0)"; break;
+    case OP_SLE: v = "(x <= y ? 1 : 0)"; break;
+    case OP_SEQ: v = "(x == y ? 1 : 0)"; break;
+    case OP_SNE: v = "(x != y ? 1 : 0)"; break;
+    case OP_SLTU: v = "(ux < uy ? 1 : 0)"; break;
+    default: v = "0"; break;
+    }
+    o << "            const int32_t v = " << v << ";\n            if (act) " << d << " = v;\n        }\n";
+}
+
+void gen_mem(std::ostringstream &o, const Instr &I) {
+    const bool sh = (I.op & 2u) == 0, st = (I.op & 1u) != 0;
+    const char *lim = sh ? "B.sh_words" : "B.n_words";
+    const char *arr = sh ? "S.sh" : "B.mem";
+    o << "        {\n            const int32_t addr = (int32_t)((uint32_t)" << reg(I.a) << " + (uint32_t)" << lit(I.imm)
+      << ");\n";
+    o << "            const bool inb = act && (uint32_t)addr < " << lim << ";\n";
+    if (st) {
+        o << "            if (inb) " << arr << "[addr] = " << reg(I.b) << ";\n";
+    } else {
+        o << "            int32_t v = 0;\n            if (inb) v = " << arr << "[addr];\n";
+        o << "            if (act) " << reg(I.d) << " = v;\n";
+    }
+    if (sh) {
+        o << "            if (LOCAL) {\n";
+        o << "                if (inb) shadow_update(S.shadow, (uint32_t)addr, B.tid, " << (st ? "true" : "false")
+          << ");\n";
+        o << "                L.total += (uint32_t)__popcll(__ballot(inb));\n            } else {\n    ";
+    }
+    o << "            log_rec(A, S.stage, L, inb, B.kep | ((uint64_t)" << (sh ? 0 : 1) << "u << A.kp.s_sp) | "
+      << (st ? "1ull" : "0ull") << " | ((uint64_t)(uint32_t)addr << A.kp.s_addr));\n";
+    if (sh) o << "            }\n";
+    o << "            emit_fault(act && !inb, A, B, F_OOB, epoch, " << ((sh ? 0 : 2) + (st ? 1 : 0))
+      << "u, B.tid, (uint32_t)addr, 0);\n        }\n";
+}
+
+}  // namespace
+
+std::string jit_source(const uint64_t *words, uint32_t n, int waves) {
+    std::vector<char> lead(n + 1, 0);
+    lead[0] = 1;
+    lead[n] = 1;
+    for (uint32_t pc = 0; pc < n; pc++) {
+        const Instr I = decode(words[pc]);
+        if (I.op == OP_JMP || I.op == OP_BZ || I.op == OP_BNZ) {
+            lead[(uint32_t)I.imm] = 1;
+            lead[pc + 1] = 1;
+        } else if (I.op == OP_BAR || I.op == OP_EXIT) {
+            lead[pc + 1] = 1;
+        }
+    }
+    std::vector<uint32_t> starts;
+    for (uint32_t pc = 0; pc < n; pc++)
+        if (lead[pc]) starts.push_back(pc);
+
+    std::ostringstream o;
+    o << "#include \"kc_internal.h\"\n#include \"kc_device.h\"\n\nnamespace kc {\nnamespace {\n\n";
+    o << "template <bool LOCAL>\n__device__ __forceinline__ uint32_t jit_run(const InterpArgs &A, BlockCtx &B, "
+         "const Shared &S, Lane &t, LogState &L) {\n";
+    o << "    uint32_t epoch = 0;\n";
+    for (uint32_t r = 0; r < 16; r++) o << "    int32_t r" << r << " = 0;\n";
+    o << "    bool conv = true;\n    int upc = 0;\n    uint32_t guard = B.u->fuel;\n";
+    o << "    for (;;) {\n      for (;;) {\n";
+    o << "        const uint64_t runm = __ballot(t.st == ST_RUN);\n        if (runm == 0) break;\n";
+    o << "        int cur;\n        bool act;\n        bool slow;\n";
+    o << "        if (conv) {\n            cur = upc;\n            act = t.st == ST_RUN;\n        } else {\n";
+    o << "            cur = uni(wave_min(t.st == ST_RUN ? t.pc : INT_MAX));\n";
+    o << "            act = t.st == ST_RUN && t.pc == cur;\n";
+    o << "            if (__ballot(act) == runm) { conv = true; upc = cur; }\n        }\n";
+    o << "        switch (cur) {\n";
+    for (uint32_t s : starts) o << "        case " << s << ": goto BB_" << s << ";\n";
+    o << "        default: goto BB_END;\n        }\n";
+    for (size_t bi = 0; bi < starts.size(); bi++) {
+        const uint32_t s = starts[bi];
+        uint32_t e = s + 1;
+        while (e < n && !lead[e]) e++;
+        const uint32_t len = e - s;
+        o << "    BB_" << s << ":\n";
+        o << "        slow = guard < " << len << "u;\n";
+        o << "        if (!slow) {\n            guard -= " << len << "u;\n            if (act) t.fuel -= " << len
+          << "u;\n        }\n";
+        for (uint32_t pc = s; pc < e; pc++) {
+            const Instr I = decode(words[pc]);
+            o << "        // pc " << pc << "\n" << kSlowFuel;
+            const uint32_t base = I.op & ~uint32_t(OP_IMM);
+            if (base >= OP_ADD && base <= OP_SLTU) {
+                gen_alu(o, I, pc);
+            } else if ((I.op >> 4) == 5) {
+                gen_mem(o, I);
+            } else if (I.op == OP_MOV) {
+                o << "        if (act) " << reg(I.d) << " = " << reg(I.a) << ";\n";
+            } else if (I.op == OP_MOVI) {
+                o << "        if (act) " << reg(I.d) << " = " << lit(I.imm) << ";\n";
+            } else if (I.op == OP_SREG) {
+                o << "        if (act) " << reg(I.d) << " = special(B, " << (uint32_t)I.imm << "u);\n";
+            }
+        }
+        o << "        if (slow) guard = wave_min_u((t.st == ST_RUN || t.st == ST_WAIT) ? t.fuel : 0xFFFFFFFFu);\n";
+        const Instr T = decode(words[e - 1]);
+        if (T.op == OP_JMP) {
+            o << "        if (conv) goto " << label((uint32_t)T.imm, n) << ";\n";
+            o << "        if (act) t.pc = " << T.imm << ";\n        continue;\n";
+        } else if (T.op == OP_BZ || T.op == OP_BNZ) {
+            o << "        {\n            const bool c = act && (" << reg(T.a) << (T.op == OP_BZ ? " == 0" : " != 0")
+              << ");\n";
+            o << "            const uint64_t am = __ballot(act), tk = __ballot(c);\n";
+            o << "            if (conv) {\n                if (tk == 0) goto " << label(e, n) << ";\n";
+            o << "                if (tk == am) goto " << label((uint32_t)T.imm, n) << ";\n";
+            o << "                conv = false;\n            }\n";
+            o << "            if (act) t.pc = c ? " << T.imm << " : " << e << ";\n            continue;\n        }\n";
+        } else if (T.op == OP_BAR) {
+            o << "        if (act) { t.st = ST_WAIT; t.bar_pc = " << (e - 1) << "; }\n        continue;\n";
+        } else if (T.op == OP_EXIT) {
+            o << "        if (act) t.st = ST_EXIT;\n        continue;\n";
+        } else {
+            o << "        if (conv) goto " << label(e, n) << ";\n";
+            o << "        if (act) t.pc = " << e << ";\n        continue;\n";
+        }
+    }
+    o << "    BB_END:\n        if (act) t.st = ST_EXIT;\n        continue;\n";
+    o << "      }\n";
+    o << "      if (barrier_episode<LOCAL>(A, B, S, t, L, epoch) == EP_DONE) break;\n";
+    o << "      const int lo = wave_min(t.st == ST_RUN ? t.pc : INT_MAX);\n";
+    o << "      const int hi = wave_max(t.st == ST_RUN ? t.pc : -1);\n";
+    o << "      conv = (lo == hi) || hi < 0;\n      upc = uni(lo);\n    }\n    return epoch;\n}\n\n";
+    o << "}  // namespace\n}  // namespace kc\n\n";
+    // workgroups of up to 256 threads get the whole register file; larger ones
+    // are bounded to 128 VGPRs
+    const struct { const char *name; int bound; bool local; } kernels[] = {
+        {"kc_jit_free_local_256", 256, true}, {"kc_jit_free_local_1024", 1024, true}, {"kc_jit_free_1024", 1024, false}};
+    for (const auto &k : kernels) {
+        o << "extern \"C\" __global__ void __launch_bounds__(" << k.bound << ") ";
+        if (waves > 0) o << "__attribute__((amdgpu_waves_per_eu(" << waves << ", " << waves << "))) ";
+        o << k.name << "(kc::InterpArgs A) {\n";
+        o << "    kc::free_block(A, [](const kc::InterpArgs &a, kc::BlockCtx &b, const kc::Shared &s, kc::Lane &t, "
+             "kc::LogState &l) {\n";
+        o << "        return kc::jit_run<" << (k.local ? "true" : "false") << ">(a, b, s, t, l);\n    });\n}\n";
+    }
+    return o.str();
+}
+
+// ---- compilation and cache -------------------------------------------------------
+
+struct JitEntry {
+    std::string words;              // the program
+    int waves = 0;                  // occupancy target of the kernels (0: the compiler's choice)
+    std::mutex mu;
+    std::condition_variable cv;
+    int state = 0;                  // 0 not compiled, 2 being compiled, 1 code ready, -1 failed
+    std::vector<char> code;
+    std::string log;
+    double compile_ms = 0.0;
+    bool reported = false;          // a failure was printed
+    std::map<int, std::pair<hipModule_t, JitFunctions>> loaded;   // per device
+};
+
+namespace {
+
+// Process-wide cache, never freed.
+struct Globals {
+    std::mutex mu;
+    std::map<std::string, std::shared_ptr<JitEntry>> cache;
+};
+Globals &G() {
+    static Globals *g = new Globals;
+    return *g;
+}
+
+}  // namespace
+
+void jit_compile(const std::shared_ptr<JitEntry> &e) {
+    const auto t0 = std::chrono::steady_clock::now();
+    const std::string src = jit_source((const uint64_t *)e->words.data(), (uint32_t)(e->words.size() / 8), e->waves);
+    std::vector<char> code;
+    std::string log;
+    bool ok = false;
+    hiprtcProgram prog = nullptr;
+    const char *headers[] = {kc_jit_internal_h, kc_jit_device_h};
+    const char *names[] = {"kc_internal.h", "kc_device.h"};
+    if (hiprtcCreateProgram(&prog, src.c_str(), "kc_jit.hip", 2, headers, names) == HIPRTC_SUCCESS) {
+        const char *opts[] = {"--offload-arch=gfx950", "-O3", "-std=c++17", "-Xclang", "-target-feature",
+                              "-Xclang", "-packed-fp32-ops"};
+        const hiprtcResult r = hiprtcCompileProgram(prog, 7, opts);
+        size_t ls = 0;
+        if (hiprtcGetProgramLogSize(prog, &ls) == HIPRTC_SUCCESS && ls > 1) {
+            log.resize(ls);
+            hiprtcGetProgramLog(prog, &log[0]);
+        }
+        size_t cs = 0;
+        if (r == HIPRTC_SUCCESS && hiprtcGetCodeSize(prog, &cs) == HIPRTC_SUCCESS && cs > 0) {
+            code.resize(cs);
+            ok = hiprtcGetCode(prog, code.data()) == HIPRTC_SUCCESS;
+        }
+        hiprtcDestroyProgram(&prog);
+    } else {
+        log = "hiprtcCreateProgram failed";
+    }
+    const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    {
+        std::lock_guard<std::mutex> lk(e->mu);
+        e->code = std::move(code);
+        e->log = std::move(log);
+        e->compile_ms = ms;
+        e->state = ok ? 1 : -1;
+    }
+    e->cv.notify_all();
+}
+
+std::shared_ptr<JitEntry> jit_request(const uint64_t *words, uint32_t n, int waves) {
+    std::string key((const char *)words, (size_t)n * 8);
+    key.push_back((char)waves);
+    std::lock_guard<std::mutex> g(G().mu);
+    auto it = G().cache.find(key);
+    if (it != G().cache.end()) return it->second;
+    auto e = std::make_shared<JitEntry>();
+    e->words.assign((const char *)words, (size_t)n * 8);
+    e->waves = waves;
+    G().cache[key] = e;
+    return e;
+}
+
+bool jit_claim(const std::shared_ptr<JitEntry> &e) {
+    std::lock_guard<std::mutex> lk(e->mu);
+    if (e->state != 0) return false;
+    e->state = 2;
+    return true;
+}
+
+bool jit_functions(const std::shared_ptr<JitEntry> &e, int device, bool wait, JitFunctions &out, double *compile_ms) {
+    if (!e) return false;
+    std::unique_lock<std::mutex> lk(e->mu);
+    if (wait) e->cv.wait(lk, [&] { return e->state != 2; });
+    if (e->state < 0 && !e->reported) {
+        e->reported = true;
+        std::fprintf(stderr, "libkc: specialised kernels unavailable, the interpreter runs instead:\n%s\n",
+                     e->log.c_str());
+    }
+    if (e->state != 1) return false;
+    auto it = e->loaded.find(device);
+    if (it == e->loaded.end()) {
+        JitFunctions f{};
+        hipModule_t mod = nullptr;
+        if (hipModuleLoadData(&mod, e->code.data()) != hipSuccess) {
+            (void)hipGetLastError();
+            e->state = -1;
+            e->log += "\nhipModuleLoadData failed";
+            return false;
+        }
+        if (hipModuleGetFunction(&f.local_256, mod, "kc_jit_free_local_256") != hipSuccess ||
+            hipModuleGetFunction(&f.local_1024, mod, "kc_jit_free_local_1024") != hipSuccess ||
+            hipModuleGetFunction(&f.free_1024, mod, "kc_jit_free_1024") != hipSuccess) {
+            (void)hipGetLastError();
+            e->state = -1;
+            e->log += "\nhipModuleGetFunction failed";
+            return false;
+        }
+        it = e->loaded.emplace(device, std::make_pair(mod, f)).first;
+        if (compile_ms) *compile_ms = e->compile_ms;
+    }
+    out = it->second.second;
+    return true;
+}
+
+int jit_state(const std::shared_ptr<JitEntry> &e) {
+    if (!e) return -1;
+    std::lock_guard<std::mutex> lk(e->mu);
+    return e->state;
+}
+
+std::string jit_log(const std::shared_ptr<JitEntry> &e) {
+    if (!e) return "";
+    std::lock_guard<std::mutex> lk(e->mu);
+    return e->log;
+}
+
+hipError_t launch_jit(const JitFunctions &f, const InterpArgs &a, uint32_t n_wg, uint32_t wg_threads,
+                      hipStream_t s) {
+    if (n_wg == 0) return hipSuccess;
+    InterpArgs args = a;
+    size_t lds = interp_lds_bytes(args.sh_words_max, wg_threads, args.stage, false, args.local != 0);
+    while (lds > 64 * 1024 && args.stage > 64) {
+        args.stage = (args.stage / 2 + 63) / 64 * 64;
+        lds = interp_lds_bytes(args.sh_words_max, wg_threads, args.stage, false, args.local != 0);
+    }
+    if (lds > 64 * 1024 && args.local) {
+        args.local = 0;
+        lds = interp_lds_bytes(args.sh_words_max, wg_threads, args.stage, false, false);
+    }
+    if (lds > 64 * 1024) return hipErrorInvalidValue;    // the caller falls back to the interpreter
+    void *params[] = {&args};
+    hipFunction_t fn = !args.local ? f.free_1024 : (wg_threads <= 256 ? f.local_256 : f.local_1024);
+    return hipModuleLaunchKernel(fn, n_wg, 1, 1, wg_threads, 1, 1, (unsigned)lds, s, params, nullptr);
+}
+
+bool jit_fits(uint32_t sh_words_max, uint32_t wg_threads) {
+    return interp_lds_bytes(sh_words_max, wg_threads, 64, false, false) <= 64 * 1024;
+}
+
+}  // namespace kc

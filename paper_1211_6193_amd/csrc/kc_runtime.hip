@@ -35,6 +35,7 @@
 
 #include "../../include/kc.h"
 #include "kc_internal.h"
+#include "kc_jit.h"
 
 using namespace kc;
 
@@ -42,6 +43,8 @@ struct kc_program {
     std::vector<uint64_t> words;
     uint64_t *dev = nullptr;
     int device = 0;
+    mutable std::mutex jit_mu;
+    mutable std::shared_ptr<kc::JitEntry> jit[9];   // program-specialised kernels, by occupancy target
 };
 
 struct kc_report {
@@ -153,11 +156,13 @@ struct Options {
     int check = 1;
     uint32_t fuel = 1u << 20;
     int timing = 0;
-    uint32_t sort_tile = 4096;
+    uint32_t sort_tile = 2048;
     uint64_t log_records = 1ull << 22;
     uint32_t stage = 256;           // staged records per wave in the lockstep replay
     uint32_t stage_bytes = 16384;   // LDS for staging + local sort per workgroup (free run)
     int local = 1;                  // epoch-local check in LDS
+    int jit = 0;                    // program-specialised free-run kernels (compiled at first use)
+    int jit_waves = 0;              // their occupancy target, waves per SIMD (0: the compiler's choice)
 };
 
 }  // namespace
@@ -447,22 +452,55 @@ struct Stage {
             HIPCHK(launch_interp(a, n_comp, wg, true, s));
             return;
         }
-        // free run: one launch per workgroup-size class
-        std::map<uint32_t, std::vector<uint32_t>> classes;   // wg -> unit ids
-        for (uint32_t i = 0; i < hu.size(); i++) classes[(hu[i].nt + 63) / 64 * 64].push_back(i);
+        // free run: one launch per (workgroup size, kernel) class; a unit whose
+        // program has compiled specialised kernels runs those, the rest the
+        // interpreter
+        if (ctx->opt.jit) jit_prepare();
+        std::vector<JitFunctions> jf(hu.size());
+        std::vector<char> use_jit(hu.size(), 0);
+        for (uint32_t i = 0; i < hu.size(); i++) use_jit[i] = jit_for(i, jf[i]) ? 1 : 0;
+        auto launch = [&](const InterpArgs &args, uint32_t n_wg, uint32_t wg, bool jit, const JitFunctions &f) {
+            if (jit) {
+                const hipError_t e = launch_jit(f, args, n_wg, wg, s);
+                if (e == hipSuccess) {
+                    ctx->stat_add("jit_launches", 1);
+                    return;
+                }
+                if (e != hipErrorInvalidValue) HIPCHK(e);
+                (void)hipGetLastError();
+            }
+            HIPCHK(launch_interp(args, n_wg, wg, false, s));
+        };
         if (hu.size() == 1) {
+            const uint32_t wg = (hu[0].nt + 63) / 64 * 64;
             a.items = nullptr;
             a.sh_words_max = hu[0].sh_words;
-            a.stage = stage_for((hu[0].nt + 63) / 64 * 64);
-            HIPCHK(launch_interp(a, hu[0].nb, (hu[0].nt + 63) / 64 * 64, false, s));
+            a.stage = stage_for(wg);
+            launch(a, hu[0].nb, wg, use_jit[0] != 0, jf[0]);
             return;
+        }
+        struct Class {
+            uint32_t wg;
+            bool jit;
+            JitFunctions f;
+            std::vector<uint32_t> units;
+        };
+        std::map<std::pair<uint32_t, const void *>, Class> classes;
+        for (uint32_t i = 0; i < hu.size(); i++) {
+            const uint32_t wg = (hu[i].nt + 63) / 64 * 64;
+            const void *kf = use_jit[i] ? (const void *)jf[i].local_256 : nullptr;
+            Class &c = classes[{wg, kf}];
+            c.wg = wg;
+            c.jit = use_jit[i] != 0;
+            c.f = jf[i];
+            c.units.push_back(i);
         }
         std::vector<uint2> items;
         items.reserve(total_blocks);
         std::vector<std::pair<size_t, size_t>> ranges;
         for (auto &kv : classes) {
             size_t b0 = items.size();
-            for (uint32_t ui : kv.second)
+            for (uint32_t ui : kv.second.units)
                 for (uint32_t b = 0; b < hu[ui].nb; b++) items.push_back(make_uint2(ui, b));
             ranges.push_back({b0, items.size()});
         }
@@ -471,13 +509,60 @@ struct Stage {
         size_t ci = 0;
         for (auto &kv : classes) {
             uint32_t shmax = 0;
-            for (uint32_t ui : kv.second) shmax = std::max(shmax, hu[ui].sh_words);
+            for (uint32_t ui : kv.second.units) shmax = std::max(shmax, hu[ui].sh_words);
             a.items = ws.items.as<uint2>() + ranges[ci].first;
             a.sh_words_max = shmax;
-            a.stage = stage_for(kv.first);
-            HIPCHK(launch_interp(a, (uint32_t)(ranges[ci].second - ranges[ci].first), kv.first, false, s));
+            a.stage = stage_for(kv.second.wg);
+            launch(a, (uint32_t)(ranges[ci].second - ranges[ci].first), kv.second.wg, kv.second.jit, kv.second.f);
             ci++;
         }
+    }
+
+    // Compile the stage's programs that nobody has compiled yet, in parallel;
+    // every thread is joined before the launches.
+    void jit_prepare() {
+        std::vector<std::shared_ptr<JitEntry>> todo;
+        for (uint32_t i = 0; i < hu.size(); i++) {
+            std::shared_ptr<JitEntry> e = jit_entry(i);
+            if (e && jit_claim(e)) todo.push_back(e);
+        }
+        if (todo.empty()) return;
+        std::atomic<size_t> next{0};
+        auto work = [&] {
+            for (size_t k; (k = next.fetch_add(1)) < todo.size();) jit_compile(todo[k]);
+        };
+        const size_t nt = std::min<size_t>(todo.size(), std::max(1u, std::min(8u, std::thread::hardware_concurrency())));
+        std::vector<std::thread> th;
+        for (size_t t = 1; t < nt; t++) th.emplace_back(work);
+        work();
+        for (auto &t : th) t.join();
+        ctx->stat_add("jit_compiled", (double)todo.size());
+    }
+
+    // Cache entry of unit i's program for the current occupancy target.
+    std::shared_ptr<JitEntry> jit_entry(uint32_t i) {
+        const kc_program *p = in[i].desc->prog;
+        if (p->words.empty()) return nullptr;
+        const int w = ctx->opt.jit_waves;
+        std::lock_guard<std::mutex> g(p->jit_mu);
+        if (!p->jit[w]) p->jit[w] = jit_request(p->words.data(), (uint32_t)p->words.size(), w);
+        return p->jit[w];
+    }
+
+    // Specialised kernels of unit i's program, if enabled, compiled and the
+    // launch shape fits them.
+    bool jit_for(uint32_t i, JitFunctions &f) {
+        if (!ctx->opt.jit) return false;
+        std::shared_ptr<JitEntry> e = jit_entry(i);
+        if (!e) return false;
+        if (!jit_fits(hu[i].sh_words, (hu[i].nt + 63) / 64 * 64)) return false;
+        double cms = 0.0;
+        if (!jit_functions(e, ctx->device, true, f, &cms)) {
+            if (jit_state(e) < 0) ctx->stat_add("jit_failures", 1);
+            return false;
+        }
+        if (cms > 0.0) ctx->stat_add("jit_compile_ms", cms);
+        return true;
     }
 
     void run() {
@@ -995,11 +1080,13 @@ kc_status kc_ctx_set_option(kc_ctx *ctx, const char *key, int64_t v) {
     if (k == "check" && (v == 0 || v == 1)) ctx->opt.check = (int)v;
     else if (k == "fuel" && v >= 1 && v <= 0xFFFFFFFFll) ctx->opt.fuel = (uint32_t)v;
     else if (k == "timing" && (v == 0 || v == 1)) ctx->opt.timing = (int)v;
-    else if (k == "sort_tile" && (v == 2048 || v == 4096 || v == 8192)) ctx->opt.sort_tile = (uint32_t)v;
+    else if (k == "sort_tile" && (v == 1024 || v == 2048 || v == 4096 || v == 8192)) ctx->opt.sort_tile = (uint32_t)v;
     else if (k == "log_records" && v >= 1024) ctx->opt.log_records = (uint64_t)v;
     else if (k == "stage" && (v == 128 || v == 256 || v == 512 || v == 1024)) ctx->opt.stage = (uint32_t)v;
     else if (k == "stage_bytes" && v >= 8192 && v <= 98304) ctx->opt.stage_bytes = (uint32_t)v;
     else if (k == "local" && (v == 0 || v == 1)) ctx->opt.local = (int)v;
+    else if (k == "jit" && (v == 0 || v == 1)) ctx->opt.jit = (int)v;
+    else if (k == "jit_waves" && (v == 0 || (v >= 2 && v <= 8))) ctx->opt.jit_waves = (int)v;
     else if (k == "reset" && v == 1) {
         std::lock_guard<std::mutex> g(ctx->mu);
         ctx->stats.clear();
@@ -1025,6 +1112,8 @@ double kc_ctx_get_stat(kc_ctx *ctx, const char *key) {
         if (o == "stage") return op.stage;
         if (o == "stage_bytes") return op.stage_bytes;
         if (o == "local") return op.local;
+        if (o == "jit") return op.jit;
+        if (o == "jit_waves") return op.jit_waves;
         return 0.0;
     }
     auto it = ctx->stats.find(key);

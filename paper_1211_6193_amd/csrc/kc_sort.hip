@@ -209,86 +209,102 @@ hipError_t sort_passes(uint64_t *keys, uint64_t n, const VKey &vk, uint32_t hi, 
 // ---- one-workgroup sort of small inputs --------------------------------------
 constexpr int SWG = 1024;
 constexpr int SNW = SWG / WAVE;
-constexpr uint64_t SMALL_N = 32768;
+constexpr uint64_t SMALL_N = 16384;     // keys staged in LDS: 128 KiB
 
-// One stable counting pass of src[0..n) into dst by one digit: wave w owns a
-// contiguous chunk, counts it per digit (8-ballot match), the counters are
-// scanned digit-major / wave-minor, and each wave writes its keys in order.
-__device__ __forceinline__ void small_pass(const uint64_t *__restrict__ src, uint64_t *__restrict__ dst, uint32_t n,
-                                           const VKey &vk, uint32_t shift, uint32_t bits, uint32_t (*wc)[256]) {
+__device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid) {
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (uint32_t b = 0; b < 8; b++) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t bb = __ballot(valid && bit);
+        peers &= bit ? bb : ~bb;
+    }
+    return peers;
+}
+
+// All passes over keys[0..n) (n <= SMALL_N) ping-ponging with alt; the
+// result is in keys when the number of passes is even, else in alt.  Each pass
+// stages the input in LDS (coalesced, every load in flight at once), counts
+// digits per wave over the wave's contiguous chunk (8-ballot match), scans the
+// counters digit-major / wave-minor and writes every wave's keys in order
+// (stable) to the other buffer: one round trip to memory per pass.
+__global__ void __launch_bounds__(SWG) k_rs_small(uint64_t *__restrict__ keys, uint64_t *__restrict__ alt, uint32_t n,
+                                                  VKey vk, uint32_t hi) {
+    extern __shared__ uint64_t stage[];     // n keys
+    __shared__ uint32_t wc[SNW][256];
+    __shared__ uint32_t wtot[4];
     const uint32_t w = threadIdx.x / WAVE, lane = lane_id();
     const uint32_t per = (n + SNW - 1) / SNW;
     const uint32_t c0 = min(n, w * per), c1 = min(n, c0 + per);
-    for (uint32_t d = lane; d < 256; d += WAVE) wc[w][d] = 0;
     const uint64_t lt = (1ull << lane) - 1ull;
-    for (uint32_t base = c0; base < c1; base += WAVE) {
-        const bool valid = base + lane < c1;
-        const uint32_t d = valid ? digit_of(src[base + lane], vk, shift, bits) : 0u;
-        uint64_t peers = __ballot(valid);
-#pragma unroll
-        for (uint32_t b = 0; b < 8; b++) {
-            const bool bit = (d >> b) & 1u;
-            const uint64_t bb = __ballot(valid && bit);
-            peers &= bit ? bb : ~bb;
-        }
-        if (valid && lane == (uint32_t)__ffsll((long long)peers) - 1) wc[w][d] += (uint32_t)__popcll(peers);
-    }
-    __syncthreads();
-    if (w == 0) {       // exclusive offsets: digit-major, wave-minor (lane owns digits 4 lane .. 4 lane + 3)
-        uint32_t sum = 0;
-#pragma unroll 1
-        for (uint32_t q = 0; q < SNW; q++) sum += wc[q][4 * lane] + wc[q][4 * lane + 1] + wc[q][4 * lane + 2] +
-                                                  wc[q][4 * lane + 3];
-        uint32_t incl = sum;
-#pragma unroll
-        for (int o = 1; o < WAVE; o <<= 1) {
-            const uint32_t y = __shfl_up(incl, o);
-            if ((int)lane >= o) incl += y;
-        }
-        uint32_t run = incl - sum;
-#pragma unroll 1
-        for (uint32_t r = 0; r < 4; r++)
-#pragma unroll 1
-            for (uint32_t q = 0; q < SNW; q++) {
-                const uint32_t x = wc[q][4 * lane + r];
-                wc[q][4 * lane + r] = run;
-                run += x;
-            }
-    }
-    __syncthreads();
-    for (uint32_t base = c0; base < c1; base += WAVE) {
-        const bool valid = base + lane < c1;
-        const uint64_t key = valid ? src[base + lane] : 0ull;
-        const uint32_t d = valid ? digit_of(key, vk, shift, bits) : 0u;
-        uint64_t peers = __ballot(valid);
-#pragma unroll
-        for (uint32_t b = 0; b < 8; b++) {
-            const bool bit = (d >> b) & 1u;
-            const uint64_t bb = __ballot(valid && bit);
-            peers &= bit ? bb : ~bb;
-        }
-        const uint32_t leader = valid ? (uint32_t)__ffsll((long long)peers) - 1 : 0u;
-        uint32_t old = 0;
-        if (valid && lane == leader) {
-            old = wc[w][d];
-            wc[w][d] = old + (uint32_t)__popcll(peers);
-        }
-        old = __shfl(old, (int)leader);
-        if (valid) dst[old + (uint32_t)__popcll(peers & lt)] = key;
-    }
-    __syncthreads();
-}
-
-// All passes over keys[0..n) ping-ponging with alt; the result is in keys when
-// the number of passes is even, else in alt.
-__global__ void __launch_bounds__(SWG) k_rs_small(uint64_t *__restrict__ keys, uint64_t *__restrict__ alt, uint32_t n,
-                                                  VKey vk, uint32_t hi) {
-    __shared__ uint32_t wc[SNW][256];
     uint64_t *a = keys, *b = alt;
     for (uint32_t sh = 0; sh < hi; sh += 8) {
-        small_pass(a, b, n, vk, sh, (hi - sh) < 8 ? (hi - sh) : 8, wc);
-        __threadfence();        // the next pass reads what other waves wrote
+        const uint32_t bits = (hi - sh) < 8 ? (hi - sh) : 8;
+        {   // all loads in flight before the first LDS store
+            constexpr int R = (int)(SMALL_N / SWG);
+            uint64_t v[R];
+#pragma unroll
+            for (int j = 0; j < R; j++) {
+                const uint32_t i = threadIdx.x + (uint32_t)j * SWG;
+                v[j] = i < n ? a[i] : 0ull;
+            }
+#pragma unroll
+            for (int j = 0; j < R; j++) {
+                const uint32_t i = threadIdx.x + (uint32_t)j * SWG;
+                if (i < n) stage[i] = v[j];
+            }
+        }
+        for (uint32_t d = lane; d < 256; d += WAVE) wc[w][d] = 0;
         __syncthreads();
+        for (uint32_t base = c0; base < c1; base += WAVE) {
+            const bool valid = base + lane < c1;
+            const uint32_t d = valid ? digit_of(stage[base + lane], vk, sh, bits) : 0u;
+            const uint64_t peers = digit_peers(d, valid);
+            if (valid && lane == (uint32_t)__ffsll((long long)peers) - 1) wc[w][d] += (uint32_t)__popcll(peers);
+        }
+        __syncthreads();
+        // thread d < 256: digit d summed over the waves, exclusive scan over
+        // digits (waves of 64 digits, then the four wave totals), and the
+        // per-wave starts of digit d in wave order
+        uint32_t dsum = 0, dincl = 0;
+        if (threadIdx.x < 256) {
+#pragma unroll
+            for (int q = 0; q < SNW; q++) dsum += wc[q][threadIdx.x];
+            dincl = dsum;
+#pragma unroll
+            for (int o = 1; o < WAVE; o <<= 1) {
+                const uint32_t y = __shfl_up(dincl, o);
+                if ((int)lane >= o) dincl += y;
+            }
+            if (lane == WAVE - 1) wtot[w] = dincl;
+        }
+        __syncthreads();
+        if (threadIdx.x < 256) {
+            uint32_t run = dincl - dsum;
+            for (uint32_t q = 0; q < w; q++) run += wtot[q];
+#pragma unroll
+            for (int q = 0; q < SNW; q++) {
+                const uint32_t x = wc[q][threadIdx.x];
+                wc[q][threadIdx.x] = run;
+                run += x;
+            }
+        }
+        __syncthreads();
+        for (uint32_t base = c0; base < c1; base += WAVE) {
+            const bool valid = base + lane < c1;
+            const uint64_t key = valid ? stage[base + lane] : 0ull;
+            const uint32_t d = valid ? digit_of(key, vk, sh, bits) : 0u;
+            const uint64_t peers = digit_peers(d, valid);
+            const uint32_t leader = valid ? (uint32_t)__ffsll((long long)peers) - 1 : 0u;
+            uint32_t old = 0;
+            if (valid && lane == leader) {
+                old = wc[w][d];
+                wc[w][d] = old + (uint32_t)__popcll(peers);
+            }
+            old = __shfl(old, (int)leader);
+            if (valid) b[old + (uint32_t)__popcll(peers & lt)] = key;
+        }
+        __syncthreads();        // the next pass reads what other waves wrote (one CU: the barrier suffices)
         uint64_t *t = a; a = b; b = t;
     }
 }
@@ -305,14 +321,23 @@ hipError_t radix_sort(uint64_t *keys, uint64_t n, const VKey &vk, SortScratch &s
     *out = keys;
     if (n <= 1 || vk.vbits == 0) return hipSuccess;
     if (n <= SMALL_N) {
-        hipLaunchKernelGGL(k_rs_small, dim3(1), dim3(SWG), 0, s, keys, sc.alt, (uint32_t)n, vk, vk.vbits);
+        static bool attr_set = false;
+        if (!attr_set) {
+            hipError_t e = hipFuncSetAttribute((const void *)k_rs_small, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               (int)(SMALL_N * 8));
+            if (e != hipSuccess) return e;
+            attr_set = true;
+        }
+        hipLaunchKernelGGL(k_rs_small, dim3(1), dim3(SWG), n * 8, s, keys, sc.alt, (uint32_t)n, vk, vk.vbits);
         *out = ((vk.vbits + 7) / 8) % 2 ? sc.alt : keys;
         return hipGetLastError();
     }
     switch (tile) {
+    case 1024: return sort_passes<4>(keys, n, vk, vk.vbits, sc, s, out);
     case 2048: return sort_passes<8>(keys, n, vk, vk.vbits, sc, s, out);
     case 8192: return sort_passes<32>(keys, n, vk, vk.vbits, sc, s, out);
-    default: return sort_passes<16>(keys, n, vk, vk.vbits, sc, s, out);
+    case 4096: return sort_passes<16>(keys, n, vk, vk.vbits, sc, s, out);
+    default: return sort_passes<8>(keys, n, vk, vk.vbits, sc, s, out);
     }
 }
 

@@ -26,9 +26,10 @@ COPY_BYTES = 1 << 30
 
 
 def kernel_source_digest() -> str:
-    """Digest of the sources of the interpreter kernels."""
+    """Digest of the sources of the free-run kernels (interpreter and
+    program-specialised)."""
     h = hashlib.sha256()
-    for f in ("kc_interp.hip", "kc_internal.h"):
+    for f in ("kc_internal.h", "kc_device.h", "kc_interp.hip", "kc_jit.hip"):
         with open(os.path.join(CSRC, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -25,7 +25,7 @@ import numpy as np
 from . import kc
 
 SPACE: Dict[str, Sequence[int]] = {
-    "sort_tile": (2048, 4096, 8192),
+    "sort_tile": (1024, 2048, 4096, 8192),
     "stage_bytes": (8192, 16384, 32768, 65536),
     "stage": (128, 256, 512),
     "local": (0, 1),

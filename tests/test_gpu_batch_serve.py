@@ -46,14 +46,14 @@ def test_batch_equals_alone_and_oracle(ctx):
 def test_sort_tile_invariance(ctx):
     jobs = W.config3_jobs(n=200, seed=77)
     base, bm = kc.run_jobs(ctx, jobs)
-    for tile in (2048, 8192):
+    for tile in (1024, 4096, 8192):
         ctx.set_option("sort_tile", tile)
         say(f"sort tile {tile}")
         reps, mems = kc.run_jobs(ctx, jobs)
         for i in range(len(jobs)):
             _same(base[i], reps[i], f"tile {tile} job {i}")
             assert torch.equal(bm[i], mems[i])
-    ctx.set_option("sort_tile", 4096)
+    ctx.set_option("sort_tile", 2048)
 
 
 def test_served_mix_equals_alone(ctx):
