@@ -109,8 +109,19 @@ struct Workspace {
     DBuf units, items, comp_off, comp_blocks, mask;
     DBuf snap, log, alt, rlog, ralt, fs, hist, part;
     DBuf faults, rfaults, races, lraces, rlraces, edges, blk_recs, rblk_recs, blk_flags, rflags, ctr, rctr;
-    DBuf longseg;
+    DBuf longseg, covlist;
     DevCounters *h_ctr = nullptr;   // pinned
+    void *h_pin = nullptr;          // pinned staging of gathered device-to-host copies
+    size_t h_pin_bytes = 0;
+    void pin_reserve(size_t need) {
+        if (need <= h_pin_bytes) return;
+        if (h_pin) HIPCHK(hipHostFree(h_pin));
+        h_pin = nullptr;
+        h_pin_bytes = 0;
+        const size_t nb = std::max<size_t>(need + need / 2, 1 << 16);
+        HIPCHK(hipHostMalloc(&h_pin, nb, hipHostMallocDefault));
+        h_pin_bytes = nb;
+    }
     hipEvent_t ev[12] = {};
     bool init = false;
     void setup() {
@@ -122,7 +133,7 @@ struct Workspace {
     size_t device_bytes() const {
         const DBuf *all[] = {&units, &items, &comp_off, &comp_blocks, &mask, &snap, &log, &alt, &rlog,
                              &ralt, &fs, &hist, &part, &faults, &rfaults, &races, &edges, &blk_recs,
-                             &rblk_recs, &blk_flags, &rflags, &ctr, &rctr, &lraces, &rlraces, &longseg};
+                             &rblk_recs, &blk_flags, &rflags, &ctr, &rctr, &lraces, &rlraces, &longseg, &covlist};
         size_t s = 0;
         for (auto *b : all) s += b->bytes;
         return s;
@@ -130,9 +141,10 @@ struct Workspace {
     ~Workspace() {
         DBuf *all[] = {&units, &items, &comp_off, &comp_blocks, &mask, &snap, &log, &alt, &rlog,
                        &ralt, &fs, &hist, &part, &faults, &rfaults, &races, &edges, &blk_recs,
-                       &rblk_recs, &blk_flags, &rflags, &ctr, &rctr, &lraces, &rlraces, &longseg};
+                       &rblk_recs, &blk_flags, &rflags, &ctr, &rctr, &lraces, &rlraces, &longseg, &covlist};
         for (auto *b : all) b->release();
         if (h_ctr) (void)hipHostFree(h_ctr);
+        if (h_pin) (void)hipHostFree(h_pin);
         for (auto &e : ev)
             if (e) (void)hipEventDestroy(e);
     }
@@ -343,6 +355,44 @@ struct Stage {
         return VKey{kp.s_ep, used_epoch_bits, kp.s_blk, kp.s_ep, kp.s_ep + used_epoch_bits + (kp.total - kp.s_blk)};
     }
     std::vector<uint32_t> blk_recs;
+
+    // Device-to-host copies gathered into the pinned staging buffer and
+    // completed with one synchronisation (each one costs a round trip with the
+    // device idle).  Results are valid until the next fetch.
+    struct Fetch {
+        struct Item { const void *dev; size_t bytes, off; };
+        std::vector<Item> items;
+        size_t total = 0;
+        size_t add(const void *dev, size_t bytes) {
+            const size_t off = (total + 255) & ~size_t(255);
+            items.push_back(Item{dev, bytes, off});
+            total = off + bytes;
+            return items.size() - 1;
+        }
+    };
+    void run_fetch(Fetch &f) {
+        ws.pin_reserve(f.total);
+        for (auto &it : f.items)
+            if (it.bytes) HIPCHK(hipMemcpyAsync((char *)ws.h_pin + it.off, it.dev, it.bytes, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+    }
+    template <class T> const T *fetched(const Fetch &f, size_t i) const {
+        return (const T *)((const char *)ws.h_pin + f.items[i].off);
+    }
+    // Entries speculatively fetched with their counts; more need a second trip.
+    static constexpr uint32_t kSpec = 512;
+    template <class T> void take_list(const Fetch &f, size_t item, uint32_t count, uint32_t cap, const void *dev,
+                                      std::vector<T> &out) {
+        const uint32_t n = std::min(count, cap);
+        out.resize(n);
+        const uint32_t first = std::min(n, kSpec);
+        if (first) std::memcpy(out.data(), fetched<T>(f, item), (size_t)first * sizeof(T));
+        if (n > first) {
+            HIPCHK(hipMemcpyAsync(out.data() + first, (const T *)dev + first, (size_t)(n - first) * sizeof(T),
+                                  hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+        }
+    }
 
     DevCounters read_ctr(DBuf &c) {
         HIPCHK(hipMemcpyAsync(ws.h_ctr, c.p, sizeof(DevCounters), hipMemcpyDeviceToHost, s));
@@ -592,6 +642,7 @@ struct Stage {
         ws.blk_recs.reserve((size_t)total_blocks * 4);
         ws.blk_flags.reserve((size_t)total_blocks * 4);
         DevCounters c{};
+        Fetch fetch;
         for (;;) {
             ws.faults.reserve((size_t)fault_cap * sizeof(DevFault));
             ws.lraces.reserve((size_t)lrace_cap * sizeof(DevRace));
@@ -602,7 +653,13 @@ struct Stage {
             interp(false, ws.log, log_cap, ws.ctr, ws.faults, fault_cap, ws.blk_recs, 0, ws.lraces, lrace_cap,
                    ws.blk_flags);
             tm.mark(1);
-            c = read_ctr(ws.ctr);
+            fetch = Fetch{};
+            const size_t i_ctr = fetch.add(ws.ctr.p, sizeof(DevCounters));
+            fetch.add(ws.blk_recs.p, (size_t)total_blocks * 4);
+            fetch.add(ws.faults.p, (size_t)std::min(fault_cap, kSpec) * sizeof(DevFault));
+            fetch.add(ws.lraces.p, (size_t)std::min(lrace_cap, kSpec) * sizeof(DevRace));
+            run_fetch(fetch);
+            c = *fetched<DevCounters>(fetch, i_ctr);
             ctx->stat_add("interp_ms", tm.ms(0, 1));
             ctx->stat_add("interp_launches", 1);
             if (c.flags & FLAG_EPOCH_OVERFLOW)
@@ -633,16 +690,11 @@ struct Stage {
         used_epoch_bits = bits_for((uint64_t)c.max_epoch + 2);   // one more value: representative records
 
         blk_recs.resize(total_blocks);
-        HIPCHK(hipMemcpyAsync(blk_recs.data(), ws.blk_recs.p, (size_t)total_blocks * 4, hipMemcpyDeviceToHost, s));
-        std::vector<DevFault> faults(std::min<uint32_t>(c.fault_count, fault_cap));
-        if (!faults.empty())
-            HIPCHK(hipMemcpyAsync(faults.data(), ws.faults.p, faults.size() * sizeof(DevFault),
-                                  hipMemcpyDeviceToHost, s));
-        std::vector<DevRace> lraces(std::min<uint32_t>(c.race_count, lrace_cap));
-        if (!lraces.empty())
-            HIPCHK(hipMemcpyAsync(lraces.data(), ws.lraces.p, lraces.size() * sizeof(DevRace),
-                                  hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
+        std::memcpy(blk_recs.data(), fetched<uint32_t>(fetch, 1), (size_t)total_blocks * 4);
+        std::vector<DevFault> faults;
+        std::vector<DevRace> lraces;
+        take_list(fetch, 2, c.fault_count, fault_cap, ws.faults.p, faults);
+        take_list(fetch, 3, c.race_count, lrace_cap, ws.lraces.p, lraces);
         {
             uint64_t total = 0;
             for (uint32_t v : blk_recs) total += v;
@@ -708,9 +760,11 @@ struct Stage {
     }
 
     // Conflict check over sorted records: races and cross-block links to the
-    // host, racy blocks flagged in `flags`.
+    // host, racy blocks flagged in `flags`.  `extra` (device counters of work
+    // queued before the check, or null) comes back in the same trip.
     void run_check(const uint64_t *sorted, uint64_t n, DBuf &flags, std::vector<DevRace> &races,
-                   std::vector<DevEdge> &edges, bool zero_flags = true) {
+                   std::vector<DevEdge> &edges, bool zero_flags = true, const DevCounters *extra = nullptr,
+                   DevCounters *extra_out = nullptr) {
         uint32_t race_cap = 4096, edge_cap = 4096;
         flags.reserve((size_t)std::max<uint32_t>(total_blocks, 1) * 4);
         ws.longseg.reserve(check_long_cap(n) * 8);
@@ -732,21 +786,21 @@ struct Stage {
             ca.ctr = ws.rctr.as<DevCounters>();
             ca.longseg = ws.longseg.as<uint64_t>();
             HIPCHK(launch_check(ca, s));
-            DevCounters rc = read_ctr(ws.rctr);
+            Fetch f;
+            const size_t i_ctr = f.add(ws.rctr.p, sizeof(DevCounters));
+            const size_t i_r = f.add(ws.races.p, (size_t)std::min(race_cap, kSpec) * sizeof(DevRace));
+            const size_t i_e = f.add(ws.edges.p, (size_t)std::min(edge_cap, kSpec) * sizeof(DevEdge));
+            const size_t i_x = extra ? f.add(extra, sizeof(DevCounters)) : 0;
+            run_fetch(f);
+            const DevCounters rc = *fetched<DevCounters>(f, i_ctr);
+            if (extra) *extra_out = *fetched<DevCounters>(f, i_x);
             if (rc.flags & (FLAG_RACE_OVERFLOW | FLAG_EDGE_OVERFLOW)) {
                 race_cap = std::max(race_cap, rc.race_count + 1024);
                 edge_cap = std::max(edge_cap, rc.edge_count + 1024);
                 continue;
             }
-            races.resize(rc.race_count);
-            edges.resize(rc.edge_count);
-            if (!races.empty())
-                HIPCHK(hipMemcpyAsync(races.data(), ws.races.p, races.size() * sizeof(DevRace),
-                                      hipMemcpyDeviceToHost, s));
-            if (!edges.empty())
-                HIPCHK(hipMemcpyAsync(edges.data(), ws.edges.p, edges.size() * sizeof(DevEdge),
-                                      hipMemcpyDeviceToHost, s));
-            HIPCHK(hipStreamSynchronize(s));
+            take_list(f, i_r, rc.race_count, race_cap, ws.races.p, races);
+            take_list(f, i_e, rc.edge_count, edge_cap, ws.edges.p, edges);
             return;
         }
     }
@@ -766,8 +820,16 @@ struct Stage {
     }
 
     // One lockstep pass over `comps`; records go to ws.rlog (capacity rcap).
+    // One lockstep pass over `comps`; records go to ws.rlog (capacity rcap).
+    // With `res`, its findings, per-block record counts and local races come
+    // back in the same trip as the counters.
+    struct ReplayOut {
+        std::vector<DevFault> faults;
+        std::vector<uint32_t> recs;
+        std::vector<DevRace> lraces;
+    };
     DevCounters lockstep_once(const std::vector<std::vector<uint2>> &comps, uint64_t rcap, uint32_t fcap,
-                              uint32_t rlcap) {
+                              uint32_t rlcap, ReplayOut *res = nullptr) {
         upload_comps(comps);
         ws.rblk_recs.reserve((size_t)total_blocks * 4);
         ws.rflags.reserve((size_t)std::max<uint32_t>(total_blocks, 1) * 4);
@@ -778,9 +840,23 @@ struct Stage {
         HIPCHK(launch_zero(ws.rblk_recs.p, (size_t)total_blocks * 4, s));
         interp(true, ws.rlog, rcap, ws.rctr, ws.rfaults, fcap, ws.rblk_recs, (uint32_t)comps.size(), ws.rlraces,
                rlcap, ws.rflags);
-        DevCounters c = read_ctr(ws.rctr);
+        Fetch f;
+        const size_t i_ctr = f.add(ws.rctr.p, sizeof(DevCounters));
+        if (res) {
+            f.add(ws.rfaults.p, (size_t)std::min(fcap, kSpec) * sizeof(DevFault));
+            f.add(ws.rblk_recs.p, (size_t)total_blocks * 4);
+            f.add(ws.rlraces.p, (size_t)std::min(rlcap, kSpec) * sizeof(DevRace));
+        }
+        run_fetch(f);
+        const DevCounters c = *fetched<DevCounters>(f, i_ctr);
         if (c.flags & FLAG_EPOCH_OVERFLOW)
             throw KcError{KC_E_OVERFLOW, "barrier epochs exceed the record's epoch field"};
+        if (res && !(c.flags & (FLAG_LOG_OVERFLOW | FLAG_FAULT_OVERFLOW | FLAG_RACE_OVERFLOW))) {
+            res->recs.resize(total_blocks);
+            std::memcpy(res->recs.data(), fetched<uint32_t>(f, 2), (size_t)total_blocks * 4);
+            take_list(f, 1, c.fault_count, fcap, ws.rfaults.p, res->faults);
+            take_list(f, 3, c.race_count, rlcap, ws.rlraces.p, res->lraces);
+        }
         return c;
     }
 
@@ -820,7 +896,8 @@ struct Stage {
         HIPCHK(launch_restore(sorted, nrec, kp, ws.units.as<DevUnit>(), ws.blk_flags.as<uint32_t>(), s));
         uint64_t rcap = s_recs + s_recs / 4 + 1024;
         uint32_t fcap = 4096, rlcap = 4096 + (uint32_t)races.size() * 2;
-        DevCounters rc = lockstep_once(comps, rcap, fcap, rlcap);
+        ReplayOut ro;
+        DevCounters rc = lockstep_once(comps, rcap, fcap, rlcap, &ro);
         tm.mark(7);
         ctx->stat_add("replay_lockstep_ms", tm.ms(5, 7));
         bool ok = !(rc.flags & (FLAG_LOG_OVERFLOW | FLAG_FAULT_OVERFLOW | FLAG_RACE_OVERFLOW));
@@ -830,32 +907,28 @@ struct Stage {
             used_epoch_bits = std::max(used_epoch_bits, bits_for((uint64_t)rc.max_epoch + 2));
             uint64_t *rs = sort_check(ws.rlog, ws.ralt, rc.log_count);
             tm.mark(8);
-            run_check(rs, rc.log_count, ws.rflags, rr, re);
-            tm.mark(9);
-            ctx->stat_add("replay_sort_ms", tm.ms(7, 8));
-            ctx->stat_add("replay_check_ms", tm.ms(8, 9));
+            // the exactness check is queued first; its flag returns with the
+            // conflict check's results
             reset_counters(ws.ctr);
-            ws.longseg.reserve((size_t)rc.log_count * 8);
+            ws.covlist.reserve(std::max<uint64_t>(rc.log_count, 1) * 8);
             HIPCHK(launch_coverage(rs, rc.log_count, sorted, nrec, kp, ws.units.as<DevUnit>(),
                                    ws.blk_flags.as<uint32_t>(), ws.ctr.as<DevCounters>(),
-                                   ws.longseg.as<uint64_t>(), s));
-            ok = !(read_ctr(ws.ctr).flags & FLAG_MISMATCH);
+                                   ws.covlist.as<uint64_t>(), s));
             tm.mark(10);
-            ctx->stat_add("replay_coverage_ms", tm.ms(9, 10));
+            DevCounters cov{};
+            run_check(rs, rc.log_count, ws.rflags, rr, re, true, ws.ctr.as<DevCounters>(), &cov);
+            tm.mark(9);
+            ok = !(cov.flags & FLAG_MISMATCH);
+            ctx->stat_add("replay_sort_ms", tm.ms(7, 8));
+            ctx->stat_add("replay_coverage_ms", tm.ms(8, 10));
+            ctx->stat_add("replay_check_ms", tm.ms(10, 9));
             for (auto &e : re)
                 if (comp_of[ub_key(e.unit, e.b0)] != comp_of[ub_key(e.unit, e.b1)]) ok = false;
         }
         if (ok) {
-            std::vector<DevFault> rf(std::min<uint32_t>(rc.fault_count, fcap));
-            if (!rf.empty())
-                HIPCHK(hipMemcpyAsync(rf.data(), ws.rfaults.p, rf.size() * sizeof(DevFault), hipMemcpyDeviceToHost, s));
-            std::vector<uint32_t> rrecs(total_blocks);
-            HIPCHK(hipMemcpyAsync(rrecs.data(), ws.rblk_recs.p, (size_t)total_blocks * 4, hipMemcpyDeviceToHost, s));
-            std::vector<DevRace> rl(std::min<uint32_t>(rc.race_count, rlcap));
-            if (!rl.empty())
-                HIPCHK(hipMemcpyAsync(rl.data(), ws.rlraces.p, rl.size() * sizeof(DevRace), hipMemcpyDeviceToHost, s));
-            HIPCHK(hipStreamSynchronize(s));
-            rr.insert(rr.end(), rl.begin(), rl.end());
+            const std::vector<DevFault> &rf = ro.faults;
+            const std::vector<uint32_t> &rrecs = ro.recs;
+            rr.insert(rr.end(), ro.lraces.begin(), ro.lraces.end());
             std::vector<char> in_s(total_blocks, 0);
             for (auto &c : comps)
                 for (auto &ub : c) {
@@ -899,24 +972,19 @@ struct Stage {
         }
         rcap = std::max<uint64_t>(rcap, need + need / 4 + 1024);
         DevCounters fc;
+        ReplayOut fo;
         for (;;) {
             HIPCHK(launch_copy_units(ws.units.as<DevUnit>(), (uint32_t)hu.size(), max_words, false,
                                      ws.mask.as<uint32_t>(), s));
-            fc = lockstep_once(full, rcap, fcap, rlcap);
+            fc = lockstep_once(full, rcap, fcap, rlcap, &fo);
             if (!(fc.flags & (FLAG_LOG_OVERFLOW | FLAG_FAULT_OVERFLOW | FLAG_RACE_OVERFLOW))) break;
             rcap = std::max<uint64_t>(rcap, fc.log_count + 1024);
             fcap = std::max<uint32_t>(fcap, fc.fault_count + 1024);
             rlcap = std::max<uint32_t>(rlcap, fc.race_count + 1024);
         }
-        std::vector<DevFault> ff(std::min<uint32_t>(fc.fault_count, fcap));
-        if (!ff.empty())
-            HIPCHK(hipMemcpyAsync(ff.data(), ws.rfaults.p, ff.size() * sizeof(DevFault), hipMemcpyDeviceToHost, s));
-        std::vector<uint32_t> rrecs(total_blocks);
-        HIPCHK(hipMemcpyAsync(rrecs.data(), ws.rblk_recs.p, (size_t)total_blocks * 4, hipMemcpyDeviceToHost, s));
-        std::vector<DevRace> fl(std::min<uint32_t>(fc.race_count, rlcap));
-        if (!fl.empty())
-            HIPCHK(hipMemcpyAsync(fl.data(), ws.rlraces.p, fl.size() * sizeof(DevRace), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
+        const std::vector<DevFault> &ff = fo.faults;
+        const std::vector<uint32_t> &rrecs = fo.recs;
+        const std::vector<DevRace> &fl = fo.lraces;
         used_epoch_bits = std::max(used_epoch_bits, bits_for((uint64_t)fc.max_epoch + 2));
         uint64_t *rs = sort_check(ws.rlog, ws.ralt, fc.log_count);
         std::vector<DevRace> nr;
