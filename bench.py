@@ -228,7 +228,7 @@ def batched_vs_plain(ctx, W, kc, torch, np, reps=3, plain_sample=200, verify=40)
         res = batch.poll(batch.submit(prep, stream=stream), wait=True)
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t0)
-    records = sum(r.records for r in res)
+    records = res.total_records()
     best = min(times)
     idx = list(range(0, len(jobs), max(1, len(jobs) // plain_sample)))[:plain_sample]
     launches = [(ctx.program(jobs[i].launches[0].program), jobs[i].launches[0]) for i in idx]

@@ -209,6 +209,18 @@ const kc_fault *kc_report_faults(const kc_report *r, uint64_t *n);
 uint64_t kc_report_tag(const kc_report *r);
 void kc_report_free(kc_report *r);
 
+/* Many reports at once (a polled batch): for report i, records[i],
+ * launches[i], tags[i], n_races[i] and n_faults[i] (each array n entries or
+ * NULL); the races and findings of all reports concatenated in report order
+ * into `races` and `faults` (sized by the sums of n_races and n_faults, or
+ * NULL to skip).  Reports are not modified.  Errors: KC_E_INVAL for a null
+ * report pointer. */
+kc_status kc_reports_collect(kc_report *const *reports, uint32_t n, uint64_t *records, uint32_t *launches,
+                             uint64_t *tags, uint64_t *n_races, uint64_t *n_faults, kc_race *races,
+                             kc_fault *faults);
+/* Free n reports (null entries are skipped). */
+void kc_reports_free(kc_report *const *reports, uint32_t n);
+
 #ifdef __cplusplus
 }
 #endif

@@ -213,6 +213,19 @@ struct kc_ctx {
         std::lock_guard<std::mutex> g(mu);
         opt.log_records = std::max(opt.log_records, n);
     }
+    // Capacities of the finding and local-race lists, grown to what earlier
+    // stages needed so that a repeated workload does not interpret twice.
+    uint32_t fault_hint = 4096, lrace_hint = 4096;
+    void caps(uint32_t &faults, uint32_t &lraces) {
+        std::lock_guard<std::mutex> g(mu);
+        faults = fault_hint;
+        lraces = lrace_hint;
+    }
+    void note_caps(uint32_t faults, uint32_t lraces) {
+        std::lock_guard<std::mutex> g(mu);
+        fault_hint = std::max(fault_hint, faults);
+        lrace_hint = std::max(lrace_hint, lraces);
+    }
     void stat_add(const char *k, double v) {
         std::lock_guard<std::mutex> g(mu);
         stats[k] += v;
@@ -281,25 +294,6 @@ std::string validate_desc(const kc_launch_desc *d, int32_t *mem, uint64_t n_word
 // ---------------------------------------------------------------------------
 // union-find for racy components
 // ---------------------------------------------------------------------------
-struct DSU {
-    std::unordered_map<uint64_t, uint64_t> p;
-    uint64_t find(uint64_t x) {
-        auto it = p.find(x);
-        if (it == p.end()) { p[x] = x; return x; }
-        uint64_t r = x;
-        while (p[r] != r) r = p[r];
-        while (p[x] != r) { uint64_t n = p[x]; p[x] = r; x = n; }
-        return r;
-    }
-    void unite(uint64_t a, uint64_t b) {
-        a = find(a);
-        b = find(b);
-        if (a != b) p[std::max(a, b)] = std::min(a, b);
-    }
-};
-
-inline uint64_t ub_key(uint32_t unit, uint32_t block) { return ((uint64_t)unit << 32) | block; }
-
 bool fault_less(const kc_fault &x, const kc_fault &y) {
     const uint32_t kx[8] = {x.launch, x.block, x.epoch, x.kind, x.a, x.b, x.c, x.d};
     const uint32_t ky[8] = {y.launch, y.block, y.epoch, y.kind, y.a, y.b, y.c, y.d};
@@ -639,6 +633,7 @@ struct Stage {
         uint64_t log_cap = check ? std::max<uint64_t>(ctx->log_hint(), 1024) : 0;
         if (check) ws.log.reserve(log_cap * 8);
         uint32_t fault_cap = 4096;
+        ctx->caps(fault_cap, lrace_cap);
         ws.blk_recs.reserve((size_t)total_blocks * 4);
         ws.blk_flags.reserve((size_t)total_blocks * 4);
         DevCounters c{};
@@ -687,6 +682,7 @@ struct Stage {
         }
         ctx->stat_add("instructions", (double)c.instructions);
         if (check) ctx->note_log_records(c.log_count + c.log_count / 8);
+        ctx->note_caps(c.fault_count + c.fault_count / 8, c.race_count + c.race_count / 8);
         used_epoch_bits = bits_for((uint64_t)c.max_epoch + 2);   // one more value: representative records
 
         blk_recs.resize(total_blocks);
@@ -871,24 +867,42 @@ struct Stage {
                 uint64_t nrec, std::vector<std::vector<kc_fault>> &ufaults,
                 std::vector<std::vector<kc_race>> &uraces, std::vector<uint64_t> &urecs, Timer &tm) {
         tm.mark(5);
-        DSU dsu;
-        for (auto &r : races) dsu.find(ub_key(r.unit, r.block));
-        for (auto &e : edges) dsu.unite(ub_key(e.unit, e.b0), ub_key(e.unit, e.b1));
-        std::map<uint64_t, std::vector<uint2>> groups;
-        std::vector<uint64_t> keys;
-        for (auto &kv : dsu.p) keys.push_back(kv.first);
-        for (uint64_t k : keys) groups[dsu.find(k)].push_back(make_uint2((uint32_t)(k >> 32), (uint32_t)k));
-        std::vector<std::vector<uint2>> comps;
-        std::unordered_map<uint64_t, uint32_t> comp_of;
-        uint64_t s_recs = 0;
-        for (auto &kv : groups) {
-            auto v = kv.second;
-            std::sort(v.begin(), v.end(), [](uint2 a, uint2 b) { return a.x != b.x ? a.x < b.x : a.y < b.y; });
-            for (auto &ub : v) {
-                s_recs += blk_recs[hu[ub.x].block_base + ub.y];
-                comp_of[ub_key(ub.x, ub.y)] = (uint32_t)comps.size();
+        // components: racy blocks (global block index) united along the
+        // cross-block links; the root of a component is its smallest block
+        constexpr uint32_t NOT_RACY = 0xFFFFFFFFu;
+        std::vector<uint32_t> parent(total_blocks, NOT_RACY);
+        auto find = [&](uint32_t x) {
+            while (parent[x] != x) {
+                parent[x] = parent[parent[x]];
+                x = parent[x];
             }
-            comps.push_back(std::move(v));
+            return x;
+        };
+        auto mark = [&](uint32_t g) {
+            if (parent[g] == NOT_RACY) parent[g] = g;
+            return g;
+        };
+        for (auto &r : races) mark(hu[r.unit].block_base + r.block);
+        for (auto &e : edges) {
+            const uint32_t a = find(mark(hu[e.unit].block_base + e.b0)), b = find(mark(hu[e.unit].block_base + e.b1));
+            if (a != b) parent[std::max(a, b)] = std::min(a, b);
+        }
+        std::vector<std::vector<uint2>> comps;
+        std::vector<uint32_t> comp_of(total_blocks, NOT_RACY);
+        uint64_t s_recs = 0;
+        uint32_t unit = 0;
+        for (uint32_t g = 0; g < total_blocks; g++) {
+            if (parent[g] == NOT_RACY) continue;
+            while (unit + 1 < hu.size() && hu[unit + 1].block_base <= g) unit++;
+            const uint32_t root = find(g);
+            if (root == g) {
+                comp_of[g] = (uint32_t)comps.size();
+                comps.emplace_back();
+            } else {
+                comp_of[g] = comp_of[root];     // the root is smaller: already numbered
+            }
+            comps[comp_of[g]].push_back(make_uint2(unit, g - hu[unit].block_base));
+            s_recs += blk_recs[g];
         }
         ctx->stat_add("replays", (double)comps.size());
 
@@ -923,7 +937,7 @@ struct Stage {
             ctx->stat_add("replay_coverage_ms", tm.ms(8, 10));
             ctx->stat_add("replay_check_ms", tm.ms(10, 9));
             for (auto &e : re)
-                if (comp_of[ub_key(e.unit, e.b0)] != comp_of[ub_key(e.unit, e.b1)]) ok = false;
+                if (comp_of[hu[e.unit].block_base + e.b0] != comp_of[hu[e.unit].block_base + e.b1]) ok = false;
         }
         if (ok) {
             const std::vector<DevFault> &rf = ro.faults;
@@ -1352,5 +1366,32 @@ const kc_fault *kc_report_faults(const kc_report *r, uint64_t *n) {
 }
 uint64_t kc_report_tag(const kc_report *r) { return r ? r->tag : 0; }
 void kc_report_free(kc_report *r) { delete r; }
+
+kc_status kc_reports_collect(kc_report *const *reports, uint32_t n, uint64_t *records, uint32_t *launches,
+                             uint64_t *tags, uint64_t *n_races, uint64_t *n_faults, kc_race *races,
+                             kc_fault *faults) {
+    if (n && !reports) return KC_E_INVAL;
+    uint64_t ro = 0, fo = 0;
+    for (uint32_t i = 0; i < n; i++) {
+        const kc_report *r = reports[i];
+        if (!r) return KC_E_INVAL;
+        if (records) records[i] = r->records;
+        if (launches) launches[i] = r->launches_completed;
+        if (tags) tags[i] = r->tag;
+        if (n_races) n_races[i] = r->races.size();
+        if (n_faults) n_faults[i] = r->faults.size();
+        if (races && !r->races.empty()) std::memcpy(races + ro, r->races.data(), r->races.size() * sizeof(kc_race));
+        if (faults && !r->faults.empty())
+            std::memcpy(faults + fo, r->faults.data(), r->faults.size() * sizeof(kc_fault));
+        ro += r->races.size();
+        fo += r->faults.size();
+    }
+    return KC_OK;
+}
+
+void kc_reports_free(kc_report *const *reports, uint32_t n) {
+    if (!reports) return;
+    for (uint32_t i = 0; i < n; i++) delete reports[i];
+}
 
 }  // extern "C"

@@ -7,13 +7,16 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import collections.abc as cabc
 from dataclasses import dataclass
 from typing import Dict, List, Optional, Sequence, Tuple
 
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libkc.so")
+# The library built in-tree; KC_LIBRARY names another build of it (for
+# comparing build variants side by side).
+LIB_PATH = os.environ.get("KC_LIBRARY") or os.path.join(_HERE, "libkc.so")
 
 KC_OK, KC_E_INVAL, KC_E_PROGRAM, KC_E_NOMEM, KC_E_DEVICE, KC_E_PENDING, KC_E_BUDGET, KC_E_OVERFLOW = range(8)
 STATUS_NAMES = ["KC_OK", "KC_E_INVAL", "KC_E_PROGRAM", "KC_E_NOMEM", "KC_E_DEVICE", "KC_E_PENDING",
@@ -24,7 +27,7 @@ DEADLOCK, DIVERGENCE, OOB, FUEL, ARITH = 1, 2, 3, 4, 5
 EXPORTS = ["kc_ctx_create", "kc_ctx_destroy", "kc_ctx_set_option", "kc_ctx_get_stat", "kc_last_error",
            "kc_program_load", "kc_program_free", "kc_launch", "kc_batch_submit", "kc_poll",
            "kc_report_records", "kc_report_launches_completed", "kc_report_races", "kc_report_faults",
-           "kc_report_tag", "kc_report_free"]
+           "kc_report_tag", "kc_report_free", "kc_reports_collect", "kc_reports_free"]
 
 RACE_DTYPE = np.dtype([(f, "<u4") for f in ("launch", "space", "scope", "block", "epoch", "addr", "w_tid", "o_tid")])
 FAULT_DTYPE = np.dtype([(f, "<u4") for f in ("launch", "kind", "block", "epoch", "a", "b", "c", "d")])
@@ -79,6 +82,8 @@ def load_library(path: str = LIB_PATH):
         "kc_report_faults": ([vp, C.POINTER(u64)], vp),
         "kc_report_tag": ([vp], u64),
         "kc_report_free": ([vp], None),
+        "kc_reports_collect": ([vp, u32, vp, vp, vp, vp, vp, vp, vp], C.c_int),
+        "kc_reports_free": ([vp, u32], None),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -107,6 +112,51 @@ class Report:
 
     def fault_tuples(self) -> List[Tuple[int, ...]]:
         return [tuple(int(x) for x in f) for f in self.faults]
+
+
+class ReportList(cabc.Sequence):
+    """The reports of a polled batch, gathered with two library calls; a
+    Report is built when an item is accessed.  `records`, `launches_completed`
+    and `tags` are arrays over the batch."""
+
+    def __init__(self, lib, ptrs, n: int):
+        self.n = n
+        u64, u32 = np.uint64, np.uint32
+        self.records = np.zeros(n, u64)
+        self.launches_completed = np.zeros(n, u32)
+        self.tags = np.zeros(n, u64)
+        nr = np.zeros(n, u64)
+        nf = np.zeros(n, u64)
+        p = lambda a: a.ctypes.data if a.size else None
+        st = lib.kc_reports_collect(ptrs, n, p(self.records), p(self.launches_completed), p(self.tags), p(nr), p(nf),
+                                    None, None)
+        if st != KC_OK:
+            raise KcError(st, "kc_reports_collect")
+        self._races = np.zeros(int(nr.sum()), RACE_DTYPE)
+        self._faults = np.zeros(int(nf.sum()), FAULT_DTYPE)
+        st = lib.kc_reports_collect(ptrs, n, None, None, None, None, None, p(self._races), p(self._faults))
+        lib.kc_reports_free(ptrs, n)
+        if st != KC_OK:
+            raise KcError(st, "kc_reports_collect")
+        self._roff = np.concatenate([[0], np.cumsum(nr)]).astype(np.int64)
+        self._foff = np.concatenate([[0], np.cumsum(nf)]).astype(np.int64)
+
+    def __len__(self) -> int:
+        return self.n
+
+    def __getitem__(self, i):
+        if isinstance(i, slice):
+            return [self[j] for j in range(*i.indices(self.n))]
+        if i < 0:
+            i += self.n
+        if not 0 <= i < self.n:
+            raise IndexError(i)
+        return Report(int(self.records[i]), int(self.launches_completed[i]),
+                      self._races[self._roff[i]:self._roff[i + 1]].copy(),
+                      self._faults[self._foff[i]:self._foff[i + 1]].copy(), int(self.tags[i]))
+
+    def total_records(self) -> int:
+        return int(self.records.sum())
 
 
 def _take_report(lib, ptr) -> Report:
@@ -276,7 +326,7 @@ class Batch:
             return None
         self._keep.pop(ticket, None)
         self.ctx._check(st, "kc_poll")
-        return [_take_report(self.ctx.lib, out[i]) for i in range(n)]
+        return ReportList(self.ctx.lib, out, n)
 
 
 # ---------------------------------------------------------------------------

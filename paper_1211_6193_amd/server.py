@@ -159,11 +159,11 @@ class Server:
                     still.append((ticket, si, batch, mems))
                     continue
                 done = time.perf_counter() - t0
-                for r, rep, m in zip(batch, reps, mems):
+                records += int(reps.records.sum())
+                for i, (r, m) in enumerate(zip(batch, mems)):
                     r.done = done
-                    records += rep.records
                     if keep_reports:
-                        r.report = rep
+                        r.report = reps[i]
                     if keep_memory:
                         memories[r.rid] = m.cpu().numpy()
                 self.adm.finish(batch)
