@@ -19,6 +19,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <atomic>
 #include <condition_variable>
 #include <cstdio>
@@ -306,6 +307,15 @@ bool race_less(const kc_race &x, const kc_race &y) {
     return std::lexicographical_compare(kx, kx + 6, ky, ky + 6);
 }
 
+// Host time of a section, added to statistic `key` when timing is on.
+struct HostTimer {
+    kc_ctx *ctx;
+    const char *key;
+    bool on;
+    std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+    ~HostTimer();
+};
+
 struct Timer {
     kc_ctx *ctx;
     Workspace &ws;
@@ -323,6 +333,10 @@ struct Timer {
         return v;
     }
 };
+
+HostTimer::~HostTimer() {
+    if (on) ctx->stat_add(key, std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
+}
 
 // ---------------------------------------------------------------------------
 // one stage
@@ -610,7 +624,11 @@ struct Stage {
     }
 
     void run() {
-        plan();
+        HostTimer whole{ctx, "stage_host_ms", ctx->opt.timing != 0};
+        {
+            HostTimer ht{ctx, "host_plan_ms", ctx->opt.timing != 0};
+            plan();
+        }
         const uint32_t n = (uint32_t)hu.size();
         out.assign(n, UnitOut{});
         const bool check = ctx->opt.check != 0;
@@ -713,6 +731,7 @@ struct Stage {
             ctx->stat_add("sort_keys", (double)nrec);
         }
 
+        HostTimer post{ctx, "host_post_ms", ctx->opt.timing != 0};
         // per-unit findings of the free run
         std::vector<std::vector<kc_fault>> ufaults(n);
         for (auto &f : faults) ufaults[f.unit].push_back(kc_fault{0, f.kind, f.block, f.epoch, f.a, f.b, f.c, f.d});
@@ -1056,6 +1075,7 @@ void run_jobs(kc_ctx *ctx, const kc_job *jobs, uint32_t n_jobs, hipStream_t s, s
             Stage st{ctx, ws, s, in, out};
             st.run();
             ctx->stat_add("launches", (double)in.size());
+            HostTimer ht{ctx, "host_reports_ms", ctx->opt.timing != 0};
             for (size_t i = 0; i < who.size(); i++) {
                 kc_report *r = reports[who[i]];
                 UnitOut &o = out[i];
