@@ -41,6 +41,8 @@ def main():
     ap.add_argument("--jit", type=int, default=0, choices=(0, 1),
                     help="1: program-specialised free-run kernels; 0: the interpreter (default, faster on this "
                          "barrier- and shared-memory-heavy workload)")
+    ap.add_argument("--no-sort-path", action="store_true",
+                    help="skip the comparison of the in-LDS epoch-local check with the sort-only check")
     ap.add_argument("--serve-seconds", type=float, default=3.0, help="arrival window per served rate")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB three times (the known-size kernel that scales "
@@ -98,6 +100,7 @@ def main():
     per = {k: stats[k] / args.steps for k in ("interp_ms", "sort_ms", "check_ms", "replay_ms")}
     roofline = interp_roofline(stats, args.steps, records, value, per)
 
+    sort_path = None if args.no_sort_path else local_vs_sort(ctx, step, rep, mem, torch, np)
     batched, sample = (None, []) if args.no_batched else batched_vs_plain(ctx, W, kc, torch, np)
     serving = None if args.no_serve else served(ctx, W, torch, np, args.serve_seconds)
 
@@ -123,12 +126,14 @@ def main():
                    "replays_per_step": stats["replays"] / args.steps, "fallbacks": stats["fallbacks"]},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "shadow_vs_sort": sort_path,
         "batched_vs_plain": batched,
         "served": serving,
     }
     print(json.dumps(out), flush=True)
     ctx.close()
-    if exact is False or (batched and batched.get("bit_exact_sample") is False):
+    if exact is False or (batched and batched.get("bit_exact_sample") is False) or \
+            (sort_path and not sort_path["same_reports"]):
         sys.exit(1)
 
 
@@ -206,6 +211,35 @@ def cpu_baseline_leg(job, rep, mem, cpu_seconds, np, sample=()):
     cpu = {"value": round(orc.records * reps / cs, 1), "unit": "records/s", "cores": 1, "kind": "oracle",
            "sample": f"the whole workload run {reps}x by the single-threaded C oracle ({cs:.1f} s)"}
     return cpu, exact, sample_exact
+
+
+def local_vs_sort(ctx, step, rep, mem, torch, np, steps=10):
+    """The same step with the epoch-local check switched off (option "local" =
+    0): every access goes to the log and through the sort and the segmented
+    check.  Reports and final memory must equal the default path's."""
+    ref = mem.clone()
+    ctx.set_option("local", 0)
+    try:
+        for _ in range(2):
+            step()
+        ctx.reset_stats()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            r = step()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        st = {k: ctx.stat(k) / steps for k in ("interp_ms", "sort_ms", "check_ms", "replay_ms", "log_entries")}
+    finally:
+        ctx.set_option("local", 1)
+    same = (r.records == rep.records and r.race_tuples() == rep.race_tuples()
+            and r.fault_tuples() == rep.fault_tuples() and bool(torch.equal(mem, ref)))
+    if not same:
+        print("bench: the sort-only path differs from the epoch-local path", file=sys.stderr)
+    return {"sort_only_records_per_s": round(r.records * steps / el, 1), "sort_only_ms_per_step": round(el * 1e3 / steps, 4),
+            "sort_only_log_entries": st["log_entries"], "sort_only_stage_ms": {k: round(st[k], 4) for k in
+                                                                             ("interp_ms", "sort_ms", "check_ms", "replay_ms")},
+            "same_reports": same}
 
 
 def batched_vs_plain(ctx, W, kc, torch, np, reps=3, plain_sample=200, verify=40):

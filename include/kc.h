@@ -100,8 +100,11 @@ void kc_ctx_destroy(kc_ctx *ctx);
  * tile: 1024, 2048 (default), 4096 or 8192), "log_records" (initial log capacity, >= 1024),
  * "stage" (interpreter staging granule per wave: 128, 256, 512 or 1024
  * records), "stage_bytes" (LDS bytes of per-block record staging, 8192 to
- * 98304), "local" (1 = check shared accesses and sort staged global records
- * per barrier epoch inside the interpreter, default; 0 = log every access),
+ * 98304, default 8192), "local" (1 = check each barrier epoch's accesses inside
+ * the interpreter, default: shared words through per-word access tuples,
+ * global locations as set by "shadow_global"; 0 = log every access),
+ * "shadow_global" (1 = global locations through an LDS table of per-location
+ * access tuples, default; 0 = stage their records and sort them per epoch),
  * "jit" (1 = run free runs on program-specialised kernels: each program is
  * translated to HIP and compiled with hiprtc for gfx950 at its first launch,
  * once per process, which takes seconds; results are identical to the

@@ -127,6 +127,7 @@ struct Shared {
     uint32_t *wc;       // nwaves x 256 digit counters (epoch-local sort)
     uint32_t *tmp;      // 256 words
     unsigned long long *shadow;   // per simulated shared word: access tuple of the current epoch
+    unsigned long long *gst;      // global shadow table: per global location, its tuple of the epoch
     uint32_t *slots;    // 16 waves x 8 words: episode reductions
     uint32_t *slots2;   // 16 x 4: divergence second round
 };
@@ -267,6 +268,108 @@ __device__ __forceinline__ void shadow_update(unsigned long long *sh, uint32_t a
     }
 }
 
+// ---- global shadow table ------------------------------------------------------
+// The same tuple for the global locations a block touches in the current
+// epoch, kept in an open-addressing LDS table (linear probing).  A slot packs
+// the location and its tuple in one word, so inserting a location and
+// updating its tuple is one compare-and-swap:
+//   t1(11) | t2(11) | w(11) | address(31),   empty slot = all ones.
+// Tids are below 1024; 0x7FF is "none".  Locations need at most 31 bits.
+// A location that finds no slot within GST_PROBES probes, or no free slot
+// while the table is half full, is not absorbed: its access is staged as a
+// record instead and the epoch is marked overflowed; at the episode the
+// table's tuples then go to the log as records (at most three per location:
+// t1, t2 and the smallest writer, which reduce to the same tuple) together
+// with the staged ones, and the global check reduces them.
+constexpr unsigned long long GST_EMPTY = ~0ull;
+constexpr uint32_t GT_NONE = 0x7FFu;
+constexpr uint32_t GST_PROBES = 16;
+
+__device__ __forceinline__ unsigned long long gst_tuple(uint32_t t1, uint32_t t2, uint32_t w) {
+    return (unsigned long long)t1 | ((unsigned long long)t2 << 11) | ((unsigned long long)w << 22);
+}
+__device__ __forceinline__ uint32_t gst_addr(unsigned long long s) { return (uint32_t)(s >> 33); }
+
+// Merge tuple `u` (t1, t2, w fields) into slot word `s`.
+__device__ __forceinline__ unsigned long long gst_merge(unsigned long long s, unsigned long long u) {
+    uint32_t t1 = (uint32_t)s & GT_NONE, t2 = (uint32_t)(s >> 11) & GT_NONE, w = (uint32_t)(s >> 22) & GT_NONE;
+    const uint32_t u1 = (uint32_t)u & GT_NONE, u2 = (uint32_t)(u >> 11) & GT_NONE, v = (uint32_t)(u >> 22) & GT_NONE;
+    w = min(w, v);
+#pragma unroll
+    for (int q = 0; q < 2; q++) {
+        const uint32_t x = q ? u2 : u1;
+        if (x < t1) { t2 = t1; t1 = x; }
+        else if (x != t1 && x < t2) t2 = x;
+    }
+    return (s & ~((1ull << 33) - 1ull)) | gst_tuple(t1, t2, w);
+}
+
+// Absorb tuple `u` of location `addr`; false if the location found no slot.
+__device__ __forceinline__ bool gst_insert(unsigned long long *gst, uint32_t bits, uint32_t *occupied,
+                                           uint32_t addr, unsigned long long u) {
+    const uint32_t mask = (1u << bits) - 1u;
+    uint32_t slot = (addr * 2654435761u) >> (32 - bits);
+    for (uint32_t p = 0; p < GST_PROBES; p++) {
+        unsigned long long cur = gst[slot];
+        for (;;) {
+            if (cur == GST_EMPTY) {
+                if (__hip_atomic_load(occupied, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) > (mask >> 1))
+                    return false;                   // half full: no new locations
+                const unsigned long long prev =
+                    atomicCAS(&gst[slot], GST_EMPTY, ((unsigned long long)addr << 33) | u);
+                if (prev == GST_EMPTY) {
+                    atomicAdd(occupied, 1u);
+                    return true;
+                }
+                cur = prev;                         // taken meanwhile: look again
+                continue;
+            }
+            if (gst_addr(cur) != addr) break;       // another location: next slot
+            const unsigned long long nw = gst_merge(cur, u);
+            if (nw == cur) return true;
+            const unsigned long long prev = atomicCAS(&gst[slot], cur, nw);
+            if (prev == cur) return true;
+            cur = prev;
+        }
+        slot = (slot + 1u) & mask;
+    }
+    return false;
+}
+
+// An in-bounds global access (lanes with `inb`) under the epoch-local check:
+// absorbed into the global shadow table, else staged as record `key`.  When
+// every accessing lane of the wave names one location (a broadcast read, a
+// table entry), the wave's tuple -- its two lowest lanes, and the lowest as
+// writer for a store -- is inserted once.
+__device__ __forceinline__ void global_access(const InterpArgs &A, const BlockCtx &B, const Shared &S, LogState &L,
+                                              bool inb, uint32_t addr, bool store, uint64_t key) {
+    if (A.gst_bits == 0) {
+        log_rec(A, S.stage, L, inb, key);
+        return;
+    }
+    const uint64_t m = __ballot(inb);
+    if (m == 0) return;
+    const uint32_t first = (uint32_t)__ffsll((long long)m) - 1u;
+    const uint32_t a0 = (uint32_t)__shfl((int)addr, (int)first);
+    bool ok = false;
+    if (__ballot(inb && addr != a0) == 0) {
+        if (lane_id() == first) {
+            const uint64_t m2 = m & (m - 1ull);
+            const uint32_t t1 = B.tid, t2 = m2 ? B.wave * WAVE + (uint32_t)__ffsll((long long)m2) - 1u : GT_NONE;
+            ok = gst_insert(S.gst, A.gst_bits, &S.tmp[36], a0, gst_tuple(t1, t2, store ? t1 : GT_NONE));
+        }
+        ok = __shfl((int)ok, (int)first) != 0;
+    } else if (inb) {
+        ok = gst_insert(S.gst, A.gst_bits, &S.tmp[36], addr, gst_tuple(B.tid, GT_NONE, store ? B.tid : GT_NONE));
+    }
+    L.total += (uint32_t)__popcll(__ballot(inb && ok));
+    const bool miss = inb && !ok;
+    if (__ballot(miss)) {
+        if (lane_id() == 0) S.tmp[37] = 1u;         // the epoch overflowed the table
+        log_rec(A, S.stage, L, miss, key);
+    }
+}
+
 __device__ __forceinline__ uint32_t local_key(uint64_t r, const KeyPlan &k) {
     return (rec_field(r, k.s_sp, 1) << k.ab) | rec_field(r, k.s_addr, k.ab);
 }
@@ -390,6 +493,72 @@ __device__ __forceinline__ void local_segment_done(const InterpArgs &A, const Bl
     if (two) dst[at + 1] = base | ((uint64_t)st.minw << k.s_tid) | 1ull;
 }
 
+// Empty the global shadow table at an episode.  With `reduced`, each location
+// yields its intra-block race and its representatives (as from a reduced
+// segment); otherwise its tuple goes to the log as up to three records of the
+// epoch, for the global check.  The log space is reserved with one atomic per
+// block; S.tmp[32] must be zero on entry.
+__device__ __forceinline__ uint32_t gst_records(unsigned long long s, bool reduced) {
+    const uint32_t t1 = (uint32_t)s & GT_NONE, t2 = (uint32_t)(s >> 11) & GT_NONE, w = (uint32_t)(s >> 22) & GT_NONE;
+    if (reduced) return (w != GT_NONE && w != t1) ? 2u : 1u;
+    return 1u + (t2 != GT_NONE ? 1u : 0u) + ((w != GT_NONE && w != t1 && w != t2) ? 1u : 0u);
+}
+
+__device__ __forceinline__ void gst_drain(const InterpArgs &A, const BlockCtx &B, const Shared &S, uint32_t epoch,
+                                          bool reduced) {
+    const KeyPlan &k = A.kp;
+    const uint32_t C = 1u << A.gst_bits;
+    uint32_t mine = 0;
+    for (uint32_t i = threadIdx.x; i < C; i += blockDim.x) {
+        const unsigned long long v = S.gst[i];
+        if (v != GST_EMPTY) mine += gst_records(v, reduced);
+    }
+    uint32_t incl = mine;
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+        const uint32_t y = __shfl_up(incl, o);
+        if ((int)lane_id() >= o) incl += y;
+    }
+    const uint32_t wtot = (uint32_t)__shfl((int)incl, WAVE - 1);
+    uint32_t woff = 0;
+    if (lane_id() == WAVE - 1 && wtot) woff = atomicAdd(&S.tmp[32], wtot);
+    woff = (uint32_t)__shfl((int)woff, WAVE - 1);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t total = S.tmp[32];
+        unsigned long long base = 0;
+        if (total) {
+            base = atomicAdd(A.log_count, (unsigned long long)total);
+            if (base + total > A.log_cap) atomicOr(A.flags, FLAG_LOG_OVERFLOW);
+        }
+        S.tmp[33] = (uint32_t)base;
+        S.tmp[34] = (uint32_t)(base >> 32);
+    }
+    __syncthreads();
+    unsigned long long pos = ((unsigned long long)S.tmp[33] | ((unsigned long long)S.tmp[34] << 32)) + woff + incl - mine;
+    const uint64_t ep = reduced ? (uint64_t)k.ep_rep : (uint64_t)epoch;
+    for (uint32_t i = threadIdx.x; i < C; i += blockDim.x) {
+        const unsigned long long v = S.gst[i];
+        if (v == GST_EMPTY) continue;
+        S.gst[i] = GST_EMPTY;
+        const uint32_t t1 = (uint32_t)v & GT_NONE, t2 = (uint32_t)(v >> 11) & GT_NONE, w = (uint32_t)(v >> 22) & GT_NONE;
+        const uint32_t addr = gst_addr(v);
+        const uint64_t base = rec_pack(k, B.unit, 1u, addr, B.block, 0u, 0u, 0u) | (ep << k.s_ep);
+        uint64_t r[3];
+        uint32_t n = 0;
+        r[n++] = base | ((uint64_t)t1 << k.s_tid) | (w == t1 ? 1ull : 0ull);
+        if (reduced) {
+            if (w != GT_NONE && t2 != GT_NONE) push_local_race(A, B, 1u, epoch, addr, w, t1 == w ? t2 : t1);
+            if (w != GT_NONE && w != t1) r[n++] = base | ((uint64_t)w << k.s_tid) | 1ull;
+        } else {
+            if (t2 != GT_NONE) r[n++] = base | ((uint64_t)t2 << k.s_tid) | (w == t2 ? 1ull : 0ull);
+            if (w != GT_NONE && w != t1 && w != t2) r[n++] = base | ((uint64_t)w << k.s_tid) | 1ull;
+        }
+        for (uint32_t j = 0; j < n; j++, pos++)
+            if (pos < A.log_cap) A.log[pos] = r[j];
+    }
+}
+
 __device__ __forceinline__ void epoch_local_check(const InterpArgs &A, const BlockCtx &B, const Shared &S,
                                                   LogState &L, uint32_t epoch) {
     const KeyPlan &k = A.kp;
@@ -397,7 +566,9 @@ __device__ __forceinline__ void epoch_local_check(const InterpArgs &A, const Blo
         S.tmp[B.wave] = L.cur;
         S.tmp[16 + B.wave] = L.spilled ? 1u : 0u;
     }
+    if (threadIdx.x == 0) S.tmp[32] = 0;
     __syncthreads();
+    const uint32_t g_occupied = S.tmp[36], g_overflow = S.tmp[37];
     uint32_t n = 0, off = 0, spilled = 0;
     for (uint32_t w = 0; w < B.nwaves; w++) {
         const uint32_t c = S.tmp[w];
@@ -414,8 +585,15 @@ __device__ __forceinline__ void epoch_local_check(const InterpArgs &A, const Blo
         if (w != SH_NONE && t2 != SH_NONE) push_local_race(A, B, 0u, epoch, a, w, t1 == w ? t2 : t1);
         S.shadow[a] = SHADOW_EMPTY;
     }
-    // global memory: the staged records of the epoch
-    if (spilled) {              // the epoch's records go to the global check unreduced
+    // global memory: the table, or the staged records of the epoch
+    if (A.gst_bits) {
+        // Without an overflow nothing was staged and the table holds every
+        // location: reduce it here.  After one, the staged records and the
+        // table's tuples go to the global check unreduced.
+        const bool unreduced = spilled || g_overflow;
+        if (unreduced) flush_stage(A, S.stage, L.cur);
+        if (g_occupied) gst_drain(A, B, S, epoch, !unreduced);
+    } else if (spilled) {       // the epoch's records go to the global check unreduced
         flush_stage(A, S.stage, L.cur);
     } else if (n) {
         for (uint32_t i = lane_id(); i < L.cur; i += WAVE) S.alt[off + i] = S.stage[i];
@@ -492,7 +670,11 @@ __device__ __forceinline__ void epoch_local_check(const InterpArgs &A, const Blo
                 if (base + j < A.log_cap) A.log[base + j] = dst[j];
         }
     }
-    __syncthreads();            // the staging areas are free again
+    __syncthreads();            // the staging areas and the table are free again
+    if (threadIdx.x == 0) {
+        S.tmp[36] = 0;          // table occupancy
+        S.tmp[37] = 0;          // table overflow
+    }
     L.cur = 0;
     L.spilled = false;
 }
@@ -669,13 +851,15 @@ __device__ __forceinline__ void exec_one(const InterpArgs &A, const BlockCtx &B,
             }
         }
         const uint32_t space = is_sh ? 0u : 1u;
+        const uint64_t key = B.kep | ((uint64_t)space << k.s_sp) | (uint64_t)(is_st ? 1u : 0u) |
+                             ((uint64_t)(uint32_t)addr << k.s_addr);
         if (LOCAL && is_sh) {       // shared accesses update the shadow tuple instead of the log
             if (inb) shadow_update(S.shadow, (uint32_t)addr, B.tid, is_st);
             L.total += (uint32_t)__popcll(__ballot(inb));
+        } else if (LOCAL) {
+            global_access(A, B, S, L, inb, (uint32_t)addr, is_st, key);
         } else {
-            log_rec(A, S.stage, L, inb,
-                    B.kep | ((uint64_t)space << k.s_sp) | (uint64_t)(is_st ? 1u : 0u) |
-                        ((uint64_t)(uint32_t)addr << k.s_addr));
+            log_rec(A, S.stage, L, inb, key);
         }
         emit_fault(active && !inb, A, B, F_OOB, epoch, space * 2u + (is_st ? 1u : 0u), B.tid, (uint32_t)addr, 0);
     } else if (op == OP_MOV) {
@@ -709,6 +893,13 @@ __device__ __forceinline__ void setup_block(const InterpArgs &A, BlockCtx &B, co
     for (uint32_t i = threadIdx.x; i < B.sh_words; i += blockDim.x) S.sh[i] = 0;
     if (A.local)
         for (uint32_t i = threadIdx.x; i < B.sh_words; i += blockDim.x) S.shadow[i] = SHADOW_EMPTY;
+    if (A.gst_bits) {
+        for (uint32_t i = threadIdx.x; i < (1u << A.gst_bits); i += blockDim.x) S.gst[i] = GST_EMPTY;
+        if (threadIdx.x == 0) {
+            S.tmp[36] = 0;
+            S.tmp[37] = 0;
+        }
+    }
     t.pc = 0;
     t.st = (B.tid < B.nt) ? ST_RUN : ST_DEAD;
     t.fuel = u->fuel;
@@ -970,7 +1161,8 @@ __device__ __forceinline__ uint32_t run_block_lockstep(const InterpArgs &A, Bloc
 
 // LDS layout: simulated shared memory | staging (nwaves x stage records) |
 // [local check: second buffer of the same size | nwaves x 256 counters |
-// 256 words] | episode slots | [lockstep: store-owner tables].
+// 256 words | shared-word tuples | global shadow table] | episode slots |
+// [lockstep: store-owner tables].
 __device__ __forceinline__ size_t carve_lds(uint8_t *smem, const InterpArgs &A, Shared &S, uint32_t nwaves,
                                            uint32_t wave) {
     S.sh = (int32_t *)smem;
@@ -987,6 +1179,8 @@ __device__ __forceinline__ size_t carve_lds(uint8_t *smem, const InterpArgs &A, 
         off += 256 * 4;
         S.shadow = (unsigned long long *)(smem + off);
         off += (size_t)A.sh_words_max * 8;
+        S.gst = (unsigned long long *)(smem + off);
+        off += A.gst_bits ? ((size_t)8 << A.gst_bits) : 0;
     }
     S.slots = (uint32_t *)(smem + off);
     S.slots2 = S.slots + 16 * 8;

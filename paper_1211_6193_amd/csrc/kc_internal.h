@@ -115,13 +115,19 @@ struct InterpArgs {
     uint32_t *lrace_count;
     uint32_t *blk_flags;        // racy blocks
     unsigned long long *instructions;   // free run: thread-instructions executed (added to), or null
+    uint32_t gst_bits;          // local check: log2 slots of the global shadow table (0: stage and sort)
+    uint32_t pad;
 };
 
 #ifndef __HIPCC_RTC__
 // ---- host side ----------------------------------------------------------------
 // Launchers (defined in the .hip files).
 hipError_t launch_interp(const InterpArgs &a, uint32_t n_wg, uint32_t wg_threads, bool lockstep, hipStream_t s);
-size_t interp_lds_bytes(uint32_t sh_words_max, uint32_t wg_threads, uint32_t stage, bool lockstep, bool local);
+size_t interp_lds_bytes(uint32_t sh_words_max, uint32_t wg_threads, uint32_t stage, bool lockstep, bool local,
+                        uint32_t gst_bits);
+// Size (log2 slots) of the global shadow table for a workgroup: four slots per
+// thread, at least 256.
+uint32_t gst_bits_for(uint32_t wg_threads);
 
 struct SortScratch {
     uint64_t *alt = nullptr;         // ping-pong buffer, >= n keys

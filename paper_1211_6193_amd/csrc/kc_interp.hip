@@ -21,11 +21,19 @@ __global__ void __launch_bounds__(1024) k_interp_lockstep_local(InterpArgs A) { 
 
 }  // namespace
 
-size_t interp_lds_bytes(uint32_t sh_words_max, uint32_t wg_threads, uint32_t stage, bool lockstep, bool local) {
+uint32_t gst_bits_for(uint32_t wg_threads) {
+    uint32_t b = 8;
+    while ((1u << b) < 4u * wg_threads) b++;
+    return b;
+}
+
+size_t interp_lds_bytes(uint32_t sh_words_max, uint32_t wg_threads, uint32_t stage, bool lockstep, bool local,
+                        uint32_t gst_bits) {
     const uint32_t nwaves = (wg_threads + WAVE - 1) / WAVE;
     size_t off = ((size_t)sh_words_max * 4 + 15) & ~(size_t)15;
     off += (size_t)nwaves * stage * 8;
     if (local) off += (size_t)nwaves * stage * 8 + (size_t)nwaves * 256 * 4 + 256 * 4 + (size_t)sh_words_max * 8;
+    if (local && gst_bits) off += (size_t)8 << gst_bits;
     off += (16 * 8 + 16 * 4) * 4;
     if (lockstep) off += (size_t)sh_words_max * 4 + ((size_t)8 << lockstep_hash_bits(wg_threads));
     return off;
@@ -34,14 +42,22 @@ size_t interp_lds_bytes(uint32_t sh_words_max, uint32_t wg_threads, uint32_t sta
 hipError_t launch_interp(const InterpArgs &a, uint32_t n_wg, uint32_t wg_threads, bool lockstep, hipStream_t s) {
     if (n_wg == 0) return hipSuccess;
     InterpArgs args = a;
-    size_t lds = interp_lds_bytes(args.sh_words_max, wg_threads, args.stage, lockstep, args.local != 0);
+    if (!args.local) args.gst_bits = 0;
+    auto bytes = [&] {
+        return interp_lds_bytes(args.sh_words_max, wg_threads, args.stage, lockstep, args.local != 0, args.gst_bits);
+    };
+    size_t lds = bytes();
     while (lds > 160 * 1024 && args.stage > 64) {   // shrink the record staging area to fit
         args.stage = (args.stage / 2 + 63) / 64 * 64;
-        lds = interp_lds_bytes(args.sh_words_max, wg_threads, args.stage, lockstep, args.local != 0);
+        lds = bytes();
+    }
+    if (lds > 160 * 1024 && args.gst_bits) {          // no room for the table: stage and sort
+        args.gst_bits = 0;
+        lds = bytes();
     }
     if (lds > 160 * 1024 && args.local) {             // no room for the epoch-local check: log everything
         args.local = 0;
-        lds = interp_lds_bytes(args.sh_words_max, wg_threads, args.stage, lockstep, false);
+        lds = bytes();
     }
     if (lds > 160 * 1024) return hipErrorInvalidValue;
     static bool attr_set = false;

@@ -127,9 +127,15 @@ void gen_mem(std::ostringstream &o, const Instr &I) {
           << ");\n";
         o << "                L.total += (uint32_t)__popcll(__ballot(inb));\n            } else {\n    ";
     }
-    o << "            log_rec(A, S.stage, L, inb, B.kep | ((uint64_t)" << (sh ? 0 : 1) << "u << A.kp.s_sp) | "
-      << (st ? "1ull" : "0ull") << " | ((uint64_t)(uint32_t)addr << A.kp.s_addr));\n";
-    if (sh) o << "            }\n";
+    const std::string key = std::string("B.kep | ((uint64_t)") + (sh ? "0" : "1") + "u << A.kp.s_sp) | " +
+                            (st ? "1ull" : "0ull") + " | ((uint64_t)(uint32_t)addr << A.kp.s_addr)";
+    if (sh) {
+        o << "            log_rec(A, S.stage, L, inb, " << key << ");\n            }\n";
+    } else {
+        o << "            if (LOCAL) global_access(A, B, S, L, inb, (uint32_t)addr, " << (st ? "true" : "false") << ", "
+          << key << ");\n";
+        o << "            else log_rec(A, S.stage, L, inb, " << key << ");\n";
+    }
     o << "            emit_fault(act && !inb, A, B, F_OOB, epoch, " << ((sh ? 0 : 2) + (st ? 1 : 0))
       << "u, B.tid, (uint32_t)addr, 0);\n        }\n";
 }
@@ -377,14 +383,22 @@ hipError_t launch_jit(const JitFunctions &f, const InterpArgs &a, uint32_t n_wg,
                       hipStream_t s) {
     if (n_wg == 0) return hipSuccess;
     InterpArgs args = a;
-    size_t lds = interp_lds_bytes(args.sh_words_max, wg_threads, args.stage, false, args.local != 0);
+    if (!args.local) args.gst_bits = 0;
+    auto bytes = [&] {
+        return interp_lds_bytes(args.sh_words_max, wg_threads, args.stage, false, args.local != 0, args.gst_bits);
+    };
+    size_t lds = bytes();
     while (lds > 64 * 1024 && args.stage > 64) {
         args.stage = (args.stage / 2 + 63) / 64 * 64;
-        lds = interp_lds_bytes(args.sh_words_max, wg_threads, args.stage, false, args.local != 0);
+        lds = bytes();
+    }
+    if (lds > 64 * 1024 && args.gst_bits) {
+        args.gst_bits = 0;
+        lds = bytes();
     }
     if (lds > 64 * 1024 && args.local) {
         args.local = 0;
-        lds = interp_lds_bytes(args.sh_words_max, wg_threads, args.stage, false, false);
+        lds = bytes();
     }
     if (lds > 64 * 1024) return hipErrorInvalidValue;    // the caller falls back to the interpreter
     void *params[] = {&args};
@@ -393,7 +407,7 @@ hipError_t launch_jit(const JitFunctions &f, const InterpArgs &a, uint32_t n_wg,
 }
 
 bool jit_fits(uint32_t sh_words_max, uint32_t wg_threads) {
-    return interp_lds_bytes(sh_words_max, wg_threads, 64, false, false) <= 64 * 1024;
+    return interp_lds_bytes(sh_words_max, wg_threads, 64, false, false, 0) <= 64 * 1024;
 }
 
 }  // namespace kc

@@ -172,8 +172,9 @@ struct Options {
     uint32_t sort_tile = 2048;
     uint64_t log_records = 1ull << 22;
     uint32_t stage = 256;           // staged records per wave in the lockstep replay
-    uint32_t stage_bytes = 16384;   // LDS for staging + local sort per workgroup (free run)
+    uint32_t stage_bytes = 8192;    // LDS for staging + local sort per workgroup (free run)
     int local = 1;                  // epoch-local check in LDS
+    int shadow_global = 1;          // ... with global locations in an LDS shadow table (0: stage and sort)
     int jit = 0;                    // program-specialised free-run kernels (compiled at first use)
     int jit_waves = 0;              // their occupancy target, waves per SIMD (0: the compiler's choice)
 };
@@ -497,6 +498,8 @@ struct Stage {
         a.lrace_count = &ctr.as<DevCounters>()->race_count;
         a.blk_flags = flags.as<uint32_t>();
         a.instructions = lockstep ? nullptr : &ctr.as<DevCounters>()->instructions;
+        // the global shadow table packs a location in 31 bits
+        const bool gst = a.local && ctx->opt.shadow_global && kp.ab <= 31;
         if (lockstep) {
             a.stage = ctx->opt.stage;
             uint32_t wg = 64, shmax = 0;
@@ -507,6 +510,7 @@ struct Stage {
             a.comp_off = ws.comp_off.as<uint32_t>();
             a.comp_blocks = ws.comp_blocks.as<uint2>();
             a.sh_words_max = shmax;
+            a.gst_bits = gst ? gst_bits_for(wg) : 0u;
             HIPCHK(launch_interp(a, n_comp, wg, true, s));
             return;
         }
@@ -517,7 +521,8 @@ struct Stage {
         std::vector<JitFunctions> jf(hu.size());
         std::vector<char> use_jit(hu.size(), 0);
         for (uint32_t i = 0; i < hu.size(); i++) use_jit[i] = jit_for(i, jf[i]) ? 1 : 0;
-        auto launch = [&](const InterpArgs &args, uint32_t n_wg, uint32_t wg, bool jit, const JitFunctions &f) {
+        auto launch = [&](InterpArgs args, uint32_t n_wg, uint32_t wg, bool jit, const JitFunctions &f) {
+            args.gst_bits = gst ? gst_bits_for(wg) : 0u;
             if (jit) {
                 const hipError_t e = launch_jit(f, args, n_wg, wg, s);
                 if (e == hipSuccess) {
@@ -1187,6 +1192,7 @@ kc_status kc_ctx_set_option(kc_ctx *ctx, const char *key, int64_t v) {
     else if (k == "stage" && (v == 128 || v == 256 || v == 512 || v == 1024)) ctx->opt.stage = (uint32_t)v;
     else if (k == "stage_bytes" && v >= 8192 && v <= 98304) ctx->opt.stage_bytes = (uint32_t)v;
     else if (k == "local" && (v == 0 || v == 1)) ctx->opt.local = (int)v;
+    else if (k == "shadow_global" && (v == 0 || v == 1)) ctx->opt.shadow_global = (int)v;
     else if (k == "jit" && (v == 0 || v == 1)) ctx->opt.jit = (int)v;
     else if (k == "jit_waves" && (v == 0 || (v >= 2 && v <= 8))) ctx->opt.jit_waves = (int)v;
     else if (k == "reset" && v == 1) {
@@ -1214,6 +1220,7 @@ double kc_ctx_get_stat(kc_ctx *ctx, const char *key) {
         if (o == "stage") return op.stage;
         if (o == "stage_bytes") return op.stage_bytes;
         if (o == "local") return op.local;
+        if (o == "shadow_global") return op.shadow_global;
         if (o == "jit") return op.jit;
         if (o == "jit_waves") return op.jit_waves;
         return 0.0;

@@ -71,17 +71,18 @@ def test_served_mix_equals_alone(ctx):
 
 
 def test_local_check_modes_agree(ctx):
-    """Epoch-local checking in LDS, its spill path (tiny staging areas) and the
-    all-global path give identical reports and memory."""
+    """Epoch-local checking in LDS (global locations in the shadow table, or
+    staged and sorted), its spill path (tiny staging areas) and the all-global
+    path give identical reports and memory."""
     rng = np.random.default_rng(21)
     jobs = W.config3_jobs(n=150, seed=99) + [W.tree256_job(n_blocks=128, seed=4, drop_frac=0.05, div_frac=0.02)]
     jobs += [W.family_job(f, 5, t, rng, x, 2, 1) for f in W.FAMILIES for t in (64, 256, 1024)
              for x in (None,) + W.FAULTS[f]]
-    settings = [("local", 0), ("stage_bytes", 8192), ("stage_bytes", 98304), ("local", 1)]
+    settings = [("local", 0), ("stage_bytes", 8192), ("stage_bytes", 98304), ("local", 1),
+                ("shadow_global", 0), ("stage_bytes", 8192), ("shadow_global", 1)]
     for key, val in settings:
         ctx.set_option(key, val)
         say(f"{key}={val}")
         reps, mems = kc.run_jobs(ctx, jobs)
         for i, (j, r, m) in enumerate(zip(jobs, reps, mems)):
             assert_same(r, m, O.run_job(j), f"{key}={val} job {i}")
-    ctx.set_option("stage_bytes", 16384)
