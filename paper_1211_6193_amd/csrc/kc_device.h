@@ -789,9 +789,8 @@ struct Pending {
 // 2 conditional branch (cond per lane), 3 BAR/EXIT; target is the branch target.
 template <bool LOCKSTEP, bool LOCAL>
 __device__ __forceinline__ void exec_one(const InterpArgs &A, const BlockCtx &B, const Shared &S, Lane &t,
-                                         LogState &L, Pending &P, uint32_t epoch, int cur, bool active,
+                                         LogState &L, Pending &P, uint32_t epoch, int cur, uint64_t w, bool active,
                                          int &ctl, int &target, bool &cond) {
-    const uint64_t w = B.prog[(uint32_t)uni(cur)];
     const uint32_t op = uniu((uint32_t)w & 0xFFu);
     const uint32_t d = uniu((uint32_t)(w >> 8) & 0xFFu);
     const uint32_t ra = uniu((uint32_t)(w >> 16) & 0xFFu);
@@ -956,6 +955,11 @@ __device__ __forceinline__ uint32_t run_block_free(const InterpArgs &A, BlockCtx
     uint32_t guard = B.u->fuel;     // lower bound of every live lane's fuel
     for (;;) {
         for (;;) {
+            // The scheduling state is the same in every lane; reading it
+            // through lane 0 lets the compiler branch on it with scalar code.
+            conv = uni(conv ? 1 : 0) != 0;
+            upc = uni(upc);
+            guard = uniu(guard);
             uint64_t runm = __ballot(t.st == ST_RUN);
             if (runm == 0) break;
             int cur;
@@ -985,7 +989,8 @@ __device__ __forceinline__ uint32_t run_block_free(const InterpArgs &A, BlockCtx
             if (guard) guard--;
             int ctl, target;
             bool cond;
-            exec_one<false, LOCAL>(A, B, S, t, L, P, epoch, cur, active, ctl, target, cond);
+            exec_one<false, LOCAL>(A, B, S, t, L, P, epoch, cur, B.prog[(uint32_t)uni(cur)], active, ctl, target,
+                                   cond);
             if (ctl == 3) continue;                        // BAR/EXIT: lanes left the running set
             if (ctl == 2) {
                 uint64_t actm = __ballot(active);
@@ -1037,12 +1042,28 @@ constexpr uint32_t EMPTY_KEY = 0xFFFFFFFFu;
 
 __device__ __forceinline__ uint32_t ghash(uint32_t a, uint32_t hbits) { return (a * 2654435761u) >> (32 - hbits); }
 
+// The smallest pc among the lanes of `todo` (wave-uniform).  A converged
+// group -- every lane of `todo` at one pc -- needs no reduction.
+__device__ __forceinline__ int group_pc(uint64_t todo, int pc) {
+    const uint32_t first = (uint32_t)__ffsll((long long)todo) - 1u;
+    const int p0 = __builtin_amdgcn_readlane(pc, (int)first);
+    const bool mine = (todo >> lane_id()) & 1ull;
+    if (__ballot(mine && pc != p0) == 0) return uni(p0);
+    return uni(wave_min(mine ? pc : INT_MAX));
+}
+
+// The program word at `cur`, or 0 past the end.
+__device__ __forceinline__ uint64_t fetch_word(const BlockCtx &B, int cur) {
+    return (uint32_t)cur < B.n_instr ? B.prog[(uint32_t)uni(cur)] : 0ull;
+}
+
 // One step's group: the running lanes of the wave at the smallest pc among
 // `todo` execute their instruction (loads read memory now, stores are held in
 // P); returns the lanes that took part.
 template <bool LOCAL>
 __device__ __forceinline__ uint64_t lockstep_group(const InterpArgs &A, BlockCtx &B, const Shared &S, Lane &t,
-                                                   LogState &L, Pending &P, uint32_t epoch, uint64_t todo, int cur) {
+                                                   LogState &L, Pending &P, uint32_t epoch, uint64_t todo, int cur,
+                                                   uint64_t w) {
     const bool mine = (todo >> lane_id()) & 1ull;
     bool active = mine && t.pc == cur;
     const uint64_t done = __ballot(active);
@@ -1059,7 +1080,7 @@ __device__ __forceinline__ uint64_t lockstep_group(const InterpArgs &A, BlockCtx
     if (active) t.fuel--;
     int ctl, target;
     bool cond;
-    exec_one<true, LOCAL>(A, B, S, t, L, P, epoch, cur, active, ctl, target, cond);
+    exec_one<true, LOCAL>(A, B, S, t, L, P, epoch, cur, w, active, ctl, target, cond);
     if (active && ctl != 3) {
         if (ctl == 2) t.pc = cond ? target : cur + 1;
         else t.pc = target;
@@ -1095,13 +1116,13 @@ __device__ __forceinline__ uint32_t run_block_lockstep(const InterpArgs &A, Bloc
                 }
                 bool at_mem = false;
                 while (todo) {
-                    const bool mine = (todo >> lane_id()) & 1ull;
-                    const int cur = uni(wave_min(mine ? t.pc : INT_MAX));
-                    if ((uint32_t)cur < B.n_instr && ((uniu((uint32_t)B.prog[(uint32_t)cur]) & 0xFFu) >> 4) == 5u) {
+                    const int cur = group_pc(todo, t.pc);
+                    const uint64_t w = fetch_word(B, cur);
+                    if ((uint32_t)cur < B.n_instr && ((uniu((uint32_t)w) & 0xFFu) >> 4) == 5u) {
                         at_mem = true;
                         break;
                     }
-                    todo &= ~lockstep_group<LOCAL>(A, B, S, t, L, P, epoch, todo, cur);
+                    todo &= ~lockstep_group<LOCAL>(A, B, S, t, L, P, epoch, todo, cur, w);
                 }
                 if (at_mem) {
                     m = wstep;
@@ -1117,9 +1138,8 @@ __device__ __forceinline__ uint32_t run_block_lockstep(const InterpArgs &A, Bloc
             if (M == NO_STEP) break;                   // no running lane anywhere: barrier episode
             if (m == M) {           // finish step M, memory groups included
                 while (todo) {
-                    const bool mine = (todo >> lane_id()) & 1ull;
-                    const int cur = uni(wave_min(mine ? t.pc : INT_MAX));
-                    todo &= ~lockstep_group<LOCAL>(A, B, S, t, L, P, epoch, todo, cur);
+                    const int cur = group_pc(todo, t.pc);
+                    todo &= ~lockstep_group<LOCAL>(A, B, S, t, L, P, epoch, todo, cur, fetch_word(B, cur));
                 }
                 wstep++;
             }

@@ -57,11 +57,10 @@ std::string lit(int32_t v) {
     if (v == INT32_MIN) return "(-2147483647 - 1)";
     return "(" + std::to_string(v) + ")";
 }
-std::string label(uint32_t pc, uint32_t n) { return pc >= n ? std::string("BB_END") : "BB_" + std::to_string(pc); }
 
-// Spend fuel one instruction at a time (slow path of a block).
+// Spend fuel one instruction at a time (slow copy of a block).
 const char *kSlowFuel =
-    "        if (slow) {\n"
+    "        {\n"
     "            const bool nofuel = act && t.fuel == 0u;\n"
     "            if (__ballot(nofuel)) {\n"
     "                emit_fault(nofuel, A, B, F_FUEL, epoch, 0, B.tid, 0, 0);\n"
@@ -167,63 +166,76 @@ std::string jit_source(const uint64_t *words, uint32_t n, int waves) {
     for (uint32_t r = 0; r < 16; r++) o << "    int32_t r" << r << " = 0;\n";
     o << "    bool conv = true;\n    int upc = 0;\n    uint32_t guard = B.u->fuel;\n";
     o << "    for (;;) {\n      for (;;) {\n";
+    // the scheduling state is wave-uniform: reading it through lane 0 keeps
+    // the branches on it scalar
+    o << "        conv = uni(conv ? 1 : 0) != 0;\n        upc = uni(upc);\n        guard = uniu(guard);\n";
     o << "        const uint64_t runm = __ballot(t.st == ST_RUN);\n        if (runm == 0) break;\n";
-    o << "        int cur;\n        bool act;\n        bool slow;\n";
+    o << "        int cur;\n        bool act;\n";
     o << "        if (conv) {\n            cur = upc;\n            act = t.st == ST_RUN;\n        } else {\n";
     o << "            cur = uni(wave_min(t.st == ST_RUN ? t.pc : INT_MAX));\n";
     o << "            act = t.st == ST_RUN && t.pc == cur;\n";
     o << "            if (__ballot(act) == runm) { conv = true; upc = cur; }\n        }\n";
+    // One case per basic block; every block ends by naming the next pc
+    // (upc when converged, t.pc per lane otherwise) and returning to the
+    // dispatch, so the control flow stays reducible.
     o << "        switch (cur) {\n";
-    for (uint32_t s : starts) o << "        case " << s << ": goto BB_" << s << ";\n";
-    o << "        default: goto BB_END;\n        }\n";
+    auto next = [&](const std::string &pc) {
+        o << "            if (conv) upc = " << pc << ";\n            else if (act) t.pc = " << pc << ";\n"
+          << "            break;\n";
+    };
     for (size_t bi = 0; bi < starts.size(); bi++) {
         const uint32_t s = starts[bi];
         uint32_t e = s + 1;
         while (e < n && !lead[e]) e++;
         const uint32_t len = e - s;
-        o << "    BB_" << s << ":\n";
-        o << "        slow = guard < " << len << "u;\n";
-        o << "        if (!slow) {\n            guard -= " << len << "u;\n            if (act) t.fuel -= " << len
-          << "u;\n        }\n";
-        for (uint32_t pc = s; pc < e; pc++) {
-            const Instr I = decode(words[pc]);
-            o << "        // pc " << pc << "\n" << kSlowFuel;
-            const uint32_t base = I.op & ~uint32_t(OP_IMM);
-            if (base >= OP_ADD && base <= OP_SLTU) {
-                gen_alu(o, I, pc);
-            } else if ((I.op >> 4) == 5) {
-                gen_mem(o, I);
-            } else if (I.op == OP_MOV) {
-                o << "        if (act) " << reg(I.d) << " = " << reg(I.a) << ";\n";
-            } else if (I.op == OP_MOVI) {
-                o << "        if (act) " << reg(I.d) << " = " << lit(I.imm) << ";\n";
-            } else if (I.op == OP_SREG) {
-                o << "        if (act) " << reg(I.d) << " = special(B, " << (uint32_t)I.imm << "u);\n";
+        o << "        case " << s << ": {\n";
+        auto body = [&](bool checks) {
+            for (uint32_t pc = s; pc < e; pc++) {
+                const Instr I = decode(words[pc]);
+                o << "        // pc " << pc << "\n";
+                if (checks) o << kSlowFuel;
+                const uint32_t base = I.op & ~uint32_t(OP_IMM);
+                if (base >= OP_ADD && base <= OP_SLTU) {
+                    gen_alu(o, I, pc);
+                } else if ((I.op >> 4) == 5) {
+                    gen_mem(o, I);
+                } else if (I.op == OP_MOV) {
+                    o << "        if (act) " << reg(I.d) << " = " << reg(I.a) << ";\n";
+                } else if (I.op == OP_MOVI) {
+                    o << "        if (act) " << reg(I.d) << " = " << lit(I.imm) << ";\n";
+                } else if (I.op == OP_SREG) {
+                    o << "        if (act) " << reg(I.d) << " = special(B, " << (uint32_t)I.imm << "u);\n";
+                }
             }
-        }
-        o << "        if (slow) guard = wave_min_u((t.st == ST_RUN || t.st == ST_WAIT) ? t.fuel : 0xFFFFFFFFu);\n";
+        };
+        // fast copy: every live lane holds fuel for the whole block; slow
+        // copy: fuel checked and spent per instruction
+        o << "        const bool fast = guard >= " << len << "u;\n";
+        o << "        if (fast) {\n            guard -= " << len << "u;\n            if (act) t.fuel -= " << len << "u;\n";
+        body(false);
+        o << "        } else {\n";
+        body(true);
+        o << "            guard = uniu(wave_min_u((t.st == ST_RUN || t.st == ST_WAIT) ? t.fuel : 0xFFFFFFFFu));\n";
+        o << "        }\n";
         const Instr T = decode(words[e - 1]);
         if (T.op == OP_JMP) {
-            o << "        if (conv) goto " << label((uint32_t)T.imm, n) << ";\n";
-            o << "        if (act) t.pc = " << T.imm << ";\n        continue;\n";
+            next(std::to_string(T.imm));
         } else if (T.op == OP_BZ || T.op == OP_BNZ) {
-            o << "        {\n            const bool c = act && (" << reg(T.a) << (T.op == OP_BZ ? " == 0" : " != 0")
-              << ");\n";
+            o << "            const bool c = act && (" << reg(T.a) << (T.op == OP_BZ ? " == 0" : " != 0") << ");\n";
             o << "            const uint64_t am = __ballot(act), tk = __ballot(c);\n";
-            o << "            if (conv) {\n                if (tk == 0) goto " << label(e, n) << ";\n";
-            o << "                if (tk == am) goto " << label((uint32_t)T.imm, n) << ";\n";
-            o << "                conv = false;\n            }\n";
-            o << "            if (act) t.pc = c ? " << T.imm << " : " << e << ";\n            continue;\n        }\n";
+            o << "            if (conv && tk != 0 && tk != am) conv = false;\n";
+            o << "            if (conv) upc = tk ? " << T.imm << " : " << e << ";\n";
+            o << "            else if (act) t.pc = c ? " << T.imm << " : " << e << ";\n            break;\n";
         } else if (T.op == OP_BAR) {
-            o << "        if (act) { t.st = ST_WAIT; t.bar_pc = " << (e - 1) << "; }\n        continue;\n";
+            o << "            if (act) { t.st = ST_WAIT; t.bar_pc = " << (e - 1) << "; }\n            break;\n";
         } else if (T.op == OP_EXIT) {
-            o << "        if (act) t.st = ST_EXIT;\n        continue;\n";
+            o << "            if (act) t.st = ST_EXIT;\n            break;\n";
         } else {
-            o << "        if (conv) goto " << label(e, n) << ";\n";
-            o << "        if (act) t.pc = " << e << ";\n        continue;\n";
+            next(std::to_string(e));
         }
+        o << "        }\n";
     }
-    o << "    BB_END:\n        if (act) t.st = ST_EXIT;\n        continue;\n";
+    o << "        default:\n            if (act) t.st = ST_EXIT;\n            break;\n        }\n";
     o << "      }\n";
     o << "      if (barrier_episode<LOCAL>(A, B, S, t, L, epoch) == EP_DONE) break;\n";
     o << "      const int lo = wave_min(t.st == ST_RUN ? t.pc : INT_MAX);\n";
