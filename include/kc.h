@@ -117,7 +117,8 @@ kc_status kc_ctx_set_option(kc_ctx *ctx, const char *key, int64_t value);
  * "interp_ms", "sort_ms", "check_ms", "replay_ms", "launches", "records",
  * "replays", "fallbacks", "retries", "interp_launches", "sort_keys",
  * "instructions" (thread-instructions executed by the parallel free run; a
- * canonical replay of racy blocks is not counted), "jit_launches",
+ * canonical replay of racy blocks is not counted), "jit_launches", "jit_replays"
+ * (replay launches on specialised kernels),
  * "jit_compiled", "jit_compile_ms", "jit_failures".
  * Timings are only collected with option "timing" set.  "option.<name>"
  * reads back the current value of option <name>.  Returns 0 for an unknown

@@ -1060,10 +1060,13 @@ __device__ __forceinline__ uint64_t fetch_word(const BlockCtx &B, int cur) {
 // One step's group: the running lanes of the wave at the smallest pc among
 // `todo` execute their instruction (loads read memory now, stores are held in
 // P); returns the lanes that took part.
-template <bool LOCAL>
+// `exec(cur, w, active, P, epoch, ctl, target, cond)` executes the
+// instruction at `cur` (program word `w`) for the lanes with `active`, as
+// exec_one does in lockstep mode.
+template <bool LOCAL, class Exec>
 __device__ __forceinline__ uint64_t lockstep_group(const InterpArgs &A, BlockCtx &B, const Shared &S, Lane &t,
                                                    LogState &L, Pending &P, uint32_t epoch, uint64_t todo, int cur,
-                                                   uint64_t w) {
+                                                   uint64_t w, Exec &exec) {
     const bool mine = (todo >> lane_id()) & 1ull;
     bool active = mine && t.pc == cur;
     const uint64_t done = __ballot(active);
@@ -1080,7 +1083,7 @@ __device__ __forceinline__ uint64_t lockstep_group(const InterpArgs &A, BlockCtx
     if (active) t.fuel--;
     int ctl, target;
     bool cond;
-    exec_one<true, LOCAL>(A, B, S, t, L, P, epoch, cur, w, active, ctl, target, cond);
+    exec(cur, w, active, P, epoch, ctl, target, cond);
     if (active && ctl != 3) {
         if (ctl == 2) t.pc = cond ? target : cur + 1;
         else t.pc = target;
@@ -1097,9 +1100,15 @@ __device__ __forceinline__ uint64_t lockstep_group(const InterpArgs &A, BlockCtx
 // step's stores land with the highest tid winning per location -- the same
 // order as stepping every wave through every step together.  When no wave has
 // a running lane the block takes its barrier episode.
-template <bool LOCAL>
+//
+// `run(todo, epoch)` may execute, for a converged wave at the start of a step,
+// its memory-free instructions in one go (one step each, charging fuel and
+// leaving pc and state in `t`), stopping before a load or store; it returns
+// the number of steps taken, 0 when it took none.
+template <bool LOCAL, class Exec, class Run>
 __device__ __forceinline__ uint32_t run_block_lockstep(const InterpArgs &A, BlockCtx &B, const Shared &S,
-                                                   const StoreTables &T, Lane &t, LogState &L) {
+                                                   const StoreTables &T, Lane &t, LogState &L, Exec &exec,
+                                                   Run &run) {
     constexpr uint32_t NO_STEP = 0xFFFFFFFFu;
     uint32_t epoch = 0;
     uint32_t par = 0;               // round slots alternate so one barrier per round suffices
@@ -1113,6 +1122,12 @@ __device__ __forceinline__ uint32_t run_block_lockstep(const InterpArgs &A, Bloc
                 if (todo == 0) {
                     todo = __ballot(t.st == ST_RUN);
                     if (todo == 0) break;
+                    const uint32_t k = run(todo, epoch);
+                    if (k) {
+                        wstep += k;
+                        todo = 0;
+                        continue;
+                    }
                 }
                 bool at_mem = false;
                 while (todo) {
@@ -1122,7 +1137,7 @@ __device__ __forceinline__ uint32_t run_block_lockstep(const InterpArgs &A, Bloc
                         at_mem = true;
                         break;
                     }
-                    todo &= ~lockstep_group<LOCAL>(A, B, S, t, L, P, epoch, todo, cur, w);
+                    todo &= ~lockstep_group<LOCAL>(A, B, S, t, L, P, epoch, todo, cur, w, exec);
                 }
                 if (at_mem) {
                     m = wstep;
@@ -1139,7 +1154,7 @@ __device__ __forceinline__ uint32_t run_block_lockstep(const InterpArgs &A, Bloc
             if (m == M) {           // finish step M, memory groups included
                 while (todo) {
                     const int cur = group_pc(todo, t.pc);
-                    todo &= ~lockstep_group<LOCAL>(A, B, S, t, L, P, epoch, todo, cur, fetch_word(B, cur));
+                    todo &= ~lockstep_group<LOCAL>(A, B, S, t, L, P, epoch, todo, cur, fetch_word(B, cur), exec);
                 }
                 wstep++;
             }
@@ -1242,8 +1257,11 @@ __device__ __forceinline__ void interp_free_body(const InterpArgs &A) {
 }
 
 
-template <bool LOCAL>
-__device__ __forceinline__ void interp_lockstep_body(const InterpArgs &A) {
+// One workgroup of a replay launch: the blocks of one component in
+// ascending order, each run with `run(A, B, S, T, t, L)` (the interpreter's
+// lockstep loop, or one with program-specialised instruction bodies).
+template <class Run>
+__device__ __forceinline__ void lockstep_body(const InterpArgs &A, Run run) {
     extern __shared__ __align__(16) uint8_t smem[];
     Shared S;
     const uint32_t nwaves = (blockDim.x + WAVE - 1) / WAVE;
@@ -1270,9 +1288,22 @@ __device__ __forceinline__ void interp_lockstep_body(const InterpArgs &A) {
     for (uint32_t c = c0; c < c1; c++) {
         uint2 it = A.comp_blocks[c];
         setup_block(A, B, S, t, uniu(it.x), uniu(it.y));
-        const uint32_t epoch = run_block_lockstep<LOCAL>(A, B, S, T, t, L);
+        const uint32_t epoch = run(A, B, S, T, t, L);
         finish_block(A, B, S, L, t, epoch);
     }
+}
+
+template <bool LOCAL>
+__device__ __forceinline__ void interp_lockstep_body(const InterpArgs &A) {
+    lockstep_body(A, [](const InterpArgs &a, BlockCtx &b, const Shared &s, const StoreTables &tb, Lane &t,
+                        LogState &l) {
+        auto exec = [&](int cur, uint64_t w, bool active, Pending &P, uint32_t epoch, int &ctl, int &target,
+                        bool &cond) {
+            exec_one<true, LOCAL>(a, b, s, t, l, P, epoch, cur, w, active, ctl, target, cond);
+        };
+        auto run = [](uint64_t, uint32_t) { return 0u; };
+        return run_block_lockstep<LOCAL>(a, b, s, tb, t, l, exec, run);
+    });
 }
 
 }  // namespace

@@ -1,4 +1,4 @@
-// Program-specialised free-run kernels (host side).
+// Program-specialised free-run and replay kernels (host side).
 #pragma once
 #include <memory>
 #include <string>
@@ -12,6 +12,8 @@ struct JitFunctions {
     hipFunction_t local_256 = nullptr;    // epoch-local check, workgroups up to 256 threads
     hipFunction_t local_1024 = nullptr;   // epoch-local check, up to 1024 threads
     hipFunction_t free_1024 = nullptr;    // every access logged
+    hipFunction_t lock_local = nullptr;   // lockstep replay, epoch-local check
+    hipFunction_t lock = nullptr;         // lockstep replay, every access logged
 };
 
 // HIP source of the specialised kernels of a program (validated words);
@@ -35,5 +37,9 @@ std::string jit_log(const std::shared_ptr<JitEntry> &e);
 bool jit_fits(uint32_t sh_words_max, uint32_t wg_threads);
 hipError_t launch_jit(const JitFunctions &f, const InterpArgs &a, uint32_t n_wg, uint32_t wg_threads,
                       hipStream_t s);
+// A lockstep replay launch of one program's components (same arguments as
+// launch_interp with lockstep set); hipErrorInvalidValue if it does not fit.
+hipError_t launch_jit_lockstep(const JitFunctions &f, const InterpArgs &a, uint32_t n_wg, uint32_t wg_threads,
+                               hipStream_t s);
 
 }  // namespace kc

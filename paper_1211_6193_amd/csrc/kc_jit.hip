@@ -1,4 +1,4 @@
-// Program-specialised free-run kernels.
+// Program-specialised free-run and lockstep replay kernels.
 //
 // A KC-IR program is translated into HIP source in which every basic block is
 // straight-line code: the simulated registers are variables (real VGPRs, no
@@ -107,14 +107,19 @@ void gen_alu(std::ostringstream &o, const Instr &I, uint32_t pc) {
     o << "            const int32_t v = " << v << ";\n            if (act) " << d << " = v;\n        }\n";
 }
 
-void gen_mem(std::ostringstream &o, const Instr &I) {
+// A load or store; in lockstep mode a store is held in P until the step's
+// stores land.
+void gen_mem(std::ostringstream &o, const Instr &I, bool lockstep = false) {
     const bool sh = (I.op & 2u) == 0, st = (I.op & 1u) != 0;
     const char *lim = sh ? "B.sh_words" : "B.n_words";
     const char *arr = sh ? "S.sh" : "B.mem";
     o << "        {\n            const int32_t addr = (int32_t)((uint32_t)" << reg(I.a) << " + (uint32_t)" << lit(I.imm)
       << ");\n";
     o << "            const bool inb = act && (uint32_t)addr < " << lim << ";\n";
-    if (st) {
+    if (st && lockstep) {
+        o << "            if (inb) {\n                P.on = true;\n                P.shared = " << (sh ? "true" : "false")
+          << ";\n                P.addr = addr;\n                P.val = " << reg(I.b) << ";\n            }\n";
+    } else if (st) {
         o << "            if (inb) " << arr << "[addr] = " << reg(I.b) << ";\n";
     } else {
         o << "            int32_t v = 0;\n            if (inb) v = " << arr << "[addr];\n";
@@ -241,11 +246,111 @@ std::string jit_source(const uint64_t *words, uint32_t n, int waves) {
     o << "      const int lo = wave_min(t.st == ST_RUN ? t.pc : INT_MAX);\n";
     o << "      const int hi = wave_max(t.st == ST_RUN ? t.pc : -1);\n";
     o << "      conv = (lo == hi) || hi < 0;\n      upc = uni(lo);\n    }\n    return epoch;\n}\n\n";
+    // Lockstep replay: the interpreter's round protocol with one specialised
+    // case per instruction.
+    o << "template <bool LOCAL>\n__device__ __forceinline__ uint32_t jit_lock_run(const InterpArgs &A, BlockCtx &B, "
+         "const Shared &S, const StoreTables &T, Lane &t, LogState &L) {\n";
+    for (uint32_t r = 0; r < 16; r++) o << "    int32_t r" << r << " = 0;\n";
+    o << "    auto exec = [&](int cur, uint64_t, bool act, Pending &P, uint32_t epoch, int &ctl, int &target, "
+         "bool &cond) {\n";
+    o << "        ctl = 0;\n        target = cur + 1;\n        cond = false;\n        (void)P;\n";
+    o << "        switch (cur) {\n";
+    for (uint32_t pc = 0; pc < n; pc++) {
+        const Instr I = decode(words[pc]);
+        const uint32_t base = I.op & ~uint32_t(OP_IMM);
+        o << "        case " << pc << ": {\n";
+        if (base >= OP_ADD && base <= OP_SLTU) {
+            gen_alu(o, I, pc);
+        } else if ((I.op >> 4) == 5) {
+            gen_mem(o, I, true);
+        } else if (I.op == OP_MOV) {
+            o << "        if (act) " << reg(I.d) << " = " << reg(I.a) << ";\n";
+        } else if (I.op == OP_MOVI) {
+            o << "        if (act) " << reg(I.d) << " = " << lit(I.imm) << ";\n";
+        } else if (I.op == OP_SREG) {
+            o << "        if (act) " << reg(I.d) << " = special(B, " << (uint32_t)I.imm << "u);\n";
+        } else if (I.op == OP_JMP) {
+            o << "        ctl = 1;\n        target = " << I.imm << ";\n";
+        } else if (I.op == OP_BZ || I.op == OP_BNZ) {
+            o << "        ctl = 2;\n        target = " << I.imm << ";\n        cond = " << reg(I.a)
+              << (I.op == OP_BZ ? " == 0" : " != 0") << ";\n";
+        } else if (I.op == OP_BAR) {
+            o << "        ctl = 3;\n        if (act) {\n            t.st = ST_WAIT;\n            t.bar_pc = " << pc
+              << ";\n        }\n";
+        } else if (I.op == OP_EXIT) {
+            o << "        ctl = 3;\n        if (act) t.st = ST_EXIT;\n";
+        }
+        o << "        } break;\n";
+    }
+    o << "        default: break;\n        }\n    };\n";
+    // Converged memory-free runs: straight-line segments between loads and
+    // stores, one step per instruction.
+    std::vector<char> lead2(lead);
+    for (uint32_t pc = 0; pc < n; pc++)
+        if ((decode(words[pc]).op >> 4) == 5) lead2[pc] = lead2[pc + 1] = 1;
+    o << "    auto run = [&](uint64_t todo, uint32_t epoch) -> uint32_t {\n";
+    o << "        const bool act = (todo >> lane_id()) & 1ull;\n";
+    o << "        int upc = uni(__builtin_amdgcn_readlane(t.pc, (int)((uint32_t)__ffsll((long long)todo) - 1u)));\n";
+    o << "        if (__ballot(act && t.pc != upc)) return 0u;\n";
+    o << "        uint32_t fmin = uniu(wave_min_u(act ? t.fuel : 0xFFFFFFFFu));\n";
+    o << "        uint32_t steps = 0;\n        (void)epoch;\n";
+    o << "        for (;;) {\n            upc = uni(upc);\n            fmin = uniu(fmin);\n            switch (upc) {\n";
+    for (uint32_t s0 = 0; s0 < n; s0++) {
+        if (!lead2[s0] || (decode(words[s0]).op >> 4) == 5) continue;
+        uint32_t e = s0 + 1;
+        while (e < n && !lead2[e]) e++;
+        const uint32_t len = e - s0;
+        o << "            case " << s0 << ": {\n";
+        o << "                if (fmin < " << len << "u) goto out;\n";
+        o << "                fmin -= " << len << "u;\n                if (act) t.fuel -= " << len << "u;\n";
+        o << "                steps += " << len << "u;\n";
+        for (uint32_t pc = s0; pc < e; pc++) {
+            const Instr I = decode(words[pc]);
+            const uint32_t base = I.op & ~uint32_t(OP_IMM);
+            if (base >= OP_ADD && base <= OP_SLTU) {
+                gen_alu(o, I, pc);
+            } else if (I.op == OP_MOV) {
+                o << "        if (act) " << reg(I.d) << " = " << reg(I.a) << ";\n";
+            } else if (I.op == OP_MOVI) {
+                o << "        if (act) " << reg(I.d) << " = " << lit(I.imm) << ";\n";
+            } else if (I.op == OP_SREG) {
+                o << "        if (act) " << reg(I.d) << " = special(B, " << (uint32_t)I.imm << "u);\n";
+            }
+        }
+        const Instr T = decode(words[e - 1]);
+        if (T.op == OP_JMP) {
+            o << "                upc = " << T.imm << ";\n                continue;\n";
+        } else if (T.op == OP_BZ || T.op == OP_BNZ) {
+            o << "                const bool c = act && (" << reg(T.a) << (T.op == OP_BZ ? " == 0" : " != 0") << ");\n";
+            o << "                const uint64_t am = __ballot(act), tk = __ballot(c);\n";
+            o << "                if (tk == 0) { upc = " << e << "; continue; }\n";
+            o << "                if (tk == am) { upc = " << T.imm << "; continue; }\n";
+            o << "                if (act) t.pc = c ? " << T.imm << " : " << e << ";\n                return steps;\n";
+        } else if (T.op == OP_BAR) {
+            o << "                if (act) {\n                    t.st = ST_WAIT;\n                    t.bar_pc = " << (e - 1)
+              << ";\n                }\n                return steps;\n";
+        } else if (T.op == OP_EXIT) {
+            o << "                if (act) t.st = ST_EXIT;\n                return steps;\n";
+        } else {
+            o << "                upc = " << e << ";\n                continue;\n";
+        }
+        o << "            }\n";
+    }
+    o << "            default: goto out;\n            }\n        }\n";
+    o << "    out:\n        if (act) t.pc = upc;\n        return steps;\n    };\n";
+    o << "    return run_block_lockstep<LOCAL>(A, B, S, T, t, L, exec, run);\n}\n\n";
     o << "}  // namespace\n}  // namespace kc\n\n";
     // workgroups of up to 256 threads get the whole register file; larger ones
     // are bounded to 128 VGPRs
     const struct { const char *name; int bound; bool local; } kernels[] = {
         {"kc_jit_free_local_256", 256, true}, {"kc_jit_free_local_1024", 1024, true}, {"kc_jit_free_1024", 1024, false}};
+    for (const char *name : {"kc_jit_lock_local", "kc_jit_lock"}) {
+        const bool local = std::string(name) == "kc_jit_lock_local";
+        o << "extern \"C\" __global__ void __launch_bounds__(1024) " << name << "(kc::InterpArgs A) {\n";
+        o << "    kc::lockstep_body(A, [](const kc::InterpArgs &a, kc::BlockCtx &b, const kc::Shared &s, "
+             "const kc::StoreTables &tb, kc::Lane &t, kc::LogState &l) {\n";
+        o << "        return kc::jit_lock_run<" << (local ? "true" : "false") << ">(a, b, s, tb, t, l);\n    });\n}\n";
+    }
     for (const auto &k : kernels) {
         o << "extern \"C\" __global__ void __launch_bounds__(" << k.bound << ") ";
         if (waves > 0) o << "__attribute__((amdgpu_waves_per_eu(" << waves << ", " << waves << "))) ";
@@ -366,7 +471,9 @@ bool jit_functions(const std::shared_ptr<JitEntry> &e, int device, bool wait, Ji
         }
         if (hipModuleGetFunction(&f.local_256, mod, "kc_jit_free_local_256") != hipSuccess ||
             hipModuleGetFunction(&f.local_1024, mod, "kc_jit_free_local_1024") != hipSuccess ||
-            hipModuleGetFunction(&f.free_1024, mod, "kc_jit_free_1024") != hipSuccess) {
+            hipModuleGetFunction(&f.free_1024, mod, "kc_jit_free_1024") != hipSuccess ||
+            hipModuleGetFunction(&f.lock_local, mod, "kc_jit_lock_local") != hipSuccess ||
+            hipModuleGetFunction(&f.lock, mod, "kc_jit_lock") != hipSuccess) {
             (void)hipGetLastError();
             e->state = -1;
             e->log += "\nhipModuleGetFunction failed";
@@ -416,6 +523,33 @@ hipError_t launch_jit(const JitFunctions &f, const InterpArgs &a, uint32_t n_wg,
     void *params[] = {&args};
     hipFunction_t fn = !args.local ? f.free_1024 : (wg_threads <= 256 ? f.local_256 : f.local_1024);
     return hipModuleLaunchKernel(fn, n_wg, 1, 1, wg_threads, 1, 1, (unsigned)lds, s, params, nullptr);
+}
+
+hipError_t launch_jit_lockstep(const JitFunctions &f, const InterpArgs &a, uint32_t n_wg, uint32_t wg_threads,
+                               hipStream_t s) {
+    if (n_wg == 0) return hipSuccess;
+    InterpArgs args = a;
+    if (!args.local) args.gst_bits = 0;
+    auto bytes = [&] {
+        return interp_lds_bytes(args.sh_words_max, wg_threads, args.stage, true, args.local != 0, args.gst_bits);
+    };
+    size_t lds = bytes();
+    while (lds > 64 * 1024 && args.stage > 64) {
+        args.stage = (args.stage / 2 + 63) / 64 * 64;
+        lds = bytes();
+    }
+    if (lds > 64 * 1024 && args.gst_bits) {
+        args.gst_bits = 0;
+        lds = bytes();
+    }
+    if (lds > 64 * 1024 && args.local) {
+        args.local = 0;
+        lds = bytes();
+    }
+    if (lds > 64 * 1024) return hipErrorInvalidValue;    // the caller falls back to the interpreter
+    void *params[] = {&args};
+    return hipModuleLaunchKernel(args.local ? f.lock_local : f.lock, n_wg, 1, 1, wg_threads, 1, 1, (unsigned)lds, s,
+                                 params, nullptr);
 }
 
 bool jit_fits(uint32_t sh_words_max, uint32_t wg_threads) {

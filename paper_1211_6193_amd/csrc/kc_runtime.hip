@@ -511,6 +511,19 @@ struct Stage {
             a.comp_blocks = ws.comp_blocks.as<uint2>();
             a.sh_words_max = shmax;
             a.gst_bits = gst ? gst_bits_for(wg) : 0u;
+            // one program for every unit: its specialised replay kernels
+            bool one_program = true;
+            for (const auto &x : in) one_program = one_program && x.desc->prog == in[0].desc->prog;
+            JitFunctions f;
+            if (one_program && !hu.empty() && jit_for(0, f)) {
+                const hipError_t e = launch_jit_lockstep(f, a, n_comp, wg, s);
+                if (e == hipSuccess) {
+                    ctx->stat_add("jit_replays", 1);
+                    return;
+                }
+                if (e != hipErrorInvalidValue) HIPCHK(e);
+                (void)hipGetLastError();
+            }
             HIPCHK(launch_interp(a, n_comp, wg, true, s));
             return;
         }

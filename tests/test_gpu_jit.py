@@ -1,5 +1,6 @@
 """Program-specialised kernels: with option "jit" = 1 every free run compiles
-(at first use) and runs its program's specialised kernels, so these cases run
+(at first use) and runs its program's specialised kernels, and the replay of a
+single-program stage runs its specialised lockstep kernel, so these cases run
 the specialised code
 (checked through the "jit_launches" statistic) and must equal the CPU oracle
 bit for bit, like the interpreter.  Covers the Figure 1 variants, random tiny
@@ -77,6 +78,7 @@ def test_jit_families(ctx):
 def test_jit_workload2_full_size(ctx):
     say("jit workload 2 full size")
     _run(ctx, W.tree256_job(), "workload2")
+    assert ctx.stat("jit_replays") >= 1          # its racy blocks replay on specialised kernels
 
 
 def test_jit_edge_cases(ctx):
