@@ -38,9 +38,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the workload-3 batched vs plain comparison")
     ap.add_argument("--no-serve", action="store_true", help="skip the served-form measurement")
-    ap.add_argument("--jit", type=int, default=0, choices=(0, 1),
-                    help="1: program-specialised free-run kernels; 0: the interpreter (default, faster on this "
-                         "barrier- and shared-memory-heavy workload)")
+    ap.add_argument("--jit", type=int, default=1, choices=(0, 1),
+                    help="1: program-specialised free-run and replay kernels, compiled (hiprtc, gfx950) by the "
+                         "first warm-up step (default); 0: the interpreter")
     ap.add_argument("--no-sort-path", action="store_true",
                     help="skip the comparison of the in-LDS epoch-local check with the sort-only check")
     ap.add_argument("--serve-seconds", type=float, default=3.0, help="arrival window per served rate")
@@ -79,6 +79,7 @@ def main():
 
     for _ in range(args.warmup):
         rep = step()
+    compile_ms = ctx.stat("jit_compile_ms")
     ctx.reset_stats()
     torch.cuda.synchronize()
     lat = []
@@ -119,6 +120,8 @@ def main():
         "config": {"workload": "tree256-plain: 4096 blocks x 256 threads over 2^20 int32 in [0,2^16), "
                                "1% dropped-barrier and 0.1% tid-barrier blocks, seed 12116195",
                    "form": "plain (one kc_launch per step)", "records_per_step": records,
+                   "kernels": ("program-specialised (compiled once per process, before the timed steps: "
+                               f"{compile_ms:.0f} ms)" if args.jit else "interpreter"),
                    "races": len(rep.races), "findings": len(rep.faults),
                    "bit_exact_vs_oracle": exact,
                    "p50_ms": round(lat_ms[len(lat_ms) // 2], 4),
@@ -171,7 +174,8 @@ def measured_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed counter summary
     (FETCH_SIZE and WRITE_SIZE passes scaled by a copy kernel's reading), or
     None when it covers another kernel or the sources changed since."""
-    path = os.path.join(ROOT, "profiles", "interp_tree256_traffic.json")
+    name = "interp" if kernel.startswith("k_interp") else "jit"
+    path = os.path.join(ROOT, "profiles", f"{name}_tree256_traffic.json")
     try:
         with open(path) as f:
             t = json.load(f)
