@@ -400,6 +400,16 @@ __global__ void __launch_bounds__(WG) k_zero(uint32_t *__restrict__ p, size_t wo
 
 inline uint32_t blocks_for(uint64_t n) { return (uint32_t)((n + WG - 1) / WG); }
 
+// Copy every item of a gather into the host-visible staging buffer: one
+// kernel instead of one copy per item.
+__global__ void __launch_bounds__(WG) k_gather(GatherArgs a) {
+    for (uint32_t k = 0; k < a.n; k++) {
+        const uint32_t *src = a.src[k];
+        uint32_t *dst = a.dst + a.dst_off[k];
+        for (uint32_t i = blockIdx.x * WG + threadIdx.x; i < a.words[k]; i += gridDim.x * WG) dst[i] = src[i];
+    }
+}
+
 }  // namespace
 
 size_t check_long_cap(uint64_t n) { return (size_t)(2 * (n / SEG_LIMIT) + 2); }
@@ -442,6 +452,16 @@ hipError_t launch_copy_units(const DevUnit *units, uint32_t n_units, uint32_t ma
     if (n_units == 0) return hipSuccess;
     uint32_t gx = (uint32_t)std::min<uint64_t>(1024, std::max<uint64_t>(1, max_words / (WG * 16)));
     hipLaunchKernelGGL(k_copy_units, dim3(gx, n_units), dim3(WG), 0, s, units, to_snapshot ? 1 : 0, unit_mask);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather(const GatherArgs &a, hipStream_t s) {
+    uint32_t most = 0;
+    for (uint32_t k = 0; k < a.n; k++) most = a.words[k] > most ? a.words[k] : most;
+    if (most == 0) return hipSuccess;
+    uint32_t g = (most + WG - 1) / WG;
+    if (g > 256) g = 256;
+    hipLaunchKernelGGL(k_gather, dim3(g), dim3(WG), 0, s, a);
     return hipGetLastError();
 }
 

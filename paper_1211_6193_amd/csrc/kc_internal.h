@@ -171,6 +171,16 @@ hipError_t launch_coverage(const uint64_t *rs, uint64_t n_rs, const uint64_t *lo
 hipError_t launch_copy_units(const DevUnit *units, uint32_t n_units, uint32_t max_words, bool to_snapshot,
                              const uint32_t *unit_mask, hipStream_t s);
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);
+// Word copies of up to 8 device arrays into one destination (host-visible
+// pinned memory), at word offsets.
+struct GatherArgs {
+    const uint32_t *src[8];
+    uint32_t words[8];
+    uint32_t dst_off[8];
+    uint32_t *dst;
+    uint32_t n;
+};
+hipError_t launch_gather(const GatherArgs &a, hipStream_t s);
 #endif  // __HIPCC_RTC__
 
 }  // namespace kc

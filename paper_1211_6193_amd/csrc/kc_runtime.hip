@@ -113,14 +113,17 @@ struct Workspace {
     DBuf longseg, covlist;
     DevCounters *h_ctr = nullptr;   // pinned
     void *h_pin = nullptr;          // pinned staging of gathered device-to-host copies
+    void *d_pin = nullptr;          // its device mapping
     size_t h_pin_bytes = 0;
     void pin_reserve(size_t need) {
         if (need <= h_pin_bytes) return;
         if (h_pin) HIPCHK(hipHostFree(h_pin));
-        h_pin = nullptr;
+        h_pin = d_pin = nullptr;
         h_pin_bytes = 0;
         const size_t nb = std::max<size_t>(need + need / 2, 1 << 16);
-        HIPCHK(hipHostMalloc(&h_pin, nb, hipHostMallocDefault));
+        // coherent: the gather kernel's stores reach host memory directly
+        HIPCHK(hipHostMalloc(&h_pin, nb, hipHostMallocMapped | hipHostMallocCoherent));
+        HIPCHK(hipHostGetDevicePointer(&d_pin, h_pin, 0));
         h_pin_bytes = nb;
     }
     hipEvent_t ev[12] = {};
@@ -379,10 +382,26 @@ struct Stage {
             return items.size() - 1;
         }
     };
+    // One gather kernel writes every item straight into the pinned buffer
+    // (its device mapping); items are whole words at 256-byte offsets.
     void run_fetch(Fetch &f) {
         ws.pin_reserve(f.total);
-        for (auto &it : f.items)
-            if (it.bytes) HIPCHK(hipMemcpyAsync((char *)ws.h_pin + it.off, it.dev, it.bytes, hipMemcpyDeviceToHost, s));
+        GatherArgs g{};
+        for (auto &it : f.items) {
+            if (!it.bytes) continue;
+            g.src[g.n] = (const uint32_t *)it.dev;
+            g.words[g.n] = (uint32_t)(it.bytes / 4);
+            g.dst_off[g.n] = (uint32_t)(it.off / 4);
+            if (++g.n == 8) {
+                g.dst = (uint32_t *)ws.d_pin;
+                HIPCHK(launch_gather(g, s));
+                g.n = 0;
+            }
+        }
+        if (g.n) {
+            g.dst = (uint32_t *)ws.d_pin;
+            HIPCHK(launch_gather(g, s));
+        }
         HIPCHK(hipStreamSynchronize(s));
     }
     template <class T> const T *fetched(const Fetch &f, size_t i) const {
