@@ -32,6 +32,14 @@
  *     have exited, no rule can fire again: that is the deadlock of Section 3.1
  *     (a thread fails to reach a barrier another thread reached); a DEADLOCK
  *     finding is recorded and the block halts.
+ *   - Barriers with a predicate (Section 3 feature list: __syncthreads_count,
+ *     __syncthreads_and, __syncthreads_or): BARP d, a, k waits like a plain
+ *     barrier; when the episode completes, each thread that waits at a BARP
+ *     receives in register d the number of threads of the block whose
+ *     predicate is nonzero (k = 0), 1 if every thread's is (k = 1), or 1 if
+ *     any thread's is (k = 2), else 0.  A thread's predicate is its register
+ *     a while it waits (registers do not change while waiting); a thread
+ *     waiting at a plain barrier counts as predicate 0.
  *   - Every in-bounds load and store appends an access record
  *     {space, word address, block, barrier epoch, tid, read/write}, the
  *     information the race tuples of Section 3.1 keep per location.
@@ -62,7 +70,7 @@ enum {
     OP_SHL, OP_SHRA, OP_SHRL, OP_MIN, OP_MAX, OP_SLT, OP_SLE, OP_SEQ, OP_SNE, OP_SLTU,
     OP_MOV = 0x40, OP_MOVI = 0x41, OP_SREG = 0x42,
     OP_LDS = 0x50, OP_STS = 0x51, OP_LDG = 0x52, OP_STG = 0x53,
-    OP_JMP = 0x60, OP_BZ = 0x61, OP_BNZ = 0x62, OP_BAR = 0x63, OP_EXIT = 0x64
+    OP_JMP = 0x60, OP_BZ = 0x61, OP_BNZ = 0x62, OP_BAR = 0x63, OP_EXIT = 0x64, OP_BARP = 0x65
 };
 
 enum { ST_RUN = 0, ST_WAIT = 1, ST_EXIT = 2 };
@@ -132,7 +140,7 @@ static int valid_op(uint32_t op) {
     if (base >= OP_ADD && base <= OP_SLTU) return 1;
     return op == OP_MOV || op == OP_MOVI || op == OP_SREG || op == OP_LDS || op == OP_STS ||
            op == OP_LDG || op == OP_STG || op == OP_JMP || op == OP_BZ || op == OP_BNZ ||
-           op == OP_BAR || op == OP_EXIT;
+           op == OP_BAR || op == OP_EXIT || op == OP_BARP;
 }
 
 int ora_validate(const uint64_t *prog, uint32_t n) {
@@ -144,6 +152,7 @@ int ora_validate(const uint64_t *prog, uint32_t n) {
         if (!valid_op(op) || d >= 16 || a >= 16 || b >= 16) return 2;
         if ((op == OP_JMP || op == OP_BZ || op == OP_BNZ) && (imm < 0 || (uint32_t)imm > n)) return 2;
         if (op == OP_SREG && (imm < 0 || imm >= 24)) return 2;
+        if (op == OP_BARP && (imm < 0 || imm > 2)) return 2;
     }
     return 0;
 }
@@ -296,7 +305,7 @@ static int run_block(ora_result *res, uint32_t li, const uint64_t *prog, uint32_
                     case OP_JMP: next = (uint32_t)imm; break;
                     case OP_BZ: if (T->r[a] == 0) next = (uint32_t)imm; break;
                     case OP_BNZ: if (T->r[a] != 0) next = (uint32_t)imm; break;
-                    case OP_BAR: T->status = ST_WAIT; T->bar_pc = T->pc; break;
+                    case OP_BAR: case OP_BARP: T->status = ST_WAIT; T->bar_pc = T->pc; break;
                     case OP_EXIT: T->status = ST_EXIT; break;
                     }
                 }
@@ -324,6 +333,19 @@ static int run_block(ora_result *res, uint32_t li, const uint64_t *prog, uint32_
                     if (th[t].bar_pc > lo && th[t].bar_pc < hi) { hi = th[t].bar_pc; hi_tid = t; }
                 if (hi != UINT32_MAX)
                     add_fault(res, li, F_DIVERGENCE, bid, epoch, lo, lo_tid, hi, hi_tid);
+                /* predicate barriers: the block-wide count, and, or */
+                uint32_t count = 0;
+                for (uint32_t t = 0; t < nt; t++) {
+                    uint64_t w = prog[th[t].bar_pc];
+                    if ((w & 0xFF) == OP_BARP && th[t].r[(w >> 16) & 0xFF] != 0) count++;
+                }
+                for (uint32_t t = 0; t < nt; t++) {
+                    uint64_t w = prog[th[t].bar_pc];
+                    if ((w & 0xFF) != OP_BARP) continue;
+                    int32_t kind = (int32_t)(uint32_t)(w >> 32);
+                    int32_t v = kind == 0 ? (int32_t)count : kind == 1 ? (count == nt) : (count > 0);
+                    th[t].r[(w >> 8) & 0xFF] = v;
+                }
                 epoch++;
                 for (uint32_t t = 0; t < nt; t++) {
                     th[t].status = ST_RUN;

@@ -49,7 +49,9 @@ OTHER = {
     "BNZ": 0x62,   # if a != 0: pc = imm
     "BAR": 0x63,   # __syncthreads()
     "EXIT": 0x64,  # thread returns
+    "BARP": 0x65,  # d = __syncthreads_count/and/or(a) for imm = 0/1/2
 }
+BARP_KINDS = {"COUNT": 0, "AND": 1, "OR": 2}
 OPCODES: Dict[str, int] = {**ALU_RR, **ALU_RI, **OTHER}
 OPNAMES: Dict[int, str] = {v: k for k, v in OPCODES.items()}
 
@@ -169,6 +171,12 @@ class Asm:
     def BAR(self):
         return self._emit("BAR")
 
+    def BARP(self, d, a, kind: Union[str, int] = "COUNT"):
+        """Barrier with a predicate: d = count of threads with a != 0 (COUNT),
+        all of them (AND) or any (OR), once every thread of the block waits."""
+        k = BARP_KINDS[kind] if isinstance(kind, str) else int(kind)
+        return self._emit("BARP", d, a, 0, k)
+
     def EXIT(self):
         return self._emit("EXIT")
 
@@ -233,6 +241,9 @@ def assemble_text(src: str) -> List[int]:
             a._emit(mn, 0, _reg(args[0]), 0, imm(args[1]))
         elif mn in ("BAR", "EXIT"):
             a._emit(mn)
+        elif mn == "BARP":
+            k = args[2].upper()
+            a.BARP(_reg(args[0]), _reg(args[1]), k if k in BARP_KINDS else int(k, 0))
         else:
             raise ValueError(f"unknown mnemonic {mn!r}")
     return a.assemble()
@@ -263,6 +274,8 @@ def disassemble(words: Sequence[int]) -> str:
             s = f"JMP {imm}"
         elif name in ("BZ", "BNZ"):
             s = f"{name} r{a}, {imm}"
+        elif name == "BARP":
+            s = f"BARP r{d}, r{a}, {({v: k for k, v in BARP_KINDS.items()}).get(imm, imm)}"
         else:
             s = name
         out.append(f"{pc:5d}: {s}")

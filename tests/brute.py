@@ -134,8 +134,15 @@ def enumerate_launch(prog: List[int], grid: int, block: int, shmem_words: int,
             ts = threads[b * nt:(b + 1) * nt]
             if all(t[2] == 1 for t in ts):
                 nts = list(threads)
+                # predicate barriers: registers are unchanged while waiting
+                preds = [code[t[3]][0] == 0x65 and t[1][code[t[3]][2]] != 0 for t in ts]
                 for k in range(nt):
                     pc, rg, s, bp = ts[k]
+                    op_b, d_b, _, _, kind = code[bp]
+                    if op_b == 0x65:
+                        rg = list(rg)
+                        rg[d_b] = [sum(preds), int(all(preds)), int(any(preds))][kind]
+                        rg = tuple(rg)
                     nts[b * nt + k] = (bp + 1, rg, 0, -1)
                 ne = list(epochs); ne[b] += 1
                 succ.append((tuple(nts), shs, gm, tuple(ne), recs))
@@ -191,7 +198,7 @@ def enumerate_launch(prog: List[int], grid: int, block: int, shmem_words: int,
                 elif op == 0x60: npc = imm
                 elif op == 0x61: npc = imm if regs[a] == 0 else pc + 1
                 elif op == 0x62: npc = imm if regs[a] != 0 else pc + 1
-                elif op == 0x63: ns, nbp = 1, pc
+                elif op in (0x63, 0x65): ns, nbp = 1, pc
                 elif op == 0x64: ns = 2
                 else:
                     raise ValueError(f"bad opcode {op:#x}")

@@ -33,7 +33,7 @@ def random_kernel(rng: random.Random):
     n_stmt = rng.randint(2, 6)
     lab = 0
     for _ in range(n_stmt):
-        kind = rng.choice(["sts", "lds", "stg", "ldg", "alu", "bar", "cond"])
+        kind = rng.choice(["sts", "lds", "stg", "ldg", "alu", "bar", "barp", "cond"])
         base = rng.choice([0, 15, 1])
         if kind == "sts":
             a.STS(rng.choice([0, 15]), rng.randint(0, 2), rng.choice([2, 3, 4]))
@@ -47,12 +47,16 @@ def random_kernel(rng: random.Random):
             a.ADD(rng.choice([2, 3, 4]), rng.choice([2, 3, 4]), rng.choice([0, 1, 2]))
         elif kind == "bar":
             a.BAR()
+        elif kind == "barp":
+            a.BARP(rng.choice([2, 3, 4]), rng.choice([0, 2, 3, 4]), rng.choice(["COUNT", "AND", "OR"]))
         else:
             lab += 1
             a.SEQI(8, 0, rng.randint(0, 2)).BZ(8, f"S{lab}")
-            inner = rng.choice(["bar", "sts", "stg", "exit"])
+            inner = rng.choice(["bar", "barp", "sts", "stg", "exit"])
             if inner == "bar":
                 a.BAR()
+            elif inner == "barp":
+                a.BARP(3, 0, rng.choice(["COUNT", "AND", "OR"]))
             elif inner == "sts":
                 a.STS(15, rng.randint(0, 2), 2)
             elif inner == "stg":
