@@ -32,7 +32,11 @@
  * LDS 0x50 (d = shared[a+imm]), STS 0x51 (shared[a+imm] = b),
  * LDG 0x52 (d = global[a+imm]), STG 0x53 (global[a+imm] = b),
  * JMP 0x60, BZ 0x61 (if a == 0), BNZ 0x62 (if a != 0) to absolute pc imm,
- * BAR 0x63 (__syncthreads), EXIT 0x64.  Special registers: 0..2 threadIdx
+ * BAR 0x63 (__syncthreads), EXIT 0x64, BARP 0x65 (a barrier with a
+ * predicate, Section 3's __syncthreads_count / _and / _or for imm 0 / 1 / 2:
+ * when the episode completes, d = the number of threads of the block whose
+ * register a is nonzero, 1 if all are, or 1 if any is; a thread waiting at a
+ * plain BAR in the same episode counts as 0).  Special registers: 0..2 threadIdx
  * x/y/z, 3..5 blockIdx, 6..8 blockDim, 9..11 gridDim, 12 linear tid,
  * 13 linear block id, 14 threads per block, 15 warpSize (32), 16..23 the
  * launch parameters.  Registers r0..r15 are int32 and start at 0.

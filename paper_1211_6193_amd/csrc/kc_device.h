@@ -230,6 +230,8 @@ struct Lane {
     int st;
     uint32_t fuel;
     int bar_pc;
+    int bpred;          // at a barrier with a predicate: (kind + 1) << 1 | predicate; 0 at a plain one
+    int32_t bres;       // its result once the episode completes
     regfile_t r;
 };
 
@@ -685,6 +687,27 @@ enum : int { EP_RELEASED = 0, EP_DONE = 1 };
 // All waves are quiescent (no running lane).  Count arrivals and decide.
 template <bool LOCAL>
 __device__ __forceinline__ int barrier_episode(const InterpArgs &A, BlockCtx &B, const Shared &S, Lane &t,
+                               LogState &L, uint32_t &epoch);
+
+// After a release: each lane released from a barrier with a predicate writes
+// the result into the destination register of its barrier instruction (one
+// group per barrier site, so the register index stays wave-uniform).
+__device__ __forceinline__ void barrier_results(const BlockCtx &B, Lane &t) {
+    uint64_t m = __ballot(t.bpred != 0);
+    while (m) {
+        const bool mine = (m >> lane_id()) & 1ull;
+        const int pc = uni(wave_min(mine ? t.bar_pc : INT_MAX));
+        const uint32_t d = uniu((uint32_t)(B.prog[(uint32_t)pc] >> 8) & 0xFFu);
+        const bool here = mine && t.bar_pc == pc;
+        const int32_t old = t.r[d];
+        t.r[d] = here ? t.bres : old;
+        m &= ~__ballot(here);
+    }
+    t.bpred = 0;
+}
+
+template <bool LOCAL>
+__device__ __forceinline__ int barrier_episode(const InterpArgs &A, BlockCtx &B, const Shared &S, Lane &t,
                                LogState &L, uint32_t &epoch) {
     __syncthreads();
     if (LOCAL) epoch_local_check(A, B, S, L, epoch);
@@ -693,8 +716,10 @@ __device__ __forceinline__ int barrier_episode(const InterpArgs &A, BlockCtx &B,
     uint64_t em = __ballot(t.st == ST_EXIT);
     int bmin = wave_min(t.st == ST_WAIT ? t.bar_pc : INT_MAX);
     int bmax = wave_max(t.st == ST_WAIT ? t.bar_pc : -1);
+    const uint64_t pm = __ballot(t.st == ST_WAIT && (t.bpred & 1));
     (void)is_thread;
     if (lane_id() == 0) {
+        S.slots2[4 * B.wave + 3] = (uint32_t)__popcll(pm);     // predicates that hold
         uint32_t *s = S.slots + 8 * B.wave;
         s[0] = (uint32_t)__popcll(wm);
         s[1] = (uint32_t)__popcll(em);
@@ -743,9 +768,15 @@ __device__ __forceinline__ int barrier_episode(const InterpArgs &A, BlockCtx &B,
     }
     epoch++;
     if (threadIdx.x == 0 && epoch > A.kp.max_epoch) atomicOr(A.flags, FLAG_EPOCH_OVERFLOW);
+    // barriers with a predicate: every thread of the block waits here, so
+    // AND holds when the count reaches the thread count
+    uint32_t npred = 0;
+    for (uint32_t w = 0; w < B.nwaves; w++) npred += S.slots2[4 * w + 3];
     if (t.st == ST_WAIT) {
         t.st = ST_RUN;
         t.pc = t.bar_pc + 1;
+        const int kind = (t.bpred >> 1) - 1;
+        if (kind >= 0) t.bres = kind == 0 ? (int32_t)npred : kind == 1 ? (npred == B.nt ? 1 : 0) : (npred ? 1 : 0);
     }
     B.kep = B.kbase | ((uint64_t)epoch << A.kp.s_ep);
     return EP_RELEASED;
@@ -812,8 +843,12 @@ __device__ __forceinline__ void exec_one(const InterpArgs &A, const BlockCtx &B,
             cond = (op == OP_BZ) ? (x == 0) : (x != 0);
         } else {
             ctl = 3;
-            if (op == OP_BAR) {
-                if (active) { t.st = ST_WAIT; t.bar_pc = cur; }
+            if (op == OP_BAR || op == OP_BARP) {
+                if (active) {
+                    t.st = ST_WAIT;
+                    t.bar_pc = cur;
+                    t.bpred = op == OP_BARP ? (int)(((uint32_t)imm + 1u) << 1) | (t.r[ra] != 0 ? 1 : 0) : 0;
+                }
             } else if (active) {
                 t.st = ST_EXIT;
             }
@@ -903,6 +938,8 @@ __device__ __forceinline__ void setup_block(const InterpArgs &A, BlockCtx &B, co
     t.st = (B.tid < B.nt) ? ST_RUN : ST_DEAD;
     t.fuel = u->fuel;
     t.bar_pc = 0;
+    t.bpred = 0;
+    t.bres = 0;
     t.r = (regfile_t)(0);
     __syncthreads();
 }
@@ -1012,6 +1049,7 @@ __device__ __forceinline__ uint32_t run_block_free(const InterpArgs &A, BlockCtx
         }
         // wave quiescent
         if (barrier_episode<LOCAL>(A, B, S, t, L, epoch) == EP_DONE) break;
+        barrier_results(B, t);
         int lo = wave_min(t.st == ST_RUN ? t.pc : INT_MAX);
         int hi = wave_max(t.st == ST_RUN ? t.pc : -1);
         conv = (lo == hi) || hi < 0;
@@ -1105,10 +1143,13 @@ __device__ __forceinline__ uint64_t lockstep_group(const InterpArgs &A, BlockCtx
 // its memory-free instructions in one go (one step each, charging fuel and
 // leaving pc and state in `t`), stopping before a load or store; it returns
 // the number of steps taken, 0 when it took none.
-template <bool LOCAL, class Exec, class Run>
+//
+// `release()` runs after every completed episode (the results of barriers
+// with a predicate).
+template <bool LOCAL, class Exec, class Run, class Release>
 __device__ __forceinline__ uint32_t run_block_lockstep(const InterpArgs &A, BlockCtx &B, const Shared &S,
                                                    const StoreTables &T, Lane &t, LogState &L, Exec &exec,
-                                                   Run &run) {
+                                                   Run &run, Release &release) {
     constexpr uint32_t NO_STEP = 0xFFFFFFFFu;
     uint32_t epoch = 0;
     uint32_t par = 0;               // round slots alternate so one barrier per round suffices
@@ -1190,6 +1231,7 @@ __device__ __forceinline__ uint32_t run_block_lockstep(const InterpArgs &A, Bloc
             }
         }
         if (barrier_episode<LOCAL>(A, B, S, t, L, epoch) == EP_DONE) break;
+        release();
     }
     return epoch;
 }
@@ -1302,7 +1344,8 @@ __device__ __forceinline__ void interp_lockstep_body(const InterpArgs &A) {
             exec_one<true, LOCAL>(a, b, s, t, l, P, epoch, cur, w, active, ctl, target, cond);
         };
         auto run = [](uint64_t, uint32_t) { return 0u; };
-        return run_block_lockstep<LOCAL>(a, b, s, tb, t, l, exec, run);
+        auto release = [&] { barrier_results(b, t); };
+        return run_block_lockstep<LOCAL>(a, b, s, tb, t, l, exec, run, release);
     });
 }
 

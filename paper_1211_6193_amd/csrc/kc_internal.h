@@ -18,6 +18,7 @@ enum : uint32_t {
     OP_MOV = 0x40, OP_MOVI = 0x41, OP_SREG = 0x42,
     OP_LDS = 0x50, OP_STS = 0x51, OP_LDG = 0x52, OP_STG = 0x53,
     OP_JMP = 0x60, OP_BZ = 0x61, OP_BNZ = 0x62, OP_BAR = 0x63, OP_EXIT = 0x64,
+    OP_BARP = 0x65,     // barrier with a predicate: d = count / and / or (imm 0 / 1 / 2) of register a
 };
 constexpr uint32_t N_SREGS = 24;
 constexpr uint32_t MAX_INSTR = 1u << 16;

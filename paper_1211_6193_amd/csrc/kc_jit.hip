@@ -146,6 +146,35 @@ void gen_mem(std::ostringstream &o, const Instr &I, bool lockstep = false) {
 
 }  // namespace
 
+// A thread arriving at the barrier at `pc` (plain or with a predicate).
+std::string arrive(const Instr &I, uint32_t pc, const char *indent) {
+    std::ostringstream o;
+    o << indent << "if (act) {\n" << indent << "    t.st = ST_WAIT;\n" << indent << "    t.bar_pc = " << pc << ";\n";
+    if (I.op == OP_BARP)
+        o << indent << "    t.bpred = " << ((I.imm + 1) << 1) << " | (" << reg(I.a) << " != 0 ? 1 : 0);\n";
+    else
+        o << indent << "    t.bpred = 0;\n";
+    o << indent << "}\n";
+    return o.str();
+}
+
+// After a release: the result of each barrier with a predicate goes to its
+// destination register, for the lanes released from that barrier.
+std::string barrier_results(const uint64_t *words, uint32_t n, const char *indent) {
+    std::ostringstream o;
+    bool any = false;
+    for (uint32_t pc = 0; pc < n; pc++) any = any || decode(words[pc]).op == OP_BARP;
+    if (!any) return "";
+    o << indent << "if (__ballot(t.bpred != 0)) {\n";
+    for (uint32_t pc = 0; pc < n; pc++) {
+        const Instr I = decode(words[pc]);
+        if (I.op == OP_BARP)
+            o << indent << "    if (t.bpred != 0 && t.bar_pc == " << pc << ") " << reg(I.d) << " = t.bres;\n";
+    }
+    o << indent << "    t.bpred = 0;\n" << indent << "}\n";
+    return o.str();
+}
+
 std::string jit_source(const uint64_t *words, uint32_t n, int waves) {
     std::vector<char> lead(n + 1, 0);
     lead[0] = 1;
@@ -155,7 +184,7 @@ std::string jit_source(const uint64_t *words, uint32_t n, int waves) {
         if (I.op == OP_JMP || I.op == OP_BZ || I.op == OP_BNZ) {
             lead[(uint32_t)I.imm] = 1;
             lead[pc + 1] = 1;
-        } else if (I.op == OP_BAR || I.op == OP_EXIT) {
+        } else if (I.op == OP_BAR || I.op == OP_BARP || I.op == OP_EXIT) {
             lead[pc + 1] = 1;
         }
     }
@@ -231,8 +260,8 @@ std::string jit_source(const uint64_t *words, uint32_t n, int waves) {
             o << "            if (conv && tk != 0 && tk != am) conv = false;\n";
             o << "            if (conv) upc = tk ? " << T.imm << " : " << e << ";\n";
             o << "            else if (act) t.pc = c ? " << T.imm << " : " << e << ";\n            break;\n";
-        } else if (T.op == OP_BAR) {
-            o << "            if (act) { t.st = ST_WAIT; t.bar_pc = " << (e - 1) << "; }\n            break;\n";
+        } else if (T.op == OP_BAR || T.op == OP_BARP) {
+            o << arrive(T, e - 1, "            ") << "            break;\n";
         } else if (T.op == OP_EXIT) {
             o << "            if (act) t.st = ST_EXIT;\n            break;\n";
         } else {
@@ -243,6 +272,7 @@ std::string jit_source(const uint64_t *words, uint32_t n, int waves) {
     o << "        default:\n            if (act) t.st = ST_EXIT;\n            break;\n        }\n";
     o << "      }\n";
     o << "      if (barrier_episode<LOCAL>(A, B, S, t, L, epoch) == EP_DONE) break;\n";
+    o << barrier_results(words, n, "      ");
     o << "      const int lo = wave_min(t.st == ST_RUN ? t.pc : INT_MAX);\n";
     o << "      const int hi = wave_max(t.st == ST_RUN ? t.pc : -1);\n";
     o << "      conv = (lo == hi) || hi < 0;\n      upc = uni(lo);\n    }\n    return epoch;\n}\n\n";
@@ -274,9 +304,8 @@ std::string jit_source(const uint64_t *words, uint32_t n, int waves) {
         } else if (I.op == OP_BZ || I.op == OP_BNZ) {
             o << "        ctl = 2;\n        target = " << I.imm << ";\n        cond = " << reg(I.a)
               << (I.op == OP_BZ ? " == 0" : " != 0") << ";\n";
-        } else if (I.op == OP_BAR) {
-            o << "        ctl = 3;\n        if (act) {\n            t.st = ST_WAIT;\n            t.bar_pc = " << pc
-              << ";\n        }\n";
+        } else if (I.op == OP_BAR || I.op == OP_BARP) {
+            o << "        ctl = 3;\n" << arrive(I, pc, "        ");
         } else if (I.op == OP_EXIT) {
             o << "        ctl = 3;\n        if (act) t.st = ST_EXIT;\n";
         }
@@ -326,9 +355,8 @@ std::string jit_source(const uint64_t *words, uint32_t n, int waves) {
             o << "                if (tk == 0) { upc = " << e << "; continue; }\n";
             o << "                if (tk == am) { upc = " << T.imm << "; continue; }\n";
             o << "                if (act) t.pc = c ? " << T.imm << " : " << e << ";\n                return steps;\n";
-        } else if (T.op == OP_BAR) {
-            o << "                if (act) {\n                    t.st = ST_WAIT;\n                    t.bar_pc = " << (e - 1)
-              << ";\n                }\n                return steps;\n";
+        } else if (T.op == OP_BAR || T.op == OP_BARP) {
+            o << arrive(T, e - 1, "                ") << "                return steps;\n";
         } else if (T.op == OP_EXIT) {
             o << "                if (act) t.st = ST_EXIT;\n                return steps;\n";
         } else {
@@ -338,7 +366,8 @@ std::string jit_source(const uint64_t *words, uint32_t n, int waves) {
     }
     o << "            default: goto out;\n            }\n        }\n";
     o << "    out:\n        if (act) t.pc = upc;\n        return steps;\n    };\n";
-    o << "    return run_block_lockstep<LOCAL>(A, B, S, T, t, L, exec, run);\n}\n\n";
+    o << "    auto release = [&] {\n" << barrier_results(words, n, "        ") << "    };\n";
+    o << "    return run_block_lockstep<LOCAL>(A, B, S, T, t, L, exec, run, release);\n}\n\n";
     o << "}  // namespace\n}  // namespace kc\n\n";
     // workgroups of up to 256 threads get the whole register file; larger ones
     // are bounded to 128 VGPRs

@@ -260,7 +260,7 @@ bool valid_opcode(uint32_t op) {
     if (base >= OP_ADD && base <= OP_SLTU) return true;
     switch (op) {
     case OP_MOV: case OP_MOVI: case OP_SREG: case OP_LDS: case OP_STS: case OP_LDG: case OP_STG:
-    case OP_JMP: case OP_BZ: case OP_BNZ: case OP_BAR: case OP_EXIT:
+    case OP_JMP: case OP_BZ: case OP_BNZ: case OP_BAR: case OP_EXIT: case OP_BARP:
         return true;
     default:
         return false;
@@ -279,6 +279,8 @@ std::string validate_program(const uint64_t *w, uint32_t n) {
             return "branch target out of range at pc " + std::to_string(pc);
         if (op == OP_SREG && (imm < 0 || (uint32_t)imm >= N_SREGS))
             return "special register out of range at pc " + std::to_string(pc);
+        if (op == OP_BARP && (imm < 0 || imm > 2))
+            return "barrier predicate kind out of range at pc " + std::to_string(pc);
     }
     return "";
 }
