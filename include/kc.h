@@ -120,6 +120,9 @@ kc_status kc_ctx_set_option(kc_ctx *ctx, const char *key, int64_t value);
 /* Accumulated statistics since the last reset ("reset" clears them):
  * "interp_ms", "sort_ms", "check_ms", "replay_ms", "launches", "records",
  * "replays", "fallbacks", "retries", "interp_launches", "sort_keys",
+ * "replay_sorted_checks" (replays whose records needed the sorted check: an
+ * unreduced record, or a location written by one replayed block and touched
+ * by another; the others are checked through a hash table of locations),
  * "instructions" (thread-instructions executed by the parallel free run; a
  * canonical replay of racy blocks is not counted), "jit_launches", "jit_replays"
  * (replay launches on specialised kernels),

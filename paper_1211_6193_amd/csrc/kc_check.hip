@@ -380,6 +380,83 @@ __global__ void __launch_bounds__(WG) k_coverage_long(const uint64_t *__restrict
     }
 }
 
+// Replayed locations in a hash table: key (location + 1, 0 = empty), the
+// replayed block that touched it first (+1) and flags (bit 0 a write, bit 1
+// a second replayed block).
+struct RTable {
+    unsigned long long *key;
+    uint32_t *owner;
+    uint32_t *flag;
+};
+__device__ __forceinline__ RTable rtable(void *p, uint32_t bits) {
+    RTable t;
+    t.key = (unsigned long long *)p;
+    t.owner = (uint32_t *)(t.key + (1u << bits));
+    t.flag = t.owner + (1u << bits);
+    return t;
+}
+
+__global__ void __launch_bounds__(WG) k_rtable_insert(ReplayTableArgs a) {
+    const uint64_t i = (uint64_t)blockIdx.x * WG + threadIdx.x;
+    if (i >= a.n_rs) return;
+    const KeyPlan &k = a.kp;
+    const uint64_t r = a.rs[i];
+    if (rec_field(r, k.s_sp, 1) != 1u || rec_field(r, k.s_ep, k.eb) != k.ep_rep) {
+        atomicOr(&a.ctr->flags, FLAG_NEED_SORT);    // an unreduced record
+        return;
+    }
+    const RTable t = rtable(a.table, a.bits);
+    const unsigned long long loc = (r >> k.s_addr) + 1ull;
+    const uint32_t mask = (1u << a.bits) - 1u;
+    uint32_t slot = (uint32_t)((loc * 0x9E3779B97F4A7C15ull) >> (64 - a.bits));
+    for (uint32_t p = 0;; p++) {
+        if (p > mask) {
+            atomicOr(&a.ctr->flags, FLAG_NEED_SORT);
+            return;
+        }
+        const unsigned long long old = atomicCAS(&t.key[slot], 0ull, loc);
+        if (old == 0ull || old == loc) break;
+        slot = (slot + 1u) & mask;
+    }
+    const uint32_t blk = a.units[rec_field(r, k.s_unit, k.ub)].block_base + rec_field(r, k.s_blk, k.bb) + 1u;
+    if (r & 1ull) atomicOr(&t.flag[slot], 1u);
+    const uint32_t prev = atomicCAS(&t.owner[slot], 0u, blk);
+    if (prev != 0u && prev != blk) atomicOr(&t.flag[slot], 2u);
+}
+
+// Per replayed location: a write shared between replayed blocks needs the
+// sorted check; otherwise the location's free-run records of blocks that were
+// not replayed must not conflict with it (at most COV_LIMIT of them scanned).
+__global__ void __launch_bounds__(WG) k_rtable_check(ReplayTableArgs a) {
+    const uint32_t slot = blockIdx.x * WG + threadIdx.x;
+    if (slot >= (1u << a.bits)) return;
+    const RTable t = rtable(a.table, a.bits);
+    const unsigned long long loc1 = t.key[slot];
+    if (loc1 == 0ull) return;
+    const uint32_t f = t.flag[slot];
+    if (f == 3u) {
+        atomicOr(&a.ctr->flags, FLAG_NEED_SORT);
+        return;
+    }
+    const KeyPlan &k = a.kp;
+    const uint64_t target = loc1 - 1ull;
+    const uint64_t lo = lower_bound_loc(a.log, a.n_log, target, k.s_addr);
+    for (uint64_t j = lo; j < a.n_log; j++) {
+        const uint64_t x = a.log[j];
+        if ((x >> k.s_addr) != target) break;
+        if (j - lo == COV_LIMIT) {
+            atomicOr(&a.ctr->flags, FLAG_NEED_SORT);
+            return;
+        }
+        const DevUnit &u = a.units[rec_field(x, k.s_unit, k.ub)];
+        if (a.blk_flags[u.block_base + rec_field(x, k.s_blk, k.bb)]) continue;     // replayed block
+        if ((f & 1u) || (x & 1ull)) {
+            atomicOr(&a.ctr->flags, FLAG_MISMATCH);
+            return;
+        }
+    }
+}
+
 // mem <-> snapshot of each unit (blockIdx.y = unit), optionally masked.
 __global__ void __launch_bounds__(WG) k_copy_units(const DevUnit *__restrict__ units, int to_snapshot,
                                                    const uint32_t *__restrict__ mask) {
@@ -452,6 +529,15 @@ hipError_t launch_copy_units(const DevUnit *units, uint32_t n_units, uint32_t ma
     if (n_units == 0) return hipSuccess;
     uint32_t gx = (uint32_t)std::min<uint64_t>(1024, std::max<uint64_t>(1, max_words / (WG * 16)));
     hipLaunchKernelGGL(k_copy_units, dim3(gx, n_units), dim3(WG), 0, s, units, to_snapshot ? 1 : 0, unit_mask);
+    return hipGetLastError();
+}
+
+hipError_t launch_replay_table(const ReplayTableArgs &a, hipStream_t s) {
+    if (a.n_rs == 0) return hipSuccess;
+    hipError_t e = launch_zero(a.table, (size_t)16 << a.bits, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_rtable_insert, dim3(blocks_for(a.n_rs)), dim3(WG), 0, s, a);
+    hipLaunchKernelGGL(k_rtable_check, dim3(blocks_for(1ull << a.bits)), dim3(WG), 0, s, a);
     return hipGetLastError();
 }
 

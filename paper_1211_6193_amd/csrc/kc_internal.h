@@ -76,6 +76,7 @@ enum : uint32_t {
     FLAG_RACE_OVERFLOW = 1u << 3,
     FLAG_EDGE_OVERFLOW = 1u << 4,
     FLAG_MISMATCH = 1u << 5,
+    FLAG_NEED_SORT = 1u << 6,   // the replay's records need the sorted check
 };
 
 // Counters in one small device block (zeroed before a stage).
@@ -169,6 +170,26 @@ hipError_t launch_restore(const uint64_t *keys, uint64_t n, KeyPlan kp, const De
 hipError_t launch_coverage(const uint64_t *rs, uint64_t n_rs, const uint64_t *log, uint64_t n_log, KeyPlan kp,
                            const DevUnit *units, const uint32_t *blk_flags, DevCounters *ctr, uint64_t *list,
                            hipStream_t s);
+// Exactness of a replay without sorting its records, for the common case:
+// every replayed record is a representative (epoch ep_rep) and no global
+// location is written by one replayed block and touched by another.  Sets
+// FLAG_MISMATCH as launch_coverage would, or FLAG_NEED_SORT when the case does
+// not hold (or a location has more free-run records than the scan takes), in
+// which case the caller sorts and checks as usual.  `table` holds 16 << bits
+// bytes with 2^bits >= 2 n_rs.
+struct ReplayTableArgs {
+    const uint64_t *rs;         // the replay's records (any order)
+    uint64_t n_rs;
+    const uint64_t *log;        // the free run's records, sorted
+    uint64_t n_log;
+    KeyPlan kp;
+    const DevUnit *units;
+    const uint32_t *blk_flags;  // replayed blocks
+    void *table;
+    uint32_t bits;
+    DevCounters *ctr;
+};
+hipError_t launch_replay_table(const ReplayTableArgs &a, hipStream_t s);
 hipError_t launch_copy_units(const DevUnit *units, uint32_t n_units, uint32_t max_words, bool to_snapshot,
                              const uint32_t *unit_mask, hipStream_t s);
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);

@@ -110,7 +110,7 @@ struct Workspace {
     DBuf units, items, comp_off, comp_blocks, mask;
     DBuf snap, log, alt, rlog, ralt, fs, hist, part;
     DBuf faults, rfaults, races, lraces, rlraces, edges, blk_recs, rblk_recs, blk_flags, rflags, ctr, rctr;
-    DBuf longseg, covlist;
+    DBuf longseg, covlist, rtable;
     DevCounters *h_ctr = nullptr;   // pinned
     void *h_pin = nullptr;          // pinned staging of gathered device-to-host copies
     void *d_pin = nullptr;          // its device mapping
@@ -975,7 +975,33 @@ struct Stage {
         bool ok = !(rc.flags & (FLAG_LOG_OVERFLOW | FLAG_FAULT_OVERFLOW | FLAG_RACE_OVERFLOW));
         std::vector<DevRace> rr;
         std::vector<DevEdge> re;
-        if (ok) {
+        bool sorted_check = ok && rc.log_count > 0;
+        if (sorted_check) {
+            // Common case first: the replay's records are all representatives
+            // and no replayed location is shared by replayed blocks with a
+            // write; then its exactness needs no sort (one hash pass over the
+            // records, one binary search per location).
+            uint32_t bits = 10;
+            while ((1ull << bits) < 2 * rc.log_count) bits++;
+            ws.rtable.reserve((size_t)16 << bits);
+            reset_counters(ws.ctr);
+            ReplayTableArgs ta{ws.rlog.as<uint64_t>(), rc.log_count, sorted, nrec, kp, ws.units.as<DevUnit>(),
+                               ws.blk_flags.as<uint32_t>(), ws.rtable.p, bits, ws.ctr.as<DevCounters>()};
+            HIPCHK(launch_replay_table(ta, s));
+            Fetch f;
+            const size_t i_t = f.add(ws.ctr.p, sizeof(DevCounters));
+            run_fetch(f);
+            const DevCounters tc = *fetched<DevCounters>(f, i_t);
+            tm.mark(11);
+            ctx->stat_add("replay_table_ms", tm.ms(7, 11));
+            if (!(tc.flags & FLAG_NEED_SORT)) {
+                sorted_check = false;
+                ok = !(tc.flags & FLAG_MISMATCH);
+            } else {
+                ctx->stat_add("replay_sorted_checks", 1);
+            }
+        }
+        if (sorted_check) {
             used_epoch_bits = std::max(used_epoch_bits, bits_for((uint64_t)rc.max_epoch + 2));
             uint64_t *rs = sort_check(ws.rlog, ws.ralt, rc.log_count);
             tm.mark(8);
@@ -991,7 +1017,7 @@ struct Stage {
             run_check(rs, rc.log_count, ws.rflags, rr, re, true, ws.ctr.as<DevCounters>(), &cov);
             tm.mark(9);
             ok = !(cov.flags & FLAG_MISMATCH);
-            ctx->stat_add("replay_sort_ms", tm.ms(7, 8));
+            ctx->stat_add("replay_sort_ms", tm.ms(11, 8));
             ctx->stat_add("replay_coverage_ms", tm.ms(8, 10));
             ctx->stat_add("replay_check_ms", tm.ms(10, 9));
             for (auto &e : re)

@@ -183,6 +183,28 @@ def test_replay_paths(ctx):
         assert ctx.stat("replays") >= 1
 
 
+def test_replay_exactness_paths(ctx):
+    """Replays whose records are all representatives and share no written
+    location between replayed blocks are checked through the hash table of
+    locations (no sorted check); replays of cross-block components take the
+    sorted check.  Both must equal the oracle."""
+    job = W.tree256_job(n_blocks=256, drop_frac=0.05, div_frac=0.01, seed=9)
+    say("tree replay: hash-table exactness")
+    ctx.reset_stats()
+    rep, mem = kc.run_job(ctx, job)
+    assert_same(rep, mem, O.run_job(job), "tree replay")
+    assert ctx.stat("replays") >= 1 and ctx.stat("replay_sorted_checks") == 0 and ctx.stat("fallbacks") == 0
+    job = W.stencil_pingpong_job(n=1 << 12, threads=256, steps=2, bug_frac=0.0, seed=4)
+    n, nb = job.meta["n"], job.meta["n_blocks"]
+    for b in (1, 6, nb - 1):
+        job.memory[2 * n + b] = 1
+    say("cross-block components: sorted check")
+    ctx.reset_stats()
+    rep, mem = kc.run_job(ctx, job)
+    assert_same(rep, mem, O.run_job(job), "pingpong components")
+    assert ctx.stat("replays") >= 1 and ctx.stat("replay_sorted_checks") >= 1
+
+
 def test_instruction_count_of_race_free_runs(ctx):
     # A race-free free run executes the canonical per-thread traces, so the
     # library's count of executed thread-instructions equals the oracle's.
