@@ -109,6 +109,10 @@ void kc_ctx_destroy(kc_ctx *ctx);
  * global locations as set by "shadow_global"; 0 = log every access),
  * "shadow_global" (1 = global locations through an LDS table of per-location
  * access tuples, default; 0 = stage their records and sort them per epoch),
+ * "hash_check" (1 = a log of representative records in which no global
+ * location is written by one block and touched by another is checked
+ * through a hash table of its locations, without sorting, default; 0 = every
+ * log is sorted and checked segment by segment),
  * "jit" (1 = run free runs on program-specialised kernels: each program is
  * translated to HIP and compiled with hiprtc for gfx950 at its first launch,
  * once per process, which takes seconds; results are identical to the
@@ -120,6 +124,8 @@ kc_status kc_ctx_set_option(kc_ctx *ctx, const char *key, int64_t value);
 /* Accumulated statistics since the last reset ("reset" clears them):
  * "interp_ms", "sort_ms", "check_ms", "replay_ms", "launches", "records",
  * "replays", "fallbacks", "retries", "interp_launches", "sort_keys",
+ * "sorted_checks", "hash_check_ms" (free-run logs that needed the sort, and
+ * the time of the location-table checks),
  * "replay_sorted_checks" (replays whose records needed the sorted check: an
  * unreduced record, or a location written by one replayed block and touched
  * by another; the others are checked through a hash table of locations),

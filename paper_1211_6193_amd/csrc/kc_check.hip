@@ -380,21 +380,23 @@ __global__ void __launch_bounds__(WG) k_coverage_long(const uint64_t *__restrict
     }
 }
 
-// Replayed locations in a hash table: key (location + 1, 0 = empty), the
-// replayed block that touched it first (+1) and flags (bit 0 a write, bit 1
-// a second replayed block).
-struct RTable {
-    unsigned long long *key;
-    uint32_t *owner;
-    uint32_t *flag;
+// Locations of a log in a hash table (linear probing), one 64-bit word per
+// slot: location + 1 (0 = empty) | first block + 1 (obits bits) | flags (bit 0
+// a write, bit 1 a second block), so inserting a record is one
+// compare-and-swap.
+struct LocTable {
+    unsigned long long *w;
+    uint32_t bits, obits;
+    __device__ unsigned long long loc(unsigned long long v) const { return v >> (obits + 2); }
+    __device__ uint32_t owner(unsigned long long v) const { return (uint32_t)(v >> 2) & ((1u << obits) - 1u); }
+    __device__ uint32_t flags(unsigned long long v) const { return (uint32_t)v & 3u; }
+    __device__ unsigned long long pack(unsigned long long loc1, uint32_t own1, uint32_t f) const {
+        return (loc1 << (obits + 2)) | ((unsigned long long)own1 << 2) | f;
+    }
+    __device__ uint32_t home(unsigned long long loc1) const {
+        return (uint32_t)((loc1 * 0x9E3779B97F4A7C15ull) >> (64 - bits));
+    }
 };
-__device__ __forceinline__ RTable rtable(void *p, uint32_t bits) {
-    RTable t;
-    t.key = (unsigned long long *)p;
-    t.owner = (uint32_t *)(t.key + (1u << bits));
-    t.flag = t.owner + (1u << bits);
-    return t;
-}
 
 __global__ void __launch_bounds__(WG) k_rtable_insert(ReplayTableArgs a) {
     const uint64_t i = (uint64_t)blockIdx.x * WG + threadIdx.x;
@@ -405,37 +407,81 @@ __global__ void __launch_bounds__(WG) k_rtable_insert(ReplayTableArgs a) {
         atomicOr(&a.ctr->flags, FLAG_NEED_SORT);    // an unreduced record
         return;
     }
-    const RTable t = rtable(a.table, a.bits);
-    const unsigned long long loc = (r >> k.s_addr) + 1ull;
+    const LocTable t{(unsigned long long *)a.table, a.bits, a.obits};
+    const unsigned long long loc1 = (r >> k.s_addr) + 1ull;
+    const uint32_t blk = a.units[rec_field(r, k.s_unit, k.ub)].block_base + rec_field(r, k.s_blk, k.bb) + 1u;
+    const uint32_t wr = (uint32_t)(r & 1ull);
     const uint32_t mask = (1u << a.bits) - 1u;
-    uint32_t slot = (uint32_t)((loc * 0x9E3779B97F4A7C15ull) >> (64 - a.bits));
-    for (uint32_t p = 0;; p++) {
-        if (p > mask) {
-            atomicOr(&a.ctr->flags, FLAG_NEED_SORT);
-            return;
+    uint32_t slot = t.home(loc1);
+    for (uint32_t p = 0; p <= mask; p++) {
+        unsigned long long cur = t.w[slot];
+        if (cur == 0ull) {
+            cur = atomicCAS(&t.w[slot], 0ull, t.pack(loc1, blk, wr));
+            if (cur == 0ull) return;
         }
-        const unsigned long long old = atomicCAS(&t.key[slot], 0ull, loc);
-        if (old == 0ull || old == loc) break;
+        if (t.loc(cur) == loc1) {
+            for (;;) {
+                const uint32_t own = t.owner(cur);
+                const unsigned long long nw = t.pack(loc1, own, t.flags(cur) | wr | (own != blk ? 2u : 0u));
+                if (nw == cur) return;
+                const unsigned long long prev = atomicCAS(&t.w[slot], cur, nw);
+                if (prev == cur) return;
+                cur = prev;
+            }
+        }
         slot = (slot + 1u) & mask;
     }
-    const uint32_t blk = a.units[rec_field(r, k.s_unit, k.ub)].block_base + rec_field(r, k.s_blk, k.bb) + 1u;
-    if (r & 1ull) atomicOr(&t.flag[slot], 1u);
-    const uint32_t prev = atomicCAS(&t.owner[slot], 0u, blk);
-    if (prev != 0u && prev != blk) atomicOr(&t.flag[slot], 2u);
+    atomicOr(&a.ctr->flags, FLAG_NEED_SORT);        // no free slot
+}
+
+__device__ __forceinline__ int64_t ltable_find(const LocTable &t, unsigned long long loc1) {
+    const uint32_t mask = (1u << t.bits) - 1u;
+    uint32_t slot = t.home(loc1);
+    for (uint32_t p = 0; p <= mask; p++) {
+        const unsigned long long v = t.w[slot];
+        if (v == 0ull) return -1;
+        if (t.loc(v) == loc1) return slot;
+        slot = (slot + 1u) & mask;
+    }
+    return -1;
+}
+
+// Locations written by one block and touched by another.
+__global__ void __launch_bounds__(WG) k_rtable_conflicts(ReplayTableArgs a) {
+    const uint32_t slot = blockIdx.x * WG + threadIdx.x;
+    if (slot >= (1u << a.bits)) return;
+    const unsigned long long v = ((const unsigned long long *)a.table)[slot];
+    if (v != 0ull && (v & 3ull) == 3ull) atomicOr(&a.ctr->flags, FLAG_NEED_SORT);
 }
 
 // Per replayed location: a write shared between replayed blocks needs the
 // sorted check; otherwise the location's free-run records of blocks that were
-// not replayed must not conflict with it (at most COV_LIMIT of them scanned).
+// not replayed must not conflict with it (at most COV_LIMIT of them scanned),
+// or, with the free run's location table, its one block (several: sorted
+// check).
 __global__ void __launch_bounds__(WG) k_rtable_check(ReplayTableArgs a) {
     const uint32_t slot = blockIdx.x * WG + threadIdx.x;
     if (slot >= (1u << a.bits)) return;
-    const RTable t = rtable(a.table, a.bits);
-    const unsigned long long loc1 = t.key[slot];
-    if (loc1 == 0ull) return;
-    const uint32_t f = t.flag[slot];
+    const LocTable t{(unsigned long long *)a.table, a.bits, a.obits};
+    const unsigned long long v = t.w[slot];
+    if (v == 0ull) return;
+    const uint32_t f = t.flags(v);
     if (f == 3u) {
         atomicOr(&a.ctr->flags, FLAG_NEED_SORT);
+        return;
+    }
+    const unsigned long long loc1 = t.loc(v);
+    if (a.ftable) {
+        const LocTable ft{(unsigned long long *)const_cast<void *>(a.ftable), a.fbits, a.obits};
+        const int64_t fs = ltable_find(ft, loc1);
+        if (fs < 0) return;                                 // untouched by the free run
+        const unsigned long long fv = ft.w[fs];
+        if (ft.flags(fv) & 2u) {
+            atomicOr(&a.ctr->flags, FLAG_NEED_SORT);
+            return;
+        }
+        if (a.blk_flags[ft.owner(fv) - 1u]) return;        // its one block was replayed
+        if ((f & 1u) || (ft.flags(fv) & 1u)) atomicOr(&a.ctr->flags, FLAG_MISMATCH);
         return;
     }
     const KeyPlan &k = a.kp;
@@ -534,10 +580,19 @@ hipError_t launch_copy_units(const DevUnit *units, uint32_t n_units, uint32_t ma
 
 hipError_t launch_replay_table(const ReplayTableArgs &a, hipStream_t s) {
     if (a.n_rs == 0) return hipSuccess;
-    hipError_t e = launch_zero(a.table, (size_t)16 << a.bits, s);
+    hipError_t e = launch_zero(a.table, (size_t)8 << a.bits, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_rtable_insert, dim3(blocks_for(a.n_rs)), dim3(WG), 0, s, a);
     hipLaunchKernelGGL(k_rtable_check, dim3(blocks_for(1ull << a.bits)), dim3(WG), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_log_table(const ReplayTableArgs &a, hipStream_t s) {
+    if (a.n_rs == 0) return hipSuccess;
+    hipError_t e = launch_zero(a.table, (size_t)8 << a.bits, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_rtable_insert, dim3(blocks_for(a.n_rs)), dim3(WG), 0, s, a);
+    hipLaunchKernelGGL(k_rtable_conflicts, dim3(blocks_for(1ull << a.bits)), dim3(WG), 0, s, a);
     return hipGetLastError();
 }
 

@@ -175,8 +175,7 @@ hipError_t launch_coverage(const uint64_t *rs, uint64_t n_rs, const uint64_t *lo
 // location is written by one replayed block and touched by another.  Sets
 // FLAG_MISMATCH as launch_coverage would, or FLAG_NEED_SORT when the case does
 // not hold (or a location has more free-run records than the scan takes), in
-// which case the caller sorts and checks as usual.  `table` holds 16 << bits
-// bytes with 2^bits >= 2 n_rs.
+// which case the caller sorts and checks as usual.  2^bits >= 2 n_rs.
 struct ReplayTableArgs {
     const uint64_t *rs;         // the replay's records (any order)
     uint64_t n_rs;
@@ -185,11 +184,21 @@ struct ReplayTableArgs {
     KeyPlan kp;
     const DevUnit *units;
     const uint32_t *blk_flags;  // replayed blocks
-    void *table;
+    void *table;                // 8 << bits bytes
     uint32_t bits;
     DevCounters *ctr;
+    const void *ftable;         // when the free-run log is not sorted: its location table (launch_log_table)
+    uint32_t fbits;
+    uint32_t obits;             // width of the block field of a table word; location bits + obits + 2 <= 64
 };
 hipError_t launch_replay_table(const ReplayTableArgs &a, hipStream_t s);
+// The free run's conflict check without sorting, for the common case: every
+// record is a representative and no global location is written by one block
+// and touched by another.  Builds the location table of the log (rs, n_rs;
+// 2^bits >= 2 n_rs) and sets FLAG_NEED_SORT in
+// ctr->flags when the case does not hold; otherwise there are no cross-block
+// races or links and the epoch-local races are all the races.
+hipError_t launch_log_table(const ReplayTableArgs &a, hipStream_t s);
 hipError_t launch_copy_units(const DevUnit *units, uint32_t n_units, uint32_t max_words, bool to_snapshot,
                              const uint32_t *unit_mask, hipStream_t s);
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);

@@ -110,7 +110,7 @@ struct Workspace {
     DBuf units, items, comp_off, comp_blocks, mask;
     DBuf snap, log, alt, rlog, ralt, fs, hist, part;
     DBuf faults, rfaults, races, lraces, rlraces, edges, blk_recs, rblk_recs, blk_flags, rflags, ctr, rctr;
-    DBuf longseg, covlist, rtable;
+    DBuf longseg, covlist, rtable, ftable;
     DevCounters *h_ctr = nullptr;   // pinned
     void *h_pin = nullptr;          // pinned staging of gathered device-to-host copies
     void *d_pin = nullptr;          // its device mapping
@@ -178,6 +178,7 @@ struct Options {
     uint32_t stage_bytes = 8192;    // LDS for staging + local sort per workgroup (free run)
     int local = 1;                  // epoch-local check in LDS
     int shadow_global = 1;          // ... with global locations in an LDS shadow table (0: stage and sort)
+    int hash_check = 1;             // conflict-free logs checked through a location table, without sorting
     int jit = 0;                    // program-specialised free-run kernels (compiled at first use)
     int jit_waves = 0;              // their occupancy target, waves per SIMD (0: the compiler's choice)
 };
@@ -369,6 +370,14 @@ struct Stage {
         return VKey{kp.s_ep, used_epoch_bits, kp.s_blk, kp.s_ep, kp.s_ep + used_epoch_bits + (kp.total - kp.s_blk)};
     }
     std::vector<uint32_t> blk_recs;
+    // Width of the block field in a location-table word (a global block index
+    // + 1), or 0 when location, block and flags do not fit 64 bits.
+    uint32_t table_obits() const {
+        const uint32_t ob = bits_for((uint64_t)total_blocks + 1);
+        return (kp.total - kp.s_addr) + ob + 2 <= 63 ? ob : 0u;
+    }
+    bool log_sorted = false;        // the free-run log was sorted for its check
+    uint32_t ftable_bits = 0;       // else: log2 slots of its location table (ws.ftable)
 
     // Device-to-host copies gathered into the pinned staging buffer and
     // completed with one synchronisation (each one costs a round trip with the
@@ -759,15 +768,52 @@ struct Stage {
         std::vector<DevEdge> edges;
         uint64_t *sorted = ws.log.as<uint64_t>();
         const uint64_t nrec = c.log_count;
+        log_sorted = false;
+        ftable_bits = 0;
         if (check && nrec) {
-            tm.mark(2);
-            sorted = sort_check(ws.log, ws.alt, nrec);
-            tm.mark(3);
-            run_check(sorted, nrec, ws.blk_flags, races, edges, false);
-            tm.mark(4);
-            ctx->stat_add("sort_ms", tm.ms(2, 3));
-            ctx->stat_add("check_ms", tm.ms(3, 4));
-            ctx->stat_add("sort_keys", (double)nrec);
+            // Common case first: a log of representatives in which no global
+            // location is written by one block and touched by another has no
+            // cross-block races or links, so it needs no sort: a table of its
+            // locations shows it.  Otherwise sort and check.
+            bool need_sort = true;
+            // representatives exist only with the epoch-local check; a very
+            // long log would spend more on its table than on the sort
+            if (ctx->opt.hash_check && ctx->opt.local && nrec <= (1ull << 24) && table_obits() != 0) {
+                tm.mark(2);
+                uint32_t bits = 10;
+                while ((1ull << bits) < 2 * nrec) bits++;
+                ws.ftable.reserve((size_t)8 << bits);
+                reset_counters(ws.rctr);
+                ReplayTableArgs ta{};
+                ta.rs = ws.log.as<uint64_t>();
+                ta.n_rs = nrec;
+                ta.kp = kp;
+                ta.units = ws.units.as<DevUnit>();
+                ta.table = ws.ftable.p;
+                ta.bits = bits;
+                ta.obits = table_obits();
+                ta.ctr = ws.rctr.as<DevCounters>();
+                HIPCHK(launch_log_table(ta, s));
+                Fetch f;
+                const size_t i_t = f.add(ws.rctr.p, sizeof(DevCounters));
+                run_fetch(f);
+                need_sort = (fetched<DevCounters>(f, i_t)->flags & FLAG_NEED_SORT) != 0;
+                tm.mark(3);
+                ctx->stat_add("hash_check_ms", tm.ms(2, 3));
+                if (!need_sort) ftable_bits = bits;
+            }
+            if (need_sort) {
+                tm.mark(2);
+                sorted = sort_check(ws.log, ws.alt, nrec);
+                tm.mark(3);
+                run_check(sorted, nrec, ws.blk_flags, races, edges, false);
+                tm.mark(4);
+                log_sorted = true;
+                ctx->stat_add("sort_ms", tm.ms(2, 3));
+                ctx->stat_add("check_ms", tm.ms(3, 4));
+                ctx->stat_add("sort_keys", (double)nrec);
+                ctx->stat_add("sorted_checks", 1);
+            }
         }
 
         HostTimer post{ctx, "host_post_ms", ctx->opt.timing != 0};
@@ -921,10 +967,11 @@ struct Stage {
     // other; then the canonical execution is the free run of the other blocks
     // plus the replay, and its races are those of the replayed records.
     // Otherwise every block of the affected units is re-executed canonically.
-    void replay(const std::vector<DevRace> &races, const std::vector<DevEdge> &edges, const uint64_t *sorted,
+    void replay(const std::vector<DevRace> &races, const std::vector<DevEdge> &edges, const uint64_t *log_in,
                 uint64_t nrec, std::vector<std::vector<kc_fault>> &ufaults,
                 std::vector<std::vector<kc_race>> &uraces, std::vector<uint64_t> &urecs, Timer &tm) {
         tm.mark(5);
+        const uint64_t *sorted = log_in;     // the free-run log; sorted if log_sorted
         // components: racy blocks (global block index) united along the
         // cross-block links; the root of a component is its smallest block
         constexpr uint32_t NOT_RACY = 0xFFFFFFFFu;
@@ -976,17 +1023,18 @@ struct Stage {
         std::vector<DevRace> rr;
         std::vector<DevEdge> re;
         bool sorted_check = ok && rc.log_count > 0;
-        if (sorted_check) {
+        if (sorted_check && table_obits() != 0) {
             // Common case first: the replay's records are all representatives
             // and no replayed location is shared by replayed blocks with a
             // write; then its exactness needs no sort (one hash pass over the
             // records, one binary search per location).
             uint32_t bits = 10;
             while ((1ull << bits) < 2 * rc.log_count) bits++;
-            ws.rtable.reserve((size_t)16 << bits);
+            ws.rtable.reserve((size_t)8 << bits);
             reset_counters(ws.ctr);
             ReplayTableArgs ta{ws.rlog.as<uint64_t>(), rc.log_count, sorted, nrec, kp, ws.units.as<DevUnit>(),
-                               ws.blk_flags.as<uint32_t>(), ws.rtable.p, bits, ws.ctr.as<DevCounters>()};
+                               ws.blk_flags.as<uint32_t>(), ws.rtable.p, bits, ws.ctr.as<DevCounters>(),
+                               log_sorted ? nullptr : ws.ftable.p, ftable_bits, table_obits()};
             HIPCHK(launch_replay_table(ta, s));
             Fetch f;
             const size_t i_t = f.add(ws.ctr.p, sizeof(DevCounters));
@@ -999,6 +1047,10 @@ struct Stage {
                 ok = !(tc.flags & FLAG_MISMATCH);
             } else {
                 ctx->stat_add("replay_sorted_checks", 1);
+                if (!log_sorted) {      // the exactness scan needs the free-run log sorted
+                    sorted = sort_check(ws.log, ws.alt, nrec);
+                    log_sorted = true;
+                }
             }
         }
         if (sorted_check) {
@@ -1253,6 +1305,7 @@ kc_status kc_ctx_set_option(kc_ctx *ctx, const char *key, int64_t v) {
     else if (k == "stage_bytes" && v >= 8192 && v <= 98304) ctx->opt.stage_bytes = (uint32_t)v;
     else if (k == "local" && (v == 0 || v == 1)) ctx->opt.local = (int)v;
     else if (k == "shadow_global" && (v == 0 || v == 1)) ctx->opt.shadow_global = (int)v;
+    else if (k == "hash_check" && (v == 0 || v == 1)) ctx->opt.hash_check = (int)v;
     else if (k == "jit" && (v == 0 || v == 1)) ctx->opt.jit = (int)v;
     else if (k == "jit_waves" && (v == 0 || (v >= 2 && v <= 8))) ctx->opt.jit_waves = (int)v;
     else if (k == "reset" && v == 1) {
@@ -1281,6 +1334,7 @@ double kc_ctx_get_stat(kc_ctx *ctx, const char *key) {
         if (o == "stage_bytes") return op.stage_bytes;
         if (o == "local") return op.local;
         if (o == "shadow_global") return op.shadow_global;
+        if (o == "hash_check") return op.hash_check;
         if (o == "jit") return op.jit;
         if (o == "jit_waves") return op.jit_waves;
         return 0.0;

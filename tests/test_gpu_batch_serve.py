@@ -79,7 +79,8 @@ def test_local_check_modes_agree(ctx):
     jobs += [W.family_job(f, 5, t, rng, x, 2, 1) for f in W.FAMILIES for t in (64, 256, 1024)
              for x in (None,) + W.FAULTS[f]]
     settings = [("local", 0), ("stage_bytes", 8192), ("stage_bytes", 98304), ("local", 1),
-                ("shadow_global", 0), ("stage_bytes", 8192), ("shadow_global", 1)]
+                ("shadow_global", 0), ("stage_bytes", 8192), ("shadow_global", 1),
+                ("hash_check", 0), ("hash_check", 1)]
     for key, val in settings:
         ctx.set_option(key, val)
         say(f"{key}={val}")

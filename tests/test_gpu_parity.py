@@ -184,16 +184,17 @@ def test_replay_paths(ctx):
 
 
 def test_replay_exactness_paths(ctx):
-    """Replays whose records are all representatives and share no written
-    location between replayed blocks are checked through the hash table of
-    locations (no sorted check); replays of cross-block components take the
-    sorted check.  Both must equal the oracle."""
+    """Logs (of the free run or of a replay) whose records are all
+    representatives and share no written location between blocks are checked
+    through a hash table of locations (no sort); cross-block components take
+    the sorted check.  Both must equal the oracle."""
     job = W.tree256_job(n_blocks=256, drop_frac=0.05, div_frac=0.01, seed=9)
     say("tree replay: hash-table exactness")
     ctx.reset_stats()
     rep, mem = kc.run_job(ctx, job)
     assert_same(rep, mem, O.run_job(job), "tree replay")
     assert ctx.stat("replays") >= 1 and ctx.stat("replay_sorted_checks") == 0 and ctx.stat("fallbacks") == 0
+    assert ctx.stat("sorted_checks") == 0          # its free-run log had no cross-block conflict either
     job = W.stencil_pingpong_job(n=1 << 12, threads=256, steps=2, bug_frac=0.0, seed=4)
     n, nb = job.meta["n"], job.meta["n_blocks"]
     for b in (1, 6, nb - 1):
@@ -202,7 +203,7 @@ def test_replay_exactness_paths(ctx):
     ctx.reset_stats()
     rep, mem = kc.run_job(ctx, job)
     assert_same(rep, mem, O.run_job(job), "pingpong components")
-    assert ctx.stat("replays") >= 1 and ctx.stat("replay_sorted_checks") >= 1
+    assert ctx.stat("replays") >= 1 and ctx.stat("replay_sorted_checks") >= 1 and ctx.stat("sorted_checks") >= 1
 
 
 def test_instruction_count_of_race_free_runs(ctx):
