@@ -380,6 +380,11 @@ __global__ void __launch_bounds__(WG) k_coverage_long(const uint64_t *__restrict
     }
 }
 
+__device__ __forceinline__ void need_sort(DevCounters *ctr) {
+    if (!(__hip_atomic_load(&ctr->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & FLAG_NEED_SORT))
+        atomicOr(&ctr->flags, FLAG_NEED_SORT);
+}
+
 // Locations of a log in a hash table (linear probing), one 64-bit word per
 // slot: location + 1 (0 = empty) | first block + 1 (obits bits) | flags (bit 0
 // a write, bit 1 a second block), so inserting a record is one
@@ -404,7 +409,7 @@ __global__ void __launch_bounds__(WG) k_rtable_insert(ReplayTableArgs a) {
     const KeyPlan &k = a.kp;
     const uint64_t r = a.rs[i];
     if (rec_field(r, k.s_sp, 1) != 1u || rec_field(r, k.s_ep, k.eb) != k.ep_rep) {
-        atomicOr(&a.ctr->flags, FLAG_NEED_SORT);    // an unreduced record
+        need_sort(a.ctr);    // an unreduced record
         return;
     }
     const LocTable t{(unsigned long long *)a.table, a.bits, a.obits};
@@ -431,7 +436,7 @@ __global__ void __launch_bounds__(WG) k_rtable_insert(ReplayTableArgs a) {
         }
         slot = (slot + 1u) & mask;
     }
-    atomicOr(&a.ctr->flags, FLAG_NEED_SORT);        // no free slot
+    need_sort(a.ctr);        // no free slot
 }
 
 __device__ __forceinline__ int64_t ltable_find(const LocTable &t, unsigned long long loc1) {
@@ -446,12 +451,47 @@ __device__ __forceinline__ int64_t ltable_find(const LocTable &t, unsigned long 
     return -1;
 }
 
+// Direct tables, first pass: every word a record touches takes the record's
+// block (one of them wins when several blocks store) and writes set its
+// written flag; plain stores, no atomics.
+__global__ void __launch_bounds__(WG) k_dtable_own(ReplayTableArgs a) {
+    const uint64_t i = (uint64_t)blockIdx.x * WG + threadIdx.x;
+    if (i >= a.n_rs) return;
+    const KeyPlan &k = a.kp;
+    const uint64_t r = a.rs[i];
+    if (rec_field(r, k.s_sp, 1) != 1u || rec_field(r, k.s_ep, k.eb) != k.ep_rep) {
+        need_sort(a.ctr);
+        return;
+    }
+    const DevUnit &u = a.units[rec_field(r, k.s_unit, k.ub)];
+    const uint64_t w = (uint64_t)(u.snap - a.snap_base) + rec_field(r, k.s_addr, k.ab);
+    a.downer[w] = u.block_base + rec_field(r, k.s_blk, k.bb) + 1u;
+    if (r & 1ull) a.dflags[w] = 1;
+}
+
+// Second pass: a record whose block lost the word to another block marks the
+// word as touched by several blocks; with a write among them that is a
+// cross-block conflict.  (Every such word has a record that lost.)
+__global__ void __launch_bounds__(WG) k_dtable_multi(ReplayTableArgs a) {
+    const uint64_t i = (uint64_t)blockIdx.x * WG + threadIdx.x;
+    if (i >= a.n_rs) return;
+    const KeyPlan &k = a.kp;
+    const uint64_t r = a.rs[i];
+    if (rec_field(r, k.s_sp, 1) != 1u || rec_field(r, k.s_ep, k.eb) != k.ep_rep) return;
+    const DevUnit &u = a.units[rec_field(r, k.s_unit, k.ub)];
+    const uint64_t w = (uint64_t)(u.snap - a.snap_base) + rec_field(r, k.s_addr, k.ab);
+    if (a.downer[w] == u.block_base + rec_field(r, k.s_blk, k.bb) + 1u) return;
+    const uint8_t f = a.dflags[w];
+    a.dflags[w] = f | 2;        // every such store writes the same value
+    if (f & 1) need_sort(a.ctr);
+}
+
 // Locations written by one block and touched by another.
 __global__ void __launch_bounds__(WG) k_rtable_conflicts(ReplayTableArgs a) {
     const uint32_t slot = blockIdx.x * WG + threadIdx.x;
     if (slot >= (1u << a.bits)) return;
     const unsigned long long v = ((const unsigned long long *)a.table)[slot];
-    if (v != 0ull && (v & 3ull) == 3ull) atomicOr(&a.ctr->flags, FLAG_NEED_SORT);
+    if (v != 0ull && (v & 3ull) == 3ull) need_sort(a.ctr);
 }
 
 // Per replayed location: a write shared between replayed blocks needs the
@@ -467,17 +507,33 @@ __global__ void __launch_bounds__(WG) k_rtable_check(ReplayTableArgs a) {
     if (v == 0ull) return;
     const uint32_t f = t.flags(v);
     if (f == 3u) {
-        atomicOr(&a.ctr->flags, FLAG_NEED_SORT);
+        need_sort(a.ctr);
         return;
     }
     const unsigned long long loc1 = t.loc(v);
+    if (a.downer) {
+        const KeyPlan &k = a.kp;
+        const unsigned long long loc = loc1 - 1ull;     // address | space << ab | unit << (ab + 1)
+        const DevUnit &u = a.units[(uint32_t)(loc >> (k.ab + 1))];
+        const uint64_t w = (uint64_t)(u.snap - a.snap_base) + (uint32_t)(loc & ((1ull << k.ab) - 1ull));
+        const uint32_t own = a.downer[w];
+        if (own == 0u) return;                              // untouched by the free run
+        const uint8_t ff = a.dflags[w];
+        if (ff & 2) {
+            need_sort(a.ctr);
+            return;
+        }
+        if (a.blk_flags[own - 1u]) return;                  // its one block was replayed
+        if ((f & 1u) || (ff & 1)) atomicOr(&a.ctr->flags, FLAG_MISMATCH);
+        return;
+    }
     if (a.ftable) {
         const LocTable ft{(unsigned long long *)const_cast<void *>(a.ftable), a.fbits, a.obits};
         const int64_t fs = ltable_find(ft, loc1);
         if (fs < 0) return;                                 // untouched by the free run
         const unsigned long long fv = ft.w[fs];
         if (ft.flags(fv) & 2u) {
-            atomicOr(&a.ctr->flags, FLAG_NEED_SORT);
+            need_sort(a.ctr);
             return;
         }
         if (a.blk_flags[ft.owner(fv) - 1u]) return;        // its one block was replayed
@@ -491,7 +547,7 @@ __global__ void __launch_bounds__(WG) k_rtable_check(ReplayTableArgs a) {
         const uint64_t x = a.log[j];
         if ((x >> k.s_addr) != target) break;
         if (j - lo == COV_LIMIT) {
-            atomicOr(&a.ctr->flags, FLAG_NEED_SORT);
+            need_sort(a.ctr);
             return;
         }
         const DevUnit &u = a.units[rec_field(x, k.s_unit, k.ub)];
@@ -593,6 +649,16 @@ hipError_t launch_log_table(const ReplayTableArgs &a, hipStream_t s) {
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_rtable_insert, dim3(blocks_for(a.n_rs)), dim3(WG), 0, s, a);
     hipLaunchKernelGGL(k_rtable_conflicts, dim3(blocks_for(1ull << a.bits)), dim3(WG), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_log_direct(const ReplayTableArgs &a, uint64_t words, hipStream_t s) {
+    if (a.n_rs == 0) return hipSuccess;
+    hipError_t e = launch_zero(a.downer, (size_t)words * 4, s);
+    if (e == hipSuccess) e = launch_zero(a.dflags, (size_t)((words + 3) / 4) * 4, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_dtable_own, dim3(blocks_for(a.n_rs)), dim3(WG), 0, s, a);
+    hipLaunchKernelGGL(k_dtable_multi, dim3(blocks_for(a.n_rs)), dim3(WG), 0, s, a);
     return hipGetLastError();
 }
 

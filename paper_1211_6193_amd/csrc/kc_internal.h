@@ -190,6 +190,14 @@ struct ReplayTableArgs {
     const void *ftable;         // when the free-run log is not sorted: its location table (launch_log_table)
     uint32_t fbits;
     uint32_t obits;             // width of the block field of a table word; location bits + obits + 2 <= 64
+    // Direct tables, one entry per memory word of every unit (word index =
+    // unit snapshot - snap_base + address), used instead of the hash table
+    // when memories are small next to the log: the block + 1 of a record that
+    // touched the word (0: untouched), and flags (bit 0 written, bit 1 several
+    // blocks).  With downer set, the replay looks locations up there.
+    const int32_t *snap_base;
+    uint32_t *downer;
+    uint8_t *dflags;
 };
 hipError_t launch_replay_table(const ReplayTableArgs &a, hipStream_t s);
 // The free run's conflict check without sorting, for the common case: every
@@ -199,6 +207,9 @@ hipError_t launch_replay_table(const ReplayTableArgs &a, hipStream_t s);
 // ctr->flags when the case does not hold; otherwise there are no cross-block
 // races or links and the epoch-local races are all the races.
 hipError_t launch_log_table(const ReplayTableArgs &a, hipStream_t s);
+// The same check through the direct tables (rs, n_rs, kp, units, snap_base,
+// downer, dflags; `words` entries, zeroed here).
+hipError_t launch_log_direct(const ReplayTableArgs &a, uint64_t words, hipStream_t s);
 hipError_t launch_copy_units(const DevUnit *units, uint32_t n_units, uint32_t max_words, bool to_snapshot,
                              const uint32_t *unit_mask, hipStream_t s);
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);

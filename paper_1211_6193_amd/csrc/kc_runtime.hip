@@ -110,7 +110,7 @@ struct Workspace {
     DBuf units, items, comp_off, comp_blocks, mask;
     DBuf snap, log, alt, rlog, ralt, fs, hist, part;
     DBuf faults, rfaults, races, lraces, rlraces, edges, blk_recs, rblk_recs, blk_flags, rflags, ctr, rctr;
-    DBuf longseg, covlist, rtable, ftable;
+    DBuf longseg, covlist, rtable, ftable, downer, dflags;
     DevCounters *h_ctr = nullptr;   // pinned
     void *h_pin = nullptr;          // pinned staging of gathered device-to-host copies
     void *d_pin = nullptr;          // its device mapping
@@ -377,7 +377,8 @@ struct Stage {
         return (kp.total - kp.s_addr) + ob + 2 <= 63 ? ob : 0u;
     }
     bool log_sorted = false;        // the free-run log was sorted for its check
-    uint32_t ftable_bits = 0;       // else: log2 slots of its location table (ws.ftable)
+    uint32_t ftable_bits = 0;       // else: log2 slots of its location table (ws.ftable),
+    bool direct_tables = false;     // or its direct word tables (ws.downer, ws.dflags)
 
     // Device-to-host copies gathered into the pinned staging buffer and
     // completed with one synchronisation (each one costs a round trip with the
@@ -770,6 +771,7 @@ struct Stage {
         const uint64_t nrec = c.log_count;
         log_sorted = false;
         ftable_bits = 0;
+        direct_tables = false;
         if (check && nrec) {
             // Common case first: a log of representatives in which no global
             // location is written by one block and touched by another has no
@@ -778,29 +780,44 @@ struct Stage {
             bool need_sort = true;
             // representatives exist only with the epoch-local check; a very
             // long log would spend more on its table than on the sort
-            if (ctx->opt.hash_check && ctx->opt.local && nrec <= (1ull << 24) && table_obits() != 0) {
+            // Memories small next to the log: one table entry per memory word
+            // (two passes of plain stores); else a hash table of locations.
+            const bool direct = total_words <= 4 * nrec + (1u << 16);
+            if (ctx->opt.hash_check && ctx->opt.local && nrec <= (1ull << 24) && (direct || table_obits() != 0)) {
                 tm.mark(2);
                 uint32_t bits = 10;
                 while ((1ull << bits) < 2 * nrec) bits++;
-                ws.ftable.reserve((size_t)8 << bits);
                 reset_counters(ws.rctr);
                 ReplayTableArgs ta{};
                 ta.rs = ws.log.as<uint64_t>();
                 ta.n_rs = nrec;
                 ta.kp = kp;
                 ta.units = ws.units.as<DevUnit>();
-                ta.table = ws.ftable.p;
-                ta.bits = bits;
-                ta.obits = table_obits();
                 ta.ctr = ws.rctr.as<DevCounters>();
-                HIPCHK(launch_log_table(ta, s));
+                if (direct) {
+                    ws.downer.reserve(std::max<uint64_t>(total_words, 1) * 4);
+                    ws.dflags.reserve((std::max<uint64_t>(total_words, 1) + 3) / 4 * 4);
+                    ta.snap_base = ws.snap.as<int32_t>();
+                    ta.downer = ws.downer.as<uint32_t>();
+                    ta.dflags = ws.dflags.as<uint8_t>();
+                    HIPCHK(launch_log_direct(ta, total_words, s));
+                } else {
+                    ws.ftable.reserve((size_t)8 << bits);
+                    ta.table = ws.ftable.p;
+                    ta.bits = bits;
+                    ta.obits = table_obits();
+                    HIPCHK(launch_log_table(ta, s));
+                }
                 Fetch f;
                 const size_t i_t = f.add(ws.rctr.p, sizeof(DevCounters));
                 run_fetch(f);
                 need_sort = (fetched<DevCounters>(f, i_t)->flags & FLAG_NEED_SORT) != 0;
                 tm.mark(3);
                 ctx->stat_add("hash_check_ms", tm.ms(2, 3));
-                if (!need_sort) ftable_bits = bits;
+                if (!need_sort) {
+                    ftable_bits = direct ? 0 : bits;
+                    direct_tables = direct;
+                }
             }
             if (need_sort) {
                 tm.mark(2);
@@ -1034,7 +1051,9 @@ struct Stage {
             reset_counters(ws.ctr);
             ReplayTableArgs ta{ws.rlog.as<uint64_t>(), rc.log_count, sorted, nrec, kp, ws.units.as<DevUnit>(),
                                ws.blk_flags.as<uint32_t>(), ws.rtable.p, bits, ws.ctr.as<DevCounters>(),
-                               log_sorted ? nullptr : ws.ftable.p, ftable_bits, table_obits()};
+                               (log_sorted || direct_tables) ? nullptr : ws.ftable.p, ftable_bits, table_obits(),
+                               ws.snap.as<int32_t>(), (!log_sorted && direct_tables) ? ws.downer.as<uint32_t>() : nullptr,
+                               ws.dflags.as<uint8_t>()};
             HIPCHK(launch_replay_table(ta, s));
             Fetch f;
             const size_t i_t = f.add(ws.ctr.p, sizeof(DevCounters));
@@ -1047,11 +1066,11 @@ struct Stage {
                 ok = !(tc.flags & FLAG_MISMATCH);
             } else {
                 ctx->stat_add("replay_sorted_checks", 1);
-                if (!log_sorted) {      // the exactness scan needs the free-run log sorted
-                    sorted = sort_check(ws.log, ws.alt, nrec);
-                    log_sorted = true;
-                }
             }
+        }
+        if (sorted_check && !log_sorted) {      // the exactness scan needs the free-run log sorted
+            sorted = sort_check(ws.log, ws.alt, nrec);
+            log_sorted = true;
         }
         if (sorted_check) {
             used_epoch_bits = std::max(used_epoch_bits, bits_for((uint64_t)rc.max_epoch + 2));

@@ -195,6 +195,15 @@ def test_replay_exactness_paths(ctx):
     assert_same(rep, mem, O.run_job(job), "tree replay")
     assert ctx.stat("replays") >= 1 and ctx.stat("replay_sorted_checks") == 0 and ctx.stat("fallbacks") == 0
     assert ctx.stat("sorted_checks") == 0          # its free-run log had no cross-block conflict either
+    # the same on a memory much larger than the log: locations go to the hash
+    # table instead of one entry per memory word
+    job = W.tree256_job(n_blocks=64, drop_frac=0.1, div_frac=0.03, seed=10)
+    job.memory = np.concatenate([job.memory, np.zeros(1 << 20, np.int32)])
+    say("tree replay on a large memory: hash-table check")
+    ctx.reset_stats()
+    rep, mem = kc.run_job(ctx, job)
+    assert_same(rep, mem, O.run_job(job), "tree replay, large memory")
+    assert ctx.stat("replays") >= 1 and ctx.stat("sorted_checks") == 0 and ctx.stat("replay_sorted_checks") == 0
     job = W.stencil_pingpong_job(n=1 << 12, threads=256, steps=2, bug_frac=0.0, seed=4)
     n, nb = job.meta["n"], job.meta["n_blocks"]
     for b in (1, 6, nb - 1):
