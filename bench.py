@@ -98,7 +98,7 @@ def main():
                                       "fallbacks", "retries", "sort_keys", "records", "interp_launches",
                                       "replay_lockstep_ms", "replay_sort_ms", "replay_check_ms",
                                       "replay_coverage_ms", "log_entries", "instructions", "jit_launches",
-                                      "hash_check_ms", "sorted_checks", "replay_table_ms", "replay_sorted_checks")}
+                                      "hash_check_ms", "sorted_checks", "replay_sorted_checks")}
     per = {k: stats[k] / args.steps for k in ("interp_ms", "hash_check_ms", "sort_ms", "check_ms", "replay_ms")}
     roofline = interp_roofline(stats, args.steps, records, value, per)
 
@@ -165,7 +165,7 @@ def interp_roofline(stats, steps, records, value, per):
             "avg_ms": round(per["interp_ms"], 4), "thread_instructions_per_launch": int(instr),
             "stage_ms": {k: round(v, 4) for k, v in per.items()},
             "replay_detail_ms": {k: round(stats[k] / steps, 4) for k in
-                                 ("replay_lockstep_ms", "replay_table_ms", "replay_sort_ms", "replay_check_ms",
+                                 ("replay_lockstep_ms", "replay_sort_ms", "replay_check_ms",
                                   "replay_coverage_ms")},
             "sorted_checks_per_step": stats["sorted_checks"] / steps,
             "replay_sorted_checks_per_step": stats["replay_sorted_checks"] / steps,

@@ -380,6 +380,14 @@ __global__ void __launch_bounds__(WG) k_coverage_long(const uint64_t *__restrict
     }
 }
 
+// Records of the table's log: n_rs, or the count the producing kernel left
+// on the device (n_rs is then its capacity).
+__device__ __forceinline__ uint64_t n_records(const ReplayTableArgs &a) {
+    if (!a.n_dev) return a.n_rs;
+    const uint64_t n = __hip_atomic_load(a.n_dev, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return n < a.n_rs ? n : a.n_rs;
+}
+
 __device__ __forceinline__ void need_sort(DevCounters *ctr) {
     if (!(__hip_atomic_load(&ctr->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & FLAG_NEED_SORT))
         atomicOr(&ctr->flags, FLAG_NEED_SORT);
@@ -405,7 +413,7 @@ struct LocTable {
 
 __global__ void __launch_bounds__(WG) k_rtable_insert(ReplayTableArgs a) {
     const uint64_t i = (uint64_t)blockIdx.x * WG + threadIdx.x;
-    if (i >= a.n_rs) return;
+    if (i >= n_records(a)) return;
     const KeyPlan &k = a.kp;
     const uint64_t r = a.rs[i];
     if (rec_field(r, k.s_sp, 1) != 1u || rec_field(r, k.s_ep, k.eb) != k.ep_rep) {
@@ -456,7 +464,7 @@ __device__ __forceinline__ int64_t ltable_find(const LocTable &t, unsigned long 
 // written flag; plain stores, no atomics.
 __global__ void __launch_bounds__(WG) k_dtable_own(ReplayTableArgs a) {
     const uint64_t i = (uint64_t)blockIdx.x * WG + threadIdx.x;
-    if (i >= a.n_rs) return;
+    if (i >= n_records(a)) return;
     const KeyPlan &k = a.kp;
     const uint64_t r = a.rs[i];
     if (rec_field(r, k.s_sp, 1) != 1u || rec_field(r, k.s_ep, k.eb) != k.ep_rep) {
@@ -474,7 +482,7 @@ __global__ void __launch_bounds__(WG) k_dtable_own(ReplayTableArgs a) {
 // cross-block conflict.  (Every such word has a record that lost.)
 __global__ void __launch_bounds__(WG) k_dtable_multi(ReplayTableArgs a) {
     const uint64_t i = (uint64_t)blockIdx.x * WG + threadIdx.x;
-    if (i >= a.n_rs) return;
+    if (i >= n_records(a)) return;
     const KeyPlan &k = a.kp;
     const uint64_t r = a.rs[i];
     if (rec_field(r, k.s_sp, 1) != 1u || rec_field(r, k.s_ep, k.eb) != k.ep_rep) return;

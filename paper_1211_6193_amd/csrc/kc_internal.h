@@ -198,6 +198,10 @@ struct ReplayTableArgs {
     const int32_t *snap_base;
     uint32_t *downer;
     uint8_t *dflags;
+    // When set, the number of records is read here on the device (the log's
+    // counter), and n_rs is only its capacity: the tables can be queued
+    // behind the kernel that writes the log.
+    const unsigned long long *n_dev;
 };
 hipError_t launch_replay_table(const ReplayTableArgs &a, hipStream_t s);
 // The free run's conflict check without sorting, for the common case: every

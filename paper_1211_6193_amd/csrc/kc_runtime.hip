@@ -126,7 +126,7 @@ struct Workspace {
         HIPCHK(hipHostGetDevicePointer(&d_pin, h_pin, 0));
         h_pin_bytes = nb;
     }
-    hipEvent_t ev[12] = {};
+    hipEvent_t ev[16] = {};
     bool init = false;
     void setup() {
         if (init) return;
@@ -370,6 +370,48 @@ struct Stage {
         return VKey{kp.s_ep, used_epoch_bits, kp.s_blk, kp.s_ep, kp.s_ep + used_epoch_bits + (kp.total - kp.s_blk)};
     }
     std::vector<uint32_t> blk_recs;
+    // Queue the free run's conflict check through location tables (see
+    // launch_log_table) behind the free run, for a log of up to `cap`
+    // records whose count the kernels read on the device.  Memories small
+    // next to the log get one table entry per memory word (two passes of
+    // plain stores), others a hash table of locations.  Flags go to ws.rctr.
+    bool qt_direct = false;
+    uint32_t qt_bits = 0;
+    bool queue_log_check(uint64_t cap) {
+        // representatives exist only with the epoch-local check; a very long
+        // log would spend more on its table than on the sort
+        const bool direct = total_words <= 4 * cap + (1u << 16);
+        if (!(ctx->opt.hash_check && ctx->opt.local && cap <= (1ull << 24) && (direct || table_obits() != 0)))
+            return false;
+        uint32_t bits = 10;
+        while ((1ull << bits) < 2 * cap) bits++;
+        reset_counters(ws.rctr);
+        ReplayTableArgs ta{};
+        ta.rs = ws.log.as<uint64_t>();
+        ta.n_rs = cap;
+        ta.n_dev = &ws.ctr.as<DevCounters>()->log_count;
+        ta.kp = kp;
+        ta.units = ws.units.as<DevUnit>();
+        ta.ctr = ws.rctr.as<DevCounters>();
+        if (direct) {
+            ws.downer.reserve(std::max<uint64_t>(total_words, 1) * 4);
+            ws.dflags.reserve((std::max<uint64_t>(total_words, 1) + 3) / 4 * 4);
+            ta.snap_base = ws.snap.as<int32_t>();
+            ta.downer = ws.downer.as<uint32_t>();
+            ta.dflags = ws.dflags.as<uint8_t>();
+            HIPCHK(launch_log_direct(ta, total_words, s));
+        } else {
+            ws.ftable.reserve((size_t)8 << bits);
+            ta.table = ws.ftable.p;
+            ta.bits = bits;
+            ta.obits = table_obits();
+            HIPCHK(launch_log_table(ta, s));
+        }
+        qt_direct = direct;
+        qt_bits = bits;
+        return true;
+    }
+
     // Width of the block field in a location-table word (a global block index
     // + 1), or 0 when location, block and flags do not fit 64 bits.
     uint32_t table_obits() const {
@@ -705,6 +747,7 @@ struct Stage {
         ws.blk_flags.reserve((size_t)total_blocks * 4);
         DevCounters c{};
         Fetch fetch;
+        bool table_queued = false;
         for (;;) {
             ws.faults.reserve((size_t)fault_cap * sizeof(DevFault));
             ws.lraces.reserve((size_t)lrace_cap * sizeof(DevRace));
@@ -715,11 +758,14 @@ struct Stage {
             interp(false, ws.log, log_cap, ws.ctr, ws.faults, fault_cap, ws.blk_recs, 0, ws.lraces, lrace_cap,
                    ws.blk_flags);
             tm.mark(1);
+            table_queued = check && queue_log_check(log_cap);
+            tm.mark(12);
             fetch = Fetch{};
             const size_t i_ctr = fetch.add(ws.ctr.p, sizeof(DevCounters));
             fetch.add(ws.blk_recs.p, (size_t)total_blocks * 4);
             fetch.add(ws.faults.p, (size_t)std::min(fault_cap, kSpec) * sizeof(DevFault));
             fetch.add(ws.lraces.p, (size_t)std::min(lrace_cap, kSpec) * sizeof(DevRace));
+            if (table_queued) fetch.add(ws.rctr.p, sizeof(DevCounters));      // item 4
             run_fetch(fetch);
             c = *fetched<DevCounters>(fetch, i_ctr);
             ctx->stat_add("interp_ms", tm.ms(0, 1));
@@ -778,45 +824,12 @@ struct Stage {
             // cross-block races or links, so it needs no sort: a table of its
             // locations shows it.  Otherwise sort and check.
             bool need_sort = true;
-            // representatives exist only with the epoch-local check; a very
-            // long log would spend more on its table than on the sort
-            // Memories small next to the log: one table entry per memory word
-            // (two passes of plain stores); else a hash table of locations.
-            const bool direct = total_words <= 4 * nrec + (1u << 16);
-            if (ctx->opt.hash_check && ctx->opt.local && nrec <= (1ull << 24) && (direct || table_obits() != 0)) {
-                tm.mark(2);
-                uint32_t bits = 10;
-                while ((1ull << bits) < 2 * nrec) bits++;
-                reset_counters(ws.rctr);
-                ReplayTableArgs ta{};
-                ta.rs = ws.log.as<uint64_t>();
-                ta.n_rs = nrec;
-                ta.kp = kp;
-                ta.units = ws.units.as<DevUnit>();
-                ta.ctr = ws.rctr.as<DevCounters>();
-                if (direct) {
-                    ws.downer.reserve(std::max<uint64_t>(total_words, 1) * 4);
-                    ws.dflags.reserve((std::max<uint64_t>(total_words, 1) + 3) / 4 * 4);
-                    ta.snap_base = ws.snap.as<int32_t>();
-                    ta.downer = ws.downer.as<uint32_t>();
-                    ta.dflags = ws.dflags.as<uint8_t>();
-                    HIPCHK(launch_log_direct(ta, total_words, s));
-                } else {
-                    ws.ftable.reserve((size_t)8 << bits);
-                    ta.table = ws.ftable.p;
-                    ta.bits = bits;
-                    ta.obits = table_obits();
-                    HIPCHK(launch_log_table(ta, s));
-                }
-                Fetch f;
-                const size_t i_t = f.add(ws.rctr.p, sizeof(DevCounters));
-                run_fetch(f);
-                need_sort = (fetched<DevCounters>(f, i_t)->flags & FLAG_NEED_SORT) != 0;
-                tm.mark(3);
-                ctx->stat_add("hash_check_ms", tm.ms(2, 3));
+            if (table_queued) {     // queued behind the free run: its flags came with the counters
+                need_sort = (fetched<DevCounters>(fetch, 4)->flags & FLAG_NEED_SORT) != 0;
+                ctx->stat_add("hash_check_ms", tm.ms(1, 12));
                 if (!need_sort) {
-                    ftable_bits = direct ? 0 : bits;
-                    direct_tables = direct;
+                    ftable_bits = qt_direct ? 0 : qt_bits;
+                    direct_tables = qt_direct;
                 }
             }
             if (need_sort) {
@@ -944,9 +957,10 @@ struct Stage {
         std::vector<DevFault> faults;
         std::vector<uint32_t> recs;
         std::vector<DevRace> lraces;
+        uint32_t table_flags = 0;      // flags of the exactness tables, if queued
     };
     DevCounters lockstep_once(const std::vector<std::vector<uint2>> &comps, uint64_t rcap, uint32_t fcap,
-                              uint32_t rlcap, ReplayOut *res = nullptr) {
+                              uint32_t rlcap, ReplayOut *res = nullptr, const ReplayTableArgs *table = nullptr) {
         upload_comps(comps);
         ws.rblk_recs.reserve((size_t)total_blocks * 4);
         ws.rflags.reserve((size_t)std::max<uint32_t>(total_blocks, 1) * 4);
@@ -957,6 +971,10 @@ struct Stage {
         HIPCHK(launch_zero(ws.rblk_recs.p, (size_t)total_blocks * 4, s));
         interp(true, ws.rlog, rcap, ws.rctr, ws.rfaults, fcap, ws.rblk_recs, (uint32_t)comps.size(), ws.rlraces,
                rlcap, ws.rflags);
+        if (table) {            // the replay's exactness tables, queued behind it (flags in ws.ctr)
+            reset_counters(ws.ctr);
+            HIPCHK(launch_replay_table(*table, s));
+        }
         Fetch f;
         const size_t i_ctr = f.add(ws.rctr.p, sizeof(DevCounters));
         if (res) {
@@ -964,8 +982,10 @@ struct Stage {
             f.add(ws.rblk_recs.p, (size_t)total_blocks * 4);
             f.add(ws.rlraces.p, (size_t)std::min(rlcap, kSpec) * sizeof(DevRace));
         }
+        const size_t i_tab = table ? f.add(ws.ctr.p, sizeof(DevCounters)) : 0;
         run_fetch(f);
         const DevCounters c = *fetched<DevCounters>(f, i_ctr);
+        if (res && table) res->table_flags = fetched<DevCounters>(f, i_tab)->flags;
         if (c.flags & FLAG_EPOCH_OVERFLOW)
             throw KcError{KC_E_OVERFLOW, "barrier epochs exceed the record's epoch field"};
         if (res && !(c.flags & (FLAG_LOG_OVERFLOW | FLAG_FAULT_OVERFLOW | FLAG_RACE_OVERFLOW))) {
@@ -1033,37 +1053,35 @@ struct Stage {
         uint64_t rcap = s_recs + s_recs / 4 + 1024;
         uint32_t fcap = 4096, rlcap = 4096 + (uint32_t)races.size() * 2;
         ReplayOut ro;
-        DevCounters rc = lockstep_once(comps, rcap, fcap, rlcap, &ro);
+        // Common case first: the replay's records are all representatives and
+        // no replayed location is shared by replayed blocks with a write; then
+        // its exactness needs no sort (a table of its locations, each looked
+        // up in the free run's tables or its sorted log).  Queued behind the
+        // lockstep kernel, sized for its log capacity.
+        const bool use_table = table_obits() != 0;
+        uint32_t bits = 10;
+        while ((1ull << bits) < 2 * rcap) bits++;
+        if (use_table) ws.rtable.reserve((size_t)8 << bits);
+        ws.rlog.reserve(rcap * 8);
+        ReplayTableArgs ta{ws.rlog.as<uint64_t>(), rcap, sorted, nrec, kp, ws.units.as<DevUnit>(),
+                           ws.blk_flags.as<uint32_t>(), use_table ? ws.rtable.p : nullptr, bits,
+                           ws.ctr.as<DevCounters>(), (log_sorted || direct_tables) ? nullptr : ws.ftable.p,
+                           ftable_bits, table_obits(), ws.snap.as<int32_t>(),
+                           (!log_sorted && direct_tables) ? ws.downer.as<uint32_t>() : nullptr,
+                           ws.dflags.as<uint8_t>(), nullptr};
+        ws.rctr.reserve(sizeof(DevCounters));
+        ta.n_dev = &ws.rctr.as<DevCounters>()->log_count;
+        DevCounters rc = lockstep_once(comps, rcap, fcap, rlcap, &ro, use_table ? &ta : nullptr);
         tm.mark(7);
         ctx->stat_add("replay_lockstep_ms", tm.ms(5, 7));
         bool ok = !(rc.flags & (FLAG_LOG_OVERFLOW | FLAG_FAULT_OVERFLOW | FLAG_RACE_OVERFLOW));
         std::vector<DevRace> rr;
         std::vector<DevEdge> re;
         bool sorted_check = ok && rc.log_count > 0;
-        if (sorted_check && table_obits() != 0) {
-            // Common case first: the replay's records are all representatives
-            // and no replayed location is shared by replayed blocks with a
-            // write; then its exactness needs no sort (one hash pass over the
-            // records, one binary search per location).
-            uint32_t bits = 10;
-            while ((1ull << bits) < 2 * rc.log_count) bits++;
-            ws.rtable.reserve((size_t)8 << bits);
-            reset_counters(ws.ctr);
-            ReplayTableArgs ta{ws.rlog.as<uint64_t>(), rc.log_count, sorted, nrec, kp, ws.units.as<DevUnit>(),
-                               ws.blk_flags.as<uint32_t>(), ws.rtable.p, bits, ws.ctr.as<DevCounters>(),
-                               (log_sorted || direct_tables) ? nullptr : ws.ftable.p, ftable_bits, table_obits(),
-                               ws.snap.as<int32_t>(), (!log_sorted && direct_tables) ? ws.downer.as<uint32_t>() : nullptr,
-                               ws.dflags.as<uint8_t>()};
-            HIPCHK(launch_replay_table(ta, s));
-            Fetch f;
-            const size_t i_t = f.add(ws.ctr.p, sizeof(DevCounters));
-            run_fetch(f);
-            const DevCounters tc = *fetched<DevCounters>(f, i_t);
-            tm.mark(11);
-            ctx->stat_add("replay_table_ms", tm.ms(7, 11));
-            if (!(tc.flags & FLAG_NEED_SORT)) {
+        if (sorted_check && use_table) {
+            if (!(ro.table_flags & FLAG_NEED_SORT)) {
                 sorted_check = false;
-                ok = !(tc.flags & FLAG_MISMATCH);
+                ok = !(ro.table_flags & FLAG_MISMATCH);
             } else {
                 ctx->stat_add("replay_sorted_checks", 1);
             }
@@ -1088,7 +1106,7 @@ struct Stage {
             run_check(rs, rc.log_count, ws.rflags, rr, re, true, ws.ctr.as<DevCounters>(), &cov);
             tm.mark(9);
             ok = !(cov.flags & FLAG_MISMATCH);
-            ctx->stat_add("replay_sort_ms", tm.ms(11, 8));
+            ctx->stat_add("replay_sort_ms", tm.ms(7, 8));
             ctx->stat_add("replay_coverage_ms", tm.ms(8, 10));
             ctx->stat_add("replay_check_ms", tm.ms(10, 9));
             for (auto &e : re)
