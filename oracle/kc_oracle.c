@@ -14,6 +14,20 @@
  *     Section 3 "Streams and events").  A launch whose grid does not complete
  *     (a block deadlocked) ends the job: a grid counts as complete only when
  *     all of its threads have finished (Section 3 "Threads and memory").
+ *   - Streams and events (Section 3 "Streams and events"): each launch may
+ *     name a stream, and a dependency (before, after) says that launch `after`
+ *     waits for launch `before` to finish (an event recorded behind `before`
+ *     and waited on ahead of `after`, or a host synchronisation).  Launch i
+ *     happens before launch j when a chain of same-stream order (an earlier
+ *     launch of the same stream) and dependencies leads from i to j.  Two
+ *     launches ordered neither way may run in parallel; the job still
+ *     executes them in submission order, which respects every chain.  A global
+ *     word accessed by two such launches, written by at least one, is a race
+ *     between them (scope 2), reported on the later launch j with
+ *     block = i, epoch = 0xFFFFFFFF, w_tid = the smallest global thread id of
+ *     j whose access to the word conflicts with an access of i, and o_tid the
+ *     same for i: if the other launch writes the word every access conflicts,
+ *     otherwise only writes do.
  *   - Within a launch the blocks run one after another in ascending linear
  *     block id; this is one of the interleavings the semantics admits
  *     (Section 3 "Threads and memory": scheduling is constrained only by grid
@@ -455,11 +469,68 @@ static int cmp_fault(const void *pa, const void *pb) {
     return 0;
 }
 
-/* Run a job.  progs[i]/prog_lens[i] is launch i's program; mem is updated in place. */
-int ora_run_job(uint32_t n_launches, const uint64_t *const *progs, const uint32_t *prog_lens,
-                const ora_launch *launches, int32_t *mem, uint64_t n_words, uint32_t fuel,
-                int keep_records, ora_result **out) {
+/* ---- launches that may run in parallel (Section 3 "Streams and events") ---- */
+/* hb[i * n + j] = 1 when launch i happens before launch j: the transitive
+ * closure (Warshall) of "an earlier launch of the same stream" and of the
+ * dependencies.  NULL streams put every launch in one stream. */
+static uint8_t *happens_before(uint32_t n, const uint32_t *streams, const uint32_t *deps, uint32_t n_deps) {
+    uint8_t *hb = calloc((size_t)n * n + 1, 1);
+    if (!hb) return NULL;
+    for (uint32_t j = 0; j < n; j++)
+        for (uint32_t i = 0; i < j; i++)
+            if (!streams || streams[i] == streams[j]) hb[(size_t)i * n + j] = 1;
+    for (uint32_t d = 0; d < n_deps; d++) hb[(size_t)deps[2 * d] * n + deps[2 * d + 1]] = 1;
+    for (uint32_t k = 0; k < n; k++)
+        for (uint32_t i = 0; i < n; i++)
+            if (hb[(size_t)i * n + k])
+                for (uint32_t j = 0; j < n; j++)
+                    if (hb[(size_t)k * n + j]) hb[(size_t)i * n + j] = 1;
+    return hb;
+}
+
+/* Smallest global thread id accessing each global word (acc) and writing it
+ * (wr) in the current launch's records; 0xFFFFFFFF where none. */
+static uint32_t *access_summary(const ora_result *res, uint64_t n_words, uint32_t nt) {
+    uint32_t *sum = malloc((2 * n_words + 1) * sizeof(uint32_t));
+    if (!sum) return NULL;
+    for (uint64_t x = 0; x < 2 * n_words; x++) sum[x] = 0xFFFFFFFFu;
+    uint32_t *acc = sum, *wr = sum + n_words;
+    for (uint64_t i = 0; i < res->n_recs; i++) {
+        const ora_record *r = &res->recs[i];
+        if (r->space != SP_GLOBAL) continue;
+        const uint32_t g = r->block * nt + r->tid;
+        if (g < acc[r->addr]) acc[r->addr] = g;
+        if (r->kind == K_WRITE && g < wr[r->addr]) wr[r->addr] = g;
+    }
+    return sum;
+}
+
+/* Races between launch i (summary si) and the later launch j (sj). */
+static void cross_launch_races(ora_result *res, uint32_t i, const uint32_t *si, uint32_t j, const uint32_t *sj,
+                               uint64_t n_words) {
+    const uint32_t NONE = 0xFFFFFFFFu;
+    for (uint64_t x = 0; x < n_words; x++) {
+        const uint32_t ai = si[x], wi = si[n_words + x], aj = sj[x], wj = sj[n_words + x];
+        const int conflict = (wi != NONE && aj != NONE) || (wj != NONE && ai != NONE);
+        if (!conflict) continue;
+        const uint32_t tj = wi != NONE ? aj : wj;   /* j's smallest thread conflicting with i */
+        const uint32_t ti = wj != NONE ? ai : wi;
+        ora_race rc = {j, SP_GLOBAL, 2, i, 0xFFFFFFFFu, (uint32_t)x, tj, ti};
+        add_race(res, rc);
+        if (res->oom) return;
+    }
+}
+
+/* Run a job.  progs[i]/prog_lens[i] is launch i's program; mem is updated in
+ * place.  streams (n_launches entries) and deps (n_deps pairs before, after
+ * with before < after) may be NULL / 0: one stream. */
+int ora_run_job_streams(uint32_t n_launches, const uint64_t *const *progs, const uint32_t *prog_lens,
+                        const ora_launch *launches, int32_t *mem, uint64_t n_words, uint32_t fuel,
+                        int keep_records, const uint32_t *streams, const uint32_t *deps, uint32_t n_deps,
+                        ora_result **out) {
     *out = NULL;
+    for (uint32_t d = 0; d < n_deps; d++)
+        if (deps[2 * d] >= deps[2 * d + 1] || deps[2 * d + 1] >= n_launches) return 1;
     for (uint32_t i = 0; i < n_launches; i++) {
         if (ora_validate(progs[i], prog_lens[i])) return 2;
         const ora_launch *L = &launches[i];
@@ -470,7 +541,10 @@ int ora_run_job(uint32_t n_launches, const uint64_t *const *progs, const uint32_
     ora_result *res = calloc(1, sizeof(ora_result));
     if (!res) return 3;
     res->keep_records = keep_records;
-    for (uint32_t li = 0; li < n_launches; li++) {
+    uint8_t *hb = happens_before(n_launches, streams, deps, n_deps);
+    uint32_t **sums = calloc((size_t)n_launches + 1, sizeof(uint32_t *));
+    if (!hb || !sums) res->oom = 1;
+    for (uint32_t li = 0; li < n_launches && !res->oom; li++) {
         const ora_launch *L = &launches[li];
         uint32_t nt = L->block[0] * L->block[1] * L->block[2];
         uint32_t nb = L->grid[0] * L->grid[1] * L->grid[2];
@@ -483,11 +557,26 @@ int ora_run_job(uint32_t n_launches, const uint64_t *const *progs, const uint32_
             deadlocked |= run_block(res, li, progs[li], prog_lens[li], L, b, mem, n_words, fuel, th, sh, q);
         free(th); free(sh); free(q);
         if (res->oom) break;
+        int parallel = 0;   /* may this launch run in parallel with another one? */
+        for (uint32_t k = 0; k < n_launches; k++)
+            if (k != li && !hb[(size_t)k * n_launches + li] && !hb[(size_t)li * n_launches + k]) parallel = 1;
+        if (parallel) {
+            sums[li] = access_summary(res, n_words, nt);
+            if (!sums[li]) { res->oom = 1; break; }
+            for (uint32_t k = 0; k < li && !res->oom; k++)
+                if (sums[k] && !hb[(size_t)k * n_launches + li])
+                    cross_launch_races(res, k, sums[k], li, sums[li], n_words);
+            if (res->oom) break;
+        }
         check_launch(res, li, nt);
         if (res->oom) break;
         if (deadlocked) break;
         res->launches_completed = li + 1;
     }
+    if (sums)
+        for (uint32_t k = 0; k < n_launches; k++) free(sums[k]);
+    free(sums);
+    free(hb);
     if (res->oom) {
         free(res->recs); free(res->kept); free(res->races); free(res->faults); free(res);
         return 3;
@@ -500,6 +589,13 @@ int ora_run_job(uint32_t n_launches, const uint64_t *const *progs, const uint32_
     res->n_faults = m;
     *out = res;
     return 0;
+}
+
+int ora_run_job(uint32_t n_launches, const uint64_t *const *progs, const uint32_t *prog_lens,
+                const ora_launch *launches, int32_t *mem, uint64_t n_words, uint32_t fuel,
+                int keep_records, ora_result **out) {
+    return ora_run_job_streams(n_launches, progs, prog_lens, launches, mem, n_words, fuel, keep_records,
+                               NULL, NULL, 0, out);
 }
 
 uint64_t ora_records(const ora_result *r) { return r->n_records; }

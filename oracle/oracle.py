@@ -56,6 +56,10 @@ def _load():
                                     C.POINTER(_Launch), C.c_void_p, C.c_uint64, C.c_uint32, C.c_int,
                                     C.POINTER(C.c_void_p)]
         lib.ora_run_job.restype = C.c_int
+        lib.ora_run_job_streams.argtypes = [C.c_uint32, C.POINTER(C.c_void_p), C.POINTER(C.c_uint32),
+                                            C.POINTER(_Launch), C.c_void_p, C.c_uint64, C.c_uint32, C.c_int,
+                                            C.c_void_p, C.c_void_p, C.c_uint32, C.POINTER(C.c_void_p)]
+        lib.ora_run_job_streams.restype = C.c_int
         lib.ora_records.argtypes = [C.c_void_p]
         lib.ora_records.restype = C.c_uint64
         lib.ora_instructions.argtypes = [C.c_void_p]
@@ -104,7 +108,11 @@ def validate(words) -> bool:
 
 def run_job(job, fuel: int = DEFAULT_FUEL, keep_records: bool = False,
             memory: Optional[np.ndarray] = None) -> OracleResult:
-    """Run every launch of ``job`` on a copy of its memory (or on ``memory``)."""
+    """Run every launch of ``job`` on a copy of its memory (or on ``memory``).
+
+    ``job.streams`` (one stream id per launch) and ``job.deps`` ((before,
+    after) launch pairs), when the job has them, describe which launches may
+    run in parallel; races between such launches are reported with scope 2."""
     lib = _load()
     progs = [np.ascontiguousarray(np.asarray(L.program, dtype=np.uint64)) for L in job.launches]
     n = len(progs)
@@ -118,8 +126,16 @@ def run_job(job, fuel: int = DEFAULT_FUEL, keep_records: bool = False,
         params = list(L.params) + [0] * (8 - len(L.params))
         ls[i].params[:] = [int(np.int32(p)) for p in params]
     mem = np.array(job.memory if memory is None else memory, dtype=np.int32, copy=True)
+    streams = getattr(job, "streams", None)
+    deps = getattr(job, "deps", None) or []
+    st = None if streams is None else np.ascontiguousarray(np.asarray(streams, dtype=np.uint32))
+    if st is not None and len(st) != n:
+        raise ValueError("one stream per launch")
+    dp = np.ascontiguousarray(np.asarray(deps, dtype=np.uint32).reshape(-1, 2))
     out = C.c_void_p()
-    rc = lib.ora_run_job(n, ptrs, lens, ls, mem.ctypes.data, len(mem), fuel, int(keep_records), C.byref(out))
+    rc = lib.ora_run_job_streams(n, ptrs, lens, ls, mem.ctypes.data, len(mem), fuel, int(keep_records),
+                                 None if st is None else st.ctypes.data, dp.ctypes.data if len(dp) else None,
+                                 len(dp), C.byref(out))
     if rc != 0:
         raise ValueError(f"oracle rejected the job (code {rc})")
     try:

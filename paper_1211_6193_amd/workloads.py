@@ -53,6 +53,8 @@ class Job:
     launches: List[LaunchSpec]
     memory: np.ndarray                  # int32 initial global memory
     meta: Dict = field(default_factory=dict)
+    streams: Optional[List[int]] = None             # stream of each launch (None: one stream)
+    deps: List[Tuple[int, int]] = field(default_factory=list)   # (before, after): after waits for before
 
 
 def _prog(a: Asm) -> np.ndarray:
