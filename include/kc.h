@@ -169,14 +169,34 @@ typedef struct {
 kc_status kc_launch(kc_ctx *ctx, const kc_launch_desc *desc, int32_t *dev_mem, uint64_t n_words,
                     void *stream, kc_report **out);
 
-/* A job: launches run in order on one memory, as one stream (Section 2).
- * The report's launch fields are indices into `launches`. */
+/* An event dependency between two launches of a job (Section 3 "Streams
+ * and events"): launch `after` starts only once launch `before` has finished,
+ * as when an event recorded in before's stream right behind it is waited on
+ * (cudaStreamWaitEvent) in after's stream ahead of it, or the host
+ * synchronises in between.  before < after. */
+typedef struct {
+    uint32_t before, after;
+} kc_dep;
+
+/* A job: launches on one memory (Section 2).  By default they form one
+ * stream and run in order.  With `streams` (one stream id per launch) and
+ * `deps`, launch i happens before launch j when a chain of same-stream order
+ * (an earlier launch of the same stream) and dependencies leads from i to j;
+ * two launches ordered neither way may run in parallel, and every global word
+ * one of them writes and the other touches is reported as a race between
+ * them (scope 2).  The launches still execute in submission order, which
+ * respects every chain, so the final memory is that order's.  The report's
+ * launch fields are indices into `launches`.  `streams` and `deps` are read
+ * during the call (kc_batch_submit copies them). */
 typedef struct {
     const kc_launch_desc *launches;
     uint32_t n_launches;
     int32_t *dev_mem;
     uint64_t n_words;
     uint64_t tag;               /* returned by kc_report_tag */
+    const uint32_t *streams;    /* n_launches entries, or NULL: one stream */
+    const kc_dep *deps;         /* n_deps entries (before < after < n_launches), or NULL */
+    uint32_t n_deps;
 } kc_job;
 
 /* Submit jobs as one batch; returns at once.  All jobs of the batch execute
@@ -195,12 +215,18 @@ kc_status kc_poll(kc_ctx *ctx, uint64_t ticket, int wait, kc_report **out, uint3
 
 /* ---- reports -------------------------------------------------------------------- */
 
+/* Scope 2 (launches that may run in parallel, see kc_job): `launch` is the
+ * later launch j, `block` the earlier launch i, epoch 0xFFFFFFFF, `addr` the
+ * global word; w_tid is the smallest global thread id (block*threads+tid) of
+ * j whose access to the word conflicts with an access of i, o_tid the same
+ * for i (every access conflicts when the other launch writes the word, only
+ * writes otherwise). */
 typedef struct {
     uint32_t launch;
     uint32_t space;     /* 0 shared, 1 global */
-    uint32_t scope;     /* 0 intra-block, 1 cross-block */
-    uint32_t block;     /* linear block id (of w_tid when cross-block) */
-    uint32_t epoch;     /* barrier epoch; 0xFFFFFFFF when cross-block */
+    uint32_t scope;     /* 0 intra-block, 1 cross-block, 2 cross-launch */
+    uint32_t block;     /* linear block id (of w_tid when cross-block); the other launch when cross-launch */
+    uint32_t epoch;     /* barrier epoch; 0xFFFFFFFF when cross-block or cross-launch */
     uint32_t addr;      /* word index: shared offset or global word */
     uint32_t w_tid;     /* smallest writer; linear tid, or block*threads+tid when cross-block */
     uint32_t o_tid;     /* smallest other conflicting thread, same numbering */

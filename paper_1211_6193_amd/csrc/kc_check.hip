@@ -597,7 +597,63 @@ __global__ void __launch_bounds__(WG) k_gather(GatherArgs a) {
     }
 }
 
+// Access summary of a launch (streams and events): per global word, the
+// smallest global thread id that touched it and the smallest that wrote it,
+// from the records of a log.  Every record stands for an access of its
+// thread of the kind its low bit gives (representatives and unreduced
+// tuples alike), so the minima over records are the minima over accesses.
+__global__ void __launch_bounds__(WG) k_summary(SummaryArgs a) {
+    const KeyPlan &k = a.kp;
+    const uint64_t n = a.n_dev ? min((uint64_t)*a.n_dev, a.n) : a.n;
+    for (uint64_t i = (uint64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (uint64_t)gridDim.x * WG) {
+        const uint64_t r = a.log[i];
+        if (rec_field(r, k.s_sp, 1) != 1u) continue;
+        const uint32_t unit = rec_field(r, k.s_unit, k.ub);
+        uint32_t *sum = a.sums[unit];
+        if (!sum || (a.skip_units && a.skip_units[unit])) continue;
+        const DevUnit &u = a.units[unit];
+        const uint32_t block = rec_field(r, k.s_blk, k.bb);
+        if (a.skip_blocks && a.skip_blocks[u.block_base + block]) continue;
+        const uint32_t addr = rec_field(r, k.s_addr, k.ab);
+        const uint32_t g = block * u.nt + rec_field(r, k.s_tid, k.tb);
+        atomicMin(&sum[addr], g);
+        if (r & 1ull) atomicMin(&sum[u.n_words + addr], g);
+    }
+}
+
+// Races between an earlier launch (summary si) and a later one (sj) of a job
+// that may run in parallel: every word one writes and the other touches.
+__global__ void __launch_bounds__(WG) k_cross_launch(const uint32_t *__restrict__ si, const uint32_t *__restrict__ sj,
+                                                     uint64_t n_words, uint32_t tag, uint32_t earlier,
+                                                     DevRace *__restrict__ out, uint32_t cap,
+                                                     uint32_t *__restrict__ count) {
+    for (uint64_t x = (uint64_t)blockIdx.x * WG + threadIdx.x; x < n_words; x += (uint64_t)gridDim.x * WG) {
+        const uint32_t ai = si[x], wi = si[n_words + x], aj = sj[x], wj = sj[n_words + x];
+        if (!((wi != NONE && aj != NONE) || (wj != NONE && ai != NONE))) continue;
+        DevRace r;
+        r.unit = tag; r.space = 1; r.scope = 2; r.block = earlier; r.epoch = NONE; r.addr = (uint32_t)x;
+        r.w = wi != NONE ? aj : wj;     // the later launch's smallest conflicting thread
+        r.o = wj != NONE ? ai : wi;     // the earlier launch's
+        const uint32_t at = atomicAdd(count, 1u);
+        if (at < cap) out[at] = r;
+    }
+}
+
 }  // namespace
+
+hipError_t launch_summary(const SummaryArgs &a, hipStream_t s) {
+    if (a.n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_summary, dim3((uint32_t)std::min<uint64_t>(blocks_for(a.n), 8192)), dim3(WG), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_cross_launch(const uint32_t *si, const uint32_t *sj, uint64_t n_words, uint32_t tag,
+                               uint32_t earlier, DevRace *out, uint32_t cap, uint32_t *count, hipStream_t s) {
+    if (n_words == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cross_launch, dim3((uint32_t)std::min<uint64_t>(blocks_for(n_words), 8192)), dim3(WG), 0, s,
+                       si, sj, n_words, tag, earlier, out, cap, count);
+    return hipGetLastError();
+}
 
 size_t check_long_cap(uint64_t n) { return (size_t)(2 * (n / SEG_LIMIT) + 2); }
 

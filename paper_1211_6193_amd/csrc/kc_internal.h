@@ -214,6 +214,28 @@ hipError_t launch_log_table(const ReplayTableArgs &a, hipStream_t s);
 // The same check through the direct tables (rs, n_rs, kp, units, snap_base,
 // downer, dflags; `words` entries, zeroed here).
 hipError_t launch_log_direct(const ReplayTableArgs &a, uint64_t words, hipStream_t s);
+// Access summaries of launches that may run in parallel with another launch
+// of their job: for each unit u with sums[u] set, sums[u][x] becomes the
+// smallest global thread id among the records of global word x and
+// sums[u][n_words + x] the smallest among its writes (atomicMin: the arrays
+// start at 0xFFFFFFFF).  Records of blocks flagged in skip_blocks (global
+// block index) or of units flagged in skip_units are left out.
+struct SummaryArgs {
+    const uint64_t *log;
+    uint64_t n;
+    const unsigned long long *n_dev;    // when set, the record count is read here (at most n)
+    KeyPlan kp;
+    const DevUnit *units;
+    uint32_t *const *sums;
+    const uint32_t *skip_blocks;
+    const uint32_t *skip_units;
+};
+hipError_t launch_summary(const SummaryArgs &a, hipStream_t s);
+// Races between launch `earlier` (summary si) and a later launch (sj) over
+// n_words words, appended to out (cap entries; *count counts them all) with
+// unit = tag.
+hipError_t launch_cross_launch(const uint32_t *si, const uint32_t *sj, uint64_t n_words, uint32_t tag,
+                               uint32_t earlier, DevRace *out, uint32_t cap, uint32_t *count, hipStream_t s);
 hipError_t launch_copy_units(const DevUnit *units, uint32_t n_units, uint32_t max_words, bool to_snapshot,
                              const uint32_t *unit_mask, hipStream_t s);
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);

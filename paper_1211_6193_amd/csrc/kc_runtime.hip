@@ -31,6 +31,7 @@
 #include <numeric>
 #include <string>
 #include <thread>
+#include <tuple>
 #include <unordered_map>
 #include <vector>
 
@@ -238,9 +239,15 @@ struct kc_ctx {
     }
 };
 
+// Launches per job when streams or dependencies are given (the launch order
+// is kept as one bit per pair).
+constexpr uint32_t kMaxStreamLaunches = 4096;
+
 struct Batch {
     std::vector<kc_job> jobs;
     std::vector<std::vector<kc_launch_desc>> descs;
+    std::vector<std::vector<uint32_t>> streams;
+    std::vector<std::vector<kc_dep>> deps;
     hipStream_t stream = nullptr;
     std::thread worker;
     std::mutex mu;
@@ -418,6 +425,14 @@ struct Stage {
         const uint32_t ob = bits_for((uint64_t)total_blocks + 1);
         return (kp.total - kp.s_addr) + ob + 2 <= 63 ? ob : 0u;
     }
+    // Where the canonical accesses of the stage are once run() returns: the
+    // free-run log less the blocks flagged in ws.blk_flags (replayed) or the
+    // units flagged in ws.mask (replayed whole), plus the replay's records.
+    const uint64_t *fin_log = nullptr;
+    uint64_t fin_n = 0;
+    const uint64_t *rep_log = nullptr;
+    uint64_t rep_n = 0;
+    bool skip_flagged = false, skip_masked = false;
     bool log_sorted = false;        // the free-run log was sorted for its check
     uint32_t ftable_bits = 0;       // else: log2 slots of its location table (ws.ftable),
     bool direct_tables = false;     // or its direct word tables (ws.downer, ws.dflags)
@@ -858,6 +873,8 @@ struct Stage {
         for (uint32_t i = 0; i < n; i++)
             for (uint32_t b = 0; b < hu[i].nb; b++) urecs[i] += blk_recs[hu[i].block_base + b];
 
+        fin_log = sorted;
+        fin_n = check ? nrec : 0;
         if (!races.empty()) replay(races, edges, sorted, nrec, ufaults, uraces, urecs, tm);
 
         for (uint32_t i = 0; i < n; i++) {
@@ -1089,10 +1106,15 @@ struct Stage {
         if (sorted_check && !log_sorted) {      // the exactness scan needs the free-run log sorted
             sorted = sort_check(ws.log, ws.alt, nrec);
             log_sorted = true;
+            fin_log = sorted;
         }
+        rep_log = ws.rlog.as<uint64_t>();
+        rep_n = rc.log_count;
+        skip_flagged = true;
         if (sorted_check) {
             used_epoch_bits = std::max(used_epoch_bits, bits_for((uint64_t)rc.max_epoch + 2));
             uint64_t *rs = sort_check(ws.rlog, ws.ralt, rc.log_count);
+            rep_log = rs;
             tm.mark(8);
             // the exactness check is queued first; its flag returns with the
             // conflict check's results
@@ -1174,6 +1196,10 @@ struct Stage {
         const std::vector<DevRace> &fl = fo.lraces;
         used_epoch_bits = std::max(used_epoch_bits, bits_for((uint64_t)fc.max_epoch + 2));
         uint64_t *rs = sort_check(ws.rlog, ws.ralt, fc.log_count);
+        rep_log = rs;
+        rep_n = fc.log_count;
+        skip_flagged = false;
+        skip_masked = true;
         std::vector<DevRace> nr;
         std::vector<DevEdge> ne;
         run_check(rs, fc.log_count, ws.rflags, nr, ne);
@@ -1190,6 +1216,28 @@ struct Stage {
         tm.mark(6);
         ctx->stat_add("replay_ms", tm.ms(5, 6));
     }
+
+    // Queue the access summaries of the units with sums[u] set (device array
+    // of per-unit pointers, see launch_summary) from the stage's canonical
+    // accesses.
+    void summarize(uint32_t *const *sums) {
+        SummaryArgs a{};
+        a.kp = kp;
+        a.units = ws.units.as<DevUnit>();
+        a.sums = sums;
+        a.log = fin_log;
+        a.n = fin_n;
+        a.skip_blocks = skip_flagged ? ws.blk_flags.as<uint32_t>() : nullptr;
+        a.skip_units = skip_masked ? ws.mask.as<uint32_t>() : nullptr;
+        HIPCHK(launch_summary(a, s));
+        if (rep_log && rep_n) {
+            a.log = rep_log;
+            a.n = rep_n;
+            a.skip_blocks = nullptr;
+            a.skip_units = nullptr;
+            HIPCHK(launch_summary(a, s));
+        }
+    }
 };
 
 kc_status fail(kc_ctx *ctx, const KcError &e) {
@@ -1200,12 +1248,127 @@ kc_status fail(kc_ctx *ctx, const KcError &e) {
     return e.st;
 }
 
+// Which launches of a job may run in parallel (Section 3 "Streams and
+// events").  before[j] holds bit i when launch i happens before launch j: the
+// closure of same-stream order and dependencies, built in launch order since
+// every edge points forward.
+struct LaunchOrder {
+    uint32_t n = 0, words = 0;
+    std::vector<uint64_t> before;       // n rows of `words` words
+    std::vector<char> parallel;         // launch may run in parallel with another one
+    bool any = false;
+    bool ordered(uint32_t i, uint32_t j) const { return (before[(size_t)j * words + i / 64] >> (i % 64)) & 1u; }
+
+    explicit LaunchOrder(const kc_job &job) {
+        if (!job.streams && !job.n_deps) return;
+        n = job.n_launches;
+        words = (n + 63) / 64;
+        before.assign((size_t)n * words, 0);
+        std::vector<std::vector<uint32_t>> preds(n);
+        std::unordered_map<uint32_t, uint32_t> last;    // stream -> its latest launch
+        for (uint32_t j = 0; j < n; j++) {
+            const uint32_t sid = job.streams ? job.streams[j] : 0u;
+            auto it = last.find(sid);
+            if (it != last.end()) preds[j].push_back(it->second);
+            last[sid] = j;
+        }
+        for (uint32_t d = 0; d < job.n_deps; d++) preds[job.deps[d].after].push_back(job.deps[d].before);
+        for (uint32_t j = 0; j < n; j++) {
+            uint64_t *row = &before[(size_t)j * words];
+            for (uint32_t p : preds[j]) {
+                const uint64_t *prow = &before[(size_t)p * words];
+                for (uint32_t w = 0; w < words; w++) row[w] |= prow[w];
+                row[p / 64] |= 1ull << (p % 64);
+            }
+        }
+        parallel.assign(n, 0);
+        for (uint32_t j = 0; j < n; j++)
+            for (uint32_t i = 0; i < j; i++)
+                if (!ordered(i, j)) parallel[i] = parallel[j] = 1, any = true;
+    }
+};
+
+// Races between launches that may run in parallel, for the units of a stage
+// (launch index li): the access summary of each unit whose launch may run in
+// parallel with another, then one scan against each earlier such launch.
+// Summaries stay in `sums` (per job and launch) for the later stages.
+void cross_launch_check(kc_ctx *ctx, Workspace &ws, hipStream_t s, Stage &st, uint32_t li, const kc_job *jobs,
+                        const std::vector<uint32_t> &who, const std::vector<LaunchOrder> &order,
+                        std::vector<std::vector<DBuf>> &sums, std::vector<kc_report *> &reports) {
+    std::vector<uint32_t *> ptr(who.size(), nullptr);
+    bool any = false;
+    size_t held = 0;
+    for (auto &v : sums)
+        for (auto &b : v) held += b.bytes;
+    for (size_t i = 0; i < who.size(); i++) {
+        const uint32_t j = who[i];
+        if (!order[j].any || !order[j].parallel[li]) continue;
+        if (sums[j].empty()) sums[j].resize(jobs[j].n_launches);
+        DBuf &b = sums[j][li];
+        b.reserve(std::max<uint64_t>(jobs[j].n_words, 1) * 8);
+        held += b.bytes;
+        if (ctx->budget && ws.device_bytes() + held > ctx->budget)
+            throw KcError{KC_E_BUDGET, "launch summaries exceed the HBM budget"};
+        HIPCHK(hipMemsetAsync(b.p, 0xFF, jobs[j].n_words * 8, s));
+        ptr[i] = b.as<uint32_t>();
+        any = true;
+    }
+    if (!any) return;
+    struct Scratch {
+        DBuf ptrs, list, count;
+        ~Scratch() {
+            ptrs.release();
+            list.release();
+            count.release();
+        }
+    } tmp;
+    DBuf &dptr = tmp.ptrs, &list = tmp.list, &count = tmp.count;
+    dptr.reserve(ptr.size() * sizeof(uint32_t *));
+    HIPCHK(hipMemcpyAsync(dptr.p, ptr.data(), ptr.size() * sizeof(uint32_t *), hipMemcpyHostToDevice, s));
+    st.summarize(dptr.as<uint32_t *>());
+    uint32_t cap = 4096;
+    count.reserve(4);
+    std::vector<DevRace> got;
+    for (;;) {
+        list.reserve((size_t)cap * sizeof(DevRace));
+        HIPCHK(launch_zero(count.p, 4, s));
+        for (size_t i = 0; i < who.size(); i++) {
+            if (!ptr[i]) continue;
+            const uint32_t j = who[i];
+            for (uint32_t k = 0; k < li; k++)
+                if (order[j].parallel[k] && !order[j].ordered(k, li) && !sums[j].empty() && sums[j][k].p)
+                    HIPCHK(launch_cross_launch(sums[j][k].as<uint32_t>(), ptr[i], jobs[j].n_words, j, k,
+                                               list.as<DevRace>(), cap, count.as<uint32_t>(), s));
+        }
+        uint32_t n = 0;
+        HIPCHK(hipMemcpyAsync(&n, count.p, 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (n > cap) {
+            cap = n;
+            continue;
+        }
+        got.resize(n);
+        if (n) HIPCHK(hipMemcpy(got.data(), list.p, (size_t)n * sizeof(DevRace), hipMemcpyDeviceToHost));
+        break;
+    }
+    std::sort(got.begin(), got.end(), [](const DevRace &a, const DevRace &b) {
+        return std::tie(a.unit, a.block, a.addr) < std::tie(b.unit, b.block, b.addr);
+    });
+    for (auto &r : got) reports[r.unit]->races.push_back(kc_race{li, 1, 2, r.block, r.epoch, r.addr, r.w, r.o});
+    ctx->stat_add("cross_launch_races", (double)got.size());
+}
+
 // Run every launch of `jobs` in order, stage by stage (launch index j of all
 // jobs still running), and build one report per job.
 void run_jobs(kc_ctx *ctx, const kc_job *jobs, uint32_t n_jobs, hipStream_t s, std::vector<kc_report *> &reports) {
     HIPCHK(hipSetDevice(ctx->device));
     auto wsp = ctx->acquire();
     Workspace &ws = *wsp;
+    std::vector<std::vector<DBuf>> sums(n_jobs);
+    auto free_sums = [&]() {
+        for (auto &v : sums)
+            for (auto &b : v) b.release();
+    };
     try {
         ws.setup();
         reports.assign(n_jobs, nullptr);
@@ -1213,6 +1376,14 @@ void run_jobs(kc_ctx *ctx, const kc_job *jobs, uint32_t n_jobs, hipStream_t s, s
             reports[j] = new kc_report();
             reports[j]->tag = jobs[j].tag;
         }
+        std::vector<LaunchOrder> order;
+        order.reserve(n_jobs);
+        bool streams = false;
+        for (uint32_t j = 0; j < n_jobs; j++) {
+            order.emplace_back(jobs[j]);
+            streams |= order.back().any;
+        }
+        streams &= ctx->opt.check != 0;
         std::vector<char> alive(n_jobs, 1);
         uint32_t max_l = 0;
         for (uint32_t j = 0; j < n_jobs; j++) max_l = std::max(max_l, jobs[j].n_launches);
@@ -1239,13 +1410,16 @@ void run_jobs(kc_ctx *ctx, const kc_job *jobs, uint32_t n_jobs, hipStream_t s, s
                 if (o.deadlocked) alive[who[i]] = 0;
                 else r->launches_completed = li + 1;
             }
+            if (streams) cross_launch_check(ctx, ws, s, st, li, jobs, who, order, sums, reports);
         }
     } catch (...) {
+        free_sums();
         for (auto *r : reports) delete r;
         reports.clear();
         ctx->release(std::move(wsp));
         throw;
     }
+    free_sums();
     ctx->release(std::move(wsp));
 }
 
@@ -1454,13 +1628,40 @@ kc_status kc_batch_submit(kc_ctx *ctx, const kc_job *jobs, uint32_t n_jobs, void
                 return KC_E_INVAL;
             }
         }
+        if (jobs[j].n_deps && !jobs[j].deps) {
+            ctx->err = "job " + std::to_string(j) + ": n_deps without a dependency array";
+            return KC_E_INVAL;
+        }
+        if ((jobs[j].streams || jobs[j].n_deps) && jobs[j].n_launches > kMaxStreamLaunches) {
+            ctx->err = "job " + std::to_string(j) + ": more than " + std::to_string(kMaxStreamLaunches) +
+                       " launches with streams";
+            return KC_E_INVAL;
+        }
+        for (uint32_t d = 0; d < jobs[j].n_deps; d++) {
+            const kc_dep &e = jobs[j].deps[d];
+            if (e.before >= e.after || e.after >= jobs[j].n_launches) {
+                ctx->err = "job " + std::to_string(j) + " dependency " + std::to_string(d) +
+                           ": needs before < after < n_launches";
+                return KC_E_INVAL;
+            }
+        }
     }
     auto b = std::make_shared<Batch>();
     b->jobs.assign(jobs, jobs + n_jobs);
     b->descs.resize(n_jobs);
+    b->streams.resize(n_jobs);
+    b->deps.resize(n_jobs);
     for (uint32_t j = 0; j < n_jobs; j++) {
         b->descs[j].assign(jobs[j].launches, jobs[j].launches + jobs[j].n_launches);
         b->jobs[j].launches = b->descs[j].data();
+        if (jobs[j].streams) {
+            b->streams[j].assign(jobs[j].streams, jobs[j].streams + jobs[j].n_launches);
+            b->jobs[j].streams = b->streams[j].data();
+        }
+        if (jobs[j].n_deps) {
+            b->deps[j].assign(jobs[j].deps, jobs[j].deps + jobs[j].n_deps);
+            b->jobs[j].deps = b->deps[j].data();
+        }
     }
     b->stream = (hipStream_t)stream;
     uint64_t t;

@@ -48,9 +48,14 @@ class LaunchDesc(C.Structure):
                 ("params", C.c_int32 * 8), ("n_params", C.c_uint32)]
 
 
+class Dep(C.Structure):
+    _fields_ = [("before", C.c_uint32), ("after", C.c_uint32)]
+
+
 class JobDesc(C.Structure):
     _fields_ = [("launches", C.POINTER(LaunchDesc)), ("n_launches", C.c_uint32), ("dev_mem", C.c_void_p),
-                ("n_words", C.c_uint64), ("tag", C.c_uint64)]
+                ("n_words", C.c_uint64), ("tag", C.c_uint64), ("streams", C.POINTER(C.c_uint32)),
+                ("deps", C.POINTER(Dep)), ("n_deps", C.c_uint32)]
 
 
 _lib = None
@@ -296,7 +301,10 @@ class Batch:
         n = len(jobs)
         jd = (JobDesc * max(n, 1))()
         keep = []
-        for i, (launches, mem, tag) in enumerate(jobs):
+        for i, item in enumerate(jobs):
+            launches, mem, tag = item[:3]
+            streams = item[3] if len(item) > 3 else None
+            deps = item[4] if len(item) > 4 else ()
             arr = (LaunchDesc * max(len(launches), 1))()
             for j, (p, g, b, sh, ps) in enumerate(launches):
                 arr[j] = _desc(p, g, b, sh, ps)
@@ -306,11 +314,24 @@ class Batch:
             jd[i].dev_mem = mem.data_ptr()
             jd[i].n_words = mem.numel()
             jd[i].tag = tag
-        return Prepared(jd, keep, n, [m for _, m, _ in jobs])
+            if streams is not None:
+                if len(streams) != len(launches):
+                    raise ValueError("one stream per launch")
+                sarr = (C.c_uint32 * max(len(streams), 1))(*[int(x) for x in streams])
+                keep.append(sarr)
+                jd[i].streams = C.cast(sarr, C.POINTER(C.c_uint32))
+            if len(deps):
+                darr = (Dep * len(deps))(*[Dep(int(a), int(b)) for a, b in deps])
+                keep.append(darr)
+                jd[i].deps = C.cast(darr, C.POINTER(Dep))
+                jd[i].n_deps = len(deps)
+        return Prepared(jd, keep, n, [item[1] for item in jobs])
 
     def submit(self, jobs, stream=None) -> int:
-        """jobs: a Prepared batch or a list of (launches, mem_tensor, tag) with
-        launches = [(prog, grid, block, shmem, params), ...]."""
+        """jobs: a Prepared batch or a list of (launches, mem_tensor, tag) or
+        (launches, mem_tensor, tag, streams, deps) with launches =
+        [(prog, grid, block, shmem, params), ...], streams one stream id per
+        launch (or None) and deps (before, after) launch pairs."""
         prep = jobs if isinstance(jobs, Prepared) else self.prepare(jobs)
         t = C.c_uint64()
         self.ctx._check(self.ctx.lib.kc_batch_submit(self.ctx.h, prep.jd, prep.n, _stream_handle(stream),
@@ -336,13 +357,17 @@ def job_launches(ctx: Context, job) -> list:
     return [(ctx.program(L.program), L.grid, L.block, L.shmem_bytes, L.params) for L in job.launches]
 
 
+def job_item(ctx: Context, job, mem, tag):
+    return (job_launches(ctx, job), mem, tag, getattr(job, "streams", None), getattr(job, "deps", None) or ())
+
+
 def run_job(ctx: Context, job, mem=None, stream=None):
     """Run all launches of ``job`` as one job; returns (Report, final memory tensor)."""
     import torch
     if mem is None:
         mem = torch.from_numpy(np.ascontiguousarray(job.memory, dtype=np.int32)).to(f"cuda:{ctx.device}")
     b = Batch(ctx)
-    t = b.submit([(job_launches(ctx, job), mem, 0)], stream=stream)
+    t = b.submit([job_item(ctx, job, mem, 0)], stream=stream)
     return b.poll(t, wait=True)[0], mem
 
 
@@ -353,5 +378,5 @@ def run_jobs(ctx: Context, jobs, mems=None, stream=None):
         mems = [torch.from_numpy(np.ascontiguousarray(j.memory, dtype=np.int32)).to(f"cuda:{ctx.device}")
                 for j in jobs]
     b = Batch(ctx)
-    t = b.submit([(job_launches(ctx, j), m, i) for i, (j, m) in enumerate(zip(jobs, mems))], stream=stream)
+    t = b.submit([job_item(ctx, j, m, i) for i, (j, m) in enumerate(zip(jobs, mems))], stream=stream)
     return b.poll(t, wait=True), mems

@@ -190,7 +190,7 @@ class Server:
                 now = time.perf_counter() - t0
                 for r in batch:
                     r.admitted = now
-                ticket = self.batch.submit([(kc.job_launches(self.ctx, r.job), m, r.rid)
+                ticket = self.batch.submit([kc.job_item(self.ctx, r.job, m, r.rid)
                                             for r, m in zip(batch, mems)], stream=st)
                 inflight.append((ticket, si, batch, mems))
                 busy_batches += 1
