@@ -54,6 +54,16 @@
  *     any thread's is (k = 2), else 0.  A thread's predicate is its register
  *     a while it waits (registers do not change while waiting); a thread
  *     waiting at a plain barrier counts as predicate 0.
+ *   - Memory objects (Section 3 feature list: device memory allocation; the
+ *     tool's checks for out-of-bounds and illegal device or host memory
+ *     access): a job may list its device allocations as word ranges of its
+ *     memory.  A global load or store that lands on a word of the memory
+ *     outside every allocation (host memory or nothing at all, from the
+ *     device's side) is an illegal access.  It still takes effect (the memory
+ *     is one array); each block that made such accesses to a word gets one
+ *     finding ALLOC {block, epoch 0xFFFFFFFF, a = 2 + (1 if the block stored
+ *     to it), b = the smallest tid of the block that accessed it, c = the
+ *     word, d = the smallest tid that stored to it or 0xFFFFFFFF}.
  *   - Every in-bounds load and store appends an access record
  *     {space, word address, block, barrier epoch, tid, read/write}, the
  *     information the race tuples of Section 3.1 keep per location.
@@ -90,7 +100,7 @@ enum {
 enum { ST_RUN = 0, ST_WAIT = 1, ST_EXIT = 2 };
 enum { SP_SHARED = 0, SP_GLOBAL = 1 };
 enum { K_READ = 0, K_WRITE = 1 };
-enum { F_DEADLOCK = 1, F_DIVERGENCE = 2, F_OOB = 3, F_FUEL = 4, F_ARITH = 5 };
+enum { F_DEADLOCK = 1, F_DIVERGENCE = 2, F_OOB = 3, F_FUEL = 4, F_ARITH = 5, F_ALLOC = 6 };
 
 typedef struct {
     uint32_t grid[3], block[3];
@@ -521,16 +531,50 @@ static void cross_launch_races(ora_result *res, uint32_t i, const uint32_t *si, 
     }
 }
 
+/* ALLOC findings of the current launch's records: per block, the words it
+ * accessed outside every allocation (allocated[x] = 0). */
+static int cmp_block_addr(const void *pa, const void *pb) {
+    const ora_record *x = pa, *y = pb;
+    if (x->block != y->block) return x->block < y->block ? -1 : 1;
+    if (x->addr != y->addr) return x->addr < y->addr ? -1 : 1;
+    return x->tid < y->tid ? -1 : x->tid > y->tid;
+}
+
+static void illegal_accesses(ora_result *res, uint32_t li, const uint8_t *allocated) {
+    uint64_t n = 0;
+    ora_record *bad = malloc((res->n_recs + 1) * sizeof(ora_record));
+    if (!bad) { res->oom = 1; return; }
+    for (uint64_t i = 0; i < res->n_recs; i++)
+        if (res->recs[i].space == SP_GLOBAL && !allocated[res->recs[i].addr]) bad[n++] = res->recs[i];
+    qsort(bad, n, sizeof(ora_record), cmp_block_addr);
+    for (uint64_t i = 0; i < n;) {
+        uint64_t j = i;
+        uint32_t wmin = 0xFFFFFFFFu;
+        while (j < n && bad[j].block == bad[i].block && bad[j].addr == bad[i].addr) {
+            if (bad[j].kind == K_WRITE && bad[j].tid < wmin) wmin = bad[j].tid;
+            j++;
+        }
+        /* tids ascend in the group: bad[i] holds the smallest */
+        add_fault(res, li, F_ALLOC, bad[i].block, 0xFFFFFFFFu, 2u + (wmin != 0xFFFFFFFFu), bad[i].tid,
+                  bad[i].addr, wmin);
+        i = j;
+    }
+    free(bad);
+}
+
 /* Run a job.  progs[i]/prog_lens[i] is launch i's program; mem is updated in
  * place.  streams (n_launches entries) and deps (n_deps pairs before, after
- * with before < after) may be NULL / 0: one stream. */
-int ora_run_job_streams(uint32_t n_launches, const uint64_t *const *progs, const uint32_t *prog_lens,
-                        const ora_launch *launches, int32_t *mem, uint64_t n_words, uint32_t fuel,
-                        int keep_records, const uint32_t *streams, const uint32_t *deps, uint32_t n_deps,
-                        ora_result **out) {
+ * with before < after) may be NULL / 0: one stream.  allocs (n_allocs pairs
+ * base, words), when not NULL, lists the device allocations. */
+int ora_run_job_ex(uint32_t n_launches, const uint64_t *const *progs, const uint32_t *prog_lens,
+                   const ora_launch *launches, int32_t *mem, uint64_t n_words, uint32_t fuel,
+                   int keep_records, const uint32_t *streams, const uint32_t *deps, uint32_t n_deps,
+                   const uint64_t *allocs, uint32_t n_allocs, ora_result **out) {
     *out = NULL;
     for (uint32_t d = 0; d < n_deps; d++)
         if (deps[2 * d] >= deps[2 * d + 1] || deps[2 * d + 1] >= n_launches) return 1;
+    for (uint32_t a = 0; allocs && a < n_allocs; a++)
+        if (allocs[2 * a] > n_words || allocs[2 * a + 1] > n_words - allocs[2 * a]) return 1;
     for (uint32_t i = 0; i < n_launches; i++) {
         if (ora_validate(progs[i], prog_lens[i])) return 2;
         const ora_launch *L = &launches[i];
@@ -543,7 +587,13 @@ int ora_run_job_streams(uint32_t n_launches, const uint64_t *const *progs, const
     res->keep_records = keep_records;
     uint8_t *hb = happens_before(n_launches, streams, deps, n_deps);
     uint32_t **sums = calloc((size_t)n_launches + 1, sizeof(uint32_t *));
-    if (!hb || !sums) res->oom = 1;
+    uint8_t *allocated = NULL;
+    if (allocs) {
+        allocated = calloc(n_words + 1, 1);
+        for (uint32_t a = 0; allocated && a < n_allocs; a++)
+            memset(allocated + allocs[2 * a], 1, allocs[2 * a + 1]);
+    }
+    if (!hb || !sums || (allocs && !allocated)) res->oom = 1;
     for (uint32_t li = 0; li < n_launches && !res->oom; li++) {
         const ora_launch *L = &launches[li];
         uint32_t nt = L->block[0] * L->block[1] * L->block[2];
@@ -568,6 +618,8 @@ int ora_run_job_streams(uint32_t n_launches, const uint64_t *const *progs, const
                     cross_launch_races(res, k, sums[k], li, sums[li], n_words);
             if (res->oom) break;
         }
+        if (allocated) illegal_accesses(res, li, allocated);
+        if (res->oom) break;
         check_launch(res, li, nt);
         if (res->oom) break;
         if (deadlocked) break;
@@ -577,6 +629,7 @@ int ora_run_job_streams(uint32_t n_launches, const uint64_t *const *progs, const
         for (uint32_t k = 0; k < n_launches; k++) free(sums[k]);
     free(sums);
     free(hb);
+    free(allocated);
     if (res->oom) {
         free(res->recs); free(res->kept); free(res->races); free(res->faults); free(res);
         return 3;
@@ -594,8 +647,8 @@ int ora_run_job_streams(uint32_t n_launches, const uint64_t *const *progs, const
 int ora_run_job(uint32_t n_launches, const uint64_t *const *progs, const uint32_t *prog_lens,
                 const ora_launch *launches, int32_t *mem, uint64_t n_words, uint32_t fuel,
                 int keep_records, ora_result **out) {
-    return ora_run_job_streams(n_launches, progs, prog_lens, launches, mem, n_words, fuel, keep_records,
-                               NULL, NULL, 0, out);
+    return ora_run_job_ex(n_launches, progs, prog_lens, launches, mem, n_words, fuel, keep_records,
+                          NULL, NULL, 0, NULL, 0, out);
 }
 
 uint64_t ora_records(const ora_result *r) { return r->n_records; }

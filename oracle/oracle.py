@@ -21,7 +21,7 @@ SRC_PATH = os.path.join(_HERE, "kc_oracle.c")
 
 DEFAULT_FUEL = 1 << 20
 
-F_DEADLOCK, F_DIVERGENCE, F_OOB, F_FUEL, F_ARITH = 1, 2, 3, 4, 5
+F_DEADLOCK, F_DIVERGENCE, F_OOB, F_FUEL, F_ARITH, F_ALLOC = 1, 2, 3, 4, 5, 6
 
 
 def build(force: bool = True) -> str:
@@ -44,6 +44,7 @@ FAULT_DTYPE = np.dtype([(f, "<u4") for f in ("launch", "kind", "block", "epoch",
 RECORD_DTYPE = np.dtype([(f, "<u4") for f in ("launch", "space", "addr", "block", "epoch", "tid", "kind")])
 
 _lib = None
+_EMPTY_ALLOCS = (C.c_uint64 * 2)()      # a non-null list of no allocations
 
 
 def _load():
@@ -56,10 +57,11 @@ def _load():
                                     C.POINTER(_Launch), C.c_void_p, C.c_uint64, C.c_uint32, C.c_int,
                                     C.POINTER(C.c_void_p)]
         lib.ora_run_job.restype = C.c_int
-        lib.ora_run_job_streams.argtypes = [C.c_uint32, C.POINTER(C.c_void_p), C.POINTER(C.c_uint32),
-                                            C.POINTER(_Launch), C.c_void_p, C.c_uint64, C.c_uint32, C.c_int,
-                                            C.c_void_p, C.c_void_p, C.c_uint32, C.POINTER(C.c_void_p)]
-        lib.ora_run_job_streams.restype = C.c_int
+        lib.ora_run_job_ex.argtypes = [C.c_uint32, C.POINTER(C.c_void_p), C.POINTER(C.c_uint32),
+                                       C.POINTER(_Launch), C.c_void_p, C.c_uint64, C.c_uint32, C.c_int,
+                                       C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p, C.c_uint32,
+                                       C.POINTER(C.c_void_p)]
+        lib.ora_run_job_ex.restype = C.c_int
         lib.ora_records.argtypes = [C.c_void_p]
         lib.ora_records.restype = C.c_uint64
         lib.ora_instructions.argtypes = [C.c_void_p]
@@ -112,7 +114,9 @@ def run_job(job, fuel: int = DEFAULT_FUEL, keep_records: bool = False,
 
     ``job.streams`` (one stream id per launch) and ``job.deps`` ((before,
     after) launch pairs), when the job has them, describe which launches may
-    run in parallel; races between such launches are reported with scope 2."""
+    run in parallel; races between such launches are reported with scope 2.
+    ``job.allocs`` ((base, words) ranges), when not None, lists the device
+    allocations: accesses outside them are reported as ALLOC findings."""
     lib = _load()
     progs = [np.ascontiguousarray(np.asarray(L.program, dtype=np.uint64)) for L in job.launches]
     n = len(progs)
@@ -132,10 +136,14 @@ def run_job(job, fuel: int = DEFAULT_FUEL, keep_records: bool = False,
     if st is not None and len(st) != n:
         raise ValueError("one stream per launch")
     dp = np.ascontiguousarray(np.asarray(deps, dtype=np.uint32).reshape(-1, 2))
+    allocs = getattr(job, "allocs", None)
+    al = None if allocs is None else np.ascontiguousarray(np.asarray(allocs, dtype=np.uint64).reshape(-1, 2))
     out = C.c_void_p()
-    rc = lib.ora_run_job_streams(n, ptrs, lens, ls, mem.ctypes.data, len(mem), fuel, int(keep_records),
-                                 None if st is None else st.ctypes.data, dp.ctypes.data if len(dp) else None,
-                                 len(dp), C.byref(out))
+    rc = lib.ora_run_job_ex(n, ptrs, lens, ls, mem.ctypes.data, len(mem), fuel, int(keep_records),
+                            None if st is None else st.ctypes.data, dp.ctypes.data if len(dp) else None,
+                            len(dp), None if al is None else (al.ctypes.data if len(al) else
+                                                              C.addressof(_EMPTY_ALLOCS)),
+                            0 if al is None else len(al), C.byref(out))
     if rc != 0:
         raise ValueError(f"oracle rejected the job (code {rc})")
     try:

@@ -55,6 +55,7 @@ class Job:
     meta: Dict = field(default_factory=dict)
     streams: Optional[List[int]] = None             # stream of each launch (None: one stream)
     deps: List[Tuple[int, int]] = field(default_factory=list)   # (before, after): after waits for before
+    allocs: Optional[List[Tuple[int, int]]] = None  # device allocations (base, words); None: no check
 
 
 def _prog(a: Asm) -> np.ndarray:
