@@ -43,6 +43,8 @@ def main():
                          "first warm-up step (default); 0: the interpreter")
     ap.add_argument("--no-sort-path", action="store_true",
                     help="skip the comparison of the in-LDS epoch-local check with the sort-only check")
+    ap.add_argument("--no-streams", action="store_true",
+                    help="skip the streams-and-events measurement (two streams against one)")
     ap.add_argument("--serve-seconds", type=float, default=3.0, help="arrival window per served rate")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB three times (the known-size kernel that scales "
@@ -105,6 +107,7 @@ def main():
     sort_path = None if args.no_sort_path else local_vs_sort(ctx, step, rep, mem, torch, np)
     batched, sample = (None, []) if args.no_batched else batched_vs_plain(ctx, W, kc, torch, np)
     serving = None if args.no_serve else served(ctx, W, torch, np, args.serve_seconds)
+    streams = None if args.no_streams else streams_leg(ctx, W, kc, torch, np)
 
     cpu, exact = None, None
     if not args.no_cpu_baseline:
@@ -112,6 +115,13 @@ def main():
         if batched is not None:
             batched["bit_exact_sample"] = sample_exact
             batched["verified_instances"] = len(sample)
+        if streams is not None:
+            _, _, s_exact = cpu_baseline_leg(None, None, None, 0, np,
+                                             [(streams["job"], streams["report"], streams["memory"].cpu().numpy())])
+            streams["missing_event_bit_exact_vs_oracle"] = s_exact
+    if streams is not None:
+        for k in ("job", "report", "memory"):
+            streams.pop(k)
 
     lat_ms = sorted(x * 1e3 for x in lat)
     out = {
@@ -133,11 +143,13 @@ def main():
         "shadow_vs_sort": sort_path,
         "batched_vs_plain": batched,
         "served": serving,
+        "streams": streams,
     }
     print(json.dumps(out), flush=True)
     ctx.close()
     if exact is False or (batched and batched.get("bit_exact_sample") is False) or \
-            (sort_path and not sort_path["same_reports"]):
+            (sort_path and not sort_path["same_reports"]) or \
+            (streams and (not streams["same_otherwise"] or streams.get("missing_event_bit_exact_vs_oracle") is False)):
         sys.exit(1)
 
 
@@ -202,6 +214,8 @@ def cpu_baseline_leg(job, rep, mem, cpu_seconds, np, sample=()):
     bit-exact comparison of the GPU's last step (and of a sample of batched
     instances, (job, report, final memory)) with the oracle's runs."""
     from oracle import oracle as O
+    if job is None:             # only the sample
+        return None, None, all(_same(r, m, O.run_job(j), np) for j, r, m in sample)
     t_o = time.perf_counter()
     orc = O.run_job(job)
     oracle_s = time.perf_counter() - t_o
@@ -293,6 +307,51 @@ def batched_vs_plain(ctx, W, kc, torch, np, reps=3, plain_sample=200, verify=40)
             "plain_p99_ms": round(lat_ms[min(len(lat_ms) - 1, int(0.99 * len(lat_ms)))], 4),
             "speedup": round((records / best) / plain_rate, 2),
             "bit_exact_sample": None, "verified_instances": 0}, sample
+
+
+def streams_leg(ctx, W, kc, torch, np, reps=5):
+    """Streams and events: two workload-2 tree reductions (4096 x 256 each,
+    1% dropped-barrier blocks) in two streams, then a final reduction of both
+    partial-sum arrays in the first stream that waits for the second through
+    an event (seed 12116199).  Timed as one stream (no launch may overlap, no
+    summaries), with the two streams and the event (the two reductions may
+    run in parallel: their access summaries are built and compared; no race
+    between launches), and with the event left out (the final launch races
+    with the second reduction on its 4096 partial sums).  Each run starts
+    from the initial memory (copied outside the timed region).  Reports must
+    agree except for the races between launches."""
+    variants = {"one_stream": W.streams_reduce_job(), "two_streams": W.streams_reduce_job(),
+                "missing_event": W.streams_reduce_job(missing_event=True)}
+    variants["one_stream"].streams, variants["one_stream"].deps = None, []
+    init = torch.from_numpy(np.ascontiguousarray(variants["one_stream"].memory)).cuda()
+    out, reps_of, mem_of = {}, {}, {}
+    for name, job in variants.items():
+        times = []
+        for _ in range(reps + 1):           # the first run is a warm-up
+            mem = init.clone()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rep, mem = kc.run_job(ctx, job, mem=mem)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        best = min(times[1:])
+        reps_of[name], mem_of[name] = rep, mem
+        out[name] = {"ms": round(best * 1e3, 3), "records_per_s": round(rep.records / best, 1),
+                     "races_between_launches": sum(1 for r in rep.race_tuples() if r[2] == 2)}
+    one = reps_of["one_stream"]
+    same = True
+    for name in ("two_streams", "missing_event"):
+        r = reps_of[name]
+        same &= (r.records == one.records and [x for x in r.race_tuples() if x[2] != 2] == one.race_tuples()
+                 and r.fault_tuples() == one.fault_tuples() and bool(torch.equal(mem_of[name], mem_of["one_stream"])))
+    if not same:
+        print("bench: the stream variants differ beyond their races between launches", file=sys.stderr)
+    out.update({"workload": "two workload-2 trees (4096 x 256 each, 1% dropped barriers) in two streams + a final "
+                            "tree in stream 0 after an event; seed 12116199",
+                "records": one.records, "same_otherwise": same,
+                "job": variants["missing_event"], "report": reps_of["missing_event"],
+                "memory": mem_of["missing_event"]})
+    return out
 
 
 def served(ctx, W, torch, np, seconds, rates=(1000.0, 5000.0, 20000.0)):

@@ -84,7 +84,7 @@ typedef struct kc_report kc_report;
 typedef struct { uint32_t x, y, z; } kc_dim3;
 
 /* Finding kinds (kc_fault.kind). */
-enum { KC_DEADLOCK = 1, KC_DIVERGENCE = 2, KC_OOB = 3, KC_FUEL = 4, KC_ARITH = 5 };
+enum { KC_DEADLOCK = 1, KC_DIVERGENCE = 2, KC_OOB = 3, KC_FUEL = 4, KC_ARITH = 5, KC_ALLOC = 6 };
 
 /* ---- context ------------------------------------------------------------ */
 
@@ -178,6 +178,11 @@ typedef struct {
     uint32_t before, after;
 } kc_dep;
 
+/* A device allocation inside a job's memory: words [base, base + words). */
+typedef struct {
+    uint64_t base, words;
+} kc_region;
+
 /* A job: launches on one memory (Section 2).  By default they form one
  * stream and run in order.  With `streams` (one stream id per launch) and
  * `deps`, launch i happens before launch j when a chain of same-stream order
@@ -197,6 +202,14 @@ typedef struct {
     const uint32_t *streams;    /* n_launches entries, or NULL: one stream */
     const kc_dep *deps;         /* n_deps entries (before < after < n_launches), or NULL */
     uint32_t n_deps;
+    /* Memory objects: when `allocs` is not NULL it lists the job's device
+     * allocations (n_allocs entries, possibly 0, each inside the memory,
+     * overlaps allowed).  A global access by a kernel to a word outside every
+     * allocation (host memory or nothing, from the device's side) is illegal:
+     * it takes effect, and each block that made such accesses to a word gets
+     * one KC_ALLOC finding.  NULL: no check. */
+    const kc_region *allocs;
+    uint32_t n_allocs;
 } kc_job;
 
 /* Submit jobs as one batch; returns at once.  All jobs of the batch execute
@@ -239,7 +252,9 @@ typedef struct {
      * DIVERGENCE: a = smallest barrier pc, b = smallest tid there, c = next barrier pc, d = its smallest tid
      * OOB:        a = space*2 + (1 if store), b = tid, c = address (int32)
      * FUEL:       b = tid
-     * ARITH:      b = tid, c = pc */
+     * ARITH:      b = tid, c = pc
+     * ALLOC:      epoch 0xFFFFFFFF, a = 2 + (1 if the block stored to the word), b = smallest tid of the
+     *             block that accessed it, c = word, d = smallest tid that stored to it or 0xFFFFFFFF */
 } kc_fault;
 
 uint64_t kc_report_records(const kc_report *r);            /* canonical access-record count */

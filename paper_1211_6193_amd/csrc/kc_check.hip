@@ -621,6 +621,23 @@ __global__ void __launch_bounds__(WG) k_summary(SummaryArgs a) {
     }
 }
 
+// Memory objects: records of global words outside the unit's allocations.
+__global__ void __launch_bounds__(WG) k_alloc_scan(AllocScanArgs a) {
+    const KeyPlan &k = a.kp;
+    for (uint64_t i = (uint64_t)blockIdx.x * WG + threadIdx.x; i < a.n; i += (uint64_t)gridDim.x * WG) {
+        const uint64_t r = a.log[i];
+        if (rec_field(r, k.s_sp, 1) != 1u) continue;
+        const uint32_t unit = rec_field(r, k.s_unit, k.ub);
+        const uint32_t *bm = a.allocated[unit];
+        if (!bm || (a.skip_units && a.skip_units[unit])) continue;
+        if (a.skip_blocks && a.skip_blocks[a.units[unit].block_base + rec_field(r, k.s_blk, k.bb)]) continue;
+        const uint32_t addr = rec_field(r, k.s_addr, k.ab);
+        if ((bm[addr >> 5] >> (addr & 31u)) & 1u) continue;
+        const uint32_t at = atomicAdd(a.count, 1u);
+        if (at < a.cap) a.out[at] = r;
+    }
+}
+
 // Races between an earlier launch (summary si) and a later one (sj) of a job
 // that may run in parallel: every word one writes and the other touches.
 __global__ void __launch_bounds__(WG) k_cross_launch(const uint32_t *__restrict__ si, const uint32_t *__restrict__ sj,
@@ -644,6 +661,12 @@ __global__ void __launch_bounds__(WG) k_cross_launch(const uint32_t *__restrict_
 hipError_t launch_summary(const SummaryArgs &a, hipStream_t s) {
     if (a.n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_summary, dim3((uint32_t)std::min<uint64_t>(blocks_for(a.n), 8192)), dim3(WG), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_alloc_scan(const AllocScanArgs &a, hipStream_t s) {
+    if (a.n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_alloc_scan, dim3((uint32_t)std::min<uint64_t>(blocks_for(a.n), 8192)), dim3(WG), 0, s, a);
     return hipGetLastError();
 }
 

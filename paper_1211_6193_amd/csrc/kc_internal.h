@@ -25,7 +25,7 @@ constexpr uint32_t MAX_INSTR = 1u << 16;
 constexpr uint32_t MAX_THREADS = 1024;
 constexpr uint32_t MAX_SHMEM_WORDS = 16384;     // 64 KiB of simulated shared memory
 
-enum : uint32_t { F_DEADLOCK = 1, F_DIVERGENCE = 2, F_OOB = 3, F_FUEL = 4, F_ARITH = 5 };
+enum : uint32_t { F_DEADLOCK = 1, F_DIVERGENCE = 2, F_OOB = 3, F_FUEL = 4, F_ARITH = 5, F_ALLOC = 6 };
 
 // ---- one (instance, launch) as the device sees it -------------------------
 struct DevUnit {
@@ -231,6 +231,23 @@ struct SummaryArgs {
     const uint32_t *skip_units;
 };
 hipError_t launch_summary(const SummaryArgs &a, hipStream_t s);
+// Memory objects: the records of a log whose global word lies outside the
+// unit's allocations (allocated[u]: one bit per word, bit x % 32 of word
+// x / 32; null: no check) are copied to out (cap entries; *count counts them
+// all).  Skips as for launch_summary.
+struct AllocScanArgs {
+    const uint64_t *log;
+    uint64_t n;
+    KeyPlan kp;
+    const DevUnit *units;
+    const uint32_t *const *allocated;
+    const uint32_t *skip_blocks;
+    const uint32_t *skip_units;
+    uint64_t *out;
+    uint32_t cap;
+    uint32_t *count;
+};
+hipError_t launch_alloc_scan(const AllocScanArgs &a, hipStream_t s);
 // Races between launch `earlier` (summary si) and a later launch (sj) over
 // n_words words, appended to out (cap entries; *count counts them all) with
 // unit = tag.

@@ -248,6 +248,7 @@ struct Batch {
     std::vector<std::vector<kc_launch_desc>> descs;
     std::vector<std::vector<uint32_t>> streams;
     std::vector<std::vector<kc_dep>> deps;
+    std::vector<std::vector<kc_region>> allocs;
     hipStream_t stream = nullptr;
     std::thread worker;
     std::mutex mu;
@@ -1217,26 +1218,82 @@ struct Stage {
         ctx->stat_add("replay_ms", tm.ms(5, 6));
     }
 
+    // Call f(log, n, skip_blocks, skip_units) for each part of the stage's
+    // canonical accesses (see fin_log).
+    template <class F> void canonical_logs(F f) {
+        f(fin_log, fin_n, skip_flagged ? ws.blk_flags.as<uint32_t>() : nullptr,
+          skip_masked ? ws.mask.as<uint32_t>() : nullptr);
+        if (rep_log && rep_n) f(rep_log, rep_n, nullptr, nullptr);
+    }
+
     // Queue the access summaries of the units with sums[u] set (device array
     // of per-unit pointers, see launch_summary) from the stage's canonical
     // accesses.
     void summarize(uint32_t *const *sums) {
-        SummaryArgs a{};
-        a.kp = kp;
-        a.units = ws.units.as<DevUnit>();
-        a.sums = sums;
-        a.log = fin_log;
-        a.n = fin_n;
-        a.skip_blocks = skip_flagged ? ws.blk_flags.as<uint32_t>() : nullptr;
-        a.skip_units = skip_masked ? ws.mask.as<uint32_t>() : nullptr;
-        HIPCHK(launch_summary(a, s));
-        if (rep_log && rep_n) {
-            a.log = rep_log;
-            a.n = rep_n;
-            a.skip_blocks = nullptr;
-            a.skip_units = nullptr;
+        canonical_logs([&](const uint64_t *log, uint64_t n, const uint32_t *skip_b, const uint32_t *skip_u) {
+            SummaryArgs a{};
+            a.kp = kp;
+            a.units = ws.units.as<DevUnit>();
+            a.sums = sums;
+            a.log = log;
+            a.n = n;
+            a.skip_blocks = skip_b;
+            a.skip_units = skip_u;
             HIPCHK(launch_summary(a, s));
+        });
+    }
+
+    // Memory objects: the canonical records of global words outside their
+    // unit's allocations (allocated: device array of per-unit bitmaps), as
+    // ALLOC findings per (unit, block, word) in `found`.
+    void illegal_accesses(const uint32_t *const *allocated, std::vector<std::vector<kc_fault>> &found) {
+        uint32_t cap = 4096;
+        struct Scratch {
+            DBuf list, count;
+            ~Scratch() {
+                list.release();
+                count.release();
+            }
+        } tmp;
+        tmp.count.reserve(4);
+        std::vector<uint64_t> got;
+        for (;;) {
+            tmp.list.reserve((size_t)cap * 8);
+            HIPCHK(launch_zero(tmp.count.p, 4, s));
+            canonical_logs([&](const uint64_t *log, uint64_t n, const uint32_t *skip_b, const uint32_t *skip_u) {
+                AllocScanArgs a{log, n, kp, ws.units.as<DevUnit>(), allocated, skip_b, skip_u,
+                                tmp.list.as<uint64_t>(), cap, tmp.count.as<uint32_t>()};
+                HIPCHK(launch_alloc_scan(a, s));
+            });
+            uint32_t n = 0;
+            HIPCHK(hipMemcpyAsync(&n, tmp.count.p, 4, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            if (n > cap) {
+                cap = n;
+                continue;
+            }
+            got.resize(n);
+            if (n) HIPCHK(hipMemcpy(got.data(), tmp.list.p, (size_t)n * 8, hipMemcpyDeviceToHost));
+            break;
         }
+        // smallest accessing and storing tid per (unit, block, word)
+        constexpr uint32_t NONE_U32 = 0xFFFFFFFFu;
+        std::map<std::tuple<uint32_t, uint32_t, uint32_t>, std::pair<uint32_t, uint32_t>> m;
+        for (uint64_t r : got) {
+            const uint32_t tid = rec_field(r, kp.s_tid, kp.tb);
+            auto key = std::make_tuple(rec_field(r, kp.s_unit, kp.ub), rec_field(r, kp.s_blk, kp.bb),
+                                       rec_field(r, kp.s_addr, kp.ab));
+            auto it = m.emplace(key, std::make_pair(NONE_U32, NONE_U32)).first;
+            it->second.first = std::min(it->second.first, tid);
+            if (r & 1ull) it->second.second = std::min(it->second.second, tid);
+        }
+        for (auto &e : m) {
+            const uint32_t w = e.second.second;
+            found[std::get<0>(e.first)].push_back(kc_fault{0, F_ALLOC, std::get<1>(e.first), NONE_U32,
+                                                           w != NONE_U32 ? 3u : 2u, e.second.first,
+                                                           std::get<2>(e.first), w});
+        }
+        ctx->stat_add("alloc_findings", (double)m.size());
     }
 };
 
@@ -1365,9 +1422,11 @@ void run_jobs(kc_ctx *ctx, const kc_job *jobs, uint32_t n_jobs, hipStream_t s, s
     auto wsp = ctx->acquire();
     Workspace &ws = *wsp;
     std::vector<std::vector<DBuf>> sums(n_jobs);
+    std::vector<DBuf> allocated(n_jobs);       // memory objects: per job, one bit per allocated word
     auto free_sums = [&]() {
         for (auto &v : sums)
             for (auto &b : v) b.release();
+        for (auto &b : allocated) b.release();
     };
     try {
         ws.setup();
@@ -1384,6 +1443,21 @@ void run_jobs(kc_ctx *ctx, const kc_job *jobs, uint32_t n_jobs, hipStream_t s, s
             streams |= order.back().any;
         }
         streams &= ctx->opt.check != 0;
+        bool objects = false;
+        for (uint32_t j = 0; j < n_jobs && ctx->opt.check; j++) {
+            if (!jobs[j].allocs) continue;
+            std::vector<uint32_t> bits((jobs[j].n_words + 31) / 32 + 1, 0u);
+            for (uint32_t a = 0; a < jobs[j].n_allocs; a++) {
+                uint64_t x = jobs[j].allocs[a].base;
+                const uint64_t end = x + jobs[j].allocs[a].words;
+                for (; x < end && (x & 31); x++) bits[x >> 5] |= 1u << (x & 31);
+                for (; x + 32 <= end; x += 32) bits[x >> 5] = 0xFFFFFFFFu;
+                for (; x < end; x++) bits[x >> 5] |= 1u << (x & 31);
+            }
+            allocated[j].reserve(bits.size() * 4);
+            HIPCHK(hipMemcpy(allocated[j].p, bits.data(), bits.size() * 4, hipMemcpyHostToDevice));
+            objects = true;
+        }
         std::vector<char> alive(n_jobs, 1);
         uint32_t max_l = 0;
         for (uint32_t j = 0; j < n_jobs; j++) max_l = std::max(max_l, jobs[j].n_launches);
@@ -1411,6 +1485,32 @@ void run_jobs(kc_ctx *ctx, const kc_job *jobs, uint32_t n_jobs, hipStream_t s, s
                 else r->launches_completed = li + 1;
             }
             if (streams) cross_launch_check(ctx, ws, s, st, li, jobs, who, order, sums, reports);
+            if (objects) {
+                std::vector<const uint32_t *> bm(who.size(), nullptr);
+                bool any = false;
+                for (size_t i = 0; i < who.size(); i++)
+                    if (allocated[who[i]].p) bm[i] = allocated[who[i]].as<uint32_t>(), any = true;
+                if (any) {
+                    DBuf dbm;
+                    dbm.reserve(bm.size() * sizeof(uint32_t *));
+                    std::vector<std::vector<kc_fault>> found(who.size());
+                    try {
+                        HIPCHK(hipMemcpy(dbm.p, bm.data(), bm.size() * sizeof(uint32_t *), hipMemcpyHostToDevice));
+                        st.illegal_accesses(dbm.as<const uint32_t *>(), found);
+                    } catch (...) {
+                        dbm.release();
+                        throw;
+                    }
+                    dbm.release();
+                    for (size_t i = 0; i < who.size(); i++) {
+                        if (found[i].empty()) continue;
+                        auto &fv = reports[who[i]]->faults;
+                        const size_t first = fv.size() - out[i].faults.size();     // this launch's findings
+                        for (auto &f : found[i]) { f.launch = li; fv.push_back(f); }
+                        std::sort(fv.begin() + first, fv.end(), fault_less);
+                    }
+                }
+            }
         }
     } catch (...) {
         free_sums();
@@ -1637,6 +1737,13 @@ kc_status kc_batch_submit(kc_ctx *ctx, const kc_job *jobs, uint32_t n_jobs, void
                        " launches with streams";
             return KC_E_INVAL;
         }
+        for (uint32_t a = 0; jobs[j].allocs && a < jobs[j].n_allocs; a++) {
+            const kc_region &g = jobs[j].allocs[a];
+            if (g.base > jobs[j].n_words || g.words > jobs[j].n_words - g.base) {
+                ctx->err = "job " + std::to_string(j) + " allocation " + std::to_string(a) + ": outside the memory";
+                return KC_E_INVAL;
+            }
+        }
         for (uint32_t d = 0; d < jobs[j].n_deps; d++) {
             const kc_dep &e = jobs[j].deps[d];
             if (e.before >= e.after || e.after >= jobs[j].n_launches) {
@@ -1651,6 +1758,7 @@ kc_status kc_batch_submit(kc_ctx *ctx, const kc_job *jobs, uint32_t n_jobs, void
     b->descs.resize(n_jobs);
     b->streams.resize(n_jobs);
     b->deps.resize(n_jobs);
+    b->allocs.resize(n_jobs);
     for (uint32_t j = 0; j < n_jobs; j++) {
         b->descs[j].assign(jobs[j].launches, jobs[j].launches + jobs[j].n_launches);
         b->jobs[j].launches = b->descs[j].data();
@@ -1661,6 +1769,12 @@ kc_status kc_batch_submit(kc_ctx *ctx, const kc_job *jobs, uint32_t n_jobs, void
         if (jobs[j].n_deps) {
             b->deps[j].assign(jobs[j].deps, jobs[j].deps + jobs[j].n_deps);
             b->jobs[j].deps = b->deps[j].data();
+        }
+        if (jobs[j].allocs) {
+            // one spare entry keeps the pointer non-null for an empty list
+            b->allocs[j].assign(jobs[j].allocs, jobs[j].allocs + jobs[j].n_allocs);
+            b->allocs[j].push_back(kc_region{0, 0});
+            b->jobs[j].allocs = b->allocs[j].data();
         }
     }
     b->stream = (hipStream_t)stream;

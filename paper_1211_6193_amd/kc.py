@@ -52,10 +52,15 @@ class Dep(C.Structure):
     _fields_ = [("before", C.c_uint32), ("after", C.c_uint32)]
 
 
+class Region(C.Structure):
+    _fields_ = [("base", C.c_uint64), ("words", C.c_uint64)]
+
+
 class JobDesc(C.Structure):
     _fields_ = [("launches", C.POINTER(LaunchDesc)), ("n_launches", C.c_uint32), ("dev_mem", C.c_void_p),
                 ("n_words", C.c_uint64), ("tag", C.c_uint64), ("streams", C.POINTER(C.c_uint32)),
-                ("deps", C.POINTER(Dep)), ("n_deps", C.c_uint32)]
+                ("deps", C.POINTER(Dep)), ("n_deps", C.c_uint32), ("allocs", C.POINTER(Region)),
+                ("n_allocs", C.c_uint32)]
 
 
 _lib = None
@@ -305,6 +310,7 @@ class Batch:
             launches, mem, tag = item[:3]
             streams = item[3] if len(item) > 3 else None
             deps = item[4] if len(item) > 4 else ()
+            allocs = item[5] if len(item) > 5 else None
             arr = (LaunchDesc * max(len(launches), 1))()
             for j, (p, g, b, sh, ps) in enumerate(launches):
                 arr[j] = _desc(p, g, b, sh, ps)
@@ -325,13 +331,19 @@ class Batch:
                 keep.append(darr)
                 jd[i].deps = C.cast(darr, C.POINTER(Dep))
                 jd[i].n_deps = len(deps)
+            if allocs is not None:
+                rarr = (Region * max(len(allocs), 1))(*[Region(int(b), int(w)) for b, w in allocs])
+                keep.append(rarr)
+                jd[i].allocs = C.cast(rarr, C.POINTER(Region))
+                jd[i].n_allocs = len(allocs)
         return Prepared(jd, keep, n, [item[1] for item in jobs])
 
     def submit(self, jobs, stream=None) -> int:
         """jobs: a Prepared batch or a list of (launches, mem_tensor, tag) or
-        (launches, mem_tensor, tag, streams, deps) with launches =
+        (launches, mem_tensor, tag, streams, deps[, allocs]) with launches =
         [(prog, grid, block, shmem, params), ...], streams one stream id per
-        launch (or None) and deps (before, after) launch pairs."""
+        launch (or None), deps (before, after) launch pairs and allocs the
+        device allocations as (base, words) ranges (or None: no check)."""
         prep = jobs if isinstance(jobs, Prepared) else self.prepare(jobs)
         t = C.c_uint64()
         self.ctx._check(self.ctx.lib.kc_batch_submit(self.ctx.h, prep.jd, prep.n, _stream_handle(stream),
@@ -358,7 +370,8 @@ def job_launches(ctx: Context, job) -> list:
 
 
 def job_item(ctx: Context, job, mem, tag):
-    return (job_launches(ctx, job), mem, tag, getattr(job, "streams", None), getattr(job, "deps", None) or ())
+    return (job_launches(ctx, job), mem, tag, getattr(job, "streams", None), getattr(job, "deps", None) or (),
+            getattr(job, "allocs", None))
 
 
 def run_job(ctx: Context, job, mem=None, stream=None):

@@ -196,6 +196,34 @@ def tree256_job(n_blocks: int = 4096, threads: int = 256, drop_frac: float = 0.0
                              "in_base": in_base, "out_base": out_base})
 
 
+def streams_reduce_job(n_blocks: int = 4096, missing_event: bool = False, seed: int = BASE_SEED + 6) -> Job:
+    """Streams and events: two workload-2 tree reductions (1% dropped-barrier
+    blocks) over separate input arrays, launched in two streams (they may run in parallel), then a third
+    tree launch in the first stream that reduces both partial-sum arrays and
+    waits for the second stream through an event (the dependency (1, 2)).
+    With ``missing_event`` the wait is left out, so the final launch reads the
+    second reduction's partial sums while it may still be writing them."""
+    a = tree256_job(n_blocks, div_frac=0.0, seed=seed)        # dropped barriers only: every launch completes
+    b = tree256_job(n_blocks, div_frac=0.0, seed=seed + 1000)
+    n = n_blocks * 256
+    m = 2 * n_blocks // 256                  # blocks of the final reduction
+    in_a, in_b, out_a, out_b = 0, n, 2 * n, 2 * n + n_blocks
+    tab_a, tab_b = 2 * n + 2 * n_blocks, 2 * n + 4 * n_blocks
+    out_c, tab_c = 2 * n + 6 * n_blocks, 2 * n + 6 * n_blocks + m
+    mem = np.zeros(tab_c + 2 * m, dtype=np.int32)
+    mem[in_a:in_a + n] = a.memory[:n]
+    mem[in_b:in_b + n] = b.memory[:n]
+    mem[tab_a:tab_a + 2 * n_blocks] = a.memory[n + n_blocks:n + 3 * n_blocks]
+    mem[tab_b:tab_b + 2 * n_blocks] = b.memory[n + n_blocks:n + 3 * n_blocks]
+    mem[tab_c:tab_c + 2 * m] = -1
+    prog = tree256_tables_program()
+    launches = [LaunchSpec(prog, (n_blocks, 1, 1), (256, 1, 1), 1024, (in_a, out_a, tab_a, tab_a + n_blocks)),
+                LaunchSpec(prog, (n_blocks, 1, 1), (256, 1, 1), 1024, (in_b, out_b, tab_b, tab_b + n_blocks)),
+                LaunchSpec(prog, (m, 1, 1), (256, 1, 1), 1024, (out_a, out_c, tab_c, tab_c + m))]
+    return Job(launches, mem, {"family": "STREAMS-REDUCE", "n_blocks": n_blocks},
+               streams=[0, 1, 0], deps=[] if missing_event else [(1, 2)])
+
+
 # ---------------------------------------------------------------------------
 # Mixed families (workload 3) with one optionally faulty block
 # ---------------------------------------------------------------------------
