@@ -67,6 +67,12 @@
  *   - Every in-bounds load and store appends an access record
  *     {space, word address, block, barrier epoch, tid, read/write}, the
  *     information the race tuples of Section 3.1 keep per location.
+ *   - Source sites (the tool reports a race with the source line it was
+ *     detected at, Section 3.2): each race tuple carries w_pc, the smallest
+ *     pc of a store by w_tid to the location, and o_pc, the smallest pc of an
+ *     access by o_tid to it, within the tuple's block and epoch (intra-block)
+ *     or the launch (cross-block); races between launches carry none
+ *     (0xFFFFFFFF).
  *   - Races (Section 3.1): two accesses to one location by different threads,
  *     at least one a write, with no synchronization point between them.  For
  *     shared memory the synchronization point is a completed barrier episode of
@@ -108,8 +114,8 @@ typedef struct {
     int32_t params[8];
 } ora_launch;
 
-typedef struct { uint32_t launch, space, addr, block, epoch, tid, kind; } ora_record;
-typedef struct { uint32_t launch, space, scope, block, epoch, addr, w_tid, o_tid; } ora_race;
+typedef struct { uint32_t launch, space, addr, block, epoch, tid, kind, pc; } ora_record;
+typedef struct { uint32_t launch, space, scope, block, epoch, addr, w_tid, o_tid, w_pc, o_pc; } ora_race;
 typedef struct { uint32_t launch, kind, block, epoch, a, b, c, d; } ora_fault;
 
 typedef struct {
@@ -135,8 +141,8 @@ typedef struct {
     } while (0)
 
 static void add_record(ora_result *res, uint32_t launch, uint32_t space, uint32_t addr,
-                       uint32_t block, uint32_t epoch, uint32_t tid, uint32_t kind) {
-    ora_record r = {launch, space, addr, block, epoch, tid, kind};
+                       uint32_t block, uint32_t epoch, uint32_t tid, uint32_t kind, uint32_t pc) {
+    ora_record r = {launch, space, addr, block, epoch, tid, kind, pc};
     GROW(res->recs, res->n_recs, res->cap_recs, ora_record);
     res->recs[res->n_recs++] = r;
     res->n_records++;
@@ -309,7 +315,7 @@ static int run_block(ora_result *res, uint32_t li, const uint64_t *prog, uint32_
                             T->r[d] = 0;
                         } else {
                             T->r[d] = space == SP_SHARED ? sh[addr] : mem[addr];
-                            add_record(res, li, space, (uint32_t)addr, bid, epoch, t, K_READ);
+                            add_record(res, li, space, (uint32_t)addr, bid, epoch, t, K_READ, T->pc);
                         }
                         break;
                     }
@@ -322,7 +328,7 @@ static int run_block(ora_result *res, uint32_t li, const uint64_t *prog, uint32_
                         } else {
                             q[nq].tid = t; q[nq].space = space; q[nq].addr = addr; q[nq].val = T->r[b];
                             nq++;
-                            add_record(res, li, space, (uint32_t)addr, bid, epoch, t, K_WRITE);
+                            add_record(res, li, space, (uint32_t)addr, bid, epoch, t, K_WRITE, T->pc);
                         }
                         break;
                     }
@@ -426,7 +432,14 @@ static void check_launch(ora_result *res, uint32_t li, uint32_t nt) {
         if (has_w) {
             for (uint64_t k = i; k < j; k++) {
                 if (r[k].tid != w) {
-                    ora_race rc = {li, r[i].space, 0, r[i].block, r[i].epoch, r[i].addr, w, r[k].tid};
+                    ora_race rc = {li, r[i].space, 0, r[i].block, r[i].epoch, r[i].addr, w, r[k].tid,
+                                   0xFFFFFFFFu, 0xFFFFFFFFu};
+                    /* source sites: the smallest pc of w's stores to the location and of the
+                     * other thread's accesses to it, in this block and epoch */
+                    for (uint64_t q = i; q < j; q++) {
+                        if (r[q].tid == w && r[q].kind == K_WRITE && r[q].pc < rc.w_pc) rc.w_pc = r[q].pc;
+                        if (r[q].tid == rc.o_tid && r[q].pc < rc.o_pc) rc.o_pc = r[q].pc;
+                    }
                     add_race(res, rc);
                     break;
                 }
@@ -449,7 +462,13 @@ static void check_launch(ora_result *res, uint32_t li, uint32_t nt) {
                 for (uint64_t k = i; k < j; k++) {
                     if (r[k].block != wb) {
                         ora_race rc = {li, SP_GLOBAL, 1, wb, 0xFFFFFFFFu, r[i].addr,
-                                       wb * nt + r[wk].tid, r[k].block * nt + r[k].tid};
+                                       wb * nt + r[wk].tid, r[k].block * nt + r[k].tid, 0xFFFFFFFFu, 0xFFFFFFFFu};
+                        /* source sites over the whole launch */
+                        for (uint64_t q = i; q < j; q++) {
+                            const uint32_t g = r[q].block * nt + r[q].tid;
+                            if (g == rc.w_tid && r[q].kind == K_WRITE && r[q].pc < rc.w_pc) rc.w_pc = r[q].pc;
+                            if (g == rc.o_tid && r[q].pc < rc.o_pc) rc.o_pc = r[q].pc;
+                        }
                         add_race(res, rc);
                         break;
                     }
@@ -525,7 +544,7 @@ static void cross_launch_races(ora_result *res, uint32_t i, const uint32_t *si, 
         if (!conflict) continue;
         const uint32_t tj = wi != NONE ? aj : wj;   /* j's smallest thread conflicting with i */
         const uint32_t ti = wj != NONE ? ai : wi;
-        ora_race rc = {j, SP_GLOBAL, 2, i, 0xFFFFFFFFu, (uint32_t)x, tj, ti};
+        ora_race rc = {j, SP_GLOBAL, 2, i, 0xFFFFFFFFu, (uint32_t)x, tj, ti, 0xFFFFFFFFu, 0xFFFFFFFFu};
         add_race(res, rc);
         if (res->oom) return;
     }

@@ -39,9 +39,10 @@ class _Launch(C.Structure):
                 ("params", C.c_int32 * 8)]
 
 
-RACE_DTYPE = np.dtype([(f, "<u4") for f in ("launch", "space", "scope", "block", "epoch", "addr", "w_tid", "o_tid")])
+RACE_DTYPE = np.dtype([(f, "<u4") for f in ("launch", "space", "scope", "block", "epoch", "addr", "w_tid", "o_tid",
+                                            "w_pc", "o_pc")])
 FAULT_DTYPE = np.dtype([(f, "<u4") for f in ("launch", "kind", "block", "epoch", "a", "b", "c", "d")])
-RECORD_DTYPE = np.dtype([(f, "<u4") for f in ("launch", "space", "addr", "block", "epoch", "tid", "kind")])
+RECORD_DTYPE = np.dtype([(f, "<u4") for f in ("launch", "space", "addr", "block", "epoch", "tid", "kind", "pc")])
 
 _lib = None
 _EMPTY_ALLOCS = (C.c_uint64 * 2)()      # a non-null list of no allocations
@@ -90,7 +91,12 @@ class OracleResult:
     instructions: int = 0         # thread-instructions executed (fuel spent)
 
     def race_tuples(self) -> List[Tuple[int, ...]]:
-        return [tuple(int(x) for x in r) for r in self.races]
+        """(launch, space, scope, block, epoch, addr, w_tid, o_tid) per race."""
+        return [tuple(int(x) for x in tuple(r)[:8]) for r in self.races]
+
+    def race_sites(self) -> List[Tuple[int, int]]:
+        """(w_pc, o_pc) per race, in the order of race_tuples()."""
+        return [(int(r["w_pc"]), int(r["o_pc"])) for r in self.races]
 
     def fault_tuples(self) -> List[Tuple[int, ...]]:
         return [tuple(int(x) for x in f) for f in self.faults]

@@ -190,22 +190,27 @@ def test_records_permutation_free_definition():
         recs = r.record_log
         segs = {}
         for x in recs:
-            L, sp, ad, bl, ep, ti, ki = (int(v) for v in x)
-            segs.setdefault((L, sp, 0, bl, ep, ad), []).append((ti, ki))
+            L, sp, ad, bl, ep, ti, ki, pc = (int(v) for v in x)
+            segs.setdefault((L, sp, 0, bl, ep, ad), []).append((ti, ki, pc))
             if sp == 1:
-                segs.setdefault((L, sp, 1, ad), []).append((bl * nt + ti, ki, bl))
-        want = []
+                segs.setdefault((L, sp, 1, ad), []).append((bl * nt + ti, ki, bl, pc))
+        want, sites = [], {}
         for key, rs in segs.items():
             if key[2] == 0:
                 pairs = [(a, b) for a in rs for b in rs if a[0] != b[0] and (a[1] or b[1])]
                 if pairs:
-                    w = min(t for t, k in rs if k == 1)
-                    o = min(t for t, k in rs if t != w)      # every other tid conflicts with w
+                    w = min(t for t, k, _ in rs if k == 1)
+                    o = min(t for t, k, _ in rs if t != w)      # every other tid conflicts with w
                     want.append(key + (w, o))
+                    # source sites: w's first store site and o's first access site by pc
+                    sites[want[-1]] = (min(p for t, k, p in rs if t == w and k == 1), min(p for t, _, p in rs if t == o))
             else:
                 pairs = [(a, b) for a in rs for b in rs if a[2] != b[2] and (a[1] or b[1])]
                 if pairs:
-                    w, wb = min((g, b) for g, k, b in rs if k == 1)
-                    o = min(g for g, k, b in rs if b != wb)
+                    w, wb = min((g, b) for g, k, b, _ in rs if k == 1)
+                    o = min(g for g, k, b, _ in rs if b != wb)
                     want.append((key[0], 1, 1, wb, 0xFFFFFFFF, key[3], w, o))
+                    sites[want[-1]] = (min(p for g, k, _, p in rs if g == w and k == 1),
+                                       min(p for g, _, _, p in rs if g == o))
         assert r.race_tuples() == sorted(want, key=_key)
+        assert r.race_sites() == [sites[t] for t in r.race_tuples()]

@@ -50,7 +50,7 @@ def _reader_of(base):
 
 
 def _cross(res):
-    return sorted(tuple(int(v) for v in r) for r in res.races if r["scope"] == 2)
+    return sorted(t for t in res.race_tuples() if t[2] == 2)
 
 
 def _job(specs, streams=None, deps=(), words=16):
