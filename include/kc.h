@@ -116,8 +116,10 @@ void kc_ctx_destroy(kc_ctx *ctx);
  * "jit" (1 = run free runs on program-specialised kernels: each program is
  * translated to HIP and compiled with hiprtc for gfx950 at its first launch,
  * once per process, which takes seconds; results are identical to the
- * interpreter's; 0 = interpreter only, default), "reset" (1 = clear the
- * statistics).
+ * interpreter's; 0 = interpreter only, default), "sites" (1 = fill the
+ * races' source sites, kc_report_race_sites: the racy blocks are replayed
+ * once more with a site table; 0 = not computed, default), "reset" (1 =
+ * clear the statistics).
  * Errors: KC_E_INVAL for an unknown key or out-of-range value. */
 kc_status kc_ctx_set_option(kc_ctx *ctx, const char *key, int64_t value);
 
@@ -132,7 +134,8 @@ kc_status kc_ctx_set_option(kc_ctx *ctx, const char *key, int64_t value);
  * "instructions" (thread-instructions executed by the parallel free run; a
  * canonical replay of racy blocks is not counted), "jit_launches", "jit_replays"
  * (replay launches on specialised kernels),
- * "jit_compiled", "jit_compile_ms", "jit_failures".
+ * "jit_compiled", "jit_compile_ms", "jit_failures", "site_replays",
+ * "cross_launch_races", "alloc_findings".
  * Timings are only collected with option "timing" set.  "option.<name>"
  * reads back the current value of option <name>.  Returns 0 for an unknown
  * key. */
@@ -257,6 +260,15 @@ typedef struct {
      *             block that accessed it, c = word, d = smallest tid that stored to it or 0xFFFFFFFF */
 } kc_fault;
 
+/* Source sites of a race (the tool names the source line a race was found
+ * at, Section 3.2): w_pc is the smallest pc of a store by w_tid to the
+ * location, o_pc the smallest pc of an access by o_tid to it, within the
+ * tuple's block and epoch (scope 0) or its launch (scope 1); 0xFFFFFFFF when
+ * not computed (option "sites" off, and always for scope 2). */
+typedef struct {
+    uint32_t w_pc, o_pc;
+} kc_race_site;
+
 uint64_t kc_report_records(const kc_report *r);            /* canonical access-record count */
 uint32_t kc_report_launches_completed(const kc_report *r);
 /* Races ascending by (launch, space, scope, block, epoch, addr); the array
@@ -264,18 +276,20 @@ uint32_t kc_report_launches_completed(const kc_report *r);
 const kc_race *kc_report_races(const kc_report *r, uint64_t *n);
 /* Findings ascending by (launch, block, epoch, kind, a, b, c, d), no repeats. */
 const kc_fault *kc_report_faults(const kc_report *r, uint64_t *n);
+/* Sites of the races, one per race in the same order; lives as long as the report. */
+const kc_race_site *kc_report_race_sites(const kc_report *r, uint64_t *n);
 uint64_t kc_report_tag(const kc_report *r);
 void kc_report_free(kc_report *r);
 
 /* Many reports at once (a polled batch): for report i, records[i],
  * launches[i], tags[i], n_races[i] and n_faults[i] (each array n entries or
- * NULL); the races and findings of all reports concatenated in report order
- * into `races` and `faults` (sized by the sums of n_races and n_faults, or
- * NULL to skip).  Reports are not modified.  Errors: KC_E_INVAL for a null
- * report pointer. */
+ * NULL); the races, their sites and the findings of all reports concatenated
+ * in report order into `races`, `sites` and `faults` (sized by the sums of
+ * n_races and n_faults, or NULL to skip).  Reports are not modified.
+ * Errors: KC_E_INVAL for a null report pointer. */
 kc_status kc_reports_collect(kc_report *const *reports, uint32_t n, uint64_t *records, uint32_t *launches,
                              uint64_t *tags, uint64_t *n_races, uint64_t *n_faults, kc_race *races,
-                             kc_fault *faults);
+                             kc_fault *faults, kc_race_site *sites);
 /* Free n reports (null entries are skipped). */
 void kc_reports_free(kc_report *const *reports, uint32_t n);
 

@@ -1335,6 +1335,52 @@ __device__ __forceinline__ void lockstep_body(const InterpArgs &A, Run run) {
     }
 }
 
+// Source sites: a replayed access of `tid` (linear, or global for the
+// cross-block key) at `pc` to a location that has a race tuple.
+__device__ __forceinline__ void site_hit(const InterpArgs &A, uint32_t unit, uint32_t space, uint32_t block,
+                                         uint32_t epoch, uint32_t addr, uint32_t tid, bool store, int pc) {
+    const uint32_t mask = (1u << A.site_bits) - 1u;
+    uint32_t h = site_hash(unit, space, block, epoch, addr) & mask;
+    for (uint32_t probe = 0; probe <= mask; probe++) {
+        SiteSlot &e = A.sites[h];
+        if (!e.used) return;
+        if (e.addr == addr && e.block == block && e.epoch == epoch && e.unit == unit && e.space == space) {
+            if (store && tid == e.w) atomicMin(&e.w_pc, (uint32_t)pc);
+            if (tid == e.o) atomicMin(&e.o_pc, (uint32_t)pc);
+            return;
+        }
+        h = (h + 1) & mask;
+    }
+}
+
+__device__ __forceinline__ void site_probe(const InterpArgs &A, const BlockCtx &B, const Lane &t, int cur,
+                                           uint64_t w, bool active, uint32_t epoch) {
+    const uint32_t op = (uint32_t)w & 0xFFu;
+    if ((op >> 4) != 5u || !active) return;
+    const uint32_t ra = (uint32_t)(w >> 16) & 0xFFu;
+    const uint32_t addr = (uint32_t)t.r[ra] + (uint32_t)(int32_t)(uint32_t)(w >> 32);
+    const bool is_sh = (op & 2u) == 0, is_st = (op & 1u) != 0;
+    if (addr >= (is_sh ? B.sh_words : B.n_words)) return;
+    site_hit(A, B.unit, is_sh ? 0u : 1u, B.block, epoch, addr, B.tid, is_st, cur);
+    if (!is_sh) site_hit(A, B.unit, 1u, 0xFFFFFFFFu, 0xFFFFFFFFu, addr, B.block * B.nt + B.tid, is_st, cur);
+}
+
+// The canonical replay once more, probing the source-site table at every
+// access (without the epoch-local check: every access is logged).
+__device__ __forceinline__ void interp_lockstep_sites_body(const InterpArgs &A) {
+    lockstep_body(A, [](const InterpArgs &a, BlockCtx &b, const Shared &s, const StoreTables &tb, Lane &t,
+                        LogState &l) {
+        auto exec = [&](int cur, uint64_t w, bool active, Pending &P, uint32_t epoch, int &ctl, int &target,
+                        bool &cond) {
+            site_probe(a, b, t, cur, w, active, epoch);
+            exec_one<true, false>(a, b, s, t, l, P, epoch, cur, w, active, ctl, target, cond);
+        };
+        auto run = [](uint64_t, uint32_t) { return 0u; };
+        auto release = [&] { barrier_results(b, t); };
+        return run_block_lockstep<false>(a, b, s, tb, t, l, exec, run, release);
+    });
+}
+
 template <bool LOCAL>
 __device__ __forceinline__ void interp_lockstep_body(const InterpArgs &A) {
     lockstep_body(A, [](const InterpArgs &a, BlockCtx &b, const Shared &s, const StoreTables &tb, Lane &t,

@@ -94,6 +94,25 @@ struct DevCounters {
     uint32_t pad[5];
 };
 
+// Source sites of race tuples: one slot per tuple of an open-addressing
+// table keyed by (unit, space, block, epoch, addr) -- block and epoch
+// 0xFFFFFFFF for a cross-block tuple, whose w and o are global thread ids.
+// A replay with the table (InterpArgs::sites) lowers w_pc to the smallest pc
+// of w's stores to the location and o_pc to the smallest pc of o's accesses
+// to it (atomicMin; both start at 0xFFFFFFFF).
+struct SiteSlot {
+    uint32_t unit, space, block, epoch, addr, w, o, used;
+    uint32_t w_pc, o_pc, pad0, pad1;
+};
+__host__ __device__ inline uint32_t site_hash(uint32_t unit, uint32_t space, uint32_t block, uint32_t epoch,
+                                              uint32_t addr) {
+    uint32_t h = addr * 0x9E3779B1u;
+    h ^= (block + 0x7F4A7C15u) * 0x85EBCA77u;
+    h ^= (epoch + 0x165667B1u) * 0xC2B2AE3Du;
+    h ^= (unit * 2u + space) * 0x27D4EB2Fu;
+    return h ^ (h >> 15);
+}
+
 struct InterpArgs {
     const DevUnit *units;
     const uint2 *items;         // (unit, block) per workgroup; null: unit 0, block = blockIdx.x
@@ -118,7 +137,8 @@ struct InterpArgs {
     uint32_t *blk_flags;        // racy blocks
     unsigned long long *instructions;   // free run: thread-instructions executed (added to), or null
     uint32_t gst_bits;          // local check: log2 slots of the global shadow table (0: stage and sort)
-    uint32_t pad;
+    uint32_t site_bits;         // log2 slots of `sites`
+    SiteSlot *sites;            // lockstep replay for source sites, or null
 };
 
 #ifndef __HIPCC_RTC__

@@ -18,6 +18,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6, 6)
 
 __global__ void __launch_bounds__(1024) k_interp_lockstep(InterpArgs A) { interp_lockstep_body<false>(A); }
 __global__ void __launch_bounds__(1024) k_interp_lockstep_local(InterpArgs A) { interp_lockstep_body<true>(A); }
+__global__ void __launch_bounds__(1024) k_interp_lockstep_sites(InterpArgs A) { interp_lockstep_sites_body(A); }
 
 }  // namespace
 
@@ -42,6 +43,7 @@ size_t interp_lds_bytes(uint32_t sh_words_max, uint32_t wg_threads, uint32_t sta
 hipError_t launch_interp(const InterpArgs &a, uint32_t n_wg, uint32_t wg_threads, bool lockstep, hipStream_t s) {
     if (n_wg == 0) return hipSuccess;
     InterpArgs args = a;
+    if (args.sites) args.local = 0;                   // the source-site replay logs every access
     if (!args.local) args.gst_bits = 0;
     auto bytes = [&] {
         return interp_lds_bytes(args.sh_words_max, wg_threads, args.stage, lockstep, args.local != 0, args.gst_bits);
@@ -71,12 +73,17 @@ hipError_t launch_interp(const InterpArgs &a, uint32_t n_wg, uint32_t wg_threads
                                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         hipError_t e3 = hipFuncSetAttribute((const void *)k_interp_lockstep_local,
                                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        hipError_t e4 = hipFuncSetAttribute((const void *)k_interp_lockstep_sites,
+                                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e3 != hipSuccess) return e3;
         if (e1 != hipSuccess) return e1;
         if (e2 != hipSuccess) return e2;
+        if (e4 != hipSuccess) return e4;
         attr_set = true;
     }
-    if (lockstep && args.local)
+    if (lockstep && args.sites)
+        hipLaunchKernelGGL(k_interp_lockstep_sites, dim3(n_wg), dim3(wg_threads), lds, s, args);
+    else if (lockstep && args.local)
         hipLaunchKernelGGL(k_interp_lockstep_local, dim3(n_wg), dim3(wg_threads), lds, s, args);
     else if (lockstep)
         hipLaunchKernelGGL(k_interp_lockstep, dim3(n_wg), dim3(wg_threads), lds, s, args);

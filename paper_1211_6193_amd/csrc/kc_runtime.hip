@@ -53,8 +53,13 @@ struct kc_report {
     uint64_t records = 0;
     uint32_t launches_completed = 0;
     std::vector<kc_race> races;
+    std::vector<kc_race_site> sites;    // parallel to races
     std::vector<kc_fault> faults;
     uint64_t tag = 0;
+    void add_race(const kc_race &r, kc_race_site site = kc_race_site{0xFFFFFFFFu, 0xFFFFFFFFu}) {
+        races.push_back(r);
+        sites.push_back(site);
+    }
 };
 
 namespace {
@@ -166,6 +171,7 @@ struct UnitOut {
     uint64_t records = 0;
     bool deadlocked = false;
     std::vector<kc_race> races;     // launch field filled by the caller
+    std::vector<kc_race_site> sites;    // parallel to races (option sites), else empty
     std::vector<kc_fault> faults;
 };
 
@@ -182,6 +188,7 @@ struct Options {
     int hash_check = 1;             // conflict-free logs checked through a location table, without sorting
     int jit = 0;                    // program-specialised free-run kernels (compiled at first use)
     int jit_waves = 0;              // their occupancy target, waves per SIMD (0: the compiler's choice)
+    int sites = 0;                  // source sites of races (one more replay of the racy blocks)
 };
 
 }  // namespace
@@ -434,6 +441,9 @@ struct Stage {
     const uint64_t *rep_log = nullptr;
     uint64_t rep_n = 0;
     bool skip_flagged = false, skip_masked = false;
+    std::vector<std::vector<uint2>> replayed;   // the components the replay ran (whole units: skip_masked)
+    SiteSlot *site_table = nullptr;             // set during the source-site replay
+    uint32_t site_bits = 0;
     bool log_sorted = false;        // the free-run log was sorted for its check
     uint32_t ftable_bits = 0;       // else: log2 slots of its location table (ws.ftable),
     bool direct_tables = false;     // or its direct word tables (ws.downer, ws.dflags)
@@ -600,6 +610,12 @@ struct Stage {
             a.comp_blocks = ws.comp_blocks.as<uint2>();
             a.sh_words_max = shmax;
             a.gst_bits = gst ? gst_bits_for(wg) : 0u;
+            if (site_table) {       // the source-site replay: the interpreter with the site probe
+                a.sites = site_table;
+                a.site_bits = site_bits;
+                HIPCHK(launch_interp(a, n_comp, wg, true, s));
+                return;
+            }
             // one program for every unit: its specialised replay kernels
             bool one_program = true;
             for (const auto &x : in) one_program = one_program && x.desc->prog == in[0].desc->prog;
@@ -1089,6 +1105,7 @@ struct Stage {
                            ws.dflags.as<uint8_t>(), nullptr};
         ws.rctr.reserve(sizeof(DevCounters));
         ta.n_dev = &ws.rctr.as<DevCounters>()->log_count;
+        replayed = comps;
         DevCounters rc = lockstep_once(comps, rcap, fcap, rlcap, &ro, use_table ? &ta : nullptr);
         tm.mark(7);
         ctx->stat_add("replay_lockstep_ms", tm.ms(5, 7));
@@ -1181,6 +1198,7 @@ struct Stage {
             full.push_back(std::move(v));
         }
         rcap = std::max<uint64_t>(rcap, need + need / 4 + 1024);
+        replayed = full;
         DevCounters fc;
         ReplayOut fo;
         for (;;) {
@@ -1216,6 +1234,77 @@ struct Stage {
         for (auto &f : ff) ufaults[f.unit].push_back(kc_fault{0, f.kind, f.block, f.epoch, f.a, f.b, f.c, f.d});
         tm.mark(6);
         ctx->stat_add("replay_ms", tm.ms(5, 6));
+    }
+
+    // Source sites of the stage's races (scope 0 and 1): put back what the
+    // replay wrote, run the replayed components once more with the site
+    // table (the same canonical execution, so memory ends the same), and read
+    // the smallest store pc of each tuple's writer and access pc of its other
+    // thread.  Fills out[i].sites parallel to out[i].races.
+    void sites_pass(std::vector<UnitOut> &out) {
+        constexpr uint32_t NONE = 0xFFFFFFFFu;
+        uint64_t n_races = 0;
+        for (auto &o : out) {
+            o.sites.assign(o.races.size(), kc_race_site{NONE, NONE});
+            n_races += o.races.size();
+        }
+        if (!n_races || replayed.empty()) return;
+        uint32_t bits = 10;
+        while ((1ull << bits) < 2 * n_races) bits++;
+        std::vector<SiteSlot> table((size_t)1 << bits);
+        std::vector<std::pair<uint32_t, size_t>> where;     // (unit, race index) per filled slot
+        std::vector<uint32_t> slot_of;
+        for (uint32_t u = 0; u < out.size(); u++)
+            for (size_t q = 0; q < out[u].races.size(); q++) {
+                const kc_race &r = out[u].races[q];
+                const uint32_t mask = (1u << bits) - 1u;
+                uint32_t h = site_hash(u, r.space, r.block, r.epoch, r.addr) & mask;
+                if (r.scope == 1) h = site_hash(u, 1u, NONE, NONE, r.addr) & mask;
+                while (table[h].used) h = (h + 1) & mask;
+                SiteSlot &e = table[h];
+                e.unit = u;
+                e.space = r.space;
+                e.block = r.scope == 1 ? NONE : r.block;
+                e.epoch = r.scope == 1 ? NONE : r.epoch;
+                e.addr = r.addr;
+                e.w = r.w_tid;
+                e.o = r.o_tid;
+                e.used = 1;
+                e.w_pc = e.o_pc = NONE;
+                where.push_back({u, q});
+                slot_of.push_back(h);
+            }
+        struct Scratch {
+            DBuf t;
+            ~Scratch() { t.release(); }
+        } tmp;
+        tmp.t.reserve(table.size() * sizeof(SiteSlot));
+        HIPCHK(hipMemcpyAsync(tmp.t.p, table.data(), table.size() * sizeof(SiteSlot), hipMemcpyHostToDevice, s));
+        // back to the memory the replay started from
+        if (skip_masked)
+            HIPCHK(launch_copy_units(ws.units.as<DevUnit>(), (uint32_t)hu.size(), max_words, false,
+                                     ws.mask.as<uint32_t>(), s));
+        else
+            HIPCHK(launch_restore(rep_log, rep_n, kp, ws.units.as<DevUnit>(), ws.blk_flags.as<uint32_t>(), s));
+        site_table = tmp.t.as<SiteSlot>();
+        site_bits = bits;
+        const uint64_t cap = std::max<uint64_t>(ws.rlog.bytes / 8, 1);
+        const uint32_t fcap = (uint32_t)std::max<size_t>(ws.rfaults.bytes / sizeof(DevFault), 1);
+        const uint32_t rlcap = (uint32_t)std::max<size_t>(ws.rlraces.bytes / sizeof(DevRace), 1);
+        try {
+            lockstep_once(replayed, cap, fcap, rlcap);      // its log may overflow: only the sites are used
+        } catch (...) {
+            site_table = nullptr;
+            throw;
+        }
+        site_table = nullptr;
+        HIPCHK(hipMemcpyAsync(table.data(), tmp.t.p, table.size() * sizeof(SiteSlot), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        for (size_t i = 0; i < where.size(); i++) {
+            const SiteSlot &e = table[slot_of[i]];
+            out[where[i].first].sites[where[i].second] = kc_race_site{e.w_pc, e.o_pc};
+        }
+        ctx->stat_add("site_replays", 1);
     }
 
     // Call f(log, n, skip_blocks, skip_units) for each part of the stage's
@@ -1411,7 +1500,7 @@ void cross_launch_check(kc_ctx *ctx, Workspace &ws, hipStream_t s, Stage &st, ui
     std::sort(got.begin(), got.end(), [](const DevRace &a, const DevRace &b) {
         return std::tie(a.unit, a.block, a.addr) < std::tie(b.unit, b.block, b.addr);
     });
-    for (auto &r : got) reports[r.unit]->races.push_back(kc_race{li, 1, 2, r.block, r.epoch, r.addr, r.w, r.o});
+    for (auto &r : got) reports[r.unit]->add_race(kc_race{li, 1, 2, r.block, r.epoch, r.addr, r.w, r.o});
     ctx->stat_add("cross_launch_races", (double)got.size());
 }
 
@@ -1475,11 +1564,13 @@ void run_jobs(kc_ctx *ctx, const kc_job *jobs, uint32_t n_jobs, hipStream_t s, s
             st.run();
             ctx->stat_add("launches", (double)in.size());
             HostTimer ht{ctx, "host_reports_ms", ctx->opt.timing != 0};
+            std::vector<size_t> first_race(who.size());
             for (size_t i = 0; i < who.size(); i++) {
                 kc_report *r = reports[who[i]];
                 UnitOut &o = out[i];
                 r->records += o.records;
-                for (auto &x : o.races) { x.launch = li; r->races.push_back(x); }
+                first_race[i] = r->races.size();
+                for (auto &x : o.races) { x.launch = li; r->add_race(x); }
                 for (auto &f : o.faults) { f.launch = li; r->faults.push_back(f); }
                 if (o.deadlocked) alive[who[i]] = 0;
                 else r->launches_completed = li + 1;
@@ -1510,6 +1601,14 @@ void run_jobs(kc_ctx *ctx, const kc_job *jobs, uint32_t n_jobs, hipStream_t s, s
                         std::sort(fv.begin() + first, fv.end(), fault_less);
                     }
                 }
+            }
+            // last: it runs the replay again over the replay's log, which the
+            // stream summaries and memory-object scans read
+            if (ctx->opt.sites && ctx->opt.check) {
+                st.sites_pass(out);
+                for (size_t i = 0; i < who.size(); i++)
+                    std::copy(out[i].sites.begin(), out[i].sites.end(),
+                              reports[who[i]]->sites.begin() + first_race[i]);
             }
         }
     } catch (...) {
@@ -1619,6 +1718,7 @@ kc_status kc_ctx_set_option(kc_ctx *ctx, const char *key, int64_t v) {
     else if (k == "hash_check" && (v == 0 || v == 1)) ctx->opt.hash_check = (int)v;
     else if (k == "jit" && (v == 0 || v == 1)) ctx->opt.jit = (int)v;
     else if (k == "jit_waves" && (v == 0 || (v >= 2 && v <= 8))) ctx->opt.jit_waves = (int)v;
+    else if (k == "sites" && (v == 0 || v == 1)) ctx->opt.sites = (int)v;
     else if (k == "reset" && v == 1) {
         std::lock_guard<std::mutex> g(ctx->mu);
         ctx->stats.clear();
@@ -1853,6 +1953,10 @@ const kc_race *kc_report_races(const kc_report *r, uint64_t *n) {
     if (n) *n = r ? r->races.size() : 0;
     return r && !r->races.empty() ? r->races.data() : nullptr;
 }
+const kc_race_site *kc_report_race_sites(const kc_report *r, uint64_t *n) {
+    if (n) *n = r ? r->sites.size() : 0;
+    return r && !r->sites.empty() ? r->sites.data() : nullptr;
+}
 const kc_fault *kc_report_faults(const kc_report *r, uint64_t *n) {
     if (n) *n = r ? r->faults.size() : 0;
     return r && !r->faults.empty() ? r->faults.data() : nullptr;
@@ -1862,7 +1966,7 @@ void kc_report_free(kc_report *r) { delete r; }
 
 kc_status kc_reports_collect(kc_report *const *reports, uint32_t n, uint64_t *records, uint32_t *launches,
                              uint64_t *tags, uint64_t *n_races, uint64_t *n_faults, kc_race *races,
-                             kc_fault *faults) {
+                             kc_fault *faults, kc_race_site *sites) {
     if (n && !reports) return KC_E_INVAL;
     uint64_t ro = 0, fo = 0;
     for (uint32_t i = 0; i < n; i++) {
@@ -1874,6 +1978,8 @@ kc_status kc_reports_collect(kc_report *const *reports, uint32_t n, uint64_t *re
         if (n_races) n_races[i] = r->races.size();
         if (n_faults) n_faults[i] = r->faults.size();
         if (races && !r->races.empty()) std::memcpy(races + ro, r->races.data(), r->races.size() * sizeof(kc_race));
+        if (sites && !r->sites.empty())
+            std::memcpy(sites + ro, r->sites.data(), r->sites.size() * sizeof(kc_race_site));
         if (faults && !r->faults.empty())
             std::memcpy(faults + fo, r->faults.data(), r->faults.size() * sizeof(kc_fault));
         ro += r->races.size();

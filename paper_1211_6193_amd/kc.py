@@ -27,10 +27,12 @@ DEADLOCK, DIVERGENCE, OOB, FUEL, ARITH = 1, 2, 3, 4, 5
 EXPORTS = ["kc_ctx_create", "kc_ctx_destroy", "kc_ctx_set_option", "kc_ctx_get_stat", "kc_last_error",
            "kc_program_load", "kc_program_free", "kc_launch", "kc_batch_submit", "kc_poll",
            "kc_report_records", "kc_report_launches_completed", "kc_report_races", "kc_report_faults",
+           "kc_report_race_sites",
            "kc_report_tag", "kc_report_free", "kc_reports_collect", "kc_reports_free"]
 
 RACE_DTYPE = np.dtype([(f, "<u4") for f in ("launch", "space", "scope", "block", "epoch", "addr", "w_tid", "o_tid")])
 FAULT_DTYPE = np.dtype([(f, "<u4") for f in ("launch", "kind", "block", "epoch", "a", "b", "c", "d")])
+SITE_DTYPE = np.dtype([(f, "<u4") for f in ("w_pc", "o_pc")])
 
 
 class KcError(RuntimeError):
@@ -90,9 +92,10 @@ def load_library(path: str = LIB_PATH):
         "kc_report_launches_completed": ([vp], u32),
         "kc_report_races": ([vp, C.POINTER(u64)], vp),
         "kc_report_faults": ([vp, C.POINTER(u64)], vp),
+        "kc_report_race_sites": ([vp, C.POINTER(u64)], vp),
         "kc_report_tag": ([vp], u64),
         "kc_report_free": ([vp], None),
-        "kc_reports_collect": ([vp, u32, vp, vp, vp, vp, vp, vp, vp], C.c_int),
+        "kc_reports_collect": ([vp, u32, vp, vp, vp, vp, vp, vp, vp, vp], C.c_int),
         "kc_reports_free": ([vp, u32], None),
     }
     for name, (args, res) in sig.items():
@@ -116,9 +119,16 @@ class Report:
     races: np.ndarray
     faults: np.ndarray
     tag: int = 0
+    sites: Optional[np.ndarray] = None     # SITE_DTYPE, parallel to races
 
     def race_tuples(self) -> List[Tuple[int, ...]]:
         return [tuple(int(x) for x in r) for r in self.races]
+
+    def race_sites(self) -> List[Tuple[int, int]]:
+        """(w_pc, o_pc) per race (0xFFFFFFFF where not computed)."""
+        if self.sites is None:
+            return [(0xFFFFFFFF, 0xFFFFFFFF)] * len(self.races)
+        return [(int(x["w_pc"]), int(x["o_pc"])) for x in self.sites]
 
     def fault_tuples(self) -> List[Tuple[int, ...]]:
         return [tuple(int(x) for x in f) for f in self.faults]
@@ -139,12 +149,14 @@ class ReportList(cabc.Sequence):
         nf = np.zeros(n, u64)
         p = lambda a: a.ctypes.data if a.size else None
         st = lib.kc_reports_collect(ptrs, n, p(self.records), p(self.launches_completed), p(self.tags), p(nr), p(nf),
-                                    None, None)
+                                    None, None, None)
         if st != KC_OK:
             raise KcError(st, "kc_reports_collect")
         self._races = np.zeros(int(nr.sum()), RACE_DTYPE)
         self._faults = np.zeros(int(nf.sum()), FAULT_DTYPE)
-        st = lib.kc_reports_collect(ptrs, n, None, None, None, None, None, p(self._races), p(self._faults))
+        self._sites = np.zeros(int(nr.sum()), SITE_DTYPE)
+        st = lib.kc_reports_collect(ptrs, n, None, None, None, None, None, p(self._races), p(self._faults),
+                                    p(self._sites))
         lib.kc_reports_free(ptrs, n)
         if st != KC_OK:
             raise KcError(st, "kc_reports_collect")
@@ -163,7 +175,8 @@ class ReportList(cabc.Sequence):
             raise IndexError(i)
         return Report(int(self.records[i]), int(self.launches_completed[i]),
                       self._races[self._roff[i]:self._roff[i + 1]].copy(),
-                      self._faults[self._foff[i]:self._foff[i + 1]].copy(), int(self.tags[i]))
+                      self._faults[self._foff[i]:self._foff[i + 1]].copy(), int(self.tags[i]),
+                      self._sites[self._roff[i]:self._roff[i + 1]].copy())
 
     def total_records(self) -> int:
         return int(self.records.sum())
@@ -172,9 +185,10 @@ class ReportList(cabc.Sequence):
 def _take_report(lib, ptr) -> Report:
     n = C.c_uint64()
     races = _copy(lib.kc_report_races(ptr, C.byref(n)), n.value, RACE_DTYPE)
+    sites = _copy(lib.kc_report_race_sites(ptr, C.byref(n)), n.value, SITE_DTYPE)
     faults = _copy(lib.kc_report_faults(ptr, C.byref(n)), n.value, FAULT_DTYPE)
     rep = Report(int(lib.kc_report_records(ptr)), int(lib.kc_report_launches_completed(ptr)), races, faults,
-                 int(lib.kc_report_tag(ptr)))
+                 int(lib.kc_report_tag(ptr)), sites)
     lib.kc_report_free(ptr)
     return rep
 
