@@ -128,6 +128,7 @@ struct Shared {
     uint32_t *tmp;      // 256 words
     unsigned long long *shadow;   // per simulated shared word: access tuple of the current epoch
     unsigned long long *gst;      // global shadow table: per global location, its tuple of the epoch
+    uint64_t *repbuf;   // with the table: representative records held until the block ends (REP_HOLD)
     uint32_t *slots;    // 16 waves x 8 words: episode reductions
     uint32_t *slots2;   // 16 x 4: divergence second round
 };
@@ -527,16 +528,26 @@ __device__ __forceinline__ void gst_drain(const InterpArgs &A, const BlockCtx &B
     woff = (uint32_t)__shfl((int)woff, WAVE - 1);
     __syncthreads();
     if (threadIdx.x == 0) {
+        // representatives are held in LDS while they fit (written to the log
+        // at the end of the block); others are reserved in the log now
         const uint32_t total = S.tmp[32];
+        const uint32_t held = S.tmp[38];
         unsigned long long base = 0;
-        if (total) {
+        uint32_t hold = 0;
+        if (total && reduced && held + total <= REP_HOLD) {
+            base = held;
+            hold = 1;
+            S.tmp[38] = held + total;
+        } else if (total) {
             base = atomicAdd(A.log_count, (unsigned long long)total);
             if (base + total > A.log_cap) atomicOr(A.flags, FLAG_LOG_OVERFLOW);
         }
         S.tmp[33] = (uint32_t)base;
         S.tmp[34] = (uint32_t)(base >> 32);
+        S.tmp[39] = hold;
     }
     __syncthreads();
+    const bool hold = S.tmp[39] != 0;
     unsigned long long pos = ((unsigned long long)S.tmp[33] | ((unsigned long long)S.tmp[34] << 32)) + woff + incl - mine;
     const uint64_t ep = reduced ? (uint64_t)k.ep_rep : (uint64_t)epoch;
     for (uint32_t i = threadIdx.x; i < C; i += blockDim.x) {
@@ -556,8 +567,10 @@ __device__ __forceinline__ void gst_drain(const InterpArgs &A, const BlockCtx &B
             if (t2 != GT_NONE) r[n++] = base | ((uint64_t)t2 << k.s_tid) | (w == t2 ? 1ull : 0ull);
             if (w != GT_NONE && w != t1 && w != t2) r[n++] = base | ((uint64_t)w << k.s_tid) | 1ull;
         }
-        for (uint32_t j = 0; j < n; j++, pos++)
-            if (pos < A.log_cap) A.log[pos] = r[j];
+        for (uint32_t j = 0; j < n; j++, pos++) {
+            if (hold) S.repbuf[pos] = r[j];
+            else if (pos < A.log_cap) A.log[pos] = r[j];
+        }
     }
 }
 
@@ -932,6 +945,7 @@ __device__ __forceinline__ void setup_block(const InterpArgs &A, BlockCtx &B, co
         if (threadIdx.x == 0) {
             S.tmp[36] = 0;
             S.tmp[37] = 0;
+            S.tmp[38] = 0;          // representatives held in LDS
         }
     }
     t.pc = 0;
@@ -954,11 +968,27 @@ __device__ __forceinline__ void finish_block(const InterpArgs &A, const BlockCtx
     flush_stage(A, S.stage, L.cur);
     L.cur = 0;
     unsigned long long spent = 0;
-    if (A.instructions) {
+    if (A.blk_instr) {
         spent = (t.st != ST_DEAD) ? (unsigned long long)(B.u->fuel - t.fuel) : 0ull;
         for (int o = 32; o > 0; o >>= 1) spent += __shfl_xor(spent, o);
     }
-    __syncthreads();            // the episode slots are free
+    __syncthreads();            // the episode slots are free; held representatives are complete
+    if (A.local && A.gst_bits) {
+        const uint32_t held = S.tmp[38];
+        if (held) {
+            if (threadIdx.x == 0) {
+                const unsigned long long base = atomicAdd(A.log_count, (unsigned long long)held);
+                if (base + held > A.log_cap) atomicOr(A.flags, FLAG_LOG_OVERFLOW);
+                S.tmp[33] = (uint32_t)base;
+                S.tmp[34] = (uint32_t)(base >> 32);
+            }
+            __syncthreads();
+            const unsigned long long base = (unsigned long long)S.tmp[33] | ((unsigned long long)S.tmp[34] << 32);
+            for (uint32_t j = threadIdx.x; j < held; j += blockDim.x)
+                if (base + j < A.log_cap) A.log[base + j] = S.repbuf[j];
+            __syncthreads();
+        }
+    }
     if (lane_id() == 0) {
         S.slots[8 * B.wave] = L.total;
         S.slots[8 * B.wave + 1] = (uint32_t)spent;
@@ -973,7 +1003,7 @@ __device__ __forceinline__ void finish_block(const InterpArgs &A, const BlockCtx
             instr += (unsigned long long)S.slots[8 * w + 1] | ((unsigned long long)S.slots[8 * w + 2] << 32);
         }
         if (recs) atomicAdd(&A.blk_recs[B.u->block_base + B.block], recs);
-        if (instr) atomicAdd(A.instructions, instr);
+        if (A.blk_instr) A.blk_instr[B.u->block_base + B.block] = (uint32_t)instr;
         if (epoch > __hip_atomic_load(A.max_epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
             atomicMax(A.max_epoch, epoch);
     }
@@ -1258,6 +1288,8 @@ __device__ __forceinline__ size_t carve_lds(uint8_t *smem, const InterpArgs &A, 
         off += (size_t)A.sh_words_max * 8;
         S.gst = (unsigned long long *)(smem + off);
         off += A.gst_bits ? ((size_t)8 << A.gst_bits) : 0;
+        S.repbuf = (uint64_t *)(smem + off);
+        off += A.gst_bits ? (size_t)REP_HOLD * 8 : 0;
     }
     S.slots = (uint32_t *)(smem + off);
     S.slots2 = S.slots + 16 * 8;

@@ -24,6 +24,11 @@ constexpr uint32_t N_SREGS = 24;
 constexpr uint32_t MAX_INSTR = 1u << 16;
 constexpr uint32_t MAX_THREADS = 1024;
 constexpr uint32_t MAX_SHMEM_WORDS = 16384;     // 64 KiB of simulated shared memory
+// Representative records a block holds in LDS (with the global shadow table)
+// before it reserves log space for them: one reservation per block in the
+// common case instead of one per epoch, since every block of a launch
+// reserves on the same counter.
+constexpr uint32_t REP_HOLD = 512;
 
 enum : uint32_t { F_DEADLOCK = 1, F_DIVERGENCE = 2, F_OOB = 3, F_FUEL = 4, F_ARITH = 5, F_ALLOC = 6 };
 
@@ -135,7 +140,7 @@ struct InterpArgs {
     uint32_t lrace_cap;
     uint32_t *lrace_count;
     uint32_t *blk_flags;        // racy blocks
-    unsigned long long *instructions;   // free run: thread-instructions executed (added to), or null
+    uint32_t *blk_instr;        // free run: thread-instructions executed, per block (stored), or null
     uint32_t gst_bits;          // local check: log2 slots of the global shadow table (0: stage and sort)
     uint32_t site_bits;         // log2 slots of `sites`
     SiteSlot *sites;            // lockstep replay for source sites, or null

@@ -116,7 +116,7 @@ struct Workspace {
     DBuf units, items, comp_off, comp_blocks, mask;
     DBuf snap, log, alt, rlog, ralt, fs, hist, part;
     DBuf faults, rfaults, races, lraces, rlraces, edges, blk_recs, rblk_recs, blk_flags, rflags, ctr, rctr;
-    DBuf longseg, covlist, rtable, ftable, downer, dflags;
+    DBuf longseg, covlist, rtable, ftable, downer, dflags, blk_instr;
     DevCounters *h_ctr = nullptr;   // pinned
     void *h_pin = nullptr;          // pinned staging of gathered device-to-host copies
     void *d_pin = nullptr;          // its device mapping
@@ -151,7 +151,8 @@ struct Workspace {
     ~Workspace() {
         DBuf *all[] = {&units, &items, &comp_off, &comp_blocks, &mask, &snap, &log, &alt, &rlog,
                        &ralt, &fs, &hist, &part, &faults, &rfaults, &races, &edges, &blk_recs,
-                       &rblk_recs, &blk_flags, &rflags, &ctr, &rctr, &lraces, &rlraces, &longseg, &covlist};
+                       &rblk_recs, &blk_flags, &rflags, &ctr, &rctr, &lraces, &rlraces, &longseg, &covlist,
+                       &rtable, &ftable, &downer, &dflags, &blk_instr};
         for (auto *b : all) b->release();
         if (h_ctr) (void)hipHostFree(h_ctr);
         if (h_pin) (void)hipHostFree(h_pin);
@@ -596,7 +597,7 @@ struct Stage {
         a.lrace_cap = lrace_cap_;
         a.lrace_count = &ctr.as<DevCounters>()->race_count;
         a.blk_flags = flags.as<uint32_t>();
-        a.instructions = lockstep ? nullptr : &ctr.as<DevCounters>()->instructions;
+        a.blk_instr = lockstep ? nullptr : ws.blk_instr.as<uint32_t>();
         // the global shadow table packs a location in 31 bits
         const bool gst = a.local && ctx->opt.shadow_global && kp.ab <= 31;
         if (lockstep) {
@@ -777,7 +778,9 @@ struct Stage {
         ctx->caps(fault_cap, lrace_cap);
         ws.blk_recs.reserve((size_t)total_blocks * 4);
         ws.blk_flags.reserve((size_t)total_blocks * 4);
+        ws.blk_instr.reserve((size_t)total_blocks * 4);
         DevCounters c{};
+        size_t i_instr = 0;
         Fetch fetch;
         bool table_queued = false;
         for (;;) {
@@ -798,6 +801,7 @@ struct Stage {
             fetch.add(ws.faults.p, (size_t)std::min(fault_cap, kSpec) * sizeof(DevFault));
             fetch.add(ws.lraces.p, (size_t)std::min(lrace_cap, kSpec) * sizeof(DevRace));
             if (table_queued) fetch.add(ws.rctr.p, sizeof(DevCounters));      // item 4
+            i_instr = fetch.add(ws.blk_instr.p, (size_t)total_blocks * 4);
             run_fetch(fetch);
             c = *fetched<DevCounters>(fetch, i_ctr);
             ctx->stat_add("interp_ms", tm.ms(0, 1));
@@ -825,7 +829,12 @@ struct Stage {
             HIPCHK(launch_copy_units(ws.units.as<DevUnit>(), n, max_words, false, nullptr, s));   // back to launch start
             ctx->stat_add("retries", 1);
         }
-        ctx->stat_add("instructions", (double)c.instructions);
+        {
+            const uint32_t *bi = fetched<uint32_t>(fetch, i_instr);
+            uint64_t instr = 0;
+            for (uint32_t b = 0; b < total_blocks; b++) instr += bi[b];
+            ctx->stat_add("instructions", (double)instr);
+        }
         if (check) ctx->note_log_records(c.log_count + c.log_count / 8);
         ctx->note_caps(c.fault_count + c.fault_count / 8, c.race_count + c.race_count / 8);
         used_epoch_bits = bits_for((uint64_t)c.max_epoch + 2);   // one more value: representative records
