@@ -217,10 +217,13 @@ typedef struct {
 
 /* Submit jobs as one batch; returns at once.  All jobs of the batch execute
  * together (one interpreter launch per block-size class and launch index,
- * one sort and one check over all of them).  The descriptor arrays are
- * copied; device memories stay owned by the caller and must not be touched
- * until kc_poll reports the batch done.  Errors: KC_E_INVAL, KC_E_BUDGET,
- * KC_E_NOMEM, KC_E_DEVICE. */
+ * one sort and one check over all of them).  The descriptor, stream,
+ * dependency and allocation arrays are copied; device memories stay owned by
+ * the caller and must not be touched until kc_poll reports the batch done.
+ * Errors: KC_E_INVAL (also for a dependency that does not point forward,
+ * more than 4096 launches in a job with streams or dependencies, n_deps
+ * without a dependency array, or an allocation outside the job's memory),
+ * KC_E_BUDGET, KC_E_NOMEM, KC_E_DEVICE. */
 kc_status kc_batch_submit(kc_ctx *ctx, const kc_job *jobs, uint32_t n_jobs, void *stream, uint64_t *ticket);
 
 /* Collect a batch.  With wait = 0 returns KC_E_PENDING (out untouched) while
