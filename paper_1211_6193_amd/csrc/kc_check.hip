@@ -463,35 +463,37 @@ __device__ __forceinline__ int64_t ltable_find(const LocTable &t, unsigned long 
 // block (one of them wins when several blocks store) and writes set its
 // written flag; plain stores, no atomics.
 __global__ void __launch_bounds__(WG) k_dtable_own(ReplayTableArgs a) {
-    const uint64_t i = (uint64_t)blockIdx.x * WG + threadIdx.x;
-    if (i >= n_records(a)) return;
+    const uint64_t n = n_records(a);
     const KeyPlan &k = a.kp;
-    const uint64_t r = a.rs[i];
-    if (rec_field(r, k.s_sp, 1) != 1u || rec_field(r, k.s_ep, k.eb) != k.ep_rep) {
-        need_sort(a.ctr);
-        return;
+    for (uint64_t i = (uint64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (uint64_t)gridDim.x * WG) {
+        const uint64_t r = a.rs[i];
+        if (rec_field(r, k.s_sp, 1) != 1u || rec_field(r, k.s_ep, k.eb) != k.ep_rep) {
+            need_sort(a.ctr);
+            continue;
+        }
+        const DevUnit &u = a.units[rec_field(r, k.s_unit, k.ub)];
+        const uint64_t w = (uint64_t)(u.snap - a.snap_base) + rec_field(r, k.s_addr, k.ab);
+        a.downer[w] = u.block_base + rec_field(r, k.s_blk, k.bb) + 1u;
+        if (r & 1ull) a.dflags[w] = 1;
     }
-    const DevUnit &u = a.units[rec_field(r, k.s_unit, k.ub)];
-    const uint64_t w = (uint64_t)(u.snap - a.snap_base) + rec_field(r, k.s_addr, k.ab);
-    a.downer[w] = u.block_base + rec_field(r, k.s_blk, k.bb) + 1u;
-    if (r & 1ull) a.dflags[w] = 1;
 }
 
 // Second pass: a record whose block lost the word to another block marks the
 // word as touched by several blocks; with a write among them that is a
 // cross-block conflict.  (Every such word has a record that lost.)
 __global__ void __launch_bounds__(WG) k_dtable_multi(ReplayTableArgs a) {
-    const uint64_t i = (uint64_t)blockIdx.x * WG + threadIdx.x;
-    if (i >= n_records(a)) return;
+    const uint64_t n = n_records(a);
     const KeyPlan &k = a.kp;
-    const uint64_t r = a.rs[i];
-    if (rec_field(r, k.s_sp, 1) != 1u || rec_field(r, k.s_ep, k.eb) != k.ep_rep) return;
-    const DevUnit &u = a.units[rec_field(r, k.s_unit, k.ub)];
-    const uint64_t w = (uint64_t)(u.snap - a.snap_base) + rec_field(r, k.s_addr, k.ab);
-    if (a.downer[w] == u.block_base + rec_field(r, k.s_blk, k.bb) + 1u) return;
-    const uint8_t f = a.dflags[w];
-    a.dflags[w] = f | 2;        // every such store writes the same value
-    if (f & 1) need_sort(a.ctr);
+    for (uint64_t i = (uint64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (uint64_t)gridDim.x * WG) {
+        const uint64_t r = a.rs[i];
+        if (rec_field(r, k.s_sp, 1) != 1u || rec_field(r, k.s_ep, k.eb) != k.ep_rep) continue;
+        const DevUnit &u = a.units[rec_field(r, k.s_unit, k.ub)];
+        const uint64_t w = (uint64_t)(u.snap - a.snap_base) + rec_field(r, k.s_addr, k.ab);
+        if (a.downer[w] == u.block_base + rec_field(r, k.s_blk, k.bb) + 1u) continue;
+        const uint8_t f = a.dflags[w];
+        a.dflags[w] = f | 2;        // every such store writes the same value
+        if (f & 1) need_sort(a.ctr);
+    }
 }
 
 // Locations written by one block and touched by another.
@@ -583,6 +585,12 @@ __global__ void __launch_bounds__(WG) k_copy_units(const DevUnit *__restrict__ u
 
 __global__ void __launch_bounds__(WG) k_zero(uint32_t *__restrict__ p, size_t words) {
     for (size_t i = (size_t)blockIdx.x * WG + threadIdx.x; i < words; i += (size_t)gridDim.x * WG) p[i] = 0;
+}
+
+__global__ void __launch_bounds__(WG) k_zero_many(ZeroArgs z) {
+    for (uint32_t k = 0; k < z.n; k++)
+        for (size_t i = (size_t)blockIdx.x * WG + threadIdx.x; i < z.words[k]; i += (size_t)gridDim.x * WG)
+            z.p[k][i] = 0;
 }
 
 inline uint32_t blocks_for(uint64_t n) { return (uint32_t)((n + WG - 1) / WG); }
@@ -723,7 +731,8 @@ hipError_t launch_copy_units(const DevUnit *units, uint32_t n_units, uint32_t ma
 
 hipError_t launch_replay_table(const ReplayTableArgs &a, hipStream_t s) {
     if (a.n_rs == 0) return hipSuccess;
-    hipError_t e = launch_zero(a.table, (size_t)8 << a.bits, s);
+    ZeroArgs z{{(uint32_t *)a.table, (uint32_t *)a.ctr}, {(size_t)2 << a.bits, sizeof(DevCounters) / 4}, 2};
+    hipError_t e = launch_zero_many(z, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_rtable_insert, dim3(blocks_for(a.n_rs)), dim3(WG), 0, s, a);
     hipLaunchKernelGGL(k_rtable_check, dim3(blocks_for(1ull << a.bits)), dim3(WG), 0, s, a);
@@ -732,7 +741,8 @@ hipError_t launch_replay_table(const ReplayTableArgs &a, hipStream_t s) {
 
 hipError_t launch_log_table(const ReplayTableArgs &a, hipStream_t s) {
     if (a.n_rs == 0) return hipSuccess;
-    hipError_t e = launch_zero(a.table, (size_t)8 << a.bits, s);
+    ZeroArgs z{{(uint32_t *)a.table, (uint32_t *)a.ctr}, {(size_t)2 << a.bits, sizeof(DevCounters) / 4}, 2};
+    hipError_t e = launch_zero_many(z, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_rtable_insert, dim3(blocks_for(a.n_rs)), dim3(WG), 0, s, a);
     hipLaunchKernelGGL(k_rtable_conflicts, dim3(blocks_for(1ull << a.bits)), dim3(WG), 0, s, a);
@@ -741,11 +751,15 @@ hipError_t launch_log_table(const ReplayTableArgs &a, hipStream_t s) {
 
 hipError_t launch_log_direct(const ReplayTableArgs &a, uint64_t words, hipStream_t s) {
     if (a.n_rs == 0) return hipSuccess;
-    hipError_t e = launch_zero(a.downer, (size_t)words * 4, s);
-    if (e == hipSuccess) e = launch_zero(a.dflags, (size_t)((words + 3) / 4) * 4, s);
+    ZeroArgs z{{a.downer, (uint32_t *)a.dflags, (uint32_t *)a.ctr},
+               {(size_t)words, (size_t)(words + 3) / 4, sizeof(DevCounters) / 4}, 3};
+    hipError_t e = launch_zero_many(z, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_dtable_own, dim3(blocks_for(a.n_rs)), dim3(WG), 0, s, a);
-    hipLaunchKernelGGL(k_dtable_multi, dim3(blocks_for(a.n_rs)), dim3(WG), 0, s, a);
+    // the record count is read on the device: a strided grid sized for a
+    // fraction of the capacity
+    const uint32_t g = std::min<uint32_t>(blocks_for(a.n_rs), 2048);
+    hipLaunchKernelGGL(k_dtable_own, dim3(g), dim3(WG), 0, s, a);
+    hipLaunchKernelGGL(k_dtable_multi, dim3(g), dim3(WG), 0, s, a);
     return hipGetLastError();
 }
 
@@ -756,6 +770,16 @@ hipError_t launch_gather(const GatherArgs &a, hipStream_t s) {
     uint32_t g = (most + WG - 1) / WG;
     if (g > 256) g = 256;
     hipLaunchKernelGGL(k_gather, dim3(g), dim3(WG), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_many(const ZeroArgs &z, hipStream_t s) {
+    size_t most = 0;
+    for (uint32_t k = 0; k < z.n; k++) most = z.words[k] > most ? z.words[k] : most;
+    if (most == 0) return hipSuccess;
+    size_t g = (most + WG - 1) / WG;
+    if (g > 4096) g = 4096;
+    hipLaunchKernelGGL(k_zero_many, dim3((uint32_t)g), dim3(WG), 0, s, z);
     return hipGetLastError();
 }
 

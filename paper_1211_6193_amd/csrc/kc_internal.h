@@ -281,6 +281,13 @@ hipError_t launch_cross_launch(const uint32_t *si, const uint32_t *sj, uint64_t 
 hipError_t launch_copy_units(const DevUnit *units, uint32_t n_units, uint32_t max_words, bool to_snapshot,
                              const uint32_t *unit_mask, hipStream_t s);
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);
+// Zero up to 8 buffers (whole words) with one kernel launch.
+struct ZeroArgs {
+    uint32_t *p[8];
+    size_t words[8];
+    uint32_t n;
+};
+hipError_t launch_zero_many(const ZeroArgs &z, hipStream_t s);
 // Word copies of up to 8 device arrays into one destination (host-visible
 // pinned memory), at word offsets.
 struct GatherArgs {

@@ -401,7 +401,7 @@ struct Stage {
             return false;
         uint32_t bits = 10;
         while ((1ull << bits) < 2 * cap) bits++;
-        reset_counters(ws.rctr);
+        ws.rctr.reserve(sizeof(DevCounters));     // zeroed by the table launch
         ReplayTableArgs ta{};
         ta.rs = ws.log.as<uint64_t>();
         ta.n_rs = cap;
@@ -786,9 +786,10 @@ struct Stage {
         for (;;) {
             ws.faults.reserve((size_t)fault_cap * sizeof(DevFault));
             ws.lraces.reserve((size_t)lrace_cap * sizeof(DevRace));
-            reset_counters(ws.ctr);
-            HIPCHK(launch_zero(ws.blk_recs.p, (size_t)total_blocks * 4, s));
-            HIPCHK(launch_zero(ws.blk_flags.p, (size_t)total_blocks * 4, s));
+            ws.ctr.reserve(sizeof(DevCounters));
+            ZeroArgs z{{ws.ctr.as<uint32_t>(), ws.blk_recs.as<uint32_t>(), ws.blk_flags.as<uint32_t>()},
+                       {sizeof(DevCounters) / 4, (size_t)total_blocks, (size_t)total_blocks}, 3};
+            HIPCHK(launch_zero_many(z, s));
             tm.mark(0);
             interp(false, ws.log, log_cap, ws.ctr, ws.faults, fault_cap, ws.blk_recs, 0, ws.lraces, lrace_cap,
                    ws.blk_flags);
@@ -1010,12 +1011,16 @@ struct Stage {
         ws.rlog.reserve(rcap * 8);
         ws.rfaults.reserve((size_t)fcap * sizeof(DevFault));
         ws.rlraces.reserve((size_t)rlcap * sizeof(DevRace));
-        reset_counters(ws.rctr);
-        HIPCHK(launch_zero(ws.rblk_recs.p, (size_t)total_blocks * 4, s));
+        ws.rctr.reserve(sizeof(DevCounters));
+        {
+            ZeroArgs z{{ws.rctr.as<uint32_t>(), ws.rblk_recs.as<uint32_t>()},
+                       {sizeof(DevCounters) / 4, (size_t)total_blocks}, 2};
+            HIPCHK(launch_zero_many(z, s));
+        }
         interp(true, ws.rlog, rcap, ws.rctr, ws.rfaults, fcap, ws.rblk_recs, (uint32_t)comps.size(), ws.rlraces,
                rlcap, ws.rflags);
-        if (table) {            // the replay's exactness tables, queued behind it (flags in ws.ctr)
-            reset_counters(ws.ctr);
+        if (table) {            // the replay's exactness tables, queued behind it (flags in ws.ctr, zeroed there)
+            ws.ctr.reserve(sizeof(DevCounters));
             HIPCHK(launch_replay_table(*table, s));
         }
         Fetch f;
