@@ -100,7 +100,8 @@ void kc_ctx_destroy(kc_ctx *ctx);
 
 /* Options: "check" (1 = log and check, default; 0 = interpret only),
  * "fuel" (instructions per thread, default 1<<20), "timing" (1 = time the
- * stages with HIP events on the launch stream), "sort_tile" (keys per sort
+ * stages with HIP events on the launch stream; 2 = time only the free run,
+ * which records two events per stage instead of about six), "sort_tile" (keys per sort
  * tile: 1024, 2048 (default), 4096 or 8192), "log_records" (initial log capacity, >= 1024),
  * "stage" (interpreter staging granule per wave: 128, 256, 512 or 1024
  * records), "stage_bytes" (LDS bytes of per-block record staging, 8192 to

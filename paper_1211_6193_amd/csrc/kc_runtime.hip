@@ -339,17 +339,21 @@ struct HostTimer {
     ~HostTimer();
 };
 
+// Stage times from HIP events on the launch stream: level 1 times every
+// stage; level 2 only the free run (marks 0 and 1), since every recorded
+// event costs the stream a short pause.
 struct Timer {
     kc_ctx *ctx;
     Workspace &ws;
     hipStream_t s;
-    bool on;
+    int level;
     int idx = 0;
+    bool on(int i) const { return level == 1 || (level == 2 && (i == 0 || i == 1)); }
     void mark(int i) {
-        if (on) HIPCHK(hipEventRecord(ws.ev[i], s));
+        if (on(i)) HIPCHK(hipEventRecord(ws.ev[i], s));
     }
     double ms(int a, int b) {
-        if (!on) return 0.0;
+        if (!on(a) || !on(b)) return 0.0;
         float v = 0.f;
         HIPCHK(hipEventSynchronize(ws.ev[b]));
         HIPCHK(hipEventElapsedTime(&v, ws.ev[a], ws.ev[b]));
@@ -756,7 +760,7 @@ struct Stage {
         const uint32_t n = (uint32_t)hu.size();
         out.assign(n, UnitOut{});
         const bool check = ctx->opt.check != 0;
-        Timer tm{ctx, ws, s, ctx->opt.timing != 0};
+        Timer tm{ctx, ws, s, ctx->opt.timing};
 
         // snapshot buffer: each unit's memory at launch start
         if (check) {
@@ -1722,7 +1726,7 @@ kc_status kc_ctx_set_option(kc_ctx *ctx, const char *key, int64_t v) {
     std::string k(key);
     if (k == "check" && (v == 0 || v == 1)) ctx->opt.check = (int)v;
     else if (k == "fuel" && v >= 1 && v <= 0xFFFFFFFFll) ctx->opt.fuel = (uint32_t)v;
-    else if (k == "timing" && (v == 0 || v == 1)) ctx->opt.timing = (int)v;
+    else if (k == "timing" && v >= 0 && v <= 2) ctx->opt.timing = (int)v;
     else if (k == "sort_tile" && (v == 1024 || v == 2048 || v == 4096 || v == 8192)) ctx->opt.sort_tile = (uint32_t)v;
     else if (k == "log_records" && v >= 1024) ctx->opt.log_records = (uint64_t)v;
     else if (k == "stage" && (v == 128 || v == 256 || v == 512 || v == 1024)) ctx->opt.stage = (uint32_t)v;
