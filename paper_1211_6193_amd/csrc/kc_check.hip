@@ -646,6 +646,51 @@ __global__ void __launch_bounds__(WG) k_alloc_scan(AllocScanArgs a) {
     }
 }
 
+// Offsets of the blocks' held representatives in the log: an exclusive scan
+// of their counts (one workgroup) after the records counted so far.
+__global__ void __launch_bounds__(1024) k_held_scan(const uint32_t *__restrict__ held, uint64_t *__restrict__ off,
+                                                    uint32_t n, unsigned long long log_cap,
+                                                    unsigned long long *log_count, uint32_t *flags) {
+    __shared__ unsigned long long part[1024];
+    __shared__ unsigned long long base_s;
+    if (threadIdx.x == 0) base_s = *log_count;      // read before the last thread rewrites it
+    const uint32_t per = (n + blockDim.x - 1) / blockDim.x;
+    const uint32_t b0 = min(n, threadIdx.x * per), b1 = min(n, b0 + per);
+    unsigned long long mine = 0;
+    for (uint32_t b = b0; b < b1; b++) mine += held[b];
+    part[threadIdx.x] = mine;
+    __syncthreads();
+    for (uint32_t d = 1; d < blockDim.x; d <<= 1) {      // inclusive scan of the chunk sums
+        const unsigned long long v = threadIdx.x >= d ? part[threadIdx.x - d] : 0ull;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    const unsigned long long base = base_s;
+    unsigned long long at = base + part[threadIdx.x] - mine;
+    for (uint32_t b = b0; b < b1; b++) {
+        off[b] = at;
+        at += held[b];
+    }
+    if (threadIdx.x == blockDim.x - 1) {
+        const unsigned long long end = base + part[threadIdx.x];
+        *log_count = end;
+        if (end > log_cap) atomicOr(flags, FLAG_LOG_OVERFLOW);
+    }
+}
+
+__global__ void __launch_bounds__(WG) k_held_copy(const uint64_t *__restrict__ blk_log,
+                                                  const uint32_t *__restrict__ held,
+                                                  const uint64_t *__restrict__ off, uint32_t n, uint64_t *log,
+                                                  unsigned long long log_cap) {
+    for (uint32_t b = blockIdx.x; b < n; b += gridDim.x) {
+        const uint32_t cnt = held[b];
+        const uint64_t o = off[b];
+        for (uint32_t j = threadIdx.x; j < cnt; j += WG)
+            if (o + j < log_cap) log[o + j] = blk_log[(size_t)b * REP_HOLD + j];
+    }
+}
+
 // Races between an earlier launch (summary si) and a later one (sj) of a job
 // that may run in parallel: every word one writes and the other touches.
 __global__ void __launch_bounds__(WG) k_cross_launch(const uint32_t *__restrict__ si, const uint32_t *__restrict__ sj,
@@ -669,6 +714,18 @@ __global__ void __launch_bounds__(WG) k_cross_launch(const uint32_t *__restrict_
 hipError_t launch_summary(const SummaryArgs &a, hipStream_t s) {
     if (a.n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_summary, dim3((uint32_t)std::min<uint64_t>(blocks_for(a.n), 8192)), dim3(WG), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_held_compact(const uint64_t *blk_log, const uint32_t *blk_held, uint64_t *blk_off,
+                               uint32_t n_blocks, uint64_t *log, unsigned long long log_cap,
+                               unsigned long long *log_count, uint32_t *flags, hipStream_t s) {
+    if (n_blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_held_scan, dim3(1), dim3(1024), 0, s, blk_held, blk_off, n_blocks, log_cap, log_count, flags);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_held_copy, dim3(std::min<uint32_t>(n_blocks, 8192)), dim3(WG), 0, s, blk_log, blk_held,
+                       blk_off, n_blocks, log, log_cap);
     return hipGetLastError();
 }
 

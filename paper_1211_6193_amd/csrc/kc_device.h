@@ -973,7 +973,13 @@ __device__ __forceinline__ void finish_block(const InterpArgs &A, const BlockCtx
         for (int o = 32; o > 0; o >>= 1) spent += __shfl_xor(spent, o);
     }
     __syncthreads();            // the episode slots are free; held representatives are complete
-    if (A.local && A.gst_bits) {
+    if (A.local && A.gst_bits && A.blk_log) {          // to the block's own region, appended after the kernel
+        const uint32_t held = S.tmp[38];
+        const size_t gb = (size_t)B.u->block_base + B.block;
+        uint64_t *dst = A.blk_log + gb * REP_HOLD;
+        for (uint32_t j = threadIdx.x; j < held; j += blockDim.x) dst[j] = S.repbuf[j];
+        if (threadIdx.x == 0) A.blk_held[gb] = held;
+    } else if (A.local && A.gst_bits) {
         const uint32_t held = S.tmp[38];
         if (held) {
             if (threadIdx.x == 0) {

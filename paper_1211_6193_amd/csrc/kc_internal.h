@@ -144,6 +144,12 @@ struct InterpArgs {
     uint32_t gst_bits;          // local check: log2 slots of the global shadow table (0: stage and sort)
     uint32_t site_bits;         // log2 slots of `sites`
     SiteSlot *sites;            // lockstep replay for source sites, or null
+    // With the shadow table: when set, each block writes its held
+    // representatives to its own region (REP_HOLD records at block_base +
+    // block) and their number to blk_held, instead of reserving log space on
+    // the shared counter; launch_held_compact appends them to the log.
+    uint64_t *blk_log;
+    uint32_t *blk_held;
 };
 
 #ifndef __HIPCC_RTC__
@@ -273,6 +279,13 @@ struct AllocScanArgs {
     uint32_t *count;
 };
 hipError_t launch_alloc_scan(const AllocScanArgs &a, hipStream_t s);
+// Append the representatives the blocks of a free run held in their regions
+// (blk_log, blk_held; n_blocks blocks) to the log after the records already
+// counted in *log_count, and add them to it (FLAG_LOG_OVERFLOW in *flags
+// beyond log_cap).  blk_off: n_blocks scratch entries.
+hipError_t launch_held_compact(const uint64_t *blk_log, const uint32_t *blk_held, uint64_t *blk_off,
+                               uint32_t n_blocks, uint64_t *log, unsigned long long log_cap,
+                               unsigned long long *log_count, uint32_t *flags, hipStream_t s);
 // Races between launch `earlier` (summary si) and a later launch (sj) over
 // n_words words, appended to out (cap entries; *count counts them all) with
 // unit = tag.

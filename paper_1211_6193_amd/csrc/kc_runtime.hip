@@ -116,7 +116,7 @@ struct Workspace {
     DBuf units, items, comp_off, comp_blocks, mask;
     DBuf snap, log, alt, rlog, ralt, fs, hist, part;
     DBuf faults, rfaults, races, lraces, rlraces, edges, blk_recs, rblk_recs, blk_flags, rflags, ctr, rctr;
-    DBuf longseg, covlist, rtable, ftable, downer, dflags, blk_instr;
+    DBuf longseg, covlist, rtable, ftable, downer, dflags, blk_instr, blk_log, blk_held, blk_off;
     DevCounters *h_ctr = nullptr;   // pinned
     void *h_pin = nullptr;          // pinned staging of gathered device-to-host copies
     void *d_pin = nullptr;          // its device mapping
@@ -152,7 +152,7 @@ struct Workspace {
         DBuf *all[] = {&units, &items, &comp_off, &comp_blocks, &mask, &snap, &log, &alt, &rlog,
                        &ralt, &fs, &hist, &part, &faults, &rfaults, &races, &edges, &blk_recs,
                        &rblk_recs, &blk_flags, &rflags, &ctr, &rctr, &lraces, &rlraces, &longseg, &covlist,
-                       &rtable, &ftable, &downer, &dflags, &blk_instr};
+                       &rtable, &ftable, &downer, &dflags, &blk_instr, &blk_log, &blk_held, &blk_off};
         for (auto *b : all) b->release();
         if (h_ctr) (void)hipHostFree(h_ctr);
         if (h_pin) (void)hipHostFree(h_pin);
@@ -449,6 +449,7 @@ struct Stage {
     std::vector<std::vector<uint2>> replayed;   // the components the replay ran (whole units: skip_masked)
     SiteSlot *site_table = nullptr;             // set during the source-site replay
     uint32_t site_bits = 0;
+    bool held_regions = false;      // free run: held representatives in per-block regions
     bool log_sorted = false;        // the free-run log was sorted for its check
     uint32_t ftable_bits = 0;       // else: log2 slots of its location table (ws.ftable),
     bool direct_tables = false;     // or its direct word tables (ws.downer, ws.dflags)
@@ -602,6 +603,8 @@ struct Stage {
         a.lrace_count = &ctr.as<DevCounters>()->race_count;
         a.blk_flags = flags.as<uint32_t>();
         a.blk_instr = lockstep ? nullptr : ws.blk_instr.as<uint32_t>();
+        a.blk_log = (!lockstep && held_regions) ? ws.blk_log.as<uint64_t>() : nullptr;
+        a.blk_held = (!lockstep && held_regions) ? ws.blk_held.as<uint32_t>() : nullptr;
         // the global shadow table packs a location in 31 bits
         const bool gst = a.local && ctx->opt.shadow_global && kp.ab <= 31;
         if (lockstep) {
@@ -783,6 +786,15 @@ struct Stage {
         ws.blk_recs.reserve((size_t)total_blocks * 4);
         ws.blk_flags.reserve((size_t)total_blocks * 4);
         ws.blk_instr.reserve((size_t)total_blocks * 4);
+        // held representatives go to per-block regions (no queue on the log
+        // counter at the end of every block) while the regions stay small
+        held_regions = check && ctx->opt.local && ctx->opt.shadow_global && kp.ab <= 31 &&
+                       (uint64_t)total_blocks * REP_HOLD * 8 <= (256ull << 20);
+        if (held_regions) {
+            ws.blk_log.reserve((size_t)total_blocks * REP_HOLD * 8);
+            ws.blk_held.reserve((size_t)total_blocks * 4);
+            ws.blk_off.reserve((size_t)total_blocks * 8);
+        }
         DevCounters c{};
         size_t i_instr = 0;
         Fetch fetch;
@@ -791,13 +803,22 @@ struct Stage {
             ws.faults.reserve((size_t)fault_cap * sizeof(DevFault));
             ws.lraces.reserve((size_t)lrace_cap * sizeof(DevRace));
             ws.ctr.reserve(sizeof(DevCounters));
-            ZeroArgs z{{ws.ctr.as<uint32_t>(), ws.blk_recs.as<uint32_t>(), ws.blk_flags.as<uint32_t>()},
-                       {sizeof(DevCounters) / 4, (size_t)total_blocks, (size_t)total_blocks}, 3};
+            // held counts start at zero: a block run without the shadow table leaves its own alone
+            ZeroArgs z{{ws.ctr.as<uint32_t>(), ws.blk_recs.as<uint32_t>(), ws.blk_flags.as<uint32_t>(),
+                        held_regions ? ws.blk_held.as<uint32_t>() : nullptr},
+                       {sizeof(DevCounters) / 4, (size_t)total_blocks, (size_t)total_blocks,
+                        held_regions ? (size_t)total_blocks : 0},
+                       4};
             HIPCHK(launch_zero_many(z, s));
             tm.mark(0);
             interp(false, ws.log, log_cap, ws.ctr, ws.faults, fault_cap, ws.blk_recs, 0, ws.lraces, lrace_cap,
                    ws.blk_flags);
             tm.mark(1);
+            if (held_regions)
+                HIPCHK(launch_held_compact(ws.blk_log.as<uint64_t>(), ws.blk_held.as<uint32_t>(),
+                                           ws.blk_off.as<uint64_t>(), total_blocks, ws.log.as<uint64_t>(), log_cap,
+                                           &ws.ctr.as<DevCounters>()->log_count,
+                                           &ws.ctr.as<DevCounters>()->flags, s));
             table_queued = check && queue_log_check(log_cap);
             tm.mark(12);
             fetch = Fetch{};
