@@ -143,7 +143,8 @@ struct Workspace {
     size_t device_bytes() const {
         const DBuf *all[] = {&units, &items, &comp_off, &comp_blocks, &mask, &snap, &log, &alt, &rlog,
                              &ralt, &fs, &hist, &part, &faults, &rfaults, &races, &edges, &blk_recs,
-                             &rblk_recs, &blk_flags, &rflags, &ctr, &rctr, &lraces, &rlraces, &longseg, &covlist};
+                             &rblk_recs, &blk_flags, &rflags, &ctr, &rctr, &lraces, &rlraces, &longseg, &covlist,
+                             &rtable, &ftable, &downer, &dflags, &blk_instr, &blk_log, &blk_held, &blk_off};
         size_t s = 0;
         for (auto *b : all) s += b->bytes;
         return s;
