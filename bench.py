@@ -52,7 +52,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the checker's "
-              f"multi-GPU sharding is a design note, not part of this build)", file=sys.stderr)
+              f"sharding of the checker over several GPUs is described, not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
