@@ -51,8 +51,8 @@ def main():
                          "HBM counter readings) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the checker's "
-              f"sharding of the checker over several GPUs is described, not implemented)", file=sys.stderr)
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (sharding the checker "
+              f"over several GPUs is described, not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
