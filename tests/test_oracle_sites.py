@@ -1,9 +1,9 @@
 """Pin the source sites of race tuples (w_pc: the smallest pc of the writer's
 stores to the location, o_pc: the smallest pc of the other thread's accesses
-to it).  The paper's tool reports the racy variant of Figure 1 (the barrier
-of line 14 removed) as a possible race on shared memory detected at line 17
-of sum.cu (Section 3.2): thread 0's read of shared[i] in the serial loop,
-against the stores of line 12.  The recomputation of the sites from the
+to it).  For the racy variant of Figure 1 (the barrier of line 14 removed)
+the paper's tool names line 17 of the figure as the place of the race
+(Section 3.2): thread 0's read of shared[i] in the serial loop, against the
+stores of line 12.  The recomputation of the sites from the
 oracle's records is in test_oracle_faults.py."""
 from oracle import oracle as O
 from paper_1211_6193_amd import workloads as W
