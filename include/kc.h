@@ -19,9 +19,13 @@
  *     findings, not errors: a run with findings returns KC_OK and a
  *     non-empty report.  On an error kc_last_error() describes it.
  *   - KC_E_DEVICE means a HIP call failed; the context is then poisoned and
- *     every later call on it returns KC_E_DEVICE.
- *   - A context is not thread-safe, except that kc_poll may be called for
- *     different tickets from different threads.
+ *     every later call on it returns KC_E_DEVICE.  KC_E_INTERNAL (an
+ *     unexpected failure inside the library) poisons it too.  No C++
+ *     exception ever leaves an entry point or a batch's worker thread.
+ *   - A context is not thread-safe, except that kc_poll may be called from
+ *     several threads (each ticket is handed over once), and that
+ *     kc_ctx_set_option and kc_ctx_get_stat may be called while batches
+ *     run: a call uses the options as they were when it started.
  *
  * Instruction format (KC-IR v1): one 64-bit word per instruction,
  *   op = bits 0..7, d = 8..15, a = 16..23, b = 24..31, imm = 32..63 (int32).
@@ -74,7 +78,8 @@ typedef enum {
     KC_E_DEVICE = 4,    /* a HIP call failed; the context is poisoned */
     KC_E_PENDING = 5,   /* kc_poll without wait: the batch is still running */
     KC_E_BUDGET = 6,    /* the job can never fit in the context's HBM budget */
-    KC_E_OVERFLOW = 7   /* a record field cannot hold the launch's ids */
+    KC_E_OVERFLOW = 7,  /* a record field cannot hold the launch's ids */
+    KC_E_INTERNAL = 8   /* an unexpected internal failure of the library; the context is poisoned */
 } kc_status;
 
 typedef struct kc_ctx kc_ctx;
@@ -224,13 +229,17 @@ typedef struct {
  * Errors: KC_E_INVAL (also for a dependency that does not point forward,
  * more than 4096 launches in a job with streams or dependencies, n_deps
  * without a dependency array, or an allocation outside the job's memory),
- * KC_E_BUDGET, KC_E_NOMEM, KC_E_DEVICE. */
+ * KC_E_NOMEM (also when the batch's worker thread cannot be started),
+ * KC_E_DEVICE.  Errors of the run itself come back from kc_poll. */
 kc_status kc_batch_submit(kc_ctx *ctx, const kc_job *jobs, uint32_t n_jobs, void *stream, uint64_t *ticket);
 
 /* Collect a batch.  With wait = 0 returns KC_E_PENDING (out untouched) while
  * it runs.  On KC_OK `out` (n_out >= n_jobs pointers) receives one report per
  * job in submission order, each owned by the caller; the ticket is retired.
- * Errors: KC_E_INVAL (unknown ticket, n_out too small), KC_E_DEVICE. */
+ * A failed batch retires its ticket with the batch's status.
+ * Errors: KC_E_INVAL (unknown or already collected ticket, n_out too small:
+ * the ticket stays valid), the batch's own error (KC_E_NOMEM, KC_E_BUDGET,
+ * KC_E_OVERFLOW, KC_E_DEVICE, KC_E_INTERNAL). */
 kc_status kc_poll(kc_ctx *ctx, uint64_t ticket, int wait, kc_report **out, uint32_t n_out);
 
 /* ---- reports -------------------------------------------------------------------- */

@@ -3,6 +3,8 @@
 // kc_device.h.
 #include "kc_device.h"
 
+#include <mutex>
+
 namespace kc {
 
 namespace {
@@ -21,6 +23,30 @@ __global__ void __launch_bounds__(1024) k_interp_lockstep_local(InterpArgs A) { 
 __global__ void __launch_bounds__(1024) k_interp_lockstep_sites(InterpArgs A) { interp_lockstep_sites_body(A); }
 
 }  // namespace
+
+// Raise the dynamic LDS limit of the interpreter kernels to 160 KiB, once per
+// device: batch worker threads may launch for the first time together.
+static hipError_t raise_lds_limits() {
+    constexpr int kMaxDevices = 64;
+    static std::once_flag once[kMaxDevices];
+    static hipError_t result[kMaxDevices];
+    int dev = 0;
+    const hipError_t eg = hipGetDevice(&dev);
+    if (eg != hipSuccess) return eg;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::call_once(once[dev], [dev] {
+        const void *kernels[] = {(const void *)k_interp_free, (const void *)k_interp_free_local,
+                                 (const void *)k_interp_lockstep, (const void *)k_interp_lockstep_local,
+                                 (const void *)k_interp_lockstep_sites};
+        hipError_t e = hipSuccess;
+        for (const void *k : kernels) {
+            const hipError_t ek = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+            if (e == hipSuccess) e = ek;
+        }
+        result[dev] = e;
+    });
+    return result[dev];
+}
 
 uint32_t gst_bits_for(uint32_t wg_threads) {
     uint32_t b = 8;
@@ -62,25 +88,8 @@ hipError_t launch_interp(const InterpArgs &a, uint32_t n_wg, uint32_t wg_threads
         lds = bytes();
     }
     if (lds > 160 * 1024) return hipErrorInvalidValue;
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e1 = hipFuncSetAttribute((const void *)k_interp_free,
-                                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        hipError_t e0 = hipFuncSetAttribute((const void *)k_interp_free_local,
-                                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        if (e0 != hipSuccess) return e0;
-        hipError_t e2 = hipFuncSetAttribute((const void *)k_interp_lockstep,
-                                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        hipError_t e3 = hipFuncSetAttribute((const void *)k_interp_lockstep_local,
-                                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        hipError_t e4 = hipFuncSetAttribute((const void *)k_interp_lockstep_sites,
-                                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        if (e3 != hipSuccess) return e3;
-        if (e1 != hipSuccess) return e1;
-        if (e2 != hipSuccess) return e2;
-        if (e4 != hipSuccess) return e4;
-        attr_set = true;
-    }
+    const hipError_t ea = raise_lds_limits();
+    if (ea != hipSuccess) return ea;
     if (lockstep && args.sites)
         hipLaunchKernelGGL(k_interp_lockstep_sites, dim3(n_wg), dim3(wg_threads), lds, s, args);
     else if (lockstep && args.local)

@@ -420,7 +420,24 @@ Globals &G() {
 
 }  // namespace
 
+static void jit_compile_body(const std::shared_ptr<JitEntry> &e);
+
+// Compile an entry claimed with jit_claim.  Never throws: a failure of any
+// kind leaves the entry failed (state -1) and wakes its waiters.
 void jit_compile(const std::shared_ptr<JitEntry> &e) {
+    try {
+        jit_compile_body(e);
+    } catch (...) {
+        {
+            std::lock_guard<std::mutex> lk(e->mu);
+            e->state = -1;
+            e->log = "compilation of the specialised kernels failed (host exception)";
+        }
+        e->cv.notify_all();
+    }
+}
+
+static void jit_compile_body(const std::shared_ptr<JitEntry> &e) {
     const auto t0 = std::chrono::steady_clock::now();
     const std::string src = jit_source((const uint64_t *)e->words.data(), (uint32_t)(e->words.size() / 8), e->waves);
     std::vector<char> code;

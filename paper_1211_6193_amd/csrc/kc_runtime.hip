@@ -30,6 +30,7 @@
 #include <mutex>
 #include <numeric>
 #include <string>
+#include <system_error>
 #include <thread>
 #include <tuple>
 #include <unordered_map>
@@ -202,7 +203,7 @@ struct kc_ctx {
     uint64_t budget = 0;
     Options opt;
     std::string err;
-    bool poisoned = false;
+    std::atomic<bool> poisoned{false};
     std::mutex mu;
     std::vector<std::unique_ptr<Workspace>> free_ws;
     std::unordered_map<std::string, double> stats;
@@ -224,6 +225,12 @@ struct kc_ctx {
     uint64_t log_hint() {
         std::lock_guard<std::mutex> g(mu);
         return opt.log_records;
+    }
+    // A copy of the options for one call: kc_ctx_set_option may run while a
+    // batch works.
+    Options options() {
+        std::lock_guard<std::mutex> g(mu);
+        return opt;
     }
     void note_log_records(uint64_t n) {
         std::lock_guard<std::mutex> g(mu);
@@ -260,9 +267,18 @@ struct Batch {
     std::vector<std::vector<kc_region>> allocs;
     hipStream_t stream = nullptr;
     std::thread worker;
+    std::once_flag joined;
     std::mutex mu;
     std::condition_variable cv;
     bool done = false;
+    bool collected = false;         // a kc_poll took the reports (under mu)
+    // Join the worker exactly once, whichever of kc_poll and kc_ctx_destroy
+    // gets here first (joining a thread twice throws).
+    void join() {
+        std::call_once(joined, [this] {
+            if (worker.joinable()) worker.join();
+        });
+    }
     kc_status status = KC_OK;
     std::string err;
     std::vector<kc_report *> reports;
@@ -375,6 +391,7 @@ struct Stage {
     hipStream_t s;
     const std::vector<UnitIn> &in;
     std::vector<UnitOut> &out;
+    const Options &opt;     // the options as they were when the call began
 
     std::vector<DevUnit> hu;
     KeyPlan kp{};
@@ -402,7 +419,7 @@ struct Stage {
         // representatives exist only with the epoch-local check; a very long
         // log would spend more on its table than on the sort
         const bool direct = total_words <= 4 * cap + (1u << 16);
-        if (!(ctx->opt.hash_check && ctx->opt.local && cap <= (1ull << 24) && (direct || table_obits() != 0)))
+        if (!(opt.hash_check && opt.local && cap <= (1ull << 24) && (direct || table_obits() != 0)))
             return false;
         uint32_t bits = 10;
         while ((1ull << bits) < 2 * cap) bits++;
@@ -534,7 +551,7 @@ struct Stage {
             u.nt = d->block.x * d->block.y * d->block.z;
             u.nb = d->grid.x * d->grid.y * d->grid.z;
             u.sh_words = d->shmem_bytes / 4;
-            u.fuel = ctx->opt.fuel;
+            u.fuel = opt.fuel;
             for (uint32_t p = 0; p < 8; p++) u.params[p] = p < d->n_params ? d->params[p] : 0;
             u.block_base = total_blocks;
             total_blocks += u.nb;
@@ -568,7 +585,7 @@ struct Stage {
     // (staging + the epoch-local sort's second buffer), a multiple of 64.
     uint32_t stage_for(uint32_t wg_threads) const {
         const uint32_t nw = (wg_threads + 63) / 64;
-        uint32_t st = (uint32_t)(ctx->opt.stage_bytes / (nw * 16u)) / 64u * 64u;
+        uint32_t st = (uint32_t)(opt.stage_bytes / (nw * 16u)) / 64u * 64u;
         return std::max<uint32_t>(64u, std::min<uint32_t>(st, 2048u));
     }
 
@@ -597,8 +614,8 @@ struct Stage {
         a.blk_recs = recs.as<uint32_t>();
         a.flags = &ctr.as<DevCounters>()->flags;
         a.max_epoch = &ctr.as<DevCounters>()->max_epoch;
-        a.stage = ctx->opt.stage;
-        a.local = (ctx->opt.check && ctx->opt.local) ? 1u : 0u;
+        a.stage = opt.stage;
+        a.local = (opt.check && opt.local) ? 1u : 0u;
         a.lraces = lrace_buf.as<DevRace>();
         a.lrace_cap = lrace_cap_;
         a.lrace_count = &ctr.as<DevCounters>()->race_count;
@@ -607,9 +624,9 @@ struct Stage {
         a.blk_log = (!lockstep && held_regions) ? ws.blk_log.as<uint64_t>() : nullptr;
         a.blk_held = (!lockstep && held_regions) ? ws.blk_held.as<uint32_t>() : nullptr;
         // the global shadow table packs a location in 31 bits
-        const bool gst = a.local && ctx->opt.shadow_global && kp.ab <= 31;
+        const bool gst = a.local && opt.shadow_global && kp.ab <= 31;
         if (lockstep) {
-            a.stage = ctx->opt.stage;
+            a.stage = opt.stage;
             uint32_t wg = 64, shmax = 0;
             for (auto &u : hu) {
                 wg = std::max<uint32_t>(wg, (u.nt + 63) / 64 * 64);
@@ -644,7 +661,7 @@ struct Stage {
         // free run: one launch per (workgroup size, kernel) class; a unit whose
         // program has compiled specialised kernels runs those, the rest the
         // interpreter
-        if (ctx->opt.jit) jit_prepare();
+        if (opt.jit) jit_prepare();
         std::vector<JitFunctions> jf(hu.size());
         std::vector<char> use_jit(hu.size(), 0);
         for (uint32_t i = 0; i < hu.size(); i++) use_jit[i] = jit_for(i, jf[i]) ? 1 : 0;
@@ -723,7 +740,11 @@ struct Stage {
         };
         const size_t nt = std::min<size_t>(todo.size(), std::max(1u, std::min(8u, std::thread::hardware_concurrency())));
         std::vector<std::thread> th;
-        for (size_t t = 1; t < nt; t++) th.emplace_back(work);
+        try {
+            for (size_t t = 1; t < nt; t++) th.emplace_back(work);
+        } catch (...) {
+            // fewer helper threads: the ones started and this thread share the work
+        }
         work();
         for (auto &t : th) t.join();
         ctx->stat_add("jit_compiled", (double)todo.size());
@@ -733,7 +754,7 @@ struct Stage {
     std::shared_ptr<JitEntry> jit_entry(uint32_t i) {
         const kc_program *p = in[i].desc->prog;
         if (p->words.empty()) return nullptr;
-        const int w = ctx->opt.jit_waves;
+        const int w = opt.jit_waves;
         std::lock_guard<std::mutex> g(p->jit_mu);
         if (!p->jit[w]) p->jit[w] = jit_request(p->words.data(), (uint32_t)p->words.size(), w);
         return p->jit[w];
@@ -742,7 +763,7 @@ struct Stage {
     // Specialised kernels of unit i's program, if enabled, compiled and the
     // launch shape fits them.
     bool jit_for(uint32_t i, JitFunctions &f) {
-        if (!ctx->opt.jit) return false;
+        if (!opt.jit) return false;
         std::shared_ptr<JitEntry> e = jit_entry(i);
         if (!e) return false;
         if (!jit_fits(hu[i].sh_words, (hu[i].nt + 63) / 64 * 64)) return false;
@@ -756,15 +777,15 @@ struct Stage {
     }
 
     void run() {
-        HostTimer whole{ctx, "stage_host_ms", ctx->opt.timing != 0};
+        HostTimer whole{ctx, "stage_host_ms", opt.timing != 0};
         {
-            HostTimer ht{ctx, "host_plan_ms", ctx->opt.timing != 0};
+            HostTimer ht{ctx, "host_plan_ms", opt.timing != 0};
             plan();
         }
         const uint32_t n = (uint32_t)hu.size();
         out.assign(n, UnitOut{});
-        const bool check = ctx->opt.check != 0;
-        Timer tm{ctx, ws, s, ctx->opt.timing};
+        const bool check = opt.check != 0;
+        Timer tm{ctx, ws, s, opt.timing};
 
         // snapshot buffer: each unit's memory at launch start
         if (check) {
@@ -789,7 +810,7 @@ struct Stage {
         ws.blk_instr.reserve((size_t)total_blocks * 4);
         // held representatives go to per-block regions (no queue on the log
         // counter at the end of every block) while the regions stay small
-        held_regions = check && ctx->opt.local && ctx->opt.shadow_global && kp.ab <= 31 &&
+        held_regions = check && opt.local && opt.shadow_global && kp.ab <= 31 &&
                        (uint64_t)total_blocks * REP_HOLD * 8 <= (256ull << 20);
         if (held_regions) {
             ws.blk_log.reserve((size_t)total_blocks * REP_HOLD * 8);
@@ -914,7 +935,7 @@ struct Stage {
             }
         }
 
-        HostTimer post{ctx, "host_post_ms", ctx->opt.timing != 0};
+        HostTimer post{ctx, "host_post_ms", opt.timing != 0};
         // per-unit findings of the free run
         std::vector<std::vector<kc_fault>> ufaults(n);
         for (auto &f : faults) ufaults[f.unit].push_back(kc_fault{0, f.kind, f.block, f.epoch, f.a, f.b, f.c, f.d});
@@ -950,12 +971,12 @@ struct Stage {
         if (n <= 1) return res;
         SortScratch sc;
         alt.reserve(n * 8);
-        ws.hist.reserve(radix_hist_entries(n, ctx->opt.sort_tile) * 4);
+        ws.hist.reserve(radix_hist_entries(n, opt.sort_tile) * 4);
         ws.part.reserve(256 * 4);
         sc.alt = alt.as<uint64_t>();
         sc.hist = ws.hist.as<uint32_t>();
         sc.part = ws.part.as<uint32_t>();
-        HIPCHK(radix_sort(keys.as<uint64_t>(), n, check_key(), sc, ctx->opt.sort_tile, s, &res));
+        HIPCHK(radix_sort(keys.as<uint64_t>(), n, check_key(), sc, opt.sort_tile, s, &res));
         return res;
     }
 
@@ -1402,7 +1423,10 @@ struct Stage {
                 continue;
             }
             got.resize(n);
-            if (n) HIPCHK(hipMemcpy(got.data(), tmp.list.p, (size_t)n * 8, hipMemcpyDeviceToHost));
+            if (n) {
+                HIPCHK(hipMemcpyAsync(got.data(), tmp.list.p, (size_t)n * 8, hipMemcpyDeviceToHost, s));
+                HIPCHK(hipStreamSynchronize(s));
+            }
             break;
         }
         // smallest accessing and storing tid per (unit, block, word)
@@ -1428,10 +1452,40 @@ struct Stage {
 
 kc_status fail(kc_ctx *ctx, const KcError &e) {
     if (ctx) {
+        std::lock_guard<std::mutex> g(ctx->mu);
         ctx->err = e.msg;
-        if (e.st == KC_E_DEVICE) ctx->poisoned = true;
+        if (e.st == KC_E_DEVICE || e.st == KC_E_INTERNAL) ctx->poisoned = true;
     }
     return e.st;
+}
+
+// The status and message of the exception being handled.  Every exception
+// the library can raise maps to a status, so none reaches a C caller or ends
+// a worker thread (either would end the process in std::terminate).
+KcError current_error() {
+    try {
+        throw;
+    } catch (const KcError &e) {
+        return e;
+    } catch (const std::bad_alloc &) {
+        return KcError{KC_E_NOMEM, "host allocation failed"};
+    } catch (const std::system_error &e) {
+        // thread creation and mutex failures: the process is out of resources
+        return KcError{KC_E_NOMEM, std::string("system resource: ") + e.what()};
+    } catch (const std::exception &e) {
+        return KcError{KC_E_INTERNAL, std::string("internal error: ") + e.what()};
+    } catch (...) {
+        return KcError{KC_E_INTERNAL, "internal error: unknown exception"};
+    }
+}
+
+// Run an entry point's body; any exception becomes its status.
+template <class F> kc_status guarded(kc_ctx *ctx, F &&body) {
+    try {
+        return body();
+    } catch (...) {
+        return fail(ctx, current_error());
+    }
 }
 
 // Which launches of a job may run in parallel (Section 3 "Streams and
@@ -1534,7 +1588,10 @@ void cross_launch_check(kc_ctx *ctx, Workspace &ws, hipStream_t s, Stage &st, ui
             continue;
         }
         got.resize(n);
-        if (n) HIPCHK(hipMemcpy(got.data(), list.p, (size_t)n * sizeof(DevRace), hipMemcpyDeviceToHost));
+        if (n) {
+            HIPCHK(hipMemcpyAsync(got.data(), list.p, (size_t)n * sizeof(DevRace), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+        }
         break;
     }
     std::sort(got.begin(), got.end(), [](const DevRace &a, const DevRace &b) {
@@ -1548,6 +1605,7 @@ void cross_launch_check(kc_ctx *ctx, Workspace &ws, hipStream_t s, Stage &st, ui
 // jobs still running), and build one report per job.
 void run_jobs(kc_ctx *ctx, const kc_job *jobs, uint32_t n_jobs, hipStream_t s, std::vector<kc_report *> &reports) {
     HIPCHK(hipSetDevice(ctx->device));
+    const Options opt = ctx->options();
     auto wsp = ctx->acquire();
     Workspace &ws = *wsp;
     std::vector<std::vector<DBuf>> sums(n_jobs);
@@ -1571,9 +1629,9 @@ void run_jobs(kc_ctx *ctx, const kc_job *jobs, uint32_t n_jobs, hipStream_t s, s
             order.emplace_back(jobs[j]);
             streams |= order.back().any;
         }
-        streams &= ctx->opt.check != 0;
+        streams &= opt.check != 0;
         bool objects = false;
-        for (uint32_t j = 0; j < n_jobs && ctx->opt.check; j++) {
+        for (uint32_t j = 0; j < n_jobs && opt.check; j++) {
             if (!jobs[j].allocs) continue;
             std::vector<uint32_t> bits((jobs[j].n_words + 31) / 32 + 1, 0u);
             for (uint32_t a = 0; a < jobs[j].n_allocs; a++) {
@@ -1584,7 +1642,9 @@ void run_jobs(kc_ctx *ctx, const kc_job *jobs, uint32_t n_jobs, hipStream_t s, s
                 for (; x < end; x++) bits[x >> 5] |= 1u << (x & 31);
             }
             allocated[j].reserve(bits.size() * 4);
-            HIPCHK(hipMemcpy(allocated[j].p, bits.data(), bits.size() * 4, hipMemcpyHostToDevice));
+            // on the batch's stream (the null stream would not order it with it)
+            HIPCHK(hipMemcpyAsync(allocated[j].p, bits.data(), bits.size() * 4, hipMemcpyHostToDevice, s));
+            HIPCHK(hipStreamSynchronize(s));    // `bits` is freed at the end of the iteration
             objects = true;
         }
         std::vector<char> alive(n_jobs, 1);
@@ -1600,10 +1660,10 @@ void run_jobs(kc_ctx *ctx, const kc_job *jobs, uint32_t n_jobs, hipStream_t s, s
             }
             if (in.empty()) break;
             std::vector<UnitOut> out;
-            Stage st{ctx, ws, s, in, out};
+            Stage st{ctx, ws, s, in, out, opt};
             st.run();
             ctx->stat_add("launches", (double)in.size());
-            HostTimer ht{ctx, "host_reports_ms", ctx->opt.timing != 0};
+            HostTimer ht{ctx, "host_reports_ms", opt.timing != 0};
             std::vector<size_t> first_race(who.size());
             for (size_t i = 0; i < who.size(); i++) {
                 kc_report *r = reports[who[i]];
@@ -1626,7 +1686,8 @@ void run_jobs(kc_ctx *ctx, const kc_job *jobs, uint32_t n_jobs, hipStream_t s, s
                     dbm.reserve(bm.size() * sizeof(uint32_t *));
                     std::vector<std::vector<kc_fault>> found(who.size());
                     try {
-                        HIPCHK(hipMemcpy(dbm.p, bm.data(), bm.size() * sizeof(uint32_t *), hipMemcpyHostToDevice));
+                        HIPCHK(hipMemcpyAsync(dbm.p, bm.data(), bm.size() * sizeof(uint32_t *),
+                                              hipMemcpyHostToDevice, s));
                         st.illegal_accesses(dbm.as<const uint32_t *>(), found);
                     } catch (...) {
                         dbm.release();
@@ -1644,7 +1705,7 @@ void run_jobs(kc_ctx *ctx, const kc_job *jobs, uint32_t n_jobs, hipStream_t s, s
             }
             // last: it runs the replay again over the replay's log, which the
             // stream summaries and memory-object scans read
-            if (ctx->opt.sites && ctx->opt.check) {
+            if (opt.sites && opt.check) {
                 st.sites_pass(out);
                 for (size_t i = 0; i < who.size(); i++)
                     std::copy(out[i].sites.begin(), out[i].sites.end(),
@@ -1667,6 +1728,213 @@ void run_jobs(kc_ctx *ctx, const kc_job *jobs, uint32_t n_jobs, hipStream_t s, s
 // ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
+// Option writes and statistic reads, under the context lock (batch workers
+// read options and add statistics concurrently).
+static kc_status set_option_locked(kc_ctx *ctx, const char *key, int64_t v) {
+    const std::string k(key);
+    std::lock_guard<std::mutex> g(ctx->mu);
+    if (k == "check" && (v == 0 || v == 1)) ctx->opt.check = (int)v;
+    else if (k == "fuel" && v >= 1 && v <= 0xFFFFFFFFll) ctx->opt.fuel = (uint32_t)v;
+    else if (k == "timing" && v >= 0 && v <= 2) ctx->opt.timing = (int)v;
+    else if (k == "sort_tile" && (v == 1024 || v == 2048 || v == 4096 || v == 8192)) ctx->opt.sort_tile = (uint32_t)v;
+    else if (k == "log_records" && v >= 1024) ctx->opt.log_records = (uint64_t)v;
+    else if (k == "stage" && (v == 128 || v == 256 || v == 512 || v == 1024)) ctx->opt.stage = (uint32_t)v;
+    else if (k == "stage_bytes" && v >= 8192 && v <= 98304) ctx->opt.stage_bytes = (uint32_t)v;
+    else if (k == "local" && (v == 0 || v == 1)) ctx->opt.local = (int)v;
+    else if (k == "shadow_global" && (v == 0 || v == 1)) ctx->opt.shadow_global = (int)v;
+    else if (k == "hash_check" && (v == 0 || v == 1)) ctx->opt.hash_check = (int)v;
+    else if (k == "jit" && (v == 0 || v == 1)) ctx->opt.jit = (int)v;
+    else if (k == "jit_waves" && (v == 0 || (v >= 2 && v <= 8))) ctx->opt.jit_waves = (int)v;
+    else if (k == "sites" && (v == 0 || v == 1)) ctx->opt.sites = (int)v;
+    else if (k == "reset" && v == 1) {
+        ctx->stats.clear();
+    } else {
+        ctx->err = "unknown option or value: " + k;
+        return KC_E_INVAL;
+    }
+    return KC_OK;
+}
+
+static double get_stat_locked(kc_ctx *ctx, const char *key) {
+    std::lock_guard<std::mutex> g(ctx->mu);
+    const std::string k(key);
+    if (k.rfind("option.", 0) == 0) {
+        const std::string o = k.substr(7);
+        const Options &op = ctx->opt;
+        if (o == "check") return op.check;
+        if (o == "fuel") return op.fuel;
+        if (o == "timing") return op.timing;
+        if (o == "sort_tile") return op.sort_tile;
+        if (o == "log_records") return (double)op.log_records;
+        if (o == "stage") return op.stage;
+        if (o == "stage_bytes") return op.stage_bytes;
+        if (o == "local") return op.local;
+        if (o == "shadow_global") return op.shadow_global;
+        if (o == "hash_check") return op.hash_check;
+        if (o == "jit") return op.jit;
+        if (o == "jit_waves") return op.jit_waves;
+        if (o == "sites") return op.sites;
+        return 0.0;
+    }
+    auto it = ctx->stats.find(key);
+    return it == ctx->stats.end() ? 0.0 : it->second;
+}
+
+// kc_batch_submit's argument checks.
+static kc_status validate_jobs(kc_ctx *ctx, const kc_job *jobs, uint32_t n_jobs) {
+    for (uint32_t j = 0; j < n_jobs; j++) {
+        if (jobs[j].n_launches && !jobs[j].launches) {
+            ctx->err = "job without launch array";
+            return KC_E_INVAL;
+        }
+        for (uint32_t l = 0; l < jobs[j].n_launches; l++) {
+            std::string why = validate_desc(&jobs[j].launches[l], jobs[j].dev_mem, jobs[j].n_words);
+            if (!why.empty()) {
+                ctx->err = "job " + std::to_string(j) + " launch " + std::to_string(l) + ": " + why;
+                return KC_E_INVAL;
+            }
+        }
+        if (jobs[j].n_deps && !jobs[j].deps) {
+            ctx->err = "job " + std::to_string(j) + ": n_deps without a dependency array";
+            return KC_E_INVAL;
+        }
+        if ((jobs[j].streams || jobs[j].n_deps) && jobs[j].n_launches > kMaxStreamLaunches) {
+            ctx->err = "job " + std::to_string(j) + ": more than " + std::to_string(kMaxStreamLaunches) +
+                       " launches with streams";
+            return KC_E_INVAL;
+        }
+        for (uint32_t a = 0; jobs[j].allocs && a < jobs[j].n_allocs; a++) {
+            const kc_region &g = jobs[j].allocs[a];
+            if (g.base > jobs[j].n_words || g.words > jobs[j].n_words - g.base) {
+                ctx->err = "job " + std::to_string(j) + " allocation " + std::to_string(a) + ": outside the memory";
+                return KC_E_INVAL;
+            }
+        }
+        for (uint32_t d = 0; d < jobs[j].n_deps; d++) {
+            const kc_dep &e = jobs[j].deps[d];
+            if (e.before >= e.after || e.after >= jobs[j].n_launches) {
+                ctx->err = "job " + std::to_string(j) + " dependency " + std::to_string(d) +
+                           ": needs before < after < n_launches";
+                return KC_E_INVAL;
+            }
+        }
+    }
+    return KC_OK;
+}
+
+// The part of kc_batch_submit after validation: copy the batch and start its
+// worker thread.
+static kc_status submit_batch(kc_ctx *ctx, const kc_job *jobs, uint32_t n_jobs, void *stream, uint64_t *ticket) {
+    auto b = std::make_shared<Batch>();
+    b->jobs.assign(jobs, jobs + n_jobs);
+    b->descs.resize(n_jobs);
+    b->streams.resize(n_jobs);
+    b->deps.resize(n_jobs);
+    b->allocs.resize(n_jobs);
+    for (uint32_t j = 0; j < n_jobs; j++) {
+        b->descs[j].assign(jobs[j].launches, jobs[j].launches + jobs[j].n_launches);
+        b->jobs[j].launches = b->descs[j].data();
+        if (jobs[j].streams) {
+            b->streams[j].assign(jobs[j].streams, jobs[j].streams + jobs[j].n_launches);
+            b->jobs[j].streams = b->streams[j].data();
+        }
+        if (jobs[j].n_deps) {
+            b->deps[j].assign(jobs[j].deps, jobs[j].deps + jobs[j].n_deps);
+            b->jobs[j].deps = b->deps[j].data();
+        }
+        if (jobs[j].allocs) {
+            // one spare entry keeps the pointer non-null for an empty list
+            b->allocs[j].assign(jobs[j].allocs, jobs[j].allocs + jobs[j].n_allocs);
+            b->allocs[j].push_back(kc_region{0, 0});
+            b->jobs[j].allocs = b->allocs[j].data();
+        }
+    }
+    b->stream = (hipStream_t)stream;
+    uint64_t t;
+    {
+        std::lock_guard<std::mutex> g(ctx->mu);
+        t = ctx->next_ticket++;
+        ctx->batches[t] = b;
+    }
+    Batch *bp = b.get();
+    try {
+        bp->worker = std::thread([ctx, bp]() {
+            kc_status st = KC_OK;
+            std::string err;
+            std::vector<kc_report *> reps;
+            try {
+                run_jobs(ctx, bp->jobs.data(), (uint32_t)bp->jobs.size(), bp->stream, reps);
+            } catch (...) {
+                // nothing may leave the thread function: that would end the process
+                const KcError e = current_error();
+                st = e.st;
+                err = e.msg;
+            }
+            std::lock_guard<std::mutex> g(bp->mu);
+            bp->status = st;
+            bp->err = std::move(err);
+            bp->reports = std::move(reps);
+            bp->done = true;
+            bp->cv.notify_all();
+        });
+    } catch (...) {
+        std::lock_guard<std::mutex> g(ctx->mu);
+        ctx->batches.erase(t);
+        throw;
+    }
+    *ticket = t;
+    return KC_OK;
+}
+
+// kc_poll: wait for (or test) the batch, join its worker once, hand its
+// reports over once.
+static kc_status poll_batch(kc_ctx *ctx, uint64_t ticket, int wait, kc_report **out, uint32_t n_out) {
+    std::shared_ptr<Batch> b;
+    {
+        std::lock_guard<std::mutex> g(ctx->mu);
+        auto it = ctx->batches.find(ticket);
+        if (it == ctx->batches.end()) {
+            ctx->err = "unknown ticket";
+            return KC_E_INVAL;
+        }
+        b = it->second;
+    }
+    {
+        std::unique_lock<std::mutex> g(b->mu);
+        if (!b->done) {
+            if (!wait) return KC_E_PENDING;
+            b->cv.wait(g, [&] { return b->done; });
+        }
+    }
+    b->join();
+    std::vector<kc_report *> reps;
+    {
+        std::lock_guard<std::mutex> g(b->mu);
+        if (b->collected) {
+            std::lock_guard<std::mutex> gc(ctx->mu);
+            ctx->err = "ticket already collected";
+            return KC_E_INVAL;
+        }
+        if (b->status == KC_OK && (!out || n_out < b->reports.size())) {
+            std::lock_guard<std::mutex> gc(ctx->mu);
+            ctx->err = "output array too small";
+            return KC_E_INVAL;
+        }
+        b->collected = true;
+        reps = std::move(b->reports);
+        b->reports.clear();
+    }
+    std::lock_guard<std::mutex> g(ctx->mu);
+    ctx->batches.erase(ticket);
+    if (b->status != KC_OK) {
+        ctx->err = b->err;
+        if (b->status == KC_E_DEVICE || b->status == KC_E_INTERNAL) ctx->poisoned = true;
+        return b->status;
+    }
+    for (size_t i = 0; i < reps.size(); i++) out[i] = reps[i];
+    return KC_OK;
+}
+
 extern "C" {
 
 // Tuned launch parameters: a flat JSON object of integer options written by
@@ -1713,15 +1981,21 @@ kc_status kc_ctx_create(int hip_device, uint64_t hbm_budget_bytes, const char *t
         return KC_E_INVAL;
     }
     if (hipSetDevice(hip_device) != hipSuccess) return KC_E_DEVICE;
-    kc_ctx *c = new kc_ctx();
-    c->device = hip_device;
-    c->budget = hbm_budget_bytes;
-    if (tune_cache && *tune_cache) {
-        kc_status st = apply_tune_cache(c, tune_cache);
-        if (st != KC_OK) {
-            delete c;
-            return st;
+    kc_ctx *c = nullptr;
+    try {
+        c = new kc_ctx();
+        c->device = hip_device;
+        c->budget = hbm_budget_bytes;
+        if (tune_cache && *tune_cache) {
+            kc_status st = apply_tune_cache(c, tune_cache);
+            if (st != KC_OK) {
+                delete c;
+                return st;
+            }
         }
+    } catch (...) {
+        delete c;
+        return current_error().st;
     }
     *out = c;
     return KC_OK;
@@ -1735,8 +2009,15 @@ void kc_ctx_destroy(kc_ctx *ctx) {
         for (auto &kv : ctx->batches) pending.push_back(kv.second);
     }
     for (auto &b : pending) {
-        if (b->worker.joinable()) b->worker.join();
+        try {
+            b->join();
+        } catch (...) {
+            // joining failed (the worker cannot be waited for): the reports it
+            // may still write are leaked rather than freed under it
+            continue;
+        }
         for (auto *r : b->reports) delete r;
+        b->reports.clear();
     }
     (void)hipSetDevice(ctx->device);
     ctx->free_ws.clear();
@@ -1745,53 +2026,16 @@ void kc_ctx_destroy(kc_ctx *ctx) {
 
 kc_status kc_ctx_set_option(kc_ctx *ctx, const char *key, int64_t v) {
     if (!ctx || !key) return KC_E_INVAL;
-    std::string k(key);
-    if (k == "check" && (v == 0 || v == 1)) ctx->opt.check = (int)v;
-    else if (k == "fuel" && v >= 1 && v <= 0xFFFFFFFFll) ctx->opt.fuel = (uint32_t)v;
-    else if (k == "timing" && v >= 0 && v <= 2) ctx->opt.timing = (int)v;
-    else if (k == "sort_tile" && (v == 1024 || v == 2048 || v == 4096 || v == 8192)) ctx->opt.sort_tile = (uint32_t)v;
-    else if (k == "log_records" && v >= 1024) ctx->opt.log_records = (uint64_t)v;
-    else if (k == "stage" && (v == 128 || v == 256 || v == 512 || v == 1024)) ctx->opt.stage = (uint32_t)v;
-    else if (k == "stage_bytes" && v >= 8192 && v <= 98304) ctx->opt.stage_bytes = (uint32_t)v;
-    else if (k == "local" && (v == 0 || v == 1)) ctx->opt.local = (int)v;
-    else if (k == "shadow_global" && (v == 0 || v == 1)) ctx->opt.shadow_global = (int)v;
-    else if (k == "hash_check" && (v == 0 || v == 1)) ctx->opt.hash_check = (int)v;
-    else if (k == "jit" && (v == 0 || v == 1)) ctx->opt.jit = (int)v;
-    else if (k == "jit_waves" && (v == 0 || (v >= 2 && v <= 8))) ctx->opt.jit_waves = (int)v;
-    else if (k == "sites" && (v == 0 || v == 1)) ctx->opt.sites = (int)v;
-    else if (k == "reset" && v == 1) {
-        std::lock_guard<std::mutex> g(ctx->mu);
-        ctx->stats.clear();
-    } else {
-        ctx->err = "unknown option or value: " + k;
-        return KC_E_INVAL;
-    }
-    return KC_OK;
+    return guarded(ctx, [&] { return set_option_locked(ctx, key, v); });
 }
 
 double kc_ctx_get_stat(kc_ctx *ctx, const char *key) {
     if (!ctx || !key) return 0.0;
-    std::lock_guard<std::mutex> g(ctx->mu);
-    const std::string k(key);
-    if (k.rfind("option.", 0) == 0) {
-        const std::string o = k.substr(7);
-        const Options &op = ctx->opt;
-        if (o == "check") return op.check;
-        if (o == "fuel") return op.fuel;
-        if (o == "timing") return op.timing;
-        if (o == "sort_tile") return op.sort_tile;
-        if (o == "log_records") return (double)op.log_records;
-        if (o == "stage") return op.stage;
-        if (o == "stage_bytes") return op.stage_bytes;
-        if (o == "local") return op.local;
-        if (o == "shadow_global") return op.shadow_global;
-        if (o == "hash_check") return op.hash_check;
-        if (o == "jit") return op.jit;
-        if (o == "jit_waves") return op.jit_waves;
+    try {
+        return get_stat_locked(ctx, key);
+    } catch (...) {
         return 0.0;
     }
-    auto it = ctx->stats.find(key);
-    return it == ctx->stats.end() ? 0.0 : it->second;
 }
 
 const char *kc_last_error(const kc_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
@@ -1805,17 +2049,18 @@ kc_status kc_program_load(kc_ctx *ctx, const uint64_t *words, uint32_t n_words, 
         ctx->err = why;
         return KC_E_PROGRAM;
     }
-    auto *p = new kc_program();
-    p->words.assign(words, words + n_words);
-    p->device = ctx->device;
+    kc_program *p = nullptr;
     try {
+        p = new kc_program();
+        p->words.assign(words, words + n_words);
+        p->device = ctx->device;
         HIPCHK(hipSetDevice(ctx->device));
         HIPCHK(hipMalloc(&p->dev, (size_t)n_words * 8));
         HIPCHK(hipMemcpy(p->dev, words, (size_t)n_words * 8, hipMemcpyHostToDevice));
-    } catch (const KcError &e) {
-        if (p->dev) (void)hipFree(p->dev);
+    } catch (...) {
+        if (p && p->dev) (void)hipFree(p->dev);
         delete p;
-        return fail(ctx, e);
+        return fail(ctx, current_error());
     }
     *out = p;
     return KC_OK;
@@ -1840,151 +2085,27 @@ kc_status kc_launch(kc_ctx *ctx, const kc_launch_desc *desc, int32_t *dev_mem, u
         ctx->err = why;
         return KC_E_INVAL;
     }
-    kc_job job{desc, 1, dev_mem, n_words, 0};
-    std::vector<kc_report *> reps;
-    try {
+    return guarded(ctx, [&] {
+        kc_job job{desc, 1, dev_mem, n_words, 0};
+        std::vector<kc_report *> reps;
         run_jobs(ctx, &job, 1, (hipStream_t)stream, reps);
-    } catch (const KcError &e) {
-        return fail(ctx, e);
-    } catch (const std::bad_alloc &) {
-        return fail(ctx, KcError{KC_E_NOMEM, "host allocation failed"});
-    }
-    *out = reps[0];
-    return KC_OK;
+        *out = reps[0];
+        return KC_OK;
+    });
 }
 
 kc_status kc_batch_submit(kc_ctx *ctx, const kc_job *jobs, uint32_t n_jobs, void *stream, uint64_t *ticket) {
     if (!ctx || !ticket || (!jobs && n_jobs)) return KC_E_INVAL;
     if (ctx->poisoned) return KC_E_DEVICE;
-    for (uint32_t j = 0; j < n_jobs; j++) {
-        if (jobs[j].n_launches && !jobs[j].launches) {
-            ctx->err = "job without launch array";
-            return KC_E_INVAL;
-        }
-        for (uint32_t l = 0; l < jobs[j].n_launches; l++) {
-            std::string why = validate_desc(&jobs[j].launches[l], jobs[j].dev_mem, jobs[j].n_words);
-            if (!why.empty()) {
-                ctx->err = "job " + std::to_string(j) + " launch " + std::to_string(l) + ": " + why;
-                return KC_E_INVAL;
-            }
-        }
-        if (jobs[j].n_deps && !jobs[j].deps) {
-            ctx->err = "job " + std::to_string(j) + ": n_deps without a dependency array";
-            return KC_E_INVAL;
-        }
-        if ((jobs[j].streams || jobs[j].n_deps) && jobs[j].n_launches > kMaxStreamLaunches) {
-            ctx->err = "job " + std::to_string(j) + ": more than " + std::to_string(kMaxStreamLaunches) +
-                       " launches with streams";
-            return KC_E_INVAL;
-        }
-        for (uint32_t a = 0; jobs[j].allocs && a < jobs[j].n_allocs; a++) {
-            const kc_region &g = jobs[j].allocs[a];
-            if (g.base > jobs[j].n_words || g.words > jobs[j].n_words - g.base) {
-                ctx->err = "job " + std::to_string(j) + " allocation " + std::to_string(a) + ": outside the memory";
-                return KC_E_INVAL;
-            }
-        }
-        for (uint32_t d = 0; d < jobs[j].n_deps; d++) {
-            const kc_dep &e = jobs[j].deps[d];
-            if (e.before >= e.after || e.after >= jobs[j].n_launches) {
-                ctx->err = "job " + std::to_string(j) + " dependency " + std::to_string(d) +
-                           ": needs before < after < n_launches";
-                return KC_E_INVAL;
-            }
-        }
-    }
-    auto b = std::make_shared<Batch>();
-    b->jobs.assign(jobs, jobs + n_jobs);
-    b->descs.resize(n_jobs);
-    b->streams.resize(n_jobs);
-    b->deps.resize(n_jobs);
-    b->allocs.resize(n_jobs);
-    for (uint32_t j = 0; j < n_jobs; j++) {
-        b->descs[j].assign(jobs[j].launches, jobs[j].launches + jobs[j].n_launches);
-        b->jobs[j].launches = b->descs[j].data();
-        if (jobs[j].streams) {
-            b->streams[j].assign(jobs[j].streams, jobs[j].streams + jobs[j].n_launches);
-            b->jobs[j].streams = b->streams[j].data();
-        }
-        if (jobs[j].n_deps) {
-            b->deps[j].assign(jobs[j].deps, jobs[j].deps + jobs[j].n_deps);
-            b->jobs[j].deps = b->deps[j].data();
-        }
-        if (jobs[j].allocs) {
-            // one spare entry keeps the pointer non-null for an empty list
-            b->allocs[j].assign(jobs[j].allocs, jobs[j].allocs + jobs[j].n_allocs);
-            b->allocs[j].push_back(kc_region{0, 0});
-            b->jobs[j].allocs = b->allocs[j].data();
-        }
-    }
-    b->stream = (hipStream_t)stream;
-    uint64_t t;
-    {
-        std::lock_guard<std::mutex> g(ctx->mu);
-        t = ctx->next_ticket++;
-        ctx->batches[t] = b;
-    }
-    Batch *bp = b.get();
-    bp->worker = std::thread([ctx, bp]() {
-        kc_status st = KC_OK;
-        std::string err;
-        std::vector<kc_report *> reps;
-        try {
-            run_jobs(ctx, bp->jobs.data(), (uint32_t)bp->jobs.size(), bp->stream, reps);
-        } catch (const KcError &e) {
-            st = e.st;
-            err = e.msg;
-        } catch (const std::bad_alloc &) {
-            st = KC_E_NOMEM;
-            err = "host allocation failed";
-        }
-        std::lock_guard<std::mutex> g(bp->mu);
-        bp->status = st;
-        bp->err = err;
-        bp->reports = std::move(reps);
-        bp->done = true;
-        bp->cv.notify_all();
+    return guarded(ctx, [&] {
+        const kc_status st = validate_jobs(ctx, jobs, n_jobs);
+        return st != KC_OK ? st : submit_batch(ctx, jobs, n_jobs, stream, ticket);
     });
-    *ticket = t;
-    return KC_OK;
 }
 
 kc_status kc_poll(kc_ctx *ctx, uint64_t ticket, int wait, kc_report **out, uint32_t n_out) {
     if (!ctx) return KC_E_INVAL;
-    std::shared_ptr<Batch> b;
-    {
-        std::lock_guard<std::mutex> g(ctx->mu);
-        auto it = ctx->batches.find(ticket);
-        if (it == ctx->batches.end()) {
-            ctx->err = "unknown ticket";
-            return KC_E_INVAL;
-        }
-        b = it->second;
-    }
-    {
-        std::unique_lock<std::mutex> g(b->mu);
-        if (!b->done) {
-            if (!wait) return KC_E_PENDING;
-            b->cv.wait(g, [&] { return b->done; });
-        }
-    }
-    if (b->worker.joinable()) b->worker.join();
-    if (b->status != KC_OK) {
-        std::lock_guard<std::mutex> g(ctx->mu);
-        ctx->err = b->err;
-        if (b->status == KC_E_DEVICE) ctx->poisoned = true;
-        ctx->batches.erase(ticket);
-        return b->status;
-    }
-    if (!out || n_out < b->reports.size()) {
-        ctx->err = "output array too small";
-        return KC_E_INVAL;
-    }
-    for (size_t i = 0; i < b->reports.size(); i++) out[i] = b->reports[i];
-    b->reports.clear();
-    std::lock_guard<std::mutex> g(ctx->mu);
-    ctx->batches.erase(ticket);
-    return KC_OK;
+    return guarded(ctx, [&] { return poll_batch(ctx, ticket, wait, out, n_out); });
 }
 
 uint64_t kc_report_records(const kc_report *r) { return r ? r->records : 0; }

@@ -14,6 +14,8 @@
 // waves, all passes in one launch, ping-ponging between the two buffers.
 #include "kc_internal.h"
 
+#include <mutex>
+
 namespace kc {
 
 namespace {
@@ -311,6 +313,23 @@ __global__ void __launch_bounds__(SWG) k_rs_small(uint64_t *__restrict__ keys, u
 
 }  // namespace
 
+// Raise the small sort's dynamic LDS limit, once per device (batch worker
+// threads may sort for the first time together).
+static hipError_t raise_small_lds_limit() {
+    constexpr int kMaxDevices = 64;
+    static std::once_flag once[kMaxDevices];
+    static hipError_t result[kMaxDevices];
+    int dev = 0;
+    const hipError_t eg = hipGetDevice(&dev);
+    if (eg != hipSuccess) return eg;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::call_once(once[dev], [dev] {
+        result[dev] = hipFuncSetAttribute((const void *)k_rs_small, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                          (int)(SMALL_N * 8));
+    });
+    return result[dev];
+}
+
 size_t radix_hist_entries(uint64_t n, uint32_t tile) {
     const uint64_t n_tiles = (n + tile - 1) / tile;
     return (size_t)(n_tiles ? n_tiles : 1) * 256;
@@ -321,13 +340,8 @@ hipError_t radix_sort(uint64_t *keys, uint64_t n, const VKey &vk, SortScratch &s
     *out = keys;
     if (n <= 1 || vk.vbits == 0) return hipSuccess;
     if (n <= SMALL_N) {
-        static bool attr_set = false;
-        if (!attr_set) {
-            hipError_t e = hipFuncSetAttribute((const void *)k_rs_small, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                               (int)(SMALL_N * 8));
-            if (e != hipSuccess) return e;
-            attr_set = true;
-        }
+        const hipError_t ea = raise_small_lds_limit();
+        if (ea != hipSuccess) return ea;
         hipLaunchKernelGGL(k_rs_small, dim3(1), dim3(SWG), n * 8, s, keys, sc.alt, (uint32_t)n, vk, vk.vbits);
         *out = ((vk.vbits + 7) / 8) % 2 ? sc.alt : keys;
         return hipGetLastError();

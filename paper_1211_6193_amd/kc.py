@@ -18,9 +18,10 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 # comparing build variants side by side).
 LIB_PATH = os.environ.get("KC_LIBRARY") or os.path.join(_HERE, "libkc.so")
 
-KC_OK, KC_E_INVAL, KC_E_PROGRAM, KC_E_NOMEM, KC_E_DEVICE, KC_E_PENDING, KC_E_BUDGET, KC_E_OVERFLOW = range(8)
+(KC_OK, KC_E_INVAL, KC_E_PROGRAM, KC_E_NOMEM, KC_E_DEVICE, KC_E_PENDING, KC_E_BUDGET, KC_E_OVERFLOW,
+ KC_E_INTERNAL) = range(9)
 STATUS_NAMES = ["KC_OK", "KC_E_INVAL", "KC_E_PROGRAM", "KC_E_NOMEM", "KC_E_DEVICE", "KC_E_PENDING",
-                "KC_E_BUDGET", "KC_E_OVERFLOW"]
+                "KC_E_BUDGET", "KC_E_OVERFLOW", "KC_E_INTERNAL"]
 DEADLOCK, DIVERGENCE, OOB, FUEL, ARITH = 1, 2, 3, 4, 5
 
 # Every entry point include/kc.h declares.
@@ -37,7 +38,7 @@ SITE_DTYPE = np.dtype([(f, "<u4") for f in ("w_pc", "o_pc")])
 
 class KcError(RuntimeError):
     def __init__(self, status: int, msg: str):
-        super().__init__(f"{STATUS_NAMES[status] if 0 <= status < 8 else status}: {msg}")
+        super().__init__(f"{STATUS_NAMES[status] if 0 <= status < len(STATUS_NAMES) else status}: {msg}")
         self.status = status
 
 
