@@ -9,10 +9,19 @@ own small interpreter written independently of the oracle, and reports the set
 of reachable outcomes.
 
 Per maximal execution it records: the final global memory, whether some block
-ended stuck at a barrier (deadlock), the multiset of access records and
-whether any two accesses conflict (same location, different threads, one a
-write, not separated by a completed barrier episode of their block for
-intra-block pairs; any epochs for global accesses of different blocks).
+ended stuck at a barrier (deadlock), the multiset of access records, whether
+any two accesses conflict (same location, different threads, one a write, not
+separated by a completed barrier episode of their block for intra-block pairs;
+any epochs for global accesses of different blocks), and the set of per-access
+findings: out-of-bounds accesses (the load yields 0, the store is dropped, no
+record), division by zero, and threads that run out of fuel.
+
+Findings use the report's numbering: (kind, block, epoch, a, b, c) with
+OOB = 3 {a = 2 * space + (1 for a store), b = tid, c = the address as an
+unsigned 32-bit value}, FUEL = 4 {a = 0, b = tid, c = 0} and
+ARITH = 5 {a = 0, b = tid, c = pc}.  A thread whose turn comes at the end of
+the program exits; otherwise, with no fuel left, it records FUEL and exits;
+otherwise it executes one instruction and spends one unit of fuel.
 """
 from __future__ import annotations
 
@@ -75,12 +84,16 @@ def _dec(w: int):
     return w & 0xFF, (w >> 8) & 0xFF, (w >> 16) & 0xFF, (w >> 24) & 0xFF, s32(imm)
 
 
+OOB, FUEL, ARITH = 3, 4, 5
+
+
 @dataclass
 class Outcome:
     memory: Tuple[int, ...]
     deadlock: bool
     racy: bool
     records: FrozenSet  # frozenset of (record, count)
+    findings: FrozenSet = frozenset()   # (kind, block, epoch, a, b, c)
 
 
 def _racy(recs: Counter, nt: int) -> bool:
@@ -100,8 +113,10 @@ def _racy(recs: Counter, nt: int) -> bool:
 
 
 def enumerate_launch(prog: List[int], grid: int, block: int, shmem_words: int,
-                     memory: List[int], params=(), limit_states: int = 2_000_000) -> List[Outcome]:
-    """All outcomes of one launch (1-D grid/block) over every interleaving."""
+                     memory: List[int], params=(), limit_states: int = 2_000_000,
+                     fuel: int = 1 << 20) -> List[Outcome]:
+    """All outcomes of one launch (1-D grid/block) over every interleaving;
+    each thread may execute at most ``fuel`` instructions."""
     n = len(prog)
     params = list(params) + [0] * (8 - len(params))
     nt, nb = block, grid
@@ -112,10 +127,10 @@ def enumerate_launch(prog: List[int], grid: int, block: int, shmem_words: int,
                  12: tid, 13: bid, 14: nt, 15: 32}
         return table[k] if k < 16 else params[k - 16]
 
-    # thread state: (pc, regs, status)  status 0 run, 1 wait(bar_pc), 2 exit
-    init_threads = tuple((0, (0,) * 16, 0, -1) for _ in range(nb * nt))
+    # thread state: (pc, regs, status, bar_pc, fuel left)  status 0 run, 1 wait, 2 exit
+    init_threads = tuple((0, (0,) * 16, 0, -1, fuel) for _ in range(nb * nt))
     init = (init_threads, tuple(tuple([0] * shmem_words) for _ in range(nb)), tuple(memory),
-            (0,) * nb, frozenset())
+            (0,) * nb, frozenset(), frozenset())
     seen: Set = set()
     outcomes: Dict = {}
     stack = [init]
@@ -126,7 +141,7 @@ def enumerate_launch(prog: List[int], grid: int, block: int, shmem_words: int,
         seen.add(st)
         if len(seen) > limit_states:
             raise RuntimeError("state space too large")
-        threads, shs, gm, epochs, recs = st
+        threads, shs, gm, epochs, recs, finds = st
         succ = []
         # barrier releases (deterministic per block)
         released = False
@@ -137,27 +152,31 @@ def enumerate_launch(prog: List[int], grid: int, block: int, shmem_words: int,
                 # predicate barriers: registers are unchanged while waiting
                 preds = [code[t[3]][0] == 0x65 and t[1][code[t[3]][2]] != 0 for t in ts]
                 for k in range(nt):
-                    pc, rg, s, bp = ts[k]
+                    pc, rg, s, bp, fl = ts[k]
                     op_b, d_b, _, _, kind = code[bp]
                     if op_b == 0x65:
                         rg = list(rg)
                         rg[d_b] = [sum(preds), int(all(preds)), int(any(preds))][kind]
                         rg = tuple(rg)
-                    nts[b * nt + k] = (bp + 1, rg, 0, -1)
+                    nts[b * nt + k] = (bp + 1, rg, 0, -1, fl)
                 ne = list(epochs); ne[b] += 1
-                succ.append((tuple(nts), shs, gm, tuple(ne), recs))
+                succ.append((tuple(nts), shs, gm, tuple(ne), recs, finds))
                 released = True
                 break
         if not released:
             for g in range(nb * nt):
-                pc, rg, s, bp = threads[g]
+                pc, rg, s, bp, fl = threads[g]
                 if s != 0:
                     continue
                 b, t = divmod(g, nt)
-                nts = list(threads); nshs = shs; ngm = gm; nrec = recs
+                nts = list(threads); nshs = shs; ngm = gm; nrec = recs; nfind = finds
                 if pc == n:
-                    nts[g] = (pc, rg, 2, -1)
-                    succ.append((tuple(nts), nshs, ngm, epochs, nrec))
+                    nts[g] = (pc, rg, 2, -1, fl)
+                    succ.append((tuple(nts), nshs, ngm, epochs, nrec, nfind))
+                    continue
+                if fl == 0:
+                    nts[g] = (pc, rg, 2, -1, fl)
+                    succ.append((tuple(nts), nshs, ngm, epochs, nrec, finds | {(FUEL, b, epochs[b], 0, t, 0)}))
                     continue
                 op, d, a, bb, imm = code[pc]
                 regs = list(rg)
@@ -168,9 +187,15 @@ def enumerate_launch(prog: List[int], grid: int, block: int, shmem_words: int,
                     c[(space, addr, b, epochs[b], t, kind)] += 1
                     return frozenset(c.items())
 
+                def finding(kind, a_, c_):
+                    return finds | {(kind, b, epochs[b], a_, t, c_ & M32)}
+
                 if op in _OPS:
                     name, isimm = _OPS[op]
-                    regs[d] = alu(name, regs[a], imm if isimm else regs[bb])
+                    y = imm if isimm else regs[bb]
+                    regs[d] = alu(name, regs[a], y)
+                    if name in ("DIV", "REM") and y == 0:
+                        nfind = finding(ARITH, 0, pc)
                 elif op == 0x40: regs[d] = regs[a]
                 elif op == 0x41: regs[d] = imm
                 elif op == 0x42: regs[d] = sreg(imm, t, b)
@@ -180,10 +205,12 @@ def enumerate_launch(prog: List[int], grid: int, block: int, shmem_words: int,
                         ok = 0 <= addr < shmem_words
                         regs[d] = shs[b][addr] if ok else 0
                         if ok: nrec = addrec(0, addr, 0)
+                        else: nfind = finding(OOB, 0, addr)
                     else:
                         ok = 0 <= addr < len(gm)
                         regs[d] = gm[addr] if ok else 0
                         if ok: nrec = addrec(1, addr, 0)
+                        else: nfind = finding(OOB, 2, addr)
                 elif op in (0x51, 0x53):
                     addr = s32(regs[a] + imm)
                     if op == 0x51:
@@ -191,10 +218,14 @@ def enumerate_launch(prog: List[int], grid: int, block: int, shmem_words: int,
                             row = list(shs[b]); row[addr] = regs[bb]
                             nshs = shs[:b] + (tuple(row),) + shs[b + 1:]
                             nrec = addrec(0, addr, 1)
+                        else:
+                            nfind = finding(OOB, 1, addr)
                     else:
                         if 0 <= addr < len(gm):
                             m = list(gm); m[addr] = regs[bb]; ngm = tuple(m)
                             nrec = addrec(1, addr, 1)
+                        else:
+                            nfind = finding(OOB, 3, addr)
                 elif op == 0x60: npc = imm
                 elif op == 0x61: npc = imm if regs[a] == 0 else pc + 1
                 elif op == 0x62: npc = imm if regs[a] != 0 else pc + 1
@@ -202,13 +233,13 @@ def enumerate_launch(prog: List[int], grid: int, block: int, shmem_words: int,
                 elif op == 0x64: ns = 2
                 else:
                     raise ValueError(f"bad opcode {op:#x}")
-                nts[g] = (npc, tuple(regs), ns, nbp)
-                succ.append((tuple(nts), nshs, ngm, epochs, nrec))
+                nts[g] = (npc, tuple(regs), ns, nbp, fl - 1)
+                succ.append((tuple(nts), nshs, ngm, epochs, nrec, nfind))
         if not succ:
             deadlock = any(any(threads[b * nt + k][2] == 1 for k in range(nt)) for b in range(nb))
             c = Counter(dict(recs))
-            oc = Outcome(gm, deadlock, _racy(c, nt), recs)
-            outcomes[(gm, deadlock, oc.racy, recs)] = oc
+            oc = Outcome(gm, deadlock, _racy(c, nt), recs, finds)
+            outcomes[(gm, deadlock, oc.racy, recs, finds)] = oc
         else:
             stack.extend(succ)
     return list(outcomes.values())

@@ -64,6 +64,23 @@ def test_random_tiny_kernels(ctx):
         assert_same(rep, mem, O.run_job(j), f"tiny {i}")
 
 
+def test_random_tiny_kernels_with_little_fuel(ctx):
+    """The brute-force fuel cases: threads run out of fuel part-way, next to
+    out-of-bounds accesses and divisions by zero (every finding field)."""
+    by_fuel = {}
+    for chunk in range(3):
+        for prog, nb, nt, mem, fuel in TB.fuel_cases(20, 8100 + chunk):
+            by_fuel.setdefault(fuel, []).append(
+                W.Job([W.LaunchSpec(np.array(prog, dtype=np.uint64), (nb, 1, 1), (nt, 1, 1), 4 * TB.SH_WORDS,
+                                    ())], np.array(mem, dtype=np.int32)))
+    try:
+        for fuel, jobs in sorted(by_fuel.items()):
+            ctx.set_option("fuel", fuel)
+            check_jobs(ctx, jobs, fuel=fuel, label=f"tiny-fuel-{fuel}")
+    finally:
+        ctx.set_option("fuel", O.DEFAULT_FUEL)
+
+
 def test_tree_tables_with_faults(ctx):
     job = W.tree256_job(n_blocks=64, threads=256, drop_frac=0.0, div_frac=0.0, seed=11)
     n = job.meta["n"]
