@@ -138,7 +138,8 @@ kc_status kc_ctx_set_option(kc_ctx *ctx, const char *key, int64_t value);
  * unreduced record, or a location written by one replayed block and touched
  * by another; the others are checked through a hash table of locations),
  * "instructions" (thread-instructions executed by the parallel free run; a
- * canonical replay of racy blocks is not counted), "jit_launches", "jit_replays"
+ * canonical replay of racy blocks is not counted), "global_accesses"
+ * (in-bounds global-memory accesses of the free run), "jit_launches", "jit_replays"
  * (replay launches on specialised kernels),
  * "jit_compiled", "jit_compile_ms", "jit_failures", "site_replays",
  * "cross_launch_races", "alloc_findings".

@@ -126,11 +126,13 @@ struct Shared {
     uint64_t *alt;      // second buffer of the same size (epoch-local sort)
     uint32_t *wc;       // nwaves x 256 digit counters (epoch-local sort)
     uint32_t *tmp;      // 256 words
-    unsigned long long *shadow;   // per simulated shared word: access tuple of the current epoch
+    unsigned long long *shadow;   // per simulated shared word: access tuple of the current epoch (replay)
+    uint32_t *vmin, *vmax, *vw;   // the same region in the free run: smallest and largest accessing tid, any store
     unsigned long long *gst;      // global shadow table: per global location, its tuple of the epoch
     uint64_t *repbuf;   // with the table: representative records held until the block ends (REP_HOLD)
-    uint32_t *slots;    // 16 waves x 8 words: episode reductions
+    uint32_t *slots;    // 16 waves x 10 words: episode reductions, lockstep rounds
     uint32_t *slots2;   // 16 x 4: divergence second round
+    uint32_t *eps;      // free-run episodes: 3 sets of EPS_WORDS summary words, used in turn
 };
 
 typedef const __attribute__((address_space(4))) uint64_t const_word_t;   // scalar-cache reads
@@ -146,6 +148,7 @@ struct BlockCtx {
     uint32_t n_instr, n_words, sh_words;
     uint64_t kbase;         // record bits fixed for this lane: unit, block, tid
     uint64_t kep;           // kbase plus the current epoch
+    uint32_t *gocc;         // global shadow table: occupancy and overflow words of the current epoch
 };
 
 // Wave-aggregated append of findings.
@@ -204,6 +207,7 @@ __device__ __forceinline__ void flush_stage(const InterpArgs &A, uint64_t *stage
 struct LogState {
     uint32_t cur;       // staged records (wave-uniform)
     uint32_t total;     // records of this wave for the block
+    uint32_t gtotal;    // of which global-space
     bool spilled;       // this wave flushed records of the current epoch to HBM
 };
 
@@ -269,6 +273,23 @@ __device__ __forceinline__ void shadow_update(unsigned long long *sh, uint32_t a
         if (prev == old) return;
         old = prev;
     }
+}
+
+// The free run needs only a verdict per shared word and epoch: a block with
+// an intra-block race is replayed, and the replay computes the canonical
+// tuples.  Racy means a store and two distinct threads, i.e. the smallest and
+// the largest accessing tid differ and some access stored, which three
+// non-returning LDS atomics maintain (no compare-and-swap loop, no wait).
+__device__ __forceinline__ void shadow_mark(const Shared &S, uint32_t addr, uint32_t tid, bool write) {
+    atomicMin(&S.vmin[addr], tid);
+    atomicMax(&S.vmax[addr], tid);
+    if (write) atomicOr(&S.vw[addr], 1u);
+}
+
+// Bytes of the shadow region: 8 per shared word for the replay's tuples, 12
+// for the free run's three verdict words; rounded to 16.
+__host__ __device__ inline size_t shadow_region_bytes(uint32_t sh_words) {
+    return ((size_t)sh_words * 12 + 15) & ~(size_t)15;
 }
 
 // ---- global shadow table ------------------------------------------------------
@@ -359,16 +380,16 @@ __device__ __forceinline__ void global_access(const InterpArgs &A, const BlockCt
         if (lane_id() == first) {
             const uint64_t m2 = m & (m - 1ull);
             const uint32_t t1 = B.tid, t2 = m2 ? B.wave * WAVE + (uint32_t)__ffsll((long long)m2) - 1u : GT_NONE;
-            ok = gst_insert(S.gst, A.gst_bits, &S.tmp[36], a0, gst_tuple(t1, t2, store ? t1 : GT_NONE));
+            ok = gst_insert(S.gst, A.gst_bits, B.gocc, a0, gst_tuple(t1, t2, store ? t1 : GT_NONE));
         }
         ok = __shfl((int)ok, (int)first) != 0;
     } else if (inb) {
-        ok = gst_insert(S.gst, A.gst_bits, &S.tmp[36], addr, gst_tuple(B.tid, GT_NONE, store ? B.tid : GT_NONE));
+        ok = gst_insert(S.gst, A.gst_bits, B.gocc, addr, gst_tuple(B.tid, GT_NONE, store ? B.tid : GT_NONE));
     }
     L.total += (uint32_t)__popcll(__ballot(inb && ok));
     const bool miss = inb && !ok;
     if (__ballot(miss)) {
-        if (lane_id() == 0) S.tmp[37] = 1u;         // the epoch overflowed the table
+        if (lane_id() == 0) B.gocc[1] = 1u;         // the epoch overflowed the table
         log_rec(A, S.stage, L, miss, key);
     }
 }
@@ -574,6 +595,82 @@ __device__ __forceinline__ void gst_drain(const InterpArgs &A, const BlockCtx &B
     }
 }
 
+// Reduce the epoch's staged global records, sorted by (space, address) in
+// `src` (n records), to each location's race and representatives (compacted
+// into `dst`), reserved in the log with one atomic per block.
+__device__ __forceinline__ void local_reduce_sorted(const InterpArgs &A, const BlockCtx &B, const Shared &S,
+                                                    uint32_t epoch, const uint64_t *src, uint64_t *dst, uint32_t n) {
+    const KeyPlan &k = A.kp;
+    // Segments (one location) of the sorted epoch: the head thread reduces
+    // up to LOCAL_SEG_LIMIT records; longer segments (a location touched
+    // by many threads) are listed and reduced by whole waves.
+    // Representatives are compacted into dst (a segment yields no more
+    // representatives than records, so n entries suffice) and reserved in
+    // the log with one atomic per block: a single global counter serves
+    // every block of the launch.
+    if (threadIdx.x == 0) {
+        S.tmp[32] = 0;      // representatives in dst
+        S.tmp[35] = 0;      // long segments listed in wc
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+        const uint64_t r = src[i];
+        const uint32_t lk = local_key(r, k);
+        if (i != 0 && local_key(src[i - 1], k) == lk) continue;
+        SegState st{NONE_U32, NONE_U32, NONE_U32};
+        bool is_long = false;
+        for (uint32_t j = i; j < n; j++) {
+            const uint64_t x = src[j];
+            if (local_key(x, k) != lk) break;
+            if (j - i == LOCAL_SEG_LIMIT) {
+                is_long = true;
+                break;
+            }
+            seg_add(st, rec_field(x, k.s_tid, k.tb), (x & 1ull) != 0);
+        }
+        if (is_long) S.wc[atomicAdd(&S.tmp[35], 1u)] = i;
+        else local_segment_done(A, B, S, r, epoch, st, dst);
+    }
+    __syncthreads();
+    const uint32_t nlong = S.tmp[35];
+    for (uint32_t e = B.wave; e < nlong; e += B.nwaves) {
+        const uint32_t i = S.wc[e];
+        const uint64_t r = src[i];
+        const uint32_t lk = local_key(r, k);
+        SegState st{NONE_U32, NONE_U32, NONE_U32};
+        for (uint32_t base = i;; base += WAVE) {
+            const uint32_t j = base + lane_id();
+            const uint64_t x = j < n ? src[j] : 0ull;
+            const bool in = j < n && local_key(x, k) == lk;
+            if (in) seg_add(st, rec_field(x, k.s_tid, k.tb), (x & 1ull) != 0);
+            if (__ballot(!in)) break;           // sorted: the segment ended in this chunk
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const SegState y{(uint32_t)__shfl_xor((int)st.minw, o), (uint32_t)__shfl_xor((int)st.t1, o),
+                             (uint32_t)__shfl_xor((int)st.t2, o)};
+            seg_merge(st, y);
+        }
+        if (lane_id() == 0) local_segment_done(A, B, S, r, epoch, st, dst);
+    }
+    __syncthreads();
+    const uint32_t nrep = S.tmp[32];
+    if (nrep) {
+        if (threadIdx.x == 0) {
+            const unsigned long long base = atomicAdd(A.log_count, (unsigned long long)nrep);
+            S.tmp[33] = (uint32_t)base;
+            S.tmp[34] = (uint32_t)(base >> 32);
+            if (base + nrep > A.log_cap) atomicOr(A.flags, FLAG_LOG_OVERFLOW);
+        }
+        __syncthreads();
+        const unsigned long long base = (unsigned long long)S.tmp[33] | ((unsigned long long)S.tmp[34] << 32);
+        for (uint32_t j = threadIdx.x; j < nrep; j += blockDim.x)
+            if (base + j < A.log_cap) A.log[base + j] = dst[j];
+    }
+}
+
+// The replay's epoch-local check: exact tuples of the shared words, the
+// global shadow table or the staged global records of the epoch.
 __device__ __forceinline__ void epoch_local_check(const InterpArgs &A, const BlockCtx &B, const Shared &S,
                                                   LogState &L, uint32_t epoch) {
     const KeyPlan &k = A.kp;
@@ -618,72 +715,7 @@ __device__ __forceinline__ void epoch_local_check(const InterpArgs &A, const Blo
             local_sort_pass(S, B, k, src, dst, n, shift);
             uint64_t *t = src; src = dst; dst = t;
         }
-        // Segments (one location) of the sorted epoch: the head thread reduces
-        // up to LOCAL_SEG_LIMIT records; longer segments (a location touched
-        // by many threads) are listed and reduced by whole waves.
-        // Representatives are compacted into dst (a segment yields no more
-        // representatives than records, so n entries suffice) and reserved in
-        // the log with one atomic per block: a single global counter serves
-        // every block of the launch.
-        if (threadIdx.x == 0) {
-            S.tmp[32] = 0;      // representatives in dst
-            S.tmp[35] = 0;      // long segments listed in wc
-        }
-        __syncthreads();
-        for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
-            const uint64_t r = src[i];
-            const uint32_t lk = local_key(r, k);
-            if (i != 0 && local_key(src[i - 1], k) == lk) continue;
-            SegState st{NONE_U32, NONE_U32, NONE_U32};
-            bool is_long = false;
-            for (uint32_t j = i; j < n; j++) {
-                const uint64_t x = src[j];
-                if (local_key(x, k) != lk) break;
-                if (j - i == LOCAL_SEG_LIMIT) {
-                    is_long = true;
-                    break;
-                }
-                seg_add(st, rec_field(x, k.s_tid, k.tb), (x & 1ull) != 0);
-            }
-            if (is_long) S.wc[atomicAdd(&S.tmp[35], 1u)] = i;
-            else local_segment_done(A, B, S, r, epoch, st, dst);
-        }
-        __syncthreads();
-        const uint32_t nlong = S.tmp[35];
-        for (uint32_t e = B.wave; e < nlong; e += B.nwaves) {
-            const uint32_t i = S.wc[e];
-            const uint64_t r = src[i];
-            const uint32_t lk = local_key(r, k);
-            SegState st{NONE_U32, NONE_U32, NONE_U32};
-            for (uint32_t base = i;; base += WAVE) {
-                const uint32_t j = base + lane_id();
-                const uint64_t x = j < n ? src[j] : 0ull;
-                const bool in = j < n && local_key(x, k) == lk;
-                if (in) seg_add(st, rec_field(x, k.s_tid, k.tb), (x & 1ull) != 0);
-                if (__ballot(!in)) break;           // sorted: the segment ended in this chunk
-            }
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) {
-                const SegState y{(uint32_t)__shfl_xor((int)st.minw, o), (uint32_t)__shfl_xor((int)st.t1, o),
-                                 (uint32_t)__shfl_xor((int)st.t2, o)};
-                seg_merge(st, y);
-            }
-            if (lane_id() == 0) local_segment_done(A, B, S, r, epoch, st, dst);
-        }
-        __syncthreads();
-        const uint32_t nrep = S.tmp[32];
-        if (nrep) {
-            if (threadIdx.x == 0) {
-                const unsigned long long base = atomicAdd(A.log_count, (unsigned long long)nrep);
-                S.tmp[33] = (uint32_t)base;
-                S.tmp[34] = (uint32_t)(base >> 32);
-                if (base + nrep > A.log_cap) atomicOr(A.flags, FLAG_LOG_OVERFLOW);
-            }
-            __syncthreads();
-            const unsigned long long base = (unsigned long long)S.tmp[33] | ((unsigned long long)S.tmp[34] << 32);
-            for (uint32_t j = threadIdx.x; j < nrep; j += blockDim.x)
-                if (base + j < A.log_cap) A.log[base + j] = dst[j];
-        }
+        local_reduce_sorted(A, B, S, epoch, src, dst, n);
     }
     __syncthreads();            // the staging areas and the table are free again
     if (threadIdx.x == 0) {
@@ -719,6 +751,7 @@ __device__ __forceinline__ void barrier_results(const BlockCtx &B, Lane &t) {
     t.bpred = 0;
 }
 
+// The replay's episode (the free run's is free_episode).
 template <bool LOCAL>
 __device__ __forceinline__ int barrier_episode(const InterpArgs &A, BlockCtx &B, const Shared &S, Lane &t,
                                LogState &L, uint32_t &epoch) {
@@ -733,7 +766,7 @@ __device__ __forceinline__ int barrier_episode(const InterpArgs &A, BlockCtx &B,
     (void)is_thread;
     if (lane_id() == 0) {
         S.slots2[4 * B.wave + 3] = (uint32_t)__popcll(pm);     // predicates that hold
-        uint32_t *s = S.slots + 8 * B.wave;
+        uint32_t *s = S.slots + 10 * B.wave;
         s[0] = (uint32_t)__popcll(wm);
         s[1] = (uint32_t)__popcll(em);
         s[2] = (uint32_t)bmin;
@@ -745,7 +778,7 @@ __device__ __forceinline__ int barrier_episode(const InterpArgs &A, BlockCtx &B,
     uint32_t nw = 0, ne = 0, minw = 0xFFFFFFFFu, mine = 0xFFFFFFFFu;
     int BMIN = INT_MAX, BMAX = -1;
     for (uint32_t w = 0; w < B.nwaves; w++) {
-        const uint32_t *s = S.slots + 8 * w;
+        const uint32_t *s = S.slots + 10 * w;
         nw += s[0];
         ne += s[1];
         BMIN = min(BMIN, (int)s[2]);
@@ -793,6 +826,194 @@ __device__ __forceinline__ int barrier_episode(const InterpArgs &A, BlockCtx &B,
     }
     B.kep = B.kbase | ((uint64_t)epoch << A.kp.s_ep);
     return EP_RELEASED;
+}
+
+// ---- free-run barrier episode ---------------------------------------------------
+// The same decisions as barrier_episode, with two workgroup barriers: every
+// wave publishes its arrivals with LDS atomics into the episode's summary
+// words before the first barrier (three sets used in turn, so the set the
+// next episode fills was last read two episodes ago and is reset now); the
+// epoch-local check (shared-word verdicts, the global shadow table) runs
+// between the barriers, and the second makes its resets visible before the
+// next epoch's accesses.  The global table's occupancy words alternate by
+// epoch parity for the same reason.
+enum : uint32_t { EPS_WAIT = 0, EPS_EXIT, EPS_BMIN, EPS_BMAX, EPS_PRED, EPS_TWAIT, EPS_TEXIT, EPS_SPILL, EPS_WORDS };
+
+// The epoch-local check of a free-run episode, after its first barrier.
+__device__ __forceinline__ void free_local_check(const InterpArgs &A, BlockCtx &B, const Shared &S, LogState &L,
+                                                 uint32_t epoch, bool spilled) {
+    const KeyPlan &k = A.kp;
+    // shared words: verdicts; one marker per wave that found a racy word
+    // flags the block for the replay (the tuple is not canonical and is
+    // never reported; the count sizes the replay's race list)
+    uint32_t nracy = 0, ra = 0, rmin = 0, rmax = 0;
+    for (uint32_t a = threadIdx.x; a < B.sh_words; a += blockDim.x) {
+        const uint32_t mn = S.vmin[a];
+        if (mn == NONE_U32) continue;
+        const uint32_t mx = S.vmax[a];
+        if (S.vw[a] != 0u && mn != mx) {
+            nracy++;
+            ra = a;
+            rmin = mn;
+            rmax = mx;
+        }
+        S.vmin[a] = NONE_U32;
+        S.vmax[a] = 0u;
+        S.vw[a] = 0u;
+    }
+    const uint64_t rm = __ballot(nracy != 0);
+    if (rm) {
+        uint32_t tot = nracy;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) tot += (uint32_t)__shfl_xor((int)tot, o);
+        if (lane_id() == (uint32_t)__ffsll((long long)rm) - 1u) {
+            push_local_race(A, B, 0u, epoch, ra, rmin, rmax);
+            if (A.racy_words) atomicAdd(A.racy_words, tot);
+        }
+    }
+    if (A.gst_bits) {
+        const uint32_t g_occupied = B.gocc[0], g_overflow = B.gocc[1];
+        const bool unreduced = spilled || g_overflow;
+        if (unreduced) flush_stage(A, S.stage, L.cur);
+        if (g_occupied) gst_drain(A, B, S, epoch, !unreduced);      // tmp[32] was zeroed before the barrier
+    } else if (spilled) {
+        flush_stage(A, S.stage, L.cur);
+    } else {
+        // the sorting variant: the staged records of every wave (counts in tmp[w])
+        uint32_t n = 0, off = 0;
+        for (uint32_t w = 0; w < B.nwaves; w++) {
+            const uint32_t c = S.tmp[w];
+            if (w < B.wave) off += c;
+            n += c;
+        }
+        if (n) {
+            for (uint32_t i = lane_id(); i < L.cur; i += WAVE) S.alt[off + i] = S.stage[i];
+            __syncthreads();
+            uint64_t *src = S.alt, *dst = S.stage_all;
+            for (uint32_t shift = 0; shift < 1 + k.ab; shift += 8) {
+                local_sort_pass(S, B, k, src, dst, n, shift);
+                uint64_t *t = src; src = dst; dst = t;
+            }
+            local_reduce_sorted(A, B, S, epoch, src, dst, n);
+        }
+    }
+    L.cur = 0;
+    L.spilled = false;
+}
+
+template <bool LOCAL>
+__device__ __forceinline__ int free_episode(const InterpArgs &A, BlockCtx &B, const Shared &S, Lane &t, LogState &L,
+                                            uint32_t &epoch) {
+    uint32_t *E = S.eps + EPS_WORDS * (epoch % 3u);
+    const bool waiting = t.st == ST_WAIT;
+    const uint64_t wm = __ballot(waiting), em = __ballot(t.st == ST_EXIT);
+    const uint64_t pm = __ballot(waiting && (t.bpred & 1));
+    int bmin = INT_MAX, bmax = -1;
+    if (wm) {
+        const int p0 = __builtin_amdgcn_readlane(t.bar_pc, (int)((uint32_t)__ffsll((long long)wm) - 1u));
+        if (__ballot(waiting && t.bar_pc != p0) == 0) {
+            bmin = bmax = p0;
+        } else {
+            bmin = wave_min(waiting ? t.bar_pc : INT_MAX);
+            bmax = wave_max(waiting ? t.bar_pc : -1);
+        }
+    }
+    if (threadIdx.x == 0) {     // the next episode's set, and the table's reservation counter
+        if (LOCAL) S.tmp[32] = 0u;
+        uint32_t *F = S.eps + EPS_WORDS * ((epoch + 1u) % 3u);
+        F[EPS_WAIT] = 0u;
+        F[EPS_EXIT] = 0u;
+        F[EPS_BMIN] = (uint32_t)INT_MAX;
+        F[EPS_BMAX] = (uint32_t)-1;
+        F[EPS_PRED] = 0u;
+        F[EPS_TWAIT] = NONE_U32;
+        F[EPS_TEXIT] = NONE_U32;
+        F[EPS_SPILL] = 0u;
+        if (LOCAL && A.gst_bits) {      // the next epoch's table words (last read two episodes ago)
+            uint32_t *g = (epoch & 1u) ? &S.tmp[36] : &S.tmp[40];
+            g[0] = 0u;
+            g[1] = 0u;
+        }
+    }
+    if (lane_id() == 0) {
+        if (wm) {
+            atomicAdd(&E[EPS_WAIT], (uint32_t)__popcll(wm));
+            atomicMin((int *)&E[EPS_BMIN], bmin);
+            atomicMax((int *)&E[EPS_BMAX], bmax);
+            atomicMin(&E[EPS_TWAIT], B.wave * WAVE + (uint32_t)__ffsll((long long)wm) - 1u);
+        }
+        if (em) {
+            atomicAdd(&E[EPS_EXIT], (uint32_t)__popcll(em));
+            atomicMin(&E[EPS_TEXIT], B.wave * WAVE + (uint32_t)__ffsll((long long)em) - 1u);
+        }
+        if (pm) atomicAdd(&E[EPS_PRED], (uint32_t)__popcll(pm));
+        if (LOCAL) {
+            if (L.spilled) atomicOr(&E[EPS_SPILL], 1u);
+            S.tmp[B.wave] = L.cur;      // staged records (the sorting variant)
+        }
+    }
+    __syncthreads();
+    const uint32_t nw = E[EPS_WAIT], ne = E[EPS_EXIT], npred = E[EPS_PRED];
+    const int BMIN = (int)E[EPS_BMIN], BMAX = (int)E[EPS_BMAX];
+    if (LOCAL) free_local_check(A, B, S, L, epoch, E[EPS_SPILL] != 0u);
+    if (nw == 0) return EP_DONE;                       // every thread exited
+    if (ne > 0) {                                      // waiting threads can never be released
+        emit_fault(threadIdx.x == 0, A, B, F_DEADLOCK, epoch, nw, E[EPS_TWAIT], E[EPS_TEXIT], 0);
+        return EP_DONE;
+    }
+    if (BMIN != BMAX) {
+        // sites differ: find the next larger site and the smallest tid at each
+        int cw = wave_min(waiting && t.bar_pc > BMIN ? t.bar_pc : INT_MAX);
+        uint64_t lo_m = __ballot(waiting && t.bar_pc == BMIN);
+        uint64_t c_m = __ballot(waiting && t.bar_pc == cw && cw != INT_MAX);
+        if (lane_id() == 0) {
+            uint32_t *q = S.slots2 + 4 * B.wave;
+            q[0] = (uint32_t)cw;
+            q[1] = lo_m ? B.wave * WAVE + (uint32_t)__ffsll((long long)lo_m) - 1 : 0xFFFFFFFFu;
+            q[2] = c_m ? B.wave * WAVE + (uint32_t)__ffsll((long long)c_m) - 1 : 0xFFFFFFFFu;
+        }
+        __syncthreads();
+        int C = INT_MAX;
+        uint32_t tlo = 0xFFFFFFFFu, tc = 0xFFFFFFFFu;
+        for (uint32_t w = 0; w < B.nwaves; w++) C = min(C, (int)S.slots2[4 * w]);
+        for (uint32_t w = 0; w < B.nwaves; w++) {
+            tlo = min(tlo, S.slots2[4 * w + 1]);
+            if ((int)S.slots2[4 * w] == C) tc = min(tc, S.slots2[4 * w + 2]);
+        }
+        emit_fault(threadIdx.x == 0, A, B, F_DIVERGENCE, epoch, (uint32_t)BMIN, tlo, (uint32_t)C, tc);
+    }
+    epoch++;
+    if (threadIdx.x == 0 && epoch > A.kp.max_epoch) atomicOr(A.flags, FLAG_EPOCH_OVERFLOW);
+    if (waiting) {
+        t.st = ST_RUN;
+        t.pc = t.bar_pc + 1;
+        const int kind = (t.bpred >> 1) - 1;
+        if (kind >= 0) t.bres = kind == 0 ? (int32_t)npred : kind == 1 ? (npred == B.nt ? 1 : 0) : (npred ? 1 : 0);
+    }
+    B.kep = B.kbase | ((uint64_t)epoch << A.kp.s_ep);
+    if (LOCAL && A.gst_bits) B.gocc = (epoch & 1u) ? &S.tmp[40] : &S.tmp[36];
+    __syncthreads();            // the check's resets before the next epoch's accesses; divergence slots free
+    return EP_RELEASED;
+}
+
+// After a free-run release: whether the wave's running lanes share one pc,
+// and the smallest pc (the dispatch point).
+__device__ __forceinline__ void free_reconverge(const Lane &t, bool &conv, int &upc) {
+    const bool run = t.st == ST_RUN;
+    const uint64_t rm = __ballot(run);
+    if (rm == 0) {
+        conv = true;
+        upc = 0;
+        return;
+    }
+    const int p0 = __builtin_amdgcn_readlane(t.pc, (int)((uint32_t)__ffsll((long long)rm) - 1u));
+    if (__ballot(run && t.pc != p0) == 0) {
+        conv = true;
+        upc = uni(p0);
+    } else {
+        conv = false;
+        upc = uni(wave_min(run ? t.pc : INT_MAX));
+    }
 }
 
 __device__ __forceinline__ int32_t special(const BlockCtx &B, uint32_t k) {
@@ -900,8 +1121,10 @@ __device__ __forceinline__ void exec_one(const InterpArgs &A, const BlockCtx &B,
         const uint32_t space = is_sh ? 0u : 1u;
         const uint64_t key = B.kep | ((uint64_t)space << k.s_sp) | (uint64_t)(is_st ? 1u : 0u) |
                              ((uint64_t)(uint32_t)addr << k.s_addr);
+        if (!is_sh) L.gtotal += (uint32_t)__popcll(__ballot(inb));
         if (LOCAL && is_sh) {       // shared accesses update the shadow tuple instead of the log
-            if (inb) shadow_update(S.shadow, (uint32_t)addr, B.tid, is_st);
+            if (inb && LOCKSTEP) shadow_update(S.shadow, (uint32_t)addr, B.tid, is_st);
+            if (inb && !LOCKSTEP) shadow_mark(S, (uint32_t)addr, B.tid, is_st);
             L.total += (uint32_t)__popcll(__ballot(inb));
         } else if (LOCAL) {
             global_access(A, B, S, L, inb, (uint32_t)addr, is_st, key);
@@ -922,8 +1145,9 @@ __device__ __forceinline__ void exec_one(const InterpArgs &A, const BlockCtx &B,
     }
 }
 
+// `exact`: the shared words keep full tuples (replay), else verdicts (free run).
 __device__ __forceinline__ void setup_block(const InterpArgs &A, BlockCtx &B, const Shared &S, Lane &t, uint32_t unit,
-                            uint32_t block) {
+                            uint32_t block, bool exact) {
     const DevUnit *u = &A.units[unit];
     B.u = u;
     B.prog = (const_word_t *)u->prog;
@@ -936,17 +1160,36 @@ __device__ __forceinline__ void setup_block(const InterpArgs &A, BlockCtx &B, co
     B.sh_words = u->sh_words;
     B.tid = threadIdx.x;
     B.kbase = rec_pack(A.kp, unit, 0u, 0u, block, 0u, B.tid, 0u);
+    B.gocc = A.local ? &S.tmp[36] : nullptr;
     B.kep = B.kbase;
     for (uint32_t i = threadIdx.x; i < B.sh_words; i += blockDim.x) S.sh[i] = 0;
-    if (A.local)
+    if (A.local && exact)
         for (uint32_t i = threadIdx.x; i < B.sh_words; i += blockDim.x) S.shadow[i] = SHADOW_EMPTY;
+    if (A.local && !exact)
+        for (uint32_t i = threadIdx.x; i < B.sh_words; i += blockDim.x) {
+            S.vmin[i] = NONE_U32;
+            S.vmax[i] = 0u;
+            S.vw[i] = 0u;
+        }
     if (A.gst_bits) {
         for (uint32_t i = threadIdx.x; i < (1u << A.gst_bits); i += blockDim.x) S.gst[i] = GST_EMPTY;
         if (threadIdx.x == 0) {
             S.tmp[36] = 0;
             S.tmp[37] = 0;
             S.tmp[38] = 0;          // representatives held in LDS
+            S.tmp[40] = 0;          // occupancy and overflow of odd epochs (free run)
+            S.tmp[41] = 0;
         }
+    }
+    if (threadIdx.x == 0) {     // the first free-run episode's summary words
+        S.eps[EPS_WAIT] = 0u;
+        S.eps[EPS_EXIT] = 0u;
+        S.eps[EPS_BMIN] = (uint32_t)INT_MAX;
+        S.eps[EPS_BMAX] = (uint32_t)-1;
+        S.eps[EPS_PRED] = 0u;
+        S.eps[EPS_TWAIT] = NONE_U32;
+        S.eps[EPS_TEXIT] = NONE_U32;
+        S.eps[EPS_SPILL] = 0u;
     }
     t.pc = 0;
     t.st = (B.tid < B.nt) ? ST_RUN : ST_DEAD;
@@ -996,24 +1239,28 @@ __device__ __forceinline__ void finish_block(const InterpArgs &A, const BlockCtx
         }
     }
     if (lane_id() == 0) {
-        S.slots[8 * B.wave] = L.total;
-        S.slots[8 * B.wave + 1] = (uint32_t)spent;
-        S.slots[8 * B.wave + 2] = (uint32_t)(spent >> 32);
+        S.slots[10 * B.wave] = L.total;
+        S.slots[10 * B.wave + 1] = (uint32_t)spent;
+        S.slots[10 * B.wave + 2] = (uint32_t)(spent >> 32);
+        S.slots[10 * B.wave + 3] = L.gtotal;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        uint32_t recs = 0;
+        uint32_t recs = 0, grecs = 0;
         unsigned long long instr = 0;
         for (uint32_t w = 0; w < B.nwaves; w++) {
-            recs += S.slots[8 * w];
-            instr += (unsigned long long)S.slots[8 * w + 1] | ((unsigned long long)S.slots[8 * w + 2] << 32);
+            recs += S.slots[10 * w];
+            instr += (unsigned long long)S.slots[10 * w + 1] | ((unsigned long long)S.slots[10 * w + 2] << 32);
+            grecs += S.slots[10 * w + 3];
         }
         if (recs) atomicAdd(&A.blk_recs[B.u->block_base + B.block], recs);
         if (A.blk_instr) A.blk_instr[B.u->block_base + B.block] = (uint32_t)instr;
+        if (A.blk_grecs) A.blk_grecs[B.u->block_base + B.block] = grecs;
         if (epoch > __hip_atomic_load(A.max_epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
             atomicMax(A.max_epoch, epoch);
     }
     L.total = 0;
+    L.gtotal = 0;
     __syncthreads();
 }
 
@@ -1084,12 +1331,9 @@ __device__ __forceinline__ uint32_t run_block_free(const InterpArgs &A, BlockCtx
             }
         }
         // wave quiescent
-        if (barrier_episode<LOCAL>(A, B, S, t, L, epoch) == EP_DONE) break;
+        if (free_episode<LOCAL>(A, B, S, t, L, epoch) == EP_DONE) break;
         barrier_results(B, t);
-        int lo = wave_min(t.st == ST_RUN ? t.pc : INT_MAX);
-        int hi = wave_max(t.st == ST_RUN ? t.pc : -1);
-        conv = (lo == hi) || hi < 0;
-        upc = uni(lo);
+        free_reconverge(t, conv, upc);
     }
     return epoch;
 }
@@ -1166,19 +1410,26 @@ __device__ __forceinline__ uint64_t lockstep_group(const InterpArgs &A, BlockCtx
 }
 
 // Canonical lockstep execution of one block.  Within an epoch every running
-// thread executes its i-th instruction at step i, so only steps that touch
-// memory need the other waves: a wave runs its memory-free steps on its own
-// and stops at its next step with a load or store.  A round then takes the
-// smallest such step of the block: the waves stopped there finish it (loads
-// read memory as of the start of the step, stores are held back), and the
-// step's stores land with the highest tid winning per location -- the same
-// order as stepping every wave through every step together.  When no wave has
-// a running lane the block takes its barrier episode.
+// thread executes its i-th instruction at step i, and threads interact only
+// through loads and stores, so a thread's memory-free instructions may run
+// whenever convenient: each lane keeps the number of steps it has completed
+// in the epoch, and every group of lanes at one pc runs on its own to its next
+// load or store (or barrier, or exit), where it parks.  A round then takes the
+// smallest step at which a running lane is parked: the lanes parked there
+// execute it (loads read memory as of the start of the step, stores are held
+// back), and the step's stores land with the highest tid winning per location
+// -- the same order as stepping every thread through every step together,
+// since all loads and stores of earlier steps have been done by then.  When
+// no lane is running the block takes its barrier episode.
 //
-// `run(todo, epoch)` may execute, for a converged wave at the start of a step,
-// its memory-free instructions in one go (one step each, charging fuel and
-// leaving pc and state in `t`), stopping before a load or store; it returns
-// the number of steps taken, 0 when it took none.
+// A round costs one workgroup barrier, and one more when a store is among the
+// step's accesses; the owner entries a step's stores claimed are cleared in
+// the next round, behind its first barrier.
+//
+// `run(grp, epoch)` may execute the memory-free instructions of a converged
+// group (one step each, charging fuel and leaving pc and state in `t`),
+// stopping before a load or store; it returns the number of steps taken, 0
+// when it took none (then the group steps through `exec` one instruction).
 //
 // `release()` runs after every completed episode (the results of barriers
 // with a predicate).
@@ -1189,52 +1440,77 @@ __device__ __forceinline__ uint32_t run_block_lockstep(const InterpArgs &A, Bloc
     constexpr uint32_t NO_STEP = 0xFFFFFFFFu;
     uint32_t epoch = 0;
     uint32_t par = 0;               // round slots alternate so one barrier per round suffices
+    bool clear = false;             // this lane won a location in the last store round: free its owner entry
+    bool clear_sh = false;
+    uint32_t clear_at = 0;
     for (;;) {
-        uint32_t wstep = 0;         // steps this wave has completed in the epoch
-        uint64_t todo = 0;          // lanes yet to execute the step in progress
+        uint32_t ls = 0;            // steps this lane has completed in the epoch
+        bool parked = false;        // stopped before a load or store (its step ls)
+        bool pst = false;           // ... a store
         for (;;) {
-            Pending P{false, false, 0, 0};
-            uint32_t m = NO_STEP;   // the step this wave waits at
-            for (;;) {              // memory-free steps
-                if (todo == 0) {
-                    todo = __ballot(t.st == ST_RUN);
-                    if (todo == 0) break;
-                    const uint32_t k = run(todo, epoch);
-                    if (k) {
-                        wstep += k;
-                        todo = 0;
-                        continue;
+            // every running lane to its next load or store
+            for (;;) {
+                const bool free_lane = t.st == ST_RUN && !parked;
+                const uint64_t fm = __ballot(free_lane);
+                if (fm == 0) break;
+                const int p = uni(__builtin_amdgcn_readlane(t.pc, (int)((uint32_t)__ffsll((long long)fm) - 1u)));
+                const bool mine = free_lane && t.pc == p;
+                const uint64_t grp = __ballot(mine);
+                const uint64_t w = fetch_word(B, p);
+                if ((uint32_t)p < B.n_instr && ((uniu((uint32_t)w) & 0xFFu) >> 4) == 5u) {
+                    if (mine) {
+                        parked = true;
+                        pst = (w & 1ull) != 0;
                     }
+                    continue;
                 }
-                bool at_mem = false;
-                while (todo) {
-                    const int cur = group_pc(todo, t.pc);
-                    const uint64_t w = fetch_word(B, cur);
-                    if ((uint32_t)cur < B.n_instr && ((uniu((uint32_t)w) & 0xFFu) >> 4) == 5u) {
-                        at_mem = true;
-                        break;
-                    }
-                    todo &= ~lockstep_group<LOCAL>(A, B, S, t, L, P, epoch, todo, cur, w, exec);
+                uint32_t k = run(grp, epoch);
+                if (k == 0) {
+                    Pending none{false, false, 0, 0};
+                    lockstep_group<LOCAL>(A, B, S, t, L, none, epoch, grp, p, w, exec);
+                    k = 1;
                 }
-                if (at_mem) {
-                    m = wstep;
-                    break;
-                }
-                wstep++;
+                if (mine) ls += k;
             }
-            if (lane_id() == 0) S.slots[8 * B.wave + 6 + par] = m;
+            // the smallest parked step of the wave, and whether a store waits there
+            const bool waiting = t.st == ST_RUN && parked;
+            const uint32_t m = wave_min_u(waiting ? ls : NO_STEP);
+            const bool st_m = __ballot(waiting && ls == m && pst) != 0;
+            if (lane_id() == 0) {
+                S.slots[10 * B.wave + 6 + par] = m;
+                S.slots[10 * B.wave + 8 + par] = st_m ? 1u : 0u;
+            }
             __syncthreads();
+            if (clear) {            // every lane read its win before the barrier above
+                if (clear_sh) {
+                    T.own_sh[clear_at] = 0;
+                } else {
+                    T.gown[clear_at] = 0;
+                    T.gkey[clear_at] = EMPTY_KEY;
+                }
+                clear = false;
+            }
             uint32_t M = NO_STEP;
-            for (uint32_t w = 0; w < B.nwaves; w++) M = min(M, S.slots[8 * w + 6 + par]);
+            for (uint32_t w = 0; w < B.nwaves; w++) M = min(M, S.slots[10 * w + 6 + par]);
+            bool any_st = false;
+            for (uint32_t w = 0; w < B.nwaves; w++)
+                any_st |= S.slots[10 * w + 6 + par] == M && S.slots[10 * w + 8 + par] != 0;
             par ^= 1u;
             if (M == NO_STEP) break;                   // no running lane anywhere: barrier episode
-            if (m == M) {           // finish step M, memory groups included
+            Pending P{false, false, 0, 0};
+            if (m == M) {           // the lanes parked at step M execute it
+                const bool at = waiting && ls == M;
+                uint64_t todo = __ballot(at);
                 while (todo) {
                     const int cur = group_pc(todo, t.pc);
                     todo &= ~lockstep_group<LOCAL>(A, B, S, t, L, P, epoch, todo, cur, fetch_word(B, cur), exec);
                 }
-                wstep++;
+                if (at) {
+                    ls++;
+                    parked = false;
+                }
             }
+            if (!any_st) continue;
             // the step's stores: the highest tid per location wins
             uint32_t slot = 0;
             if (P.on) {
@@ -1256,14 +1532,10 @@ __device__ __forceinline__ uint32_t run_block_lockstep(const InterpArgs &A, Bloc
             if (P.on) win = (P.shared ? T.own_sh[P.addr] : T.gown[slot]) == B.tid + 1;
             if (win && P.shared) S.sh[P.addr] = P.val;
             if (win && !P.shared) B.mem[P.addr] = P.val;
-            __syncthreads();
-            if (win) {      // one winner per location clears its entry for the next round
-                if (P.shared) {
-                    T.own_sh[P.addr] = 0;
-                } else {
-                    T.gown[slot] = 0;
-                    T.gkey[slot] = EMPTY_KEY;
-                }
+            if (win) {              // one winner per location frees its entry next round
+                clear = true;
+                clear_sh = P.shared;
+                clear_at = P.shared ? (uint32_t)P.addr : slot;
             }
         }
         if (barrier_episode<LOCAL>(A, B, S, t, L, epoch) == EP_DONE) break;
@@ -1291,15 +1563,19 @@ __device__ __forceinline__ size_t carve_lds(uint8_t *smem, const InterpArgs &A, 
         S.tmp = (uint32_t *)(smem + off);
         off += 256 * 4;
         S.shadow = (unsigned long long *)(smem + off);
-        off += (size_t)A.sh_words_max * 8;
+        S.vmin = (uint32_t *)(smem + off);
+        S.vmax = S.vmin + A.sh_words_max;
+        S.vw = S.vmax + A.sh_words_max;
+        off += shadow_region_bytes(A.sh_words_max);
         S.gst = (unsigned long long *)(smem + off);
         off += A.gst_bits ? ((size_t)8 << A.gst_bits) : 0;
         S.repbuf = (uint64_t *)(smem + off);
         off += A.gst_bits ? (size_t)REP_HOLD * 8 : 0;
     }
     S.slots = (uint32_t *)(smem + off);
-    S.slots2 = S.slots + 16 * 8;
-    off += (16 * 8 + 16 * 4) * 4;
+    S.slots2 = S.slots + 16 * 10;
+    S.eps = S.slots2 + 16 * 4;
+    off += (16 * 10 + 16 * 4 + 3 * 8) * 4;
     return off;
 }
 
@@ -1323,8 +1599,8 @@ __device__ __forceinline__ void free_block(const InterpArgs &A, Run run) {
     B.nwaves = nwaves;
     B.wave = wave;
     Lane t;
-    LogState L{0, 0, false};
-    setup_block(A, B, S, t, unit, block);
+    LogState L{0, 0, 0, false};
+    setup_block(A, B, S, t, unit, block, false);
     const uint32_t epoch = run(A, B, S, t, L);
     finish_block(A, B, S, L, t, epoch);
 }
@@ -1364,10 +1640,10 @@ __device__ __forceinline__ void lockstep_body(const InterpArgs &A, Run run) {
     B.nwaves = nwaves;
     B.wave = wave;
     Lane t;
-    LogState L{0, 0, false};
+    LogState L{0, 0, 0, false};
     for (uint32_t c = c0; c < c1; c++) {
         uint2 it = A.comp_blocks[c];
-        setup_block(A, B, S, t, uniu(it.x), uniu(it.y));
+        setup_block(A, B, S, t, uniu(it.x), uniu(it.y), true);
         const uint32_t epoch = run(A, B, S, T, t, L);
         finish_block(A, B, S, L, t, epoch);
     }

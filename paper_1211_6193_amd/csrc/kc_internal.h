@@ -96,7 +96,8 @@ struct DevCounters {
     uint32_t pad0;
     unsigned long long instructions;   // thread-instructions of the free run
     uint32_t long_count;               // segments left to the long-segment pass of the check
-    uint32_t pad[5];
+    uint32_t racy_words;               // free run: shared words found racy by the verdicts (all epochs)
+    uint32_t pad[4];
 };
 
 // Source sites of race tuples: one slot per tuple of an open-addressing
@@ -140,7 +141,9 @@ struct InterpArgs {
     uint32_t lrace_cap;
     uint32_t *lrace_count;
     uint32_t *blk_flags;        // racy blocks
+    uint32_t *racy_words;       // free run: count of shared words the verdicts found racy (sizes the replay's lists)
     uint32_t *blk_instr;        // free run: thread-instructions executed, per block (stored), or null
+    uint32_t *blk_grecs;        // free run: in-bounds global accesses, per block (stored), or null
     uint32_t gst_bits;          // local check: log2 slots of the global shadow table (0: stage and sort)
     uint32_t site_bits;         // log2 slots of `sites`
     SiteSlot *sites;            // lockstep replay for source sites, or null

@@ -127,8 +127,11 @@ void gen_mem(std::ostringstream &o, const Instr &I, bool lockstep = false) {
     }
     if (sh) {
         o << "            if (LOCAL) {\n";
-        o << "                if (inb) shadow_update(S.shadow, (uint32_t)addr, B.tid, " << (st ? "true" : "false")
-          << ");\n";
+        if (lockstep)
+            o << "                if (inb) shadow_update(S.shadow, (uint32_t)addr, B.tid, " << (st ? "true" : "false")
+              << ");\n";
+        else
+            o << "                if (inb) shadow_mark(S, (uint32_t)addr, B.tid, " << (st ? "true" : "false") << ");\n";
         o << "                L.total += (uint32_t)__popcll(__ballot(inb));\n            } else {\n    ";
     }
     const std::string key = std::string("B.kep | ((uint64_t)") + (sh ? "0" : "1") + "u << A.kp.s_sp) | " +
@@ -136,6 +139,7 @@ void gen_mem(std::ostringstream &o, const Instr &I, bool lockstep = false) {
     if (sh) {
         o << "            log_rec(A, S.stage, L, inb, " << key << ");\n            }\n";
     } else {
+        o << "            L.gtotal += (uint32_t)__popcll(__ballot(inb));\n";
         o << "            if (LOCAL) global_access(A, B, S, L, inb, (uint32_t)addr, " << (st ? "true" : "false") << ", "
           << key << ");\n";
         o << "            else log_rec(A, S.stage, L, inb, " << key << ");\n";
@@ -271,11 +275,9 @@ std::string jit_source(const uint64_t *words, uint32_t n, int waves) {
     }
     o << "        default:\n            if (act) t.st = ST_EXIT;\n            break;\n        }\n";
     o << "      }\n";
-    o << "      if (barrier_episode<LOCAL>(A, B, S, t, L, epoch) == EP_DONE) break;\n";
+    o << "      if (free_episode<LOCAL>(A, B, S, t, L, epoch) == EP_DONE) break;\n";
     o << barrier_results(words, n, "      ");
-    o << "      const int lo = wave_min(t.st == ST_RUN ? t.pc : INT_MAX);\n";
-    o << "      const int hi = wave_max(t.st == ST_RUN ? t.pc : -1);\n";
-    o << "      conv = (lo == hi) || hi < 0;\n      upc = uni(lo);\n    }\n    return epoch;\n}\n\n";
+    o << "      free_reconverge(t, conv, upc);\n    }\n    return epoch;\n}\n\n";
     // Lockstep replay: the interpreter's round protocol with one specialised
     // case per instruction.
     o << "template <bool LOCAL>\n__device__ __forceinline__ uint32_t jit_lock_run(const InterpArgs &A, BlockCtx &B, "

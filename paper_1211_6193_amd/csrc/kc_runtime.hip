@@ -117,7 +117,7 @@ struct Workspace {
     DBuf units, items, comp_off, comp_blocks, mask;
     DBuf snap, log, alt, rlog, ralt, fs, hist, part;
     DBuf faults, rfaults, races, lraces, rlraces, edges, blk_recs, rblk_recs, blk_flags, rflags, ctr, rctr;
-    DBuf longseg, covlist, rtable, ftable, downer, dflags, blk_instr, blk_log, blk_held, blk_off;
+    DBuf longseg, covlist, rtable, ftable, downer, dflags, blk_instr, blk_grecs, blk_log, blk_held, blk_off;
     DevCounters *h_ctr = nullptr;   // pinned
     void *h_pin = nullptr;          // pinned staging of gathered device-to-host copies
     void *d_pin = nullptr;          // its device mapping
@@ -145,7 +145,7 @@ struct Workspace {
         const DBuf *all[] = {&units, &items, &comp_off, &comp_blocks, &mask, &snap, &log, &alt, &rlog,
                              &ralt, &fs, &hist, &part, &faults, &rfaults, &races, &edges, &blk_recs,
                              &rblk_recs, &blk_flags, &rflags, &ctr, &rctr, &lraces, &rlraces, &longseg, &covlist,
-                             &rtable, &ftable, &downer, &dflags, &blk_instr, &blk_log, &blk_held, &blk_off};
+                             &rtable, &ftable, &downer, &dflags, &blk_instr, &blk_grecs, &blk_log, &blk_held, &blk_off};
         size_t s = 0;
         for (auto *b : all) s += b->bytes;
         return s;
@@ -154,7 +154,7 @@ struct Workspace {
         DBuf *all[] = {&units, &items, &comp_off, &comp_blocks, &mask, &snap, &log, &alt, &rlog,
                        &ralt, &fs, &hist, &part, &faults, &rfaults, &races, &edges, &blk_recs,
                        &rblk_recs, &blk_flags, &rflags, &ctr, &rctr, &lraces, &rlraces, &longseg, &covlist,
-                       &rtable, &ftable, &downer, &dflags, &blk_instr, &blk_log, &blk_held, &blk_off};
+                       &rtable, &ftable, &downer, &dflags, &blk_instr, &blk_grecs, &blk_log, &blk_held, &blk_off};
         for (auto *b : all) b->release();
         if (h_ctr) (void)hipHostFree(h_ctr);
         if (h_pin) (void)hipHostFree(h_pin);
@@ -400,6 +400,7 @@ struct Stage {
     uint32_t max_words = 0;
     uint32_t used_epoch_bits = 0;
     uint32_t lrace_cap = 4096;
+    uint32_t racy_words = 0;        // shared words the free run's verdicts found racy
 
     // Sort order for the check: bits from the block field up, then the used
     // epoch bits; the full order for multiset comparison adds tid and kind.
@@ -620,7 +621,9 @@ struct Stage {
         a.lrace_cap = lrace_cap_;
         a.lrace_count = &ctr.as<DevCounters>()->race_count;
         a.blk_flags = flags.as<uint32_t>();
+        a.racy_words = lockstep ? nullptr : &ctr.as<DevCounters>()->racy_words;
         a.blk_instr = lockstep ? nullptr : ws.blk_instr.as<uint32_t>();
+        a.blk_grecs = lockstep ? nullptr : ws.blk_grecs.as<uint32_t>();
         a.blk_log = (!lockstep && held_regions) ? ws.blk_log.as<uint64_t>() : nullptr;
         a.blk_held = (!lockstep && held_regions) ? ws.blk_held.as<uint32_t>() : nullptr;
         // the global shadow table packs a location in 31 bits
@@ -808,6 +811,7 @@ struct Stage {
         ws.blk_recs.reserve((size_t)total_blocks * 4);
         ws.blk_flags.reserve((size_t)total_blocks * 4);
         ws.blk_instr.reserve((size_t)total_blocks * 4);
+        ws.blk_grecs.reserve((size_t)total_blocks * 4);
         // held representatives go to per-block regions (no queue on the log
         // counter at the end of every block) while the regions stay small
         held_regions = check && opt.local && opt.shadow_global && kp.ab <= 31 &&
@@ -818,7 +822,7 @@ struct Stage {
             ws.blk_off.reserve((size_t)total_blocks * 8);
         }
         DevCounters c{};
-        size_t i_instr = 0;
+        size_t i_instr = 0, i_grecs = 0;
         Fetch fetch;
         bool table_queued = false;
         for (;;) {
@@ -850,6 +854,7 @@ struct Stage {
             fetch.add(ws.lraces.p, (size_t)std::min(lrace_cap, kSpec) * sizeof(DevRace));
             if (table_queued) fetch.add(ws.rctr.p, sizeof(DevCounters));      // item 4
             i_instr = fetch.add(ws.blk_instr.p, (size_t)total_blocks * 4);
+            i_grecs = fetch.add(ws.blk_grecs.p, (size_t)total_blocks * 4);
             run_fetch(fetch);
             c = *fetched<DevCounters>(fetch, i_ctr);
             ctx->stat_add("interp_ms", tm.ms(0, 1));
@@ -879,9 +884,14 @@ struct Stage {
         }
         {
             const uint32_t *bi = fetched<uint32_t>(fetch, i_instr);
-            uint64_t instr = 0;
-            for (uint32_t b = 0; b < total_blocks; b++) instr += bi[b];
+            const uint32_t *bg = fetched<uint32_t>(fetch, i_grecs);
+            uint64_t instr = 0, grecs = 0;
+            for (uint32_t b = 0; b < total_blocks; b++) {
+                instr += bi[b];
+                grecs += bg[b];
+            }
             ctx->stat_add("instructions", (double)instr);
+            ctx->stat_add("global_accesses", (double)grecs);
         }
         if (check) ctx->note_log_records(c.log_count + c.log_count / 8);
         ctx->note_caps(c.fault_count + c.fault_count / 8, c.race_count + c.race_count / 8);
@@ -949,6 +959,7 @@ struct Stage {
 
         fin_log = sorted;
         fin_n = check ? nrec : 0;
+        racy_words = c.racy_words;
         if (!races.empty()) replay(races, edges, sorted, nrec, ufaults, uraces, urecs, tm);
 
         for (uint32_t i = 0; i < n; i++) {
@@ -1146,7 +1157,10 @@ struct Stage {
         // put back what the racy blocks wrote, then re-execute them canonically
         HIPCHK(launch_restore(sorted, nrec, kp, ws.units.as<DevUnit>(), ws.blk_flags.as<uint32_t>(), s));
         uint64_t rcap = s_recs + s_recs / 4 + 1024;
-        uint32_t fcap = 4096, rlcap = 4096 + (uint32_t)races.size() * 2;
+        // the free run's verdicts report racy shared words only by count (the
+        // replay computes their tuples)
+        uint32_t fcap = 4096, rlcap = 4096 + (uint32_t)std::min<uint64_t>(
+                                               2 * ((uint64_t)races.size() + racy_words), 1u << 30);
         ReplayOut ro;
         // Common case first: the replay's records are all representatives and
         // no replayed location is shared by replayed blocks with a write; then
