@@ -45,8 +45,8 @@ def main():
                     help="skip the comparison of the in-LDS epoch-local check with the sort-only check")
     ap.add_argument("--no-streams", action="store_true",
                     help="skip the streams-and-events measurement (two streams against one)")
-    ap.add_argument("--workload4", action="store_true",
-                    help="also time workload 4 at full size (ping-pong stencil, 2^26 elements x 16 launches)")
+    ap.add_argument("--no-workload4", action="store_true",
+                    help="skip workload 4 at full size (ping-pong stencil, 2^26 elements x 16 launches)")
     ap.add_argument("--serve-seconds", type=float, default=3.0, help="arrival window per served rate")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB three times (the known-size kernel that scales "
@@ -102,7 +102,8 @@ def main():
                                       "fallbacks", "retries", "sort_keys", "records", "interp_launches",
                                       "replay_lockstep_ms", "replay_sort_ms", "replay_check_ms",
                                       "replay_coverage_ms", "log_entries", "instructions", "jit_launches",
-                                      "hash_check_ms", "sorted_checks", "replay_sorted_checks")}
+                                      "hash_check_ms", "sorted_checks", "replay_sorted_checks",
+                                      "global_accesses")}
     per = {k: stats[k] / args.steps for k in ("interp_ms", "hash_check_ms", "sort_ms", "check_ms", "replay_ms")}
     # the stage breakdown: 10 more steps with every stage timed (each event
     # pauses the stream briefly, so the timed steps record only two)
@@ -114,24 +115,31 @@ def main():
     detail = {k: ctx.stat(k) / 10 for k in ("interp_ms", "hash_check_ms", "sort_ms", "check_ms", "replay_ms",
                                             "replay_lockstep_ms", "replay_sort_ms", "replay_check_ms",
                                             "replay_coverage_ms")}
-    roofline = interp_roofline(stats, args.steps, records, value, per, detail)
+    roofline = free_run_roofline(stats, args.steps, records, value, per, detail)
+    roofline["copy_gbs"] = copy_bandwidth(torch)
+    roofline["frac_of_copy"] = round(roofline["achieved"] / roofline["copy_gbs"], 4)
 
     sort_path = None if args.no_sort_path else local_vs_sort(ctx, step, rep, mem, torch, np)
     batched, sample = (None, []) if args.no_batched else batched_vs_plain(ctx, W, kc, torch, np)
     serving = None if args.no_serve else served(ctx, W, torch, np, args.serve_seconds)
     streams = None if args.no_streams else streams_leg(ctx, W, kc, torch, np)
-    w4 = workload4_leg(ctx, W, kc, torch, np) if args.workload4 else None
+    w4 = None if args.no_workload4 else workload4_leg(ctx, W, kc, torch, np)
 
     cpu, exact = None, None
+    served_sample = serving.pop("sample", []) if serving else []
     if not args.no_cpu_baseline:
         cpu, exact, sample_exact = cpu_baseline_leg(job, rep, mem, args.cpu_seconds, np, sample)
         if batched is not None:
             batched["bit_exact_sample"] = sample_exact
             batched["verified_instances"] = len(sample)
+            batched["oracle"] = oracle_pool_rate([j for j, _, _ in sample])
+        if serving is not None:
+            serving["bit_exact_sample"] = same_as_oracle(served_sample, np)
+            serving["verified_requests"] = len(served_sample)
+            serving["oracle"] = oracle_pool_rate([j for j, _, _ in served_sample])
         if streams is not None:
-            _, _, s_exact = cpu_baseline_leg(None, None, None, 0, np,
-                                             [(streams["job"], streams["report"], streams["memory"].cpu().numpy())])
-            streams["missing_event_bit_exact_vs_oracle"] = s_exact
+            streams["missing_event_bit_exact_vs_oracle"] = same_as_oracle(
+                [(streams["job"], streams["report"], streams["memory"].cpu().numpy())], np)
     if streams is not None:
         for k in ("job", "report", "memory"):
             streams.pop(k)
@@ -162,33 +170,48 @@ def main():
     print(json.dumps(out), flush=True)
     ctx.close()
     if exact is False or (batched and batched.get("bit_exact_sample") is False) or \
+            (serving and serving.get("bit_exact_sample") is False) or \
             (sort_path and not sort_path["same_reports"]) or \
             (streams and (not streams["same_otherwise"] or streams.get("missing_event_bit_exact_vs_oracle") is False)):
         sys.exit(1)
 
 
-# Peak of the interpreter's resource: int32 vector lane-operations.  256 CUs x
-# 4 SIMDs x 16 lanes, one wave64 int32 VALU instruction per SIMD every 4 cycles
-# = 64 lane-ops per CU per clock, at 2.4 GHz.  (The 157.3 TFLOP/s fp32 figure
-# counts an FMA as two flops and packed dual issue; int32 has neither.)
+# Peak of the free run's ALU resource, reported beside the HBM roofline:
+# int32 vector lane-operations.  256 CUs x 4 SIMDs x 16 lanes, one wave64
+# int32 VALU instruction per SIMD every 4 cycles = 64 lane-ops per CU per
+# clock, at 2.4 GHz.  (The 157.3 TFLOP/s fp32 figure counts an FMA as two
+# flops and packed dual issue; int32 has neither.)
 INT32_LANE_OPS_PEAK_G = 256 * 64 * 2.4       # G lane-ops/s = 39,321.6
+# Algorithmic HBM bytes of the checking path: each access record written once
+# and read back once (8 + 8 bytes), plus the simulated kernel's own 4-byte
+# word for each global-space access.
+BYTES_PER_RECORD = 16
+BYTES_PER_GLOBAL_ACCESS = 4
 
 
-def interp_roofline(stats, steps, records, value, per, detail):
-    """Roofline of the dominant kernel, the free-run interpreter.  Its
-    algorithmic work is one int32 lane-operation per simulated
-    thread-instruction (the library counts the free run's thread-instructions
-    from the fuel each thread spent); its duration is the library's HIP-event
-    time of the interpreter launch on the launch stream."""
+def free_run_roofline(stats, steps, records, value, per, detail):
+    """HBM roofline of the dominant kernel, the free run: its algorithmic
+    bytes per launch (16 B per access record it checks + 4 B per global-space
+    access of the simulated kernel) over its average duration, timed with HIP
+    events inside the library on the launch stream.  The same kernel's
+    instruction rate against the int32 lane-op peak is kept beside it."""
     instr = stats["instructions"] / steps
-    dur_s = per["interp_ms"] / 1e3 / max(1.0, stats["interp_launches"] / steps)
-    achieved = instr / dur_s / 1e9 if dur_s > 0 else 0.0
+    gacc = stats["global_accesses"] / steps
+    launches = max(1.0, stats["interp_launches"] / steps)
+    dur_s = per["interp_ms"] / 1e3 / launches
+    alg_bytes = BYTES_PER_RECORD * records + BYTES_PER_GLOBAL_ACCESS * gacc
+    achieved = alg_bytes / dur_s / 1e9 if dur_s > 0 else 0.0
+    lane_ops = instr / dur_s / 1e9 if dur_s > 0 else 0.0
     kernel = "kc_jit_free_local_256" if stats.get("jit_launches", 0) > 0 else "k_interp_free_local"
-    traffic = measured_traffic(kernel)
-    return {"bound": "alu", "kernel": kernel, "achieved": round(achieved, 1),
-            "peak": INT32_LANE_OPS_PEAK_G, "unit": "G thread-instructions/s (int32 lane-ops/s)",
-            "frac": round(achieved / INT32_LANE_OPS_PEAK_G, 5), "traffic": traffic,
-            "avg_ms": round(per["interp_ms"], 4), "thread_instructions_per_launch": int(instr),
+    return {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": measured_traffic(kernel),
+            "algorithmic_bytes_per_launch": int(alg_bytes), "records_per_launch": records,
+            "global_accesses_per_launch": int(gacc),
+            "avg_ms": round(per["interp_ms"] / launches, 4),
+            "alu": {"achieved": round(lane_ops, 1), "peak": INT32_LANE_OPS_PEAK_G,
+                    "unit": "G thread-instructions/s (int32 lane-ops/s)",
+                    "frac": round(lane_ops / INT32_LANE_OPS_PEAK_G, 5),
+                    "thread_instructions_per_launch": int(instr)},
             "stage_ms": {k: round(detail[k], 4) for k in per},
             "replay_detail_ms": {k: round(detail[k], 4) for k in
                                  ("replay_lockstep_ms", "replay_sort_ms", "replay_check_ms",
@@ -198,8 +221,26 @@ def interp_roofline(stats, steps, records, value, per, detail):
             "sorted_checks_per_step": stats["sorted_checks"] / steps,
             "replay_sorted_checks_per_step": stats["replay_sorted_checks"] / steps,
             "log_entries_per_step": stats["log_entries"] / steps,
-            "path_hbm_algorithmic_gbs": round(value * 16 / 1e9, 1),
-            "path_hbm_algorithmic_frac": round(value * 16 / (HBM_PEAK_GBS * 1e9), 4)}
+            "path_hbm_algorithmic_gbs": round(value * BYTES_PER_RECORD / 1e9, 1),
+            "path_hbm_algorithmic_frac": round(value * BYTES_PER_RECORD / (HBM_PEAK_GBS * 1e9), 4)}
+
+
+def copy_bandwidth(torch, n_bytes=1 << 30, reps=5):
+    """Achievable HBM bandwidth: a device-to-device copy of 1 GiB (read +
+    write counted), best of ``reps``, timed with events on the current stream."""
+    src = torch.ones(n_bytes // 4, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = float("inf")
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        b.record()
+        b.synchronize()
+        best = min(best, a.elapsed_time(b) / 1e3)
+    del src, dst
+    return round(2 * n_bytes / best / 1e9, 1)
 
 
 def measured_traffic(kernel):
@@ -225,29 +266,82 @@ def _same(rep, got, orc, np):
             and bool(np.array_equal(got, orc.memory)))
 
 
+def host_cpu():
+    """Model name of the host CPU (from /proc/cpuinfo) and its core count."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count() or 1
+
+
+def same_as_oracle(sample, np):
+    """Every (job, report, final memory) of ``sample`` equals the oracle's run
+    (the oracle runs on every host core)."""
+    from concurrent.futures import ThreadPoolExecutor
+    from oracle import oracle as O
+    ok = True
+    with ThreadPoolExecutor(max_workers=host_cpu()[1]) as ex:
+        for (j, r, m), orc in zip(sample, ex.map(O.run_job, [j for j, _, _ in sample])):
+            if not _same(r, m, orc, np):
+                print(f"bench: an instance differs from the oracle: {getattr(j, 'meta', '')}", file=sys.stderr)
+                ok = False
+    return ok
+
+
+def oracle_pool_rate(jobs, one_core_seconds=3.0):
+    """The oracle over independent instances on every host core (a thread
+    pool: the oracle's C code runs without the interpreter lock) and on one
+    core (the instances in order until ``one_core_seconds`` have passed), in
+    records/s."""
+    from concurrent.futures import ThreadPoolExecutor
+    from oracle import oracle as O
+    if not jobs:
+        return None
+    model, cores = host_cpu()
+    with ThreadPoolExecutor(max_workers=cores) as ex:
+        t0 = time.perf_counter()
+        recs = sum(r.records for r in ex.map(O.run_job, jobs))
+        allc = time.perf_counter() - t0
+    one_recs, n_one = 0, 0
+    t0 = time.perf_counter()
+    for j in jobs:
+        one_recs += O.run_job(j).records
+        n_one += 1
+        if time.perf_counter() - t0 > one_core_seconds:
+            break
+    one = time.perf_counter() - t0
+    return {"instances": len(jobs), "records": recs, "all_cores_records_per_s": round(recs / allc, 1),
+            "one_core_records_per_s": round(one_recs / one, 1), "one_core_instances": n_one,
+            "cores": cores, "cpu": model}
+
+
 def cpu_baseline_leg(job, rep, mem, cpu_seconds, np, sample=()):
     """The oracle on the host cores: its rate on the same workload, and the
     bit-exact comparison of the GPU's last step (and of a sample of batched
     instances, (job, report, final memory)) with the oracle's runs."""
     from oracle import oracle as O
-    if job is None:             # only the sample
-        return None, None, all(_same(r, m, O.run_job(j), np) for j, r, m in sample)
     t_o = time.perf_counter()
     orc = O.run_job(job)
     oracle_s = time.perf_counter() - t_o
     exact = _same(rep, mem.cpu().numpy(), orc, np)
     if not exact:
         print("bench: GPU result differs from the oracle", file=sys.stderr)
-    sample_exact = all(_same(r, m, O.run_job(j), np) for j, r, m in sample)
-    if not sample_exact:
-        print("bench: a batched instance differs from the oracle", file=sys.stderr)
+    sample_exact = same_as_oracle(sample, np)
     reps = max(1, int(cpu_seconds / max(oracle_s, 1e-3)))
     t_c = time.perf_counter()
     for _ in range(reps):
         O.run_job(job)
     cs = time.perf_counter() - t_c
+    model, ncores = host_cpu()
     cpu = {"value": round(orc.records * reps / cs, 1), "unit": "records/s", "cores": 1, "kind": "oracle",
-           "sample": f"the whole workload run {reps}x by the single-threaded C oracle ({cs:.1f} s)"}
+           "sample": f"the whole workload run {reps}x by the single-threaded C oracle ({cs:.1f} s); one "
+                     f"instance, so one core", "host_cpu": model, "host_cores": ncores}
     return cpu, exact, sample_exact
 
 
@@ -280,7 +374,7 @@ def local_vs_sort(ctx, step, rep, mem, torch, np, steps=10):
             "same_reports": same}
 
 
-def batched_vs_plain(ctx, W, kc, torch, np, reps=3, plain_sample=200, verify=40):
+def batched_vs_plain(ctx, W, kc, torch, np, reps=3, plain_sample=200, verify=400):
     """Workload 3 (10,000 mixed instances, seed 12116196): the whole set as one
     batch (kc_batch_submit + kc_poll) against one plain kc_launch per instance
     on a sample of instances; both on the same resident memories (the
@@ -312,7 +406,8 @@ def batched_vs_plain(ctx, W, kc, torch, np, reps=3, plain_sample=200, verify=40)
         lat.append(time.perf_counter() - t0)
         prec += r.records
     plain_rate = prec / sum(lat)
-    sample = [(jobs[i], res[i], mems[i].cpu().numpy()) for i in idx[:verify]]
+    vidx = list(range(0, len(jobs), max(1, len(jobs) // verify)))[:verify]
+    sample = [(jobs[i], res[i], mems[i].cpu().numpy()) for i in vidx]
     lat_ms = sorted(x * 1e3 for x in lat)
     return {"workload": "workload 3: 10000 instances (tree/stencil/transpose, 1-64 blocks x 32-1024 threads, "
                         "20% seeded faults)",
@@ -416,6 +511,11 @@ def served(ctx, W, torch, np, seconds, rates=(1000.0, 5000.0, 20000.0)):
                                  "p50_ms": round(res["p50_ms"], 3), "p99_ms": round(res["p99_ms"], 3),
                                  "wall_s": round(res["wall_s"], 3), "batches": res["batches"],
                                  "mean_batch": round(res["mean_batch"], 1)}
+    # an untimed run at the highest rate keeps every 25th request's report and
+    # final memory for the comparison with the oracle (big trees included)
+    res = srv.run(W.pooled_requests(rates[-1], 0.25, small, big, seed=W.BASE_SEED + 55), pristine=pristine,
+                  keep_every=25)
+    out["sample"] = res["sample"]
     return out
 
 

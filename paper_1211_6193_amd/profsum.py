@@ -6,6 +6,8 @@
         per kernel name and launch shape: dispatch count, mean/min/max duration
     python -m paper_1211_6193_amd.profsum counters DB
         per kernel name: dispatches and the mean of each PMC counter per dispatch
+    python -m paper_1211_6193_amd.profsum counters_by_grid DB [NAME]
+        the same per kernel name and launch shape (grid work-items, workgroup size)
     python -m paper_1211_6193_amd.profsum traffic FETCH_DB WRITE_DB COPY_FETCH_DB COPY_WRITE_DB KERNEL OUT.json
         HBM bytes per dispatch of KERNEL from FETCH_SIZE and WRITE_SIZE passes,
         each scaled by what the same counter reads for a device copy of a
@@ -80,6 +82,29 @@ def counter_means(db: str):
     return {n: (len(nd[n]), {k: v / len(nd[n]) for k, v in agg[n].items()}) for n in agg}
 
 
+def counter_means_by_grid(db: str):
+    """{(kernel name, grid work-items, workgroup size): (dispatches, {counter: mean per dispatch})}"""
+    c = sqlite3.connect(db)
+    shape = {did: (g, w) for did, g, w in c.execute("select dispatch_id, grid_x, workgroup_x from kernels")}
+    agg = collections.defaultdict(lambda: collections.defaultdict(float))
+    nd = collections.defaultdict(set)
+    for name, did, cn, cv in c.execute("select name, dispatch_id, counter_name, counter_value from pmc_events"):
+        key = (name,) + shape.get(did, (0, 0))
+        agg[key][cn] += cv
+        nd[key].add(did)
+    return {k: (len(nd[k]), {n: v / len(nd[k]) for n, v in agg[k].items()}) for k in agg}
+
+
+def counters_by_grid(db: str, like: str = "") -> str:
+    out = []
+    for (n, g, w), (d, m) in sorted(counter_means_by_grid(db).items(), key=lambda kv: -sum(kv[1][1].values())):
+        if like and like not in n:
+            continue
+        out.append(f"{_short(n)}\tgrid={g}\twg={w}\tdispatches={d}\t" +
+                   "\t".join(f"{k}={v:.6g}" for k, v in sorted(m.items())))
+    return "\n".join(out)
+
+
 def counters(db: str) -> str:
     out = []
     for n, (d, m) in sorted(counter_means(db).items(), key=lambda kv: -sum(kv[1][1].values())):
@@ -122,6 +147,8 @@ def main(argv):
             print(dispatches(argv[2], like))
     elif mode == "counters":
         print(counters(argv[2]))
+    elif mode == "counters_by_grid":
+        print(counters_by_grid(argv[2], argv[3] if len(argv) > 3 else ""))
     elif mode == "traffic":
         print(traffic(*argv[2:8]))
     else:

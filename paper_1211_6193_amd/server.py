@@ -134,11 +134,14 @@ class Server:
         self.batch = kc.Batch(ctx)
 
     def run(self, stream: Sequence[Tuple[float, object]], keep_reports: bool = False,
-            keep_memory: bool = False, pristine: Optional[Dict[int, object]] = None) -> Dict:
+            keep_memory: bool = False, pristine: Optional[Dict[int, object]] = None,
+            keep_every: int = 0) -> Dict:
         """Serve ``stream`` = [(arrival_s, job)].  ``pristine`` optionally maps
         id(job) to a device tensor holding that job's initial memory; such a
         request's memory is a device-to-device copy of it on the batch's
-        stream instead of an upload from the host."""
+        stream instead of an upload from the host.  With ``keep_every`` = k,
+        every k-th request's (job, report, final memory) is returned under
+        "sample"."""
         import torch
         reqs = [Request(i, t, j, estimate_bytes(j)) for i, (t, j) in enumerate(stream)]
         pending = collections.deque(reqs)
@@ -147,6 +150,7 @@ class Server:
         records = 0
         busy_batches = 0
         memories: Dict[int, np.ndarray] = {}
+        sample = []
         while pending or self.adm.queue or inflight:
             now = time.perf_counter() - t0
             while pending and pending[0].arrival <= now:
@@ -166,6 +170,8 @@ class Server:
                         r.report = reps[i]
                     if keep_memory:
                         memories[r.rid] = m.cpu().numpy()
+                    if keep_every and r.rid % keep_every == 0:
+                        sample.append((r.job, reps[i], m.cpu().numpy()))
                 self.adm.finish(batch)
                 self.free_streams.append(si)
             inflight = still
@@ -209,4 +215,6 @@ class Server:
             out["reports"] = {r.rid: r.report for r in reqs}
         if keep_memory:
             out["memories"] = memories
+        if keep_every:
+            out["sample"] = sample
         return out
