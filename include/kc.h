@@ -142,7 +142,9 @@ kc_status kc_ctx_set_option(kc_ctx *ctx, const char *key, int64_t value);
  * (in-bounds global-memory accesses of the free run), "jit_launches", "jit_replays"
  * (replay launches on specialised kernels),
  * "jit_compiled", "jit_compile_ms", "jit_failures", "site_replays",
- * "cross_launch_races", "alloc_findings".
+ * "cross_launch_races", "alloc_findings", "noalloc_calls" and
+ * "noalloc_scratch_peak" (calls of kc_launch_noalloc and the most bytes of
+ * its static scratch area one of them used).
  * Timings are only collected with option "timing" set.  "option.<name>"
  * reads back the current value of option <name>.  Returns 0 for an unknown
  * key. */
@@ -178,6 +180,30 @@ typedef struct {
  * Errors: KC_E_INVAL, KC_E_NOMEM, KC_E_BUDGET, KC_E_OVERFLOW, KC_E_DEVICE. */
 kc_status kc_launch(kc_ctx *ctx, const kc_launch_desc *desc, int32_t *dev_mem, uint64_t n_words,
                     void *stream, kc_report **out);
+
+/* For callers that cannot allocate device memory (code that must not call
+ * hipMalloc: under stream capture, in tight serving loops, in harnesses that
+ * forbid it): the same launch as kc_launch -- same arguments, checks, report
+ * and final memory -- but the call allocates no device memory and no pinned
+ * host memory.  Every device buffer of the run (snapshot, access log, sort
+ * and table scratch, counters, finding lists) is carved from a static
+ * scratch area of KC_NOALLOC_SCRATCH_BYTES bytes per device, which the
+ * library's code object holds on every device it is loaded on until the
+ * process ends; the host staging and the events it uses are made by
+ * kc_ctx_create.  The interpreter runs (option "jit" is ignored: the
+ * specialised kernels would be compiled and loaded at run time); the other
+ * options apply.  The report itself lives on the host heap, as kc_launch's.
+ * All calls on one device share its area, which keeps the last call's
+ * contents (every buffer a call reads is cleared or written by that call
+ * first).  The library serialises these calls per device with a lock; work
+ * of two calls that overlapped on one device would race on the area.
+ * Errors: those of kc_launch; KC_E_BUDGET when the run needs more than the
+ * area (for example a memory of more than KC_NOALLOC_SCRATCH_BYTES / 4 words,
+ * which the launch-start snapshot alone would exceed) or its results more
+ * than the host staging set up at context creation. */
+#define KC_NOALLOC_SCRATCH_BYTES ((uint64_t)64 << 20)
+kc_status kc_launch_noalloc(kc_ctx *ctx, const kc_launch_desc *desc, int32_t *dev_mem, uint64_t n_words,
+                            void *stream, kc_report **out);
 
 /* An event dependency between two launches of a job (Section 3 "Streams
  * and events"): launch `after` starts only once launch `before` has finished,

@@ -83,12 +83,40 @@ inline uint32_t bits_for(uint64_t count) {   // bits to hold values 0 .. count-1
     return b;
 }
 
-// Grow-only device buffer.
+// A fixed device area from which buffers are carved while a call runs
+// without allocating (kc_launch_noalloc): bump allocation from `base`,
+// restarted at every such call.  Set for the calling thread only.
+struct Arena {
+    char *base = nullptr;
+    size_t cap = 0, used = 0, peak = 0;
+};
+thread_local Arena *t_arena = nullptr;
+
+// Grow-only device buffer.  Its contents do not survive a growth.
 struct DBuf {
     void *p = nullptr;
     size_t bytes = 0;
+    bool carved = false;    // p lies in the calling thread's arena (never freed)
     void reserve(size_t need) {
         if (need <= bytes) return;
+        if (t_arena) {
+            Arena &a = *t_arena;
+            const size_t nb = (need + 255) & ~size_t(255);
+            if (nb > a.cap - a.used)
+                throw KcError{KC_E_BUDGET, "the launch needs more device memory than the static scratch area holds (" +
+                                               std::to_string(a.cap) + " bytes)"};
+            p = a.base + a.used;
+            bytes = nb;
+            carved = true;
+            a.used += nb;
+            a.peak = std::max(a.peak, a.used);
+            return;
+        }
+        if (carved) {
+            p = nullptr;
+            bytes = 0;
+            carved = false;
+        }
         size_t nb = std::max(need, bytes + bytes / 2);
         nb = (nb + 4095) & ~size_t(4095);
         if (p) HIPCHK(hipFree(p));
@@ -106,9 +134,10 @@ struct DBuf {
         bytes = nb;
     }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p && !carved) (void)hipFree(p);
         p = nullptr;
         bytes = 0;
+        carved = false;
     }
     template <class T> T *as() const { return (T *)p; }
 };
@@ -124,6 +153,9 @@ struct Workspace {
     size_t h_pin_bytes = 0;
     void pin_reserve(size_t need) {
         if (need <= h_pin_bytes) return;
+        if (t_arena)
+            throw KcError{KC_E_BUDGET, "the launch's results need more than the " + std::to_string(h_pin_bytes) +
+                                           " bytes of host staging set up for calls that allocate nothing"};
         if (h_pin) HIPCHK(hipHostFree(h_pin));
         h_pin = d_pin = nullptr;
         h_pin_bytes = 0;
@@ -140,6 +172,15 @@ struct Workspace {
         HIPCHK(hipHostMalloc((void **)&h_ctr, sizeof(DevCounters) * 2, hipHostMallocDefault));
         for (auto &e : ev) HIPCHK(hipEventCreate(&e));
         init = true;
+    }
+    // Forget every carved buffer (the arena restarts at each call).
+    void forget_carved() {
+        DBuf *all[] = {&units, &items, &comp_off, &comp_blocks, &mask, &snap, &log, &alt, &rlog,
+                       &ralt, &fs, &hist, &part, &faults, &rfaults, &races, &edges, &blk_recs,
+                       &rblk_recs, &blk_flags, &rflags, &ctr, &rctr, &lraces, &rlraces, &longseg, &covlist,
+                       &rtable, &ftable, &downer, &dflags, &blk_instr, &blk_grecs, &blk_log, &blk_held, &blk_off};
+        for (auto *b : all)
+            if (b->carved) b->release();
     }
     size_t device_bytes() const {
         const DBuf *all[] = {&units, &items, &comp_off, &comp_blocks, &mask, &snap, &log, &alt, &rlog,
@@ -192,14 +233,18 @@ struct Options {
     int jit = 0;                    // program-specialised free-run kernels (compiled at first use)
     int jit_waves = 0;              // their occupancy target, waves per SIMD (0: the compiler's choice)
     int sites = 0;                  // source sites of races (one more replay of the racy blocks)
+    int arena = 0;                  // set by the library: buffers come from the static scratch area
 };
 
 }  // namespace
 
 struct Batch;
+struct ScratchDevice;
 
 struct kc_ctx {
     int device = 0;
+    ScratchDevice *scratch = nullptr;           // the device's static scratch area (kc_launch_noalloc)
+    std::unique_ptr<Workspace> fixed_ws;        // its workspace: events and host staging made at creation
     uint64_t budget = 0;
     Options opt;
     std::string err;
@@ -252,6 +297,10 @@ struct kc_ctx {
     void stat_add(const char *k, double v) {
         std::lock_guard<std::mutex> g(mu);
         stats[k] += v;
+    }
+    void stat_max(const char *k, double v) {
+        std::lock_guard<std::mutex> g(mu);
+        stats[k] = std::max(stats[k], v);
     }
 };
 
@@ -799,12 +848,13 @@ struct Stage {
                 off += u.n_words;
             }
         }
-        if (ctx->budget && ws.device_bytes() > ctx->budget)
+        if (!opt.arena && ctx->budget && ws.device_bytes() > ctx->budget)
             throw KcError{KC_E_BUDGET, "workspace exceeds the HBM budget"};
         upload_units();
         if (check) HIPCHK(launch_copy_units(ws.units.as<DevUnit>(), n, max_words, true, nullptr, s));
 
         uint64_t log_cap = check ? std::max<uint64_t>(ctx->log_hint(), 1024) : 0;
+        if (opt.arena) log_cap = std::min<uint64_t>(log_cap, 1u << 20);     // grows on overflow
         if (check) ws.log.reserve(log_cap * 8);
         uint32_t fault_cap = 4096;
         ctx->caps(fault_cap, lrace_cap);
@@ -815,7 +865,7 @@ struct Stage {
         // held representatives go to per-block regions (no queue on the log
         // counter at the end of every block) while the regions stay small
         held_regions = check && opt.local && opt.shadow_global && kp.ab <= 31 &&
-                       (uint64_t)total_blocks * REP_HOLD * 8 <= (256ull << 20);
+                       (uint64_t)total_blocks * REP_HOLD * 8 <= (opt.arena ? (16ull << 20) : (256ull << 20));
         if (held_regions) {
             ws.blk_log.reserve((size_t)total_blocks * REP_HOLD * 8);
             ws.blk_held.reserve((size_t)total_blocks * 4);
@@ -864,7 +914,7 @@ struct Stage {
             bool again = false;
             if (check && (c.flags & FLAG_LOG_OVERFLOW)) {
                 log_cap = c.log_count + c.log_count / 8 + 1024;
-                if (ctx->budget && ws.device_bytes() + log_cap * 16 > ctx->budget)
+                if (!opt.arena && ctx->budget && ws.device_bytes() + log_cap * 16 > ctx->budget)
                     throw KcError{KC_E_BUDGET, "access log does not fit the HBM budget"};
                 ws.log.reserve(log_cap * 8);
                 again = true;
@@ -1617,11 +1667,19 @@ void cross_launch_check(kc_ctx *ctx, Workspace &ws, hipStream_t s, Stage &st, ui
 
 // Run every launch of `jobs` in order, stage by stage (launch index j of all
 // jobs still running), and build one report per job.
-void run_jobs(kc_ctx *ctx, const kc_job *jobs, uint32_t n_jobs, hipStream_t s, std::vector<kc_report *> &reports) {
+// With `fixed` (a call that allocates nothing: the calling thread's arena is
+// set) the stage buffers are carved from the arena and the interpreter runs
+// (the specialised kernels would be compiled and loaded at run time).
+void run_jobs(kc_ctx *ctx, const kc_job *jobs, uint32_t n_jobs, hipStream_t s, std::vector<kc_report *> &reports,
+              Workspace *fixed = nullptr) {
     HIPCHK(hipSetDevice(ctx->device));
-    const Options opt = ctx->options();
-    auto wsp = ctx->acquire();
-    Workspace &ws = *wsp;
+    Options opt = ctx->options();
+    if (fixed) {
+        opt.jit = 0;
+        opt.arena = 1;
+    }
+    std::unique_ptr<Workspace> wsp = fixed ? nullptr : ctx->acquire();
+    Workspace &ws = fixed ? *fixed : *wsp;
     std::vector<std::vector<DBuf>> sums(n_jobs);
     std::vector<DBuf> allocated(n_jobs);       // memory objects: per job, one bit per allocated word
     auto free_sums = [&]() {
@@ -1730,12 +1788,62 @@ void run_jobs(kc_ctx *ctx, const kc_job *jobs, uint32_t n_jobs, hipStream_t s, s
         free_sums();
         for (auto *r : reports) delete r;
         reports.clear();
-        ctx->release(std::move(wsp));
+        if (wsp) ctx->release(std::move(wsp));
         throw;
     }
     free_sums();
-    ctx->release(std::move(wsp));
+    if (wsp) ctx->release(std::move(wsp));
 }
+
+// ---------------------------------------------------------------------------
+// Static scratch area of kc_launch_noalloc
+// ---------------------------------------------------------------------------
+}  // namespace
+
+// Device memory of the calls that allocate nothing: one area per device, part
+// of the library's code object, so each device that loads the library holds
+// its own copy until the process ends.  Host code never hands this name to a
+// kernel or a copy (on the host it is only a stand-in): it reads the device
+// address once per device with hipGetSymbolAddress and uses that.
+static __device__ __align__(256) unsigned char scratch[KC_NOALLOC_SCRATCH_BYTES];
+
+struct ScratchDevice {
+    char *ptr = nullptr;    // device address of `scratch` on this device
+    std::mutex mu;          // calls on the device take turns with the area
+};
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::map<int, std::unique_ptr<ScratchDevice>> g_scratch;
+
+// The scratch area of device `dev`, which must be the current device; its
+// address is looked up on the first call for the device.
+ScratchDevice *scratch_device(int dev) {
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    auto it = g_scratch.find(dev);
+    if (it != g_scratch.end()) return it->second.get();
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+        (void)hipGetLastError();
+        throw KcError{KC_E_DEVICE, std::string("hipGetSymbolAddress of the static scratch area: ") +
+                                       hipGetErrorString(e)};
+    }
+    auto d = std::make_unique<ScratchDevice>();
+    d->ptr = (char *)p;
+    return g_scratch.emplace(dev, std::move(d)).first->second.get();
+}
+
+// Host staging of the fixed workspace: counters, per-block counts and the
+// first findings and races of a launch (made at context creation).
+constexpr size_t kFixedPinBytes = 1u << 20;
+
+// Arena of the calling thread for the duration of a call.
+struct ArenaUse {
+    explicit ArenaUse(Arena *a) { t_arena = a; }
+    ~ArenaUse() { t_arena = nullptr; }
+};
 
 }  // namespace
 
@@ -2000,6 +2108,10 @@ kc_status kc_ctx_create(int hip_device, uint64_t hbm_budget_bytes, const char *t
         c = new kc_ctx();
         c->device = hip_device;
         c->budget = hbm_budget_bytes;
+        c->scratch = scratch_device(hip_device);
+        c->fixed_ws = std::make_unique<Workspace>();
+        c->fixed_ws->setup();
+        c->fixed_ws->pin_reserve(kFixedPinBytes);
         if (tune_cache && *tune_cache) {
             kc_status st = apply_tune_cache(c, tune_cache);
             if (st != KC_OK) {
@@ -2035,6 +2147,7 @@ void kc_ctx_destroy(kc_ctx *ctx) {
     }
     (void)hipSetDevice(ctx->device);
     ctx->free_ws.clear();
+    ctx->fixed_ws.reset();
     delete ctx;
 }
 
@@ -2103,6 +2216,36 @@ kc_status kc_launch(kc_ctx *ctx, const kc_launch_desc *desc, int32_t *dev_mem, u
         kc_job job{desc, 1, dev_mem, n_words, 0};
         std::vector<kc_report *> reps;
         run_jobs(ctx, &job, 1, (hipStream_t)stream, reps);
+        *out = reps[0];
+        return KC_OK;
+    });
+}
+
+kc_status kc_launch_noalloc(kc_ctx *ctx, const kc_launch_desc *desc, int32_t *dev_mem, uint64_t n_words,
+                            void *stream, kc_report **out) {
+    if (!ctx || !out) return KC_E_INVAL;
+    *out = nullptr;
+    if (ctx->poisoned) return KC_E_DEVICE;
+    std::string why = validate_desc(desc, dev_mem, n_words);
+    if (!why.empty()) {
+        ctx->err = why;
+        return KC_E_INVAL;
+    }
+    return guarded(ctx, [&] {
+        if (n_words * 4 > KC_NOALLOC_SCRATCH_BYTES)      // the launch-start snapshot alone would not fit
+            throw KcError{KC_E_BUDGET, "memory of " + std::to_string(n_words) +
+                                           " words exceeds the static scratch area"};
+        std::lock_guard<std::mutex> g(ctx->scratch->mu);
+        Arena arena;
+        arena.base = ctx->scratch->ptr;
+        arena.cap = KC_NOALLOC_SCRATCH_BYTES;
+        ArenaUse use(&arena);
+        ctx->fixed_ws->forget_carved();         // the previous call's buffers
+        kc_job job{desc, 1, dev_mem, n_words, 0};
+        std::vector<kc_report *> reps;
+        run_jobs(ctx, &job, 1, (hipStream_t)stream, reps, ctx->fixed_ws.get());
+        ctx->stat_add("noalloc_calls", 1);
+        ctx->stat_max("noalloc_scratch_peak", (double)arena.peak);
         *out = reps[0];
         return KC_OK;
     });

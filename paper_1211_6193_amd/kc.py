@@ -26,7 +26,7 @@ DEADLOCK, DIVERGENCE, OOB, FUEL, ARITH = 1, 2, 3, 4, 5
 
 # Every entry point include/kc.h declares.
 EXPORTS = ["kc_ctx_create", "kc_ctx_destroy", "kc_ctx_set_option", "kc_ctx_get_stat", "kc_last_error",
-           "kc_program_load", "kc_program_free", "kc_launch", "kc_batch_submit", "kc_poll",
+           "kc_program_load", "kc_program_free", "kc_launch", "kc_launch_noalloc", "kc_batch_submit", "kc_poll",
            "kc_report_records", "kc_report_launches_completed", "kc_report_races", "kc_report_faults",
            "kc_report_race_sites",
            "kc_report_tag", "kc_report_free", "kc_reports_collect", "kc_reports_free"]
@@ -87,6 +87,7 @@ def load_library(path: str = LIB_PATH):
         "kc_program_load": ([vp, vp, u32, C.POINTER(vp)], C.c_int),
         "kc_program_free": ([vp], None),
         "kc_launch": ([vp, C.POINTER(LaunchDesc), vp, u64, vp, C.POINTER(vp)], C.c_int),
+        "kc_launch_noalloc": ([vp, C.POINTER(LaunchDesc), vp, u64, vp, C.POINTER(vp)], C.c_int),
         "kc_batch_submit": ([vp, C.POINTER(JobDesc), u32, vp, C.POINTER(u64)], C.c_int),
         "kc_poll": ([vp, u64, C.c_int, C.POINTER(vp), u32], C.c_int),
         "kc_report_records": ([vp], u64),
@@ -298,6 +299,20 @@ def launch(ctx: Context, prog: Program, grid, block, shmem_bytes: int, mem, para
     out = C.c_void_p()
     ctx._check(ctx.lib.kc_launch(ctx.h, C.byref(d), mem.data_ptr(), mem.numel(), _stream_handle(stream),
                                  C.byref(out)), "kc_launch")
+    return _take_report(ctx.lib, out)
+
+
+def launch_noalloc(ctx: Context, prog: Program, grid, block, shmem_bytes: int, mem, params: Sequence[int] = (),
+                   stream=None) -> Report:
+    """kc_launch_noalloc: the same launch as ``launch``, with every device
+    buffer carved from the library's static scratch area (no allocation)."""
+    import torch
+    if mem.dtype != torch.int32 or not mem.is_cuda or not mem.is_contiguous():
+        raise ValueError("mem must be a contiguous int32 tensor on the GPU")
+    d = _desc(prog, grid, block, shmem_bytes, params)
+    out = C.c_void_p()
+    ctx._check(ctx.lib.kc_launch_noalloc(ctx.h, C.byref(d), mem.data_ptr(), mem.numel(), _stream_handle(stream),
+                                         C.byref(out)), "kc_launch_noalloc")
     return _take_report(ctx.lib, out)
 
 
