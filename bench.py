@@ -51,7 +51,14 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB three times (the known-size kernel that scales "
                          "HBM counter readings) and exit")
+    ap.add_argument("--only", choices=("none", "sort", "batched", "serve", "streams", "workload4"),
+                    help="run the plain steps and this one optional leg only (no CPU baseline): for profiles")
     args = ap.parse_args()
+    if args.only:
+        for leg, flag in (("sort", "no_sort_path"), ("batched", "no_batched"), ("serve", "no_serve"),
+                          ("streams", "no_streams"), ("workload4", "no_workload4")):
+            setattr(args, flag, args.only != leg)
+        args.no_cpu_baseline = True
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (sharding the checker "
               f"over several GPUs is described, not implemented)", file=sys.stderr)

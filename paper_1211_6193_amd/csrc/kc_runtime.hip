@@ -166,11 +166,19 @@ struct Workspace {
         h_pin_bytes = nb;
     }
     hipEvent_t ev[16] = {};
+    // Side streams (default priority) on which the launches of one pipeline
+    // step run side by side, joined to the stage's stream by events.
+    static constexpr int kSide = 4;
+    hipStream_t side[kSide] = {};
+    hipEvent_t fork = nullptr, join[kSide] = {};
     bool init = false;
     void setup() {
         if (init) return;
         HIPCHK(hipHostMalloc((void **)&h_ctr, sizeof(DevCounters) * 2, hipHostMallocDefault));
         for (auto &e : ev) HIPCHK(hipEventCreate(&e));
+        for (auto &q : side) HIPCHK(hipStreamCreateWithFlags(&q, hipStreamNonBlocking));
+        HIPCHK(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+        for (auto &e : join) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         init = true;
     }
     // Forget every carved buffer (the arena restarts at each call).
@@ -200,6 +208,11 @@ struct Workspace {
         if (h_ctr) (void)hipHostFree(h_ctr);
         if (h_pin) (void)hipHostFree(h_pin);
         for (auto &e : ev)
+            if (e) (void)hipEventDestroy(e);
+        for (auto &q : side)
+            if (q) (void)hipStreamDestroy(q);
+        if (fork) (void)hipEventDestroy(fork);
+        for (auto &e : join)
             if (e) (void)hipEventDestroy(e);
     }
 };
@@ -576,6 +589,38 @@ struct Stage {
         }
     }
 
+    // Launches side by side: fork() makes the side streams wait for the work
+    // queued on the stage's stream so far; launch i goes to side(i); join()
+    // makes the stage's stream wait for every side stream used.
+    uint32_t side_used = 0;
+    void fork() {
+        HIPCHK(hipEventRecord(ws.fork, s));
+        side_used = 0;
+    }
+    hipStream_t side(uint32_t i) {
+        const uint32_t k = i % Workspace::kSide;
+        if (k >= side_used) {
+            for (uint32_t q = side_used; q <= k; q++) HIPCHK(hipStreamWaitEvent(ws.side[q], ws.fork, 0));
+            side_used = k + 1;
+        }
+        return ws.side[k];
+    }
+    void join() {
+        for (uint32_t q = 0; q < side_used; q++) {
+            HIPCHK(hipEventRecord(ws.join[q], ws.side[q]));
+            HIPCHK(hipStreamWaitEvent(s, ws.join[q], 0));
+        }
+        side_used = 0;
+    }
+
+    // Components of the replay grouped by program (contiguous in the uploaded
+    // component list): each group runs on that program's specialised replay
+    // kernels, the groups side by side.
+    struct CompGroup {
+        uint32_t first, count, unit, wg, shmax;
+    };
+    std::vector<CompGroup> comp_groups;
+
     DevCounters read_ctr(DBuf &c) {
         HIPCHK(hipMemcpyAsync(ws.h_ctr, c.p, sizeof(DevCounters), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
@@ -694,20 +739,50 @@ struct Stage {
                 HIPCHK(launch_interp(a, n_comp, wg, true, s));
                 return;
             }
-            // one program for every unit: its specialised replay kernels
-            bool one_program = true;
-            for (const auto &x : in) one_program = one_program && x.desc->prog == in[0].desc->prog;
-            JitFunctions f;
-            if (one_program && !hu.empty() && jit_for(0, f)) {
-                const hipError_t e = launch_jit_lockstep(f, a, n_comp, wg, s);
+            // each program's components on its specialised replay kernels,
+            // the programs side by side; the interpreter for the rest
+            std::vector<uint32_t> interp_groups;
+            bool forked = false;
+            uint32_t launched = 0;
+            for (uint32_t g = 0; g < comp_groups.size(); g++) {
+                const CompGroup &cg = comp_groups[g];
+                JitFunctions f;
+                if (!jit_for(cg.unit, f)) {
+                    interp_groups.push_back(g);
+                    continue;
+                }
+                InterpArgs ga = a;
+                ga.comp_off = ws.comp_off.as<uint32_t>() + cg.first;
+                ga.sh_words_max = cg.shmax;
+                ga.gst_bits = gst ? gst_bits_for(cg.wg) : 0u;
+                if (comp_groups.size() > 1 && !forked) {
+                    fork();
+                    forked = true;
+                }
+                const hipError_t e =
+                    launch_jit_lockstep(f, ga, cg.count, cg.wg, comp_groups.size() > 1 ? side(launched) : s);
                 if (e == hipSuccess) {
+                    launched++;
                     ctx->stat_add("jit_replays", 1);
-                    return;
+                    continue;
                 }
                 if (e != hipErrorInvalidValue) HIPCHK(e);
                 (void)hipGetLastError();
+                interp_groups.push_back(g);
             }
-            HIPCHK(launch_interp(a, n_comp, wg, true, s));
+            if (forked) join();
+            if (interp_groups.size() == comp_groups.size()) {      // one interpreter launch for all
+                HIPCHK(launch_interp(a, n_comp, wg, true, s));
+                return;
+            }
+            for (uint32_t g : interp_groups) {
+                const CompGroup &cg = comp_groups[g];
+                InterpArgs ga = a;
+                ga.comp_off = ws.comp_off.as<uint32_t>() + cg.first;
+                ga.sh_words_max = cg.shmax;
+                ga.gst_bits = gst ? gst_bits_for(cg.wg) : 0u;
+                HIPCHK(launch_interp(ga, cg.count, cg.wg, true, s));
+            }
             return;
         }
         // free run: one launch per (workgroup size, kernel) class; a unit whose
@@ -717,10 +792,11 @@ struct Stage {
         std::vector<JitFunctions> jf(hu.size());
         std::vector<char> use_jit(hu.size(), 0);
         for (uint32_t i = 0; i < hu.size(); i++) use_jit[i] = jit_for(i, jf[i]) ? 1 : 0;
-        auto launch = [&](InterpArgs args, uint32_t n_wg, uint32_t wg, bool jit, const JitFunctions &f) {
+        auto launch = [&](InterpArgs args, uint32_t n_wg, uint32_t wg, bool jit, const JitFunctions &f,
+                          hipStream_t q) {
             args.gst_bits = gst ? gst_bits_for(wg) : 0u;
             if (jit) {
-                const hipError_t e = launch_jit(f, args, n_wg, wg, s);
+                const hipError_t e = launch_jit(f, args, n_wg, wg, q);
                 if (e == hipSuccess) {
                     ctx->stat_add("jit_launches", 1);
                     return;
@@ -728,14 +804,14 @@ struct Stage {
                 if (e != hipErrorInvalidValue) HIPCHK(e);
                 (void)hipGetLastError();
             }
-            HIPCHK(launch_interp(args, n_wg, wg, false, s));
+            HIPCHK(launch_interp(args, n_wg, wg, false, q));
         };
         if (hu.size() == 1) {
             const uint32_t wg = (hu[0].nt + 63) / 64 * 64;
             a.items = nullptr;
             a.sh_words_max = hu[0].sh_words;
             a.stage = stage_for(wg);
-            launch(a, hu[0].nb, wg, use_jit[0] != 0, jf[0]);
+            launch(a, hu[0].nb, wg, use_jit[0] != 0, jf[0], s);
             return;
         }
         struct Class {
@@ -765,16 +841,21 @@ struct Stage {
         }
         ws.items.reserve(items.size() * sizeof(uint2));
         HIPCHK(hipMemcpyAsync(ws.items.p, items.data(), items.size() * sizeof(uint2), hipMemcpyHostToDevice, s));
+        // the classes side by side: each holds few blocks of long latency
         size_t ci = 0;
+        const bool par = classes.size() > 1;
+        if (par) fork();
         for (auto &kv : classes) {
             uint32_t shmax = 0;
             for (uint32_t ui : kv.second.units) shmax = std::max(shmax, hu[ui].sh_words);
             a.items = ws.items.as<uint2>() + ranges[ci].first;
             a.sh_words_max = shmax;
             a.stage = stage_for(kv.second.wg);
-            launch(a, (uint32_t)(ranges[ci].second - ranges[ci].first), kv.second.wg, kv.second.jit, kv.second.f);
+            launch(a, (uint32_t)(ranges[ci].second - ranges[ci].first), kv.second.wg, kv.second.jit, kv.second.f,
+                   par ? side((uint32_t)ci) : s);
             ci++;
         }
+        if (par) join();
     }
 
     // Compile the stage's programs that nobody has compiled yet, in parallel;
@@ -1087,11 +1168,27 @@ struct Stage {
         }
     }
 
-    // Upload components (lists of (unit, block)) for the lockstep kernel.
+    // Upload components (lists of (unit, block), each within one unit) for
+    // the lockstep kernels, grouped by program (comp_groups).
     void upload_comps(const std::vector<std::vector<uint2>> &comps) {
+        std::vector<uint32_t> order(comps.size());
+        std::iota(order.begin(), order.end(), 0u);
+        auto prog_of = [&](uint32_t c) { return in[comps[c][0].x].desc->prog; };
+        std::stable_sort(order.begin(), order.end(),
+                         [&](uint32_t x, uint32_t y) { return std::less<const void *>()(prog_of(x), prog_of(y)); });
+        comp_groups.clear();
         std::vector<uint32_t> off{0};
         std::vector<uint2> blocks;
-        for (auto &c : comps) {
+        for (uint32_t i = 0; i < order.size(); i++) {
+            const auto &c = comps[order[i]];
+            if (comp_groups.empty() || prog_of(order[i]) != prog_of(order[comp_groups.back().first]))
+                comp_groups.push_back(CompGroup{i, 0, c[0].x, 64, 0});
+            CompGroup &g = comp_groups.back();
+            g.count++;
+            for (auto &ub : c) {
+                g.wg = std::max<uint32_t>(g.wg, (hu[ub.x].nt + 63) / 64 * 64);
+                g.shmax = std::max(g.shmax, hu[ub.x].sh_words);
+            }
             blocks.insert(blocks.end(), c.begin(), c.end());
             off.push_back((uint32_t)blocks.size());
         }
