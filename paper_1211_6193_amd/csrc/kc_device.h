@@ -1375,6 +1375,12 @@ __device__ __forceinline__ uint64_t fetch_word(const BlockCtx &B, int cur) {
     return (uint32_t)cur < B.n_instr ? B.prog[(uint32_t)uni(cur)] : 0ull;
 }
 
+// 1 for a load, 2 for a store at `cur`, 0 otherwise (and past the end).
+__device__ __forceinline__ uint32_t prog_kind(const BlockCtx &B, int cur) {
+    const uint32_t op = uniu((uint32_t)fetch_word(B, cur) & 0xFFu);
+    return (op >> 4) == 5u ? 1u + (op & 1u) : 0u;
+}
+
 // One step's group: the running lanes of the wave at the smallest pc among
 // `todo` execute their instruction (loads read memory now, stores are held in
 // P); returns the lanes that took part.
@@ -1432,14 +1438,24 @@ __device__ __forceinline__ uint64_t lockstep_group(const InterpArgs &A, BlockCtx
 // when it took none (then the group steps through `exec` one instruction).
 //
 // `release()` runs after every completed episode (the results of barriers
-// with a predicate).
-template <bool LOCAL, class Exec, class Run, class Release>
+// with a predicate).  `kind(pc)` tells a load (1) or a store (2) from other
+// instructions (0; also past the end), `word(pc)` gives the program word
+// `exec` takes (the specialised kernels need neither from memory).
+//
+// The round's smallest parked step goes through one LDS word per round (three
+// used in turn: the next round's is reset before this round's barrier, after
+// every read of it two rounds ago), each wave taking the minimum of
+// (step << 1 | no store at it) with one atomic.
+template <bool LOCAL, class Exec, class Run, class Release, class Kind, class Word>
 __device__ __forceinline__ uint32_t run_block_lockstep(const InterpArgs &A, BlockCtx &B, const Shared &S,
                                                    const StoreTables &T, Lane &t, LogState &L, Exec &exec,
-                                                   Run &run, Release &release) {
+                                                   Run &run, Release &release, Kind &kind, Word &word) {
     constexpr uint32_t NO_STEP = 0xFFFFFFFFu;
     uint32_t epoch = 0;
-    uint32_t par = 0;               // round slots alternate so one barrier per round suffices
+    uint32_t rnd = 0;               // rounds of the block (selects the round word)
+    unsigned long long *RW = (unsigned long long *)S.eps;     // three round words
+    if (threadIdx.x == 0) RW[0] = ~0ull;
+    __syncthreads();
     bool clear = false;             // this lane won a location in the last store round: free its owner entry
     bool clear_sh = false;
     uint32_t clear_at = 0;
@@ -1456,30 +1472,35 @@ __device__ __forceinline__ uint32_t run_block_lockstep(const InterpArgs &A, Bloc
                 const int p = uni(__builtin_amdgcn_readlane(t.pc, (int)((uint32_t)__ffsll((long long)fm) - 1u)));
                 const bool mine = free_lane && t.pc == p;
                 const uint64_t grp = __ballot(mine);
-                const uint64_t w = fetch_word(B, p);
-                if ((uint32_t)p < B.n_instr && ((uniu((uint32_t)w) & 0xFFu) >> 4) == 5u) {
+                const uint32_t kd = kind(p);
+                if (kd != 0u) {
                     if (mine) {
                         parked = true;
-                        pst = (w & 1ull) != 0;
+                        pst = kd == 2u;
                     }
                     continue;
                 }
                 uint32_t k = run(grp, epoch);
                 if (k == 0) {
                     Pending none{false, false, 0, 0};
-                    lockstep_group<LOCAL>(A, B, S, t, L, none, epoch, grp, p, w, exec);
+                    lockstep_group<LOCAL>(A, B, S, t, L, none, epoch, grp, p, word(p), exec);
                     k = 1;
                 }
                 if (mine) ls += k;
             }
             // the smallest parked step of the wave, and whether a store waits there
             const bool waiting = t.st == ST_RUN && parked;
-            const uint32_t m = wave_min_u(waiting ? ls : NO_STEP);
-            const bool st_m = __ballot(waiting && ls == m && pst) != 0;
-            if (lane_id() == 0) {
-                S.slots[10 * B.wave + 6 + par] = m;
-                S.slots[10 * B.wave + 8 + par] = st_m ? 1u : 0u;
+            const uint64_t wmask = __ballot(waiting);
+            uint32_t m = NO_STEP;
+            if (wmask) {
+                const uint32_t l0 = (uint32_t)__builtin_amdgcn_readlane((int)ls, (int)((uint32_t)__ffsll((long long)wmask) - 1u));
+                m = __ballot(waiting && ls != l0) ? wave_min_u(waiting ? ls : NO_STEP) : l0;
+                m = uniu(m);
             }
+            const bool st_m = __ballot(waiting && ls == m && pst) != 0;
+            if (threadIdx.x == 0) RW[(rnd + 1u) % 3u] = ~0ull;
+            if (lane_id() == 0 && wmask)
+                atomicMin(&RW[rnd % 3u], ((unsigned long long)m << 1) | (st_m ? 0ull : 1ull));
             __syncthreads();
             if (clear) {            // every lane read its win before the barrier above
                 if (clear_sh) {
@@ -1490,20 +1511,18 @@ __device__ __forceinline__ uint32_t run_block_lockstep(const InterpArgs &A, Bloc
                 }
                 clear = false;
             }
-            uint32_t M = NO_STEP;
-            for (uint32_t w = 0; w < B.nwaves; w++) M = min(M, S.slots[10 * w + 6 + par]);
-            bool any_st = false;
-            for (uint32_t w = 0; w < B.nwaves; w++)
-                any_st |= S.slots[10 * w + 6 + par] == M && S.slots[10 * w + 8 + par] != 0;
-            par ^= 1u;
-            if (M == NO_STEP) break;                   // no running lane anywhere: barrier episode
+            const unsigned long long rw = RW[rnd % 3u];
+            rnd++;
+            if (rw == ~0ull) break;                    // no running lane anywhere: barrier episode
+            const uint32_t M = (uint32_t)(rw >> 1);
+            const bool any_st = (rw & 1ull) == 0;
             Pending P{false, false, 0, 0};
             if (m == M) {           // the lanes parked at step M execute it
                 const bool at = waiting && ls == M;
                 uint64_t todo = __ballot(at);
                 while (todo) {
                     const int cur = group_pc(todo, t.pc);
-                    todo &= ~lockstep_group<LOCAL>(A, B, S, t, L, P, epoch, todo, cur, fetch_word(B, cur), exec);
+                    todo &= ~lockstep_group<LOCAL>(A, B, S, t, L, P, epoch, todo, cur, word(cur), exec);
                 }
                 if (at) {
                     ls++;
@@ -1691,7 +1710,9 @@ __device__ __forceinline__ void interp_lockstep_sites_body(const InterpArgs &A) 
         };
         auto run = [](uint64_t, uint32_t) { return 0u; };
         auto release = [&] { barrier_results(b, t); };
-        return run_block_lockstep<false>(a, b, s, tb, t, l, exec, run, release);
+        auto word = [&](int p) { return fetch_word(b, p); };
+        auto kind = [&](int p) { return prog_kind(b, p); };
+        return run_block_lockstep<false>(a, b, s, tb, t, l, exec, run, release, kind, word);
     });
 }
 
@@ -1705,7 +1726,9 @@ __device__ __forceinline__ void interp_lockstep_body(const InterpArgs &A) {
         };
         auto run = [](uint64_t, uint32_t) { return 0u; };
         auto release = [&] { barrier_results(b, t); };
-        return run_block_lockstep<LOCAL>(a, b, s, tb, t, l, exec, run, release);
+        auto word = [&](int p) { return fetch_word(b, p); };
+        auto kind = [&](int p) { return prog_kind(b, p); };
+        return run_block_lockstep<LOCAL>(a, b, s, tb, t, l, exec, run, release, kind, word);
     });
 }
 

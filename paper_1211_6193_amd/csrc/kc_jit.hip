@@ -369,7 +369,26 @@ std::string jit_source(const uint64_t *words, uint32_t n, int waves) {
     o << "            default: goto out;\n            }\n        }\n";
     o << "    out:\n        if (act) t.pc = upc;\n        return steps;\n    };\n";
     o << "    auto release = [&] {\n" << barrier_results(words, n, "        ") << "    };\n";
-    o << "    return run_block_lockstep<LOCAL>(A, B, S, T, t, L, exec, run, release);\n}\n\n";
+    // loads and stores as bit masks per 64 pcs (no program fetch)
+    {
+        const uint32_t chunks = (n + 63) / 64;
+        o << "    auto kind = [](int p) -> uint32_t {\n        const uint32_t q = (uint32_t)p;\n";
+        for (uint32_t c = 0; c < chunks; c++) {
+            uint64_t mem = 0, st = 0;
+            for (uint32_t pc = c * 64; pc < std::min(n, c * 64 + 64); pc++) {
+                const Instr I = decode(words[pc]);
+                if ((I.op >> 4) == 5) {
+                    mem |= 1ull << (pc - c * 64);
+                    if (I.op & 1u) st |= 1ull << (pc - c * 64);
+                }
+            }
+            o << "        if (q < " << (c + 1) * 64 << "u) { const uint32_t b = q - " << c * 64
+              << "u; return ((" << mem << "ull >> b) & 1ull) ? 1u + (uint32_t)((" << st << "ull >> b) & 1ull) : 0u; }\n";
+        }
+        o << "        return 0u;\n    };\n";
+        o << "    auto word = [](int) -> uint64_t { return 0ull; };\n";
+    }
+    o << "    return run_block_lockstep<LOCAL>(A, B, S, T, t, L, exec, run, release, kind, word);\n}\n\n";
     o << "}  // namespace\n}  // namespace kc\n\n";
     // workgroups of up to 256 threads get the whole register file; larger ones
     // are bounded to 128 VGPRs
