@@ -78,7 +78,8 @@ typedef enum {
     KC_E_DEVICE = 4,    /* a HIP call failed; the context is poisoned */
     KC_E_PENDING = 5,   /* kc_poll without wait: the batch is still running */
     KC_E_BUDGET = 6,    /* the job can never fit in the context's HBM budget */
-    KC_E_OVERFLOW = 7,  /* a record field cannot hold the launch's ids */
+    KC_E_OVERFLOW = 7,  /* one launch's ids and barrier epochs do not fit the 64-bit access record even on
+                           its own (launches of a batch that do not fit together run in smaller groups) */
     KC_E_INTERNAL = 8   /* an unexpected internal failure of the library; the context is poisoned */
 } kc_status;
 
@@ -142,7 +143,9 @@ kc_status kc_ctx_set_option(kc_ctx *ctx, const char *key, int64_t value);
  * (in-bounds global-memory accesses of the free run), "jit_launches", "jit_replays"
  * (replay launches on specialised kernels),
  * "jit_compiled", "jit_compile_ms", "jit_failures", "site_replays",
- * "cross_launch_races", "alloc_findings", "noalloc_calls" and
+ * "cross_launch_races", "alloc_findings", "stage_splits" (groups of a batch's
+ * launches halved because their access-record key did not fit together),
+ * "noalloc_calls" and
  * "noalloc_scratch_peak" (calls of kc_launch_noalloc and the most bytes of
  * its static scratch area one of them used).
  * Timings are only collected with option "timing" set.  "option.<name>"

@@ -684,6 +684,15 @@ struct Stage {
         return std::max<uint32_t>(64u, std::min<uint32_t>(st, 2048u));
     }
 
+    // More barrier epochs than the record's epoch field holds: every unit's
+    // memory goes back to the launch-start snapshot, so that the caller can
+    // run the units again in smaller groups (wider epoch fields).
+    [[noreturn]] void epoch_overflow() {
+        HIPCHK(launch_copy_units(ws.units.as<DevUnit>(), (uint32_t)hu.size(), max_words, false, nullptr, s));
+        HIPCHK(hipStreamSynchronize(s));
+        throw KcError{KC_E_OVERFLOW, "barrier epochs exceed the record's epoch field"};
+    }
+
     void upload_units() {
         ws.units.reserve(hu.size() * sizeof(DevUnit));
         HIPCHK(hipMemcpyAsync(ws.units.p, hu.data(), hu.size() * sizeof(DevUnit), hipMemcpyHostToDevice, s));
@@ -990,8 +999,7 @@ struct Stage {
             c = *fetched<DevCounters>(fetch, i_ctr);
             ctx->stat_add("interp_ms", tm.ms(0, 1));
             ctx->stat_add("interp_launches", 1);
-            if (c.flags & FLAG_EPOCH_OVERFLOW)
-                throw KcError{KC_E_OVERFLOW, "barrier epochs exceed the record's epoch field"};
+            if (check && (c.flags & FLAG_EPOCH_OVERFLOW)) epoch_overflow();
             bool again = false;
             if (check && (c.flags & FLAG_LOG_OVERFLOW)) {
                 log_cap = c.log_count + c.log_count / 8 + 1024;
@@ -1239,8 +1247,7 @@ struct Stage {
         run_fetch(f);
         const DevCounters c = *fetched<DevCounters>(f, i_ctr);
         if (res && table) res->table_flags = fetched<DevCounters>(f, i_tab)->flags;
-        if (c.flags & FLAG_EPOCH_OVERFLOW)
-            throw KcError{KC_E_OVERFLOW, "barrier epochs exceed the record's epoch field"};
+        if (c.flags & FLAG_EPOCH_OVERFLOW) epoch_overflow();
         if (res && !(c.flags & (FLAG_LOG_OVERFLOW | FLAG_FAULT_OVERFLOW | FLAG_RACE_OVERFLOW))) {
             res->recs.resize(total_blocks);
             std::memcpy(res->recs.data(), fetched<uint32_t>(f, 2), (size_t)total_blocks * 4);
@@ -1821,17 +1828,37 @@ void run_jobs(kc_ctx *ctx, const kc_job *jobs, uint32_t n_jobs, hipStream_t s, s
         for (uint32_t j = 0; j < n_jobs; j++) max_l = std::max(max_l, jobs[j].n_launches);
         for (uint32_t li = 0; li < max_l; li++) {
             std::vector<UnitIn> in;
-            std::vector<uint32_t> who;
+            std::vector<uint32_t> all_who;
             for (uint32_t j = 0; j < n_jobs; j++) {
                 if (!alive[j] || li >= jobs[j].n_launches) continue;
                 in.push_back(UnitIn{&jobs[j].launches[li], jobs[j].dev_mem, jobs[j].n_words});
-                who.push_back(j);
+                all_who.push_back(j);
             }
             if (in.empty()) break;
+            // The units run as one stage unless their record key does not
+            // fit (too many units for its fields next to the largest grid,
+            // block and memory, or more barrier epochs than its epoch field
+            // holds): then the group is halved and each half runs again, its
+            // memories back at the launch start.  A single unit that does not
+            // fit is KC_E_OVERFLOW.
+            std::vector<std::pair<size_t, size_t>> parts{{0, in.size()}};
+            for (size_t pi = 0; pi < parts.size(); pi++) {
+            const size_t p0 = parts[pi].first, p1 = parts[pi].second;
+            const std::vector<UnitIn> pin(in.begin() + p0, in.begin() + p1);
+            const std::vector<uint32_t> who(all_who.begin() + p0, all_who.begin() + p1);
             std::vector<UnitOut> out;
-            Stage st{ctx, ws, s, in, out, opt};
-            st.run();
-            ctx->stat_add("launches", (double)in.size());
+            Stage st{ctx, ws, s, pin, out, opt};
+            try {
+                st.run();
+            } catch (const KcError &e) {
+                if (e.st != KC_E_OVERFLOW || p1 - p0 < 2) throw;
+                const size_t mid = p0 + (p1 - p0) / 2;
+                parts.push_back({p0, mid});
+                parts.push_back({mid, p1});
+                ctx->stat_add("stage_splits", 1);
+                continue;
+            }
+            ctx->stat_add("launches", (double)pin.size());
             HostTimer ht{ctx, "host_reports_ms", opt.timing != 0};
             std::vector<size_t> first_race(who.size());
             for (size_t i = 0; i < who.size(); i++) {
@@ -1879,6 +1906,7 @@ void run_jobs(kc_ctx *ctx, const kc_job *jobs, uint32_t n_jobs, hipStream_t s, s
                 for (size_t i = 0; i < who.size(); i++)
                     std::copy(out[i].sites.begin(), out[i].sites.end(),
                               reports[who[i]]->sites.begin() + first_race[i]);
+            }
             }
         }
     } catch (...) {

@@ -70,6 +70,23 @@ def test_served_mix_equals_alone(ctx):
         assert np.array_equal(mem.cpu().numpy(), out["memories"][int(i)])
 
 
+def test_served_sample_at_bench_shapes_vs_oracle(ctx):
+    """The served mix the benchmark runs (workload-3 instances and 4096 x 256
+    trees drawn from a seeded pool, continuous batching under a 64 GiB budget):
+    every 10th request's report and final memory equal the oracle's, the big
+    trees included."""
+    small, big = W.request_pool(n_small=256, n_big=3)
+    reqs = W.pooled_requests(4000.0, 0.25, small, big, big_p=0.05, seed=W.BASE_SEED + 77)
+    say(f"serving {len(reqs)} pooled requests")
+    srv = server.Server(ctx, budget_bytes=64 << 30, slots=4)
+    out = srv.run(reqs, keep_every=10)
+    sample = out["sample"]
+    assert len(sample) >= len(reqs) // 10
+    assert any(j.meta.get("family") == "TREE256" for j, _, _ in sample), "no 4096 x 256 tree in the sample"
+    for j, r, m in sample:
+        assert_same(r, m, O.run_job(j), f"served {j.meta.get('family')}")
+
+
 def test_local_check_modes_agree(ctx):
     """Epoch-local checking in LDS (global locations in the shadow table, or
     staged and sorted), its spill path (tiny staging areas) and the all-global

@@ -1,7 +1,8 @@
 """Workload 4 (ping-pong stencil with in-place bugs, 16 launches as one job).
 
-Reduced size (2^18 elements, same block shape and launch count): report and
-final memory equal the oracle's.  Full size (2^26 elements): properties that
+Reduced size (2^18 elements, same block shape and launch count) and 2^25
+elements over two launches (past every size at which the path changes):
+report and final memory equal the oracle's.  Full size (2^26 elements): properties that
 hold at any size -- the record count per launch has a closed form, the race set
 is exactly the two boundary words of every buggy block's range in the array it
 reads, every launch completes and blocks far from a bug compute the stencil."""
@@ -46,16 +47,39 @@ def records_per_launch(n, T):
     return 7 * n + 4 * nb - 2
 
 
+def _non_adjacent(bugs):
+    return all(b2 - b1 > 2 for b1, b2 in zip(bugs[:-1], bugs[1:]))
+
+
 def test_workload4_reduced_vs_oracle(ctx):
     job = W.stencil_pingpong_job(n=1 << 18, threads=256, steps=16, bug_frac=0.004, seed=12116197)
     assert len(job.meta["bug_blocks"]) >= 3
+    assert _non_adjacent(job.meta["bug_blocks"])
     say("workload 4 at 2^18 x 16 launches")
     rep, mem = kc.run_job(ctx, job)
     orc = O.run_job(job)
     assert_same(rep, mem, orc, "workload4-reduced")
-    non_adjacent = all(b2 - b1 > 2 for b1, b2 in zip(job.meta["bug_blocks"][:-1], job.meta["bug_blocks"][1:]))
-    if non_adjacent:
-        assert rep.race_tuples() == expected_races(job)
+    assert rep.race_tuples() == expected_races(job)
+
+
+def test_workload4_past_every_path_switch_vs_oracle(ctx):
+    """2^25 elements (131,072 blocks), two launches: past every size at which
+    the path changes -- the record key's block and address fields (17 and 27
+    bits), held representatives queued on the shared log counter instead of
+    per-block regions (over 65,536 blocks), a log too long for the location
+    tables (over 2^24 entries, so it is sorted: tiled radix passes) -- with
+    the bench's block shape; report and final memory equal the oracle's."""
+    job = W.stencil_pingpong_job(n=1 << 25, threads=256, steps=2, bug_frac=0.0001, seed=12116197)
+    bugs = job.meta["bug_blocks"]
+    assert len(bugs) == 13 and _non_adjacent(bugs)
+    say("workload 4 at 2^25 x 2 launches")
+    ctx.reset_stats()
+    rep, mem = kc.run_job(ctx, job)
+    assert ctx.stat("sorted_checks") == 2, "the logs were expected to take the sorted check"
+    say("workload 4 at 2^25 x 2 launches: oracle")
+    orc = O.run_job(job)
+    assert_same(rep, mem, orc, "workload4-2^25")
+    assert rep.race_tuples() == expected_races(job)
 
 
 def test_workload4_full_size_properties(ctx):
@@ -68,8 +92,8 @@ def test_workload4_full_size_properties(ctx):
     assert rep.launches_completed == 16
     assert rep.records == 16 * records_per_launch(n, T)
     assert len(rep.faults) == 0
-    if all(b2 - b1 > 2 for b1, b2 in zip(bugs[:-1], bugs[1:])):
-        assert rep.race_tuples() == expected_races(job)
+    assert _non_adjacent(bugs)
+    assert rep.race_tuples() == expected_races(job)
     # far from every bug the result is 16 clean stencil steps; checked on windows
     # padded by more than the 16 elements the stencil can propagate
     got = mem.cpu().numpy()[:n]          # 16 launches end in the first array
