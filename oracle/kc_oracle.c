@@ -64,6 +64,17 @@
  *     finding ALLOC {block, epoch 0xFFFFFFFF, a = 2 + (1 if the block stored
  *     to it), b = the smallest tid of the block that accessed it, c = the
  *     word, d = the smallest tid that stored to it or 0xFFFFFFFF}.
+ *   - Uninitialised shared memory (among the checks the tool inherits from the
+ *     C semantics are uninitialised memory accesses, Section 3.2; CUDA leaves
+ *     shared memory undefined when a block starts), when that check is on: a
+ *     load of a shared word that no thread of the block has stored to before
+ *     it -- before in the block's lockstep order: an earlier step, since the
+ *     loads of a step read memory as it was before the step's stores -- is a
+ *     finding UNINIT {block, epoch, a = 0, b = tid, c = the word, d = pc of
+ *     the load}.  The load still reads the word (zero, as shared memory starts
+ *     zeroed).  For a race-free block this order is the order of every
+ *     interleaving: a store by another thread to the word in the same epoch
+ *     would race with the load.
  *   - Every in-bounds load and store appends an access record
  *     {space, word address, block, barrier epoch, tid, read/write}, the
  *     information the race tuples of Section 3.1 keep per location.
@@ -106,7 +117,8 @@ enum {
 enum { ST_RUN = 0, ST_WAIT = 1, ST_EXIT = 2 };
 enum { SP_SHARED = 0, SP_GLOBAL = 1 };
 enum { K_READ = 0, K_WRITE = 1 };
-enum { F_DEADLOCK = 1, F_DIVERGENCE = 2, F_OOB = 3, F_FUEL = 4, F_ARITH = 5, F_ALLOC = 6 };
+enum { F_DEADLOCK = 1, F_DIVERGENCE = 2, F_OOB = 3, F_FUEL = 4, F_ARITH = 5, F_ALLOC = 6, F_UNINIT = 7 };
+enum { CHECK_UNINIT_SHARED = 1 };
 
 typedef struct {
     uint32_t grid[3], block[3];
@@ -262,11 +274,12 @@ static int32_t sreg(const ora_launch *L, uint32_t k, uint32_t tid, uint32_t bid)
 /* Run one block to completion or halt under lockstep steps.  Returns 1 if it deadlocked. */
 static int run_block(ora_result *res, uint32_t li, const uint64_t *prog, uint32_t n,
                      const ora_launch *L, uint32_t bid, int32_t *mem, uint64_t n_words,
-                     uint32_t fuel, ora_thread *th, int32_t *sh, ora_store *q) {
+                     uint32_t fuel, ora_thread *th, int32_t *sh, ora_store *q, uint8_t *shinit) {
     uint32_t nt = L->block[0] * L->block[1] * L->block[2];
     uint32_t sh_words = L->shmem_bytes / 4;
     uint32_t epoch = 0;
     memset(sh, 0, (size_t)sh_words * sizeof(int32_t));
+    if (shinit) memset(shinit, 0, (size_t)sh_words);   /* no shared word stored yet */
     for (uint32_t t = 0; t < nt; t++) {
         memset(&th[t], 0, sizeof(ora_thread));
         th[t].status = ST_RUN;
@@ -316,6 +329,8 @@ static int run_block(ora_result *res, uint32_t li, const uint64_t *prog, uint32_
                         } else {
                             T->r[d] = space == SP_SHARED ? sh[addr] : mem[addr];
                             add_record(res, li, space, (uint32_t)addr, bid, epoch, t, K_READ, T->pc);
+                            if (shinit && space == SP_SHARED && !shinit[addr])
+                                add_fault(res, li, F_UNINIT, bid, epoch, 0, t, (uint32_t)addr, T->pc);
                         }
                         break;
                     }
@@ -343,8 +358,12 @@ static int run_block(ora_result *res, uint32_t li, const uint64_t *prog, uint32_
             }
             /* phase B: stores in ascending tid order (queued in that order) */
             for (uint32_t i = 0; i < nq; i++) {
-                if (q[i].space == SP_SHARED) sh[q[i].addr] = q[i].val;
-                else mem[q[i].addr] = q[i].val;
+                if (q[i].space == SP_SHARED) {
+                    sh[q[i].addr] = q[i].val;
+                    if (shinit) shinit[q[i].addr] = 1;
+                } else {
+                    mem[q[i].addr] = q[i].val;
+                }
             }
             if (res->oom) return 0;
         } else {
@@ -585,10 +604,11 @@ static void illegal_accesses(ora_result *res, uint32_t li, const uint8_t *alloca
  * place.  streams (n_launches entries) and deps (n_deps pairs before, after
  * with before < after) may be NULL / 0: one stream.  allocs (n_allocs pairs
  * base, words), when not NULL, lists the device allocations. */
-int ora_run_job_ex(uint32_t n_launches, const uint64_t *const *progs, const uint32_t *prog_lens,
-                   const ora_launch *launches, int32_t *mem, uint64_t n_words, uint32_t fuel,
-                   int keep_records, const uint32_t *streams, const uint32_t *deps, uint32_t n_deps,
-                   const uint64_t *allocs, uint32_t n_allocs, ora_result **out) {
+/* ... and `checks` (CHECK_UNINIT_SHARED) turns on optional checks. */
+int ora_run_job_opts(uint32_t n_launches, const uint64_t *const *progs, const uint32_t *prog_lens,
+                     const ora_launch *launches, int32_t *mem, uint64_t n_words, uint32_t fuel,
+                     int keep_records, const uint32_t *streams, const uint32_t *deps, uint32_t n_deps,
+                     const uint64_t *allocs, uint32_t n_allocs, uint32_t checks, ora_result **out) {
     *out = NULL;
     for (uint32_t d = 0; d < n_deps; d++)
         if (deps[2 * d] >= deps[2 * d + 1] || deps[2 * d + 1] >= n_launches) return 1;
@@ -620,11 +640,14 @@ int ora_run_job_ex(uint32_t n_launches, const uint64_t *const *progs, const uint
         ora_thread *th = calloc(nt, sizeof(ora_thread));
         int32_t *sh = calloc(L->shmem_bytes / 4 + 1, sizeof(int32_t));
         ora_store *q = calloc(nt, sizeof(ora_store));
-        if (!th || !sh || !q) { free(th); free(sh); free(q); res->oom = 1; break; }
+        uint8_t *shinit = (checks & CHECK_UNINIT_SHARED) ? calloc(L->shmem_bytes / 4 + 1, 1) : NULL;
+        if (!th || !sh || !q || ((checks & CHECK_UNINIT_SHARED) && !shinit)) {
+            free(th); free(sh); free(q); free(shinit); res->oom = 1; break;
+        }
         int deadlocked = 0;
         for (uint32_t b = 0; b < nb; b++)
-            deadlocked |= run_block(res, li, progs[li], prog_lens[li], L, b, mem, n_words, fuel, th, sh, q);
-        free(th); free(sh); free(q);
+            deadlocked |= run_block(res, li, progs[li], prog_lens[li], L, b, mem, n_words, fuel, th, sh, q, shinit);
+        free(th); free(sh); free(q); free(shinit);
         if (res->oom) break;
         int parallel = 0;   /* may this launch run in parallel with another one? */
         for (uint32_t k = 0; k < n_launches; k++)
@@ -661,6 +684,14 @@ int ora_run_job_ex(uint32_t n_launches, const uint64_t *const *progs, const uint
     res->n_faults = m;
     *out = res;
     return 0;
+}
+
+int ora_run_job_ex(uint32_t n_launches, const uint64_t *const *progs, const uint32_t *prog_lens,
+                   const ora_launch *launches, int32_t *mem, uint64_t n_words, uint32_t fuel,
+                   int keep_records, const uint32_t *streams, const uint32_t *deps, uint32_t n_deps,
+                   const uint64_t *allocs, uint32_t n_allocs, ora_result **out) {
+    return ora_run_job_opts(n_launches, progs, prog_lens, launches, mem, n_words, fuel, keep_records, streams,
+                            deps, n_deps, allocs, n_allocs, 0, out);
 }
 
 int ora_run_job(uint32_t n_launches, const uint64_t *const *progs, const uint32_t *prog_lens,

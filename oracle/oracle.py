@@ -21,7 +21,8 @@ SRC_PATH = os.path.join(_HERE, "kc_oracle.c")
 
 DEFAULT_FUEL = 1 << 20
 
-F_DEADLOCK, F_DIVERGENCE, F_OOB, F_FUEL, F_ARITH, F_ALLOC = 1, 2, 3, 4, 5, 6
+F_DEADLOCK, F_DIVERGENCE, F_OOB, F_FUEL, F_ARITH, F_ALLOC, F_UNINIT = 1, 2, 3, 4, 5, 6, 7
+CHECK_UNINIT_SHARED = 1
 
 
 def build(force: bool = True) -> str:
@@ -63,6 +64,11 @@ def _load():
                                        C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p, C.c_uint32,
                                        C.POINTER(C.c_void_p)]
         lib.ora_run_job_ex.restype = C.c_int
+        lib.ora_run_job_opts.argtypes = [C.c_uint32, C.POINTER(C.c_void_p), C.POINTER(C.c_uint32),
+                                         C.POINTER(_Launch), C.c_void_p, C.c_uint64, C.c_uint32, C.c_int,
+                                         C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p, C.c_uint32,
+                                         C.c_uint32, C.POINTER(C.c_void_p)]
+        lib.ora_run_job_opts.restype = C.c_int
         lib.ora_records.argtypes = [C.c_void_p]
         lib.ora_records.restype = C.c_uint64
         lib.ora_instructions.argtypes = [C.c_void_p]
@@ -115,14 +121,16 @@ def validate(words) -> bool:
 
 
 def run_job(job, fuel: int = DEFAULT_FUEL, keep_records: bool = False,
-            memory: Optional[np.ndarray] = None) -> OracleResult:
+            memory: Optional[np.ndarray] = None, uninit: bool = False) -> OracleResult:
     """Run every launch of ``job`` on a copy of its memory (or on ``memory``).
 
     ``job.streams`` (one stream id per launch) and ``job.deps`` ((before,
     after) launch pairs), when the job has them, describe which launches may
     run in parallel; races between such launches are reported with scope 2.
     ``job.allocs`` ((base, words) ranges), when not None, lists the device
-    allocations: accesses outside them are reported as ALLOC findings."""
+    allocations: accesses outside them are reported as ALLOC findings.
+    ``uninit`` turns on the check of loads of shared words no thread of the
+    block has stored to before (UNINIT findings)."""
     lib = _load()
     progs = [np.ascontiguousarray(np.asarray(L.program, dtype=np.uint64)) for L in job.launches]
     n = len(progs)
@@ -145,11 +153,12 @@ def run_job(job, fuel: int = DEFAULT_FUEL, keep_records: bool = False,
     allocs = getattr(job, "allocs", None)
     al = None if allocs is None else np.ascontiguousarray(np.asarray(allocs, dtype=np.uint64).reshape(-1, 2))
     out = C.c_void_p()
-    rc = lib.ora_run_job_ex(n, ptrs, lens, ls, mem.ctypes.data, len(mem), fuel, int(keep_records),
-                            None if st is None else st.ctypes.data, dp.ctypes.data if len(dp) else None,
-                            len(dp), None if al is None else (al.ctypes.data if len(al) else
-                                                              C.addressof(_EMPTY_ALLOCS)),
-                            0 if al is None else len(al), C.byref(out))
+    rc = lib.ora_run_job_opts(n, ptrs, lens, ls, mem.ctypes.data, len(mem), fuel, int(keep_records),
+                              None if st is None else st.ctypes.data, dp.ctypes.data if len(dp) else None,
+                              len(dp), None if al is None else (al.ctypes.data if len(al) else
+                                                                C.addressof(_EMPTY_ALLOCS)),
+                              0 if al is None else len(al), CHECK_UNINIT_SHARED if uninit else 0,
+                              C.byref(out))
     if rc != 0:
         raise ValueError(f"oracle rejected the job (code {rc})")
     try:

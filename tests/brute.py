@@ -14,12 +14,14 @@ any two accesses conflict (same location, different threads, one a write, not
 separated by a completed barrier episode of their block for intra-block pairs;
 any epochs for global accesses of different blocks), and the set of per-access
 findings: out-of-bounds accesses (the load yields 0, the store is dropped, no
-record), division by zero, and threads that run out of fuel.
+record), division by zero, threads that run out of fuel, and loads of shared
+words that no thread of the block has stored to earlier in the interleaving.
 
 Findings use the report's numbering: (kind, block, epoch, a, b, c) with
 OOB = 3 {a = 2 * space + (1 for a store), b = tid, c = the address as an
 unsigned 32-bit value}, FUEL = 4 {a = 0, b = tid, c = 0} and
-ARITH = 5 {a = 0, b = tid, c = pc}.  A thread whose turn comes at the end of
+ARITH = 5 {a = 0, b = tid, c = pc} and UNINIT = 7 {a = 0, b = tid, c = the
+shared word}.  A thread whose turn comes at the end of
 the program exits; otherwise, with no fuel left, it records FUEL and exits;
 otherwise it executes one instruction and spends one unit of fuel.
 """
@@ -84,7 +86,7 @@ def _dec(w: int):
     return w & 0xFF, (w >> 8) & 0xFF, (w >> 16) & 0xFF, (w >> 24) & 0xFF, s32(imm)
 
 
-OOB, FUEL, ARITH = 3, 4, 5
+OOB, FUEL, ARITH, UNINIT = 3, 4, 5, 7
 
 
 @dataclass
@@ -129,8 +131,9 @@ def enumerate_launch(prog: List[int], grid: int, block: int, shmem_words: int,
 
     # thread state: (pc, regs, status, bar_pc, fuel left)  status 0 run, 1 wait, 2 exit
     init_threads = tuple((0, (0,) * 16, 0, -1, fuel) for _ in range(nb * nt))
+    # the last item: per block, the shared words stored to so far
     init = (init_threads, tuple(tuple([0] * shmem_words) for _ in range(nb)), tuple(memory),
-            (0,) * nb, frozenset(), frozenset())
+            (0,) * nb, frozenset(), frozenset(), (frozenset(),) * nb)
     seen: Set = set()
     outcomes: Dict = {}
     stack = [init]
@@ -141,7 +144,7 @@ def enumerate_launch(prog: List[int], grid: int, block: int, shmem_words: int,
         seen.add(st)
         if len(seen) > limit_states:
             raise RuntimeError("state space too large")
-        threads, shs, gm, epochs, recs, finds = st
+        threads, shs, gm, epochs, recs, finds, stored = st
         succ = []
         # barrier releases (deterministic per block)
         released = False
@@ -160,7 +163,7 @@ def enumerate_launch(prog: List[int], grid: int, block: int, shmem_words: int,
                         rg = tuple(rg)
                     nts[b * nt + k] = (bp + 1, rg, 0, -1, fl)
                 ne = list(epochs); ne[b] += 1
-                succ.append((tuple(nts), shs, gm, tuple(ne), recs, finds))
+                succ.append((tuple(nts), shs, gm, tuple(ne), recs, finds, stored))
                 released = True
                 break
         if not released:
@@ -169,14 +172,14 @@ def enumerate_launch(prog: List[int], grid: int, block: int, shmem_words: int,
                 if s != 0:
                     continue
                 b, t = divmod(g, nt)
-                nts = list(threads); nshs = shs; ngm = gm; nrec = recs; nfind = finds
+                nts = list(threads); nshs = shs; ngm = gm; nrec = recs; nfind = finds; nst = stored
                 if pc == n:
                     nts[g] = (pc, rg, 2, -1, fl)
-                    succ.append((tuple(nts), nshs, ngm, epochs, nrec, nfind))
+                    succ.append((tuple(nts), nshs, ngm, epochs, nrec, nfind, nst))
                     continue
                 if fl == 0:
                     nts[g] = (pc, rg, 2, -1, fl)
-                    succ.append((tuple(nts), nshs, ngm, epochs, nrec, finds | {(FUEL, b, epochs[b], 0, t, 0)}))
+                    succ.append((tuple(nts), nshs, ngm, epochs, nrec, finds | {(FUEL, b, epochs[b], 0, t, 0)}, nst))
                     continue
                 op, d, a, bb, imm = code[pc]
                 regs = list(rg)
@@ -204,8 +207,12 @@ def enumerate_launch(prog: List[int], grid: int, block: int, shmem_words: int,
                     if op == 0x50:
                         ok = 0 <= addr < shmem_words
                         regs[d] = shs[b][addr] if ok else 0
-                        if ok: nrec = addrec(0, addr, 0)
-                        else: nfind = finding(OOB, 0, addr)
+                        if ok:
+                            nrec = addrec(0, addr, 0)
+                            if addr not in stored[b]:
+                                nfind = finding(UNINIT, 0, addr)
+                        else:
+                            nfind = finding(OOB, 0, addr)
                     else:
                         ok = 0 <= addr < len(gm)
                         regs[d] = gm[addr] if ok else 0
@@ -218,6 +225,7 @@ def enumerate_launch(prog: List[int], grid: int, block: int, shmem_words: int,
                             row = list(shs[b]); row[addr] = regs[bb]
                             nshs = shs[:b] + (tuple(row),) + shs[b + 1:]
                             nrec = addrec(0, addr, 1)
+                            nst = stored[:b] + (stored[b] | {addr},) + stored[b + 1:]
                         else:
                             nfind = finding(OOB, 1, addr)
                     else:
@@ -234,7 +242,7 @@ def enumerate_launch(prog: List[int], grid: int, block: int, shmem_words: int,
                 else:
                     raise ValueError(f"bad opcode {op:#x}")
                 nts[g] = (npc, tuple(regs), ns, nbp, fl - 1)
-                succ.append((tuple(nts), nshs, ngm, epochs, nrec, nfind))
+                succ.append((tuple(nts), nshs, ngm, epochs, nrec, nfind, nst))
         if not succ:
             deadlock = any(any(threads[b * nt + k][2] == 1 for k in range(nt)) for b in range(nb))
             c = Counter(dict(recs))

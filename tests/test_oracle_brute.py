@@ -97,19 +97,20 @@ def _cases(n, seed):
 def _oracle(prog, nb, nt, mem, fuel=O.DEFAULT_FUEL):
     job = Job([LaunchSpec(np.array(prog, dtype=np.uint64), (nb, 1, 1), (nt, 1, 1), 4 * SH_WORDS, ())],
               np.array(mem, dtype=np.int32))
-    return O.run_job(job, keep_records=True, fuel=fuel)
+    return O.run_job(job, keep_records=True, fuel=fuel, uninit=True)
 
 
 # Per-access findings: the ones the brute-force interpreter produces too.
-_ACCESS_KINDS = (O.F_OOB, O.F_FUEL, O.F_ARITH)
+_ACCESS_KINDS = (O.F_OOB, O.F_FUEL, O.F_ARITH, O.F_UNINIT)
 
 
 def _access_findings(res):
-    """The oracle's OOB / FUEL / ARITH findings as brute's (kind, block, epoch, a, b, c)."""
+    """The oracle's OOB / FUEL / ARITH / UNINIT findings as brute's
+    (kind, block, epoch, a, b, c); UNINIT's load pc (d) is pinned elsewhere."""
     out = set()
     for f in res.faults:
         if int(f["kind"]) in _ACCESS_KINDS:
-            assert int(f["launch"]) == 0 and int(f["d"]) == 0
+            assert int(f["launch"]) == 0 and (int(f["d"]) == 0 or int(f["kind"]) == O.F_UNINIT)
             out.add((int(f["kind"]), int(f["block"]), int(f["epoch"]), int(f["a"]), int(f["b"]), int(f["c"])))
     return frozenset(out)
 
@@ -186,10 +187,14 @@ def test_cases_reach_every_access_finding_field():
                         seen.add(("oob-block1",))
                 elif k == O.F_ARITH:
                     seen.add(("arith",))
+                elif k == O.F_UNINIT:
+                    seen.add(("uninit", "block1" if int(f["block"]) else "block0",
+                              "epoch>0" if int(f["epoch"]) else "epoch0"))
     for chunk in range(3):
         for prog, nb, nt, mem, fuel in fuel_cases(20, 8100 + chunk):
             if any(int(f["kind"]) == O.F_FUEL for f in _oracle(prog, nb, nt, mem, fuel).faults):
                 seen.add(("fuel",))
     want = {("oob", a, side) for a in range(4) for side in ("neg", "past")}
     want |= {("oob-epoch>0",), ("oob-block1",), ("arith",), ("fuel",)}
+    want |= {("uninit", b, e) for b in ("block0", "block1") for e in ("epoch0", "epoch>0")}
     assert want <= seen, sorted(want - seen)
