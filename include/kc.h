@@ -90,7 +90,7 @@ typedef struct kc_report kc_report;
 typedef struct { uint32_t x, y, z; } kc_dim3;
 
 /* Finding kinds (kc_fault.kind). */
-enum { KC_DEADLOCK = 1, KC_DIVERGENCE = 2, KC_OOB = 3, KC_FUEL = 4, KC_ARITH = 5, KC_ALLOC = 6 };
+enum { KC_DEADLOCK = 1, KC_DIVERGENCE = 2, KC_OOB = 3, KC_FUEL = 4, KC_ARITH = 5, KC_ALLOC = 6, KC_UNINIT = 7 };
 
 /* ---- context ------------------------------------------------------------ */
 
@@ -125,8 +125,11 @@ void kc_ctx_destroy(kc_ctx *ctx);
  * once per process, which takes seconds; results are identical to the
  * interpreter's; 0 = interpreter only, default), "sites" (1 = fill the
  * races' source sites, kc_report_race_sites: the racy blocks are replayed
- * once more with a site table; 0 = not computed, default), "reset" (1 =
- * clear the statistics).
+ * once more with a site table; 0 = not computed, default), "uninit" (1 =
+ * report loads of uninitialised shared memory, KC_UNINIT: the tool's checks
+ * inherited from the C semantics include uninitialised memory accesses,
+ * Section 3.2, and CUDA leaves shared memory undefined when a block starts;
+ * 0 = off, default), "reset" (1 = clear the statistics).
  * Errors: KC_E_INVAL for an unknown key or out-of-range value. */
 kc_status kc_ctx_set_option(kc_ctx *ctx, const char *key, int64_t value);
 
@@ -300,7 +303,10 @@ typedef struct {
      * FUEL:       b = tid
      * ARITH:      b = tid, c = pc
      * ALLOC:      epoch 0xFFFFFFFF, a = 2 + (1 if the block stored to the word), b = smallest tid of the
-     *             block that accessed it, c = word, d = smallest tid that stored to it or 0xFFFFFFFF */
+     *             block that accessed it, c = word, d = smallest tid that stored to it or 0xFFFFFFFF
+     * UNINIT:     (option "uninit") a load of a shared word that no thread of the block stored to earlier
+     *             in the canonical order (an earlier step; a step's loads come before its stores):
+     *             a = 0 (shared, load), b = tid, c = word, d = pc of the load; the load reads 0 */
 } kc_fault;
 
 /* Source sites of a race (the tool names the source line a race was found

@@ -133,6 +133,7 @@ struct Shared {
     uint32_t *slots;    // 16 waves x 10 words: episode reductions, lockstep rounds
     uint32_t *slots2;   // 16 x 4: divergence second round
     uint32_t *eps;      // free-run episodes: 3 sets of EPS_WORDS summary words, used in turn
+    uint32_t *sinit;    // one bit per simulated shared word: stored to since the block began (option uninit)
 };
 
 typedef const __attribute__((address_space(4))) uint64_t const_word_t;   // scalar-cache reads
@@ -284,6 +285,16 @@ __device__ __forceinline__ void shadow_mark(const Shared &S, uint32_t addr, uint
     atomicMin(&S.vmin[addr], tid);
     atomicMax(&S.vmax[addr], tid);
     if (write) atomicOr(&S.vw[addr], 1u);
+}
+
+// Uninitialised shared words (option uninit): a bit per word, set by every
+// store to it (in the free run at once; in the replay when the step's stores
+// land, after every load of the step has tested it).
+__device__ __forceinline__ bool shared_stored(const Shared &S, uint32_t addr) {
+    return (S.sinit[addr >> 5] >> (addr & 31u)) & 1u;
+}
+__device__ __forceinline__ void mark_stored(const Shared &S, uint32_t addr) {
+    atomicOr(&S.sinit[addr >> 5], 1u << (addr & 31u));
 }
 
 // Bytes of the shadow region: 8 per shared word for the replay's tuples, 12
@@ -1108,6 +1119,9 @@ __device__ __forceinline__ void exec_one(const InterpArgs &A, const BlockCtx &B,
         const bool inb = active && (uint32_t)addr < (is_sh ? B.sh_words : B.n_words);
         if (!is_st) {
             if (inb) v = is_sh ? S.sh[addr] : B.mem[addr];
+            if (is_sh && A.uninit)
+                emit_fault(inb && !shared_stored(S, (uint32_t)addr), A, B, F_UNINIT, epoch, 0u, B.tid, (uint32_t)addr,
+                           (uint32_t)cur);
         } else {
             writes = false;
             const int32_t val = t.r[rb];
@@ -1116,6 +1130,7 @@ __device__ __forceinline__ void exec_one(const InterpArgs &A, const BlockCtx &B,
             } else if (inb) {
                 if (is_sh) S.sh[addr] = val;
                 else B.mem[addr] = val;
+                if (is_sh && A.uninit) mark_stored(S, (uint32_t)addr);
             }
         }
         const uint32_t space = is_sh ? 0u : 1u;
@@ -1163,6 +1178,8 @@ __device__ __forceinline__ void setup_block(const InterpArgs &A, BlockCtx &B, co
     B.gocc = A.local ? &S.tmp[36] : nullptr;
     B.kep = B.kbase;
     for (uint32_t i = threadIdx.x; i < B.sh_words; i += blockDim.x) S.sh[i] = 0;
+    if (A.uninit)
+        for (uint32_t i = threadIdx.x; i < (B.sh_words + 31) / 32; i += blockDim.x) S.sinit[i] = 0u;
     if (A.local && exact)
         for (uint32_t i = threadIdx.x; i < B.sh_words; i += blockDim.x) S.shadow[i] = SHADOW_EMPTY;
     if (A.local && !exact)
@@ -1547,6 +1564,7 @@ __device__ __forceinline__ uint32_t run_block_lockstep(const InterpArgs &A, Bloc
                 }
             }
             __syncthreads();
+            if (A.uninit && P.on && P.shared) mark_stored(S, (uint32_t)P.addr);   // every load of the step is done
             bool win = false;
             if (P.on) win = (P.shared ? T.own_sh[P.addr] : T.gown[slot]) == B.tid + 1;
             if (win && P.shared) S.sh[P.addr] = P.val;
@@ -1595,6 +1613,8 @@ __device__ __forceinline__ size_t carve_lds(uint8_t *smem, const InterpArgs &A, 
     S.slots2 = S.slots + 16 * 10;
     S.eps = S.slots2 + 16 * 4;
     off += (16 * 10 + 16 * 4 + 3 * 8) * 4;
+    S.sinit = (uint32_t *)(smem + off);
+    off += (size_t)(A.sh_words_max + 31) / 32 * 4;
     return off;
 }
 

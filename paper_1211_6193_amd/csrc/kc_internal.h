@@ -30,7 +30,7 @@ constexpr uint32_t MAX_SHMEM_WORDS = 16384;     // 64 KiB of simulated shared me
 // reserves on the same counter.
 constexpr uint32_t REP_HOLD = 512;
 
-enum : uint32_t { F_DEADLOCK = 1, F_DIVERGENCE = 2, F_OOB = 3, F_FUEL = 4, F_ARITH = 5, F_ALLOC = 6 };
+enum : uint32_t { F_DEADLOCK = 1, F_DIVERGENCE = 2, F_OOB = 3, F_FUEL = 4, F_ARITH = 5, F_ALLOC = 6, F_UNINIT = 7 };
 
 // ---- one (instance, launch) as the device sees it -------------------------
 struct DevUnit {
@@ -144,6 +144,7 @@ struct InterpArgs {
     uint32_t *racy_words;       // free run: count of shared words the verdicts found racy (sizes the replay's lists)
     uint32_t *blk_instr;        // free run: thread-instructions executed, per block (stored), or null
     uint32_t *blk_grecs;        // free run: in-bounds global accesses, per block (stored), or null
+    uint32_t uninit;            // check loads of shared words no thread of the block stored to before
     uint32_t gst_bits;          // local check: log2 slots of the global shadow table (0: stage and sort)
     uint32_t site_bits;         // log2 slots of `sites`
     SiteSlot *sites;            // lockstep replay for source sites, or null

@@ -61,7 +61,7 @@ size_t interp_lds_bytes(uint32_t sh_words_max, uint32_t wg_threads, uint32_t sta
     off += (size_t)nwaves * stage * 8;
     if (local) off += (size_t)nwaves * stage * 8 + (size_t)nwaves * 256 * 4 + 256 * 4 + shadow_region_bytes(sh_words_max);
     if (local && gst_bits) off += ((size_t)8 << gst_bits) + (size_t)REP_HOLD * 8;
-    off += (16 * 10 + 16 * 4 + 3 * 8) * 4;
+    off += (16 * 10 + 16 * 4 + 3 * 8) * 4 + (size_t)(sh_words_max + 31) / 32 * 4;
     if (lockstep) off += (size_t)sh_words_max * 4 + ((size_t)8 << lockstep_hash_bits(wg_threads));
     return off;
 }

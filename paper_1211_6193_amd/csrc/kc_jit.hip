@@ -109,7 +109,7 @@ void gen_alu(std::ostringstream &o, const Instr &I, uint32_t pc) {
 
 // A load or store; in lockstep mode a store is held in P until the step's
 // stores land.
-void gen_mem(std::ostringstream &o, const Instr &I, bool lockstep = false) {
+void gen_mem(std::ostringstream &o, const Instr &I, uint32_t pc, bool lockstep = false) {
     const bool sh = (I.op & 2u) == 0, st = (I.op & 1u) != 0;
     const char *lim = sh ? "B.sh_words" : "B.n_words";
     const char *arr = sh ? "S.sh" : "B.mem";
@@ -125,6 +125,10 @@ void gen_mem(std::ostringstream &o, const Instr &I, bool lockstep = false) {
         o << "            int32_t v = 0;\n            if (inb) v = " << arr << "[addr];\n";
         o << "            if (act) " << reg(I.d) << " = v;\n";
     }
+    if (sh && !st)
+        o << "            if (A.uninit) emit_fault(inb && !shared_stored(S, (uint32_t)addr), A, B, F_UNINIT, epoch, 0u, "
+             "B.tid, (uint32_t)addr, " << pc << "u);\n";
+    if (sh && st && !lockstep) o << "            if (A.uninit && inb) mark_stored(S, (uint32_t)addr);\n";
     if (sh) {
         o << "            if (LOCAL) {\n";
         if (lockstep)
@@ -236,7 +240,7 @@ std::string jit_source(const uint64_t *words, uint32_t n, int waves) {
                 if (base >= OP_ADD && base <= OP_SLTU) {
                     gen_alu(o, I, pc);
                 } else if ((I.op >> 4) == 5) {
-                    gen_mem(o, I);
+                    gen_mem(o, I, pc);
                 } else if (I.op == OP_MOV) {
                     o << "        if (act) " << reg(I.d) << " = " << reg(I.a) << ";\n";
                 } else if (I.op == OP_MOVI) {
@@ -294,7 +298,7 @@ std::string jit_source(const uint64_t *words, uint32_t n, int waves) {
         if (base >= OP_ADD && base <= OP_SLTU) {
             gen_alu(o, I, pc);
         } else if ((I.op >> 4) == 5) {
-            gen_mem(o, I, true);
+            gen_mem(o, I, pc, true);
         } else if (I.op == OP_MOV) {
             o << "        if (act) " << reg(I.d) << " = " << reg(I.a) << ";\n";
         } else if (I.op == OP_MOVI) {

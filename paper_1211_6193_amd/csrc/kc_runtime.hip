@@ -246,6 +246,7 @@ struct Options {
     int jit = 0;                    // program-specialised free-run kernels (compiled at first use)
     int jit_waves = 0;              // their occupancy target, waves per SIMD (0: the compiler's choice)
     int sites = 0;                  // source sites of races (one more replay of the racy blocks)
+    int uninit = 0;                 // UNINIT findings for loads of shared words not yet stored to
     int arena = 0;                  // set by the library: buffers come from the static scratch area
 };
 
@@ -724,6 +725,7 @@ struct Stage {
         a.lrace_cap = lrace_cap_;
         a.lrace_count = &ctr.as<DevCounters>()->race_count;
         a.blk_flags = flags.as<uint32_t>();
+        a.uninit = opt.uninit ? 1u : 0u;
         a.racy_words = lockstep ? nullptr : &ctr.as<DevCounters>()->racy_words;
         a.blk_instr = lockstep ? nullptr : ws.blk_instr.as<uint32_t>();
         a.blk_grecs = lockstep ? nullptr : ws.blk_grecs.as<uint32_t>();
@@ -1993,6 +1995,7 @@ static kc_status set_option_locked(kc_ctx *ctx, const char *key, int64_t v) {
     else if (k == "jit" && (v == 0 || v == 1)) ctx->opt.jit = (int)v;
     else if (k == "jit_waves" && (v == 0 || (v >= 2 && v <= 8))) ctx->opt.jit_waves = (int)v;
     else if (k == "sites" && (v == 0 || v == 1)) ctx->opt.sites = (int)v;
+    else if (k == "uninit" && (v == 0 || v == 1)) ctx->opt.uninit = (int)v;
     else if (k == "reset" && v == 1) {
         ctx->stats.clear();
     } else {
@@ -2021,6 +2024,7 @@ static double get_stat_locked(kc_ctx *ctx, const char *key) {
         if (o == "jit") return op.jit;
         if (o == "jit_waves") return op.jit_waves;
         if (o == "sites") return op.sites;
+        if (o == "uninit") return op.uninit;
         return 0.0;
     }
     auto it = ctx->stats.find(key);

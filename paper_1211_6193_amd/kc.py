@@ -22,7 +22,7 @@ LIB_PATH = os.environ.get("KC_LIBRARY") or os.path.join(_HERE, "libkc.so")
  KC_E_INTERNAL) = range(9)
 STATUS_NAMES = ["KC_OK", "KC_E_INVAL", "KC_E_PROGRAM", "KC_E_NOMEM", "KC_E_DEVICE", "KC_E_PENDING",
                 "KC_E_BUDGET", "KC_E_OVERFLOW", "KC_E_INTERNAL"]
-DEADLOCK, DIVERGENCE, OOB, FUEL, ARITH = 1, 2, 3, 4, 5
+DEADLOCK, DIVERGENCE, OOB, FUEL, ARITH, ALLOC, UNINIT = 1, 2, 3, 4, 5, 6, 7
 
 # Every entry point include/kc.h declares.
 EXPORTS = ["kc_ctx_create", "kc_ctx_destroy", "kc_ctx_set_option", "kc_ctx_get_stat", "kc_last_error",
