@@ -75,6 +75,11 @@
  *     zeroed).  For a race-free block this order is the order of every
  *     interleaving: a store by another thread to the word in the same epoch
  *     would race with the load.
+ *   - Warp-aware model (the finer scheduler the paper's Section 4 proposes),
+ *     when that check is on: threads form warps of 32 consecutive linear tids
+ *     that execute in lock-step, so two accesses of one block and epoch by
+ *     threads of one warp conflict only when they run at the same step; see
+ *     warp_tuple for the tuple it reports.  Cross-block tuples are unchanged.
  *   - Every in-bounds load and store appends an access record
  *     {space, word address, block, barrier epoch, tid, read/write}, the
  *     information the race tuples of Section 3.1 keep per location.
@@ -118,7 +123,8 @@ enum { ST_RUN = 0, ST_WAIT = 1, ST_EXIT = 2 };
 enum { SP_SHARED = 0, SP_GLOBAL = 1 };
 enum { K_READ = 0, K_WRITE = 1 };
 enum { F_DEADLOCK = 1, F_DIVERGENCE = 2, F_OOB = 3, F_FUEL = 4, F_ARITH = 5, F_ALLOC = 6, F_UNINIT = 7 };
-enum { CHECK_UNINIT_SHARED = 1 };
+enum { CHECK_UNINIT_SHARED = 1, CHECK_WARP = 2 };
+enum { WARP_SIZE = 32 };
 
 typedef struct {
     uint32_t grid[3], block[3];
@@ -126,7 +132,8 @@ typedef struct {
     int32_t params[8];
 } ora_launch;
 
-typedef struct { uint32_t launch, space, addr, block, epoch, tid, kind, pc; } ora_record;
+/* step: the block's lockstep step within the epoch at which the access ran */
+typedef struct { uint32_t launch, space, addr, block, epoch, tid, kind, pc, step; } ora_record;
 typedef struct { uint32_t launch, space, scope, block, epoch, addr, w_tid, o_tid, w_pc, o_pc; } ora_race;
 typedef struct { uint32_t launch, kind, block, epoch, a, b, c, d; } ora_fault;
 
@@ -153,8 +160,8 @@ typedef struct {
     } while (0)
 
 static void add_record(ora_result *res, uint32_t launch, uint32_t space, uint32_t addr,
-                       uint32_t block, uint32_t epoch, uint32_t tid, uint32_t kind, uint32_t pc) {
-    ora_record r = {launch, space, addr, block, epoch, tid, kind, pc};
+                       uint32_t block, uint32_t epoch, uint32_t tid, uint32_t kind, uint32_t pc, uint32_t step) {
+    ora_record r = {launch, space, addr, block, epoch, tid, kind, pc, step};
     GROW(res->recs, res->n_recs, res->cap_recs, ora_record);
     res->recs[res->n_recs++] = r;
     res->n_records++;
@@ -277,7 +284,7 @@ static int run_block(ora_result *res, uint32_t li, const uint64_t *prog, uint32_
                      uint32_t fuel, ora_thread *th, int32_t *sh, ora_store *q, uint8_t *shinit) {
     uint32_t nt = L->block[0] * L->block[1] * L->block[2];
     uint32_t sh_words = L->shmem_bytes / 4;
-    uint32_t epoch = 0;
+    uint32_t epoch = 0, step = 0;
     memset(sh, 0, (size_t)sh_words * sizeof(int32_t));
     if (shinit) memset(shinit, 0, (size_t)sh_words);   /* no shared word stored yet */
     for (uint32_t t = 0; t < nt; t++) {
@@ -328,7 +335,7 @@ static int run_block(ora_result *res, uint32_t li, const uint64_t *prog, uint32_
                             T->r[d] = 0;
                         } else {
                             T->r[d] = space == SP_SHARED ? sh[addr] : mem[addr];
-                            add_record(res, li, space, (uint32_t)addr, bid, epoch, t, K_READ, T->pc);
+                            add_record(res, li, space, (uint32_t)addr, bid, epoch, t, K_READ, T->pc, step);
                             if (shinit && space == SP_SHARED && !shinit[addr])
                                 add_fault(res, li, F_UNINIT, bid, epoch, 0, t, (uint32_t)addr, T->pc);
                         }
@@ -343,7 +350,7 @@ static int run_block(ora_result *res, uint32_t li, const uint64_t *prog, uint32_
                         } else {
                             q[nq].tid = t; q[nq].space = space; q[nq].addr = addr; q[nq].val = T->r[b];
                             nq++;
-                            add_record(res, li, space, (uint32_t)addr, bid, epoch, t, K_WRITE, T->pc);
+                            add_record(res, li, space, (uint32_t)addr, bid, epoch, t, K_WRITE, T->pc, step);
                         }
                         break;
                     }
@@ -365,6 +372,7 @@ static int run_block(ora_result *res, uint32_t li, const uint64_t *prog, uint32_
                     mem[q[i].addr] = q[i].val;
                 }
             }
+            step++;
             if (res->oom) return 0;
         } else {
             uint32_t nwait = 0, nexit = 0;
@@ -396,6 +404,7 @@ static int run_block(ora_result *res, uint32_t li, const uint64_t *prog, uint32_
                     th[t].r[(w >> 8) & 0xFF] = v;
                 }
                 epoch++;
+                step = 0;
                 for (uint32_t t = 0; t < nt; t++) {
                     th[t].status = ST_RUN;
                     th[t].pc = th[t].bar_pc + 1;
@@ -435,7 +444,37 @@ static int cmp_cross(const void *pa, const void *pb) {
     return (int)x->kind - (int)y->kind;
 }
 
-static void check_launch(ora_result *res, uint32_t li, uint32_t nt) {
+/* Warp-aware model (the finer scheduler the paper's Section 4 proposes:
+ * threads grouped into warps of warpSize = 32 consecutive linear tids that
+ * execute in lock-step).  Two accesses of one block and epoch by threads of
+ * one warp are ordered by the warp's instruction order unless they run at the
+ * same lockstep step; threads of different warps stay unordered until the
+ * barrier.  A write x and an access y (x != y) conflict when the threads are
+ * in different warps or the two accesses share a step.  The tuple reports
+ * w = the smallest thread with a write that conflicts, and o = the smallest
+ * other thread with an access that conflicts with one of w's writes. */
+static int warp_conflict(const ora_record *x, const ora_record *y) {
+    if (x->kind != K_WRITE || x->tid == y->tid) return 0;
+    return x->tid / WARP_SIZE != y->tid / WARP_SIZE || x->step == y->step;
+}
+
+/* The warp-aware tuple of one location's group r[i, j) (tids ascending): 1 and
+ * (w, o) if some pair conflicts. */
+static int warp_tuple(const ora_record *r, uint64_t i, uint64_t j, uint32_t *w, uint32_t *o) {
+    for (uint64_t a = i; a < j; a++) {
+        if (r[a].kind != K_WRITE) continue;
+        /* r[a] is a write of the smallest thread not yet ruled out */
+        int found = 0;
+        uint32_t best = UINT32_MAX;
+        for (uint64_t x = a; x < j && r[x].tid == r[a].tid; x++)
+            for (uint64_t b = i; b < j; b++)
+                if (warp_conflict(&r[x], &r[b]) && r[b].tid < best) { best = r[b].tid; found = 1; }
+        if (found) { *w = r[a].tid; *o = best; return 1; }
+    }
+    return 0;
+}
+
+static void check_launch(ora_result *res, uint32_t li, uint32_t nt, int warp) {
     ora_record *r = res->recs;
     uint64_t n = res->n_recs;
     /* intra-block: records of one (space, block, epoch, addr) are unordered by barriers */
@@ -445,12 +484,16 @@ static void check_launch(ora_result *res, uint32_t li, uint32_t nt) {
         while (j < n && r[j].space == r[i].space && r[j].block == r[i].block &&
                r[j].epoch == r[i].epoch && r[j].addr == r[i].addr) j++;
         /* tids ascend inside the group: the first writer is the minimum writer */
-        int has_w = 0; uint32_t w = 0;
-        for (uint64_t k = i; k < j; k++)
-            if (r[k].kind == K_WRITE) { has_w = 1; w = r[k].tid; break; }
+        int has_w = 0; uint32_t w = 0, wo = 0;
+        if (warp) {
+            has_w = warp_tuple(r, i, j, &w, &wo);
+        } else {
+            for (uint64_t k = i; k < j; k++)
+                if (r[k].kind == K_WRITE) { has_w = 1; w = r[k].tid; break; }
+        }
         if (has_w) {
             for (uint64_t k = i; k < j; k++) {
-                if (r[k].tid != w) {
+                if (r[k].tid != w && (!warp || r[k].tid == wo)) {
                     ora_race rc = {li, r[i].space, 0, r[i].block, r[i].epoch, r[i].addr, w, r[k].tid,
                                    0xFFFFFFFFu, 0xFFFFFFFFu};
                     /* source sites: the smallest pc of w's stores to the location and of the
@@ -662,7 +705,7 @@ int ora_run_job_opts(uint32_t n_launches, const uint64_t *const *progs, const ui
         }
         if (allocated) illegal_accesses(res, li, allocated);
         if (res->oom) break;
-        check_launch(res, li, nt);
+        check_launch(res, li, nt, (checks & CHECK_WARP) != 0);
         if (res->oom) break;
         if (deadlocked) break;
         res->launches_completed = li + 1;

@@ -22,7 +22,7 @@ SRC_PATH = os.path.join(_HERE, "kc_oracle.c")
 DEFAULT_FUEL = 1 << 20
 
 F_DEADLOCK, F_DIVERGENCE, F_OOB, F_FUEL, F_ARITH, F_ALLOC, F_UNINIT = 1, 2, 3, 4, 5, 6, 7
-CHECK_UNINIT_SHARED = 1
+CHECK_UNINIT_SHARED, CHECK_WARP = 1, 2
 
 
 def build(force: bool = True) -> str:
@@ -43,7 +43,8 @@ class _Launch(C.Structure):
 RACE_DTYPE = np.dtype([(f, "<u4") for f in ("launch", "space", "scope", "block", "epoch", "addr", "w_tid", "o_tid",
                                             "w_pc", "o_pc")])
 FAULT_DTYPE = np.dtype([(f, "<u4") for f in ("launch", "kind", "block", "epoch", "a", "b", "c", "d")])
-RECORD_DTYPE = np.dtype([(f, "<u4") for f in ("launch", "space", "addr", "block", "epoch", "tid", "kind", "pc")])
+RECORD_DTYPE = np.dtype([(f, "<u4") for f in ("launch", "space", "addr", "block", "epoch", "tid", "kind", "pc",
+                                             "step")])
 
 _lib = None
 _EMPTY_ALLOCS = (C.c_uint64 * 2)()      # a non-null list of no allocations
@@ -121,7 +122,7 @@ def validate(words) -> bool:
 
 
 def run_job(job, fuel: int = DEFAULT_FUEL, keep_records: bool = False,
-            memory: Optional[np.ndarray] = None, uninit: bool = False) -> OracleResult:
+            memory: Optional[np.ndarray] = None, uninit: bool = False, warp: bool = False) -> OracleResult:
     """Run every launch of ``job`` on a copy of its memory (or on ``memory``).
 
     ``job.streams`` (one stream id per launch) and ``job.deps`` ((before,
@@ -130,7 +131,8 @@ def run_job(job, fuel: int = DEFAULT_FUEL, keep_records: bool = False,
     ``job.allocs`` ((base, words) ranges), when not None, lists the device
     allocations: accesses outside them are reported as ALLOC findings.
     ``uninit`` turns on the check of loads of shared words no thread of the
-    block has stored to before (UNINIT findings)."""
+    block has stored to before (UNINIT findings); ``warp`` the warp-aware
+    model (threads of one warp conflict only at the same step)."""
     lib = _load()
     progs = [np.ascontiguousarray(np.asarray(L.program, dtype=np.uint64)) for L in job.launches]
     n = len(progs)
@@ -157,7 +159,8 @@ def run_job(job, fuel: int = DEFAULT_FUEL, keep_records: bool = False,
                               None if st is None else st.ctypes.data, dp.ctypes.data if len(dp) else None,
                               len(dp), None if al is None else (al.ctypes.data if len(al) else
                                                                 C.addressof(_EMPTY_ALLOCS)),
-                              0 if al is None else len(al), CHECK_UNINIT_SHARED if uninit else 0,
+                              0 if al is None else len(al),
+                              (CHECK_UNINIT_SHARED if uninit else 0) | (CHECK_WARP if warp else 0),
                               C.byref(out))
     if rc != 0:
         raise ValueError(f"oracle rejected the job (code {rc})")

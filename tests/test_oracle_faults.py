@@ -190,7 +190,7 @@ def test_records_permutation_free_definition():
         recs = r.record_log
         segs = {}
         for x in recs:
-            L, sp, ad, bl, ep, ti, ki, pc = (int(v) for v in x)
+            L, sp, ad, bl, ep, ti, ki, pc = (int(v) for v in tuple(x)[:8])
             segs.setdefault((L, sp, 0, bl, ep, ad), []).append((ti, ki, pc))
             if sp == 1:
                 segs.setdefault((L, sp, 1, ad), []).append((bl * nt + ti, ki, bl, pc))
