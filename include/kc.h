@@ -129,7 +129,14 @@ void kc_ctx_destroy(kc_ctx *ctx);
  * report loads of uninitialised shared memory, KC_UNINIT: the tool's checks
  * inherited from the C semantics include uninitialised memory accesses,
  * Section 3.2, and CUDA leaves shared memory undefined when a block starts;
- * 0 = off, default), "reset" (1 = clear the statistics).
+ * 0 = off, default), "warp" (1 = the warp-aware model the paper's Section 4
+ * proposes: threads form warps of 32 consecutive linear tids that execute in
+ * lock-step, so two accesses of one block and epoch by threads of one warp
+ * race only when they run at the same lockstep step; the intra-block tuple is
+ * then w = the smallest thread with a write that conflicts, o = the smallest
+ * thread whose access conflicts with one of w's writes; blocks with a race in
+ * the plain model are replayed to find the steps; 0 = off, default),
+ * "reset" (1 = clear the statistics).
  * Errors: KC_E_INVAL for an unknown key or out-of-range value. */
 kc_status kc_ctx_set_option(kc_ctx *ctx, const char *key, int64_t value);
 

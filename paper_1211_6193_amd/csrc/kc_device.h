@@ -150,6 +150,8 @@ struct BlockCtx {
     uint64_t kbase;         // record bits fixed for this lane: unit, block, tid
     uint64_t kep;           // kbase plus the current epoch
     uint32_t *gocc;         // global shadow table: occupancy and overflow words of the current epoch
+    uint32_t step;          // replay: the lockstep step being executed (warp-aware model)
+    uint32_t epoch;         // replay: the current epoch (warp-aware model)
 };
 
 // Wave-aggregated append of findings.
@@ -182,6 +184,28 @@ __device__ __forceinline__ void emit_fault(bool f, const InterpArgs &A, const Bl
     const uint64_t m = __ballot(f);
     if (m == 0) return;
     emit_fault_wave(m, f, A.fault_count, A.faults, A.fault_cap, A.flags, B.unit, B.block, kind, epoch, a, b, c, d);
+}
+
+// Warp-aware model: an in-bounds access of the replay with its step, appended
+// with one reservation per wave.
+__device__ __noinline__ void wlog_append_wave(const InterpArgs &A, uint64_t m, bool on, uint32_t unit, uint32_t block,
+                                             uint32_t epoch, uint32_t step, uint32_t addr, uint32_t tsk) {
+    const uint32_t leader = (uint32_t)__ffsll((long long)m) - 1u;
+    uint32_t base = 0;
+    if (lane_id() == leader) base = atomicAdd(A.wlog_count, (uint32_t)__popcll(m));
+    base = (uint32_t)__shfl((int)base, (int)leader);
+    if (on) {
+        const uint32_t idx = base + lane_prefix(m);
+        if (idx < A.wlog_cap) A.wlog[idx] = WarpRec{unit, block, epoch, step, addr, tsk};
+        else atomicOr(A.flags, FLAG_WLOG_OVERFLOW);
+    }
+}
+__device__ __forceinline__ void wlog_append(const InterpArgs &A, const BlockCtx &B, bool inb, uint32_t space,
+                                            uint32_t addr, bool store) {
+    const uint64_t m = __ballot(inb);
+    if (m == 0) return;
+    wlog_append_wave(A, m, inb, B.unit, B.block, B.epoch, B.step, addr,
+                     B.tid | (store ? 1u << 16 : 0u) | (space << 17));
 }
 
 // Copy a wave's staged records to the HBM log (one atomic reservation).
@@ -479,6 +503,10 @@ __device__ __forceinline__ void local_sort_pass(const Shared &S, const BlockCtx 
 
 __device__ __forceinline__ void push_local_race(const InterpArgs &A, const BlockCtx &B, uint32_t space, uint32_t epoch,
                                                 uint32_t addr, uint32_t w, uint32_t o) {
+    if (A.wlog) {           // warp-aware model: the host derives the block's tuples from the stepped accesses
+        A.blk_flags[B.u->block_base + B.block] = 1u;
+        return;
+    }
     const uint32_t idx = atomicAdd(A.lrace_count, 1u);
     if (idx < A.lrace_cap) {
         DevRace r;
@@ -1136,6 +1164,7 @@ __device__ __forceinline__ void exec_one(const InterpArgs &A, const BlockCtx &B,
         const uint32_t space = is_sh ? 0u : 1u;
         const uint64_t key = B.kep | ((uint64_t)space << k.s_sp) | (uint64_t)(is_st ? 1u : 0u) |
                              ((uint64_t)(uint32_t)addr << k.s_addr);
+        if (LOCKSTEP && A.wlog) wlog_append(A, B, inb, space, (uint32_t)addr, is_st);
         if (!is_sh) L.gtotal += (uint32_t)__popcll(__ballot(inb));
         if (LOCAL && is_sh) {       // shared accesses update the shadow tuple instead of the log
             if (inb && LOCKSTEP) shadow_update(S.shadow, (uint32_t)addr, B.tid, is_st);
@@ -1534,6 +1563,8 @@ __device__ __forceinline__ uint32_t run_block_lockstep(const InterpArgs &A, Bloc
             const uint32_t M = (uint32_t)(rw >> 1);
             const bool any_st = (rw & 1ull) == 0;
             Pending P{false, false, 0, 0};
+            B.step = M;
+            B.epoch = epoch;
             if (m == M) {           // the lanes parked at step M execute it
                 const bool at = waiting && ls == M;
                 uint64_t todo = __ballot(at);

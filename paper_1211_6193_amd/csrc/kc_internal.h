@@ -71,6 +71,9 @@ __host__ __device__ inline uint32_t rec_field(uint64_t r, uint32_t shift, uint32
 
 struct DevFault { uint32_t unit, kind, block, epoch, a, b, c, d; };
 struct DevRace { uint32_t unit, space, scope, block, epoch, addr, w, o; };
+// An access of the replay with its lockstep step (warp-aware model):
+// tsk = tid | kind << 16 | space << 17.
+struct WarpRec { uint32_t unit, block, epoch, step, addr, tsk; };
 struct DevEdge { uint32_t unit, b0, b1, pad; };
 
 // flags word bits
@@ -82,6 +85,7 @@ enum : uint32_t {
     FLAG_EDGE_OVERFLOW = 1u << 4,
     FLAG_MISMATCH = 1u << 5,
     FLAG_NEED_SORT = 1u << 6,   // the replay's records need the sorted check
+    FLAG_WLOG_OVERFLOW = 1u << 7,   // the replay's step-stamped accesses did not fit
 };
 
 // Counters in one small device block (zeroed before a stage).
@@ -97,7 +101,8 @@ struct DevCounters {
     unsigned long long instructions;   // thread-instructions of the free run
     uint32_t long_count;               // segments left to the long-segment pass of the check
     uint32_t racy_words;               // free run: shared words found racy by the verdicts (all epochs)
-    uint32_t pad[4];
+    uint32_t wlog_count;               // replay: step-stamped accesses (warp-aware model)
+    uint32_t pad[3];
 };
 
 // Source sites of race tuples: one slot per tuple of an open-addressing
@@ -145,6 +150,11 @@ struct InterpArgs {
     uint32_t *blk_instr;        // free run: thread-instructions executed, per block (stored), or null
     uint32_t *blk_grecs;        // free run: in-bounds global accesses, per block (stored), or null
     uint32_t uninit;            // check loads of shared words no thread of the block stored to before
+    // Warp-aware model (replay only): every access with its lockstep step goes
+    // to wlog, and the replay itself reports no intra-block races.
+    WarpRec *wlog;
+    uint32_t wlog_cap;
+    uint32_t *wlog_count;
     uint32_t gst_bits;          // local check: log2 slots of the global shadow table (0: stage and sort)
     uint32_t site_bits;         // log2 slots of `sites`
     SiteSlot *sites;            // lockstep replay for source sites, or null

@@ -129,6 +129,9 @@ void gen_mem(std::ostringstream &o, const Instr &I, uint32_t pc, bool lockstep =
         o << "            if (A.uninit) emit_fault(inb && !shared_stored(S, (uint32_t)addr), A, B, F_UNINIT, epoch, 0u, "
              "B.tid, (uint32_t)addr, " << pc << "u);\n";
     if (sh && st && !lockstep) o << "            if (A.uninit && inb) mark_stored(S, (uint32_t)addr);\n";
+    if (lockstep)
+        o << "            if (A.wlog) wlog_append(A, B, inb, " << (sh ? "0u" : "1u") << ", (uint32_t)addr, "
+          << (st ? "true" : "false") << ");\n";
     if (sh) {
         o << "            if (LOCAL) {\n";
         if (lockstep)

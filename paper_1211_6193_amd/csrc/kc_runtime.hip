@@ -145,7 +145,7 @@ struct DBuf {
 struct Workspace {
     DBuf units, items, comp_off, comp_blocks, mask;
     DBuf snap, log, alt, rlog, ralt, fs, hist, part;
-    DBuf faults, rfaults, races, lraces, rlraces, edges, blk_recs, rblk_recs, blk_flags, rflags, ctr, rctr;
+    DBuf faults, rfaults, races, lraces, rlraces, edges, blk_recs, rblk_recs, blk_flags, rflags, ctr, rctr, wlog;
     DBuf longseg, covlist, rtable, ftable, downer, dflags, blk_instr, blk_grecs, blk_log, blk_held, blk_off;
     DevCounters *h_ctr = nullptr;   // pinned
     void *h_pin = nullptr;          // pinned staging of gathered device-to-host copies
@@ -185,7 +185,7 @@ struct Workspace {
     void forget_carved() {
         DBuf *all[] = {&units, &items, &comp_off, &comp_blocks, &mask, &snap, &log, &alt, &rlog,
                        &ralt, &fs, &hist, &part, &faults, &rfaults, &races, &edges, &blk_recs,
-                       &rblk_recs, &blk_flags, &rflags, &ctr, &rctr, &lraces, &rlraces, &longseg, &covlist,
+                       &rblk_recs, &blk_flags, &rflags, &ctr, &rctr, &wlog, &lraces, &rlraces, &longseg, &covlist,
                        &rtable, &ftable, &downer, &dflags, &blk_instr, &blk_grecs, &blk_log, &blk_held, &blk_off};
         for (auto *b : all)
             if (b->carved) b->release();
@@ -193,7 +193,7 @@ struct Workspace {
     size_t device_bytes() const {
         const DBuf *all[] = {&units, &items, &comp_off, &comp_blocks, &mask, &snap, &log, &alt, &rlog,
                              &ralt, &fs, &hist, &part, &faults, &rfaults, &races, &edges, &blk_recs,
-                             &rblk_recs, &blk_flags, &rflags, &ctr, &rctr, &lraces, &rlraces, &longseg, &covlist,
+                             &rblk_recs, &blk_flags, &rflags, &ctr, &rctr, &wlog, &lraces, &rlraces, &longseg, &covlist,
                              &rtable, &ftable, &downer, &dflags, &blk_instr, &blk_grecs, &blk_log, &blk_held, &blk_off};
         size_t s = 0;
         for (auto *b : all) s += b->bytes;
@@ -202,7 +202,7 @@ struct Workspace {
     ~Workspace() {
         DBuf *all[] = {&units, &items, &comp_off, &comp_blocks, &mask, &snap, &log, &alt, &rlog,
                        &ralt, &fs, &hist, &part, &faults, &rfaults, &races, &edges, &blk_recs,
-                       &rblk_recs, &blk_flags, &rflags, &ctr, &rctr, &lraces, &rlraces, &longseg, &covlist,
+                       &rblk_recs, &blk_flags, &rflags, &ctr, &rctr, &wlog, &lraces, &rlraces, &longseg, &covlist,
                        &rtable, &ftable, &downer, &dflags, &blk_instr, &blk_grecs, &blk_log, &blk_held, &blk_off};
         for (auto *b : all) b->release();
         if (h_ctr) (void)hipHostFree(h_ctr);
@@ -247,6 +247,7 @@ struct Options {
     int jit_waves = 0;              // their occupancy target, waves per SIMD (0: the compiler's choice)
     int sites = 0;                  // source sites of races (one more replay of the racy blocks)
     int uninit = 0;                 // UNINIT findings for loads of shared words not yet stored to
+    int warp = 0;                   // warp-aware model: accesses of one warp conflict only at the same step
     int arena = 0;                  // set by the library: buffers come from the static scratch area
 };
 
@@ -464,6 +465,7 @@ struct Stage {
     uint32_t used_epoch_bits = 0;
     uint32_t lrace_cap = 4096;
     uint32_t racy_words = 0;        // shared words the free run's verdicts found racy
+    uint32_t wlog_cap = 0;          // warp-aware model: capacity of the replay's stepped accesses (0: off)
 
     // Sort order for the check: bits from the block field up, then the used
     // epoch bits; the full order for multiset comparison adds tid and kind.
@@ -726,6 +728,11 @@ struct Stage {
         a.lrace_count = &ctr.as<DevCounters>()->race_count;
         a.blk_flags = flags.as<uint32_t>();
         a.uninit = opt.uninit ? 1u : 0u;
+        if (lockstep && wlog_cap) {
+            a.wlog = ws.wlog.as<WarpRec>();
+            a.wlog_cap = wlog_cap;
+            a.wlog_count = &ctr.as<DevCounters>()->wlog_count;
+        }
         a.racy_words = lockstep ? nullptr : &ctr.as<DevCounters>()->racy_words;
         a.blk_instr = lockstep ? nullptr : ws.blk_instr.as<uint32_t>();
         a.blk_grecs = lockstep ? nullptr : ws.blk_grecs.as<uint32_t>();
@@ -1208,7 +1215,47 @@ struct Stage {
         HIPCHK(hipMemcpyAsync(ws.comp_blocks.p, blocks.data(), blocks.size() * sizeof(uint2), hipMemcpyHostToDevice, s));
     }
 
-    // One lockstep pass over `comps`; records go to ws.rlog (capacity rcap).
+    // Warp-aware model (the finer scheduler the paper's Section 4 proposes:
+    // warps of 32 consecutive linear tids execute in lock-step): the
+    // intra-block tuples of the replayed blocks from their accesses with
+    // lockstep steps.  A write x and an access y (x != y) of one location,
+    // block and epoch conflict when their threads are in different warps or
+    // they ran at the same step; the tuple is w = the smallest thread with a
+    // conflicting write, o = the smallest thread conflicting with one of w's
+    // writes.
+    static void warp_races(std::vector<WarpRec> &v, std::vector<DevRace> &out) {
+        auto space = [](const WarpRec &r) { return (r.tsk >> 17) & 1u; };
+        auto tid = [](const WarpRec &r) { return r.tsk & 0xFFFFu; };
+        auto store = [](const WarpRec &r) { return ((r.tsk >> 16) & 1u) != 0; };
+        std::sort(v.begin(), v.end(), [&](const WarpRec &a, const WarpRec &b) {
+            return std::make_tuple(a.unit, space(a), a.block, a.epoch, a.addr, tid(a), a.tsk, a.step) <
+                   std::make_tuple(b.unit, space(b), b.block, b.epoch, b.addr, tid(b), b.tsk, b.step);
+        });
+        auto conflict = [&](const WarpRec &x, const WarpRec &y) {
+            return store(x) && tid(x) != tid(y) && (tid(x) / 32u != tid(y) / 32u || x.step == y.step);
+        };
+        for (size_t i = 0; i < v.size();) {
+            size_t j = i;
+            while (j < v.size() && v[j].unit == v[i].unit && space(v[j]) == space(v[i]) && v[j].block == v[i].block &&
+                   v[j].epoch == v[i].epoch && v[j].addr == v[i].addr)
+                j++;
+            for (size_t a = i; a < j;) {
+                size_t ae = a;
+                while (ae < j && tid(v[ae]) == tid(v[a])) ae++;
+                uint32_t best = 0xFFFFFFFFu;
+                for (size_t x = a; x < ae; x++)
+                    for (size_t b = i; b < j; b++)
+                        if (conflict(v[x], v[b])) best = std::min(best, tid(v[b]));
+                if (best != 0xFFFFFFFFu) {
+                    out.push_back(DevRace{v[i].unit, space(v[i]), 0u, v[i].block, v[i].epoch, v[i].addr, tid(v[a]), best});
+                    break;
+                }
+                a = ae;
+            }
+            i = j;
+        }
+    }
+
     // One lockstep pass over `comps`; records go to ws.rlog (capacity rcap).
     // With `res`, its findings, per-block record counts and local races come
     // back in the same trip as the counters.
@@ -1216,6 +1263,7 @@ struct Stage {
         std::vector<DevFault> faults;
         std::vector<uint32_t> recs;
         std::vector<DevRace> lraces;
+        std::vector<DevRace> warp;     // warp-aware model: the replayed blocks' intra-block tuples
         uint32_t table_flags = 0;      // flags of the exactness tables, if queued
     };
     DevCounters lockstep_once(const std::vector<std::vector<uint2>> &comps, uint64_t rcap, uint32_t fcap,
@@ -1232,8 +1280,15 @@ struct Stage {
                        {sizeof(DevCounters) / 4, (size_t)total_blocks}, 2};
             HIPCHK(launch_zero_many(z, s));
         }
+        // the warp-aware model: every replayed access with its step (not in
+        // the source-site pass)
+        wlog_cap = (opt.warp && opt.check && !site_table)
+                       ? (uint32_t)std::min<uint64_t>(std::max<uint64_t>(rcap, 1024), 0xFFFFFFFFu) : 0u;
+        if (wlog_cap) ws.wlog.reserve((size_t)wlog_cap * sizeof(WarpRec));
         interp(true, ws.rlog, rcap, ws.rctr, ws.rfaults, fcap, ws.rblk_recs, (uint32_t)comps.size(), ws.rlraces,
                rlcap, ws.rflags);
+        const uint32_t used_wlog = wlog_cap;
+        wlog_cap = 0;
         if (table) {            // the replay's exactness tables, queued behind it (flags in ws.ctr, zeroed there)
             ws.ctr.reserve(sizeof(DevCounters));
             HIPCHK(launch_replay_table(*table, s));
@@ -1250,11 +1305,19 @@ struct Stage {
         const DevCounters c = *fetched<DevCounters>(f, i_ctr);
         if (res && table) res->table_flags = fetched<DevCounters>(f, i_tab)->flags;
         if (c.flags & FLAG_EPOCH_OVERFLOW) epoch_overflow();
-        if (res && !(c.flags & (FLAG_LOG_OVERFLOW | FLAG_FAULT_OVERFLOW | FLAG_RACE_OVERFLOW))) {
+        if (res && !(c.flags & (FLAG_LOG_OVERFLOW | FLAG_FAULT_OVERFLOW | FLAG_RACE_OVERFLOW | FLAG_WLOG_OVERFLOW))) {
             res->recs.resize(total_blocks);
             std::memcpy(res->recs.data(), fetched<uint32_t>(f, 2), (size_t)total_blocks * 4);
             take_list(f, 1, c.fault_count, fcap, ws.rfaults.p, res->faults);
             take_list(f, 3, c.race_count, rlcap, ws.rlraces.p, res->lraces);
+            if (used_wlog) {
+                std::vector<WarpRec> wl(c.wlog_count);
+                if (!wl.empty()) {
+                    HIPCHK(hipMemcpyAsync(wl.data(), ws.wlog.p, wl.size() * sizeof(WarpRec), hipMemcpyDeviceToHost, s));
+                    HIPCHK(hipStreamSynchronize(s));
+                }
+                warp_races(wl, res->warp);
+            }
         }
         return c;
     }
@@ -1340,7 +1403,7 @@ struct Stage {
         DevCounters rc = lockstep_once(comps, rcap, fcap, rlcap, &ro, use_table ? &ta : nullptr);
         tm.mark(7);
         ctx->stat_add("replay_lockstep_ms", tm.ms(5, 7));
-        bool ok = !(rc.flags & (FLAG_LOG_OVERFLOW | FLAG_FAULT_OVERFLOW | FLAG_RACE_OVERFLOW));
+        bool ok = !(rc.flags & (FLAG_LOG_OVERFLOW | FLAG_FAULT_OVERFLOW | FLAG_RACE_OVERFLOW | FLAG_WLOG_OVERFLOW));
         std::vector<DevRace> rr;
         std::vector<DevEdge> re;
         bool sorted_check = ok && rc.log_count > 0;
@@ -1387,6 +1450,11 @@ struct Stage {
             const std::vector<DevFault> &rf = ro.faults;
             const std::vector<uint32_t> &rrecs = ro.recs;
             rr.insert(rr.end(), ro.lraces.begin(), ro.lraces.end());
+            if (opt.warp) {     // intra-block tuples of the warp-aware model replace the plain ones
+                rr.erase(std::remove_if(rr.begin(), rr.end(), [](const DevRace &r) { return r.scope == 0; }),
+                         rr.end());
+                rr.insert(rr.end(), ro.warp.begin(), ro.warp.end());
+            }
             std::vector<char> in_s(total_blocks, 0);
             for (auto &c : comps)
                 for (auto &ub : c) {
@@ -1436,8 +1504,10 @@ struct Stage {
             HIPCHK(launch_copy_units(ws.units.as<DevUnit>(), (uint32_t)hu.size(), max_words, false,
                                      ws.mask.as<uint32_t>(), s));
             fc = lockstep_once(full, rcap, fcap, rlcap, &fo);
-            if (!(fc.flags & (FLAG_LOG_OVERFLOW | FLAG_FAULT_OVERFLOW | FLAG_RACE_OVERFLOW))) break;
+            if (!(fc.flags & (FLAG_LOG_OVERFLOW | FLAG_FAULT_OVERFLOW | FLAG_RACE_OVERFLOW | FLAG_WLOG_OVERFLOW)))
+                break;
             rcap = std::max<uint64_t>(rcap, fc.log_count + 1024);
+            if (fc.flags & FLAG_WLOG_OVERFLOW) rcap = std::max<uint64_t>(rcap, (uint64_t)fc.wlog_count * 2 + 1024);
             fcap = std::max<uint32_t>(fcap, fc.fault_count + 1024);
             rlcap = std::max<uint32_t>(rlcap, fc.race_count + 1024);
         }
@@ -1454,6 +1524,10 @@ struct Stage {
         std::vector<DevEdge> ne;
         run_check(rs, fc.log_count, ws.rflags, nr, ne);
         nr.insert(nr.end(), fl.begin(), fl.end());
+        if (opt.warp) {
+            nr.erase(std::remove_if(nr.begin(), nr.end(), [](const DevRace &r) { return r.scope == 0; }), nr.end());
+            nr.insert(nr.end(), fo.warp.begin(), fo.warp.end());
+        }
         for (uint32_t u = 0; u < hu.size(); u++) {
             if (!mask[u]) continue;
             uraces[u].clear();
@@ -1996,6 +2070,7 @@ static kc_status set_option_locked(kc_ctx *ctx, const char *key, int64_t v) {
     else if (k == "jit_waves" && (v == 0 || (v >= 2 && v <= 8))) ctx->opt.jit_waves = (int)v;
     else if (k == "sites" && (v == 0 || v == 1)) ctx->opt.sites = (int)v;
     else if (k == "uninit" && (v == 0 || v == 1)) ctx->opt.uninit = (int)v;
+    else if (k == "warp" && (v == 0 || v == 1)) ctx->opt.warp = (int)v;
     else if (k == "reset" && v == 1) {
         ctx->stats.clear();
     } else {
@@ -2025,6 +2100,7 @@ static double get_stat_locked(kc_ctx *ctx, const char *key) {
         if (o == "jit_waves") return op.jit_waves;
         if (o == "sites") return op.sites;
         if (o == "uninit") return op.uninit;
+        if (o == "warp") return op.warp;
         return 0.0;
     }
     auto it = ctx->stats.find(key);
