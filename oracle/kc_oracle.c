@@ -28,6 +28,27 @@
  *     j whose access to the word conflicts with an access of i, and o_tid the
  *     same for i: if the other launch writes the word every access conflicts,
  *     otherwise only writes do.
+ *   - Memory transfers and the host (Section 3 "Streams and events": launches
+ *     and memory transfers pass through the stream queues; the host
+ *     synchronises with cudaStreamSynchronize, cudaEventSynchronize and
+ *     cudaDeviceSynchronize).  A job may instead be a list of items in the
+ *     host program's order: launches and copies (device items, each in a
+ *     stream), host reads and writes of words of the memory, and host waits.
+ *     A copy moves `words` words from src to dst (the ranges may not
+ *     overlap); its word k is copied by "thread" k.  A host read or write of
+ *     words [addr, addr + words) touches word addr + k as thread k; a write
+ *     stores `value`.  A host wait blocks the host until one earlier device
+ *     item (an event recorded right behind it, or the last item of a stream)
+ *     or every earlier device item (the device) has finished.  Item i happens
+ *     before a later item j when: both are device items of one stream; a
+ *     dependency (an event) links them; i is a host item (the host issues j
+ *     only after it); i is a copy the host waits for on the spot (a
+ *     synchronous cudaMemcpy); or j is a host wait for i (or for every
+ *     device item) -- and every chain of these.  Items ordered neither way
+ *     may run in parallel and race (scope 2) as launches do, with the
+ *     item indices in place of launch indices; items still execute in the
+ *     host program's order.  A launch that does not complete ends the job.
+ *     Copies and host accesses make no access records.
  *   - Within a launch the blocks run one after another in ascending linear
  *     block id; this is one of the interleavings the semantics admits
  *     (Section 3 "Threads and memory": scheduling is constrained only by grid
@@ -131,6 +152,19 @@ typedef struct {
     uint32_t shmem_bytes;
     int32_t params[8];
 } ora_launch;
+
+/* An item of a job in host program order (see the header comment). */
+enum { IT_LAUNCH = 0, IT_COPY = 1, IT_HOST_READ = 2, IT_HOST_WRITE = 3, IT_HOST_WAIT = 4 };
+enum { IT_SYNC = 1 };           /* flags: the host waits for this copy on the spot */
+#define WAIT_ALL 0xFFFFFFFFu    /* host wait target: every earlier device item */
+typedef struct {
+    uint32_t kind, stream;
+    uint32_t ref;               /* launch index (IT_LAUNCH); item waited for (IT_HOST_WAIT) */
+    uint32_t flags;
+    uint64_t dst, src, words;   /* IT_COPY: dst <- src; host items: words [dst, dst + words) */
+    int32_t value;              /* IT_HOST_WRITE */
+    uint32_t pad;
+} ora_item;
 
 /* step: the block's lockstep step within the epoch at which the access ran */
 typedef struct { uint32_t launch, space, addr, block, epoch, tid, kind, pc, step; } ora_record;
@@ -560,16 +594,24 @@ static int cmp_fault(const void *pa, const void *pb) {
     return 0;
 }
 
-/* ---- launches that may run in parallel (Section 3 "Streams and events") ---- */
-/* hb[i * n + j] = 1 when launch i happens before launch j: the transitive
- * closure (Warshall) of "an earlier launch of the same stream" and of the
- * dependencies.  NULL streams put every launch in one stream. */
-static uint8_t *happens_before(uint32_t n, const uint32_t *streams, const uint32_t *deps, uint32_t n_deps) {
+/* ---- items that may run in parallel (Section 3 "Streams and events") ---- */
+static int is_device(const ora_item *it) { return it->kind == IT_LAUNCH || it->kind == IT_COPY; }
+
+/* hb[i * n + j] = 1 when item i happens before item j: the rules of the
+ * header comment, closed transitively (Warshall). */
+static uint8_t *happens_before(uint32_t n, const ora_item *items, const uint32_t *deps, uint32_t n_deps) {
     uint8_t *hb = calloc((size_t)n * n + 1, 1);
     if (!hb) return NULL;
     for (uint32_t j = 0; j < n; j++)
-        for (uint32_t i = 0; i < j; i++)
-            if (!streams || streams[i] == streams[j]) hb[(size_t)i * n + j] = 1;
+        for (uint32_t i = 0; i < j; i++) {
+            const ora_item *a = &items[i], *b = &items[j];
+            int before = 0;
+            if (is_device(a) && is_device(b) && a->stream == b->stream) before = 1;   /* one stream */
+            if (!is_device(a)) before = 1;                                            /* host order */
+            if (a->kind == IT_COPY && (a->flags & IT_SYNC)) before = 1;               /* synchronous copy */
+            if (b->kind == IT_HOST_WAIT && is_device(a) && (b->ref == WAIT_ALL || b->ref == i)) before = 1;
+            if (before) hb[(size_t)i * n + j] = 1;
+        }
     for (uint32_t d = 0; d < n_deps; d++) hb[(size_t)deps[2 * d] * n + deps[2 * d + 1]] = 1;
     for (uint32_t k = 0; k < n; k++)
         for (uint32_t i = 0; i < n; i++)
@@ -577,6 +619,21 @@ static uint8_t *happens_before(uint32_t n, const uint32_t *streams, const uint32
                 for (uint32_t j = 0; j < n; j++)
                     if (hb[(size_t)k * n + j]) hb[(size_t)i * n + j] = 1;
     return hb;
+}
+
+/* Summary of a copy or host access: thread k touches the k-th word of each
+ * range it reads or writes (same layout as access_summary). */
+static uint32_t *range_summary(const ora_item *it, uint64_t n_words) {
+    uint32_t *sum = malloc((2 * n_words + 1) * sizeof(uint32_t));
+    if (!sum) return NULL;
+    for (uint64_t x = 0; x < 2 * n_words; x++) sum[x] = 0xFFFFFFFFu;
+    uint32_t *acc = sum, *wr = sum + n_words;
+    for (uint64_t k = 0; k < it->words; k++) {
+        if (it->kind == IT_COPY) acc[it->src + k] = (uint32_t)k;
+        if (it->kind != IT_HOST_WAIT) acc[it->dst + k] = (uint32_t)k;
+        if (it->kind == IT_COPY || it->kind == IT_HOST_WRITE) wr[it->dst + k] = (uint32_t)k;
+    }
+    return sum;
 }
 
 /* Smallest global thread id accessing each global word (acc) and writing it
@@ -643,18 +700,22 @@ static void illegal_accesses(ora_result *res, uint32_t li, const uint8_t *alloca
     free(bad);
 }
 
-/* Run a job.  progs[i]/prog_lens[i] is launch i's program; mem is updated in
- * place.  streams (n_launches entries) and deps (n_deps pairs before, after
- * with before < after) may be NULL / 0: one stream.  allocs (n_allocs pairs
- * base, words), when not NULL, lists the device allocations. */
-/* ... and `checks` (CHECK_UNINIT_SHARED) turns on optional checks. */
-int ora_run_job_opts(uint32_t n_launches, const uint64_t *const *progs, const uint32_t *prog_lens,
-                     const ora_launch *launches, int32_t *mem, uint64_t n_words, uint32_t fuel,
-                     int keep_records, const uint32_t *streams, const uint32_t *deps, uint32_t n_deps,
-                     const uint64_t *allocs, uint32_t n_allocs, uint32_t checks, ora_result **out) {
+/* Run a job given as items (IT_*, n_items entries, host program order).
+ * progs[i]/prog_lens[i]/launches[i] describe launch i, which launch items
+ * name by index; mem is updated in place.  deps (n_deps pairs before, after,
+ * before < after, both device items) are event dependencies.  allocs
+ * (n_allocs pairs base, words), when not NULL, lists the device allocations;
+ * `checks` (CHECK_*) turns on optional checks.  launches_completed counts the
+ * leading items that completed. */
+int ora_run_items(uint32_t n_launches, const uint64_t *const *progs, const uint32_t *prog_lens,
+                  const ora_launch *launches, const ora_item *items, uint32_t n_items, int32_t *mem,
+                  uint64_t n_words, uint32_t fuel, int keep_records, const uint32_t *deps, uint32_t n_deps,
+                  const uint64_t *allocs, uint32_t n_allocs, uint32_t checks, ora_result **out) {
     *out = NULL;
     for (uint32_t d = 0; d < n_deps; d++)
-        if (deps[2 * d] >= deps[2 * d + 1] || deps[2 * d + 1] >= n_launches) return 1;
+        if (deps[2 * d] >= deps[2 * d + 1] || deps[2 * d + 1] >= n_items || !is_device(&items[deps[2 * d]]) ||
+            !is_device(&items[deps[2 * d + 1]]))
+            return 1;
     for (uint32_t a = 0; allocs && a < n_allocs; a++)
         if (allocs[2 * a] > n_words || allocs[2 * a + 1] > n_words - allocs[2 * a]) return 1;
     for (uint32_t i = 0; i < n_launches; i++) {
@@ -664,11 +725,25 @@ int ora_run_job_opts(uint32_t n_launches, const uint64_t *const *progs, const ui
         uint64_t nb = (uint64_t)L->grid[0] * L->grid[1] * L->grid[2];
         if (nt == 0 || nt > 1024 || nb == 0 || nb * nt > 0xFFFFFFFFull || (L->shmem_bytes & 3)) return 1;
     }
+    for (uint32_t j = 0; j < n_items; j++) {
+        const ora_item *it = &items[j];
+        if (it->kind > IT_HOST_WAIT) return 1;
+        if (it->kind == IT_LAUNCH && it->ref >= n_launches) return 1;
+        if (it->kind == IT_HOST_WAIT && it->ref != WAIT_ALL && (it->ref >= j || !is_device(&items[it->ref])))
+            return 1;
+        if (it->kind == IT_COPY || it->kind == IT_HOST_READ || it->kind == IT_HOST_WRITE) {
+            if (it->dst > n_words || it->words > n_words - it->dst || it->words > 0xFFFFFFFFull) return 1;
+            if (it->kind == IT_COPY &&
+                (it->src > n_words || it->words > n_words - it->src ||
+                 (it->words && it->src < it->dst + it->words && it->dst < it->src + it->words)))
+                return 1;
+        }
+    }
     ora_result *res = calloc(1, sizeof(ora_result));
     if (!res) return 3;
     res->keep_records = keep_records;
-    uint8_t *hb = happens_before(n_launches, streams, deps, n_deps);
-    uint32_t **sums = calloc((size_t)n_launches + 1, sizeof(uint32_t *));
+    uint8_t *hb = happens_before(n_items, items, deps, n_deps);
+    uint32_t **sums = calloc((size_t)n_items + 1, sizeof(uint32_t *));
     uint8_t *allocated = NULL;
     if (allocs) {
         allocated = calloc(n_words + 1, 1);
@@ -676,42 +751,53 @@ int ora_run_job_opts(uint32_t n_launches, const uint64_t *const *progs, const ui
             memset(allocated + allocs[2 * a], 1, allocs[2 * a + 1]);
     }
     if (!hb || !sums || (allocs && !allocated)) res->oom = 1;
-    for (uint32_t li = 0; li < n_launches && !res->oom; li++) {
-        const ora_launch *L = &launches[li];
-        uint32_t nt = L->block[0] * L->block[1] * L->block[2];
-        uint32_t nb = L->grid[0] * L->grid[1] * L->grid[2];
-        ora_thread *th = calloc(nt, sizeof(ora_thread));
-        int32_t *sh = calloc(L->shmem_bytes / 4 + 1, sizeof(int32_t));
-        ora_store *q = calloc(nt, sizeof(ora_store));
-        uint8_t *shinit = (checks & CHECK_UNINIT_SHARED) ? calloc(L->shmem_bytes / 4 + 1, 1) : NULL;
-        if (!th || !sh || !q || ((checks & CHECK_UNINIT_SHARED) && !shinit)) {
-            free(th); free(sh); free(q); free(shinit); res->oom = 1; break;
-        }
+    for (uint32_t li = 0; li < n_items && !res->oom; li++) {
+        const ora_item *it = &items[li];
         int deadlocked = 0;
-        for (uint32_t b = 0; b < nb; b++)
-            deadlocked |= run_block(res, li, progs[li], prog_lens[li], L, b, mem, n_words, fuel, th, sh, q, shinit);
-        free(th); free(sh); free(q); free(shinit);
-        if (res->oom) break;
-        int parallel = 0;   /* may this launch run in parallel with another one? */
-        for (uint32_t k = 0; k < n_launches; k++)
-            if (k != li && !hb[(size_t)k * n_launches + li] && !hb[(size_t)li * n_launches + k]) parallel = 1;
-        if (parallel) {
-            sums[li] = access_summary(res, n_words, nt);
+        uint32_t nt = 1;
+        if (it->kind == IT_LAUNCH) {
+            const ora_launch *L = &launches[it->ref];
+            nt = L->block[0] * L->block[1] * L->block[2];
+            const uint32_t nb = L->grid[0] * L->grid[1] * L->grid[2];
+            ora_thread *th = calloc(nt, sizeof(ora_thread));
+            int32_t *sh = calloc(L->shmem_bytes / 4 + 1, sizeof(int32_t));
+            ora_store *q = calloc(nt, sizeof(ora_store));
+            uint8_t *shinit = (checks & CHECK_UNINIT_SHARED) ? calloc(L->shmem_bytes / 4 + 1, 1) : NULL;
+            if (!th || !sh || !q || ((checks & CHECK_UNINIT_SHARED) && !shinit)) {
+                free(th); free(sh); free(q); free(shinit); res->oom = 1; break;
+            }
+            for (uint32_t b = 0; b < nb; b++)
+                deadlocked |= run_block(res, li, progs[it->ref], prog_lens[it->ref], L, b, mem, n_words, fuel, th,
+                                        sh, q, shinit);
+            free(th); free(sh); free(q); free(shinit);
+            if (res->oom) break;
+        } else if (it->kind == IT_COPY) {
+            for (uint64_t k = 0; k < it->words; k++) mem[it->dst + k] = mem[it->src + k];   /* disjoint ranges */
+        } else if (it->kind == IT_HOST_WRITE) {
+            for (uint64_t k = 0; k < it->words; k++) mem[it->dst + k] = it->value;
+        }
+        int parallel = 0;   /* may this item run in parallel with another one? */
+        for (uint32_t k = 0; k < n_items; k++)
+            if (k != li && !hb[(size_t)k * n_items + li] && !hb[(size_t)li * n_items + k]) parallel = 1;
+        if (parallel && it->kind != IT_HOST_WAIT) {
+            sums[li] = it->kind == IT_LAUNCH ? access_summary(res, n_words, nt) : range_summary(it, n_words);
             if (!sums[li]) { res->oom = 1; break; }
             for (uint32_t k = 0; k < li && !res->oom; k++)
-                if (sums[k] && !hb[(size_t)k * n_launches + li])
+                if (sums[k] && !hb[(size_t)k * n_items + li])
                     cross_launch_races(res, k, sums[k], li, sums[li], n_words);
             if (res->oom) break;
         }
-        if (allocated) illegal_accesses(res, li, allocated);
-        if (res->oom) break;
-        check_launch(res, li, nt, (checks & CHECK_WARP) != 0);
-        if (res->oom) break;
+        if (it->kind == IT_LAUNCH) {
+            if (allocated) illegal_accesses(res, li, allocated);
+            if (res->oom) break;
+            check_launch(res, li, nt, (checks & CHECK_WARP) != 0);
+            if (res->oom) break;
+        }
         if (deadlocked) break;
         res->launches_completed = li + 1;
     }
     if (sums)
-        for (uint32_t k = 0; k < n_launches; k++) free(sums[k]);
+        for (uint32_t k = 0; k < n_items; k++) free(sums[k]);
     free(sums);
     free(hb);
     free(allocated);
@@ -727,6 +813,26 @@ int ora_run_job_opts(uint32_t n_launches, const uint64_t *const *progs, const ui
     res->n_faults = m;
     *out = res;
     return 0;
+}
+
+/* Run a job of launches only.  streams (n_launches entries) may be NULL: one
+ * stream; deps (n_deps pairs before, after with before < after) are event
+ * dependencies between launches.  The launches become items in order. */
+int ora_run_job_opts(uint32_t n_launches, const uint64_t *const *progs, const uint32_t *prog_lens,
+                     const ora_launch *launches, int32_t *mem, uint64_t n_words, uint32_t fuel,
+                     int keep_records, const uint32_t *streams, const uint32_t *deps, uint32_t n_deps,
+                     const uint64_t *allocs, uint32_t n_allocs, uint32_t checks, ora_result **out) {
+    ora_item *items = calloc((size_t)n_launches + 1, sizeof(ora_item));
+    if (!items) return 3;
+    for (uint32_t i = 0; i < n_launches; i++) {
+        items[i].kind = IT_LAUNCH;
+        items[i].ref = i;
+        items[i].stream = streams ? streams[i] : 0;
+    }
+    const int rc = ora_run_items(n_launches, progs, prog_lens, launches, items, n_launches, mem, n_words, fuel,
+                                 keep_records, deps, n_deps, allocs, n_allocs, checks, out);
+    free(items);
+    return rc;
 }
 
 int ora_run_job_ex(uint32_t n_launches, const uint64_t *const *progs, const uint32_t *prog_lens,

@@ -40,6 +40,28 @@ class _Launch(C.Structure):
                 ("params", C.c_int32 * 8)]
 
 
+ITEM_DTYPE = np.dtype([("kind", "<u4"), ("stream", "<u4"), ("ref", "<u4"), ("flags", "<u4"), ("dst", "<u8"),
+                       ("src", "<u8"), ("words", "<u8"), ("value", "<i4"), ("pad", "<u4")])
+IT_KINDS = {"launch": 0, "copy": 1, "host_read": 2, "host_write": 3, "host_wait": 4}
+WAIT_ALL = 0xFFFFFFFF
+
+
+def item_table(items) -> np.ndarray:
+    """The items of a job as the C struct array the oracle reads."""
+    t = np.zeros(max(len(items), 1), ITEM_DTYPE)
+    for i, it in enumerate(items):
+        if it.kind not in IT_KINDS:
+            raise ValueError(f"unknown item kind {it.kind!r}")
+        t[i]["kind"] = IT_KINDS[it.kind]
+        t[i]["stream"] = it.stream
+        t[i]["ref"] = it.launch if it.kind == "launch" else (
+            (WAIT_ALL if it.wait is None else it.wait) if it.kind == "host_wait" else 0)
+        t[i]["flags"] = 1 if it.sync else 0
+        t[i]["dst"], t[i]["src"], t[i]["words"] = it.dst, it.src, it.words
+        t[i]["value"] = int(np.int32(it.value))
+    return t
+
+
 RACE_DTYPE = np.dtype([(f, "<u4") for f in ("launch", "space", "scope", "block", "epoch", "addr", "w_tid", "o_tid",
                                             "w_pc", "o_pc")])
 FAULT_DTYPE = np.dtype([(f, "<u4") for f in ("launch", "kind", "block", "epoch", "a", "b", "c", "d")])
@@ -70,6 +92,11 @@ def _load():
                                          C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p, C.c_uint32,
                                          C.c_uint32, C.POINTER(C.c_void_p)]
         lib.ora_run_job_opts.restype = C.c_int
+        lib.ora_run_items.argtypes = [C.c_uint32, C.POINTER(C.c_void_p), C.POINTER(C.c_uint32),
+                                      C.POINTER(_Launch), C.c_void_p, C.c_uint32, C.c_void_p, C.c_uint64,
+                                      C.c_uint32, C.c_int, C.c_void_p, C.c_uint32, C.c_void_p, C.c_uint32,
+                                      C.c_uint32, C.POINTER(C.c_void_p)]
+        lib.ora_run_items.restype = C.c_int
         lib.ora_records.argtypes = [C.c_void_p]
         lib.ora_records.restype = C.c_uint64
         lib.ora_instructions.argtypes = [C.c_void_p]
@@ -125,6 +152,10 @@ def run_job(job, fuel: int = DEFAULT_FUEL, keep_records: bool = False,
             memory: Optional[np.ndarray] = None, uninit: bool = False, warp: bool = False) -> OracleResult:
     """Run every launch of ``job`` on a copy of its memory (or on ``memory``).
 
+    ``job.items``, when not None, is the job's host program instead: launches,
+    copies, host reads and writes and host waits in order (see ``Item``);
+    ``job.deps`` then links items and report launch fields are item indices.
+
     ``job.streams`` (one stream id per launch) and ``job.deps`` ((before,
     after) launch pairs), when the job has them, describe which launches may
     run in parallel; races between such launches are reported with scope 2.
@@ -155,13 +186,24 @@ def run_job(job, fuel: int = DEFAULT_FUEL, keep_records: bool = False,
     allocs = getattr(job, "allocs", None)
     al = None if allocs is None else np.ascontiguousarray(np.asarray(allocs, dtype=np.uint64).reshape(-1, 2))
     out = C.c_void_p()
-    rc = lib.ora_run_job_opts(n, ptrs, lens, ls, mem.ctypes.data, len(mem), fuel, int(keep_records),
-                              None if st is None else st.ctypes.data, dp.ctypes.data if len(dp) else None,
-                              len(dp), None if al is None else (al.ctypes.data if len(al) else
-                                                                C.addressof(_EMPTY_ALLOCS)),
-                              0 if al is None else len(al),
-                              (CHECK_UNINIT_SHARED if uninit else 0) | (CHECK_WARP if warp else 0),
-                              C.byref(out))
+    items = getattr(job, "items", None)
+    if items is not None:
+        if st is not None:
+            raise ValueError("a job with items gives each launch item its stream")
+        it = item_table(items)
+        rc = lib.ora_run_items(n, ptrs, lens, ls, it.ctypes.data, len(items), mem.ctypes.data, len(mem), fuel,
+                               int(keep_records), dp.ctypes.data if len(dp) else None, len(dp),
+                               None if al is None else (al.ctypes.data if len(al) else C.addressof(_EMPTY_ALLOCS)),
+                               0 if al is None else len(al),
+                               (CHECK_UNINIT_SHARED if uninit else 0) | (CHECK_WARP if warp else 0), C.byref(out))
+    else:
+        rc = lib.ora_run_job_opts(n, ptrs, lens, ls, mem.ctypes.data, len(mem), fuel, int(keep_records),
+                                  None if st is None else st.ctypes.data, dp.ctypes.data if len(dp) else None,
+                                  len(dp), None if al is None else (al.ctypes.data if len(al) else
+                                                                    C.addressof(_EMPTY_ALLOCS)),
+                                  0 if al is None else len(al),
+                                  (CHECK_UNINIT_SHARED if uninit else 0) | (CHECK_WARP if warp else 0),
+                                  C.byref(out))
     if rc != 0:
         raise ValueError(f"oracle rejected the job (code {rc})")
     try:

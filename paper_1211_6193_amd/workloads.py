@@ -48,6 +48,49 @@ class LaunchSpec:
         return self.block[0] * self.block[1] * self.block[2]
 
 
+ITEM_KINDS = ("launch", "copy", "host_read", "host_write", "host_wait")
+
+
+@dataclass
+class Item:
+    """One step of a job's host program (used when ``Job.items`` is set):
+    ``launch`` runs ``launches[launch]`` in ``stream``; ``copy`` moves
+    ``words`` words from ``src`` to ``dst`` in ``stream`` (``sync``: the host
+    waits for it, as for a cudaMemcpy); ``host_read`` / ``host_write`` are
+    the host touching words ``[dst, dst + words)`` (a write stores
+    ``value``); ``host_wait`` blocks the host until item ``wait`` (None:
+    every earlier device item) has finished."""
+    kind: str
+    stream: int = 0
+    launch: int = 0
+    dst: int = 0
+    src: int = 0
+    words: int = 0
+    value: int = 0
+    wait: Optional[int] = None
+    sync: bool = False
+
+
+def launch_item(launch: int, stream: int = 0) -> Item:
+    return Item("launch", stream=stream, launch=launch)
+
+
+def copy_item(dst: int, src: int, words: int, stream: int = 0, sync: bool = False) -> Item:
+    return Item("copy", stream=stream, dst=dst, src=src, words=words, sync=sync)
+
+
+def host_read(addr: int, words: int) -> Item:
+    return Item("host_read", dst=addr, words=words)
+
+
+def host_write(addr: int, words: int, value: int) -> Item:
+    return Item("host_write", dst=addr, words=words, value=value)
+
+
+def host_wait(item: Optional[int] = None) -> Item:
+    return Item("host_wait", wait=item)
+
+
 @dataclass
 class Job:
     launches: List[LaunchSpec]
@@ -56,6 +99,10 @@ class Job:
     streams: Optional[List[int]] = None             # stream of each launch (None: one stream)
     deps: List[Tuple[int, int]] = field(default_factory=list)   # (before, after): after waits for before
     allocs: Optional[List[Tuple[int, int]]] = None  # device allocations (base, words); None: no check
+    # host program order of launches, copies and host steps; None: the
+    # launches in order (with ``streams``).  With items, ``deps`` and every
+    # report's launch field index items, and ``streams`` must be None.
+    items: Optional[List[Item]] = None
 
 
 def _prog(a: Asm) -> np.ndarray:
