@@ -155,6 +155,7 @@ kc_status kc_ctx_set_option(kc_ctx *ctx, const char *key, int64_t value);
  * "jit_compiled", "jit_compile_ms", "jit_failures", "site_replays",
  * "cross_launch_races", "alloc_findings", "stage_splits" (groups of a batch's
  * launches halved because their access-record key did not fit together),
+ * "item_steps" (copy and host steps of host programs run),
  * "noalloc_calls" and
  * "noalloc_scratch_peak" (calls of kc_launch_noalloc and the most bytes of
  * its static scratch area one of them used).
@@ -232,6 +233,48 @@ typedef struct {
     uint64_t base, words;
 } kc_region;
 
+/* An item of a job's host program (Section 3 "Streams and events": launches
+ * and memory transfers pass through the stream queues, and the host
+ * synchronises with cudaStreamSynchronize, cudaEventSynchronize and
+ * cudaDeviceSynchronize).  Device items run in `stream`:
+ *   KC_ITEM_LAUNCH     runs launches[ref];
+ *   KC_ITEM_COPY       copies `words` words from src to dst (the two ranges
+ *                      may not overlap); flags KC_ITEM_SYNC: the host waits
+ *                      for it on the spot (a cudaMemcpy).  Its word k is
+ *                      copied by thread k.
+ * Host items (no stream):
+ *   KC_ITEM_HOST_READ  the host reads words [dst, dst + words);
+ *   KC_ITEM_HOST_WRITE the host stores `value` to words [dst, dst + words);
+ *                      word dst + k is touched by thread k;
+ *   KC_ITEM_HOST_WAIT  the host waits until device item `ref` has finished
+ *                      (an event recorded right behind it, or the last
+ *                      item of a stream), or every earlier device item when
+ *                      ref = KC_WAIT_ALL (cudaDeviceSynchronize).
+ * Item i happens before a later item j when both are device items of one
+ * stream, a dependency links them (an event), i is a host item (the host
+ * issues j after it), i is a synchronous copy, or j waits for i -- or a
+ * chain of these leads from i to j.  Items ordered neither way race as
+ * launches do (scope 2, with item indices).  Copies and host items make no
+ * access records. */
+enum {
+    KC_ITEM_LAUNCH = 0,
+    KC_ITEM_COPY = 1,
+    KC_ITEM_HOST_READ = 2,
+    KC_ITEM_HOST_WRITE = 3,
+    KC_ITEM_HOST_WAIT = 4
+};
+#define KC_ITEM_SYNC 1u
+#define KC_WAIT_ALL 0xFFFFFFFFu
+typedef struct {
+    uint32_t kind;              /* KC_ITEM_* */
+    uint32_t stream;            /* device items */
+    uint32_t ref;               /* launch index (LAUNCH), item waited for or KC_WAIT_ALL (HOST_WAIT) */
+    uint32_t flags;             /* KC_ITEM_SYNC (COPY) */
+    uint64_t dst, src, words;   /* word ranges of COPY, HOST_READ, HOST_WRITE; words < 2^32 */
+    int32_t value;              /* HOST_WRITE */
+    uint32_t pad;
+} kc_item;
+
 /* A job: launches on one memory (Section 2).  By default they form one
  * stream and run in order.  With `streams` (one stream id per launch) and
  * `deps`, launch i happens before launch j when a chain of same-stream order
@@ -259,6 +302,14 @@ typedef struct {
      * one KC_ALLOC finding.  NULL: no check. */
     const kc_region *allocs;
     uint32_t n_allocs;
+    /* The host program: when `items` is not NULL the job runs its n_items
+     * items in order (n_items <= 4096) instead of its launches; launch items
+     * name launches by index, `deps` link device items by item index,
+     * `streams` must be NULL, and every report's launch field is an item
+     * index.  launches_completed then counts the leading items that
+     * completed (a launch that does not complete ends the job). */
+    const kc_item *items;
+    uint32_t n_items;
 } kc_job;
 
 /* Submit jobs as one batch; returns at once.  All jobs of the batch execute
@@ -268,7 +319,10 @@ typedef struct {
  * the caller and must not be touched until kc_poll reports the batch done.
  * Errors: KC_E_INVAL (also for a dependency that does not point forward,
  * more than 4096 launches in a job with streams or dependencies, n_deps
- * without a dependency array, or an allocation outside the job's memory),
+ * without a dependency array, an allocation outside the job's memory, or an
+ * item that is malformed: an unknown kind, a launch index out of range, a
+ * range outside the memory, overlapping copy ranges, a wait for a host item
+ * or a later one, a dependency on a host item, streams given with items),
  * KC_E_NOMEM (also when the batch's worker thread cannot be started),
  * KC_E_DEVICE.  Errors of the run itself come back from kc_poll. */
 kc_status kc_batch_submit(kc_ctx *ctx, const kc_job *jobs, uint32_t n_jobs, void *stream, uint64_t *ticket);

@@ -11,6 +11,7 @@
 // conflicts with it.
 #include <algorithm>
 
+#include "../../include/kc.h"
 #include "kc_internal.h"
 
 namespace kc {
@@ -709,7 +710,43 @@ __global__ void __launch_bounds__(WG) k_cross_launch(const uint32_t *__restrict_
     }
 }
 
+// A copy (mem[dst + k] = mem[src + k]; the ranges do not overlap) or a host
+// write (mem[dst + k] = value) of a job's host program.
+__global__ void __launch_bounds__(WG) k_item_apply(int32_t *__restrict__ mem, uint32_t kind, uint64_t dst,
+                                                   uint64_t src, uint64_t words, int32_t value) {
+    for (uint64_t k = (uint64_t)blockIdx.x * WG + threadIdx.x; k < words; k += (uint64_t)gridDim.x * WG)
+        mem[dst + k] = kind == KC_ITEM_COPY ? mem[src + k] : value;
+}
+
+// Access summary of a copy or host access (same layout as k_summary's):
+// thread k touches the k-th word of each range it reads or writes.  The
+// ranges are disjoint, so each word is written once.
+__global__ void __launch_bounds__(WG) k_item_summary(uint32_t *__restrict__ sum, uint64_t n_words, uint32_t kind,
+                                                     uint64_t dst, uint64_t src, uint64_t words) {
+    for (uint64_t k = (uint64_t)blockIdx.x * WG + threadIdx.x; k < words; k += (uint64_t)gridDim.x * WG) {
+        if (kind == KC_ITEM_COPY) sum[src + k] = (uint32_t)k;
+        sum[dst + k] = (uint32_t)k;
+        if (kind != KC_ITEM_HOST_READ) sum[n_words + dst + k] = (uint32_t)k;
+    }
+}
+
 }  // namespace
+
+hipError_t launch_item_apply(int32_t *mem, uint32_t kind, uint64_t dst, uint64_t src, uint64_t words, int32_t value,
+                             hipStream_t s) {
+    if (words == 0 || (kind != KC_ITEM_COPY && kind != KC_ITEM_HOST_WRITE)) return hipSuccess;
+    hipLaunchKernelGGL(k_item_apply, dim3((uint32_t)std::min<uint64_t>(blocks_for(words), 8192)), dim3(WG), 0, s,
+                       mem, kind, dst, src, words, value);
+    return hipGetLastError();
+}
+
+hipError_t launch_item_summary(uint32_t *sum, uint64_t n_words, uint32_t kind, uint64_t dst, uint64_t src,
+                               uint64_t words, hipStream_t s) {
+    if (words == 0 || kind == KC_ITEM_LAUNCH || kind == KC_ITEM_HOST_WAIT) return hipSuccess;
+    hipLaunchKernelGGL(k_item_summary, dim3((uint32_t)std::min<uint64_t>(blocks_for(words), 8192)), dim3(WG), 0, s,
+                       sum, n_words, kind, dst, src, words);
+    return hipGetLastError();
+}
 
 hipError_t launch_summary(const SummaryArgs &a, hipStream_t s) {
     if (a.n == 0) return hipSuccess;

@@ -305,6 +305,13 @@ hipError_t launch_held_compact(const uint64_t *blk_log, const uint32_t *blk_held
 // unit = tag.
 hipError_t launch_cross_launch(const uint32_t *si, const uint32_t *sj, uint64_t n_words, uint32_t tag,
                                uint32_t earlier, DevRace *out, uint32_t cap, uint32_t *count, hipStream_t s);
+// Items of a job's host program: apply a copy or a host write (KC_ITEM_*
+// kind; other kinds do nothing) to mem, and write the access summary of a
+// copy or host access into sum (2 * n_words words, preset to 0xFFFFFFFF).
+hipError_t launch_item_apply(int32_t *mem, uint32_t kind, uint64_t dst, uint64_t src, uint64_t words, int32_t value,
+                             hipStream_t s);
+hipError_t launch_item_summary(uint32_t *sum, uint64_t n_words, uint32_t kind, uint64_t dst, uint64_t src,
+                               uint64_t words, hipStream_t s);
 hipError_t launch_copy_units(const DevUnit *units, uint32_t n_units, uint32_t max_words, bool to_snapshot,
                              const uint32_t *unit_mask, hipStream_t s);
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);

@@ -323,12 +323,25 @@ struct kc_ctx {
 // is kept as one bit per pair).
 constexpr uint32_t kMaxStreamLaunches = 4096;
 
+// Steps of a job: its items when it has a host program, else its launches.
+uint32_t job_steps(const kc_job &job) { return job.items ? job.n_items : job.n_launches; }
+// The launch step i runs, or nullptr for a copy or host step.
+const kc_launch_desc *step_launch(const kc_job &job, uint32_t i) {
+    if (!job.items) return &job.launches[i];
+    return job.items[i].kind == KC_ITEM_LAUNCH ? &job.launches[job.items[i].ref] : nullptr;
+}
+// Launches and copies run on the device, in streams; the rest on the host.
+bool device_item(const kc_job &job, uint32_t i) {
+    return !job.items || job.items[i].kind == KC_ITEM_LAUNCH || job.items[i].kind == KC_ITEM_COPY;
+}
+
 struct Batch {
     std::vector<kc_job> jobs;
     std::vector<std::vector<kc_launch_desc>> descs;
     std::vector<std::vector<uint32_t>> streams;
     std::vector<std::vector<kc_dep>> deps;
     std::vector<std::vector<kc_region>> allocs;
+    std::vector<std::vector<kc_item>> items;
     hipStream_t stream = nullptr;
     std::thread worker;
     std::once_flag joined;
@@ -1732,29 +1745,45 @@ template <class F> kc_status guarded(kc_ctx *ctx, F &&body) {
     }
 }
 
-// Which launches of a job may run in parallel (Section 3 "Streams and
-// events").  before[j] holds bit i when launch i happens before launch j: the
-// closure of same-stream order and dependencies, built in launch order since
-// every edge points forward.
+// Which steps (launches, or items of a host program) of a job may run in
+// parallel (Section 3 "Streams and events").  before[j] holds bit i when step
+// i happens before step j: the closure of same-stream order of device steps,
+// dependencies, host program order (a host step, or a copy the host waits
+// for on the spot, comes before every later step) and host waits (the step
+// waited for, or every earlier device step, comes before the wait); every
+// edge points forward, so rows are built in order.
 struct LaunchOrder {
     uint32_t n = 0, words = 0;
     std::vector<uint64_t> before;       // n rows of `words` words
-    std::vector<char> parallel;         // launch may run in parallel with another one
+    std::vector<char> parallel;         // step may run in parallel with another one
     bool any = false;
     bool ordered(uint32_t i, uint32_t j) const { return (before[(size_t)j * words + i / 64] >> (i % 64)) & 1u; }
 
     explicit LaunchOrder(const kc_job &job) {
-        if (!job.streams && !job.n_deps) return;
-        n = job.n_launches;
+        if (!job.streams && !job.n_deps && !job.items) return;
+        n = job_steps(job);
         words = (n + 63) / 64;
         before.assign((size_t)n * words, 0);
         std::vector<std::vector<uint32_t>> preds(n);
-        std::unordered_map<uint32_t, uint32_t> last;    // stream -> its latest launch
+        std::unordered_map<uint32_t, uint32_t> last;    // stream -> its latest device step
+        int64_t host_point = -1;                        // latest host step or synchronous copy
         for (uint32_t j = 0; j < n; j++) {
-            const uint32_t sid = job.streams ? job.streams[j] : 0u;
-            auto it = last.find(sid);
-            if (it != last.end()) preds[j].push_back(it->second);
-            last[sid] = j;
+            const kc_item *it = job.items ? &job.items[j] : nullptr;
+            if (device_item(job, j)) {
+                const uint32_t sid = it ? it->stream : job.streams ? job.streams[j] : 0u;
+                auto f = last.find(sid);
+                if (f != last.end()) preds[j].push_back(f->second);
+                last[sid] = j;
+            }
+            if (host_point >= 0) preds[j].push_back((uint32_t)host_point);
+            if (it && it->kind == KC_ITEM_HOST_WAIT) {
+                if (it->ref != KC_WAIT_ALL) preds[j].push_back(it->ref);
+                else
+                    for (uint32_t i = 0; i < j; i++)
+                        if (device_item(job, i)) preds[j].push_back(i);
+            }
+            if (it && (!device_item(job, j) || (it->kind == KC_ITEM_COPY && (it->flags & KC_ITEM_SYNC))))
+                host_point = j;
         }
         for (uint32_t d = 0; d < job.n_deps; d++) preds[job.deps[d].after].push_back(job.deps[d].before);
         for (uint32_t j = 0; j < n; j++) {
@@ -1772,22 +1801,22 @@ struct LaunchOrder {
     }
 };
 
-// Races between launches that may run in parallel, for the units of a stage
-// (launch index li): the access summary of each unit whose launch may run in
-// parallel with another, then one scan against each earlier such launch.
-// Summaries stay in `sums` (per job and launch) for the later stages.
-void cross_launch_check(kc_ctx *ctx, Workspace &ws, hipStream_t s, Stage &st, uint32_t li, const kc_job *jobs,
-                        const std::vector<uint32_t> &who, const std::vector<LaunchOrder> &order,
-                        std::vector<std::vector<DBuf>> &sums, std::vector<kc_report *> &reports) {
+// Access summaries of step li for the jobs in `who` whose step may run in
+// parallel with another (per job and step, kept in `sums` for the later
+// steps), preset to "no access"; nullptr entries for the other jobs.
+std::vector<uint32_t *> prepare_summaries(kc_ctx *ctx, Workspace &ws, hipStream_t s, uint32_t li,
+                                          const kc_job *jobs, const std::vector<uint32_t> &who,
+                                          const std::vector<LaunchOrder> &order,
+                                          std::vector<std::vector<DBuf>> &sums) {
     std::vector<uint32_t *> ptr(who.size(), nullptr);
-    bool any = false;
     size_t held = 0;
     for (auto &v : sums)
         for (auto &b : v) held += b.bytes;
     for (size_t i = 0; i < who.size(); i++) {
         const uint32_t j = who[i];
         if (!order[j].any || !order[j].parallel[li]) continue;
-        if (sums[j].empty()) sums[j].resize(jobs[j].n_launches);
+        if (jobs[j].items && jobs[j].items[li].kind == KC_ITEM_HOST_WAIT) continue;    // touches nothing
+        if (sums[j].empty()) sums[j].resize(job_steps(jobs[j]));
         DBuf &b = sums[j][li];
         b.reserve(std::max<uint64_t>(jobs[j].n_words, 1) * 8);
         held += b.bytes;
@@ -1795,21 +1824,23 @@ void cross_launch_check(kc_ctx *ctx, Workspace &ws, hipStream_t s, Stage &st, ui
             throw KcError{KC_E_BUDGET, "launch summaries exceed the HBM budget"};
         HIPCHK(hipMemsetAsync(b.p, 0xFF, jobs[j].n_words * 8, s));
         ptr[i] = b.as<uint32_t>();
-        any = true;
     }
-    if (!any) return;
+    return ptr;
+}
+
+// Races between step li (summaries `ptr`, per job of `who`) and every
+// earlier step of the same job that may run in parallel with it.
+void scan_cross(kc_ctx *ctx, hipStream_t s, uint32_t li, const kc_job *jobs, const std::vector<uint32_t> &who,
+                const std::vector<uint32_t *> &ptr, const std::vector<LaunchOrder> &order,
+                std::vector<std::vector<DBuf>> &sums, std::vector<kc_report *> &reports) {
     struct Scratch {
-        DBuf ptrs, list, count;
+        DBuf list, count;
         ~Scratch() {
-            ptrs.release();
             list.release();
             count.release();
         }
     } tmp;
-    DBuf &dptr = tmp.ptrs, &list = tmp.list, &count = tmp.count;
-    dptr.reserve(ptr.size() * sizeof(uint32_t *));
-    HIPCHK(hipMemcpyAsync(dptr.p, ptr.data(), ptr.size() * sizeof(uint32_t *), hipMemcpyHostToDevice, s));
-    st.summarize(dptr.as<uint32_t *>());
+    DBuf &list = tmp.list, &count = tmp.count;
     uint32_t cap = 4096;
     count.reserve(4);
     std::vector<DevRace> got;
@@ -1843,6 +1874,53 @@ void cross_launch_check(kc_ctx *ctx, Workspace &ws, hipStream_t s, Stage &st, ui
     });
     for (auto &r : got) reports[r.unit]->add_race(kc_race{li, 1, 2, r.block, r.epoch, r.addr, r.w, r.o});
     ctx->stat_add("cross_launch_races", (double)got.size());
+}
+
+// Races between launches that may run in parallel, for the units of a stage
+// (step li): the access summary of each unit whose launch may run in
+// parallel with another, from the stage's log, then one scan against each
+// earlier such step.
+void cross_launch_check(kc_ctx *ctx, Workspace &ws, hipStream_t s, Stage &st, uint32_t li, const kc_job *jobs,
+                        const std::vector<uint32_t> &who, const std::vector<LaunchOrder> &order,
+                        std::vector<std::vector<DBuf>> &sums, std::vector<kc_report *> &reports) {
+    std::vector<uint32_t *> ptr = prepare_summaries(ctx, ws, s, li, jobs, who, order, sums);
+    if (std::all_of(ptr.begin(), ptr.end(), [](uint32_t *p) { return p == nullptr; })) return;
+    DBuf dptr;
+    try {
+        dptr.reserve(ptr.size() * sizeof(uint32_t *));
+        HIPCHK(hipMemcpyAsync(dptr.p, ptr.data(), ptr.size() * sizeof(uint32_t *), hipMemcpyHostToDevice, s));
+        st.summarize(dptr.as<uint32_t *>());
+        HIPCHK(hipStreamSynchronize(s));    // `ptr` is read by the copy above
+    } catch (...) {
+        dptr.release();
+        throw;
+    }
+    dptr.release();
+    scan_cross(ctx, s, li, jobs, who, ptr, order, sums, reports);
+}
+
+// Copy and host steps (step li of the jobs in `who`): a copy or host write
+// takes effect on the job's memory; with streams, its access summary is
+// written and scanned against the earlier steps.  Such steps always complete.
+void run_item_steps(kc_ctx *ctx, Workspace &ws, hipStream_t s, uint32_t li, const kc_job *jobs,
+                    const std::vector<uint32_t> &who, const std::vector<LaunchOrder> &order,
+                    std::vector<std::vector<DBuf>> &sums, std::vector<kc_report *> &reports, bool streams) {
+    for (uint32_t j : who) {
+        const kc_item &it = jobs[j].items[li];
+        HIPCHK(launch_item_apply(jobs[j].dev_mem, it.kind, it.dst, it.src, it.words, it.value, s));
+        reports[j]->launches_completed = li + 1;
+    }
+    ctx->stat_add("item_steps", (double)who.size());
+    if (!streams) return;
+    std::vector<uint32_t *> ptr = prepare_summaries(ctx, ws, s, li, jobs, who, order, sums);
+    bool any = false;
+    for (size_t i = 0; i < who.size(); i++) {
+        if (!ptr[i]) continue;
+        const kc_item &it = jobs[who[i]].items[li];
+        HIPCHK(launch_item_summary(ptr[i], jobs[who[i]].n_words, it.kind, it.dst, it.src, it.words, s));
+        any = true;
+    }
+    if (any) scan_cross(ctx, s, li, jobs, who, ptr, order, sums, reports);
 }
 
 // Run every launch of `jobs` in order, stage by stage (launch index j of all
@@ -1901,23 +1979,30 @@ void run_jobs(kc_ctx *ctx, const kc_job *jobs, uint32_t n_jobs, hipStream_t s, s
         }
         std::vector<char> alive(n_jobs, 1);
         uint32_t max_l = 0;
-        for (uint32_t j = 0; j < n_jobs; j++) max_l = std::max(max_l, jobs[j].n_launches);
+        for (uint32_t j = 0; j < n_jobs; j++) max_l = std::max(max_l, job_steps(jobs[j]));
         for (uint32_t li = 0; li < max_l; li++) {
             std::vector<UnitIn> in;
-            std::vector<uint32_t> all_who;
+            std::vector<uint32_t> all_who, item_who;
             for (uint32_t j = 0; j < n_jobs; j++) {
-                if (!alive[j] || li >= jobs[j].n_launches) continue;
-                in.push_back(UnitIn{&jobs[j].launches[li], jobs[j].dev_mem, jobs[j].n_words});
-                all_who.push_back(j);
+                if (!alive[j] || li >= job_steps(jobs[j])) continue;
+                const kc_launch_desc *d = step_launch(jobs[j], li);
+                if (d) {
+                    in.push_back(UnitIn{d, jobs[j].dev_mem, jobs[j].n_words});
+                    all_who.push_back(j);
+                } else {
+                    item_who.push_back(j);
+                }
             }
-            if (in.empty()) break;
+            if (in.empty() && item_who.empty()) break;
+            if (!item_who.empty()) run_item_steps(ctx, ws, s, li, jobs, item_who, order, sums, reports, streams);
             // The units run as one stage unless their record key does not
             // fit (too many units for its fields next to the largest grid,
             // block and memory, or more barrier epochs than its epoch field
             // holds): then the group is halved and each half runs again, its
             // memories back at the launch start.  A single unit that does not
             // fit is KC_E_OVERFLOW.
-            std::vector<std::pair<size_t, size_t>> parts{{0, in.size()}};
+            std::vector<std::pair<size_t, size_t>> parts;
+            if (!in.empty()) parts.push_back({0, in.size()});
             for (size_t pi = 0; pi < parts.size(); pi++) {
             const size_t p0 = parts[pi].first, p1 = parts[pi].second;
             const std::vector<UnitIn> pin(in.begin() + p0, in.begin() + p1);
@@ -2107,6 +2192,39 @@ static double get_stat_locked(kc_ctx *ctx, const char *key) {
     return it == ctx->stats.end() ? 0.0 : it->second;
 }
 
+// The items of a job's host program (kc_item), checked against its launches
+// and memory; an empty string when they are well formed.
+static std::string validate_items(const kc_job &job) {
+    if (job.streams) return "streams given with items (each device item names its stream)";
+    if (job.n_items > kMaxStreamLaunches) return "more than " + std::to_string(kMaxStreamLaunches) + " items";
+    const uint64_t n = job.n_words;
+    for (uint32_t i = 0; i < job.n_items; i++) {
+        const kc_item &it = job.items[i];
+        const std::string at = "item " + std::to_string(i) + ": ";
+        switch (it.kind) {
+        case KC_ITEM_LAUNCH:
+            if (it.ref >= job.n_launches) return at + "launch index out of range";
+            break;
+        case KC_ITEM_COPY:
+            if (it.src > n || it.words > n - it.src) return at + "copy source outside the memory";
+            if (it.words && it.src < it.dst + it.words && it.dst < it.src + it.words) return at + "copy ranges overlap";
+            [[fallthrough]];
+        case KC_ITEM_HOST_READ:
+        case KC_ITEM_HOST_WRITE:
+            if (it.dst > n || it.words > n - it.dst) return at + "range outside the memory";
+            if (it.words > 0xFFFFFFFFull) return at + "more than 2^32 - 1 words";
+            break;
+        case KC_ITEM_HOST_WAIT:
+            if (it.ref != KC_WAIT_ALL && (it.ref >= i || !device_item(job, it.ref)))
+                return at + "a wait must name an earlier launch or copy";
+            break;
+        default:
+            return at + "unknown kind";
+        }
+    }
+    return "";
+}
+
 // kc_batch_submit's argument checks.
 static kc_status validate_jobs(kc_ctx *ctx, const kc_job *jobs, uint32_t n_jobs) {
     for (uint32_t j = 0; j < n_jobs; j++) {
@@ -2137,11 +2255,20 @@ static kc_status validate_jobs(kc_ctx *ctx, const kc_job *jobs, uint32_t n_jobs)
                 return KC_E_INVAL;
             }
         }
+        if (jobs[j].items) {
+            std::string why = validate_items(jobs[j]);
+            if (!why.empty()) {
+                ctx->err = "job " + std::to_string(j) + ": " + why;
+                return KC_E_INVAL;
+            }
+        }
         for (uint32_t d = 0; d < jobs[j].n_deps; d++) {
             const kc_dep &e = jobs[j].deps[d];
-            if (e.before >= e.after || e.after >= jobs[j].n_launches) {
+            if (e.before >= e.after || e.after >= job_steps(jobs[j]) ||
+                !device_item(jobs[j], e.before) || !device_item(jobs[j], e.after)) {
                 ctx->err = "job " + std::to_string(j) + " dependency " + std::to_string(d) +
-                           ": needs before < after < n_launches";
+                           (jobs[j].items ? ": needs before < after < n_items, both device items"
+                                          : ": needs before < after < n_launches");
                 return KC_E_INVAL;
             }
         }
@@ -2158,6 +2285,7 @@ static kc_status submit_batch(kc_ctx *ctx, const kc_job *jobs, uint32_t n_jobs, 
     b->streams.resize(n_jobs);
     b->deps.resize(n_jobs);
     b->allocs.resize(n_jobs);
+    b->items.resize(n_jobs);
     for (uint32_t j = 0; j < n_jobs; j++) {
         b->descs[j].assign(jobs[j].launches, jobs[j].launches + jobs[j].n_launches);
         b->jobs[j].launches = b->descs[j].data();
@@ -2174,6 +2302,11 @@ static kc_status submit_batch(kc_ctx *ctx, const kc_job *jobs, uint32_t n_jobs, 
             b->allocs[j].assign(jobs[j].allocs, jobs[j].allocs + jobs[j].n_allocs);
             b->allocs[j].push_back(kc_region{0, 0});
             b->jobs[j].allocs = b->allocs[j].data();
+        }
+        if (jobs[j].items) {
+            b->items[j].assign(jobs[j].items, jobs[j].items + jobs[j].n_items);
+            b->items[j].push_back(kc_item{});     // keeps the pointer non-null for an empty list
+            b->jobs[j].items = b->items[j].data();
         }
     }
     b->stream = (hipStream_t)stream;

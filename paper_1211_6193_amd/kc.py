@@ -59,11 +59,34 @@ class Region(C.Structure):
     _fields_ = [("base", C.c_uint64), ("words", C.c_uint64)]
 
 
+class ItemDesc(C.Structure):
+    _fields_ = [("kind", C.c_uint32), ("stream", C.c_uint32), ("ref", C.c_uint32), ("flags", C.c_uint32),
+                ("dst", C.c_uint64), ("src", C.c_uint64), ("words", C.c_uint64), ("value", C.c_int32),
+                ("pad", C.c_uint32)]
+
+
+# kc_item kinds (KC_ITEM_*), KC_ITEM_SYNC and KC_WAIT_ALL
+ITEM_KINDS = {"launch": 0, "copy": 1, "host_read": 2, "host_write": 3, "host_wait": 4}
+ITEM_SYNC = 1
+WAIT_ALL = 0xFFFFFFFF
+
+
 class JobDesc(C.Structure):
     _fields_ = [("launches", C.POINTER(LaunchDesc)), ("n_launches", C.c_uint32), ("dev_mem", C.c_void_p),
                 ("n_words", C.c_uint64), ("tag", C.c_uint64), ("streams", C.POINTER(C.c_uint32)),
                 ("deps", C.POINTER(Dep)), ("n_deps", C.c_uint32), ("allocs", C.POINTER(Region)),
-                ("n_allocs", C.c_uint32)]
+                ("n_allocs", C.c_uint32), ("items", C.POINTER(ItemDesc)), ("n_items", C.c_uint32)]
+
+
+def _item_desc(it) -> ItemDesc:
+    """One step of a host program (an object with the fields of
+    workloads.Item) as a kc_item."""
+    if it.kind not in ITEM_KINDS:
+        raise ValueError(f"unknown item kind {it.kind!r}")
+    ref = it.launch if it.kind == "launch" else (
+        (WAIT_ALL if it.wait is None else it.wait) if it.kind == "host_wait" else 0)
+    return ItemDesc(ITEM_KINDS[it.kind], it.stream, ref, ITEM_SYNC if it.sync else 0, it.dst, it.src, it.words,
+                    int(C.c_int32(it.value).value), 0)
 
 
 _lib = None
@@ -341,6 +364,7 @@ class Batch:
             streams = item[3] if len(item) > 3 else None
             deps = item[4] if len(item) > 4 else ()
             allocs = item[5] if len(item) > 5 else None
+            steps = item[6] if len(item) > 6 else None
             arr = (LaunchDesc * max(len(launches), 1))()
             for j, (p, g, b, sh, ps) in enumerate(launches):
                 arr[j] = _desc(p, g, b, sh, ps)
@@ -366,14 +390,21 @@ class Batch:
                 keep.append(rarr)
                 jd[i].allocs = C.cast(rarr, C.POINTER(Region))
                 jd[i].n_allocs = len(allocs)
+            if steps is not None:
+                iarr = (ItemDesc * max(len(steps), 1))(*[_item_desc(x) for x in steps])
+                keep.append(iarr)
+                jd[i].items = C.cast(iarr, C.POINTER(ItemDesc))
+                jd[i].n_items = len(steps)
         return Prepared(jd, keep, n, [item[1] for item in jobs])
 
     def submit(self, jobs, stream=None) -> int:
         """jobs: a Prepared batch or a list of (launches, mem_tensor, tag) or
-        (launches, mem_tensor, tag, streams, deps[, allocs]) with launches =
+        (launches, mem_tensor, tag, streams, deps[, allocs[, items]]) with launches =
         [(prog, grid, block, shmem, params), ...], streams one stream id per
-        launch (or None), deps (before, after) launch pairs and allocs the
-        device allocations as (base, words) ranges (or None: no check)."""
+        launch (or None), deps (before, after) launch pairs, allocs the
+        device allocations as (base, words) ranges (or None: no check) and
+        items the host program (objects with workloads.Item's fields, or
+        None: the launches in order)."""
         prep = jobs if isinstance(jobs, Prepared) else self.prepare(jobs)
         t = C.c_uint64()
         self.ctx._check(self.ctx.lib.kc_batch_submit(self.ctx.h, prep.jd, prep.n, _stream_handle(stream),
@@ -401,7 +432,7 @@ def job_launches(ctx: Context, job) -> list:
 
 def job_item(ctx: Context, job, mem, tag):
     return (job_launches(ctx, job), mem, tag, getattr(job, "streams", None), getattr(job, "deps", None) or (),
-            getattr(job, "allocs", None))
+            getattr(job, "allocs", None), getattr(job, "items", None))
 
 
 def run_job(ctx: Context, job, mem=None, stream=None):

@@ -271,6 +271,47 @@ def streams_reduce_job(n_blocks: int = 4096, missing_event: bool = False, seed: 
                streams=[0, 1, 0], deps=[] if missing_event else [(1, 2)])
 
 
+HOST_PROGRAM_BUGS = (None, "event", "wait", "reuse")
+
+
+def host_program_job(n_blocks: int = 4096, bug: Optional[str] = None, seed: int = BASE_SEED + 7) -> Job:
+    """The two-stream reduction of ``streams_reduce_job`` as a whole host
+    program (memory transfers and host synchronisation): the two input
+    arrays are copied from host buffers in streams 0 and 1 (asynchronously),
+    the three tree launches run as there, the final partial sums are copied
+    back to a host buffer in stream 0, the host waits for that copy (a stream
+    synchronisation), reads the result and then refills the first host input
+    buffer.  ``bug`` leaves out one synchronisation: "event" (the final launch
+    no longer waits for stream 1), "wait" (the host reads the result before the
+    copy back has finished), "reuse" (the host refills the second input buffer
+    right after the launches, while its copy in may still be reading it)."""
+    if bug not in HOST_PROGRAM_BUGS:
+        raise ValueError(f"unknown bug {bug!r}")
+    base = streams_reduce_job(n_blocks, seed=seed)
+    n = n_blocks * 256
+    m = 2 * n_blocks // 256
+    dev_words = len(base.memory)
+    h_a, h_b, h_out = dev_words, dev_words + n, dev_words + 2 * n
+    mem = np.zeros(h_out + m, dtype=np.int32)
+    mem[:dev_words] = base.memory
+    mem[h_a:h_a + n] = base.memory[0:n]            # host copies of the inputs
+    mem[h_b:h_b + n] = base.memory[n:2 * n]
+    mem[0:2 * n] = 0                               # device inputs arrive by copy
+    in_a, in_b, out_c = 0, n, 2 * n + 6 * n_blocks
+    items = [copy_item(in_a, h_a, n, stream=0), copy_item(in_b, h_b, n, stream=1),
+             launch_item(0, 0), launch_item(1, 1)]
+    if bug == "reuse":
+        items.append(host_write(h_b, n, 0))
+    items += [launch_item(2, 0), copy_item(h_out, out_c, m, stream=0)]
+    if bug != "wait":
+        items.append(host_wait(len(items) - 1))
+    items += [host_read(h_out, m), host_write(h_a, n, 1)]
+    final = items.index(launch_item(2, 0))
+    deps = [] if bug == "event" else [(3, final)]
+    return Job(base.launches, mem, {"family": "HOST-PROGRAM", "n_blocks": n_blocks, "bug": bug},
+               deps=deps, allocs=[(0, dev_words)], items=items)
+
+
 # ---------------------------------------------------------------------------
 # Mixed families (workload 3) with one optionally faulty block
 # ---------------------------------------------------------------------------

@@ -46,7 +46,8 @@ def test_struct_layouts_match_the_header(tmp_path):
     import subprocess
     src = tmp_path / "layout.c"
     fields = {"kc_job": ["launches", "n_launches", "dev_mem", "n_words", "tag", "streams", "deps", "n_deps",
-                         "allocs", "n_allocs"],
+                         "allocs", "n_allocs", "items", "n_items"],
+              "kc_item": ["kind", "stream", "ref", "flags", "dst", "src", "words", "value", "pad"],
               "kc_launch_desc": ["prog", "grid", "block", "shmem_bytes", "params", "n_params"],
               "kc_dep": ["before", "after"], "kc_region": ["base", "words"], "kc_race_site": ["w_pc", "o_pc"]}
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{os.path.join(ROOT, "include", "kc.h")}"',
@@ -60,7 +61,8 @@ def test_struct_layouts_match_the_header(tmp_path):
     exe = tmp_path / "layout"
     subprocess.check_call(["gcc", "-o", str(exe), str(src)])
     got = dict(l.split() for l in subprocess.check_output([str(exe)]).decode().splitlines())
-    py = {"kc_job": kc.JobDesc, "kc_launch_desc": kc.LaunchDesc, "kc_dep": kc.Dep, "kc_region": kc.Region}
+    py = {"kc_job": kc.JobDesc, "kc_launch_desc": kc.LaunchDesc, "kc_dep": kc.Dep, "kc_region": kc.Region,
+          "kc_item": kc.ItemDesc}
     for st, cls in py.items():
         assert int(got[st]) == ctypes.sizeof(cls), st
         for f in fields[st]:

@@ -51,3 +51,20 @@ def test_one_stream_per_launch_required():
     L = (_Prog(), (1, 1, 1), (4, 1, 1), 0, ())
     with pytest.raises(ValueError):
         _prepare([([L, L], _Mem(8), 0, [0], (), None)])
+
+
+def test_host_program_items_are_marshalled():
+    from paper_1211_6193_amd import workloads as W
+    L = (_Prog(), (1, 1, 1), (4, 1, 1), 0, ())
+    steps = [W.copy_item(8, 0, 4, stream=2, sync=True), W.launch_item(0, stream=1), W.host_wait(1),
+             W.host_write(0, 3, -5), W.host_read(8, 2), W.host_wait()]
+    p = _prepare([([L], _Mem(16), 3, None, [(0, 1)], None, steps), ([L], _Mem(8), 4)])
+    a, b = p.jd[0], p.jd[1]
+    assert a.n_items == 6 and not a.streams and a.n_deps == 1
+    got = [(a.items[i].kind, a.items[i].stream, a.items[i].ref, a.items[i].flags, a.items[i].dst, a.items[i].src,
+            a.items[i].words, a.items[i].value) for i in range(6)]
+    assert got == [(1, 2, 0, 1, 8, 0, 4, 0), (0, 1, 0, 0, 0, 0, 0, 0), (4, 0, 1, 0, 0, 0, 0, 0),
+                   (3, 0, 0, 0, 0, 0, 3, -5), (2, 0, 0, 0, 8, 0, 2, 0), (4, 0, kc.WAIT_ALL, 0, 0, 0, 0, 0)]
+    assert not b.items and b.n_items == 0
+    with pytest.raises(ValueError):
+        _prepare([([L], _Mem(8), 0, None, (), None, [W.Item("memset")])])
