@@ -381,6 +381,14 @@ def local_vs_sort(ctx, step, rep, mem, torch, np, steps=10):
             "same_reports": same}
 
 
+TUNE_CACHE = os.path.join(ROOT, "paper_1211_6193_amd", "tune_mi355x.json")
+
+
+def tune_keys():
+    from paper_1211_6193_amd import tune
+    return list(tune.SPACE)
+
+
 def batched_vs_plain(ctx, W, kc, torch, np, reps=3, plain_sample=200, verify=400):
     """Workload 3 (10,000 mixed instances, seed 12116196): the whole set as one
     batch (kc_batch_submit + kc_poll) against one plain kc_launch per instance
@@ -390,8 +398,13 @@ def batched_vs_plain(ctx, W, kc, torch, np, reps=3, plain_sample=200, verify=400
     memory) for the comparison with the oracle in the CPU-baseline leg."""
     jobs = W.config3_jobs(n=10000)
     mems = [torch.from_numpy(np.ascontiguousarray(j.memory)).cuda() for j in jobs]
-    batch = kc.Batch(ctx)
-    prep = batch.prepare([(kc.job_launches(ctx, j), m, i) for i, (j, m) in enumerate(zip(jobs, mems))])
+    # the batch runs with the autotuner's setting for this GPU (written by
+    # python -m paper_1211_6193_amd.tune on a 2000-instance sample)
+    tuned = os.path.exists(TUNE_CACHE)
+    bctx = kc.Context(ctx.device, tune_cache=TUNE_CACHE if tuned else None)
+    bctx.set_option("jit", int(ctx.stat("option.jit")))
+    batch = kc.Batch(bctx)
+    prep = batch.prepare([(kc.job_launches(bctx, j), m, i) for i, (j, m) in enumerate(zip(jobs, mems))])
     stream = torch.cuda.current_stream()
     res = batch.poll(batch.submit(prep, stream=stream), wait=True)          # warm-up
     times = []
@@ -424,6 +437,8 @@ def batched_vs_plain(ctx, W, kc, torch, np, reps=3, plain_sample=200, verify=400
             "plain_p50_ms": round(lat_ms[len(lat_ms) // 2], 4),
             "plain_p99_ms": round(lat_ms[min(len(lat_ms) - 1, int(0.99 * len(lat_ms)))], 4),
             "speedup": round((records / best) / plain_rate, 2),
+            "tune_cache": os.path.relpath(TUNE_CACHE, ROOT) if tuned else None,
+            "tuned_setting": {k: int(bctx.stat("option." + k)) for k in tune_keys()},
             "bit_exact_sample": None, "verified_instances": 0}, sample
 
 
@@ -510,7 +525,10 @@ def served(ctx, W, torch, np, seconds, rates=(1000.0, 5000.0, 20000.0)):
     torch.cuda.synchronize()
     out = {"workload": f"workload 5: {seconds:g} s of Poisson arrivals per rate; pool of {len(small)} workload-3 "
                        f"instances and {len(big)} 4096x256 trees (p=0.05); 4 slots, 64 GiB budget"}
-    srv = server.Server(ctx, budget_bytes=64 << 30, slots=4)
+    # the library enforces the same budget over all of its buffers; admission
+    # charges each batch the footprint the library reports for it
+    sctx = kc_budget_context(ctx, 64 << 30)
+    srv = server.Server(sctx, budget_bytes=64 << 30, slots=4)
     srv.run(W.pooled_requests(1000.0, 0.3, small, big), pristine=pristine)          # warm-up
     for rate in rates:
         res = srv.run(W.pooled_requests(rate, seconds, small, big), pristine=pristine)
@@ -523,7 +541,19 @@ def served(ctx, W, torch, np, seconds, rates=(1000.0, 5000.0, 20000.0)):
     res = srv.run(W.pooled_requests(rates[-1], 0.25, small, big, seed=W.BASE_SEED + 55), pristine=pristine,
                   keep_every=25)
     out["sample"] = res["sample"]
+    out["device_bytes_peak"] = int(sctx.stat("device_bytes_peak"))
+    out["budget_trims"] = int(sctx.stat("budget_trims"))
+    sctx.close()
     return out
+
+
+def kc_budget_context(ctx, budget):
+    """A context on ctx's device with ctx's options and an HBM budget."""
+    from paper_1211_6193_amd import kc
+    c = kc.Context(ctx.device, hbm_budget_bytes=budget)
+    for k in ("jit", "jit_waves", "sort_tile", "sort_bits", "stage_bytes", "stage", "local", "side_streams"):
+        c.set_option(k, int(ctx.stat("option." + k)))
+    return c
 
 
 if __name__ == "__main__":

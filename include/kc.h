@@ -108,7 +108,10 @@ void kc_ctx_destroy(kc_ctx *ctx);
  * "fuel" (instructions per thread, default 1<<20), "timing" (1 = time the
  * stages with HIP events on the launch stream; 2 = time only the free run,
  * which records two events per stage instead of about six), "sort_tile" (keys per sort
- * tile: 1024, 2048 (default), 4096 or 8192), "log_records" (initial log capacity, >= 1024),
+ * tile: 1024, 2048 (default), 4096 or 8192), "sort_bits" (radix digit width of
+ * the sort's passes, 4 to 8, default 8), "side_streams" (streams over which
+ * the launches of one batch step -- one per block-size class -- are spread,
+ * 1 to 4, default 4), "log_records" (initial log capacity, >= 1024),
  * "stage" (interpreter staging granule per wave: 128, 256, 512 or 1024
  * records), "stage_bytes" (LDS bytes of per-block record staging, 8192 to
  * 98304, default 8192), "local" (1 = check each barrier epoch's accesses inside
@@ -155,7 +158,9 @@ kc_status kc_ctx_set_option(kc_ctx *ctx, const char *key, int64_t value);
  * "jit_compiled", "jit_compile_ms", "jit_failures", "site_replays",
  * "cross_launch_races", "alloc_findings", "stage_splits" (groups of a batch's
  * launches halved because their access-record key did not fit together),
- * "item_steps" (copy and host steps of host programs run),
+ * "item_steps" (copy and host steps of host programs run), "device_bytes"
+ * and "device_bytes_peak" (see kc_batch_footprint), "budget_trims" (idle
+ * workspaces freed to stay within the budget),
  * "noalloc_calls" and
  * "noalloc_scratch_peak" (calls of kc_launch_noalloc and the most bytes of
  * its static scratch area one of them used).
@@ -326,6 +331,24 @@ typedef struct {
  * KC_E_NOMEM (also when the batch's worker thread cannot be started),
  * KC_E_DEVICE.  Errors of the run itself come back from kc_poll. */
 kc_status kc_batch_submit(kc_ctx *ctx, const kc_job *jobs, uint32_t n_jobs, void *stream, uint64_t *ticket);
+
+/* The device bytes the library would reserve to run `jobs` as one batch
+ * (before any growth of its access log), for admission against the
+ * context's HBM budget: the largest step's launch-start snapshot, location
+ * tables, access log at the context's current record hint (which grows with
+ * the logs seen so far) with its sort and replay scratch, per-block lists and
+ * finding lists, plus the access summaries and allocation bitmaps held for
+ * the whole run.  With n_jobs = 0 it is the part every batch reserves
+ * whatever its jobs; a batch's footprint is at most that part plus, for each
+ * of its jobs, what the job adds to it alone.  The jobs are checked as by
+ * kc_batch_submit, except that their memories need not exist yet (dev_mem
+ * may be NULL); nothing runs.
+ * The context's current device bytes and their peak are the statistics
+ * "device_bytes" and "device_bytes_peak"; its budget bounds all of its
+ * buffers together, across concurrent batches (idle workspaces kept for reuse
+ * are freed first when a call would exceed it).
+ * Errors: those of kc_batch_submit's argument checks. */
+kc_status kc_batch_footprint(kc_ctx *ctx, const kc_job *jobs, uint32_t n_jobs, uint64_t *bytes);
 
 /* Collect a batch.  With wait = 0 returns KC_E_PENDING (out untouched) while
  * it runs.  On KC_OK `out` (n_out >= n_jobs pointers) receives one report per

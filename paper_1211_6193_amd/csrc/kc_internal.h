@@ -187,10 +187,11 @@ struct SortScratch {
 struct VKey {
     uint32_t s_ep, ueb, s_blk, pb, vbits;
 };
-// Sort keys[0..n) ascending by the virtual key (stable).  *out points at the
+// Sort keys[0..n) ascending by the virtual key (stable), `digit` bits (4..8)
+// per pass over inputs larger than one workgroup's.  *out points at the
 // sorted array: keys itself or scratch.alt.
 hipError_t radix_sort(uint64_t *keys, uint64_t n, const VKey &vk, SortScratch &sc,
-                      uint32_t tile, hipStream_t s, uint64_t **out);
+                      uint32_t tile, hipStream_t s, uint64_t **out, uint32_t digit = 8);
 size_t radix_hist_entries(uint64_t n, uint32_t tile);
 
 struct CheckArgs {

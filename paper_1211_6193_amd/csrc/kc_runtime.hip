@@ -92,11 +92,24 @@ struct Arena {
 };
 thread_local Arena *t_arena = nullptr;
 
+// Device bytes a context's buffers hold (the library's own HBM use, which
+// its budget bounds), now and at most so far.
+struct DevBytes {
+    std::atomic<int64_t> live{0}, peak{0};
+    void add(int64_t d) {
+        const int64_t v = live.fetch_add(d) + d;
+        int64_t p = peak.load();
+        while (v > p && !peak.compare_exchange_weak(p, v)) {
+        }
+    }
+};
+
 // Grow-only device buffer.  Its contents do not survive a growth.
 struct DBuf {
     void *p = nullptr;
     size_t bytes = 0;
     bool carved = false;    // p lies in the calling thread's arena (never freed)
+    DevBytes *acct = nullptr;   // the owning context's count of device bytes
     void reserve(size_t need) {
         if (need <= bytes) return;
         if (t_arena) {
@@ -120,6 +133,7 @@ struct DBuf {
         size_t nb = std::max(need, bytes + bytes / 2);
         nb = (nb + 4095) & ~size_t(4095);
         if (p) HIPCHK(hipFree(p));
+        if (p && acct) acct->add(-(int64_t)bytes);
         p = nullptr;
         bytes = 0;
         if (hipMalloc(&p, nb) != hipSuccess) {
@@ -132,9 +146,13 @@ struct DBuf {
             }
         }
         bytes = nb;
+        if (acct) acct->add((int64_t)nb);
     }
     void release() {
-        if (p && !carved) (void)hipFree(p);
+        if (p && !carved) {
+            (void)hipFree(p);
+            if (acct) acct->add(-(int64_t)bytes);
+        }
         p = nullptr;
         bytes = 0;
         carved = false;
@@ -180,6 +198,14 @@ struct Workspace {
         HIPCHK(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
         for (auto &e : join) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         init = true;
+    }
+    // Count every buffer's device bytes in `a`.
+    void account(DevBytes *a) {
+        DBuf *all[] = {&units, &items, &comp_off, &comp_blocks, &mask, &snap, &log, &alt, &rlog,
+                       &ralt, &fs, &hist, &part, &faults, &rfaults, &races, &edges, &blk_recs,
+                       &rblk_recs, &blk_flags, &rflags, &ctr, &rctr, &wlog, &lraces, &rlraces, &longseg, &covlist,
+                       &rtable, &ftable, &downer, &dflags, &blk_instr, &blk_grecs, &blk_log, &blk_held, &blk_off};
+        for (auto *b : all) b->acct = a;
     }
     // Forget every carved buffer (the arena restarts at each call).
     void forget_carved() {
@@ -237,6 +263,8 @@ struct Options {
     uint32_t fuel = 1u << 20;
     int timing = 0;
     uint32_t sort_tile = 2048;
+    uint32_t sort_bits = 8;         // radix digit width of the sort's passes
+    uint32_t side_streams = 4;      // side streams over which a step's launches are spread
     uint64_t log_records = 1ull << 22;
     uint32_t stage = 256;           // staged records per wave in the lockstep replay
     uint32_t stage_bytes = 8192;    // LDS for staging + local sort per workgroup (free run)
@@ -269,6 +297,7 @@ struct kc_ctx {
     std::unordered_map<std::string, double> stats;
     std::map<uint64_t, std::shared_ptr<Batch>> batches;
     uint64_t next_ticket = 1;
+    DevBytes bytes;                             // device bytes of every workspace and summary
     std::unique_ptr<Workspace> acquire() {
         std::lock_guard<std::mutex> g(mu);
         if (!free_ws.empty()) {
@@ -276,7 +305,23 @@ struct kc_ctx {
             free_ws.pop_back();
             return w;
         }
-        return std::make_unique<Workspace>();
+        auto w = std::make_unique<Workspace>();
+        w->account(&bytes);
+        return w;
+    }
+    // Would `extra` more device bytes exceed the budget?  Idle workspaces
+    // (kept for reuse by later calls) are freed first.
+    bool over_budget(uint64_t extra = 0) {
+        if (!budget) return false;
+        if ((uint64_t)std::max<int64_t>(bytes.live.load(), 0) + extra <= budget) return false;
+        std::vector<std::unique_ptr<Workspace>> idle;
+        {
+            std::lock_guard<std::mutex> g(mu);
+            idle.swap(free_ws);
+        }
+        if (!idle.empty()) stat_add("budget_trims", (double)idle.size());
+        idle.clear();
+        return (uint64_t)std::max<int64_t>(bytes.live.load(), 0) + extra > budget;
     }
     void release(std::unique_ptr<Workspace> w) {
         std::lock_guard<std::mutex> g(mu);
@@ -614,7 +659,7 @@ struct Stage {
         side_used = 0;
     }
     hipStream_t side(uint32_t i) {
-        const uint32_t k = i % Workspace::kSide;
+        const uint32_t k = i % std::max<uint32_t>(1, std::min<uint32_t>(opt.side_streams, Workspace::kSide));
         if (k >= side_used) {
             for (uint32_t q = side_used; q <= k; q++) HIPCHK(hipStreamWaitEvent(ws.side[q], ws.fork, 0));
             side_used = k + 1;
@@ -960,7 +1005,7 @@ struct Stage {
                 off += u.n_words;
             }
         }
-        if (!opt.arena && ctx->budget && ws.device_bytes() > ctx->budget)
+        if (!opt.arena && ctx->over_budget())
             throw KcError{KC_E_BUDGET, "workspace exceeds the HBM budget"};
         upload_units();
         if (check) HIPCHK(launch_copy_units(ws.units.as<DevUnit>(), n, max_words, true, nullptr, s));
@@ -1025,7 +1070,8 @@ struct Stage {
             bool again = false;
             if (check && (c.flags & FLAG_LOG_OVERFLOW)) {
                 log_cap = c.log_count + c.log_count / 8 + 1024;
-                if (!opt.arena && ctx->budget && ws.device_bytes() + log_cap * 16 > ctx->budget)
+                if (!opt.arena && ctx->over_budget(log_cap * 16 > ws.log.bytes + ws.alt.bytes
+                                                      ? log_cap * 16 - ws.log.bytes - ws.alt.bytes : 0))
                     throw KcError{KC_E_BUDGET, "access log does not fit the HBM budget"};
                 ws.log.reserve(log_cap * 8);
                 again = true;
@@ -1148,7 +1194,7 @@ struct Stage {
         sc.alt = alt.as<uint64_t>();
         sc.hist = ws.hist.as<uint32_t>();
         sc.part = ws.part.as<uint32_t>();
-        HIPCHK(radix_sort(keys.as<uint64_t>(), n, check_key(), sc, opt.sort_tile, s, &res));
+        HIPCHK(radix_sort(keys.as<uint64_t>(), n, check_key(), sc, opt.sort_tile, s, &res, opt.sort_bits));
         return res;
     }
 
@@ -1808,20 +1854,18 @@ std::vector<uint32_t *> prepare_summaries(kc_ctx *ctx, Workspace &ws, hipStream_
                                           const kc_job *jobs, const std::vector<uint32_t> &who,
                                           const std::vector<LaunchOrder> &order,
                                           std::vector<std::vector<DBuf>> &sums) {
+    (void)ws;
     std::vector<uint32_t *> ptr(who.size(), nullptr);
-    size_t held = 0;
-    for (auto &v : sums)
-        for (auto &b : v) held += b.bytes;
     for (size_t i = 0; i < who.size(); i++) {
         const uint32_t j = who[i];
         if (!order[j].any || !order[j].parallel[li]) continue;
         if (jobs[j].items && jobs[j].items[li].kind == KC_ITEM_HOST_WAIT) continue;    // touches nothing
         if (sums[j].empty()) sums[j].resize(job_steps(jobs[j]));
         DBuf &b = sums[j][li];
-        b.reserve(std::max<uint64_t>(jobs[j].n_words, 1) * 8);
-        held += b.bytes;
-        if (ctx->budget && ws.device_bytes() + held > ctx->budget)
+        b.acct = &ctx->bytes;
+        if (ctx->over_budget(std::max<uint64_t>(jobs[j].n_words, 1) * 8))
             throw KcError{KC_E_BUDGET, "launch summaries exceed the HBM budget"};
+        b.reserve(std::max<uint64_t>(jobs[j].n_words, 1) * 8);
         HIPCHK(hipMemsetAsync(b.p, 0xFF, jobs[j].n_words * 8, s));
         ptr[i] = b.as<uint32_t>();
     }
@@ -1971,6 +2015,7 @@ void run_jobs(kc_ctx *ctx, const kc_job *jobs, uint32_t n_jobs, hipStream_t s, s
                 for (; x + 32 <= end; x += 32) bits[x >> 5] = 0xFFFFFFFFu;
                 for (; x < end; x++) bits[x >> 5] |= 1u << (x & 31);
             }
+            allocated[j].acct = &ctx->bytes;
             allocated[j].reserve(bits.size() * 4);
             // on the batch's stream (the null stream would not order it with it)
             HIPCHK(hipMemcpyAsync(allocated[j].p, bits.data(), bits.size() * 4, hipMemcpyHostToDevice, s));
@@ -2145,6 +2190,8 @@ static kc_status set_option_locked(kc_ctx *ctx, const char *key, int64_t v) {
     else if (k == "fuel" && v >= 1 && v <= 0xFFFFFFFFll) ctx->opt.fuel = (uint32_t)v;
     else if (k == "timing" && v >= 0 && v <= 2) ctx->opt.timing = (int)v;
     else if (k == "sort_tile" && (v == 1024 || v == 2048 || v == 4096 || v == 8192)) ctx->opt.sort_tile = (uint32_t)v;
+    else if (k == "sort_bits" && v >= 4 && v <= 8) ctx->opt.sort_bits = (uint32_t)v;
+    else if (k == "side_streams" && v >= 1 && v <= 4) ctx->opt.side_streams = (uint32_t)v;
     else if (k == "log_records" && v >= 1024) ctx->opt.log_records = (uint64_t)v;
     else if (k == "stage" && (v == 128 || v == 256 || v == 512 || v == 1024)) ctx->opt.stage = (uint32_t)v;
     else if (k == "stage_bytes" && v >= 8192 && v <= 98304) ctx->opt.stage_bytes = (uint32_t)v;
@@ -2168,6 +2215,8 @@ static kc_status set_option_locked(kc_ctx *ctx, const char *key, int64_t v) {
 static double get_stat_locked(kc_ctx *ctx, const char *key) {
     std::lock_guard<std::mutex> g(ctx->mu);
     const std::string k(key);
+    if (k == "device_bytes") return (double)ctx->bytes.live.load();
+    if (k == "device_bytes_peak") return (double)ctx->bytes.peak.load();
     if (k.rfind("option.", 0) == 0) {
         const std::string o = k.substr(7);
         const Options &op = ctx->opt;
@@ -2175,6 +2224,8 @@ static double get_stat_locked(kc_ctx *ctx, const char *key) {
         if (o == "fuel") return op.fuel;
         if (o == "timing") return op.timing;
         if (o == "sort_tile") return op.sort_tile;
+        if (o == "sort_bits") return op.sort_bits;
+        if (o == "side_streams") return op.side_streams;
         if (o == "log_records") return (double)op.log_records;
         if (o == "stage") return op.stage;
         if (o == "stage_bytes") return op.stage_bytes;
@@ -2274,6 +2325,52 @@ static kc_status validate_jobs(kc_ctx *ctx, const kc_job *jobs, uint32_t n_jobs)
         }
     }
     return KC_OK;
+}
+
+// The device bytes a batch's run reserves before any growth (kc_batch_footprint):
+// the access log at the context's current record hint with its sort, table
+// and replay scratch (40 B per record) and the finding lists at their
+// current capacities, whatever the jobs; per step, the launch-start snapshot
+// and the direct location tables (9 B per word of the step's memories) and
+// per-block lists (28 B per block, and 4 KiB more per block for the held
+// representatives while those regions stay small) -- the most of these over
+// the steps, since a workspace is reused from step to step; and, held for
+// the whole run, an access summary of 8 B per word for each step that may run
+// in parallel with another and the allocation bitmaps.  Every term but the
+// first grows with the jobs, so the footprint of a batch is at most that of
+// no jobs plus, for each job, what it adds on its own.
+static uint64_t batch_footprint(kc_ctx *ctx, const kc_job *jobs, uint32_t n_jobs) {
+    const Options op = ctx->options();
+    uint32_t fault_cap = 0, lrace_cap = 0;
+    ctx->caps(fault_cap, lrace_cap);
+    const uint64_t recs = std::max<uint64_t>(op.log_records, 1024);
+    uint32_t steps = 0;
+    for (uint32_t j = 0; j < n_jobs; j++) steps = std::max(steps, job_steps(jobs[j]));
+    // what every batch reserves whatever its jobs: the log and the lists
+    const uint64_t fixed = 40 * recs + (uint64_t)fault_cap * sizeof(DevFault) +
+                           (uint64_t)lrace_cap * sizeof(DevRace) + (1u << 20);
+    uint64_t stage_max = 0, held = 0;
+    for (uint32_t li = 0; li < steps; li++) {
+        uint64_t words = 0, blocks = 0;
+        for (uint32_t j = 0; j < n_jobs; j++) {
+            if (li >= job_steps(jobs[j])) continue;
+            const kc_launch_desc *d = step_launch(jobs[j], li);
+            if (!d) continue;
+            words += jobs[j].n_words;
+            blocks += (uint64_t)d->grid.x * d->grid.y * d->grid.z;
+        }
+        uint64_t b = 9 * words + 28 * blocks;
+        if (blocks * REP_HOLD * 8 <= (256ull << 20)) b += blocks * (REP_HOLD * 8 + 12);
+        stage_max = std::max(stage_max, b);
+    }
+    for (uint32_t j = 0; j < n_jobs; j++) {
+        const LaunchOrder o(jobs[j]);
+        if (o.any)
+            for (uint32_t li = 0; li < o.n; li++)
+                if (o.parallel[li]) held += std::max<uint64_t>(jobs[j].n_words, 1) * 8;
+        if (jobs[j].allocs) held += (jobs[j].n_words + 31) / 32 * 4 + 4;
+    }
+    return fixed + stage_max + held;
 }
 
 // The part of kc_batch_submit after validation: copy the batch and start its
@@ -2595,6 +2692,20 @@ kc_status kc_batch_submit(kc_ctx *ctx, const kc_job *jobs, uint32_t n_jobs, void
     return guarded(ctx, [&] {
         const kc_status st = validate_jobs(ctx, jobs, n_jobs);
         return st != KC_OK ? st : submit_batch(ctx, jobs, n_jobs, stream, ticket);
+    });
+}
+
+kc_status kc_batch_footprint(kc_ctx *ctx, const kc_job *jobs, uint32_t n_jobs, uint64_t *bytes) {
+    if (!ctx || !bytes || (!jobs && n_jobs)) return KC_E_INVAL;
+    return guarded(ctx, [&] {
+        // the memories need not exist yet: validate with a stand-in address
+        std::vector<kc_job> v(jobs, jobs + n_jobs);
+        for (auto &j : v)
+            if (!j.dev_mem) j.dev_mem = reinterpret_cast<int32_t *>(uintptr_t{256});
+        const kc_status st = validate_jobs(ctx, v.data(), n_jobs);
+        if (st != KC_OK) return st;
+        *bytes = batch_footprint(ctx, v.data(), n_jobs);
+        return KC_OK;
     });
 }
 

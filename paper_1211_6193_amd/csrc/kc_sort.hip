@@ -191,13 +191,13 @@ __global__ void __launch_bounds__(WG) k_rs_scatter(const uint64_t *__restrict__ 
 }
 
 template <int ITEMS>
-hipError_t sort_passes(uint64_t *keys, uint64_t n, const VKey &vk, uint32_t hi, SortScratch &sc, hipStream_t s,
-                       uint64_t **out) {
+hipError_t sort_passes(uint64_t *keys, uint64_t n, const VKey &vk, uint32_t hi, uint32_t digit, SortScratch &sc,
+                       hipStream_t s, uint64_t **out) {
     constexpr uint64_t TILE = WG * ITEMS;
     const uint32_t n_tiles = (uint32_t)((n + TILE - 1) / TILE);
     uint64_t *a = keys, *b = sc.alt;
-    for (uint32_t sh = 0; sh < hi; sh += 8) {
-        const uint32_t bits = (hi - sh) < 8 ? (hi - sh) : 8;
+    for (uint32_t sh = 0; sh < hi; sh += digit) {
+        const uint32_t bits = (hi - sh) < digit ? (hi - sh) : digit;
         hipLaunchKernelGGL(k_rs_hist<ITEMS>, dim3(n_tiles), dim3(WG), 0, s, a, n, vk, sh, bits, sc.hist);
         hipLaunchKernelGGL(k_rs_scan, dim3(256), dim3(WG), 0, s, sc.hist, n_tiles, sc.part);
         hipLaunchKernelGGL(k_rs_scatter<ITEMS>, dim3(n_tiles), dim3(WG), 0, s, a, b, n, vk, sh, bits, sc.hist,
@@ -336,7 +336,8 @@ size_t radix_hist_entries(uint64_t n, uint32_t tile) {
 }
 
 hipError_t radix_sort(uint64_t *keys, uint64_t n, const VKey &vk, SortScratch &sc, uint32_t tile,
-                      hipStream_t s, uint64_t **out) {
+                      hipStream_t s, uint64_t **out, uint32_t digit) {
+    if (digit < 4 || digit > 8) digit = 8;
     *out = keys;
     if (n <= 1 || vk.vbits == 0) return hipSuccess;
     if (n <= SMALL_N) {
@@ -347,11 +348,11 @@ hipError_t radix_sort(uint64_t *keys, uint64_t n, const VKey &vk, SortScratch &s
         return hipGetLastError();
     }
     switch (tile) {
-    case 1024: return sort_passes<4>(keys, n, vk, vk.vbits, sc, s, out);
-    case 2048: return sort_passes<8>(keys, n, vk, vk.vbits, sc, s, out);
-    case 8192: return sort_passes<32>(keys, n, vk, vk.vbits, sc, s, out);
-    case 4096: return sort_passes<16>(keys, n, vk, vk.vbits, sc, s, out);
-    default: return sort_passes<8>(keys, n, vk, vk.vbits, sc, s, out);
+    case 1024: return sort_passes<4>(keys, n, vk, vk.vbits, digit, sc, s, out);
+    case 2048: return sort_passes<8>(keys, n, vk, vk.vbits, digit, sc, s, out);
+    case 8192: return sort_passes<32>(keys, n, vk, vk.vbits, digit, sc, s, out);
+    case 4096: return sort_passes<16>(keys, n, vk, vk.vbits, digit, sc, s, out);
+    default: return sort_passes<8>(keys, n, vk, vk.vbits, digit, sc, s, out);
     }
 }
 

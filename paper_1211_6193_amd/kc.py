@@ -27,6 +27,7 @@ DEADLOCK, DIVERGENCE, OOB, FUEL, ARITH, ALLOC, UNINIT = 1, 2, 3, 4, 5, 6, 7
 # Every entry point include/kc.h declares.
 EXPORTS = ["kc_ctx_create", "kc_ctx_destroy", "kc_ctx_set_option", "kc_ctx_get_stat", "kc_last_error",
            "kc_program_load", "kc_program_free", "kc_launch", "kc_launch_noalloc", "kc_batch_submit", "kc_poll",
+           "kc_batch_footprint",
            "kc_report_records", "kc_report_launches_completed", "kc_report_races", "kc_report_faults",
            "kc_report_race_sites",
            "kc_report_tag", "kc_report_free", "kc_reports_collect", "kc_reports_free"]
@@ -113,6 +114,7 @@ def load_library(path: str = LIB_PATH):
         "kc_launch_noalloc": ([vp, C.POINTER(LaunchDesc), vp, u64, vp, C.POINTER(vp)], C.c_int),
         "kc_batch_submit": ([vp, C.POINTER(JobDesc), u32, vp, C.POINTER(u64)], C.c_int),
         "kc_poll": ([vp, u64, C.c_int, C.POINTER(vp), u32], C.c_int),
+        "kc_batch_footprint": ([vp, C.POINTER(JobDesc), u32, C.POINTER(u64)], C.c_int),
         "kc_report_records": ([vp], u64),
         "kc_report_launches_completed": ([vp], u32),
         "kc_report_races": ([vp, C.POINTER(u64)], vp),
@@ -371,8 +373,11 @@ class Batch:
             keep.append(arr)
             jd[i].launches = C.cast(arr, C.POINTER(LaunchDesc))
             jd[i].n_launches = len(launches)
-            jd[i].dev_mem = mem.data_ptr()
-            jd[i].n_words = mem.numel()
+            if isinstance(mem, int):           # a word count: no memory yet (kc_batch_footprint)
+                jd[i].dev_mem, jd[i].n_words = None, mem
+            else:
+                jd[i].dev_mem = mem.data_ptr()
+                jd[i].n_words = mem.numel()
             jd[i].tag = tag
             if streams is not None:
                 if len(streams) != len(launches):
@@ -412,6 +417,16 @@ class Batch:
         self._keep[t.value] = (prep.jd, prep.keep, prep.n, prep.mems)
         return t.value
 
+    def footprint(self, jobs) -> int:
+        """kc_batch_footprint: the device bytes the library would reserve to
+        run ``jobs`` (a Prepared batch or items as for ``submit``; a memory
+        may be given as its word count) as one batch."""
+        prep = jobs if isinstance(jobs, Prepared) else self.prepare(jobs)
+        b = C.c_uint64()
+        self.ctx._check(self.ctx.lib.kc_batch_footprint(self.ctx.h, prep.jd, prep.n, C.byref(b)),
+                        "kc_batch_footprint")
+        return int(b.value)
+
     def poll(self, ticket: int, wait: bool = True) -> Optional[List[Report]]:
         n = self._keep[ticket][2]
         out = (C.c_void_p * max(n, 1))()
@@ -433,6 +448,12 @@ def job_launches(ctx: Context, job) -> list:
 def job_item(ctx: Context, job, mem, tag):
     return (job_launches(ctx, job), mem, tag, getattr(job, "streams", None), getattr(job, "deps", None) or (),
             getattr(job, "allocs", None), getattr(job, "items", None))
+
+
+def jobs_footprint(ctx: Context, jobs) -> int:
+    """Device bytes the library would reserve to run workload ``jobs`` as one
+    batch (their memories need not be on the GPU)."""
+    return Batch(ctx).footprint([job_item(ctx, j, len(j.memory), i) for i, j in enumerate(jobs)])
 
 
 def run_job(ctx: Context, job, mem=None, stream=None):

@@ -2,9 +2,10 @@
 
 Requests arrive with timestamps (Poisson arrivals from ``workloads.request_stream``).
 The loop keeps up to ``slots`` batches in flight, each on its own HIP stream
-through ``kc_batch_submit``; whenever a slot is free it admits every request
-that has arrived and whose estimated device footprint fits in the free part of
-a fixed HBM budget (FIFO, a request is never skipped), uploads their memories
+through ``kc_batch_submit``; whenever a slot is free it admits the longest run
+of arrived requests whose device footprint -- as the library accounts it
+(``kc_batch_footprint``), plus their memories -- fits in the free part of a
+fixed HBM budget (FIFO, a request is never skipped), uploads their memories
 and submits them as one batch.  Completed batches are collected with
 non-blocking ``kc_poll``; their memory is released and the latency
 (completion time - arrival time) recorded.  The request source is replayed in
@@ -49,39 +50,57 @@ class Request:
 
 
 class Admission:
-    """FIFO admission under a byte budget with a bounded number of slots."""
+    """FIFO admission under a byte budget with a bounded number of slots.
 
-    def __init__(self, budget_bytes: int, slots: int, max_batch: int = 4096):
+    ``cost(requests)`` gives the device bytes a batch of those requests
+    holds (by default the sum of their ``bytes``); a batch is the longest
+    prefix of the queue, up to ``max_batch`` requests, whose cost fits in the
+    free part of the budget, found by bisection (the cost grows with the
+    batch).  A request is never skipped."""
+
+    def __init__(self, budget_bytes: int, slots: int, max_batch: int = 4096,
+                 cost: Optional[Callable[[Sequence[Request]], int]] = None):
         self.budget = budget_bytes
         self.slots = slots
         self.max_batch = max_batch
+        self.cost = cost or (lambda rs: sum(r.bytes for r in rs))
         self.in_use = 0
         self.inflight = 0
+        self.held: Dict[int, int] = {}      # id(batch list) -> its cost
         self.queue: Deque[Request] = collections.deque()
 
     def arrive(self, r: Request):
-        if r.bytes > self.budget:
-            raise ValueError(f"request {r.rid} needs {r.bytes} B, more than the whole budget")
+        if self.cost([r]) > self.budget:
+            raise ValueError(f"request {r.rid} needs {self.cost([r])} B, more than the whole budget")
         self.queue.append(r)
 
     def take(self) -> List[Request]:
         """Requests for the next batch (empty if no slot or nothing fits)."""
         if self.inflight >= self.slots or not self.queue:
             return []
-        batch, used = [], 0
-        while self.queue and len(batch) < self.max_batch:
-            r = self.queue[0]
-            if self.in_use + used + r.bytes > self.budget:
-                break
-            batch.append(self.queue.popleft())
-            used += r.bytes
-        if batch:
-            self.in_use += used
-            self.inflight += 1
+        free = self.budget - self.in_use
+        cand = [self.queue[i] for i in range(min(len(self.queue), self.max_batch))]
+        n, used = len(cand), self.cost(cand)
+        if used > free:         # the longest fitting prefix, by bisection
+            lo, hi, used = 0, n, 0
+            while hi - lo > 1:
+                mid = (lo + hi) // 2
+                c = self.cost(cand[:mid])
+                if c <= free:
+                    lo, used = mid, c
+                else:
+                    hi = mid
+            n = lo
+        if n == 0:
+            return []
+        batch = [self.queue.popleft() for _ in range(n)]
+        self.in_use += used
+        self.inflight += 1
+        self.held[id(batch)] = used
         return batch
 
     def finish(self, batch: Sequence[Request]):
-        self.in_use -= sum(r.bytes for r in batch)
+        self.in_use -= self.held.pop(id(batch))
         self.inflight -= 1
         assert self.in_use >= 0 and self.inflight >= 0
 
@@ -126,12 +145,33 @@ class Server:
     """Continuous-batching front end over a kc.Context."""
 
     def __init__(self, ctx: kc.Context, budget_bytes: int = 64 << 30, slots: int = 4):
+        """Admission charges each batch the device bytes the library reports
+        for it (kc_batch_footprint) plus its memories and their uploads;
+        ``ctx`` should carry the same budget, which the library then
+        enforces over all of its buffers."""
         import torch
         self.ctx = ctx
-        self.adm = Admission(budget_bytes, slots)
+        self._added: Dict[int, int] = {}    # id(job) -> bytes it adds to a batch's footprint
+        self.adm = Admission(budget_bytes, slots, cost=self._cost)
         self.streams = [torch.cuda.Stream() for _ in range(slots)]   # default priority
         self.free_streams = list(range(slots))
         self.batch = kc.Batch(ctx)
+
+    def _cost(self, reqs: Sequence[Request]) -> int:
+        """Library footprint of a batch, bounded by the part of an empty
+        batch plus each job's own addition (computed once per job) and the
+        jobs' memories."""
+        if not reqs:
+            return 0
+        fixed = kc.jobs_footprint(self.ctx, [])
+        total = fixed
+        for r in reqs:
+            add = self._added.get(id(r.job))
+            if add is None:
+                add = kc.jobs_footprint(self.ctx, [r.job]) - fixed + 4 * len(r.job.memory)
+                self._added[id(r.job)] = add
+            total += add
+        return total
 
     def run(self, stream: Sequence[Tuple[float, object]], keep_reports: bool = False,
             keep_memory: bool = False, pristine: Optional[Dict[int, object]] = None,
@@ -143,6 +183,7 @@ class Server:
         every k-th request's (job, report, final memory) is returned under
         "sample"."""
         import torch
+        self._added.clear()
         reqs = [Request(i, t, j, estimate_bytes(j)) for i, (t, j) in enumerate(stream)]
         pending = collections.deque(reqs)
         inflight: List[Tuple[int, int, List[Request], list]] = []   # (ticket, stream idx, reqs, mems)

@@ -1,9 +1,13 @@
 """Autotuner for the checker's launch parameters.
 
 The tunable options change how the work is laid out on the GPU, never what is
-computed: the sort tile (keys per radix-sort tile), the interpreter's LDS
-record staging (bytes per block and granule per wave) and whether shared
-accesses are checked per barrier epoch inside the interpreter.  The tuner
+computed: the sort tile (keys per radix-sort tile) and radix digit width, the
+interpreter's LDS record staging (bytes per block and granule per wave),
+whether shared accesses are checked per barrier epoch inside the
+interpreter, and the work split -- how many streams the launches of one
+batch step (one per block-size class) are spread over, and the occupancy
+target of the program-specialised kernels (simulated blocks resident per
+SIMD).  The tuner
 runs a sample workload as one batch under each candidate setting (coordinate
 descent from the current setting, one option at a time), rejects any setting
 whose reports or final memories differ from those of the starting setting,
@@ -16,6 +20,7 @@ timed region); the score of a setting is the median over ``reps`` runs.
 """
 from __future__ import annotations
 
+import argparse
 import json
 import time
 from typing import Dict, List, Optional, Sequence
@@ -25,10 +30,13 @@ import numpy as np
 from . import kc
 
 SPACE: Dict[str, Sequence[int]] = {
-    "sort_tile": (1024, 2048, 4096, 8192),
+    "sort_tile": (1024, 2048, 4096, 8192),      # keys per radix-sort tile
+    "sort_bits": (8, 7, 6, 5),                  # radix digit width (bits per pass)
     "stage_bytes": (8192, 16384, 32768, 65536),
     "stage": (128, 256, 512),
     "local": (0, 1),
+    "side_streams": (4, 2, 1),                  # work split: streams a batch step's launches spread over
+    "jit_waves": (0, 2, 4, 8),                  # work split: simulated blocks resident per SIMD
 }
 
 
@@ -108,3 +116,29 @@ def tune(ctx: kc.Context, jobs, path: Optional[str] = None, reps: int = 5, sweep
         with open(path, "w") as f:
             json.dump(best, f, indent=1, sort_keys=True)
     return {"setting": best, "seconds": best_t, "start_seconds": base_t, "tried": tried}
+
+
+def main(argv=None):
+    """Tune on a seeded sample of the mixed-family workload (workload 3) and
+    write the cache: python -m paper_1211_6193_amd.tune OUT.json"""
+    from . import workloads as W
+    ap = argparse.ArgumentParser(description=main.__doc__)
+    ap.add_argument("out")
+    ap.add_argument("--instances", type=int, default=2000)
+    ap.add_argument("--jit", type=int, default=1)
+    ap.add_argument("--reps", type=int, default=5)
+    args = ap.parse_args(argv)
+    import torch
+    torch.cuda.init()           # torch first: its device memory holds the sample's memories
+    ctx = kc.Context(0)
+    ctx.set_option("jit", args.jit)
+    jobs = W.config3_jobs(n=args.instances)
+    res = tune(ctx, jobs, path=args.out, reps=args.reps)
+    print(json.dumps({"setting": res["setting"], "ms": round(res["seconds"] * 1e3, 3),
+                      "start_ms": round(res["start_seconds"] * 1e3, 3), "settings_tried": len(res["tried"]),
+                      "all_identical": all(t[2] for t in res["tried"])}), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

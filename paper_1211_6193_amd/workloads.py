@@ -287,6 +287,8 @@ def host_program_job(n_blocks: int = 4096, bug: Optional[str] = None, seed: int 
     right after the launches, while its copy in may still be reading it)."""
     if bug not in HOST_PROGRAM_BUGS:
         raise ValueError(f"unknown bug {bug!r}")
+    if n_blocks < 128 or n_blocks % 128:
+        raise ValueError("n_blocks must be a multiple of 128 (the final launch reduces 2 * n_blocks / 256 blocks)")
     base = streams_reduce_job(n_blocks, seed=seed)
     n = n_blocks * 256
     m = 2 * n_blocks // 256

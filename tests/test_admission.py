@@ -50,3 +50,20 @@ def test_estimate_covers_memory_and_log():
     job = W.family_job("STENCIL", 4, 128, np.random.default_rng(0))
     est = estimate_bytes(job)
     assert est >= 2 * 4 * len(job.memory) + 8 * 6 * 4 * 128
+
+
+def test_longest_fitting_prefix_with_a_batch_cost():
+    # a batch costs a fixed part plus its requests' bytes (the shape of the
+    # library's footprint): the longest prefix that fits is taken, in order
+    cost = lambda rs: (50 + sum(r.bytes for r in rs)) if rs else 0
+    adm = Admission(1000, 2, cost=cost)
+    for i, b in enumerate([600, 300, 200, 10]):
+        adm.arrive(Request(i, 0.0, None, b))
+    first = adm.take()
+    assert [r.rid for r in first] == [0, 1] and adm.in_use == 950
+    assert adm.take() == []                      # 200 more does not fit next to 950
+    adm.finish(first)
+    second = adm.take()
+    assert [r.rid for r in second] == [2, 3] and adm.in_use == 260
+    with pytest.raises(ValueError):
+        adm.arrive(Request(9, 0.0, None, 960))   # 1010 with the fixed part
