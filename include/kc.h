@@ -139,13 +139,20 @@ void kc_ctx_destroy(kc_ctx *ctx);
  * then w = the smallest thread with a write that conflicts, o = the smallest
  * thread whose access conflicts with one of w's writes; blocks with a race in
  * the plain model are replayed to find the steps; 0 = off, default),
+ * "queue_replay" (1 = default: the replay of the blocks the free run found
+ * racy is queued right behind it, before the host reads any result, and
+ * stands when the log needs no sorted check; 0 = the host reads the free
+ * run's results first and queues the replay after; results are identical),
  * "reset" (1 = clear the statistics).
  * Errors: KC_E_INVAL for an unknown key or out-of-range value. */
 kc_status kc_ctx_set_option(kc_ctx *ctx, const char *key, int64_t value);
 
 /* Accumulated statistics since the last reset ("reset" clears them):
  * "interp_ms", "sort_ms", "check_ms", "replay_ms", "launches", "records",
- * "replays", "fallbacks", "retries", "interp_launches", "sort_keys",
+ * "replays", "fallbacks", "retries", "spec_replays" (stages whose replay,
+ * queued behind the free run before any result was read, stood),
+ * "spec_retries" (stages run again without it because it did not apply),
+ * "interp_launches", "sort_keys",
  * "sorted_checks", "hash_check_ms" (free-run logs that needed the sort, and
  * the time of the location-table checks),
  * "replay_sorted_checks" (replays whose records needed the sorted check: an

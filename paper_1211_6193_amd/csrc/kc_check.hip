@@ -276,11 +276,14 @@ __global__ void __launch_bounds__(WG) k_check_long(CheckArgs A) {
     }
 }
 
-// Put back the launch-start value of every global word a flagged block wrote.
+// Put back the launch-start value of every global word a flagged block wrote
+// (records [0, n), or [0, min(n, *n_dev)) when the count is on the device).
 __global__ void __launch_bounds__(WG) k_restore(const uint64_t *__restrict__ keys, uint64_t n, KeyPlan k,
                                                 const DevUnit *__restrict__ units,
-                                                const uint32_t *__restrict__ blk_flags) {
+                                                const uint32_t *__restrict__ blk_flags,
+                                                const unsigned long long *__restrict__ n_dev) {
     const uint64_t i = (uint64_t)blockIdx.x * WG + threadIdx.x;
+    if (n_dev && i >= *n_dev) return;
     if (i >= n) return;
     const uint64_t r = keys[i];
     if (!(r & 1ull) || rec_field(r, k.s_sp, 1) != 1u) return;
@@ -288,6 +291,42 @@ __global__ void __launch_bounds__(WG) k_restore(const uint64_t *__restrict__ key
     if (!blk_flags[u.block_base + rec_field(r, k.s_blk, k.bb)]) return;
     const uint32_t a = rec_field(r, k.s_addr, k.ab);
     u.mem[a] = u.snap[a];
+}
+
+// The flagged blocks in ascending global block index as (unit, block): each
+// thread counts the flags of a contiguous chunk, a block-wide scan of the
+// counts gives each chunk its place, and the chunk writes its blocks there.
+// The unit of a block is found by binary search in the units' first blocks.
+__global__ void __launch_bounds__(1024) k_flagged_comps(const uint32_t *__restrict__ blk_flags, uint32_t n_blocks,
+                                                        const DevUnit *__restrict__ units, uint32_t n_units,
+                                                        uint2 *__restrict__ comps, uint32_t *__restrict__ n_comps) {
+    __shared__ uint32_t part[1024];
+    const uint32_t per = (n_blocks + blockDim.x - 1) / blockDim.x;
+    const uint32_t b0 = min(n_blocks, threadIdx.x * per), b1 = min(n_blocks, b0 + per);
+    uint32_t mine = 0;
+    for (uint32_t b = b0; b < b1; b++) mine += blk_flags[b] != 0u;
+    part[threadIdx.x] = mine;
+    __syncthreads();
+    for (uint32_t d = 1; d < blockDim.x; d <<= 1) {      // inclusive scan of the chunk counts
+        const uint32_t v = threadIdx.x >= d ? part[threadIdx.x - d] : 0u;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    uint32_t at = part[threadIdx.x] - mine;
+    if (mine) {
+        uint32_t lo = 0, hi = n_units;      // the last unit whose first block is <= b0
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) / 2;
+            if (units[mid].block_base <= b0) lo = mid; else hi = mid;
+        }
+        uint32_t u = lo;
+        for (uint32_t b = b0; b < b1; b++) {
+            while (u + 1 < n_units && units[u + 1].block_base <= b) u++;
+            if (blk_flags[b]) comps[at++] = make_uint2(u, b - units[u].block_base);
+        }
+    }
+    if (threadIdx.x == blockDim.x - 1) *n_comps = part[threadIdx.x];
 }
 
 // Exactness condition of a replay: no global location may be touched both by
@@ -795,9 +834,15 @@ hipError_t launch_check(const CheckArgs &a, hipStream_t s) {
 }
 
 hipError_t launch_restore(const uint64_t *keys, uint64_t n, KeyPlan kp, const DevUnit *units,
-                          const uint32_t *blk_flags, hipStream_t s) {
+                          const uint32_t *blk_flags, hipStream_t s, const unsigned long long *n_dev) {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_restore, dim3(blocks_for(n)), dim3(WG), 0, s, keys, n, kp, units, blk_flags);
+    hipLaunchKernelGGL(k_restore, dim3(blocks_for(n)), dim3(WG), 0, s, keys, n, kp, units, blk_flags, n_dev);
+    return hipGetLastError();
+}
+
+hipError_t launch_flagged_comps(const uint32_t *blk_flags, uint32_t n_blocks, const DevUnit *units, uint32_t n_units,
+                                uint2 *comps, uint32_t *n_comps, hipStream_t s) {
+    hipLaunchKernelGGL(k_flagged_comps, dim3(1), dim3(1024), 0, s, blk_flags, n_blocks, units, n_units, comps, n_comps);
     return hipGetLastError();
 }
 

@@ -1705,13 +1705,18 @@ __device__ __forceinline__ void lockstep_body(const InterpArgs &A, Run run) {
         T.gkey[i] = EMPTY_KEY;
         T.gown[i] = 0;
     }
-    const uint32_t c0 = uniu(A.comp_off[blockIdx.x]), c1 = uniu(A.comp_off[blockIdx.x + 1]);
+    // a component's blocks, or (count on the device) single-block components
+    // strided over the workgroups
+    const bool strided = A.n_comps_dev != nullptr;
+    const uint32_t c0 = strided ? blockIdx.x : uniu(A.comp_off[blockIdx.x]);
+    const uint32_t c1 = strided ? uniu(*A.n_comps_dev) : uniu(A.comp_off[blockIdx.x + 1]);
+    const uint32_t dc = strided ? gridDim.x : 1u;
     BlockCtx B;
     B.nwaves = nwaves;
     B.wave = wave;
     Lane t;
     LogState L{0, 0, 0, false};
-    for (uint32_t c = c0; c < c1; c++) {
+    for (uint32_t c = c0; c < c1; c += dc) {
         uint2 it = A.comp_blocks[c];
         setup_block(A, B, S, t, uniu(it.x), uniu(it.y), true);
         const uint32_t epoch = run(A, B, S, T, t, L);

@@ -129,6 +129,9 @@ struct InterpArgs {
     const uint2 *items;         // (unit, block) per workgroup; null: unit 0, block = blockIdx.x
     const uint32_t *comp_off;   // lockstep replay: blocks of component c are comp_blocks[comp_off[c] .. comp_off[c+1])
     const uint2 *comp_blocks;   // (unit, block)
+    // When set, the components are single blocks comp_blocks[0 .. *n_comps_dev)
+    // (a count written on the device) and workgroups stride over them.
+    const uint32_t *n_comps_dev;
     KeyPlan kp;
     uint64_t *log;
     unsigned long long log_cap;
@@ -210,7 +213,12 @@ struct CheckArgs {
 size_t check_long_cap(uint64_t n);
 hipError_t launch_check(const CheckArgs &a, hipStream_t s);
 hipError_t launch_restore(const uint64_t *keys, uint64_t n, KeyPlan kp, const DevUnit *units,
-                          const uint32_t *blk_flags, hipStream_t s);
+                          const uint32_t *blk_flags, hipStream_t s, const unsigned long long *n_dev = nullptr);
+// The blocks flagged in blk_flags (n_blocks, global block indices of the
+// units), in ascending order, as (unit, block) pairs into comps, and their
+// number into *n_comps: one workgroup.
+hipError_t launch_flagged_comps(const uint32_t *blk_flags, uint32_t n_blocks, const DevUnit *units, uint32_t n_units,
+                                uint2 *comps, uint32_t *n_comps, hipStream_t s);
 // Exactness of a replay; sets FLAG_MISMATCH in ctr->flags.  ctr->long_count
 // must be zero; `list` holds n_rs entries.
 hipError_t launch_coverage(const uint64_t *rs, uint64_t n_rs, const uint64_t *log, uint64_t n_log, KeyPlan kp,

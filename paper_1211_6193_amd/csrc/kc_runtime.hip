@@ -165,6 +165,7 @@ struct Workspace {
     DBuf snap, log, alt, rlog, ralt, fs, hist, part;
     DBuf faults, rfaults, races, lraces, rlraces, edges, blk_recs, rblk_recs, blk_flags, rflags, ctr, rctr, wlog;
     DBuf longseg, covlist, rtable, ftable, downer, dflags, blk_instr, blk_grecs, blk_log, blk_held, blk_off;
+    DBuf sctr, stctr, sncomp;   // the replay queued behind the free run: counters, table counters, components
     DevCounters *h_ctr = nullptr;   // pinned
     void *h_pin = nullptr;          // pinned staging of gathered device-to-host copies
     void *d_pin = nullptr;          // its device mapping
@@ -183,6 +184,37 @@ struct Workspace {
         HIPCHK(hipHostGetDevicePointer(&d_pin, h_pin, 0));
         h_pin_bytes = nb;
     }
+    // Pinned staging of host-to-device uploads: a copy from pageable memory
+    // returns only once the stream has reached it, which would leave the GPU
+    // idle while the host queues the next work; from pinned memory it
+    // returns at once.  Regions are handed out in order and reused after the
+    // stream has been synchronised (uploads_done).
+    void *h_up = nullptr;
+    size_t h_up_bytes = 0, h_up_used = 0;
+    void upload(void *dst, const void *src, size_t bytes, hipStream_t s) {
+        if (!bytes) return;
+        if (h_up_used + bytes > h_up_bytes) {
+            if (t_arena) {      // a call that allocates nothing: no new pinned memory
+                HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s));
+                return;
+            }
+            HIPCHK(hipStreamSynchronize(s));        // earlier copies from the buffer are done
+            h_up_used = 0;
+            if (bytes > h_up_bytes) {
+                const size_t nb = std::max<size_t>(std::max<size_t>(2 * bytes, 1 << 20), 2 * h_up_bytes);
+                if (h_up) HIPCHK(hipHostFree(h_up));
+                h_up = nullptr;
+                h_up_bytes = 0;
+                HIPCHK(hipHostMalloc(&h_up, nb, hipHostMallocDefault));
+                h_up_bytes = nb;
+            }
+        }
+        char *p = (char *)h_up + h_up_used;
+        std::memcpy(p, src, bytes);
+        HIPCHK(hipMemcpyAsync(dst, p, bytes, hipMemcpyHostToDevice, s));
+        h_up_used = std::min(h_up_bytes, (h_up_used + bytes + 255) & ~size_t(255));
+    }
+    void uploads_done() { h_up_used = 0; }
     hipEvent_t ev[16] = {};
     // Side streams (default priority) on which the launches of one pipeline
     // step run side by side, joined to the stage's stream by events.
@@ -204,7 +236,8 @@ struct Workspace {
         DBuf *all[] = {&units, &items, &comp_off, &comp_blocks, &mask, &snap, &log, &alt, &rlog,
                        &ralt, &fs, &hist, &part, &faults, &rfaults, &races, &edges, &blk_recs,
                        &rblk_recs, &blk_flags, &rflags, &ctr, &rctr, &wlog, &lraces, &rlraces, &longseg, &covlist,
-                       &rtable, &ftable, &downer, &dflags, &blk_instr, &blk_grecs, &blk_log, &blk_held, &blk_off};
+                       &rtable, &ftable, &downer, &dflags, &blk_instr, &blk_grecs, &blk_log, &blk_held, &blk_off,
+                       &sctr, &stctr, &sncomp};
         for (auto *b : all) b->acct = a;
     }
     // Forget every carved buffer (the arena restarts at each call).
@@ -212,7 +245,8 @@ struct Workspace {
         DBuf *all[] = {&units, &items, &comp_off, &comp_blocks, &mask, &snap, &log, &alt, &rlog,
                        &ralt, &fs, &hist, &part, &faults, &rfaults, &races, &edges, &blk_recs,
                        &rblk_recs, &blk_flags, &rflags, &ctr, &rctr, &wlog, &lraces, &rlraces, &longseg, &covlist,
-                       &rtable, &ftable, &downer, &dflags, &blk_instr, &blk_grecs, &blk_log, &blk_held, &blk_off};
+                       &rtable, &ftable, &downer, &dflags, &blk_instr, &blk_grecs, &blk_log, &blk_held, &blk_off,
+                       &sctr, &stctr, &sncomp};
         for (auto *b : all)
             if (b->carved) b->release();
     }
@@ -220,7 +254,8 @@ struct Workspace {
         const DBuf *all[] = {&units, &items, &comp_off, &comp_blocks, &mask, &snap, &log, &alt, &rlog,
                              &ralt, &fs, &hist, &part, &faults, &rfaults, &races, &edges, &blk_recs,
                              &rblk_recs, &blk_flags, &rflags, &ctr, &rctr, &wlog, &lraces, &rlraces, &longseg, &covlist,
-                             &rtable, &ftable, &downer, &dflags, &blk_instr, &blk_grecs, &blk_log, &blk_held, &blk_off};
+                             &rtable, &ftable, &downer, &dflags, &blk_instr, &blk_grecs, &blk_log, &blk_held, &blk_off,
+                       &sctr, &stctr, &sncomp};
         size_t s = 0;
         for (auto *b : all) s += b->bytes;
         return s;
@@ -229,10 +264,12 @@ struct Workspace {
         DBuf *all[] = {&units, &items, &comp_off, &comp_blocks, &mask, &snap, &log, &alt, &rlog,
                        &ralt, &fs, &hist, &part, &faults, &rfaults, &races, &edges, &blk_recs,
                        &rblk_recs, &blk_flags, &rflags, &ctr, &rctr, &wlog, &lraces, &rlraces, &longseg, &covlist,
-                       &rtable, &ftable, &downer, &dflags, &blk_instr, &blk_grecs, &blk_log, &blk_held, &blk_off};
+                       &rtable, &ftable, &downer, &dflags, &blk_instr, &blk_grecs, &blk_log, &blk_held, &blk_off,
+                       &sctr, &stctr, &sncomp};
         for (auto *b : all) b->release();
         if (h_ctr) (void)hipHostFree(h_ctr);
         if (h_pin) (void)hipHostFree(h_pin);
+        if (h_up) (void)hipHostFree(h_up);
         for (auto &e : ev)
             if (e) (void)hipEventDestroy(e);
         for (auto &q : side)
@@ -276,6 +313,7 @@ struct Options {
     int sites = 0;                  // source sites of races (one more replay of the racy blocks)
     int uninit = 0;                 // UNINIT findings for loads of shared words not yet stored to
     int warp = 0;                   // warp-aware model: accesses of one warp conflict only at the same step
+    int queue_replay = 1;           // replay of the free run's racy blocks queued behind it
     int arena = 0;                  // set by the library: buffers come from the static scratch area
 };
 
@@ -340,6 +378,20 @@ struct kc_ctx {
     void note_log_records(uint64_t n) {
         std::lock_guard<std::mutex> g(mu);
         opt.log_records = std::max(opt.log_records, n);
+    }
+    // Capacities of the log and race list of the replay queued behind the
+    // free run, grown to what earlier stages needed.
+    uint64_t spec_log_hint = 1u << 16;
+    uint32_t spec_race_hint = 4096;
+    void spec_caps(uint64_t &log, uint32_t &races) {
+        std::lock_guard<std::mutex> g(mu);
+        log = spec_log_hint;
+        races = spec_race_hint;
+    }
+    void note_spec(uint64_t log, uint32_t races) {
+        std::lock_guard<std::mutex> g(mu);
+        spec_log_hint = std::max<uint64_t>(spec_log_hint, log + log / 4 + 1024);
+        spec_race_hint = std::max<uint32_t>(spec_race_hint, races + races / 4 + 1024);
     }
     // Capacities of the finding and local-race lists, grown to what earlier
     // stages needed so that a repeated workload does not interpret twice.
@@ -631,17 +683,20 @@ struct Stage {
             HIPCHK(launch_gather(g, s));
         }
         HIPCHK(hipStreamSynchronize(s));
+        ws.uploads_done();
     }
     template <class T> const T *fetched(const Fetch &f, size_t i) const {
         return (const T *)((const char *)ws.h_pin + f.items[i].off);
     }
     // Entries speculatively fetched with their counts; more need a second trip.
     static constexpr uint32_t kSpec = 512;
+    // the queued replay's race list holds every exact tuple: more ride along
+    static constexpr uint32_t kSpecRaces = 4096;
     template <class T> void take_list(const Fetch &f, size_t item, uint32_t count, uint32_t cap, const void *dev,
-                                      std::vector<T> &out) {
+                                      std::vector<T> &out, uint32_t fetched_n = kSpec) {
         const uint32_t n = std::min(count, cap);
         out.resize(n);
-        const uint32_t first = std::min(n, kSpec);
+        const uint32_t first = std::min(n, fetched_n);
         if (first) std::memcpy(out.data(), fetched<T>(f, item), (size_t)first * sizeof(T));
         if (n > first) {
             HIPCHK(hipMemcpyAsync(out.data() + first, (const T *)dev + first, (size_t)(n - first) * sizeof(T),
@@ -681,6 +736,78 @@ struct Stage {
         uint32_t first, count, unit, wg, shmax;
     };
     std::vector<CompGroup> comp_groups;
+
+    // The replay of the free run's racy blocks queued behind it, before the
+    // host has seen any result: the blocks the free run flagged are listed
+    // on the device (each its own component), their free-run writes put
+    // back, and they are replayed and checked for exactness; the results come
+    // back with the free run's.  They stand when the log needs no sorted
+    // check and nothing overflowed (every racy block then was flagged by the
+    // free run and is its own component); otherwise the stage runs again
+    // from the launch start without it.  Used when every unit runs one
+    // program (one replay kernel) and the replay's tables apply.
+    bool spec = false, spec_off = false, spec_ok = false;
+    uint32_t spec_ncomp = 0;                    // blocks the queued replay ran
+    DevCounters spec_counters{};
+    const uint32_t *spec_ncomps = nullptr;      // set while the queued replay is launched
+    uint64_t spec_rcap = 0;
+    uint32_t spec_fcap = 0, spec_rlcap = 0;
+    bool spec_allowed() const {
+        if (!opt.queue_replay || !opt.check || !opt.local || opt.warp || opt.sites || opt.arena || site_table)
+            return false;
+        if (!total_blocks || table_obits() == 0) return false;
+        for (auto &u : in)
+            if (u.desc->prog != in[0].desc->prog) return false;
+        return true;
+    }
+    void queue_spec_replay(uint64_t log_cap, uint32_t fault_cap, Timer &tm) {
+        tm.mark(5);
+        ctx->spec_caps(spec_rcap, spec_rlcap);
+        spec_fcap = fault_cap;
+        ws.comp_blocks.reserve((size_t)total_blocks * sizeof(uint2));
+        ws.sncomp.reserve(4);
+        ws.sctr.reserve(sizeof(DevCounters));
+        ws.stctr.reserve(sizeof(DevCounters));
+        HIPCHK(launch_restore(ws.log.as<uint64_t>(), log_cap, kp, ws.units.as<DevUnit>(),
+                              ws.blk_flags.as<uint32_t>(), s, &ws.ctr.as<DevCounters>()->log_count));
+        HIPCHK(launch_flagged_comps(ws.blk_flags.as<uint32_t>(), total_blocks, ws.units.as<DevUnit>(),
+                                    (uint32_t)hu.size(), ws.comp_blocks.as<uint2>(), ws.sncomp.as<uint32_t>(), s));
+        ws.rblk_recs.reserve((size_t)total_blocks * 4);
+        ws.rflags.reserve((size_t)total_blocks * 4);
+        ws.rlog.reserve(spec_rcap * 8);
+        ws.rfaults.reserve((size_t)spec_fcap * sizeof(DevFault));
+        ws.rlraces.reserve((size_t)spec_rlcap * sizeof(DevRace));
+        {
+            ZeroArgs z{{ws.sctr.as<uint32_t>(), ws.rblk_recs.as<uint32_t>()},
+                       {sizeof(DevCounters) / 4, (size_t)total_blocks}, 2};
+            HIPCHK(launch_zero_many(z, s));
+        }
+        uint32_t wg = 64, shmax = 0;
+        for (auto &u : hu) {
+            wg = std::max<uint32_t>(wg, (u.nt + 63) / 64 * 64);
+            shmax = std::max(shmax, u.sh_words);
+        }
+        // the racy blocks are few in the common case: two workgroups per CU
+        // stride over them, and the idle ones exit at once
+        const uint32_t grid = std::min<uint32_t>(total_blocks, 512);
+        comp_groups.assign(1, CompGroup{0, grid, 0, wg, shmax});
+        spec_ncomps = ws.sncomp.as<uint32_t>();
+        wlog_cap = 0;
+        interp(true, ws.rlog, spec_rcap, ws.sctr, ws.rfaults, spec_fcap, ws.rblk_recs, grid, ws.rlraces, spec_rlcap,
+               ws.rflags);
+        spec_ncomps = nullptr;
+        uint32_t bits = 10;
+        while ((1ull << bits) < 2 * spec_rcap) bits++;
+        ws.rtable.reserve((size_t)8 << bits);
+        ReplayTableArgs ta{ws.rlog.as<uint64_t>(), spec_rcap, ws.log.as<uint64_t>(), log_cap, kp,
+                           ws.units.as<DevUnit>(), ws.blk_flags.as<uint32_t>(), ws.rtable.p, bits,
+                           ws.stctr.as<DevCounters>(), qt_direct ? nullptr : ws.ftable.p, qt_direct ? 0u : qt_bits,
+                           table_obits(), ws.snap.as<int32_t>(), qt_direct ? ws.downer.as<uint32_t>() : nullptr,
+                           ws.dflags.as<uint8_t>(), nullptr};
+        ta.n_dev = &ws.sctr.as<DevCounters>()->log_count;
+        HIPCHK(launch_replay_table(ta, s));
+        tm.mark(7);
+    }
 
     DevCounters read_ctr(DBuf &c) {
         HIPCHK(hipMemcpyAsync(ws.h_ctr, c.p, sizeof(DevCounters), hipMemcpyDeviceToHost, s));
@@ -756,7 +883,7 @@ struct Stage {
 
     void upload_units() {
         ws.units.reserve(hu.size() * sizeof(DevUnit));
-        HIPCHK(hipMemcpyAsync(ws.units.p, hu.data(), hu.size() * sizeof(DevUnit), hipMemcpyHostToDevice, s));
+        ws.upload(ws.units.p, hu.data(), hu.size() * sizeof(DevUnit), s);
     }
 
     void reset_counters(DBuf &c) {
@@ -807,6 +934,7 @@ struct Stage {
             }
             a.comp_off = ws.comp_off.as<uint32_t>();
             a.comp_blocks = ws.comp_blocks.as<uint2>();
+            a.n_comps_dev = spec_ncomps;
             a.sh_words_max = shmax;
             a.gst_bits = gst ? gst_bits_for(wg) : 0u;
             if (site_table) {       // the source-site replay: the interpreter with the site probe
@@ -916,7 +1044,7 @@ struct Stage {
             ranges.push_back({b0, items.size()});
         }
         ws.items.reserve(items.size() * sizeof(uint2));
-        HIPCHK(hipMemcpyAsync(ws.items.p, items.data(), items.size() * sizeof(uint2), hipMemcpyHostToDevice, s));
+        ws.upload(ws.items.p, items.data(), items.size() * sizeof(uint2), s);
         // the classes side by side: each holds few blocks of long latency
         size_t ci = 0;
         const bool par = classes.size() > 1;
@@ -1029,7 +1157,7 @@ struct Stage {
             ws.blk_off.reserve((size_t)total_blocks * 8);
         }
         DevCounters c{};
-        size_t i_instr = 0, i_grecs = 0;
+        size_t i_instr = 0, i_grecs = 0, i_sctr = 0, i_sncomp = 0, i_stctr = 0, i_srf = 0, i_srecs = 0, i_srl = 0;
         Fetch fetch;
         bool table_queued = false;
         for (;;) {
@@ -1054,6 +1182,8 @@ struct Stage {
                                            &ws.ctr.as<DevCounters>()->flags, s));
             table_queued = check && queue_log_check(log_cap);
             tm.mark(12);
+            spec = table_queued && !spec_off && spec_allowed();
+            if (spec) queue_spec_replay(log_cap, fault_cap, tm);
             fetch = Fetch{};
             const size_t i_ctr = fetch.add(ws.ctr.p, sizeof(DevCounters));
             fetch.add(ws.blk_recs.p, (size_t)total_blocks * 4);
@@ -1062,6 +1192,14 @@ struct Stage {
             if (table_queued) fetch.add(ws.rctr.p, sizeof(DevCounters));      // item 4
             i_instr = fetch.add(ws.blk_instr.p, (size_t)total_blocks * 4);
             i_grecs = fetch.add(ws.blk_grecs.p, (size_t)total_blocks * 4);
+            if (spec) {
+                i_sctr = fetch.add(ws.sctr.p, sizeof(DevCounters));
+                i_sncomp = fetch.add(ws.sncomp.p, 4);
+                i_stctr = fetch.add(ws.stctr.p, sizeof(DevCounters));
+                i_srf = fetch.add(ws.rfaults.p, (size_t)std::min(spec_fcap, kSpec) * sizeof(DevFault));
+                i_srecs = fetch.add(ws.rblk_recs.p, (size_t)total_blocks * 4);
+                i_srl = fetch.add(ws.rlraces.p, (size_t)std::min(spec_rlcap, kSpecRaces) * sizeof(DevRace));
+            }
             run_fetch(fetch);
             c = *fetched<DevCounters>(fetch, i_ctr);
             ctx->stat_add("interp_ms", tm.ms(0, 1));
@@ -1083,6 +1221,25 @@ struct Stage {
             if (c.flags & FLAG_RACE_OVERFLOW) {
                 lrace_cap = c.race_count + c.race_count / 8 + 1024;
                 again = true;
+            }
+            spec_ok = false;
+            if (spec) {
+                const DevCounters sc = *fetched<DevCounters>(fetch, i_sctr);
+                const uint32_t ncomp = *fetched<uint32_t>(fetch, i_sncomp);
+                ctx->note_spec(sc.log_count, sc.race_count);
+                const bool need_sort = (fetched<DevCounters>(fetch, 4)->flags & FLAG_NEED_SORT) != 0;
+                const uint32_t sflags = sc.flags & (FLAG_LOG_OVERFLOW | FLAG_FAULT_OVERFLOW | FLAG_RACE_OVERFLOW |
+                                                    FLAG_EPOCH_OVERFLOW | FLAG_WLOG_OVERFLOW);
+                const uint32_t tflags = fetched<DevCounters>(fetch, i_stctr)->flags & (FLAG_NEED_SORT | FLAG_MISMATCH);
+                spec_ok = !again && !need_sort && !sflags && !tflags;
+                spec_ncomp = ncomp;
+                spec_counters = sc;
+                if (!spec_ok && ncomp > 0 && !again) {
+                    // the queued replay changed the memory: run the stage again without it
+                    spec_off = true;
+                    again = true;
+                    ctx->stat_add("spec_retries", 1);
+                }
             }
             if (!again) break;
             if (!check) throw KcError{KC_E_OVERFLOW, "findings overflow with check disabled"};
@@ -1167,7 +1324,17 @@ struct Stage {
         fin_log = sorted;
         fin_n = check ? nrec : 0;
         racy_words = c.racy_words;
-        if (!races.empty()) replay(races, edges, sorted, nrec, ufaults, uraces, urecs, tm);
+        if (spec_ok && spec_ncomp > 0) {
+            ReplayOut ro;
+            ro.recs.resize(total_blocks);
+            std::memcpy(ro.recs.data(), fetched<uint32_t>(fetch, i_srecs), (size_t)total_blocks * 4);
+            take_list(fetch, i_srf, spec_counters.fault_count, spec_fcap, ws.rfaults.p, ro.faults);
+            take_list(fetch, i_srl, spec_counters.race_count, spec_rlcap, ws.rlraces.p, ro.lraces, kSpecRaces);
+            spec_apply(races, ro, ufaults, uraces, urecs, tm);
+        } else if (!races.empty()) {
+            if (spec_ok) throw KcError{KC_E_INTERNAL, "racy blocks the free run did not flag"};
+            replay(races, edges, sorted, nrec, ufaults, uraces, urecs, tm);
+        }
 
         for (uint32_t i = 0; i < n; i++) {
             UnitOut &o = out[i];
@@ -1270,8 +1437,8 @@ struct Stage {
         }
         ws.comp_off.reserve(off.size() * 4);
         ws.comp_blocks.reserve(blocks.size() * sizeof(uint2));
-        HIPCHK(hipMemcpyAsync(ws.comp_off.p, off.data(), off.size() * 4, hipMemcpyHostToDevice, s));
-        HIPCHK(hipMemcpyAsync(ws.comp_blocks.p, blocks.data(), blocks.size() * sizeof(uint2), hipMemcpyHostToDevice, s));
+        ws.upload(ws.comp_off.p, off.data(), off.size() * 4, s);
+        ws.upload(ws.comp_blocks.p, blocks.data(), blocks.size() * sizeof(uint2), s);
     }
 
     // Warp-aware model (the finer scheduler the paper's Section 4 proposes:
@@ -1379,6 +1546,67 @@ struct Stage {
             }
         }
         return c;
+    }
+
+    // The results of an exact replay of `comps` replace the free run's for
+    // their blocks: records, findings and races (`rr`: races found by a
+    // sorted check of the replay's records; the replay's own intra-block
+    // races are added here).
+    void apply_replay(const std::vector<std::vector<uint2>> &comps, const ReplayOut &ro, std::vector<DevRace> &rr,
+                      std::vector<std::vector<kc_fault>> &ufaults, std::vector<std::vector<kc_race>> &uraces,
+                      std::vector<uint64_t> &urecs) {
+        const std::vector<DevFault> &rf = ro.faults;
+        const std::vector<uint32_t> &rrecs = ro.recs;
+        rr.insert(rr.end(), ro.lraces.begin(), ro.lraces.end());
+        if (opt.warp) {     // intra-block tuples of the warp-aware model replace the plain ones
+            rr.erase(std::remove_if(rr.begin(), rr.end(), [](const DevRace &r) { return r.scope == 0; }), rr.end());
+            rr.insert(rr.end(), ro.warp.begin(), ro.warp.end());
+        }
+        std::vector<char> in_s(total_blocks, 0);
+        for (auto &c : comps)
+            for (auto &ub : c) {
+                const uint32_t gb = hu[ub.x].block_base + ub.y;
+                in_s[gb] = 1;
+                urecs[ub.x] += (uint64_t)rrecs[gb];
+                urecs[ub.x] -= (uint64_t)blk_recs[gb];
+            }
+        for (uint32_t u = 0; u < hu.size(); u++) {
+            auto &fv = ufaults[u];
+            fv.erase(std::remove_if(fv.begin(), fv.end(),
+                                    [&](const kc_fault &f) { return in_s[hu[u].block_base + f.block]; }),
+                     fv.end());
+            uraces[u].clear();      // every free-run race involved replayed blocks only
+        }
+        for (auto &f : rf) ufaults[f.unit].push_back(kc_fault{0, f.kind, f.block, f.epoch, f.a, f.b, f.c, f.d});
+        for (auto &r : rr) uraces[r.unit].push_back(kc_race{0, r.space, r.scope, r.block, r.epoch, r.addr, r.w, r.o});
+    }
+
+    // The replay queued behind the free run stood (its results came with the
+    // free run's): its components are the racy blocks, each alone, in
+    // ascending global block index, as the device listed them.
+    void spec_apply(const std::vector<DevRace> &races, const ReplayOut &ro, std::vector<std::vector<kc_fault>> &ufaults,
+                    std::vector<std::vector<kc_race>> &uraces, std::vector<uint64_t> &urecs, Timer &tm) {
+        std::vector<uint32_t> g;
+        for (auto &r : races) g.push_back(hu[r.unit].block_base + r.block);
+        std::sort(g.begin(), g.end());
+        g.erase(std::unique(g.begin(), g.end()), g.end());
+        if (g.size() != spec_ncomp) throw KcError{KC_E_INTERNAL, "the queued replay ran other blocks than the racy ones"};
+        std::vector<std::vector<uint2>> comps;
+        uint32_t unit = 0;
+        for (uint32_t gb : g) {
+            while (unit + 1 < hu.size() && hu[unit + 1].block_base <= gb) unit++;
+            comps.push_back({make_uint2(unit, gb - hu[unit].block_base)});
+        }
+        ctx->stat_add("replays", (double)comps.size());
+        ctx->stat_add("spec_replays", 1);
+        ctx->stat_add("replay_lockstep_ms", tm.ms(5, 7));
+        ctx->stat_add("replay_ms", tm.ms(5, 7));
+        rep_log = ws.rlog.as<uint64_t>();
+        rep_n = spec_counters.log_count;
+        skip_flagged = true;
+        replayed = comps;
+        std::vector<DevRace> rr;
+        apply_replay(comps, ro, rr, ufaults, uraces, urecs);
     }
 
     // Racy blocks: re-execute them canonically and take their records, findings
@@ -1506,31 +1734,7 @@ struct Stage {
                 if (comp_of[hu[e.unit].block_base + e.b0] != comp_of[hu[e.unit].block_base + e.b1]) ok = false;
         }
         if (ok) {
-            const std::vector<DevFault> &rf = ro.faults;
-            const std::vector<uint32_t> &rrecs = ro.recs;
-            rr.insert(rr.end(), ro.lraces.begin(), ro.lraces.end());
-            if (opt.warp) {     // intra-block tuples of the warp-aware model replace the plain ones
-                rr.erase(std::remove_if(rr.begin(), rr.end(), [](const DevRace &r) { return r.scope == 0; }),
-                         rr.end());
-                rr.insert(rr.end(), ro.warp.begin(), ro.warp.end());
-            }
-            std::vector<char> in_s(total_blocks, 0);
-            for (auto &c : comps)
-                for (auto &ub : c) {
-                    const uint32_t gb = hu[ub.x].block_base + ub.y;
-                    in_s[gb] = 1;
-                    urecs[ub.x] += (uint64_t)rrecs[gb];
-                    urecs[ub.x] -= (uint64_t)blk_recs[gb];
-                }
-            for (uint32_t u = 0; u < hu.size(); u++) {
-                auto &fv = ufaults[u];
-                fv.erase(std::remove_if(fv.begin(), fv.end(),
-                                        [&](const kc_fault &f) { return in_s[hu[u].block_base + f.block]; }),
-                         fv.end());
-                uraces[u].clear();      // every free-run race involved replayed blocks only
-            }
-            for (auto &f : rf) ufaults[f.unit].push_back(kc_fault{0, f.kind, f.block, f.epoch, f.a, f.b, f.c, f.d});
-            for (auto &r : rr) uraces[r.unit].push_back(kc_race{0, r.space, r.scope, r.block, r.epoch, r.addr, r.w, r.o});
+            apply_replay(comps, ro, rr, ufaults, uraces, urecs);
             tm.mark(6);
             ctx->stat_add("replay_ms", tm.ms(5, 6));
             return;
@@ -1543,7 +1747,7 @@ struct Stage {
         for (auto &c : comps)
             for (auto &ub : c) mask[ub.x] = 1;
         ws.mask.reserve(mask.size() * 4);
-        HIPCHK(hipMemcpyAsync(ws.mask.p, mask.data(), mask.size() * 4, hipMemcpyHostToDevice, s));
+        ws.upload(ws.mask.p, mask.data(), mask.size() * 4, s);
         std::vector<std::vector<uint2>> full;
         uint64_t need = 0;
         for (uint32_t u = 0; u < hu.size(); u++) {
@@ -2203,6 +2407,7 @@ static kc_status set_option_locked(kc_ctx *ctx, const char *key, int64_t v) {
     else if (k == "sites" && (v == 0 || v == 1)) ctx->opt.sites = (int)v;
     else if (k == "uninit" && (v == 0 || v == 1)) ctx->opt.uninit = (int)v;
     else if (k == "warp" && (v == 0 || v == 1)) ctx->opt.warp = (int)v;
+    else if (k == "queue_replay" && (v == 0 || v == 1)) ctx->opt.queue_replay = (int)v;
     else if (k == "reset" && v == 1) {
         ctx->stats.clear();
     } else {
@@ -2237,6 +2442,7 @@ static double get_stat_locked(kc_ctx *ctx, const char *key) {
         if (o == "sites") return op.sites;
         if (o == "uninit") return op.uninit;
         if (o == "warp") return op.warp;
+        if (o == "queue_replay") return op.queue_replay;
         return 0.0;
     }
     auto it = ctx->stats.find(key);

@@ -13,6 +13,11 @@
         each scaled by what the same counter reads for a device copy of a
         known 1 GiB (the copy-calibration mode of bench.py), written as JSON
         with a digest of the interpreter sources it was measured on.
+    python -m paper_1211_6193_amd.profsum timeline DB ANCHOR [STEPS]
+        the GPU timeline of the last STEPS (default 2) intervals that start at
+        a dispatch of kernel ANCHOR: each kernel and memory copy with its start
+        offset, duration and the idle gap before it (needs a trace taken with
+        --kernel-trace --memory-copy-trace).
 """
 from __future__ import annotations
 
@@ -27,13 +32,20 @@ CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
 COPY_BYTES = 1 << 30
 
 
+HOST_SECTION = b"#ifndef __HIPCC_RTC__\n// ---- host side"
+
+
 def kernel_source_digest() -> str:
     """Digest of the sources of the free-run kernels (interpreter and
-    program-specialised)."""
+    program-specialised): the device code, and the shared header up to its
+    host-only section (declarations the kernels never see)."""
     h = hashlib.sha256()
     for f in ("kc_internal.h", "kc_device.h", "kc_interp.hip", "kc_jit.hip"):
         with open(os.path.join(CSRC, f), "rb") as fh:
-            h.update(fh.read())
+            text = fh.read()
+        if f == "kc_internal.h" and HOST_SECTION in text:
+            text = text[:text.index(HOST_SECTION)]
+        h.update(text)
     return h.hexdigest()[:16]
 
 
@@ -138,6 +150,44 @@ def traffic(fetch_db, write_db, copy_fetch_db, copy_write_db, kernel, out_path):
     return json.dumps(res)
 
 
+def _events(c):
+    """(start ns, end ns, label) of every kernel dispatch and memory copy."""
+    ev = [(s, e, _short(n)) for s, e, n in c.execute("select start, end, name from kernels")]
+    try:
+        cols = [r[1] for r in c.execute("pragma table_info(memory_copies)")]
+        label = "name" if "name" in cols else ("kind" if "kind" in cols else None)
+        q = f"select start, end, {label or 'NULL'}, size from memory_copies" if "size" in cols else \
+            f"select start, end, {label or 'NULL'}, 0 from memory_copies"
+        for s, e, n, b in c.execute(q):
+            ev.append((s, e, f"copy {n or ''} {b} B".replace("  ", " ")))
+    except sqlite3.Error:
+        pass
+    return sorted(ev)
+
+
+def timeline(db: str, anchor: str, steps: int = 2) -> str:
+    c = sqlite3.connect(db)
+    ev = _events(c)
+    starts = [i for i, (_, _, n) in enumerate(ev) if anchor in n]
+    if not starts:
+        return f"no dispatch of {anchor!r}"
+    out = []
+    sel = starts[-steps - 1:]
+    for a, b in zip(sel[:-1], sel[1:]):
+        t0 = ev[a][0]
+        busy = 0
+        prev_end = t0
+        out.append(f"-- interval of {(ev[b][0] - t0) / 1e3:.1f} us")
+        out.append("offset_us  dur_us  gap_us  event")
+        for s, e, n in ev[a:b]:
+            gap = max(0, s - prev_end)
+            busy += max(0, e - max(s, prev_end))
+            out.append(f"{(s - t0) / 1e3:9.1f} {(e - s) / 1e3:7.1f} {gap / 1e3:7.1f}  {n}")
+            prev_end = max(prev_end, e)
+        out.append(f"busy {busy / 1e3:.1f} us, idle {(ev[b][0] - t0 - busy) / 1e3:.1f} us")
+    return "\n".join(out)
+
+
 def main(argv):
     mode = argv[1]
     if mode == "kernels":
@@ -149,6 +199,8 @@ def main(argv):
         print(counters(argv[2]))
     elif mode == "counters_by_grid":
         print(counters_by_grid(argv[2], argv[3] if len(argv) > 3 else ""))
+    elif mode == "timeline":
+        print(timeline(argv[2], argv[3], int(argv[4]) if len(argv) > 4 else 2))
     elif mode == "traffic":
         print(traffic(*argv[2:8]))
     else:
