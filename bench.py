@@ -85,8 +85,10 @@ def main():
     mem = torch.from_numpy(job.memory.copy()).cuda()
     stream = torch.cuda.current_stream()
 
+    launch = kc.PreparedLaunch(ctx, prog, L.grid, L.block, L.shmem_bytes, L.params)
+
     def step():
-        return kc.launch(ctx, prog, L.grid, L.block, L.shmem_bytes, mem, L.params, stream=stream)
+        return launch.run(mem, stream=stream)
 
     for _ in range(args.warmup):
         rep = step()

@@ -296,11 +296,15 @@ __global__ void __launch_bounds__(WG) k_restore(const uint64_t *__restrict__ key
 // The flagged blocks in ascending global block index as (unit, block): each
 // thread counts the flags of a contiguous chunk, a block-wide scan of the
 // counts gives each chunk its place, and the chunk writes its blocks there.
+// The same workgroup first clears the buffers `zero` lists.
 // The unit of a block is found by binary search in the units' first blocks.
 __global__ void __launch_bounds__(1024) k_flagged_comps(const uint32_t *__restrict__ blk_flags, uint32_t n_blocks,
                                                         const DevUnit *__restrict__ units, uint32_t n_units,
-                                                        uint2 *__restrict__ comps, uint32_t *__restrict__ n_comps) {
+                                                        uint2 *__restrict__ comps, uint32_t *__restrict__ n_comps,
+                                                        ZeroArgs zero) {
     __shared__ uint32_t part[1024];
+    for (uint32_t b = 0; b < zero.n; b++)       // buffers the next kernels expect cleared
+        for (size_t i = threadIdx.x; i < zero.words[b]; i += blockDim.x) zero.p[b][i] = 0u;
     const uint32_t per = (n_blocks + blockDim.x - 1) / blockDim.x;
     const uint32_t b0 = min(n_blocks, threadIdx.x * per), b1 = min(n_blocks, b0 + per);
     uint32_t mine = 0;
@@ -841,8 +845,10 @@ hipError_t launch_restore(const uint64_t *keys, uint64_t n, KeyPlan kp, const De
 }
 
 hipError_t launch_flagged_comps(const uint32_t *blk_flags, uint32_t n_blocks, const DevUnit *units, uint32_t n_units,
-                                uint2 *comps, uint32_t *n_comps, hipStream_t s) {
-    hipLaunchKernelGGL(k_flagged_comps, dim3(1), dim3(1024), 0, s, blk_flags, n_blocks, units, n_units, comps, n_comps);
+                                uint2 *comps, uint32_t *n_comps, hipStream_t s, const ZeroArgs *zero) {
+    const ZeroArgs none{{}, {}, 0};
+    hipLaunchKernelGGL(k_flagged_comps, dim3(1), dim3(1024), 0, s, blk_flags, n_blocks, units, n_units, comps, n_comps,
+                       zero ? *zero : none);
     return hipGetLastError();
 }
 

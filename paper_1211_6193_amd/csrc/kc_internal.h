@@ -214,11 +214,13 @@ size_t check_long_cap(uint64_t n);
 hipError_t launch_check(const CheckArgs &a, hipStream_t s);
 hipError_t launch_restore(const uint64_t *keys, uint64_t n, KeyPlan kp, const DevUnit *units,
                           const uint32_t *blk_flags, hipStream_t s, const unsigned long long *n_dev = nullptr);
+struct ZeroArgs;
 // The blocks flagged in blk_flags (n_blocks, global block indices of the
 // units), in ascending order, as (unit, block) pairs into comps, and their
-// number into *n_comps: one workgroup.
+// number into *n_comps: one workgroup, which first clears the buffers of
+// `zero` (if given).
 hipError_t launch_flagged_comps(const uint32_t *blk_flags, uint32_t n_blocks, const DevUnit *units, uint32_t n_units,
-                                uint2 *comps, uint32_t *n_comps, hipStream_t s);
+                                uint2 *comps, uint32_t *n_comps, hipStream_t s, const ZeroArgs *zero = nullptr);
 // Exactness of a replay; sets FLAG_MISMATCH in ctr->flags.  ctr->long_count
 // must be zero; `list` holds n_rs entries.
 hipError_t launch_coverage(const uint64_t *rs, uint64_t n_rs, const uint64_t *log, uint64_t n_log, KeyPlan kp,
@@ -331,12 +333,13 @@ struct ZeroArgs {
     uint32_t n;
 };
 hipError_t launch_zero_many(const ZeroArgs &z, hipStream_t s);
-// Word copies of up to 8 device arrays into one destination (host-visible
-// pinned memory), at word offsets.
+// Word copies of up to GATHER_MAX device arrays into one destination
+// (host-visible pinned memory), at word offsets.
+constexpr uint32_t GATHER_MAX = 16;     // buffers one gather launch copies
 struct GatherArgs {
-    const uint32_t *src[8];
-    uint32_t words[8];
-    uint32_t dst_off[8];
+    const uint32_t *src[GATHER_MAX];
+    uint32_t words[GATHER_MAX];
+    uint32_t dst_off[GATHER_MAX];
     uint32_t *dst;
     uint32_t n;
 };

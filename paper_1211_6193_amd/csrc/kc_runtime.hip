@@ -381,7 +381,7 @@ struct kc_ctx {
     }
     // Capacities of the log and race list of the replay queued behind the
     // free run, grown to what earlier stages needed.
-    uint64_t spec_log_hint = 1u << 16;
+    uint64_t spec_log_hint = 1u << 14;
     uint32_t spec_race_hint = 4096;
     void spec_caps(uint64_t &log, uint32_t &races) {
         std::lock_guard<std::mutex> g(mu);
@@ -515,10 +515,74 @@ bool fault_less(const kc_fault &x, const kc_fault &y) {
     return std::lexicographical_compare(kx, kx + 8, ky, ky + 8);
 }
 bool fault_eq(const kc_fault &x, const kc_fault &y) { return !fault_less(x, y) && !fault_less(y, x); }
+// (launch, space, scope, block, epoch, addr), compared as three 64-bit words
+// (space < 2 and scope < 4): a whole step's races are sorted on the host.
 bool race_less(const kc_race &x, const kc_race &y) {
-    const uint32_t kx[6] = {x.launch, x.space, x.scope, x.block, x.epoch, x.addr};
-    const uint32_t ky[6] = {y.launch, y.space, y.scope, y.block, y.epoch, y.addr};
-    return std::lexicographical_compare(kx, kx + 6, ky, ky + 6);
+    const uint64_t ax = (uint64_t)x.launch << 32 | x.space << 2 | x.scope;
+    const uint64_t ay = (uint64_t)y.launch << 32 | y.space << 2 | y.scope;
+    if (ax != ay) return ax < ay;
+    const uint64_t bx = (uint64_t)x.block << 32 | x.epoch, by = (uint64_t)y.block << 32 | y.epoch;
+    if (bx != by) return bx < by;
+    return x.addr < y.addr;
+}
+
+// The races of one unit and launch into canonical order.  When space,
+// scope, block, epoch and address fit one 64-bit key at their widths (the
+// usual case), an LSD radix sort with 8-bit digits over that key's bits
+// orders positions; otherwise (or for short lists) a comparison sort.
+void sort_races(std::vector<kc_race> &v) {
+    const size_t n = v.size();
+    if (n < 64) {
+        std::stable_sort(v.begin(), v.end(), race_less);
+        return;
+    }
+    uint32_t mb = 0, me = 0, ma = 0, ms = 0;
+    for (auto &r : v) {
+        mb = std::max(mb, r.block);
+        me = std::max(me, r.epoch);
+        ma = std::max(ma, r.addr);
+        ms = std::max(ms, (r.space << 2) | r.scope);
+    }
+    auto width = [](uint64_t m) {
+        uint32_t b = 0;
+        while (b < 64 && (m >> b)) b++;
+        return b;
+    };
+    const uint32_t bb = width(mb), eb = width(me), ab = width(ma), sb = width(ms);
+    if (v[0].launch != v[n - 1].launch || bb + eb + ab + sb > 64) {
+        std::stable_sort(v.begin(), v.end(), race_less);
+        return;
+    }
+    auto shl = [](uint64_t x, uint32_t s) { return s >= 64 ? 0ull : x << s; };
+    std::vector<uint64_t> key(n), key2(n);
+    std::vector<uint32_t> pos(n), pos2(n);
+    for (size_t i = 0; i < n; i++) {
+        const kc_race &r = v[i];
+        key[i] = shl((r.space << 2) | r.scope, bb + eb + ab) | shl(r.block, eb + ab) | shl(r.epoch, ab) | r.addr;
+        pos[i] = (uint32_t)i;
+    }
+    const uint32_t total = bb + eb + ab + sb;
+    uint32_t cnt[256];
+    for (uint32_t sh = 0; sh < total; sh += 8) {
+        std::memset(cnt, 0, sizeof cnt);
+        for (size_t i = 0; i < n; i++) cnt[(key[i] >> sh) & 255u]++;
+        uint32_t at = 0;
+        for (uint32_t d = 0; d < 256; d++) {
+            const uint32_t c = cnt[d];
+            cnt[d] = at;
+            at += c;
+        }
+        for (size_t i = 0; i < n; i++) {
+            const uint32_t to = cnt[(key[i] >> sh) & 255u]++;
+            key2[to] = key[i];
+            pos2[to] = pos[i];
+        }
+        key.swap(key2);
+        pos.swap(pos2);
+    }
+    std::vector<kc_race> out(n);
+    for (size_t i = 0; i < n; i++) out[i] = v[pos[i]];
+    v.swap(out);
 }
 
 // Host time of a section, added to statistic `key` when timing is on.
@@ -672,7 +736,7 @@ struct Stage {
             g.src[g.n] = (const uint32_t *)it.dev;
             g.words[g.n] = (uint32_t)(it.bytes / 4);
             g.dst_off[g.n] = (uint32_t)(it.off / 4);
-            if (++g.n == 8) {
+            if (++g.n == GATHER_MAX) {
                 g.dst = (uint32_t *)ws.d_pin;
                 HIPCHK(launch_gather(g, s));
                 g.n = 0;
@@ -682,7 +746,10 @@ struct Stage {
             g.dst = (uint32_t *)ws.d_pin;
             HIPCHK(launch_gather(g, s));
         }
-        HIPCHK(hipStreamSynchronize(s));
+        {
+            HostTimer wt{ctx, "host_fetch_wait_ms", opt.timing != 0};
+            HIPCHK(hipStreamSynchronize(s));
+        }
         ws.uploads_done();
     }
     template <class T> const T *fetched(const Fetch &f, size_t i) const {
@@ -770,17 +837,17 @@ struct Stage {
         ws.stctr.reserve(sizeof(DevCounters));
         HIPCHK(launch_restore(ws.log.as<uint64_t>(), log_cap, kp, ws.units.as<DevUnit>(),
                               ws.blk_flags.as<uint32_t>(), s, &ws.ctr.as<DevCounters>()->log_count));
-        HIPCHK(launch_flagged_comps(ws.blk_flags.as<uint32_t>(), total_blocks, ws.units.as<DevUnit>(),
-                                    (uint32_t)hu.size(), ws.comp_blocks.as<uint2>(), ws.sncomp.as<uint32_t>(), s));
         ws.rblk_recs.reserve((size_t)total_blocks * 4);
         ws.rflags.reserve((size_t)total_blocks * 4);
         ws.rlog.reserve(spec_rcap * 8);
         ws.rfaults.reserve((size_t)spec_fcap * sizeof(DevFault));
         ws.rlraces.reserve((size_t)spec_rlcap * sizeof(DevRace));
-        {
+        {   // the replay's counters and per-block counts are cleared by the same workgroup
             ZeroArgs z{{ws.sctr.as<uint32_t>(), ws.rblk_recs.as<uint32_t>()},
                        {sizeof(DevCounters) / 4, (size_t)total_blocks}, 2};
-            HIPCHK(launch_zero_many(z, s));
+            HIPCHK(launch_flagged_comps(ws.blk_flags.as<uint32_t>(), total_blocks, ws.units.as<DevUnit>(),
+                                        (uint32_t)hu.size(), ws.comp_blocks.as<uint2>(), ws.sncomp.as<uint32_t>(), s,
+                                        &z));
         }
         uint32_t wg = 64, shmax = 0;
         for (auto &u : hu) {
@@ -1115,6 +1182,7 @@ struct Stage {
 
     void run() {
         HostTimer whole{ctx, "stage_host_ms", opt.timing != 0};
+        std::unique_ptr<HostTimer> setup_t(new HostTimer{ctx, "host_setup_ms", opt.timing != 0});
         {
             HostTimer ht{ctx, "host_plan_ms", opt.timing != 0};
             plan();
@@ -1160,6 +1228,7 @@ struct Stage {
         size_t i_instr = 0, i_grecs = 0, i_sctr = 0, i_sncomp = 0, i_stctr = 0, i_srf = 0, i_srecs = 0, i_srl = 0;
         Fetch fetch;
         bool table_queued = false;
+        setup_t.reset();
         for (;;) {
             ws.faults.reserve((size_t)fault_cap * sizeof(DevFault));
             ws.lraces.reserve((size_t)lrace_cap * sizeof(DevRace));
@@ -1246,6 +1315,7 @@ struct Stage {
             HIPCHK(launch_copy_units(ws.units.as<DevUnit>(), n, max_words, false, nullptr, s));   // back to launch start
             ctx->stat_add("retries", 1);
         }
+        std::unique_ptr<HostTimer> parse_t(new HostTimer{ctx, "host_parse_ms", opt.timing != 0});
         {
             const uint32_t *bi = fetched<uint32_t>(fetch, i_instr);
             const uint32_t *bg = fetched<uint32_t>(fetch, i_grecs);
@@ -1309,6 +1379,7 @@ struct Stage {
             }
         }
 
+        parse_t.reset();
         HostTimer post{ctx, "host_post_ms", opt.timing != 0};
         // per-unit findings of the free run
         std::vector<std::vector<kc_fault>> ufaults(n);
@@ -1330,17 +1401,19 @@ struct Stage {
             std::memcpy(ro.recs.data(), fetched<uint32_t>(fetch, i_srecs), (size_t)total_blocks * 4);
             take_list(fetch, i_srf, spec_counters.fault_count, spec_fcap, ws.rfaults.p, ro.faults);
             take_list(fetch, i_srl, spec_counters.race_count, spec_rlcap, ws.rlraces.p, ro.lraces, kSpecRaces);
+            HostTimer at{ctx, "host_replay_apply_ms", opt.timing != 0};
             spec_apply(races, ro, ufaults, uraces, urecs, tm);
         } else if (!races.empty()) {
             if (spec_ok) throw KcError{KC_E_INTERNAL, "racy blocks the free run did not flag"};
             replay(races, edges, sorted, nrec, ufaults, uraces, urecs, tm);
         }
 
+        HostTimer ut{ctx, "host_unit_out_ms", opt.timing != 0};
         for (uint32_t i = 0; i < n; i++) {
             UnitOut &o = out[i];
             o.records = urecs[i];
             o.races = std::move(uraces[i]);
-            std::sort(o.races.begin(), o.races.end(), race_less);
+            sort_races(o.races);
             o.faults = std::move(ufaults[i]);
             std::sort(o.faults.begin(), o.faults.end(), fault_less);
             o.faults.erase(std::unique(o.faults.begin(), o.faults.end(), fault_eq), o.faults.end());
@@ -2276,6 +2349,8 @@ void run_jobs(kc_ctx *ctx, const kc_job *jobs, uint32_t n_jobs, hipStream_t s, s
                 UnitOut &o = out[i];
                 r->records += o.records;
                 first_race[i] = r->races.size();
+                r->races.reserve(r->races.size() + o.races.size());
+                r->sites.reserve(r->sites.size() + o.races.size());
                 for (auto &x : o.races) { x.launch = li; r->add_race(x); }
                 for (auto &f : o.faults) { f.launch = li; r->faults.push_back(f); }
                 if (o.deadlocked) alive[who[i]] = 0;
@@ -2854,6 +2929,7 @@ kc_status kc_launch(kc_ctx *ctx, const kc_launch_desc *desc, int32_t *dev_mem, u
         return KC_E_INVAL;
     }
     return guarded(ctx, [&] {
+        HostTimer lt{ctx, "host_launch_ms", ctx->options().timing != 0};
         kc_job job{desc, 1, dev_mem, n_words, 0};
         std::vector<kc_report *> reps;
         run_jobs(ctx, &job, 1, (hipStream_t)stream, reps);

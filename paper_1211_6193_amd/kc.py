@@ -317,14 +317,29 @@ def _stream_handle(stream) -> Optional[int]:
 def launch(ctx: Context, prog: Program, grid, block, shmem_bytes: int, mem, params: Sequence[int] = (),
            stream=None) -> Report:
     """One synchronous launch on ``mem`` (an int32 CUDA tensor, updated in place)."""
-    import torch
-    if mem.dtype != torch.int32 or not mem.is_cuda or not mem.is_contiguous():
-        raise ValueError("mem must be a contiguous int32 tensor on the GPU")
-    d = _desc(prog, grid, block, shmem_bytes, params)
-    out = C.c_void_p()
-    ctx._check(ctx.lib.kc_launch(ctx.h, C.byref(d), mem.data_ptr(), mem.numel(), _stream_handle(stream),
-                                 C.byref(out)), "kc_launch")
-    return _take_report(ctx.lib, out)
+    return PreparedLaunch(ctx, prog, grid, block, shmem_bytes, params).run(mem, stream)
+
+
+class PreparedLaunch:
+    """kc_launch with its descriptor (program, grid, block, shared memory,
+    parameters) marshalled once, for callers that run the same launch on
+    memories again and again."""
+
+    def __init__(self, ctx: Context, prog: Program, grid, block, shmem_bytes: int, params: Sequence[int] = ()):
+        self.ctx = ctx
+        self.prog = prog                # keeps the program alive while the descriptor points at it
+        self.desc = _desc(prog, grid, block, shmem_bytes, params)
+        self._dref = C.byref(self.desc)
+
+    def run(self, mem, stream=None) -> Report:
+        """Run on ``mem`` (a contiguous int32 CUDA tensor, updated in place)."""
+        import torch
+        if mem.dtype != torch.int32 or not mem.is_cuda or not mem.is_contiguous():
+            raise ValueError("mem must be a contiguous int32 tensor on the GPU")
+        out = C.c_void_p()
+        self.ctx._check(self.ctx.lib.kc_launch(self.ctx.h, self._dref, mem.data_ptr(), mem.numel(),
+                                               _stream_handle(stream), C.byref(out)), "kc_launch")
+        return _take_report(self.ctx.lib, out)
 
 
 def launch_noalloc(ctx: Context, prog: Program, grid, block, shmem_bytes: int, mem, params: Sequence[int] = (),
