@@ -381,17 +381,20 @@ struct kc_ctx {
     }
     // Capacities of the log and race list of the replay queued behind the
     // free run, grown to what earlier stages needed.
+    // and of its grid: the number of racy blocks the last such stage had
     uint64_t spec_log_hint = 1u << 14;
-    uint32_t spec_race_hint = 4096;
-    void spec_caps(uint64_t &log, uint32_t &races) {
+    uint32_t spec_race_hint = 4096, spec_grid_hint = 64;
+    void spec_caps(uint64_t &log, uint32_t &races, uint32_t &grid) {
         std::lock_guard<std::mutex> g(mu);
         log = spec_log_hint;
         races = spec_race_hint;
+        grid = spec_grid_hint;
     }
-    void note_spec(uint64_t log, uint32_t races) {
+    void note_spec(uint64_t log, uint32_t races, uint32_t comps) {
         std::lock_guard<std::mutex> g(mu);
         spec_log_hint = std::max<uint64_t>(spec_log_hint, log + log / 4 + 1024);
         spec_race_hint = std::max<uint32_t>(spec_race_hint, races + races / 4 + 1024);
+        spec_grid_hint = std::max<uint32_t>(64, comps + comps / 4);
     }
     // Capacities of the finding and local-race lists, grown to what earlier
     // stages needed so that a repeated workload does not interpret twice.
@@ -829,7 +832,8 @@ struct Stage {
     }
     void queue_spec_replay(uint64_t log_cap, uint32_t fault_cap, Timer &tm) {
         tm.mark(5);
-        ctx->spec_caps(spec_rcap, spec_rlcap);
+        uint32_t grid_hint = 64;
+        ctx->spec_caps(spec_rcap, spec_rlcap, grid_hint);
         spec_fcap = fault_cap;
         ws.comp_blocks.reserve((size_t)total_blocks * sizeof(uint2));
         ws.sncomp.reserve(4);
@@ -854,9 +858,10 @@ struct Stage {
             wg = std::max<uint32_t>(wg, (u.nt + 63) / 64 * 64);
             shmax = std::max(shmax, u.sh_words);
         }
-        // the racy blocks are few in the common case: two workgroups per CU
-        // stride over them, and the idle ones exit at once
-        const uint32_t grid = std::min<uint32_t>(total_blocks, 512);
+        // about as many workgroups as the last such stage had racy blocks
+        // (the workgroups stride over the list, so more blocks only take
+        // longer; idle workgroups exit at once)
+        const uint32_t grid = std::min<uint32_t>(total_blocks, std::min<uint32_t>(grid_hint, 1024));
         comp_groups.assign(1, CompGroup{0, grid, 0, wg, shmax});
         spec_ncomps = ws.sncomp.as<uint32_t>();
         wlog_cap = 0;
@@ -1295,7 +1300,7 @@ struct Stage {
             if (spec) {
                 const DevCounters sc = *fetched<DevCounters>(fetch, i_sctr);
                 const uint32_t ncomp = *fetched<uint32_t>(fetch, i_sncomp);
-                ctx->note_spec(sc.log_count, sc.race_count);
+                ctx->note_spec(sc.log_count, sc.race_count, ncomp);
                 const bool need_sort = (fetched<DevCounters>(fetch, 4)->flags & FLAG_NEED_SORT) != 0;
                 const uint32_t sflags = sc.flags & (FLAG_LOG_OVERFLOW | FLAG_FAULT_OVERFLOW | FLAG_RACE_OVERFLOW |
                                                     FLAG_EPOCH_OVERFLOW | FLAG_WLOG_OVERFLOW);
