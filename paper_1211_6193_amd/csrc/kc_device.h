@@ -188,23 +188,26 @@ __device__ __forceinline__ void emit_fault(bool f, const InterpArgs &A, const Bl
 
 // Warp-aware model: an in-bounds access of the replay with its step, appended
 // with one reservation per wave.
-__device__ __noinline__ void wlog_append_wave(const InterpArgs &A, uint64_t m, bool on, uint32_t unit, uint32_t block,
-                                             uint32_t epoch, uint32_t step, uint32_t addr, uint32_t tsk) {
+// (The buffers are passed one by one: a reference to the kernel's argument
+// block would make every kernel that calls this copy that block to scratch.)
+__device__ __noinline__ void wlog_append_wave(WarpRec *wlog, uint32_t wlog_cap, uint32_t *wlog_count, uint32_t *flags,
+                                             uint64_t m, bool on, uint32_t unit, uint32_t block, uint32_t epoch,
+                                             uint32_t step, uint32_t addr, uint32_t tsk) {
     const uint32_t leader = (uint32_t)__ffsll((long long)m) - 1u;
     uint32_t base = 0;
-    if (lane_id() == leader) base = atomicAdd(A.wlog_count, (uint32_t)__popcll(m));
+    if (lane_id() == leader) base = atomicAdd(wlog_count, (uint32_t)__popcll(m));
     base = (uint32_t)__shfl((int)base, (int)leader);
     if (on) {
         const uint32_t idx = base + lane_prefix(m);
-        if (idx < A.wlog_cap) A.wlog[idx] = WarpRec{unit, block, epoch, step, addr, tsk};
-        else atomicOr(A.flags, FLAG_WLOG_OVERFLOW);
+        if (idx < wlog_cap) wlog[idx] = WarpRec{unit, block, epoch, step, addr, tsk};
+        else atomicOr(flags, FLAG_WLOG_OVERFLOW);
     }
 }
 __device__ __forceinline__ void wlog_append(const InterpArgs &A, const BlockCtx &B, bool inb, uint32_t space,
                                             uint32_t addr, bool store) {
     const uint64_t m = __ballot(inb);
     if (m == 0) return;
-    wlog_append_wave(A, m, inb, B.unit, B.block, B.epoch, B.step, addr,
+    wlog_append_wave(A.wlog, A.wlog_cap, A.wlog_count, A.flags, m, inb, B.unit, B.block, B.epoch, B.step, addr,
                      B.tid | (store ? 1u << 16 : 0u) | (space << 17));
 }
 

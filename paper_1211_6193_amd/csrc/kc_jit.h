@@ -13,6 +13,7 @@ struct JitFunctions {
     hipFunction_t local_1024 = nullptr;   // epoch-local check, up to 1024 threads
     hipFunction_t free_1024 = nullptr;    // every access logged
     hipFunction_t lock_local = nullptr;   // lockstep replay, epoch-local check
+    hipFunction_t lock_local_256 = nullptr;   // ... workgroups up to 256 threads (no register bound)
     hipFunction_t lock = nullptr;         // lockstep replay, every access logged
 };
 

@@ -401,9 +401,12 @@ std::string jit_source(const uint64_t *words, uint32_t n, int waves) {
     // are bounded to 128 VGPRs
     const struct { const char *name; int bound; bool local; } kernels[] = {
         {"kc_jit_free_local_256", 256, true}, {"kc_jit_free_local_1024", 1024, true}, {"kc_jit_free_1024", 1024, false}};
-    for (const char *name : {"kc_jit_lock_local", "kc_jit_lock"}) {
-        const bool local = std::string(name) == "kc_jit_lock_local";
-        o << "extern \"C\" __global__ void __launch_bounds__(1024) " << name << "(kc::InterpArgs A) {\n";
+    // the replay's blocks run one per CU, latency bound: workgroups of up to
+    // 256 threads get a kernel with the whole register file (no spills)
+    for (const char *name : {"kc_jit_lock_local_256", "kc_jit_lock_local", "kc_jit_lock"}) {
+        const bool local = std::string(name) != "kc_jit_lock";
+        const int bound = std::string(name) == "kc_jit_lock_local_256" ? 256 : 1024;
+        o << "extern \"C\" __global__ void __launch_bounds__(" << bound << ") " << name << "(kc::InterpArgs A) {\n";
         o << "    kc::lockstep_body(A, [](const kc::InterpArgs &a, kc::BlockCtx &b, const kc::Shared &s, "
              "const kc::StoreTables &tb, kc::Lane &t, kc::LogState &l) {\n";
         o << "        return kc::jit_lock_run<" << (local ? "true" : "false") << ">(a, b, s, tb, t, l);\n    });\n}\n";
@@ -547,6 +550,7 @@ bool jit_functions(const std::shared_ptr<JitEntry> &e, int device, bool wait, Ji
             hipModuleGetFunction(&f.local_1024, mod, "kc_jit_free_local_1024") != hipSuccess ||
             hipModuleGetFunction(&f.free_1024, mod, "kc_jit_free_1024") != hipSuccess ||
             hipModuleGetFunction(&f.lock_local, mod, "kc_jit_lock_local") != hipSuccess ||
+            hipModuleGetFunction(&f.lock_local_256, mod, "kc_jit_lock_local_256") != hipSuccess ||
             hipModuleGetFunction(&f.lock, mod, "kc_jit_lock") != hipSuccess) {
             (void)hipGetLastError();
             e->state = -1;
@@ -622,8 +626,8 @@ hipError_t launch_jit_lockstep(const JitFunctions &f, const InterpArgs &a, uint3
     }
     if (lds > 64 * 1024) return hipErrorInvalidValue;    // the caller falls back to the interpreter
     void *params[] = {&args};
-    return hipModuleLaunchKernel(args.local ? f.lock_local : f.lock, n_wg, 1, 1, wg_threads, 1, 1, (unsigned)lds, s,
-                                 params, nullptr);
+    hipFunction_t k = args.local ? (wg_threads <= 256 ? f.lock_local_256 : f.lock_local) : f.lock;
+    return hipModuleLaunchKernel(k, n_wg, 1, 1, wg_threads, 1, 1, (unsigned)lds, s, params, nullptr);
 }
 
 bool jit_fits(uint32_t sh_words_max, uint32_t wg_threads) {
