@@ -390,6 +390,20 @@ struct kc_ctx {
         races = spec_race_hint;
         grid = spec_grid_hint;
     }
+    // Programs whose last queued replay could not stand (its launch needed a
+    // sorted check) skip it for their next stages, trying again now and then.
+    std::unordered_map<const void *, uint32_t> spec_backoff;
+    bool spec_skip(const void *prog) {
+        std::lock_guard<std::mutex> g(mu);
+        auto it = spec_backoff.find(prog);
+        if (it == spec_backoff.end() || it->second == 0) return false;
+        it->second--;
+        return true;
+    }
+    void note_spec_failed(const void *prog) {
+        std::lock_guard<std::mutex> g(mu);
+        spec_backoff[prog] = 16;
+    }
     void note_spec(uint64_t log, uint32_t races, uint32_t comps) {
         std::lock_guard<std::mutex> g(mu);
         spec_log_hint = std::max<uint64_t>(spec_log_hint, log + log / 4 + 1024);
@@ -828,7 +842,7 @@ struct Stage {
         if (!total_blocks || table_obits() == 0) return false;
         for (auto &u : in)
             if (u.desc->prog != in[0].desc->prog) return false;
-        return true;
+        return !ctx->spec_skip(in[0].desc->prog);
     }
     void queue_spec_replay(uint64_t log_cap, uint32_t fault_cap, Timer &tm) {
         tm.mark(5);
@@ -1313,6 +1327,7 @@ struct Stage {
                     spec_off = true;
                     again = true;
                     ctx->stat_add("spec_retries", 1);
+                    if (need_sort) ctx->note_spec_failed(in[0].desc->prog);
                 }
             }
             if (!again) break;
