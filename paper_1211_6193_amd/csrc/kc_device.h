@@ -129,7 +129,7 @@ struct Shared {
     unsigned long long *shadow;   // per simulated shared word: access tuple of the current epoch (replay)
     uint32_t *vmin, *vmax, *vw;   // the same region in the free run: smallest and largest accessing tid, any store
     unsigned long long *gst;      // global shadow table: per global location, its tuple of the epoch
-    uint64_t *repbuf;   // with the table: representative records held until the block ends (REP_HOLD)
+    uint64_t *repbuf;   // with the table: representative records held until the block ends (A.rep_hold)
     uint32_t *slots;    // 16 waves x 10 words: episode reductions, lockstep rounds
     uint32_t *slots2;   // 16 x 4: divergence second round
     uint32_t *eps;      // free-run episodes: 3 sets of EPS_WORDS summary words, used in turn
@@ -597,7 +597,7 @@ __device__ __forceinline__ void gst_drain(const InterpArgs &A, const BlockCtx &B
         const uint32_t held = S.tmp[38];
         unsigned long long base = 0;
         uint32_t hold = 0;
-        if (total && reduced && held + total <= REP_HOLD) {
+        if (total && reduced && held + total <= A.rep_hold) {
             base = held;
             hold = 1;
             S.tmp[38] = held + total;
@@ -1641,7 +1641,7 @@ __device__ __forceinline__ size_t carve_lds(uint8_t *smem, const InterpArgs &A, 
         S.gst = (unsigned long long *)(smem + off);
         off += A.gst_bits ? ((size_t)8 << A.gst_bits) : 0;
         S.repbuf = (uint64_t *)(smem + off);
-        off += A.gst_bits ? (size_t)REP_HOLD * 8 : 0;
+        off += A.gst_bits ? (size_t)A.rep_hold * 8 : 0;
     }
     S.slots = (uint32_t *)(smem + off);
     S.slots2 = S.slots + 16 * 10;

@@ -29,6 +29,13 @@ constexpr uint32_t MAX_SHMEM_WORDS = 16384;     // 64 KiB of simulated shared me
 // common case instead of one per epoch, since every block of a launch
 // reserves on the same counter.
 constexpr uint32_t REP_HOLD = 512;
+// Representatives a block of `wg_threads` threads holds in LDS (at most
+// REP_HOLD): small blocks touch few locations, and a smaller buffer lets more
+// of them share a CU.
+__host__ __device__ inline uint32_t rep_hold_for(uint32_t wg_threads) {
+    const uint32_t h = 2 * wg_threads;
+    return h < 128u ? 128u : (h > REP_HOLD ? REP_HOLD : h);
+}
 
 enum : uint32_t { F_DEADLOCK = 1, F_DIVERGENCE = 2, F_OOB = 3, F_FUEL = 4, F_ARITH = 5, F_ALLOC = 6, F_UNINIT = 7 };
 
@@ -132,6 +139,7 @@ struct InterpArgs {
     // When set, the components are single blocks comp_blocks[0 .. *n_comps_dev)
     // (a count written on the device) and workgroups stride over them.
     const uint32_t *n_comps_dev;
+    uint32_t rep_hold;              // representatives a block holds in LDS (rep_hold_for its size)
     KeyPlan kp;
     uint64_t *log;
     unsigned long long log_cap;

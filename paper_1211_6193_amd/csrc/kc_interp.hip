@@ -60,7 +60,7 @@ size_t interp_lds_bytes(uint32_t sh_words_max, uint32_t wg_threads, uint32_t sta
     size_t off = ((size_t)sh_words_max * 4 + 15) & ~(size_t)15;
     off += (size_t)nwaves * stage * 8;
     if (local) off += (size_t)nwaves * stage * 8 + (size_t)nwaves * 256 * 4 + 256 * 4 + shadow_region_bytes(sh_words_max);
-    if (local && gst_bits) off += ((size_t)8 << gst_bits) + (size_t)REP_HOLD * 8;
+    if (local && gst_bits) off += ((size_t)8 << gst_bits) + (size_t)rep_hold_for(wg_threads) * 8;
     off += (16 * 10 + 16 * 4 + 3 * 8) * 4 + (size_t)(sh_words_max + 31) / 32 * 4;
     if (lockstep) off += (size_t)sh_words_max * 4 + ((size_t)8 << lockstep_hash_bits(wg_threads));
     return off;
@@ -69,6 +69,7 @@ size_t interp_lds_bytes(uint32_t sh_words_max, uint32_t wg_threads, uint32_t sta
 hipError_t launch_interp(const InterpArgs &a, uint32_t n_wg, uint32_t wg_threads, bool lockstep, hipStream_t s) {
     if (n_wg == 0) return hipSuccess;
     InterpArgs args = a;
+    args.rep_hold = rep_hold_for(wg_threads);
     if (args.sites) args.local = 0;                   // the source-site replay logs every access
     if (!args.local) args.gst_bits = 0;
     auto bytes = [&] {

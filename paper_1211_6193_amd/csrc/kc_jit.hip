@@ -580,6 +580,7 @@ hipError_t launch_jit(const JitFunctions &f, const InterpArgs &a, uint32_t n_wg,
                       hipStream_t s) {
     if (n_wg == 0) return hipSuccess;
     InterpArgs args = a;
+    args.rep_hold = rep_hold_for(wg_threads);
     if (!args.local) args.gst_bits = 0;
     auto bytes = [&] {
         return interp_lds_bytes(args.sh_words_max, wg_threads, args.stage, false, args.local != 0, args.gst_bits);
@@ -607,6 +608,7 @@ hipError_t launch_jit_lockstep(const JitFunctions &f, const InterpArgs &a, uint3
                                hipStream_t s) {
     if (n_wg == 0) return hipSuccess;
     InterpArgs args = a;
+    args.rep_hold = rep_hold_for(wg_threads);
     if (!args.local) args.gst_bits = 0;
     auto bytes = [&] {
         return interp_lds_bytes(args.sh_words_max, wg_threads, args.stage, true, args.local != 0, args.gst_bits);

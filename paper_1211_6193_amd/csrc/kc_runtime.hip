@@ -951,9 +951,11 @@ struct Stage {
     }
 
     // Records staged per wave: the LDS budget split over the workgroup's waves
-    // (staging + the epoch-local sort's second buffer), a multiple of 64.
+    // (staging + the epoch-local sort's second buffer), a multiple of 64;
+    // workgroups of fewer than four waves count as four (a small block needs
+    // no more staging per wave, and less LDS lets more of them share a CU).
     uint32_t stage_for(uint32_t wg_threads) const {
-        const uint32_t nw = (wg_threads + 63) / 64;
+        const uint32_t nw = std::max<uint32_t>((wg_threads + 63) / 64, 4u);
         uint32_t st = (uint32_t)(opt.stage_bytes / (nw * 16u)) / 64u * 64u;
         return std::max<uint32_t>(64u, std::min<uint32_t>(st, 2048u));
     }
