@@ -171,7 +171,10 @@ kc_status kc_ctx_set_option(kc_ctx *ctx, const char *key, int64_t value);
  * "noalloc_calls" and
  * "noalloc_scratch_peak" (calls of kc_launch_noalloc and the most bytes of
  * its static scratch area one of them used).
- * Timings are only collected with option "timing" set.  "option.<name>"
+ * Host times ("host_launch_ms", "stage_host_ms", "host_setup_ms",
+ * "host_fetch_wait_ms", "host_parse_ms", "host_post_ms",
+ * "host_replay_apply_ms", "host_unit_out_ms", "host_reports_ms") and the
+ * stage times are only collected with option "timing" set.  "option.<name>"
  * reads back the current value of option <name>.  Returns 0 for an unknown
  * key. */
 double kc_ctx_get_stat(kc_ctx *ctx, const char *key);
@@ -198,7 +201,11 @@ typedef struct {
     uint32_t n_params;          /* <= 8; unused params read as 0 */
 } kc_launch_desc;
 
-/* One launch, synchronous with respect to the host.  Work is queued on
+/* One launch (Section 2: a kernel launched over a grid of blocks of
+ * threads), checked as Section 3.1 describes: every race of two accesses of
+ * one location with no synchronisation point between them, barrier
+ * divergence and the deadlock of threads waiting at a barrier others never
+ * reach.  Synchronous with respect to the host.  Work is queued on
  * `stream` (a hipStream_t; NULL = the null stream).  `dev_mem` is a device
  * buffer of `n_words` int32 words (< 2^31) that the caller owns and keeps
  * untouched until the call returns; it is updated in place to the canonical
@@ -411,10 +418,16 @@ typedef struct {
 
 uint64_t kc_report_records(const kc_report *r);            /* canonical access-record count */
 uint32_t kc_report_launches_completed(const kc_report *r);
-/* Races ascending by (launch, space, scope, block, epoch, addr); the array
- * lives as long as the report. */
+/* The race tuples of Section 3.1 (one per conflicting location and, within a
+ * block, barrier epoch: the tuples are cleared at each __syncthreads()),
+ * ascending by (launch, space, scope, block, epoch, addr); the array lives as
+ * long as the report; *n receives the count. */
 const kc_race *kc_report_races(const kc_report *r, uint64_t *n);
-/* Findings ascending by (launch, block, epoch, kind, a, b, c, d), no repeats. */
+/* The findings (Section 3.1 deadlock and barrier divergence; the checks the
+ * tool inherits from the C semantics, Section 3.2: out-of-bounds,
+ * uninitialised and illegal memory accesses, undefined arithmetic; fuel)
+ * ascending by (launch, block, epoch, kind, a, b, c, d), no repeats; the
+ * array lives as long as the report. */
 const kc_fault *kc_report_faults(const kc_report *r, uint64_t *n);
 /* Sites of the races, one per race in the same order; lives as long as the report. */
 const kc_race_site *kc_report_race_sites(const kc_report *r, uint64_t *n);
