@@ -143,6 +143,14 @@ void kc_ctx_destroy(kc_ctx *ctx);
  * racy is queued right behind it, before the host reads any result, and
  * stands when the log needs no sorted check; 0 = the host reads the free
  * run's results first and queues the replay after; results are identical),
+ * "onesweep" (1 = sorts of 2^20 to 2^30 records count every pass's digits
+ * in one read and then scatter each pass in one kernel, each tile finding
+ * its output offsets from the counts earlier tiles publish; 0 = default:
+ * three kernels per pass (per-tile counts, their scan, the scatter), as fast
+ * or faster on MI355X; results are identical), "sort_spin" (the bound, in polls, of each wait of
+ * a tile for an earlier tile's counts, default 2^16, 0 to 2^30: a wait that
+ * runs out leaves that pass to the three-kernel passes, counted in
+ * "sort_stalls"),
  * "reset" (1 = clear the statistics).
  * Errors: KC_E_INVAL for an unknown key or out-of-range value. */
 kc_status kc_ctx_set_option(kc_ctx *ctx, const char *key, int64_t value);
@@ -152,7 +160,9 @@ kc_status kc_ctx_set_option(kc_ctx *ctx, const char *key, int64_t value);
  * "replays", "fallbacks", "retries", "spec_replays" (stages whose replay,
  * queued behind the free run before any result was read, stood),
  * "spec_retries" (stages run again without it because it did not apply),
- * "interp_launches", "sort_keys",
+ * "interp_launches", "sort_keys", "sort_onesweep" and "sort_stalls" (sorts
+ * that took the single-pass scatters, and those finished by three-kernel
+ * passes after a wait ran out),
  * "sorted_checks", "hash_check_ms" (free-run logs that needed the sort, and
  * the time of the location-table checks),
  * "replay_sorted_checks" (replays whose records needed the sorted check: an

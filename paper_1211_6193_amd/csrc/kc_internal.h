@@ -187,10 +187,20 @@ size_t interp_lds_bytes(uint32_t sh_words_max, uint32_t wg_threads, uint32_t sta
 // thread, at least 256.
 uint32_t gst_bits_for(uint32_t wg_threads);
 
+// Single-pass digit scatter: at most this many passes (64 bits, 4-bit digits),
+// and its counters: per pass 256 digit counts and 256 digit bases, and the
+// stall word.
+constexpr uint32_t RADIX_OS_PASSES = 16;
+constexpr size_t RADIX_OS_WORDS = 2 * RADIX_OS_PASSES * 256 + 1;
+constexpr uint64_t RADIX_OS_MIN_KEYS = 1ull << 20;
+
 struct SortScratch {
     uint64_t *alt = nullptr;         // ping-pong buffer, >= n keys
-    uint32_t *hist = nullptr;        // 256 * n_tiles, digit-major
+    uint32_t *hist = nullptr;        // 256 * n_tiles, digit-major (single-pass scatter: twice that)
     uint32_t *part = nullptr;        // 256 digit totals
+    uint32_t *os = nullptr;          // RADIX_OS_WORDS, or null: no single-pass scatter
+    uint32_t spin = 1u << 16;        // bound of each look-back wait (polls)
+    uint32_t *stall = nullptr;       // set by radix_sort when the single-pass scatter ran
     size_t cap_keys = 0, cap_hist = 0, cap_part = 0;
 };
 // Virtual sort key of a record: the bits from s_blk up, then the low ueb bits
@@ -201,8 +211,15 @@ struct VKey {
 // Sort keys[0..n) ascending by the virtual key (stable), `digit` bits (4..8)
 // per pass over inputs larger than one workgroup's.  *out points at the
 // sorted array: keys itself or scratch.alt.
+// With scratch.os set and radix_onesweep(n), the passes are single-pass
+// scatters and scratch.stall points at the device word that is 0 when they all
+// ran, else the first stalled pass + 1: then radix_sort_resume(pass) finishes
+// the sort (from that pass's input) and sets *out again.
 hipError_t radix_sort(uint64_t *keys, uint64_t n, const VKey &vk, SortScratch &sc,
                       uint32_t tile, hipStream_t s, uint64_t **out, uint32_t digit = 8);
+hipError_t radix_sort_resume(uint64_t *keys, uint64_t n, const VKey &vk, SortScratch &sc, uint32_t tile,
+                             hipStream_t s, uint64_t **out, uint32_t digit, uint32_t pass);
+bool radix_onesweep(uint64_t n);
 size_t radix_hist_entries(uint64_t n, uint32_t tile);
 
 struct CheckArgs {

@@ -314,6 +314,8 @@ struct Options {
     int uninit = 0;                 // UNINIT findings for loads of shared words not yet stored to
     int warp = 0;                   // warp-aware model: accesses of one warp conflict only at the same step
     int queue_replay = 1;           // replay of the free run's racy blocks queued behind it
+    int onesweep = 0;               // large sorts: single-pass digit scatters (decoupled look-back)
+    uint32_t sort_spin = 1u << 16;  // bound of each look-back wait, in polls
     int arena = 0;                  // set by the library: buffers come from the static scratch area
 };
 
@@ -1450,13 +1452,30 @@ struct Stage {
         uint64_t *res = keys.as<uint64_t>();
         if (n <= 1) return res;
         SortScratch sc;
+        const bool os = opt.onesweep && !opt.arena && radix_onesweep(n);
         alt.reserve(n * 8);
-        ws.hist.reserve(radix_hist_entries(n, opt.sort_tile) * 4);
-        ws.part.reserve(256 * 4);
+        ws.hist.reserve(radix_hist_entries(n, opt.sort_tile) * (os ? 8 : 4));
+        ws.part.reserve((256 + (os ? RADIX_OS_WORDS : 0)) * 4);
         sc.alt = alt.as<uint64_t>();
         sc.hist = ws.hist.as<uint32_t>();
         sc.part = ws.part.as<uint32_t>();
-        HIPCHK(radix_sort(keys.as<uint64_t>(), n, check_key(), sc, opt.sort_tile, s, &res, opt.sort_bits));
+        sc.os = os ? sc.part + 256 : nullptr;
+        sc.spin = opt.sort_spin;
+        const VKey vk = check_key();
+        HIPCHK(radix_sort(keys.as<uint64_t>(), n, vk, sc, opt.sort_tile, s, &res, opt.sort_bits));
+        if (sc.stall) {
+            // the single-pass scatter: finish with three-kernel passes if one stalled
+            Fetch f;
+            const size_t i_st = f.add(sc.stall, 4);
+            run_fetch(f);
+            const uint32_t st = *fetched<uint32_t>(f, i_st);
+            ctx->stat_add("sort_onesweep", 1);
+            if (st) {
+                ctx->stat_add("sort_stalls", 1);
+                HIPCHK(radix_sort_resume(keys.as<uint64_t>(), n, vk, sc, opt.sort_tile, s, &res, opt.sort_bits,
+                                         st - 1u));
+            }
+        }
         return res;
     }
 
@@ -2505,6 +2524,8 @@ static kc_status set_option_locked(kc_ctx *ctx, const char *key, int64_t v) {
     else if (k == "uninit" && (v == 0 || v == 1)) ctx->opt.uninit = (int)v;
     else if (k == "warp" && (v == 0 || v == 1)) ctx->opt.warp = (int)v;
     else if (k == "queue_replay" && (v == 0 || v == 1)) ctx->opt.queue_replay = (int)v;
+    else if (k == "onesweep" && (v == 0 || v == 1)) ctx->opt.onesweep = (int)v;
+    else if (k == "sort_spin" && v >= 0 && v <= (1ll << 30)) ctx->opt.sort_spin = (uint32_t)v;
     else if (k == "reset" && v == 1) {
         ctx->stats.clear();
     } else {
@@ -2540,6 +2561,8 @@ static double get_stat_locked(kc_ctx *ctx, const char *key) {
         if (o == "uninit") return op.uninit;
         if (o == "warp") return op.warp;
         if (o == "queue_replay") return op.queue_replay;
+        if (o == "onesweep") return op.onesweep;
+        if (o == "sort_spin") return op.sort_spin;
         return 0.0;
     }
     auto it = ctx->stats.find(key);

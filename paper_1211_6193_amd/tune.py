@@ -32,6 +32,7 @@ from . import kc
 SPACE: Dict[str, Sequence[int]] = {
     "sort_tile": (1024, 2048, 4096, 8192),      # keys per radix-sort tile
     "sort_bits": (8, 7, 6, 5),                  # radix digit width (bits per pass)
+    "onesweep": (1, 0),                         # large sorts: single-pass scatters or three kernels a pass
     "stage_bytes": (8192, 16384, 32768, 65536),
     "stage": (128, 256, 512),
     "local": (0, 1),
