@@ -674,7 +674,7 @@ struct Stage {
     // plain stores), others a hash table of locations.  Flags go to ws.rctr.
     bool qt_direct = false;
     uint32_t qt_bits = 0;
-    bool queue_log_check(uint64_t cap) {
+    bool queue_log_check(uint64_t cap, hipStream_t q) {
         // representatives exist only with the epoch-local check; a very long
         // log would spend more on its table than on the sort
         const bool direct = total_words <= 4 * cap + (1u << 16);
@@ -696,13 +696,13 @@ struct Stage {
             ta.snap_base = ws.snap.as<int32_t>();
             ta.downer = ws.downer.as<uint32_t>();
             ta.dflags = ws.dflags.as<uint8_t>();
-            HIPCHK(launch_log_direct(ta, total_words, s));
+            HIPCHK(launch_log_direct(ta, total_words, q));
         } else {
             ws.ftable.reserve((size_t)8 << bits);
             ta.table = ws.ftable.p;
             ta.bits = bits;
             ta.obits = table_obits();
-            HIPCHK(launch_log_table(ta, s));
+            HIPCHK(launch_log_table(ta, q));
         }
         qt_direct = direct;
         qt_bits = bits;
@@ -846,7 +846,9 @@ struct Stage {
             if (u.desc->prog != in[0].desc->prog) return false;
         return !ctx->spec_skip(in[0].desc->prog);
     }
-    void queue_spec_replay(uint64_t log_cap, uint32_t fault_cap, Timer &tm) {
+    // With `tables_aside` the free-run log's tables are being built on a side
+    // stream: joined before the exactness tables, which read them.
+    void queue_spec_replay(uint64_t log_cap, uint32_t fault_cap, Timer &tm, bool tables_aside) {
         tm.mark(5);
         uint32_t grid_hint = 64;
         ctx->spec_caps(spec_rcap, spec_rlcap, grid_hint);
@@ -893,6 +895,7 @@ struct Stage {
                            table_obits(), ws.snap.as<int32_t>(), qt_direct ? ws.downer.as<uint32_t>() : nullptr,
                            ws.dflags.as<uint8_t>(), nullptr};
         ta.n_dev = &ws.sctr.as<DevCounters>()->log_count;
+        if (tables_aside) join();
         HIPCHK(launch_replay_table(ta, s));
         tm.mark(7);
     }
@@ -1272,10 +1275,21 @@ struct Stage {
                                            ws.blk_off.as<uint64_t>(), total_blocks, ws.log.as<uint64_t>(), log_cap,
                                            &ws.ctr.as<DevCounters>()->log_count,
                                            &ws.ctr.as<DevCounters>()->flags, s));
-            table_queued = check && queue_log_check(log_cap);
+            // the free-run log's location tables and the queued replay read
+            // disjoint buffers until the replay's exactness check: the tables
+            // go to a side stream beside the replay (not when every stage is
+            // timed, whose marks need them on the stage's stream)
+            const bool aside = check && !spec_off && opt.side_streams > 1 && opt.timing != 1;
+            hipStream_t tq = s;
+            if (aside) {
+                fork();
+                tq = side(0);
+            }
+            table_queued = check && queue_log_check(log_cap, tq);
             tm.mark(12);
             spec = table_queued && !spec_off && spec_allowed();
-            if (spec) queue_spec_replay(log_cap, fault_cap, tm);
+            if (spec) queue_spec_replay(log_cap, fault_cap, tm, aside);
+            else if (aside) join();
             fetch = Fetch{};
             const size_t i_ctr = fetch.add(ws.ctr.p, sizeof(DevCounters));
             fetch.add(ws.blk_recs.p, (size_t)total_blocks * 4);
