@@ -150,7 +150,11 @@ void kc_ctx_destroy(kc_ctx *ctx);
  * or faster on MI355X; results are identical), "sort_spin" (the bound, in polls, of each wait of
  * a tile for an earlier tile's counts, default 2^16, 0 to 2^30: a wait that
  * runs out leaves that pass to the three-kernel passes, counted in
- * "sort_stalls"),
+ * "sort_stalls"), "loc_sort" (1 = default: a free-run log of 2^20 records or
+ * more made only of global-memory representatives -- one pass over it tells
+ * -- is sorted by location alone, fewer passes than the location, block and
+ * epoch key, since its check reduces each location's records in any order;
+ * 0 = always the whole key; results are identical),
  * "reset" (1 = clear the statistics).
  * Errors: KC_E_INVAL for an unknown key or out-of-range value. */
 kc_status kc_ctx_set_option(kc_ctx *ctx, const char *key, int64_t value);
@@ -162,7 +166,8 @@ kc_status kc_ctx_set_option(kc_ctx *ctx, const char *key, int64_t value);
  * "spec_retries" (stages run again without it because it did not apply),
  * "interp_launches", "sort_keys", "sort_onesweep" and "sort_stalls" (sorts
  * that took the single-pass scatters, and those finished by three-kernel
- * passes after a wait ran out),
+ * passes after a wait ran out), "loc_sorts" (free-run logs sorted by
+ * location alone),
  * "sorted_checks", "hash_check_ms" (free-run logs that needed the sort, and
  * the time of the location-table checks),
  * "replay_sorted_checks" (replays whose records needed the sorted check: an

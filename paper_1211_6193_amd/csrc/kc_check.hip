@@ -837,6 +837,26 @@ hipError_t launch_check(const CheckArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Sets *flag when a record of keys[0, n) is not a global-memory representative
+// (a shared-space record, or one of an epoch that was not checked locally).
+__global__ void __launch_bounds__(WG) k_log_reps_only(const uint64_t *__restrict__ keys, uint64_t n, KeyPlan k,
+                                                      uint32_t *__restrict__ flag) {
+    bool other = false;
+    for (uint64_t i = (uint64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (uint64_t)gridDim.x * WG) {
+        const uint64_t r = keys[i];
+        other |= rec_field(r, k.s_sp, 1) != 1u || rec_field(r, k.s_ep, k.eb) != k.ep_rep;
+    }
+    if (__ballot(other) && __lane_id() == 0) atomicOr(flag, 1u);
+}
+
+hipError_t launch_log_reps_only(const uint64_t *keys, uint64_t n, KeyPlan kp, uint32_t *flag, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    uint32_t g = blocks_for(n);
+    if (g > 2048) g = 2048;
+    hipLaunchKernelGGL(k_log_reps_only, dim3(g), dim3(WG), 0, s, keys, n, kp, flag);
+    return hipGetLastError();
+}
+
 hipError_t launch_restore(const uint64_t *keys, uint64_t n, KeyPlan kp, const DevUnit *units,
                           const uint32_t *blk_flags, hipStream_t s, const unsigned long long *n_dev) {
     if (n == 0) return hipSuccess;

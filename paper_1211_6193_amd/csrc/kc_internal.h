@@ -237,6 +237,9 @@ struct CheckArgs {
 };
 size_t check_long_cap(uint64_t n);
 hipError_t launch_check(const CheckArgs &a, hipStream_t s);
+// *flag |= 1 when keys[0, n) holds a record other than a global-memory
+// representative (the caller zeroes *flag).
+hipError_t launch_log_reps_only(const uint64_t *keys, uint64_t n, KeyPlan kp, uint32_t *flag, hipStream_t s);
 hipError_t launch_restore(const uint64_t *keys, uint64_t n, KeyPlan kp, const DevUnit *units,
                           const uint32_t *blk_flags, hipStream_t s, const unsigned long long *n_dev = nullptr);
 struct ZeroArgs;

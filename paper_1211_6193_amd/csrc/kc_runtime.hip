@@ -315,6 +315,7 @@ struct Options {
     int warp = 0;                   // warp-aware model: accesses of one warp conflict only at the same step
     int queue_replay = 1;           // replay of the free run's racy blocks queued behind it
     int onesweep = 0;               // large sorts: single-pass digit scatters (decoupled look-back)
+    int loc_sort = 1;               // large free-run logs of representatives only: sorted by location
     uint32_t sort_spin = 1u << 16;  // bound of each look-back wait, in polls
     int arena = 0;                  // set by the library: buffers come from the static scratch area
 };
@@ -1405,7 +1406,7 @@ struct Stage {
             }
             if (need_sort) {
                 tm.mark(2);
-                sorted = sort_check(ws.log, ws.alt, nrec);
+                sorted = sort_check(ws.log, ws.alt, nrec, true);
                 tm.mark(3);
                 run_check(sorted, nrec, ws.blk_flags, races, edges, false);
                 tm.mark(4);
@@ -1461,21 +1462,37 @@ struct Stage {
     }
 
     // Sort n records held in `keys` into check order; returns the sorted array
-    // (keys itself or alt).
-    uint64_t *sort_check(DBuf &keys, DBuf &alt, uint64_t n) {
+    // (keys itself or alt).  A large free-run log (`free_log`) made only of
+    // global-memory representatives is sorted by location alone: every
+    // consumer of such a log reduces a location's records in any order (the
+    // intra-block segments are those of other records), and the records of
+    // one block stay together, as the stable sort keeps the log's order.
+    uint64_t *sort_check(DBuf &keys, DBuf &alt, uint64_t n, bool free_log = false) {
         uint64_t *res = keys.as<uint64_t>();
         if (n <= 1) return res;
         SortScratch sc;
         const bool os = opt.onesweep && !opt.arena && radix_onesweep(n);
         alt.reserve(n * 8);
         ws.hist.reserve(radix_hist_entries(n, opt.sort_tile) * (os ? 8 : 4));
-        ws.part.reserve((256 + (os ? RADIX_OS_WORDS : 0)) * 4);
+        ws.part.reserve((256 + RADIX_OS_WORDS + 1) * 4);
         sc.alt = alt.as<uint64_t>();
         sc.hist = ws.hist.as<uint32_t>();
         sc.part = ws.part.as<uint32_t>();
         sc.os = os ? sc.part + 256 : nullptr;
         sc.spin = opt.sort_spin;
-        const VKey vk = check_key();
+        VKey vk = check_key();
+        if (free_log && n >= (1ull << 20) && opt.loc_sort) {
+            uint32_t *flag = sc.part + 256 + RADIX_OS_WORDS;
+            HIPCHK(launch_zero(flag, 4, s));
+            HIPCHK(launch_log_reps_only(keys.as<uint64_t>(), n, kp, flag, s));
+            Fetch f;
+            const size_t i_f = f.add(flag, 4);
+            run_fetch(f);
+            if (*fetched<uint32_t>(f, i_f) == 0) {
+                vk = VKey{0, 0, kp.s_addr, 0, kp.total - kp.s_addr};
+                ctx->stat_add("loc_sorts", 1);
+            }
+        }
         HIPCHK(radix_sort(keys.as<uint64_t>(), n, vk, sc, opt.sort_tile, s, &res, opt.sort_bits));
         if (sc.stall) {
             // the single-pass scatter: finish with three-kernel passes if one stalled
@@ -1831,7 +1848,7 @@ struct Stage {
             }
         }
         if (sorted_check && !log_sorted) {      // the exactness scan needs the free-run log sorted
-            sorted = sort_check(ws.log, ws.alt, nrec);
+            sorted = sort_check(ws.log, ws.alt, nrec, true);
             log_sorted = true;
             fin_log = sorted;
         }
@@ -2539,6 +2556,7 @@ static kc_status set_option_locked(kc_ctx *ctx, const char *key, int64_t v) {
     else if (k == "warp" && (v == 0 || v == 1)) ctx->opt.warp = (int)v;
     else if (k == "queue_replay" && (v == 0 || v == 1)) ctx->opt.queue_replay = (int)v;
     else if (k == "onesweep" && (v == 0 || v == 1)) ctx->opt.onesweep = (int)v;
+    else if (k == "loc_sort" && (v == 0 || v == 1)) ctx->opt.loc_sort = (int)v;
     else if (k == "sort_spin" && v >= 0 && v <= (1ll << 30)) ctx->opt.sort_spin = (uint32_t)v;
     else if (k == "reset" && v == 1) {
         ctx->stats.clear();
@@ -2576,6 +2594,7 @@ static double get_stat_locked(kc_ctx *ctx, const char *key) {
         if (o == "warp") return op.warp;
         if (o == "queue_replay") return op.queue_replay;
         if (o == "onesweep") return op.onesweep;
+        if (o == "loc_sort") return op.loc_sort;
         if (o == "sort_spin") return op.sort_spin;
         return 0.0;
     }

@@ -7,7 +7,9 @@ the three-kernel passes and the oracle:
 * every look-back wait bounded to no poll at all (option sort_spin = 0): a
   tile that finds an earlier tile's counts not yet published stalls its pass,
   the host finishes the sort with three-kernel passes from that pass's input,
-  and the results are still the oracle's."""
+  and the results are still the oracle's;
+* a log of representatives only sorted by location alone (option loc_sort)
+  or by the whole key: the same results."""
 import pytest
 
 torch = pytest.importorskip("torch")
@@ -49,12 +51,13 @@ def _run(ctx, case, label, **opts):
         rep, mem = kc.run_job(ctx, job)
         assert_same(rep, mem, ora, label)
         assert ctx.stat("sort_keys") >= 2 * (1 << 20)
-        return {k: ctx.stat(k) for k in ("sort_onesweep", "sort_stalls", "sorted_checks", "sort_ms")}
+        return {k: ctx.stat(k) for k in ("sort_onesweep", "sort_stalls", "sorted_checks", "sort_ms", "loc_sorts")}
     finally:
         ctx.set_option("onesweep", 0)
         ctx.set_option("sort_spin", 1 << 16)
         ctx.set_option("sort_bits", 8)
         ctx.set_option("sort_tile", 2048)
+        ctx.set_option("loc_sort", 1)
 
 
 @pytest.mark.parametrize("onesweep", [1, 0], ids=["single-pass", "three-kernel"])
@@ -77,3 +80,11 @@ def test_stalled_passes_are_finished_by_the_three_kernel_passes(ctx, case):
     st = _run(ctx, case, "no waiting", onesweep=1, sort_spin=0)
     say(f"stats {st}")
     assert st["sort_onesweep"] >= 2
+
+
+@pytest.mark.parametrize("loc", [1, 0], ids=["location-key", "whole-key"])
+def test_location_key_or_whole_key(ctx, case, loc):
+    st = _run(ctx, case, f"loc_sort={loc}", loc_sort=loc)
+    say(f"stats {st}")
+    if not loc:
+        assert st["loc_sorts"] == 0
