@@ -53,6 +53,9 @@ def main():
                          "HBM counter readings) and exit")
     ap.add_argument("--only", choices=("none", "sort", "batched", "serve", "streams", "workload4"),
                     help="run the plain steps and this one optional leg only (no CPU baseline): for profiles")
+    ap.add_argument("--option", action="append", default=[], metavar="NAME=VALUE",
+                    help="set a library option on the benchmark's context before the plain steps (for profiles "
+                         "of an alternative setting, e.g. onesweep=1; the line then names it in config.options)")
     args = ap.parse_args()
     if args.only:
         for leg, flag in (("sort", "no_sort_path"), ("batched", "no_batched"), ("serve", "no_serve"),
@@ -81,6 +84,11 @@ def main():
     ctx = kc.Context(0)
     ctx.set_option("timing", 2)         # HIP events around the free run only, during the timed steps
     ctx.set_option("jit", args.jit)     # program-specialised free-run kernels (compiled at first use)
+    extra = {}
+    for kv in args.option:
+        name, _, val = kv.partition("=")
+        ctx.set_option(name, int(val))
+        extra[name] = int(val)
     prog = ctx.program(L.program)
     mem = torch.from_numpy(job.memory.copy()).cuda()
     stream = torch.cuda.current_stream()
@@ -167,7 +175,8 @@ def main():
                    "bit_exact_vs_oracle": exact,
                    "p50_ms": round(lat_ms[len(lat_ms) // 2], 4),
                    "p99_ms": round(lat_ms[min(len(lat_ms) - 1, int(0.99 * len(lat_ms)))], 4),
-                   "replays_per_step": stats["replays"] / args.steps, "fallbacks": stats["fallbacks"]},
+                   "replays_per_step": stats["replays"] / args.steps, "fallbacks": stats["fallbacks"],
+                   **({"options": extra} if extra else {})},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "shadow_vs_sort": sort_path,
